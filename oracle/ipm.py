@@ -1,0 +1,360 @@
+"""Lifted-KKT primal-dual interior-point method (oracle side), Section 3.2,
+Algorithm 2.
+
+Problem (eq. 6, with variable bounds kept as barrier terms as the -mu Y^{-1} e
+term of r_1 in eq. 11 implies):
+    min f(y)  s.t.  c(y) = 0,  d(y) <= 0,  lb <= y <= ub.
+Lifting (eq. 16): the equalities are relaxed to -gamma <= c <= gamma, so the
+inequality rows become  g^l = [c - gamma; -c - gamma; d]  (m^l = 2 m_c + m_d),
+with slacks s >= 0, g^l + s = 0, multipliers omega (for g^l + s = 0), beta
+(for s >= 0), zL / zU (for the bounds).
+
+One Newton iteration (eqs. 10-11, 14, 17, 22-25):
+    r1 = grad f + G^T omega - mu/(y - lb) + mu/(ub - y)
+    r2 = omega - mu / s
+    r4 = g^l + s
+    Q  = beta / s,   Sigma = zL/(y - lb) + zU/(ub - y)
+    K  = W + Sigma + eta I + G^T Q G        (W = Hessian of f + lam^T c, lam = omega+ - omega-)
+    K dy = -r1 - G^T (Q r4 - r2)            (solved by Cholesky; failure -> larger eta)
+    ds = -r4 - G dy;   domega = -r2 - Q ds
+    dbeta = mu/s - beta - Q ds
+    dzL = mu/(y-lb) - zL - Sigma_L dy,  dzU = mu/(ub-y) - zU + Sigma_U dy
+Step (eq. 26): one alpha for the whole primal-dual vector z, from a
+backtracking line search on an l1 merit started at the fraction-to-boundary
+limit of every positive quantity (s, bound gaps, beta, zL, zU).  A single step
+keeps omega - beta shrinking by (1 - alpha) per iteration; the lifted
+multipliers grow like mu / gamma away from the solution, so separate primal and
+dual steps would let that difference blow up.  Barrier update after the inner test (eq. 27),
+termination on the mu = 0 optimality error (eq. 28).
+
+The constants the paper leaves open are fixed in ``IPMOptions``; the GPU library
+uses the same values.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+EPS = np.finfo(np.float64).eps
+
+
+@dataclass
+class IPMOptions:
+    tol: float = 1e-8            # epsilon_outer on E_0
+    gamma: float = 1e-9          # equality relaxation of the lifting
+    mu0_cold: float = 1e-1
+    mu0_warm: float = 1e-9       # warm start at the final barrier value
+    mu_min: float = 1e-9
+    kappa_eps: float = 10.0      # inner test: E_mu <= kappa_eps * mu
+    kappa_mu: float = 0.2
+    theta_mu: float = 1.5
+    tau_min: float = 0.99
+    armijo: float = 1e-4
+    ls_max: int = 40
+    kappa_sigma: float = 1e10
+    max_iter: int = 200
+    eta_first: float = 1e-4
+    eta_min: float = 1e-20
+    eta_max: float = 1e40
+    kp_first: float = 100.0
+    kp: float = 8.0
+    km: float = 1.0 / 3.0
+    bound_push: float = 1e-2
+    slack_push: float = 1e-2
+
+
+STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "regularization_fail",
+          4: "nonfinite"}
+
+
+@dataclass
+class IPMState:
+    y: np.ndarray
+    s: np.ndarray
+    omega: np.ndarray
+    beta: np.ndarray
+    zL: np.ndarray
+    zU: np.ndarray
+
+    def copy(self):
+        return IPMState(*(a.copy() for a in (self.y, self.s, self.omega, self.beta, self.zL, self.zU)))
+
+
+@dataclass
+class IPMResult:
+    status: int
+    iters: int
+    state: IPMState
+    mu: float
+    eta: float
+    E0: float
+    trace: list = field(default_factory=list)
+
+
+def _ftb(v, dv, tau):
+    """Largest alpha in (0, 1] with v + alpha dv >= (1 - tau) v (v > 0)."""
+    neg = dv < 0
+    if not np.any(neg):
+        return 1.0
+    return float(min(1.0, np.min(-tau * v[neg] / dv[neg])))
+
+
+class CholeskySolver:
+    """Cholesky of an SPD matrix given in CSR; banded storage when the natural
+    order has a narrow band, dense otherwise.  ``factor`` returns False when the
+    matrix is not numerically positive definite (a pivot <= 0 or non-finite)."""
+
+    def __init__(self, n, pattern_rows, pattern_cols):
+        self.n = n
+        bw = int(np.max(np.abs(np.asarray(pattern_rows) - np.asarray(pattern_cols)))) if len(pattern_rows) else 0
+        self.bw = bw
+        self.banded = (bw + 1) * 4 < n
+
+    def factor(self, K):
+        K = K.tocsr()
+        if not np.all(np.isfinite(K.data)):
+            return False
+        try:
+            if self.banded:
+                Kc = K.tocoo()
+                ab = np.zeros((self.bw + 1, self.n))
+                low = Kc.row >= Kc.col
+                ab[(Kc.row - Kc.col)[low], Kc.col[low]] = Kc.data[low]
+                self.cb = sla.cholesky_banded(ab, lower=True)
+            else:
+                self.L = np.linalg.cholesky(K.toarray())
+        except (np.linalg.LinAlgError, sla.LinAlgError):
+            return False
+        return True
+
+    def solve(self, b):
+        if self.banded:
+            return sla.cho_solve_banded((self.cb, True), b)
+        return sla.cho_solve((self.L, True), b)
+
+
+class LiftedIPM:
+    def __init__(self, nlp, opts: IPMOptions | None = None):
+        self.nlp = nlp
+        self.o = opts or IPMOptions()
+        self.n, self.mc, self.md = nlp.n, nlp.m_c, nlp.m_d
+        self.ml = 2 * self.mc + self.md
+        self.hasL = np.isfinite(nlp.lb)
+        self.hasU = np.isfinite(nlp.ub)
+        from .symbolic import kkt_lower_pattern
+        r, c = kkt_lower_pattern(nlp)
+        self.chol = CholeskySolver(self.n, r, c)
+        self.eta_last = 0.0
+
+    # ---- lifted constraint helpers ----------------------------------
+    def g_lifted(self, c, d):
+        g = self.o.gamma
+        return np.concatenate([c - g, -c - g, d])
+
+    def GT(self, Jc, Jd, v):
+        mc = self.mc
+        out = Jc.T @ (v[:mc] - v[mc:2 * mc])
+        if self.md:
+            out = out + Jd.T @ v[2 * mc:]
+        return out
+
+    def G(self, Jc, Jd, dy):
+        a = Jc @ dy
+        parts = [a, -a]
+        if self.md:
+            parts.append(Jd @ dy)
+        return np.concatenate(parts)
+
+    def gaps(self, y):
+        gl = np.where(self.hasL, y - self.nlp.lb, 1.0)
+        gu = np.where(self.hasU, self.nlp.ub - y, 1.0)
+        return gl, gu
+
+    # ---- starting points ---------------------------------------------
+    def cold_start(self, y_guess, mu0):
+        o, nlp = self.o, self.nlp
+        lb, ub = nlp.lb, nlp.ub
+        y = np.array(y_guess, dtype=np.float64)
+        # push into the interior (fraction of the bound magnitude and of the range)
+        pl = np.where(self.hasL, o.bound_push * np.maximum(1.0, np.abs(lb)), 0.0)
+        pu = np.where(self.hasU, o.bound_push * np.maximum(1.0, np.abs(ub)), 0.0)
+        both = self.hasL & self.hasU
+        rng = np.where(both, ub - lb, np.inf)
+        pl = np.where(both, np.minimum(pl, 0.5 * o.bound_push * rng), pl)
+        pu = np.where(both, np.minimum(pu, 0.5 * o.bound_push * rng), pu)
+        y = np.where(self.hasL, np.maximum(y, lb + pl), y)
+        y = np.where(self.hasU, np.minimum(y, ub - pu), y)
+        gl = self.g_lifted(nlp.cons_c(y), nlp.cons_d(y))
+        s = np.maximum(-gl, o.slack_push * np.maximum(1.0, np.abs(gl)))
+        omega = np.zeros(self.ml)
+        beta = mu0 / s
+        gL, gU = self.gaps(y)
+        zL = np.where(self.hasL, mu0 / gL, 0.0)
+        zU = np.where(self.hasU, mu0 / gU, 0.0)
+        return IPMState(y, s, omega, beta, zL, zU)
+
+    # ---- optimality errors -------------------------------------------
+    def errors(self, st, gf, c, d, Jc, Jd, mu):
+        gL, gU = self.gaps(st.y)
+        dual = gf + self.GT(Jc, Jd, st.omega) - st.zL + st.zU
+        prim = self.g_lifted(c, d) + st.s
+        e = [np.max(np.abs(dual)), np.max(np.abs(st.omega - st.beta)), np.max(np.abs(prim)),
+             np.max(np.abs(st.s * st.beta - mu))]
+        if np.any(self.hasL):
+            e.append(np.max(np.abs((gL * st.zL - mu)[self.hasL])))
+        if np.any(self.hasU):
+            e.append(np.max(np.abs((gU * st.zU - mu)[self.hasU])))
+        return float(max(e))
+
+    def merit(self, y, s, mu, nu):
+        nlp = self.nlp
+        gL, gU = self.gaps(y)
+        phi = nlp.f(y) - mu * np.sum(np.log(s))
+        if np.any(self.hasL):
+            phi -= mu * np.sum(np.log(gL[self.hasL]))
+        if np.any(self.hasU):
+            phi -= mu * np.sum(np.log(gU[self.hasU]))
+        phi += nu * np.sum(np.abs(self.g_lifted(nlp.cons_c(y), nlp.cons_d(y)) + s))
+        return float(phi)
+
+    # ---- main loop ----------------------------------------------------
+    def solve(self, start: IPMState, mu0: float, record=False):
+        o, nlp = self.o, self.nlp
+        st = start.copy()
+        mu = mu0
+        nu = 1.0
+        self.eta_last = 0.0
+        trace = []
+        status = 1
+        it = 0
+        eta = 0.0
+        E0 = np.inf
+        while True:
+            f = nlp.f(st.y)
+            gf = nlp.grad(st.y)
+            c, d = nlp.cons_c(st.y), nlp.cons_d(st.y)
+            Jc, Jd = nlp.jac_c(st.y), nlp.jac_d(st.y)
+            if not (np.isfinite(f) and np.all(np.isfinite(gf)) and np.all(np.isfinite(c))):
+                status = 4
+                break
+            E0 = self.errors(st, gf, c, d, Jc, Jd, 0.0)
+            if E0 <= o.tol:
+                status = 0
+                break
+            if it >= o.max_iter:
+                status = 1
+                break
+            # barrier update (eq. 27 inner test, Algorithm 2 outer loop)
+            Emu = self.errors(st, gf, c, d, Jc, Jd, mu)
+            while Emu <= o.kappa_eps * mu and mu > o.mu_min:
+                mu = max(o.mu_min, min(o.kappa_mu * mu, mu ** o.theta_mu))
+                Emu = self.errors(st, gf, c, d, Jc, Jd, mu)
+            tau = max(o.tau_min, 1.0 - mu)
+            step = self.newton_step(st, mu, f, gf, c, d, Jc, Jd)
+            if step is None:
+                status = 3
+                break
+            eta = step["eta"]
+            dy, ds, dom, dbe, dzL, dzU = (step[k] for k in ("dy", "ds", "domega", "dbeta", "dzL", "dzU"))
+            r4 = step["r4"]
+            gL, gU = self.gaps(st.y)
+            # fraction to boundary
+            amax = _ftb(st.s, ds, tau)
+            if np.any(self.hasL):
+                amax = min(amax, _ftb(gL[self.hasL], dy[self.hasL], tau))
+            if np.any(self.hasU):
+                amax = min(amax, _ftb(gU[self.hasU], -dy[self.hasU], tau))
+            adu = _ftb(st.beta, dbe, tau)
+            if np.any(self.hasL):
+                adu = min(adu, _ftb(st.zL[self.hasL], dzL[self.hasL], tau))
+            if np.any(self.hasU):
+                adu = min(adu, _ftb(st.zU[self.hasU], dzU[self.hasU], tau))
+            # l1 merit line search (eq. 26)
+            nu = max(nu, float(np.max(np.abs(st.omega + dom))) + 1.0)
+            phi0 = self.merit(st.y, st.s, mu, nu)
+            Dphi = (float(gf @ dy) - mu * float(np.sum(ds / st.s))
+                    - mu * float(np.sum(np.where(self.hasL, dy / gL, 0.0)))
+                    + mu * float(np.sum(np.where(self.hasU, dy / gU, 0.0)))
+                    - nu * float(np.sum(np.abs(r4))))
+            alpha = min(amax, adu)
+            accepted = False
+            trials = 0
+            for trials in range(1, o.ls_max + 1):
+                yt = st.y + alpha * dy
+                stt = st.s + alpha * ds
+                phit = self.merit(yt, stt, mu, nu)
+                if np.isfinite(phit) and phit <= phi0 + o.armijo * alpha * Dphi + 10.0 * EPS * abs(phi0):
+                    accepted = True
+                    break
+                alpha *= 0.5
+            if record:
+                trace.append(dict(it=it, mu=mu, eta=eta, amax=amax, alpha=alpha, adu=adu,
+                                  E0=E0, Emu=Emu, trials=trials, phi=phi0, Dphi=Dphi, nu=nu,
+                                  dy_norm=float(np.max(np.abs(dy)))))
+            if not accepted:
+                status = 2
+                break
+            st.y = st.y + alpha * dy
+            st.s = st.s + alpha * ds
+            st.omega = st.omega + alpha * dom
+            st.beta = st.beta + alpha * dbe
+            st.zL = st.zL + alpha * dzL
+            st.zU = st.zU + alpha * dzU
+            # keep the bound multipliers within kappa_sigma of the primal estimate
+            ks = o.kappa_sigma
+            st.beta = np.clip(st.beta, mu / (ks * st.s), ks * mu / st.s)
+            gL, gU = self.gaps(st.y)
+            st.zL = np.where(self.hasL, np.clip(st.zL, mu / (ks * gL), ks * mu / gL), 0.0)
+            st.zU = np.where(self.hasU, np.clip(st.zU, mu / (ks * gU), ks * mu / gU), 0.0)
+            it += 1
+        return IPMResult(status=status, iters=it, state=st, mu=mu, eta=eta, E0=E0, trace=trace)
+
+    def newton_step(self, st, mu, f, gf, c, d, Jc, Jd):
+        """Condensed Newton direction at ``st`` (eqs. 10-11, 14, 17, 22-25) with
+        inertia correction; returns None when eta exceeds eta_max."""
+        o, nlp, mc = self.o, self.nlp, self.mc
+        lam = st.omega[:mc] - st.omega[mc:2 * mc]
+        lam_d = st.omega[2 * mc:]
+        W = nlp.hess(st.y, lam, lam_d)
+        gL, gU = self.gaps(st.y)
+        sigL = np.where(self.hasL, st.zL / gL, 0.0)
+        sigU = np.where(self.hasU, st.zU / gU, 0.0)
+        Q = st.beta / st.s
+        r1 = (gf + self.GT(Jc, Jd, st.omega)
+              - np.where(self.hasL, mu / gL, 0.0) + np.where(self.hasU, mu / gU, 0.0))
+        r2 = st.omega - mu / st.s
+        r4 = self.g_lifted(c, d) + st.s
+        Qc = Q[:mc] + Q[mc:2 * mc]
+        JQJ = Jc.T @ sp.diags(Qc) @ Jc
+        if self.md:
+            JQJ = JQJ + Jd.T @ sp.diags(Q[2 * mc:]) @ Jd
+        K0 = (W + sp.diags(sigL + sigU) + JQJ).tocsr()
+        rhs = -r1 - self.GT(Jc, Jd, Q * r4 - r2)
+        # inertia correction (eqs. 12-13, 15, 17): eta grows until Cholesky succeeds
+        eta = 0.0
+        ok = self.chol.factor(K0)
+        if not ok:
+            eta = o.eta_first if self.eta_last == 0.0 else max(o.eta_min, o.km * self.eta_last)
+            while True:
+                ok = self.chol.factor(K0 + eta * sp.identity(self.n, format="csr"))
+                if ok:
+                    break
+                eta *= o.kp_first if self.eta_last == 0.0 else o.kp
+                if eta > o.eta_max:
+                    return None
+            self.eta_last = eta
+        dy = self.chol.solve(rhs)
+        ds = -r4 - self.G(Jc, Jd, dy)
+        dom = -r2 - Q * ds
+        dbe = mu / st.s - st.beta - Q * ds
+        dzL = np.where(self.hasL, mu / gL - st.zL - sigL * dy, 0.0)
+        dzU = np.where(self.hasU, mu / gU - st.zU + sigU * dy, 0.0)
+        return dict(dy=dy, ds=ds, domega=dom, dbeta=dbe, dzL=dzL, dzU=dzU, eta=eta,
+                    K=K0, rhs=rhs, W=W, r1=r1, r2=r2, r4=r4, Q=Q, sigL=sigL, sigU=sigU)
+
+    def multipliers(self, st):
+        """Equality multipliers of the original problem: lam = omega+ - omega-."""
+        mc = self.mc
+        return st.omega[:mc] - st.omega[mc:2 * mc], st.omega[2 * mc:]

@@ -1,0 +1,47 @@
+"""Receding-horizon loop on the oracle side, Algorithm 1.
+
+Solve, extract the first control, apply it, take the next measurement, warm
+start the next solve from the previous solution (unshifted) and update the
+parameters.  The plant is the transcription's own first stage: the predicted
+x_1 is the implicit-Euler step of the model under u_1, to which the workload
+adds its pre-drawn measurement noise.
+"""
+from __future__ import annotations
+
+import time
+import numpy as np
+
+from .distillation import DistillationOCP
+from .ipm import LiftedIPM, IPMOptions
+
+
+def distillation_episode(w, n_resolves=None, opts=None, record=False):
+    """Run one cold solve plus ``n_resolves`` warm re-solves of a distillation
+    workload.  Returns a list of per-solve dicts (parameters in, solution out)."""
+    n_resolves = w.n_resolves if n_resolves is None else n_resolves
+    m = DistillationOCP.from_workload(w)
+    ipm = LiftedIPM(m, opts or IPMOptions())
+    x0, u_prev = w.x0.copy(), w.u_prev0.copy()
+    out = []
+    state = None
+    for r in range(n_resolves + 1):
+        zF = w.zF(r)
+        m.set_parameters(x0=x0, zF=zF, u_prev=u_prev)
+        t = time.perf_counter()
+        if state is None:
+            st0 = ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold)
+            res = ipm.solve(st0, ipm.o.mu0_cold, record=record)
+        else:
+            res = ipm.solve(state, ipm.o.mu0_warm, record=record)
+        dt = time.perf_counter() - t
+        lam, om_d = ipm.multipliers(res.state)
+        out.append(dict(index=r, x0=x0.copy(), zF=zF, u_prev=u_prev.copy(),
+                        status=res.status, iters=res.iters, E0=res.E0, mu=res.mu,
+                        y=res.state.y.copy(), lam=lam.copy(), omega_d=om_d.copy(),
+                        zL=res.state.zL.copy(), zU=res.state.zU.copy(),
+                        state=res.state.copy(), seconds=dt, trace=res.trace))
+        state = res.state
+        u_prev = m.u1(res.state.y)
+        if r < n_resolves:
+            x0 = w.next_measurement(m.x1(res.state.y), r)
+    return m, out

@@ -1,0 +1,248 @@
+"""SymCholesky on the CPU (oracle side), Section 3.2.3, eqs. (18)-(19), Fig. 1.
+
+Given the lower-triangular sparsity pattern of the condensed matrix K_c^l
+(diagonal included), compute
+
+  * the fill-reducing permutation P (eq. 19).  The paper names minimum degree
+    and nested dissection without fixing one; the reading taken here is exact
+    minimum degree on the elimination graph (true degrees, no mass elimination,
+    no absorption, no dense-row handling), ties broken by the smallest original
+    index, followed by a postorder of the elimination tree;
+  * the elimination tree: parent(j) = min{ i > j : L_ij != 0 };
+  * the column structures of L_P: struct(L_*j) = struct(K_P lower col j) united
+    with struct(L_*c) minus {c} over the children c of j (Section 3.2.3);
+  * fundamental supernodes and a relaxed amalgamation (rule below), which fix
+    the stored pattern S_L including any explicit zeros.
+
+Conventions: ``perm[k]`` is the original index of the k-th pivot (new -> old),
+``iperm[v]`` is the pivot position of original index v (old -> new).
+
+Relaxed amalgamation rule.  Supernodes are visited in increasing order of their
+first column (a postorder of the supernodal tree).  A supernode s whose last
+column's parent is the first column of the next supernode p (so s is the child
+of p that immediately precedes it) is merged into p when
+      width(s) + width(p) <= AMALG_MAX_WIDTH  and
+      ( width(s) + width(p) <= AMALG_SMALL  or
+        zeros(merged) <= AMALG_ZERO_FRAC * stored(merged) )
+where stored(x) counts every entry a supernode stores in its trapezoid
+(w (w + 1) / 2 + w * below) and zeros(x) counts explicit zeros, accumulated
+over earlier merges.  A merged node keeps the later node's identity, so chains
+of merges collapse bottom-up.
+"""
+from __future__ import annotations
+
+import heapq
+import numpy as np
+
+AMALG_MAX_WIDTH = 64
+AMALG_SMALL = 8
+AMALG_ZERO_FRAC = 0.25
+
+
+def adjacency_from_lower(n, rows, cols):
+    adj = [set() for _ in range(n)]
+    for i, j in zip(rows, cols):
+        i, j = int(i), int(j)
+        if i != j:
+            adj[i].add(j)
+            adj[j].add(i)
+    return adj
+
+
+def min_degree_order(n, adj):
+    """Exact minimum degree: returns perm (new -> old)."""
+    adj = [set(a) for a in adj]
+    heap = [(len(adj[v]), v) for v in range(n)]
+    heapq.heapify(heap)
+    done = [False] * n
+    order = []
+    while heap:
+        d, v = heapq.heappop(heap)
+        if done[v] or d != len(adj[v]):
+            continue
+        done[v] = True
+        order.append(v)
+        nb = adj[v]
+        for a in nb:
+            s = adj[a]
+            s |= nb
+            s.discard(a)
+            s.discard(v)
+            heapq.heappush(heap, (len(s), a))
+        adj[v] = set()
+    assert len(order) == n
+    return np.array(order, dtype=np.int64)
+
+
+def permute_lower(rows, cols, iperm):
+    """Lower pattern of P K P^T as per-column sorted row lists."""
+    n = len(iperm)
+    colrows = [set() for _ in range(n)]
+    for i, j in zip(rows, cols):
+        a, b = int(iperm[int(i)]), int(iperm[int(j)])
+        if a < b:
+            a, b = b, a
+        colrows[b].add(a)
+    for j in range(n):
+        colrows[j].add(j)
+    return colrows
+
+
+def column_structures(colrows):
+    """Column structures of L and the elimination tree, column by column.
+
+    Children of j are the columns c < j with parent(c) = j; they are all known
+    when column j is processed because parent(c) > c.
+    """
+    n = len(colrows)
+    parent = np.full(n, -1, dtype=np.int64)
+    struct = [None] * n
+    children = [[] for _ in range(n)]
+    for j in range(n):
+        s = set(colrows[j])
+        for c in children[j]:
+            s |= struct[c]
+        # drop the children themselves: every other row of a child's column is >= j
+        s = {r for r in s if r >= j}
+        struct[j] = s
+        below = [r for r in s if r > j]
+        if below:
+            p = min(below)
+            parent[j] = p
+            children[p].append(j)
+    return struct, parent
+
+
+def postorder(parent):
+    """DFS postorder; roots and children visited in increasing index."""
+    n = len(parent)
+    children = [[] for _ in range(n)]
+    roots = []
+    for j in range(n):
+        if parent[j] < 0:
+            roots.append(j)
+        else:
+            children[parent[j]].append(j)
+    post = []
+    for r in roots:
+        stack = [(r, 0)]
+        while stack:
+            v, ci = stack.pop()
+            if ci < len(children[v]):
+                stack.append((v, ci + 1))
+                stack.append((children[v][ci], 0))
+            else:
+                post.append(v)
+    return np.array(post, dtype=np.int64)
+
+
+def fundamental_supernodes(parent, colcount):
+    """Column j+1 joins j's supernode iff parent(j) = j+1, j is the only child
+    of j+1, and colcount(j) = colcount(j+1) + 1.  Returns supernode start list."""
+    n = len(parent)
+    nchild = np.zeros(n, dtype=np.int64)
+    for j in range(n):
+        if parent[j] >= 0:
+            nchild[parent[j]] += 1
+    starts = [0]
+    for j in range(n - 1):
+        same = (parent[j] == j + 1 and nchild[j + 1] == 1
+                and colcount[j] == colcount[j + 1] + 1)
+        if not same:
+            starts.append(j + 1)
+    return starts
+
+
+def amalgamate(starts, parent, struct, n):
+    """Relaxed amalgamation (rule in the module docstring)."""
+    nodes = []   # each: [first, last_excl, below_rows(set), stored, zeros]
+    bounds = list(starts) + [n]
+    for s in range(len(starts)):
+        f, l = bounds[s], bounds[s + 1]
+        below = {r for r in struct[f] if r >= l}
+        w = l - f
+        stored = w * (w + 1) // 2 + w * len(below)
+        nodes.append([f, l, below, stored, 0])
+    out = []
+    for node in nodes:
+        # try to merge the previously emitted node (immediately preceding) into this one
+        while out:
+            prev = out[-1]
+            f0, l0 = prev[0], prev[1]
+            if l0 != node[0] or parent[l0 - 1] != node[0]:
+                break
+            w = node[1] - prev[0]
+            below = node[2]
+            stored = w * (w + 1) // 2 + w * len(below)
+            zeros = stored - (prev[3] - prev[4]) - (node[3] - node[4])
+            ok = w <= AMALG_MAX_WIDTH and (w <= AMALG_SMALL or zeros <= AMALG_ZERO_FRAC * stored)
+            if not ok:
+                break
+            out.pop()
+            node = [prev[0], node[1], below, stored, zeros]
+        out.append(node)
+    snode_ptr = np.array([nd[0] for nd in out] + [n], dtype=np.int64)
+    rows = []
+    for nd in out:
+        rows.append(np.array(list(range(nd[0], nd[1])) + sorted(nd[2]), dtype=np.int64))
+    return snode_ptr, rows
+
+
+def analyze(n, rows, cols):
+    """Full symbolic analysis of a lower pattern (original indexing).
+
+    Returns a dict with perm, iperm, parent (column etree in final order),
+    colcount (per column of the exact factor), nnz_L (exact), snode_ptr,
+    snode_rows (row list per supernode, stored pattern), snode_parent.
+    """
+    adj = adjacency_from_lower(n, rows, cols)
+    perm_md = min_degree_order(n, adj)
+    iperm_md = np.empty(n, dtype=np.int64)
+    iperm_md[perm_md] = np.arange(n)
+    colrows = permute_lower(rows, cols, iperm_md)
+    _, parent_md = column_structures(colrows)
+    post = postorder(parent_md)
+    perm = perm_md[post]
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[perm] = np.arange(n)
+    colrows = permute_lower(rows, cols, iperm)
+    struct, parent = column_structures(colrows)
+    colcount = np.array([len(s) for s in struct], dtype=np.int64)
+    starts = fundamental_supernodes(parent, colcount)
+    snode_ptr, snode_rows = amalgamate(starts, parent, struct, n)
+    nsn = len(snode_ptr) - 1
+    col2sn = np.empty(n, dtype=np.int64)
+    for s in range(nsn):
+        col2sn[snode_ptr[s]:snode_ptr[s + 1]] = s
+    snode_parent = np.full(nsn, -1, dtype=np.int64)
+    for s in range(nsn):
+        last = snode_ptr[s + 1] - 1
+        if parent[last] >= 0:
+            snode_parent[s] = col2sn[parent[last]]
+    return dict(n=n, perm=perm, iperm=iperm, parent=parent, colcount=colcount,
+                nnz_L=int(colcount.sum()), flops=int(np.sum(colcount.astype(np.int64) ** 2)),
+                snode_ptr=snode_ptr, snode_rows=snode_rows, snode_parent=snode_parent,
+                struct=struct, colrows=colrows)
+
+
+def kkt_lower_pattern(nlp):
+    """Structural lower pattern of K = W + J_c^T J_c + J_d^T J_d + diag (original order)."""
+    import scipy.sparse as sp
+    n = nlp.n
+    ent = set()
+    for r, c in zip(nlp.h_rows, nlp.h_cols):
+        ent.add((max(r, c), min(r, c)))
+    for rows_, cols_, m in ((nlp.jc_rows, nlp.jc_cols, nlp.m_c), (nlp.jd_rows, nlp.jd_cols, nlp.m_d)):
+        if m == 0:
+            continue
+        J = sp.csr_matrix((np.ones(len(rows_)), (rows_, cols_)), shape=(m, n))
+        for r in range(m):
+            cs = J.indices[J.indptr[r]:J.indptr[r + 1]]
+            for a in cs:
+                for b in cs:
+                    if a >= b:
+                        ent.add((int(a), int(b)))
+    for j in range(n):
+        ent.add((j, j))
+    ent = sorted(ent, key=lambda t: (t[1], t[0]))
+    return np.array([e[0] for e in ent]), np.array([e[1] for e in ent])

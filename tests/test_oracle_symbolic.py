@@ -1,0 +1,184 @@
+"""Pins for the oracle's SymCholesky (Section 3.2.3, Fig. 1)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import symbolic as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "fig1_cholesky_example.txt")
+
+
+def _read_fig1():
+    lower, factor, parent = {}, {}, None
+    for line in open(GOLD):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, rest = line.split(":", 1) if ":" in line else (line, "")
+        vals = [int(v) for v in rest.split()]
+        if key.startswith("matrix_lower"):
+            lower[int(key.split()[1])] = vals
+        elif key.startswith("factor"):
+            factor[int(key.split()[1])] = vals
+        elif key == "parent":
+            parent = vals
+    return lower, factor, parent
+
+
+def _dense_symbolic(n, rows, cols):
+    """Brute-force boolean elimination on a dense matrix: L pattern and etree."""
+    M = np.zeros((n, n), dtype=bool)
+    for i, j in zip(rows, cols):
+        M[max(i, j), min(i, j)] = True
+    M[np.arange(n), np.arange(n)] = True
+    for k in range(n):
+        below = np.nonzero(M[k + 1:, k])[0] + k + 1
+        for a in below:
+            for b in below:
+                if b <= a:
+                    M[a, b] = True
+    parent = np.full(n, -1)
+    for j in range(n):
+        nz = np.nonzero(M[j + 1:, j])[0]
+        if len(nz):
+            parent[j] = j + 1 + nz[0]
+    return M, parent
+
+
+def test_fig1_etree_and_factor():
+    lower, factor, parent = _read_fig1()
+    rows = [r - 1 for c in lower for r in lower[c]]
+    cols = [c - 1 for c in lower for r in lower[c]]
+    colrows = S.permute_lower(rows, cols, np.arange(6))
+    struct, par = S.column_structures(colrows)
+    assert [p + 1 if p >= 0 else 0 for p in par] == parent
+    for c in range(6):
+        assert sorted(r + 1 for r in struct[c]) == factor[c + 1]
+    counts = [len(s) for s in struct]
+    assert counts == [3, 3, 3, 2, 2, 1]
+    assert sum(counts) == 14 and len(rows) == 11
+    # fill entries of panel (c) that panel (a) does not have
+    fill = {(r + 1, c + 1) for c in range(6) for r in struct[c]} - {(r, c) for c in lower for r in lower[c]}
+    assert fill == {(4, 3), (6, 3), (6, 4)}
+    # natural order is already a postorder of this tree
+    assert list(S.postorder(par)) == [0, 1, 2, 3, 4, 5]
+
+
+def test_fig1_supernodes():
+    lower, _, _ = _read_fig1()
+    rows = [r - 1 for c in lower for r in lower[c]]
+    cols = [c - 1 for c in lower for r in lower[c]]
+    colrows = S.permute_lower(rows, cols, np.arange(6))
+    struct, par = S.column_structures(colrows)
+    cc = np.array([len(s) for s in struct])
+    # (1-based) column 3 is the only child of column 4 and count(3) = count(4) + 1,
+    # so {3, 4} is a fundamental supernode; 1, 2, 5, 6 stand alone
+    assert S.fundamental_supernodes(par, cc) == [0, 1, 2, 4, 5]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_structure_matches_dense_elimination(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 60))
+    dens = rng.uniform(0.02, 0.2)
+    rows, cols = [], []
+    for i in range(n):
+        for j in range(i):
+            if rng.random() < dens:
+                rows.append(i)
+                cols.append(j)
+    perm = rng.permutation(n)
+    iperm = np.empty(n, dtype=int)
+    iperm[perm] = np.arange(n)
+    colrows = S.permute_lower(rows, cols, iperm)
+    struct, par = S.column_structures(colrows)
+    prow = [iperm[r] for r in rows]
+    pcol = [iperm[c] for c in cols]
+    M, par_dense = _dense_symbolic(n, prow, pcol)
+    assert np.array_equal(par, par_dense)
+    for j in range(n):
+        assert sorted(struct[j]) == list(np.nonzero(M[:, j])[0])
+
+
+def _check_min_degree(n, rows, cols, order):
+    """Replay elimination on a dense boolean adjacency matrix and check that each
+    pivot had the minimum current degree, with ties broken by smallest index."""
+    A = np.zeros((n, n), dtype=bool)
+    for i, j in zip(rows, cols):
+        if i != j:
+            A[i, j] = A[j, i] = True
+    alive = np.ones(n, dtype=bool)
+    for v in order:
+        deg = np.where(alive, (A & alive[None, :]).sum(axis=1), np.iinfo(np.int64).max)
+        best = np.min(deg)
+        assert deg[v] == best
+        assert v == np.nonzero(deg == best)[0][0]
+        nb = np.nonzero(A[v] & alive)[0]
+        for a in nb:
+            A[a, nb] = True
+            A[a, a] = False
+        alive[v] = False
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_min_degree_property(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(5, 50))
+    rows, cols = [], []
+    for i in range(n):
+        for j in range(i):
+            if rng.random() < 0.1:
+                rows.append(i)
+                cols.append(j)
+    order = S.min_degree_order(n, S.adjacency_from_lower(n, rows, cols))
+    assert sorted(order) == list(range(n))
+    _check_min_degree(n, rows, cols, order)
+
+
+def test_min_degree_small_graphs():
+    # path 0-1-2-3-4: endpoints have degree 1; after 0 goes, 1 has degree 1 and wins the tie
+    rows, cols = [1, 2, 3, 4], [0, 1, 2, 3]
+    assert list(S.min_degree_order(5, S.adjacency_from_lower(5, rows, cols))) == [0, 1, 2, 3, 4]
+    # star with centre 0 and leaves 1..5: leaves go first, then the centre ties with 5
+    rows, cols = [1, 2, 3, 4, 5], [0, 0, 0, 0, 0]
+    assert list(S.min_degree_order(6, S.adjacency_from_lower(6, rows, cols))) == [1, 2, 3, 4, 0, 5]
+
+
+def test_analyze_invariants_distillation():
+    from oracle.distillation import DistillationOCP
+    m = DistillationOCP(6, 5, 0.1, 2.5)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c)
+    n = m.n
+    perm, iperm, par = a["perm"], a["iperm"], a["parent"]
+    assert sorted(perm) == list(range(n))
+    assert np.all(iperm[perm] == np.arange(n))
+    # parent(j) > j, and the tree is postordered (every subtree is contiguous)
+    assert all(par[j] > j or par[j] == -1 for j in range(n))
+    first = np.arange(n)
+    for j in range(n):
+        if par[j] >= 0:
+            first[par[j]] = min(first[par[j]], first[j])
+    for j in range(n):
+        assert np.all(par[first[j]:j] >= 0)
+    # dense brute force on the permuted pattern gives the same factor pattern
+    M, par_dense = _dense_symbolic(n, [iperm[i] for i in r], [iperm[j] for j in c])
+    assert np.array_equal(par, par_dense)
+    assert a["nnz_L"] == int(M.sum())
+    # supernodes: contiguous cover; stored rows contain the exact structure of each column;
+    # a child's rows below its columns are contained in its parent's rows
+    sp_, rows_ = a["snode_ptr"], a["snode_rows"]
+    assert sp_[0] == 0 and sp_[-1] == n and np.all(np.diff(sp_) > 0)
+    for s in range(len(sp_) - 1):
+        f, l = sp_[s], sp_[s + 1]
+        R = set(rows_[s].tolist())
+        assert list(rows_[s][:l - f]) == list(range(f, l))
+        assert list(rows_[s]) == sorted(R)
+        for j in range(f, l):
+            assert set(np.nonzero(M[:, j])[0]) <= R
+        p = a["snode_parent"][s]
+        if p >= 0:
+            assert set(rows_[s][l - f:].tolist()) <= set(rows_[p].tolist())
+        else:
+            assert len(rows_[s]) == l - f
