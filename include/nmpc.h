@@ -1,0 +1,217 @@
+/*
+ * nmpc.h - C ABI of the MI355X parametric interior-point NMPC library.
+ *
+ * The library re-solves a direct-transcribed optimal control problem whose
+ * sparsity never changes (Section 3.1, eqs. 4-6).  Each solve runs the
+ * Lifted-KKT primal-dual interior-point method of Section 3.2 / Algorithm 2 on
+ * the GPU: model evaluation, condensed KKT assembly (eqs. 14, 17), numeric
+ * supernodal Cholesky (eqs. 20-21) and forward/back solves (eqs. 22-25).  The
+ * symbolic factorization (ordering, elimination tree, supernodes; eqs. 18-19)
+ * is computed once by nmpc_analyze and reused by every later iteration and
+ * re-solve, as in Algorithms 1-2.
+ *
+ * Conventions for every entry point:
+ *   - pointers marked "host" are ordinary CPU memory owned by the caller; the
+ *     library copies what it needs before returning and never keeps them;
+ *   - all floating point is IEEE binary64 (double);
+ *   - index arrays are int32 unless stated otherwise, 0-based;
+ *   - return value: NMPC_OK (0) on success, a negative NMPC_ERR_* code on a hard
+ *     error (nothing changed; nmpc_last_error() gives a message), or, from
+ *     nmpc_solve only, a positive solver outcome (the last iterate stays
+ *     readable);
+ *   - a handle may be used by one host thread at a time.
+ */
+#ifndef NMPC_H
+#define NMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nmpc_status;
+
+enum {
+    NMPC_OK = 0,
+    /* solver outcomes (nmpc_solve), Algorithm 2 termination */
+    NMPC_MAX_ITER = 1,          /* iteration limit reached before eq. (28) held */
+    NMPC_LINESEARCH_FAIL = 2,   /* backtracking exhausted (eq. 26) */
+    NMPC_REG_FAIL = 3,          /* inertia correction exceeded eta_max (eq. 13, 17) */
+    NMPC_NONFINITE = 4,         /* NaN/Inf in a model value */
+    /* hard errors */
+    NMPC_ERR_INVALID_ARG = -1,
+    NMPC_ERR_BAD_ORDER = -2,     /* e.g. solve before analyze */
+    NMPC_ERR_STRUCT_MISMATCH = -3,
+    NMPC_ERR_NO_DEVICE = -4,     /* no HIP device visible */
+    NMPC_ERR_HIP = -5,           /* a HIP runtime call failed */
+    NMPC_ERR_OOM = -6,
+    NMPC_ERR_UNSUPPORTED = -7
+};
+
+enum { NMPC_FAMILY_DISTILLATION = 1, NMPC_FAMILY_HEATED_PLATE = 2 };
+
+/* Problem structure: everything that fixes the sparsity pattern of the
+ * transcribed OCP (eq. 6) and its constant data.  Parameters that change
+ * between re-solves (x0, setpoints, disturbance trajectories, last control) go
+ * through nmpc_set_parameters instead. */
+typedef struct nmpc_structure {
+    int32_t family;      /* NMPC_FAMILY_* */
+    int32_t horizon;     /* H: number of implicit-Euler stages */
+    double dt;           /* stage length */
+    /* distillation column (Section 4.1 family) */
+    int32_t n_trays;     /* N trays; states per stage N + 2, controls (R, V) */
+    double alpha;        /* constant relative volatility */
+    double feed_flow;    /* F */
+    double move_penalty; /* rho on |u_k - u_{k-1}|^2 */
+    double x_lo, x_hi;   /* mole-fraction bounds */
+    double u_lo, u_hi;   /* bounds on R and V */
+    /* heated plate (Section 4.2 family) */
+    int32_t grid;        /* G: G x G interior nodes */
+    double t_hi;         /* upper temperature bound */
+    double c_lo, c_hi;   /* heater control bounds */
+} nmpc_structure;
+
+/* Interior-point constants (the paper leaves them open; see the design notes).
+ * nmpc_default_options fills the defaults. */
+typedef struct nmpc_options {
+    double tol;          /* epsilon_outer on E_0, eq. (28) */
+    double gamma;        /* equality relaxation of the lifting, eq. (16) */
+    double mu0_cold, mu0_warm, mu_min;
+    double kappa_eps;    /* inner test E_mu <= kappa_eps * mu, eq. (27) */
+    double kappa_mu, theta_mu;
+    double tau_min;      /* fraction-to-boundary */
+    double armijo;
+    int32_t ls_max;
+    int32_t max_iter;
+    double kappa_sigma;
+    double eta_first, eta_min, eta_max, kp_first, kp, km;
+    double bound_push, slack_push;
+    int32_t timing;      /* 1: record HIP events around each phase (device times in nmpc_result) */
+} nmpc_options;
+
+typedef struct nmpc_result {
+    int32_t status;      /* NMPC_OK or a positive outcome */
+    int32_t iters;       /* Newton iterations */
+    int32_t factorizations;
+    int32_t ls_trials;
+    double mu, eta, E0, objective;
+    double ms_total;     /* host wall time of the call */
+    double ms_eval, ms_assemble, ms_factor, ms_solve, ms_linesearch; /* device phase times (0 unless timing enabled) */
+    int32_t factor_launches; /* kernel launches spent in numeric factorizations */
+} nmpc_result;
+
+typedef struct nmpc_problem nmpc_problem;
+
+/* Default interior-point options. */
+void nmpc_default_options(nmpc_options* o);
+
+/* Create a problem handle for a transcribed OCP family (eq. 6).  *s is copied;
+ * the caller keeps ownership.  Builds the fixed Jacobian/Hessian/KKT patterns
+ * on the host.  Needs no GPU.  Errors: INVALID_ARG for bad sizes/family. */
+nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out);
+
+/* Release the handle and every host/device buffer it owns.  NULL is a no-op. */
+void nmpc_destroy(nmpc_problem* p);
+
+/* Sizes of the transcription: n variables, m_c dynamics rows, m_d inequality
+ * rows, nx states and nu controls per stage, nnz of the lower KKT pattern. */
+nmpc_status nmpc_sizes(const nmpc_problem* p, int32_t* n, int32_t* m_c, int32_t* m_d,
+                       int32_t* nx, int32_t* nu, int64_t* nnz_k);
+
+/* SymCholesky (eqs. 18-19): ordering, elimination tree, column counts,
+ * supernodes and all scatter maps, computed once on the host and uploaded to
+ * the device when one is present.  Idempotent: a second call is a no-op. */
+nmpc_status nmpc_analyze(nmpc_problem* p);
+
+/* Sizes of the symbolic analysis: supernode count, stored entries of the
+ * supernodal factor (explicit zeros included), exact nnz(L) and sum of
+ * squared column counts, total supernode row-list length, etree depth in
+ * supernodes.  BAD_ORDER before nmpc_analyze. */
+nmpc_status nmpc_symbolic_sizes(const nmpc_problem* p, int32_t* n_supernodes, int64_t* stored_l,
+                                int64_t* nnz_l, int64_t* flops, int64_t* rows_total, int32_t* depth);
+
+/* Export the symbolic analysis into caller-allocated host arrays (any may be
+ * NULL): perm[n] (new -> old), parent[n] (column etree in the final order,
+ * -1 for roots), colcount[n], snode_ptr[n_supernodes + 1],
+ * snode_rows_ptr[n_supernodes + 1] (int64) and snode_rows[rows_total]
+ * (sorted row indices of each supernode, its own columns first). */
+nmpc_status nmpc_export_symbolic(const nmpc_problem* p, int32_t* perm, int32_t* parent,
+                                 int32_t* colcount, int32_t* snode_ptr,
+                                 int64_t* snode_rows_ptr, int32_t* snode_rows);
+
+/* Export the structural patterns (host, caller-allocated, any may be NULL):
+ * Jacobian rows/cols of [c; d] (nnz_j entries, original variable order),
+ * lower Hessian rows/cols (nnz_w entries), lower KKT rows/cols (nnz_k
+ * entries, original order, in the library's slot order). */
+nmpc_status nmpc_pattern_sizes(const nmpc_problem* p, int64_t* nnz_j, int64_t* nnz_w, int64_t* nnz_k);
+nmpc_status nmpc_export_patterns(const nmpc_problem* p, int32_t* j_rows, int32_t* j_cols,
+                                 int32_t* w_rows, int32_t* w_cols, int32_t* k_rows, int32_t* k_cols);
+
+/* Parameters p_k of the next solve (eq. 4), host arrays copied before return:
+ * x0[nx] measured initial state; setpoint: distillation (xD*, xB*), plate
+ * target field [G*G]; traj: distillation feed composition zF[H] (NULL keeps
+ * the previous one); u_prev[nu]: control applied before stage 1 (NULL keeps
+ * the previous one).  Errors: INVALID_ARG on NULL x0 or non-finite values. */
+nmpc_status nmpc_set_parameters(nmpc_problem* p, const double* x0, const double* setpoint,
+                                const double* traj, const double* u_prev);
+
+/* One NMPC solve (Algorithm 2).  warm = 0: cold start from x0 repeated over
+ * the horizon with u_prev, mu = mu0_cold.  warm = 1: start from the last
+ * iterate held by the handle (Algorithm 1, z_{k+1} <- z*_k) with mu0_warm.
+ * opts NULL = defaults.  res may be NULL.  Returns NMPC_OK, a positive
+ * outcome, or an error (BAD_ORDER before analyze or warm without a previous
+ * solve; NO_DEVICE without a GPU). */
+nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, nmpc_result* res);
+
+/* Copy the last iterate to host arrays (any may be NULL): y[n], lam[m_c]
+ * (equality multipliers omega+ - omega-), omega_d[m_d], zL[n], zU[n],
+ * u1[nu] (first-stage control, Algorithm 1 line "extract"), x1[nx]. */
+nmpc_status nmpc_get_solution(const nmpc_problem* p, double* y, double* lam, double* omega_d,
+                              double* zL, double* zU, double* u1, double* x1);
+
+/* Full primal-dual iterate z = (y, s, omega, beta, zL, zU) with the lifted
+ * vectors of length m^l = 2 m_c + m_d ordered [plus rows, minus rows, d rows].
+ * get copies it out; set replaces the handle's iterate (a warm start from an
+ * arbitrary point).  Host arrays, none may be NULL. */
+nmpc_status nmpc_get_iterate(const nmpc_problem* p, double* y, double* s, double* omega,
+                             double* beta, double* zL, double* zU);
+nmpc_status nmpc_set_iterate(nmpc_problem* p, const double* y, const double* s, const double* omega,
+                             const double* beta, const double* zL, const double* zU);
+
+/* Model evaluation on the device (eqs. 3, 11): at y[n] with equality
+ * multipliers lam[m_c] and inequality multipliers lam_d[m_d], return f,
+ * grad[n], c[m_c], d[m_d], Jacobian values j_vals[nnz_j] and lower Hessian of
+ * the Lagrangian w_vals[nnz_w], in the slot order nmpc_export_patterns gives.
+ * Host arrays; outputs may be NULL. */
+nmpc_status nmpc_eval(nmpc_problem* p, const double* y, const double* lam, const double* lam_d,
+                      double* f, double* grad, double* c, double* d, double* j_vals, double* w_vals);
+
+/* NumCholesky (eqs. 20-21) of a caller-given matrix: k_vals[nnz_k] are the
+ * lower KKT values in slot order; eta is added to the diagonal.  On return
+ * *ok = 1 when every pivot was positive and finite.  l_vals (may be NULL)
+ * receives the supernodal factor: for supernode s, a column-major
+ * rows(s) x width(s) panel, panels in supernode order (stored_l values).
+ * Requires nmpc_analyze. */
+nmpc_status nmpc_factor(nmpc_problem* p, const double* k_vals, double eta, int32_t* ok,
+                        double* l_vals);
+
+/* Forward/back substitution with the factor of the last nmpc_factor or
+ * iteration (eqs. 22-25): solves K x = b, b and x in the original order. */
+nmpc_status nmpc_linear_solve(nmpc_problem* p, const double* b, double* x);
+
+/* Condensed assembly (eqs. 14, 17) at the handle's current iterate and mu:
+ * returns the lower KKT values without regularization and the right-hand
+ * side -r1 - G^T (Q r4 - r2). */
+nmpc_status nmpc_assemble(nmpc_problem* p, double mu, double* k_vals, double* rhs);
+
+/* Thread-local message for the last error on this thread. */
+const char* nmpc_last_error(void);
+
+/* 1 when a HIP device is visible, 0 otherwise. */
+int32_t nmpc_device_available(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMPC_H */

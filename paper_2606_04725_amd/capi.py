@@ -1,0 +1,99 @@
+"""ctypes binding of libnmpc.so (argument marshalling only).
+
+Every function keeps the C name and signature of include/nmpc.h.  Loading
+fails loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmpc.so")
+
+NMPC_OK = 0
+NMPC_MAX_ITER, NMPC_LINESEARCH_FAIL, NMPC_REG_FAIL, NMPC_NONFINITE = 1, 2, 3, 4
+NMPC_ERR_INVALID_ARG, NMPC_ERR_BAD_ORDER, NMPC_ERR_STRUCT_MISMATCH = -1, -2, -3
+NMPC_ERR_NO_DEVICE, NMPC_ERR_HIP, NMPC_ERR_OOM, NMPC_ERR_UNSUPPORTED = -4, -5, -6, -7
+NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE = 1, 2
+
+
+class nmpc_structure(C.Structure):
+    _fields_ = [("family", C.c_int32), ("horizon", C.c_int32), ("dt", C.c_double),
+                ("n_trays", C.c_int32), ("alpha", C.c_double), ("feed_flow", C.c_double),
+                ("move_penalty", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("u_lo", C.c_double), ("u_hi", C.c_double),
+                ("grid", C.c_int32), ("t_hi", C.c_double), ("c_lo", C.c_double), ("c_hi", C.c_double)]
+
+
+class nmpc_options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("gamma", C.c_double), ("mu0_cold", C.c_double),
+                ("mu0_warm", C.c_double), ("mu_min", C.c_double), ("kappa_eps", C.c_double),
+                ("kappa_mu", C.c_double), ("theta_mu", C.c_double), ("tau_min", C.c_double),
+                ("armijo", C.c_double), ("ls_max", C.c_int32), ("max_iter", C.c_int32),
+                ("kappa_sigma", C.c_double), ("eta_first", C.c_double), ("eta_min", C.c_double),
+                ("eta_max", C.c_double), ("kp_first", C.c_double), ("kp", C.c_double), ("km", C.c_double),
+                ("bound_push", C.c_double), ("slack_push", C.c_double), ("timing", C.c_int32)]
+
+
+class nmpc_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("factorizations", C.c_int32),
+                ("ls_trials", C.c_int32), ("mu", C.c_double), ("eta", C.c_double), ("E0", C.c_double),
+                ("objective", C.c_double), ("ms_total", C.c_double), ("ms_eval", C.c_double),
+                ("ms_assemble", C.c_double), ("ms_factor", C.c_double), ("ms_solve", C.c_double),
+                ("ms_linesearch", C.c_double), ("factor_launches", C.c_int32)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int32)
+_L = C.POINTER(C.c_int64)
+
+SIGNATURES = {
+    "nmpc_default_options": (None, [C.POINTER(nmpc_options)]),
+    "nmpc_create_problem": (C.c_int32, [C.POINTER(nmpc_structure), C.POINTER(_P)]),
+    "nmpc_destroy": (None, [_P]),
+    "nmpc_sizes": (C.c_int32, [_P, _I, _I, _I, _I, _I, _L]),
+    "nmpc_analyze": (C.c_int32, [_P]),
+    "nmpc_symbolic_sizes": (C.c_int32, [_P, _I, _L, _L, _L, _L, _I]),
+    "nmpc_export_symbolic": (C.c_int32, [_P, _I, _I, _I, _I, _L, _I]),
+    "nmpc_pattern_sizes": (C.c_int32, [_P, _L, _L, _L]),
+    "nmpc_export_patterns": (C.c_int32, [_P, _I, _I, _I, _I, _I, _I]),
+    "nmpc_set_parameters": (C.c_int32, [_P, _D, _D, _D, _D]),
+    "nmpc_solve": (C.c_int32, [_P, C.c_int32, C.POINTER(nmpc_options), C.POINTER(nmpc_result)]),
+    "nmpc_get_solution": (C.c_int32, [_P, _D, _D, _D, _D, _D, _D, _D]),
+    "nmpc_get_iterate": (C.c_int32, [_P, _D, _D, _D, _D, _D, _D]),
+    "nmpc_set_iterate": (C.c_int32, [_P, _D, _D, _D, _D, _D, _D]),
+    "nmpc_eval": (C.c_int32, [_P, _D, _D, _D, _D, _D, _D, _D, _D, _D]),
+    "nmpc_factor": (C.c_int32, [_P, _D, C.c_double, _I, _D]),
+    "nmpc_linear_solve": (C.c_int32, [_P, _D, _D]),
+    "nmpc_assemble": (C.c_int32, [_P, C.c_double, _D, _D]),
+    "nmpc_last_error": (C.c_char_p, []),
+    "nmpc_device_available": (C.c_int32, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libnmpc.so once; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2606_04725_amd.build` (needs hipcc)")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def declared_symbols(header=None):
+    """Names of the functions the public header declares."""
+    import re
+    header = header or os.path.join(os.path.dirname(HERE), "include", "nmpc.h")
+    txt = open(header).read()
+    return sorted(set(re.findall(r"\b(nmpc_[a-z_0-9]+)\s*\(", txt)))

@@ -1,0 +1,125 @@
+// Direct transcription of the supported OCP families into fixed sparsity
+// patterns (Section 3.1, eqs. 5-6).  Only structure is built here; numeric
+// values come from the device eval kernels.
+#include <algorithm>
+#include <cmath>
+
+#include "distill_layout.h"
+#include "internal.h"
+
+namespace nmpc {
+
+static void finish_k_count(Structure& st) {
+    // nnz of the lower pattern of W + J^T J + diag (structural union)
+    std::vector<int64_t> keys;
+    const int64_t n = st.n;
+    keys.reserve(st.wrow.size() + 8 * st.jcol.size() + st.n);
+    for (size_t e = 0; e < st.wrow.size(); ++e) {
+        int64_t a = std::max(st.wrow[e], st.wcol[e]), b = std::min(st.wrow[e], st.wcol[e]);
+        keys.push_back(a * n + b);
+    }
+    const int m = st.m_c + st.m_d;
+    for (int r = 0; r < m; ++r) {
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p)
+            for (int q = st.jptr[r]; q <= p; ++q) {
+                int64_t a = std::max(st.jcol[p], st.jcol[q]), b = std::min(st.jcol[p], st.jcol[q]);
+                keys.push_back(a * n + b);
+            }
+    }
+    for (int64_t j = 0; j < n; ++j) keys.push_back(j * n + j);
+    std::sort(keys.begin(), keys.end());
+    st.nnz_k = std::unique(keys.begin(), keys.end()) - keys.begin();
+}
+
+static bool build_distillation(const nmpc_structure& s, Structure& st, std::string& err) {
+    if (s.n_trays < 2 || s.horizon < 1 || !(s.dt > 0) || !(s.alpha > 1.0) || !(s.feed_flow >= 0) ||
+        !(s.x_lo < s.x_hi) || !(s.u_lo < s.u_hi) || !(s.move_penalty >= 0)) {
+        err = "distillation: need n_trays >= 2, horizon >= 1, dt > 0, alpha > 1, valid bounds";
+        return false;
+    }
+    DistillDims D;
+    D.N = s.n_trays;
+    D.nx = D.N + 2;
+    D.ns = D.nx + 2;
+    D.H = s.horizon;
+    D.fd = D.N / 2;
+    st.nx = D.nx;
+    st.nu = 2;
+    st.H = D.H;
+    st.n = D.H * D.ns;
+    st.m_c = D.H * D.nx;
+    st.m_d = 2 * D.H;
+    const int m = st.m_c + st.m_d;
+    st.jptr.assign(m + 1, 0);
+    st.jcol.clear();
+    st.jrow.clear();
+    for (int k = 0; k < D.H; ++k)
+        for (int i = 0; i < D.nx; ++i) {
+            const int row = k * D.nx + i;
+            const int base = k * D.ns;
+            if (k > 0) st.jcol.push_back((k - 1) * D.ns + i);
+            if (i > 0) st.jcol.push_back(base + i - 1);
+            st.jcol.push_back(base + i);
+            if (i < D.nx - 1) st.jcol.push_back(base + i + 1);
+            if (i > 0) st.jcol.push_back(base + D.nx);
+            st.jcol.push_back(base + D.nx + 1);
+            st.jptr[row + 1] = (int)st.jcol.size();
+            if (st.jptr[row + 1] - st.jptr[row] != dl_row_nnz(D, k, i)) {
+                err = "internal: distillation row layout mismatch";
+                return false;
+            }
+        }
+    for (int k = 0; k < D.H; ++k)
+        for (int r = 0; r < 2; ++r) {
+            st.jcol.push_back(k * D.ns + D.nx);
+            st.jcol.push_back(k * D.ns + D.nx + 1);
+            st.jptr[st.m_c + 2 * k + r + 1] = (int)st.jcol.size();
+        }
+    st.jrow.resize(st.jcol.size());
+    for (int r = 0; r < m; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) st.jrow[p] = r;
+    // lower Hessian slots in the kernel's order
+    const int nw = dl_nnz_w(D);
+    st.wrow.assign(nw, 0);
+    st.wcol.assign(nw, 0);
+    for (int k = 0; k < D.H; ++k) {
+        const int o = k * dl_wstage(D), b = k * D.ns, iR = b + D.nx, iV = b + D.nx + 1;
+        for (int i = 0; i < D.nx; ++i) {
+            st.wrow[o + i] = b + i;            st.wcol[o + i] = b + i;
+            st.wrow[o + D.nx + i] = iR;        st.wcol[o + D.nx + i] = b + i;
+            st.wrow[o + 2 * D.nx + 1 + i] = iV; st.wcol[o + 2 * D.nx + 1 + i] = b + i;
+        }
+        st.wrow[o + 2 * D.nx] = iR;     st.wcol[o + 2 * D.nx] = iR;
+        st.wrow[o + 3 * D.nx + 1] = iV; st.wcol[o + 3 * D.nx + 1] = iV;
+        if (k > 0) {
+            const int c = dl_wcross(D, k);
+            st.wrow[c] = iR;     st.wcol[c] = iR - D.ns;
+            st.wrow[c + 1] = iV; st.wcol[c + 1] = iV - D.ns;
+        }
+    }
+    st.lb.assign(st.n, 0.0);
+    st.ub.assign(st.n, 0.0);
+    for (int k = 0; k < D.H; ++k)
+        for (int j = 0; j < D.ns; ++j) {
+            const bool is_x = j < D.nx;
+            st.lb[k * D.ns + j] = is_x ? s.x_lo : s.u_lo;
+            st.ub[k * D.ns + j] = is_x ? s.x_hi : s.u_hi;
+        }
+    return true;
+}
+
+bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) {
+    out = Structure();
+    out.desc = s;
+    bool ok = false;
+    if (s.family == NMPC_FAMILY_DISTILLATION) {
+        ok = build_distillation(s, out, err);
+    } else {
+        err = "unsupported problem family";
+        return false;
+    }
+    if (ok) finish_k_count(out);
+    return ok;
+}
+
+}  // namespace nmpc

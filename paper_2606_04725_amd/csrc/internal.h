@@ -1,0 +1,94 @@
+// Internal host-side data structures of the NMPC library.
+#ifndef NMPC_INTERNAL_H
+#define NMPC_INTERNAL_H
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nmpc.h"
+
+namespace nmpc {
+
+// Fixed structure of one transcribed OCP (eq. 6): sizes, sparsity patterns and
+// bounds, built once on the host by the family's transcription.
+struct Structure {
+    nmpc_structure desc{};
+    int n = 0, m_c = 0, m_d = 0, nx = 0, nu = 0, H = 0;
+    // Jacobian of [c; d] in CSR (rows m_c + m_d), columns ascending per row
+    std::vector<int32_t> jptr, jcol, jrow;
+    // lower Hessian pattern, slot order as the eval kernel writes it
+    std::vector<int32_t> wrow, wcol;
+    std::vector<double> lb, ub;
+    int64_t nnz_k = 0;
+};
+
+// Result of SymCholesky (eqs. 18-19) plus every map the numeric phase needs.
+struct Symbolic {
+    int n = 0;
+    std::vector<int32_t> perm, iperm, parent, colcount;
+    int64_t nnz_l = 0, flops = 0;
+    // supernodes
+    int nsn = 0;
+    std::vector<int32_t> sn_ptr;              // first column of each supernode (+ n)
+    std::vector<int64_t> sn_rows_ptr;         // into sn_rows
+    std::vector<int32_t> sn_rows;             // sorted rows, own columns first
+    std::vector<int32_t> sn_parent;
+    std::vector<int32_t> child_ptr, child_list;
+    std::vector<int32_t> level_ptr, level_list;  // bottom-up levels of the supernodal tree
+    int depth = 0;
+    int max_front = 0;
+    // storage offsets
+    std::vector<int64_t> l_off;               // rows * width panel per supernode
+    std::vector<int64_t> u_off;               // (rows - width)^2 update block per supernode
+    std::vector<int64_t> uv_off;              // (rows - width) update vector per supernode
+    std::vector<int64_t> rel_off;             // relative positions of below rows in the parent
+    std::vector<int32_t> rel;
+    int64_t stored_l = 0, stored_u = 0, stored_uv = 0;
+    // KKT slots in factor order (sorted by permuted column, then row)
+    std::vector<int32_t> k_ptr;               // per supernode
+    std::vector<int32_t> k_fpos;              // position in the supernode front (col-major)
+    std::vector<int32_t> k_orow, k_ocol;      // original (row, col), row >= col
+    std::vector<int32_t> k_wslot;             // Hessian slot or -1
+    std::vector<int32_t> k_diag;              // variable index if diagonal else -1
+    std::vector<int32_t> kc_ptr, kc_a, kc_b, kc_r;  // J^T Q J contributions per slot
+    // transposed Jacobian: per variable, (slot, row)
+    std::vector<int32_t> jt_ptr, jt_slot, jt_row;
+};
+
+struct Device;   // device-side buffers, defined in the HIP translation unit
+
+struct Problem {
+    Structure st;
+    Symbolic sym;
+    bool analyzed = false;
+    bool have_iterate = false;
+    // parameters (host copies)
+    std::vector<double> x0, setpoint, traj, u_prev;
+    Device* dev = nullptr;
+};
+
+// transcription (family.cpp)
+bool build_structure(const nmpc_structure& s, Structure& out, std::string& err);
+// SymCholesky (symbolic.cpp)
+void symbolic_analyze(const Structure& st, Symbolic& sym);
+// device side (device.hip)
+nmpc_status device_init(Problem& p, std::string& err);
+void device_free(Problem& p);
+nmpc_status device_set_parameters(Problem& p, std::string& err);
+nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err);
+nmpc_status device_get_iterate(const Problem& p, double* y, double* s, double* om, double* be,
+                               double* zl, double* zu, std::string& err);
+nmpc_status device_set_iterate(Problem& p, const double* y, const double* s, const double* om,
+                               const double* be, const double* zl, const double* zu, std::string& err);
+nmpc_status device_eval(Problem& p, const double* y, const double* lam, const double* lam_d, double* f,
+                        double* grad, double* c, double* d, double* jv, double* wv, std::string& err);
+nmpc_status device_factor(Problem& p, const double* kv, double eta, int32_t* ok, double* lv,
+                          std::string& err);
+nmpc_status device_linear_solve(Problem& p, const double* b, double* x, std::string& err);
+nmpc_status device_assemble(Problem& p, double mu, double* kv, double* rhs, std::string& err);
+bool device_present();
+
+}  // namespace nmpc
+
+#endif

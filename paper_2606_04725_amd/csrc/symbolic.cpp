@@ -1,0 +1,403 @@
+// SymCholesky on the host (Section 3.2.3, eqs. 18-19, Fig. 1), computed once
+// per problem structure and reused by every numeric factorization.
+//
+//  1. Fill-reducing ordering P: exact minimum degree on the elimination graph
+//     of the condensed matrix pattern (true degrees, no mass elimination, no
+//     element absorption); ties go to the smallest original index.
+//  2. Elimination tree parent(j) = min{i > j : L_ij != 0} and column
+//     structures struct(L_*j) = struct(K_P lower col j) united with the
+//     structures of j's children minus the children themselves.
+//  3. Postorder (children and roots in increasing index) composed into P, then
+//     step 2 again in the final order.
+//  4. Fundamental supernodes, then relaxed amalgamation: walking supernodes in
+//     order, the immediately preceding node is merged into the current one
+//     when it is that node's child, the merged width is at most 64, and the
+//     merged width is at most 8 or its explicit zeros are at most a quarter of
+//     its stored entries.
+//  5. Maps for the numeric phase: factor-order KKT slots with their position in
+//     the supernode front, the J^T Q J contributions of each slot, relative
+//     row positions of every child's update block inside its parent, and a
+//     bottom-up level schedule of the supernodal tree.
+#include <algorithm>
+#include <cstdint>
+#include <queue>
+#include <stdexcept>
+#include <utility>
+
+#include "internal.h"
+
+namespace nmpc {
+
+namespace {
+
+constexpr int kAmalgMaxWidth = 64;
+constexpr int kAmalgSmall = 8;
+
+using Adj = std::vector<std::vector<int32_t>>;
+
+void sorted_insert_union(std::vector<int32_t>& dst, const std::vector<int32_t>& src) {
+    std::vector<int32_t> out;
+    out.reserve(dst.size() + src.size());
+    std::set_union(dst.begin(), dst.end(), src.begin(), src.end(), std::back_inserter(out));
+    dst.swap(out);
+}
+
+void erase_sorted(std::vector<int32_t>& v, int32_t x) {
+    auto it = std::lower_bound(v.begin(), v.end(), x);
+    if (it != v.end() && *it == x) v.erase(it);
+}
+
+// Exact minimum degree (returns perm, new -> old).
+std::vector<int32_t> min_degree(int n, Adj adj) {
+    using Item = std::pair<int64_t, int32_t>;   // (degree, vertex); min-heap
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int v = 0; v < n; ++v) heap.push({(int64_t)adj[v].size(), v});
+    std::vector<char> done(n, 0);
+    std::vector<int32_t> order;
+    order.reserve(n);
+    while (!heap.empty()) {
+        auto [d, v] = heap.top();
+        heap.pop();
+        if (done[v] || d != (int64_t)adj[v].size()) continue;
+        done[v] = 1;
+        order.push_back(v);
+        const std::vector<int32_t> nb = adj[v];
+        for (int32_t a : nb) {
+            sorted_insert_union(adj[a], nb);
+            erase_sorted(adj[a], a);
+            erase_sorted(adj[a], v);
+            heap.push({(int64_t)adj[a].size(), a});
+        }
+        adj[v].clear();
+        adj[v].shrink_to_fit();
+    }
+    if ((int)order.size() != n) throw std::runtime_error("minimum degree: incomplete order");
+    return order;
+}
+
+// Lower pattern of P K P^T as sorted per-column row lists (diagonal included).
+Adj permute_lower(int n, const std::vector<std::pair<int32_t, int32_t>>& ent,
+                  const std::vector<int32_t>& iperm) {
+    Adj col(n);
+    for (auto [i, j] : ent) {
+        int a = iperm[i], b = iperm[j];
+        if (a < b) std::swap(a, b);
+        col[b].push_back(a);
+    }
+    for (int j = 0; j < n; ++j) {
+        col[j].push_back(j);
+        std::sort(col[j].begin(), col[j].end());
+        col[j].erase(std::unique(col[j].begin(), col[j].end()), col[j].end());
+    }
+    return col;
+}
+
+// Column structures of L and the elimination tree.
+void column_structures(const Adj& colrows, Adj& strct, std::vector<int32_t>& parent) {
+    const int n = (int)colrows.size();
+    strct.assign(n, {});
+    parent.assign(n, -1);
+    std::vector<std::vector<int32_t>> children(n);
+    for (int j = 0; j < n; ++j) {
+        std::vector<int32_t> s = colrows[j];
+        for (int32_t c : children[j]) {
+            std::vector<int32_t> t(strct[c].begin() + 1, strct[c].end());  // drop c itself
+            sorted_insert_union(s, t);
+        }
+        // every row is >= j: colrows has rows >= j, children's rows beyond c are >= j
+        strct[j] = std::move(s);
+        if (strct[j].size() > 1) {
+            parent[j] = strct[j][1];
+            children[parent[j]].push_back(j);
+        }
+    }
+}
+
+std::vector<int32_t> postorder(const std::vector<int32_t>& parent) {
+    const int n = (int)parent.size();
+    std::vector<std::vector<int32_t>> children(n);
+    std::vector<int32_t> roots;
+    for (int j = 0; j < n; ++j) {
+        if (parent[j] < 0) roots.push_back(j);
+        else children[parent[j]].push_back(j);
+    }
+    std::vector<int32_t> post;
+    post.reserve(n);
+    std::vector<std::pair<int32_t, size_t>> stack;
+    for (int32_t r : roots) {
+        stack.push_back({r, 0});
+        while (!stack.empty()) {
+            auto& top = stack.back();
+            if (top.second < children[top.first].size()) {
+                int32_t c = children[top.first][top.second++];
+                stack.push_back({c, 0});
+            } else {
+                post.push_back(top.first);
+                stack.pop_back();
+            }
+        }
+    }
+    return post;
+}
+
+struct SNode {
+    int32_t f, l;
+    std::vector<int32_t> below;
+    int64_t stored, zeros;
+};
+
+}  // namespace
+
+void symbolic_analyze(const Structure& st, Symbolic& sym) {
+    const int n = st.n;
+    sym = Symbolic();
+    sym.n = n;
+    // ---- lower pattern of K = W + J^T J + diag (original indices) ------------
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    for (size_t e = 0; e < st.wrow.size(); ++e)
+        ent.push_back({std::max(st.wrow[e], st.wcol[e]), std::min(st.wrow[e], st.wcol[e])});
+    const int m = st.m_c + st.m_d;
+    for (int r = 0; r < m; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p)
+            for (int q = st.jptr[r]; q <= p; ++q)
+                ent.push_back({std::max(st.jcol[p], st.jcol[q]), std::min(st.jcol[p], st.jcol[q])});
+    for (int j = 0; j < n; ++j) ent.push_back({j, j});
+    std::sort(ent.begin(), ent.end());
+    ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
+    // ---- 1. exact minimum degree ----------------------------------------------
+    Adj adj(n);
+    for (auto [i, j] : ent)
+        if (i != j) {
+            adj[i].push_back(j);
+            adj[j].push_back(i);
+        }
+    for (auto& a : adj) {
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+    }
+    std::vector<int32_t> perm_md = min_degree(n, std::move(adj));
+    std::vector<int32_t> iperm(n);
+    for (int k = 0; k < n; ++k) iperm[perm_md[k]] = k;
+    // ---- 2-3. etree, postorder, final order -----------------------------------
+    Adj strct;
+    std::vector<int32_t> parent;
+    column_structures(permute_lower(n, ent, iperm), strct, parent);
+    std::vector<int32_t> post = postorder(parent);
+    sym.perm.resize(n);
+    for (int k = 0; k < n; ++k) sym.perm[k] = perm_md[post[k]];
+    sym.iperm.resize(n);
+    for (int k = 0; k < n; ++k) sym.iperm[sym.perm[k]] = k;
+    column_structures(permute_lower(n, ent, sym.iperm), strct, parent);
+    sym.parent = parent;
+    sym.colcount.resize(n);
+    sym.nnz_l = 0;
+    sym.flops = 0;
+    for (int j = 0; j < n; ++j) {
+        sym.colcount[j] = (int32_t)strct[j].size();
+        sym.nnz_l += sym.colcount[j];
+        sym.flops += (int64_t)sym.colcount[j] * sym.colcount[j];
+    }
+    // ---- 4. supernodes ----------------------------------------------------------
+    std::vector<int32_t> nchild(n, 0);
+    for (int j = 0; j < n; ++j)
+        if (parent[j] >= 0) nchild[parent[j]]++;
+    std::vector<int32_t> starts{0};
+    for (int j = 0; j + 1 < n; ++j) {
+        bool same = parent[j] == j + 1 && nchild[j + 1] == 1 && sym.colcount[j] == sym.colcount[j + 1] + 1;
+        if (!same) starts.push_back(j + 1);
+    }
+    std::vector<SNode> out;
+    for (size_t s = 0; s < starts.size(); ++s) {
+        SNode nd;
+        nd.f = starts[s];
+        nd.l = s + 1 < starts.size() ? starts[s + 1] : n;
+        for (int32_t r : strct[nd.f])
+            if (r >= nd.l) nd.below.push_back(r);
+        const int64_t w = nd.l - nd.f;
+        nd.stored = w * (w + 1) / 2 + w * (int64_t)nd.below.size();
+        nd.zeros = 0;
+        while (!out.empty()) {
+            const SNode& prev = out.back();
+            if (prev.l != nd.f || parent[prev.l - 1] != nd.f) break;
+            const int64_t mw = nd.l - prev.f;
+            const int64_t stored = mw * (mw + 1) / 2 + mw * (int64_t)nd.below.size();
+            const int64_t zeros = stored - (prev.stored - prev.zeros) - (nd.stored - nd.zeros);
+            const bool ok = mw <= kAmalgMaxWidth && (mw <= kAmalgSmall || 4 * zeros <= stored);
+            if (!ok) break;
+            nd.f = prev.f;
+            nd.stored = stored;
+            nd.zeros = zeros;
+            out.pop_back();
+        }
+        out.push_back(std::move(nd));
+    }
+    const int nsn = (int)out.size();
+    sym.nsn = nsn;
+    sym.sn_ptr.resize(nsn + 1);
+    sym.sn_rows_ptr.assign(nsn + 1, 0);
+    for (int s = 0; s < nsn; ++s) {
+        sym.sn_ptr[s] = out[s].f;
+        const int w = out[s].l - out[s].f;
+        sym.sn_rows_ptr[s + 1] = sym.sn_rows_ptr[s] + w + (int64_t)out[s].below.size();
+    }
+    sym.sn_ptr[nsn] = n;
+    sym.sn_rows.resize(sym.sn_rows_ptr[nsn]);
+    for (int s = 0; s < nsn; ++s) {
+        int64_t o = sym.sn_rows_ptr[s];
+        for (int c = out[s].f; c < out[s].l; ++c) sym.sn_rows[o++] = c;
+        for (int32_t r : out[s].below) sym.sn_rows[o++] = r;
+    }
+    out.clear();
+    std::vector<int32_t> col2sn(n);
+    for (int s = 0; s < nsn; ++s)
+        for (int c = sym.sn_ptr[s]; c < sym.sn_ptr[s + 1]; ++c) col2sn[c] = s;
+    sym.sn_parent.assign(nsn, -1);
+    for (int s = 0; s < nsn; ++s) {
+        const int last = sym.sn_ptr[s + 1] - 1;
+        if (parent[last] >= 0) sym.sn_parent[s] = col2sn[parent[last]];
+    }
+    // children lists (increasing order) and bottom-up levels
+    sym.child_ptr.assign(nsn + 1, 0);
+    for (int s = 0; s < nsn; ++s)
+        if (sym.sn_parent[s] >= 0) sym.child_ptr[sym.sn_parent[s] + 1]++;
+    for (int s = 0; s < nsn; ++s) sym.child_ptr[s + 1] += sym.child_ptr[s];
+    sym.child_list.assign(sym.child_ptr[nsn], 0);
+    {
+        std::vector<int32_t> fill(sym.child_ptr.begin(), sym.child_ptr.end() - 1);
+        for (int s = 0; s < nsn; ++s)
+            if (sym.sn_parent[s] >= 0) sym.child_list[fill[sym.sn_parent[s]]++] = s;
+    }
+    std::vector<int32_t> lev(nsn, 0);
+    int maxlev = 0;
+    for (int s = 0; s < nsn; ++s) {
+        for (int c = sym.child_ptr[s]; c < sym.child_ptr[s + 1]; ++c)
+            lev[s] = std::max(lev[s], lev[sym.child_list[c]] + 1);
+        maxlev = std::max(maxlev, lev[s]);
+    }
+    sym.depth = nsn ? maxlev + 1 : 0;
+    sym.level_ptr.assign(sym.depth + 1, 0);
+    for (int s = 0; s < nsn; ++s) sym.level_ptr[lev[s] + 1]++;
+    for (int L = 0; L < sym.depth; ++L) sym.level_ptr[L + 1] += sym.level_ptr[L];
+    sym.level_list.assign(nsn, 0);
+    {
+        std::vector<int32_t> fill(sym.level_ptr.begin(), sym.level_ptr.end() - 1);
+        for (int s = 0; s < nsn; ++s) sym.level_list[fill[lev[s]]++] = s;
+    }
+    // storage offsets
+    sym.l_off.assign(nsn + 1, 0);
+    sym.u_off.assign(nsn + 1, 0);
+    sym.uv_off.assign(nsn + 1, 0);
+    sym.max_front = 0;
+    for (int s = 0; s < nsn; ++s) {
+        const int64_t w = sym.sn_ptr[s + 1] - sym.sn_ptr[s];
+        const int64_t mr = sym.sn_rows_ptr[s + 1] - sym.sn_rows_ptr[s];
+        sym.l_off[s + 1] = sym.l_off[s] + mr * w;
+        sym.u_off[s + 1] = sym.u_off[s] + (mr - w) * (mr - w);
+        sym.uv_off[s + 1] = sym.uv_off[s] + (mr - w);
+        sym.max_front = std::max<int>(sym.max_front, (int)mr);
+    }
+    sym.stored_l = sym.l_off[nsn];
+    sym.stored_u = sym.u_off[nsn];
+    sym.stored_uv = sym.uv_off[nsn];
+    // relative positions of each supernode's below rows inside its parent's rows
+    sym.rel_off.assign(nsn + 1, 0);
+    for (int s = 0; s < nsn; ++s) sym.rel_off[s + 1] = sym.rel_off[s] + (sym.uv_off[s + 1] - sym.uv_off[s]);
+    sym.rel.assign(sym.rel_off[nsn], 0);
+    for (int s = 0; s < nsn; ++s) {
+        const int p = sym.sn_parent[s];
+        const int w = sym.sn_ptr[s + 1] - sym.sn_ptr[s];
+        const int32_t* rs = &sym.sn_rows[sym.sn_rows_ptr[s]];
+        const int64_t nb = sym.uv_off[s + 1] - sym.uv_off[s];
+        if (nb == 0) continue;
+        if (p < 0) throw std::runtime_error("root supernode with rows below");
+        const int32_t* pb = &sym.sn_rows[sym.sn_rows_ptr[p]];
+        const int32_t* pe = &sym.sn_rows[sym.sn_rows_ptr[p + 1]];
+        for (int64_t t = 0; t < nb; ++t) {
+            const int32_t r = rs[w + t];
+            const int32_t* it = std::lower_bound(pb, pe, r);
+            if (it == pe || *it != r) throw std::runtime_error("child rows not contained in parent");
+            sym.rel[sym.rel_off[s] + t] = (int32_t)(it - pb);
+        }
+    }
+    // ---- 5. KKT slots in factor order -----------------------------------------
+    const int64_t nn = n;
+    std::vector<int64_t> keys(ent.size());
+    for (size_t e = 0; e < ent.size(); ++e) {
+        int a = sym.iperm[ent[e].first], b = sym.iperm[ent[e].second];
+        if (a < b) std::swap(a, b);
+        keys[e] = (int64_t)b * nn + a;     // (column, row) in the permuted matrix
+    }
+    std::sort(keys.begin(), keys.end());
+    const int64_t nk = (int64_t)keys.size();
+    auto slot_of = [&](int32_t oi, int32_t oj) -> int32_t {
+        int a = sym.iperm[oi], b = sym.iperm[oj];
+        if (a < b) std::swap(a, b);
+        const int64_t key = (int64_t)b * nn + a;
+        auto it = std::lower_bound(keys.begin(), keys.end(), key);
+        if (it == keys.end() || *it != key) throw std::runtime_error("KKT slot not found");
+        return (int32_t)(it - keys.begin());
+    };
+    sym.k_fpos.resize(nk);
+    sym.k_orow.resize(nk);
+    sym.k_ocol.resize(nk);
+    sym.k_wslot.assign(nk, -1);
+    sym.k_diag.assign(nk, -1);
+    sym.k_ptr.assign(nsn + 1, 0);
+    for (int64_t t = 0; t < nk; ++t) {
+        const int32_t pj = (int32_t)(keys[t] / nn), pi = (int32_t)(keys[t] % nn);
+        const int s = col2sn[pj];
+        const int32_t* rb = &sym.sn_rows[sym.sn_rows_ptr[s]];
+        const int32_t* re = &sym.sn_rows[sym.sn_rows_ptr[s + 1]];
+        const int32_t* it = std::lower_bound(rb, re, pi);
+        if (it == re || *it != pi) throw std::runtime_error("KKT entry outside the factor pattern");
+        const int64_t mr = re - rb;
+        sym.k_fpos[t] = (int32_t)((it - rb) + (int64_t)(pj - sym.sn_ptr[s]) * mr);
+        const int32_t oi = sym.perm[pi], oj = sym.perm[pj];
+        sym.k_orow[t] = std::max(oi, oj);
+        sym.k_ocol[t] = std::min(oi, oj);
+        if (pi == pj) sym.k_diag[t] = oi;
+        sym.k_ptr[s + 1]++;
+    }
+    for (int s = 0; s < nsn; ++s) sym.k_ptr[s + 1] += sym.k_ptr[s];
+    for (size_t e = 0; e < st.wrow.size(); ++e) {
+        const int32_t t = slot_of(st.wrow[e], st.wcol[e]);
+        if (sym.k_wslot[t] >= 0) throw std::runtime_error("duplicate Hessian slot");
+        sym.k_wslot[t] = (int32_t)e;
+    }
+    // J^T Q J contributions: every pair of entries of every constraint row
+    struct Contrib { int32_t slot, a, b, r; };
+    std::vector<Contrib> cs;
+    for (int r = 0; r < m; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p)
+            for (int q = st.jptr[r]; q <= p; ++q) cs.push_back({slot_of(st.jcol[p], st.jcol[q]), p, q, r});
+    std::stable_sort(cs.begin(), cs.end(), [](const Contrib& x, const Contrib& y) { return x.slot < y.slot; });
+    sym.kc_ptr.assign(nk + 1, 0);
+    sym.kc_a.resize(cs.size());
+    sym.kc_b.resize(cs.size());
+    sym.kc_r.resize(cs.size());
+    for (size_t e = 0; e < cs.size(); ++e) {
+        sym.kc_ptr[cs[e].slot + 1]++;
+        sym.kc_a[e] = cs[e].a;
+        sym.kc_b[e] = cs[e].b;
+        sym.kc_r[e] = cs[e].r;
+    }
+    for (int64_t t = 0; t < nk; ++t) sym.kc_ptr[t + 1] += sym.kc_ptr[t];
+    // transposed Jacobian (per variable: slots and rows, rows ascending)
+    sym.jt_ptr.assign(n + 1, 0);
+    for (size_t p = 0; p < st.jcol.size(); ++p) sym.jt_ptr[st.jcol[p] + 1]++;
+    for (int j = 0; j < n; ++j) sym.jt_ptr[j + 1] += sym.jt_ptr[j];
+    sym.jt_slot.resize(st.jcol.size());
+    sym.jt_row.resize(st.jcol.size());
+    {
+        std::vector<int32_t> fill(sym.jt_ptr.begin(), sym.jt_ptr.end() - 1);
+        for (int r = 0; r < m; ++r)
+            for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) {
+                const int32_t j = st.jcol[p];
+                sym.jt_slot[fill[j]] = p;
+                sym.jt_row[fill[j]] = r;
+                fill[j]++;
+            }
+    }
+}
+
+}  // namespace nmpc

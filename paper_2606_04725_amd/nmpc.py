@@ -1,0 +1,191 @@
+"""Python face of the C ABI: a thin handle wrapper around libnmpc.so.
+
+All arithmetic runs inside the library (host symbolic analysis, HIP kernels for
+everything numeric); this module only converts NumPy arrays to pointers and
+status codes to exceptions.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import capi
+from .capi import nmpc_options, nmpc_result, nmpc_structure
+
+
+class NMPCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nmpc error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc < 0:
+        raise NMPCError(rc, capi.lib().nmpc_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(capi._D)
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(capi._I)
+
+
+def _lp(a):
+    return None if a is None else a.ctypes.data_as(capi._L)
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def default_options(**over) -> nmpc_options:
+    o = nmpc_options()
+    capi.lib().nmpc_default_options(C.byref(o))
+    for k, v in over.items():
+        setattr(o, k, v)
+    return o
+
+
+def distillation_structure(N, H, dt, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0):
+    s = nmpc_structure()
+    s.family = capi.NMPC_FAMILY_DISTILLATION
+    s.horizon, s.dt, s.n_trays, s.alpha, s.feed_flow = H, dt, N, alpha, F
+    s.move_penalty, s.x_lo, s.x_hi, s.u_lo, s.u_hi = rho, x_lo, x_hi, u_lo, u_hi
+    return s
+
+
+class Problem:
+    """One transcribed OCP structure: create -> analyze -> set_parameters -> solve."""
+
+    def __init__(self, structure: nmpc_structure):
+        L = capi.lib()
+        h = C.c_void_p()
+        _check(L.nmpc_create_problem(C.byref(structure), C.byref(h)))
+        self._h = h
+        n, mc, md, nx, nu = (C.c_int32() for _ in range(5))
+        nk = C.c_int64()
+        _check(L.nmpc_sizes(h, C.byref(n), C.byref(mc), C.byref(md), C.byref(nx), C.byref(nu), C.byref(nk)))
+        self.n, self.m_c, self.m_d, self.nx, self.nu = n.value, mc.value, md.value, nx.value, nu.value
+        self.nnz_k = nk.value
+        self.ml = 2 * self.m_c + self.m_d
+        self.analyzed = False
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().nmpc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- symbolic ------------------------------------------------------
+    def analyze(self):
+        _check(capi.lib().nmpc_analyze(self._h))
+        self.analyzed = True
+
+    def symbolic_sizes(self):
+        ns, sl, nl, fl, rt, dp = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(capi.lib().nmpc_symbolic_sizes(self._h, C.byref(ns), C.byref(sl), C.byref(nl), C.byref(fl),
+                                              C.byref(rt), C.byref(dp)))
+        return dict(n_supernodes=ns.value, stored_l=sl.value, nnz_l=nl.value, flops=fl.value,
+                    rows_total=rt.value, depth=dp.value)
+
+    def export_symbolic(self):
+        z = self.symbolic_sizes()
+        n, ns = self.n, z["n_supernodes"]
+        perm, parent, cc = (np.empty(n, np.int32) for _ in range(3))
+        sp = np.empty(ns + 1, np.int32)
+        rp = np.empty(ns + 1, np.int64)
+        rows = np.empty(z["rows_total"], np.int32)
+        _check(capi.lib().nmpc_export_symbolic(self._h, _ip(perm), _ip(parent), _ip(cc), _ip(sp), _lp(rp), _ip(rows)))
+        return dict(perm=perm, parent=parent, colcount=cc, snode_ptr=sp, snode_rows_ptr=rp, snode_rows=rows, **z)
+
+    def patterns(self):
+        nj, nw, nk = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(capi.lib().nmpc_pattern_sizes(self._h, C.byref(nj), C.byref(nw), C.byref(nk)))
+        jr, jc = np.empty(nj.value, np.int32), np.empty(nj.value, np.int32)
+        wr, wc = np.empty(nw.value, np.int32), np.empty(nw.value, np.int32)
+        kr = kc = None
+        if self.analyzed:
+            kr, kc = np.empty(nk.value, np.int32), np.empty(nk.value, np.int32)
+        _check(capi.lib().nmpc_export_patterns(self._h, _ip(jr), _ip(jc), _ip(wr), _ip(wc), _ip(kr), _ip(kc)))
+        return dict(j_rows=jr, j_cols=jc, w_rows=wr, w_cols=wc, k_rows=kr, k_cols=kc)
+
+    # ---- parameters and solves -------------------------------------------
+    def set_parameters(self, x0, setpoint=None, traj=None, u_prev=None):
+        x0 = _f64(x0, self.nx)
+        sp = None if setpoint is None else _f64(setpoint)
+        tr = None if traj is None else _f64(traj)
+        up = None if u_prev is None else _f64(u_prev, self.nu)
+        _check(capi.lib().nmpc_set_parameters(self._h, _dp(x0), _dp(sp), _dp(tr), _dp(up)))
+
+    def solve(self, warm=False, options: nmpc_options | None = None) -> nmpc_result:
+        r = nmpc_result()
+        rc = capi.lib().nmpc_solve(self._h, 1 if warm else 0, None if options is None else C.byref(options),
+                                   C.byref(r))
+        _check(rc)
+        return r
+
+    def solution(self):
+        y, zl, zu = np.empty(self.n), np.empty(self.n), np.empty(self.n)
+        lam, om_d = np.empty(self.m_c), np.empty(max(self.m_d, 1))
+        u1, x1 = np.empty(self.nu), np.empty(self.nx)
+        _check(capi.lib().nmpc_get_solution(self._h, _dp(y), _dp(lam), _dp(om_d), _dp(zl), _dp(zu), _dp(u1),
+                                            _dp(x1)))
+        return dict(y=y, lam=lam, omega_d=om_d[:self.m_d], zL=zl, zU=zu, u1=u1, x1=x1)
+
+    def get_iterate(self):
+        n, ml = self.n, self.ml
+        a = [np.empty(n), np.empty(ml), np.empty(ml), np.empty(ml), np.empty(n), np.empty(n)]
+        _check(capi.lib().nmpc_get_iterate(self._h, *(_dp(v) for v in a)))
+        return dict(zip(("y", "s", "omega", "beta", "zL", "zU"), a))
+
+    def set_iterate(self, y, s, omega, beta, zL, zU):
+        n, ml = self.n, self.ml
+        a = [_f64(y, n), _f64(s, ml), _f64(omega, ml), _f64(beta, ml), _f64(zL, n), _f64(zU, n)]
+        _check(capi.lib().nmpc_set_iterate(self._h, *(_dp(v) for v in a)))
+
+    # ---- single steps -------------------------------------------------------
+    def eval(self, y, lam, lam_d):
+        z = self.pattern_counts()
+        f = np.empty(1)
+        g, c, d = np.empty(self.n), np.empty(self.m_c), np.empty(max(self.m_d, 1))
+        jv, wv = np.empty(z[0]), np.empty(z[1])
+        _check(capi.lib().nmpc_eval(self._h, _dp(_f64(y, self.n)), _dp(_f64(lam, self.m_c)),
+                                    _dp(_f64(lam_d, self.m_d)), _dp(f), _dp(g), _dp(c), _dp(d), _dp(jv), _dp(wv)))
+        return dict(f=float(f[0]), grad=g, c=c, d=d[:self.m_d], j_vals=jv, w_vals=wv)
+
+    def pattern_counts(self):
+        nj, nw, nk = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(capi.lib().nmpc_pattern_sizes(self._h, C.byref(nj), C.byref(nw), C.byref(nk)))
+        return nj.value, nw.value, nk.value
+
+    def factor(self, k_vals, eta=0.0, want_l=True):
+        ok = C.c_int32()
+        lv = np.empty(self.symbolic_sizes()["stored_l"]) if want_l else None
+        _check(capi.lib().nmpc_factor(self._h, _dp(_f64(k_vals, self.nnz_k)), float(eta), C.byref(ok), _dp(lv)))
+        return bool(ok.value), lv
+
+    def linear_solve(self, b):
+        x = np.empty(self.n)
+        _check(capi.lib().nmpc_linear_solve(self._h, _dp(_f64(b, self.n)), _dp(x)))
+        return x
+
+    def assemble(self, mu):
+        kv, rhs = np.empty(self.nnz_k), np.empty(self.n)
+        _check(capi.lib().nmpc_assemble(self._h, float(mu), _dp(kv), _dp(rhs)))
+        return kv, rhs
+
+
+def device_available() -> bool:
+    return bool(capi.lib().nmpc_device_available())

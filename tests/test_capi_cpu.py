@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: symbol export, host symbolic parity with the
+oracle (bit-exact), structural patterns, argument and call-order errors."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2606_04725_amd import capi
+from paper_2606_04725_amd import nmpc as N
+from oracle import symbolic as S
+from oracle.distillation import DistillationOCP
+
+
+def test_library_exports_every_declared_symbol():
+    L = capi.lib()
+    declared = capi.declared_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(capi.SIGNATURES)
+
+
+def _symbolic_parity(Ntr, H, alpha=2.5):
+    p = N.Problem(N.distillation_structure(Ntr, H, 0.1, alpha))
+    p.analyze()
+    lib = p.export_symbolic()
+    m = DistillationOCP(Ntr, H, 0.1, alpha)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c)
+    assert np.array_equal(lib["perm"], a["perm"])
+    assert np.array_equal(lib["parent"], a["parent"])
+    assert np.array_equal(lib["colcount"], a["colcount"])
+    assert np.array_equal(lib["snode_ptr"], a["snode_ptr"])
+    rp = lib["snode_rows_ptr"]
+    assert len(a["snode_rows"]) == lib["n_supernodes"]
+    for s, rows in enumerate(a["snode_rows"]):
+        assert np.array_equal(lib["snode_rows"][rp[s]:rp[s + 1]], rows)
+    assert lib["nnz_l"] == a["nnz_L"] and lib["flops"] == a["flops"]
+    pat = p.patterns()
+    assert set(zip(pat["k_rows"], pat["k_cols"])) == set(zip(r, c))
+    assert p.nnz_k == len(r)
+    mj = len(m.jc_rows)
+    assert set(zip(pat["j_rows"][:mj], pat["j_cols"][:mj])) == set(zip(m.jc_rows, m.jc_cols))
+    assert set(zip(pat["j_rows"][mj:] - m.m_c, pat["j_cols"][mj:])) == set(zip(m.jd_rows, m.jd_cols))
+    assert set(zip(pat["w_rows"], pat["w_cols"])) == set(zip(m.h_rows, m.h_cols))
+    return lib
+
+
+@pytest.mark.parametrize("Ntr,H", [(2, 1), (3, 4), (10, 20), (7, 13), (40, 100)])
+def test_symbolic_bit_exact_vs_oracle(Ntr, H):
+    _symbolic_parity(Ntr, H)
+
+
+@pytest.mark.slow
+def test_symbolic_bit_exact_batch_instance_sizes():
+    from workloads.generators import batch_distillation_workloads
+    ws = batch_distillation_workloads(64)
+    big = max(ws, key=lambda w: w.N * w.H)
+    _symbolic_parity(big.N, big.H, big.alpha)
+
+
+def test_create_rejects_bad_structures():
+    s = N.distillation_structure(10, 20, 0.1, 2.5)
+    s.horizon = 0
+    with pytest.raises(N.NMPCError) as e:
+        N.Problem(s)
+    assert e.value.code == capi.NMPC_ERR_INVALID_ARG
+    s = N.distillation_structure(10, 20, 0.1, 0.5)     # alpha must exceed 1
+    with pytest.raises(N.NMPCError):
+        N.Problem(s)
+    s = N.distillation_structure(10, 20, 0.1, 2.5)
+    s.family = 99
+    with pytest.raises(N.NMPCError) as e:
+        N.Problem(s)
+    assert e.value.code == capi.NMPC_ERR_UNSUPPORTED
+    h = C.c_void_p()
+    assert capi.lib().nmpc_create_problem(None, C.byref(h)) == capi.NMPC_ERR_INVALID_ARG
+    assert b"NULL" in capi.lib().nmpc_last_error()
+
+
+def test_call_order_and_argument_errors():
+    p = N.Problem(N.distillation_structure(4, 3, 0.1, 2.5))
+    with pytest.raises(N.NMPCError) as e:
+        p.symbolic_sizes()
+    assert e.value.code == capi.NMPC_ERR_BAD_ORDER
+    with pytest.raises(N.NMPCError) as e:
+        p.solve()
+    assert e.value.code == capi.NMPC_ERR_BAD_ORDER
+    x0 = np.full(p.nx, 0.5)
+    x0[2] = np.nan
+    with pytest.raises(N.NMPCError) as e:
+        p.set_parameters(x0)
+    assert e.value.code == capi.NMPC_ERR_INVALID_ARG
+    p.analyze()
+    p.analyze()     # idempotent
+    if not N.device_available():
+        with pytest.raises(N.NMPCError) as e:
+            p.solve()
+        assert e.value.code == capi.NMPC_ERR_NO_DEVICE
+    with pytest.raises(N.NMPCError) as e:
+        p.solve(warm=True)
+    assert e.value.code in (capi.NMPC_ERR_BAD_ORDER, capi.NMPC_ERR_NO_DEVICE)
+    capi.lib().nmpc_destroy(None)    # no-op
+
+
+def test_default_options_match_oracle():
+    from oracle.ipm import IPMOptions
+    o = N.default_options()
+    ref = IPMOptions()
+    for name in ("tol", "gamma", "mu0_cold", "mu0_warm", "mu_min", "kappa_eps", "kappa_mu", "theta_mu",
+                 "tau_min", "armijo", "ls_max", "max_iter", "kappa_sigma", "eta_first", "eta_min", "eta_max",
+                 "kp_first", "kp", "km", "bound_push", "slack_push"):
+        assert getattr(o, name) == pytest.approx(getattr(ref, name), rel=0, abs=0), name
