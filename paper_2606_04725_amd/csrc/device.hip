@@ -44,29 +44,33 @@ __device__ inline double combine(int op, double a, double b) {
     return op == kSum ? a + b : (op == kMax ? fmax(a, b) : fmin(a, b));
 }
 
-// Block-wide reduction of one value (blockDim.x == kBlock), fixed tree order.
-__device__ double block_reduce(double v, int op, double* sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (t < s) sh[t] = combine(op, sh[t], sh[t + s]);
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
 struct Ops {
     int q;
     int op[kMaxQ];
 };
 
+constexpr int kWaves = kBlock / 64;
+
+// Butterfly reduction across the 64 lanes of a wave (fixed pattern).
+__device__ inline double wave_reduce(double v, int op) {
+    for (int off = 32; off > 0; off >>= 1) v = combine(op, v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reduce every quantity over the block (waves, then the per-wave results in
+// wave order) and let thread q write quantity q's block result to part.
 __device__ void store_partials(const double* v, const Ops& ops, double* part, int nblk, double* sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int q = 0; q < ops.q; ++q) {
-        const double r = block_reduce(v[q], ops.op[q], sh);
-        if (threadIdx.x == 0) part[(int64_t)q * nblk + blockIdx.x] = r;
+        const double r = wave_reduce(v[q], ops.op[q]);
+        if (lane == 0) sh[q * kWaves + wv] = r;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ops.q) {
+        const int q = threadIdx.x;
+        double acc = sh[q * kWaves];
+        for (int w = 1; w < kWaves; ++w) acc = combine(ops.op[q], acc, sh[q * kWaves + w]);
+        part[(int64_t)q * nblk + blockIdx.x] = acc;
     }
 }
 
@@ -76,13 +80,14 @@ __device__ inline double ident(int op) {
 
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ part, int nblk, Ops ops,
                                                       double* __restrict__ out) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kMaxQ * kWaves];
+    double v[kMaxQ];
     for (int q = 0; q < ops.q; ++q) {
         double acc = ident(ops.op[q]);
         for (int b = threadIdx.x; b < nblk; b += kBlock) acc = combine(ops.op[q], acc, part[(int64_t)q * nblk + b]);
-        const double r = block_reduce(acc, ops.op[q], sh);
-        if (threadIdx.x == 0) out[q] = r;
+        v[q] = acc;
     }
+    store_partials(v, ops, out, 1, sh);
 }
 
 struct Vec {
@@ -111,7 +116,7 @@ k_phaseA(Vec V, const double* __restrict__ y, const double* __restrict__ s, cons
          const double* __restrict__ d, const double* __restrict__ jv, const int32_t* __restrict__ jt_ptr,
          const int32_t* __restrict__ jt_slot, const int32_t* __restrict__ jt_row, double* __restrict__ gtw,
          double* __restrict__ part, Ops ops) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kMaxQ * kWaves];
     double q[11] = {0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, 0.0};
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < V.n) {
@@ -230,7 +235,7 @@ k_phaseE(Vec V, double mu, double tau, const double* __restrict__ y, const doubl
          const double* __restrict__ jv, const int32_t* __restrict__ jptr, const int32_t* __restrict__ jcol,
          double* __restrict__ ds, double* __restrict__ dom, double* __restrict__ dbe, double* __restrict__ dzl,
          double* __restrict__ dzu, double* __restrict__ part, Ops ops) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kMaxQ * kWaves];
     double q[11] = {INFINITY, INFINITY, -INFINITY, 0, 0, 0, 0, 0, 0, 0, 0};
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int m = V.mc + V.md;
@@ -296,7 +301,7 @@ k_trial_point(int n, int ml, double alpha, const double* __restrict__ y, const d
 __global__ void __launch_bounds__(kBlock)
 k_phaseT(Vec V, const double* __restrict__ yt, const double* __restrict__ st, const double* __restrict__ fterm,
          const double* __restrict__ c, const double* __restrict__ d, double* __restrict__ part, Ops ops) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kMaxQ * kWaves];
     double q[6] = {0, 0, 0, 0, 0, 0};
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < V.n) {
@@ -412,10 +417,14 @@ struct Device {
     int64_t *rows_ptr = nullptr, *l_off = nullptr, *u_off = nullptr, *uv_off = nullptr, *rel_off = nullptr;
     int32_t *k_wslot = nullptr, *k_diag = nullptr, *kc_ptr = nullptr, *kc_a = nullptr, *kc_b = nullptr,
             *kc_r = nullptr;
-    std::vector<int32_t> level_ptr;
-    std::vector<size_t> lev_lds_factor, lev_lds_solve, lev_lds_vec;
+    // launch schedule of the supernodal tree: forward (leaves to root) and backward
+    struct Launch {
+        int gptr_off, groups;
+        size_t lds_factor, lds_solve, lds_vec;
+    };
+    std::vector<Launch> fwd_launches, bwd_launches;
+    int32_t *sched_nodes = nullptr, *sched_gptr = nullptr;
     bool front_in_lds = true;
-    bool panel_in_lds = true;
     double* gscratch = nullptr;
     int64_t gstride = 0;
     SnView S{};
@@ -434,6 +443,7 @@ struct Device {
     double* hscal = nullptr;   // pinned
     int* hfail = nullptr;      // pinned
     int part_blocks = 0;
+    int max_width = 0;
     std::vector<void*> allocs;
     hipEvent_t ev[10] = {};   // phase timers: eval, assemble, factor, solve, line search (start, end)
 };
@@ -518,25 +528,66 @@ nmpc_status device_init(Problem& p, std::string& err) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     const size_t lds_limit = (size_t)lds_max;
-    D.level_ptr = sy.level_ptr;
-    size_t need_factor = 0, need_solve = 0;
-    D.lev_lds_factor.assign(sy.depth, 0);
-    D.lev_lds_solve.assign(sy.depth, 0);
-    D.lev_lds_vec.assign(sy.depth, 0);
-    for (int Lv = 0; Lv < sy.depth; ++Lv)
-        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
-            const int sn = sy.level_list[i];
-            const size_t mr = (size_t)(sy.sn_rows_ptr[sn + 1] - sy.sn_rows_ptr[sn]);
-            const size_t w = (size_t)(sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]);
-            D.lev_lds_factor[Lv] = std::max(D.lev_lds_factor[Lv], mr * mr * sizeof(double));
-            D.lev_lds_solve[Lv] = std::max(D.lev_lds_solve[Lv], (mr * w + mr) * sizeof(double));
-            D.lev_lds_vec[Lv] = std::max(D.lev_lds_vec[Lv], mr * sizeof(double));
+    // Schedule: every level below the narrow top is one launch with one group per
+    // supernode; the top levels that hold at most kTailWidth supernodes each form
+    // a single group walked by one workgroup (a chain costs one launch).
+    constexpr int kTailWidth = 2;
+    int tail = sy.depth;
+    while (tail > 0 && sy.level_ptr[tail] - sy.level_ptr[tail - 1] <= kTailWidth) --tail;
+    if (sy.depth - tail < 2) tail = sy.depth;
+    std::vector<int32_t> nodes, gptr;
+    auto sizes = [&](int sn, size_t& fac, size_t& sol, size_t& vec) {
+        const size_t mr = (size_t)(sy.sn_rows_ptr[sn + 1] - sy.sn_rows_ptr[sn]);
+        const size_t w = (size_t)(sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]);
+        fac = std::max(fac, mr * (mr | 1) * sizeof(double) + kRelInts * sizeof(int32_t));
+        sol = std::max(sol, (mr * (w | 1) + mr + 2 * w) * sizeof(double));
+        vec = std::max(vec, mr * sizeof(double));
+    };
+    auto add_launch = [&](std::vector<Device::Launch>& out, const std::vector<std::vector<int32_t>>& groups) {
+        Device::Launch L{(int)gptr.size(), (int)groups.size(), 0, 0, 0};
+        for (const auto& g : groups) {
+            gptr.push_back((int32_t)nodes.size());
+            for (int32_t sn : g) {
+                nodes.push_back(sn);
+                sizes(sn, L.lds_factor, L.lds_solve, L.lds_vec);
+            }
         }
-    for (size_t b : D.lev_lds_factor) need_factor = std::max(need_factor, b);
-    for (size_t b : D.lev_lds_solve) need_solve = std::max(need_solve, b);
-    D.panel_in_lds = need_solve <= lds_limit;
-    if (!D.panel_in_lds) D.lev_lds_solve = D.lev_lds_vec;
+        gptr.push_back((int32_t)nodes.size());
+        out.push_back(L);
+    };
+    std::vector<int32_t> tail_nodes;
+    for (int Lv = tail; Lv < sy.depth; ++Lv)
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) tail_nodes.push_back(sy.level_list[i]);
+    for (int Lv = 0; Lv < tail; ++Lv) {
+        std::vector<std::vector<int32_t>> g;
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) g.push_back({sy.level_list[i]});
+        add_launch(D.fwd_launches, g);
+    }
+    if (!tail_nodes.empty()) add_launch(D.fwd_launches, {tail_nodes});
+    if (!tail_nodes.empty()) add_launch(D.bwd_launches, {std::vector<int32_t>(tail_nodes.rbegin(), tail_nodes.rend())});
+    for (int Lv = tail - 1; Lv >= 0; --Lv) {
+        std::vector<std::vector<int32_t>> g;
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) g.push_back({sy.level_list[i]});
+        add_launch(D.bwd_launches, g);
+    }
+    size_t need_factor = 0, need_solve = 0;
+    for (const auto& L : D.fwd_launches) {
+        need_factor = std::max(need_factor, L.lds_factor);
+        need_solve = std::max(need_solve, L.lds_solve);
+    }
     D.front_in_lds = need_factor <= lds_limit;
+    if (sy.max_front > kRelInts) {
+        err = "front larger than the relative-position buffer; unsupported front size";
+        return fail_cleanup(NMPC_ERR_UNSUPPORTED);
+    }
+    if (need_solve > lds_limit) {
+        err = "supernode panel exceeds shared memory; unsupported front size";
+        return fail_cleanup(NMPC_ERR_UNSUPPORTED);
+    }
+    for (int sn = 0; sn < sy.nsn; ++sn) D.max_width = std::max(D.max_width, sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]);
+
+    int max_groups = 0;
+    for (const auto& L : D.fwd_launches) max_groups = std::max(max_groups, L.groups);
     e = linalg_configure(std::min(lds_limit, std::max(need_factor, need_solve)));
     if (e != hipSuccess) {
         err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
@@ -566,7 +617,8 @@ nmpc_status device_init(Problem& p, std::string& err) {
     UP(D.rows, sy.sn_rows);
     UP(D.child_ptr, sy.child_ptr);
     UP(D.child_list, sy.child_list);
-    UP(D.level_list, sy.level_list);
+    UP(D.sched_nodes, nodes);
+    UP(D.sched_gptr, gptr);
     UP(D.l_off, sy.l_off);
     UP(D.u_off, sy.u_off);
     UP(D.uv_off, sy.uv_off);
@@ -595,10 +647,8 @@ nmpc_status device_init(Problem& p, std::string& err) {
     AL(D.part, (size_t)kMaxQ * D.part_blocks);
     AL(D.scal, kMaxQ);
     if (!D.front_in_lds) {
-        int maxlev = 0;
-        for (int Lv = 0; Lv < sy.depth; ++Lv) maxlev = std::max(maxlev, sy.level_ptr[Lv + 1] - sy.level_ptr[Lv]);
-        D.gstride = (int64_t)sy.max_front * sy.max_front;
-        AL(D.gscratch, (size_t)D.gstride * maxlev);
+        D.gstride = (int64_t)sy.max_front * (sy.max_front | 1);
+        AL(D.gscratch, (size_t)D.gstride * max_groups);
     }
 #undef UP
 #undef AL
@@ -724,15 +774,12 @@ struct Timer {
 hipError_t factor(Device& D, double eta, int& failed, Timer* tm = nullptr, int* launches = nullptr) {
     hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, D.stream, D.fail);
     hipError_t e = hipSuccess;
-    const int depth = (int)D.level_ptr.size() - 1;
     if (tm) tm->begin(kPhFactor);
-    for (int Lv = 0; Lv < depth; ++Lv) {
-        const int b = D.level_ptr[Lv], cnt = D.level_ptr[Lv + 1] - b;
-        launch_factor_level(D.front_in_lds, D.level_list + b, cnt, D.lev_lds_factor[Lv], D.S, D.kv, eta, D.L,
-                            D.U, D.fail, D.gscratch, D.gstride, D.stream);
-    }
+    for (const auto& Lc : D.fwd_launches)
+        launch_factor_groups(D.front_in_lds, D.sched_nodes, D.sched_gptr + Lc.gptr_off, Lc.groups, Lc.lds_factor, D.S,
+                             D.kv, eta, D.L, D.U, D.fail, D.gscratch, D.gstride, D.stream);
     if (tm) tm->end(kPhFactor);
-    if (launches) *launches += depth;
+    if (launches) *launches += (int)D.fwd_launches.size();
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(D.hfail, D.fail, sizeof(int), hipMemcpyDeviceToHost, D.stream);
@@ -745,17 +792,12 @@ hipError_t factor(Device& D, double eta, int& failed, Timer* tm = nullptr, int* 
 
 // Solve with the current factor: b (original order) -> x (original order).
 void solve(Device& D, const double* b, double* x) {
-    const int depth = (int)D.level_ptr.size() - 1;
-    for (int Lv = 0; Lv < depth; ++Lv) {
-        const int o = D.level_ptr[Lv], cnt = D.level_ptr[Lv + 1] - o;
-        launch_fwd_level(D.panel_in_lds, D.level_list + o, cnt, D.lev_lds_solve[Lv], D.S, D.L, D.uvec, b, D.perm,
-                         D.xp, D.stream);
-    }
-    for (int Lv = depth - 1; Lv >= 0; --Lv) {
-        const int o = D.level_ptr[Lv], cnt = D.level_ptr[Lv + 1] - o;
-        launch_bwd_level(D.panel_in_lds, D.level_list + o, cnt, D.lev_lds_solve[Lv], D.S, D.L, D.xp, D.perm, x,
-                         D.stream);
-    }
+    for (const auto& Lc : D.fwd_launches)
+        launch_fwd_groups(D.sched_nodes, D.sched_gptr + Lc.gptr_off, Lc.groups, Lc.lds_solve, D.S, D.L, D.uvec, b,
+                          D.perm, D.xp, D.stream);
+    for (const auto& Lc : D.bwd_launches)
+        launch_bwd_groups(D.sched_nodes, D.sched_gptr + Lc.gptr_off, Lc.groups, Lc.lds_solve, D.S, D.L, D.xp, D.perm,
+                          x, D.stream);
 }
 
 }  // namespace

@@ -47,7 +47,7 @@ struct Symbolic {
     int64_t stored_l = 0, stored_u = 0, stored_uv = 0;
     // KKT slots in factor order (sorted by permuted column, then row)
     std::vector<int32_t> k_ptr;               // per supernode
-    std::vector<int32_t> k_fpos;              // position in the supernode front (col-major)
+    std::vector<int32_t> k_fpos;              // position in the supernode front (r + c * (rows | 1): odd leading dimension)
     std::vector<int32_t> k_orow, k_ocol;      // original (row, col), row >= col
     std::vector<int32_t> k_wslot;             // Hessian slot or -1
     std::vector<int32_t> k_diag;              // variable index if diagonal else -1

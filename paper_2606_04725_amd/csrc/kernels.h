@@ -13,6 +13,7 @@ namespace nmpc {
 constexpr int kBlock = 256;          // threads per block of every vector kernel
 constexpr int kFactorBlock = 256;    // threads per supernode front
 constexpr int kPanel = 8;            // pivot columns per blocked step of a front
+constexpr int kRelInts = 512;        // shared-memory ints reserved ahead of a front (relative positions)
 
 struct DistillConst {
     double dt, alpha, F, rho, xD, xB;
@@ -42,19 +43,20 @@ void launch_eval_distill(bool full, const DistillDims& D, const DistillConst& C,
                          const int32_t* jptr, int mc, double* c, double* d, double* jv, double* wv,
                          double* grad, double* fterm, hipStream_t st);
 
-// Numeric multifrontal Cholesky of one level of the supernodal tree (eqs. 20-21).
-// lds: every front of the level fits in shared memory (bytes = lds_bytes).
-void launch_factor_level(bool lds, const int32_t* nodes, int count, size_t lds_bytes, const SnView& S,
-                         const double* kv, double eta, double* L, double* U, int* fail,
-                         double* gscratch, int64_t gstride, hipStream_t st);
-// Forward substitution over one level (eq. 23), permutation of the rhs fused.
-// stage: copy each L panel to shared memory first (lds_bytes covers panel + vectors).
-void launch_fwd_level(bool stage, const int32_t* nodes, int count, size_t lds_bytes, const SnView& S,
-                      const double* L, double* uvec, const double* rhs, const int32_t* perm, double* xp,
-                      hipStream_t st);
-// Back substitution over one level (eqs. 24-25), inverse permutation fused.
-void launch_bwd_level(bool stage, const int32_t* nodes, int count, size_t lds_bytes, const SnView& S,
-                      const double* L, double* xp, const int32_t* perm, double* out, hipStream_t st);
+// Numeric multifrontal Cholesky (eqs. 20-21) of a list of supernode groups:
+// workgroup b factors nodes[gptr[b] .. gptr[b+1]) in order.  lds: every front
+// fits in shared memory (bytes = lds_bytes), otherwise fronts live in gscratch.
+void launch_factor_groups(bool lds, const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes,
+                          const SnView& S, const double* kv, double eta, double* L, double* U, int* fail,
+                          double* gscratch, int64_t gstride, hipStream_t st);
+// Forward substitution (eq. 23) over groups, permutation of the rhs fused;
+// lds_bytes holds one front-length vector.
+void launch_fwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
+                       const double* L, double* uvec, const double* rhs, const int32_t* perm, double* xp,
+                       hipStream_t st);
+// Back substitution (eqs. 24-25) over groups, inverse permutation fused.
+void launch_bwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
+                       const double* L, double* xp, const int32_t* perm, double* out, hipStream_t st);
 // Raise the dynamic shared-memory limit of the front kernels (once per process).
 hipError_t linalg_configure(size_t max_lds_bytes);
 

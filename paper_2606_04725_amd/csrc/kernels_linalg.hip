@@ -4,9 +4,14 @@
 // columns, receives the update blocks of its children by extend-add through
 // precomputed relative positions, and is partially factored on its first w_s
 // columns; the factored columns are the L panel (eq. 21 restricted to S_L) and
-// the trailing block is the update passed to the parent.  One workgroup per
-// supernode, one launch per level of the supernodal elimination tree; every
-// sum is taken in a fixed order, so results do not depend on scheduling.
+// the trailing block is the update passed to the parent.
+//
+// Scheduling: a launch covers a list of supernode groups; workgroup b factors
+// the supernodes of group b one after another.  Wide levels of the supernodal
+// tree are one group per supernode (one launch per level); the narrow top of
+// the tree, where each level holds one or two supernodes, is a single group
+// walked by one workgroup, so a chain of fronts costs one launch.  Every sum is
+// taken in a fixed order, so results do not depend on scheduling.
 #include <cmath>
 
 #include "kernels.h"
@@ -15,259 +20,427 @@ namespace nmpc {
 
 namespace {
 
-// Right-looking partial Cholesky of the first w columns of an m x m front
-// (column-major, lower triangle).  Pivot columns are taken kPanel at a time:
-// the panel is factored column by column, then the rest of the front is
-// updated with 4 x 4 register tiles.  A pivot that is not positive and finite
-// sets *fail (the matrix is not numerically positive definite, eq. 12).
-__device__ void partial_cholesky(double* F, int m, int w, int* fail) {
-    const int tid = threadIdx.x;
+constexpr int kWave = 64;
+
+__device__ inline double shfl(double v, int lane) { return __shfl(v, lane, kWave); }
+
+constexpr int kBatch = 8;   // independent global loads in flight per thread
+
+// Copy n values from global to shared memory, kBatch loads in flight per thread.
+template <class T>
+__device__ void g2s(T* dst, const T* __restrict__ src, int64_t n) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int64_t base = 0; base < n; base += (int64_t)nthr * kBatch) {
+        T v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t e = base + tid + (int64_t)u * nthr;
+            v[u] = e < n ? src[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t e = base + tid + (int64_t)u * nthr;
+            if (e < n) dst[e] = v[u];
+        }
+    }
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Right-looking partial Cholesky of the first w columns of an m x m front in
+// shared memory (column-major, lower triangle, leading dimension ld, odd so that
+// a stride-ld walk touches distinct banks), kPanel pivot columns at a time:
+//  1. every thread factors the kPanel x kPanel diagonal block itself, in
+//     registers (identical arithmetic in every thread, no communication);
+//  2. every row below the block solves its own row of the panel against it;
+//  3. the rest of the front takes the rank-kPanel update on the matrix cores:
+//     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
+// A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
+// numerically positive definite); the arithmetic continues with pivot 1.
+__device__ void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
+    const int li = lane & 15, lk = lane >> 4;
     for (int kb = 0; kb < w; kb += kPanel) {
         const int kw = min(kPanel, w - kb);
-        for (int k = kb; k < kb + kw; ++k) {
-            double piv = F[k + (int64_t)k * m];
-            if (!(piv > 0.0) || !(piv < INFINITY)) {
-                if (tid == 0) *fail = 1;
+        double d[kPanel][kPanel];
+#pragma unroll
+        for (int i = 0; i < kPanel; ++i)
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j)
+                d[i][j] = (j <= i && i < kw) ? F[(kb + i) + (kb + j) * ld] : (i == j ? 1.0 : 0.0);
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) {
+            double piv = d[k][k];
+            if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
+                bad = true;
                 piv = 1.0;
             }
             const double sq = sqrt(piv);
             const double inv = 1.0 / sq;
-            for (int i = k + 1 + tid; i < m; i += blockDim.x) F[i + (int64_t)k * m] *= inv;
-            __syncthreads();
-            if (tid == 0) F[k + (int64_t)k * m] = sq;
-            const int ncol = kb + kw - (k + 1);
-            const int nr = m - (k + 1);
-            if (ncol > 0) {
-                for (int e = tid; e < ncol * nr; e += blockDim.x) {
-                    const int jj = e / nr, ii = e - jj * nr;
-                    const int jc = k + 1 + jj, ir = k + 1 + ii;
-                    if (ir >= jc) F[ir + (int64_t)jc * m] -= F[ir + (int64_t)k * m] * F[jc + (int64_t)k * m];
-                }
-            }
-            __syncthreads();
+            d[k][k] = sq;
+#pragma unroll
+            for (int i = k + 1; i < kPanel; ++i) d[i][k] *= inv;
+#pragma unroll
+            for (int j = k + 1; j < kPanel; ++j)
+#pragma unroll
+                for (int i = j; i < kPanel; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
         }
+        if (bad && tid == 0) *fail = 1;
+        double rd[kPanel];
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) rd[k] = 1.0 / d[k][k];
+        __syncthreads();   // every thread has read the diagonal block before it is overwritten
+#pragma unroll
+        for (int i = 0; i < kPanel; ++i)
+            if (tid == i && i < kw) {
+#pragma unroll
+                for (int j = 0; j <= i; ++j) F[(kb + i) + (kb + j) * ld] = d[i][j];
+            }
+        for (int r = kb + kw + tid; r < m; r += nthr) {
+            double a[kPanel];
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) a[j] = j < kw ? F[r + (kb + j) * ld] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k) {
+                double s = a[k];
+#pragma unroll
+                for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
+                a[k] = s * rd[k];
+            }
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j)
+                if (j < kw) F[r + (kb + j) * ld] = a[j];
+        }
+        __syncthreads();
         const int t0 = kb + kw;
         const int T = m - t0;
         if (T > 0) {
-            const int nt = (T + 3) / 4;
+            const int nt = (T + 15) / 16;
             const int ntiles = nt * (nt + 1) / 2;
-            for (int tile = tid; tile < ntiles; tile += blockDim.x) {
+            for (int tile = wv; tile < ntiles; tile += nw) {
                 int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
                 while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
                 while (ti * (ti + 1) / 2 > tile) --ti;
                 const int tj = tile - ti * (ti + 1) / 2;
-                const int i0 = t0 + 4 * ti, j0 = t0 + 4 * tj;
-                double acc[4][4];
+                const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
-                for (int k = kb; k < t0; ++k) {
-                    double av[4], bv[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        av[r] = (i0 + r < m) ? F[i0 + r + (int64_t)k * m] : 0.0;
-                        bv[r] = (j0 + r < m) ? F[j0 + r + (int64_t)k * m] : 0.0;
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) acc[r][q] = fma(av[r], bv[q], acc[r][q]);
+                for (int s4 = 0; s4 < kPanel / 4; ++s4) {
+                    const int kk = 4 * s4 + lk;
+                    const double* col = F + (kb + kk) * ld;
+                    const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
+                    const double b = (kk < kw && j0 + li < m) ? col[j0 + li] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int ir = i0 + r, jc = j0 + q;
-                        if (ir < m && jc < m && ir >= jc) F[ir + (int64_t)jc * m] -= acc[r][q];
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const int ir = i0 + 4 * r + lk, jc = j0 + li;
+                    if (ir < m && jc <= ir) F[ir + jc * ld] -= acc[r];
+                }
             }
         }
         __syncthreads();
     }
 }
 
+// One supernode: assemble the front, factor it, store the L panel and update.
 template <bool Lds>
-__global__ void __launch_bounds__(kFactorBlock)
-k_factor_level(const int32_t* __restrict__ nodes, SnView S, const double* __restrict__ kv, double eta,
-               double* __restrict__ L, double* __restrict__ U, int* __restrict__ fail,
-               double* __restrict__ gscratch, int64_t gstride) {
-    extern __shared__ double lds[];
-    const int s = nodes[blockIdx.x];
+__device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv, double eta, double* __restrict__ L,
+                           double* __restrict__ U, int* __restrict__ fail, double* F, int32_t* rcl) {
     const int f = S.sn_ptr[s];
     const int w = S.sn_ptr[s + 1] - f;
     const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
+    const int ld = m | 1;
     const int nb = m - w;
-    const int tid = threadIdx.x;
-    double* F = Lds ? lds : gscratch + (int64_t)blockIdx.x * gstride;
-    const int64_t mm = (int64_t)m * m;
-    for (int64_t e = tid; e < mm; e += blockDim.x) F[e] = 0.0;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
+    const int mm = m * ld;
+    for (int e = tid; e < mm; e += nthr) F[e] = 0.0;
     __syncthreads();
-    // original entries of the condensed matrix in this supernode's columns (+ eta I)
-    for (int t = S.k_ptr[s] + tid; t < S.k_ptr[s + 1]; t += blockDim.x) {
+    // original entries of the condensed matrix in this supernode's columns (+ eta I);
+    // positions are r + c * (m | 1)
+    for (int t = S.k_ptr[s] + tid; t < S.k_ptr[s + 1]; t += nthr) {
         const int pos = S.k_fpos[t];
         double v = kv[t];
-        if (pos % (m + 1) == 0) v += eta;
+        if (pos % (ld + 1) == 0) v += eta;
         F[pos] = v;
     }
     __syncthreads();
-    // extend-add of the children's update blocks, children in fixed order
+    // extend-add of the children's update blocks, children in fixed order; each
+    // wave walks columns, lanes walk rows, kBatch columns in flight
     for (int ci = S.child_ptr[s]; ci < S.child_ptr[s + 1]; ++ci) {
         const int c = S.child_list[ci];
         const int wc = S.sn_ptr[c + 1] - S.sn_ptr[c];
         const int nc = (int)(S.rows_ptr[c + 1] - S.rows_ptr[c]) - wc;
         const double* Uc = U + S.u_off[c];
-        const int32_t* rc = S.rel + S.rel_off[c];
-        const int64_t tot = (int64_t)nc * nc;
-        for (int64_t e = tid; e < tot; e += blockDim.x) {
-            const int jj = (int)(e / nc), ii = (int)(e - (int64_t)jj * nc);
-            if (ii >= jj) F[rc[ii] + (int64_t)rc[jj] * m] += Uc[ii + (int64_t)jj * nc];
+        g2s(rcl, S.rel + S.rel_off[c], nc);
+        __syncthreads();
+        for (int jb = wv; jb < nc; jb += nw * kBatch) {
+            for (int ib = lane; ib < nc; ib += kWave) {
+                double v[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int jj = jb + u * nw;
+                    v[u] = (jj < nc && ib >= jj) ? Uc[ib + jj * nc] : 0.0;
+                }
+                const int ri = rcl[ib];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int jj = jb + u * nw;
+                    if (jj < nc && ib >= jj) F[ri + rcl[jj] * ld] += v[u];
+                }
+            }
         }
         __syncthreads();
     }
-    partial_cholesky(F, m, w, fail);
-    // factored columns -> L panel, trailing block -> update for the parent
+    partial_cholesky(F, m, ld, w, fail);
     double* Ls = L + S.l_off[s];
-    const int64_t lw = (int64_t)m * w;
-    for (int64_t e = tid; e < lw; e += blockDim.x) Ls[e] = F[e];
+    for (int jc = wv; jc < w; jc += nw)
+        for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = F[i + jc * ld];
     if (nb > 0) {
         double* Us = U + S.u_off[s];
-        const int64_t tot = (int64_t)nb * nb;
-        for (int64_t e = tid; e < tot; e += blockDim.x) {
-            const int jj = (int)(e / nb), ii = (int)(e - (int64_t)jj * nb);
-            Us[e] = F[(w + ii) + (int64_t)(w + jj) * m];
+        for (int jj = wv; jj < nb; jj += nw)
+            for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[(w + ii) + (w + jj) * ld];
+    }
+    __syncthreads();   // the front buffer is reused by the next supernode of the group
+}
+
+template <bool Lds>
+__global__ void __launch_bounds__(kFactorBlock)
+k_factor_groups(const int32_t* __restrict__ nodes, const int32_t* __restrict__ gptr, SnView S,
+                const double* __restrict__ kv, double eta, double* __restrict__ L, double* __restrict__ U,
+                int* __restrict__ fail, double* __restrict__ gscratch, int64_t gstride) {
+    extern __shared__ double lds[];
+    // shared memory: the front (Lds) then kRelInts relative positions; global
+    // scratch holds the front otherwise
+    double* F = Lds ? lds + kRelInts / 2 : gscratch + (int64_t)blockIdx.x * gstride;
+    int32_t* rcl = reinterpret_cast<int32_t*>(lds);
+    for (int i = gptr[blockIdx.x]; i < gptr[blockIdx.x + 1]; ++i)
+        factor_one<Lds>(nodes[i], S, kv, eta, L, U, fail, F, rcl);
+}
+
+// Triangular solves with one supernode's panel P (m x w, column-major, lower
+// w x w diagonal block first), staged in shared memory together with the
+// reciprocals of its diagonal.  Columns go kPanel at a time: every thread
+// solves the small diagonal block itself from broadcast reads, then updates
+// the rows (forward) or columns (backward) it owns; one barrier per block.
+
+// Forward: v[0:m) holds b; on return xs[0:w) = L_dd^{-1} b[0:w) and
+// v[w:m) = b[w:m) - L_below xs.
+__device__ void blocked_forward(const double* P, const double* rdiag, int m, int w, double* v, double* xs) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int kb = 0; kb < w; kb += kPanel) {
+        const int kw = min(kPanel, w - kb);
+        double x[kPanel];
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) {
+            double s = k < kw ? v[kb + k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < k; ++j)
+                if (k < kw) s = fma(-P[(kb + k) + (int64_t)(kb + j) * m], x[j], s);
+            x[k] = k < kw ? s * rdiag[kb + k] : 0.0;
         }
+        if (tid < kw) {
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k)
+                if (k == tid) xs[kb + k] = x[k];
+        }
+        for (int r = kb + kw + tid; r < m; r += nthr) {
+            double acc = v[r];
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j)
+                if (j < kw) acc = fma(-P[r + (int64_t)(kb + j) * m], x[j], acc);
+            v[r] = acc;
+        }
+        __syncthreads();
     }
 }
 
-// Forward substitution L v = P b for one supernode: gather the permuted rhs
-// of its columns, add the children's update vectors, solve with the diagonal
-// block and form the update vector of its rows below.
-template <bool Stage>
-__global__ void __launch_bounds__(kFactorBlock)
-k_fwd_level(const int32_t* __restrict__ nodes, SnView S, const double* __restrict__ L,
-            double* __restrict__ uvec, const double* __restrict__ rhs, const int32_t* __restrict__ perm,
-            double* __restrict__ xp) {
-    extern __shared__ double lds[];
-    const int s = nodes[blockIdx.x];
+// Backward: v[0:w) holds the right-hand side of L_dd^T x = v; on return
+// xs[0:w) = x.  PT is the panel transposed: PT[c + r * ld] = L(r, c).
+__device__ void blocked_backward(const double* PT, int ld, const double* rdiag, int w, double* v, double* xs) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int nblk = (w + kPanel - 1) / kPanel;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int kb = bi * kPanel;
+        const int kw = min(kPanel, w - kb);
+        double x[kPanel];
+#pragma unroll
+        for (int k = kPanel - 1; k >= 0; --k) {
+            double s = k < kw ? v[kb + k] : 0.0;
+#pragma unroll
+            for (int j = k + 1; j < kPanel; ++j)
+                if (j < kw) s = fma(-PT[(kb + k) + (int64_t)(kb + j) * ld], x[j], s);
+            x[k] = k < kw ? s * rdiag[kb + k] : 0.0;
+        }
+        if (tid < kw) {
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k)
+                if (k == tid) xs[kb + k] = x[k];
+        }
+        for (int jc = tid; jc < kb; jc += nthr) {
+            double acc = v[jc];
+#pragma unroll
+            for (int q = 0; q < kPanel; ++q)
+                if (q < kw) acc = fma(-PT[jc + (int64_t)(kb + q) * ld], x[q], acc);
+            v[jc] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Stage one panel and the reciprocals of its diagonal in shared memory.
+__device__ void stage_panel(const double* __restrict__ Ls, int m, int w, double* P, double* rdiag) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    g2s(P, Ls, (int64_t)m * w);
+    for (int k = tid; k < w; k += nthr) rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
+}
+
+// Forward substitution L v = P b for one supernode: gather the permuted rhs of
+// its columns, add the children's update vectors, solve with the diagonal
+// block, then form the update vector of its rows below.
+// Shared memory: panel (m w) + rdiag (w) + v (m) + xs (w).
+__device__ void fwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ uvec,
+                        const double* __restrict__ rhs, const int32_t* __restrict__ perm, double* __restrict__ xp,
+                        double* lds) {
     const int f = S.sn_ptr[s];
     const int w = S.sn_ptr[s + 1] - f;
     const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
-    const int tid = threadIdx.x;
-    const double* Ls = L + S.l_off[s];
-    const int64_t lw = (int64_t)m * w;
-    double* v = Stage ? lds + lw : lds;     // m
-    if (Stage)
-        for (int64_t e = tid; e < lw; e += blockDim.x) lds[e] = Ls[e];
-    const double* P = Stage ? lds : Ls;     // m x w panel
-    for (int i = tid; i < m; i += blockDim.x) v[i] = i < w ? rhs[perm[f + i]] : 0.0;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    double* P = lds;
+    double* rdiag = P + (int64_t)m * w;
+    double* v = rdiag + w;
+    double* xs = v + m;
+    stage_panel(L + S.l_off[s], m, w, P, rdiag);
+    for (int i = tid; i < m; i += nthr) v[i] = i < w ? rhs[perm[f + i]] : 0.0;
     __syncthreads();
     for (int ci = S.child_ptr[s]; ci < S.child_ptr[s + 1]; ++ci) {
         const int c = S.child_list[ci];
         const int nc = (int)(S.uv_off[c + 1] - S.uv_off[c]);
         const double* uc = uvec + S.uv_off[c];
         const int32_t* rc = S.rel + S.rel_off[c];
-        for (int i = tid; i < nc; i += blockDim.x) v[rc[i]] += uc[i];
+        for (int i = tid; i < nc; i += nthr) v[rc[i]] += uc[i];
         __syncthreads();
     }
-    for (int k = 0; k < w; ++k) {
-        const double xk = v[k] / P[k + (int64_t)k * m];
-        if (tid == 0) xp[f + k] = xk;
-        for (int i = k + 1 + tid; i < m; i += blockDim.x) v[i] -= P[i + (int64_t)k * m] * xk;
-        __syncthreads();
-    }
-    const int nb = m - w;
+    blocked_forward(P, rdiag, m, w, v, xs);
+    for (int k = tid; k < w; k += nthr) xp[f + k] = xs[k];
     double* us = uvec + S.uv_off[s];
-    for (int i = tid; i < nb; i += blockDim.x) us[i] = v[w + i];
+    for (int i = w + tid; i < m; i += nthr) us[i - w] = v[i];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kFactorBlock)
+k_fwd_groups(const int32_t* __restrict__ nodes, const int32_t* __restrict__ gptr, SnView S,
+             const double* __restrict__ L, double* __restrict__ uvec, const double* __restrict__ rhs,
+             const int32_t* __restrict__ perm, double* __restrict__ xp) {
+    extern __shared__ double lds[];
+    for (int i = gptr[blockIdx.x]; i < gptr[blockIdx.x + 1]; ++i) fwd_one(nodes[i], S, L, uvec, rhs, perm, xp, lds);
 }
 
 // Back substitution L^T x = v for one supernode, after all its ancestors:
 // subtract the contribution of the rows below (already final), then solve
-// with the transposed diagonal block; writes x unpermuted.
-template <bool Stage>
-__global__ void __launch_bounds__(kFactorBlock)
-k_bwd_level(const int32_t* __restrict__ nodes, SnView S, const double* __restrict__ L,
-            double* __restrict__ xp, const int32_t* __restrict__ perm, double* __restrict__ out) {
-    extern __shared__ double lds[];
-    const int s = nodes[blockIdx.x];
+// with the transposed diagonal block; writes x unpermuted.  The panel is
+// staged transposed (leading dimension w | 1) so that a thread per column
+// reads consecutive shared-memory words.
+// Shared memory: panel (m (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
+__device__ void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
+                        const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
     const int f = S.sn_ptr[s];
     const int w = S.sn_ptr[s + 1] - f;
     const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
     const int nb = m - w;
-    const int tid = threadIdx.x;
-    const double* Ls = L + S.l_off[s];
-    const int64_t lw = (int64_t)m * w;
-    double* xb = Stage ? lds + lw : lds;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int ld = w | 1;
+    double* PT = lds;
+    double* rdiag = PT + (int64_t)m * ld;
+    double* xb = rdiag + w;
     double* v = xb + nb;
-    if (Stage)
-        for (int64_t e = tid; e < lw; e += blockDim.x) lds[e] = Ls[e];
-    const double* P = Stage ? lds : Ls;
+    double* xs = v + w;
+    {
+        const double* Ls = L + S.l_off[s];
+        const int64_t lw = (int64_t)m * w;
+        for (int64_t base = 0; base < lw; base += (int64_t)nthr * kBatch) {
+            double t[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int64_t e = base + tid + (int64_t)u * nthr;
+                t[u] = e < lw ? Ls[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int64_t e = base + tid + (int64_t)u * nthr;
+                if (e < lw) {
+                    const int c = (int)(e / m), r = (int)(e - (int64_t)c * m);
+                    PT[c + (int64_t)r * ld] = t[u];
+                }
+            }
+        }
+        for (int k = tid; k < w; k += nthr) rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
+    }
     const int32_t* rows = S.rows + S.rows_ptr[s];
-    for (int i = tid; i < nb; i += blockDim.x) xb[i] = xp[rows[w + i]];
+    for (int i = tid; i < nb; i += nthr) xb[i] = xp[rows[w + i]];
     __syncthreads();
-    for (int jc = tid; jc < w; jc += blockDim.x) {
+    for (int jc = tid; jc < w; jc += nthr) {
         double acc = xp[f + jc];
-        for (int i = 0; i < nb; ++i) acc -= P[(w + i) + (int64_t)jc * m] * xb[i];
+        for (int i = 0; i < nb; ++i) acc = fma(-PT[jc + (int64_t)(w + i) * ld], xb[i], acc);
         v[jc] = acc;
     }
     __syncthreads();
-    for (int k = w - 1; k >= 0; --k) {
-        const double xk = v[k] / P[k + (int64_t)k * m];
-        if (tid == 0) {
-            xp[f + k] = xk;
-            out[perm[f + k]] = xk;
-        }
-        for (int jc = tid; jc < k; jc += blockDim.x) v[jc] -= P[k + (int64_t)jc * m] * xk;
-        __syncthreads();
+    blocked_backward(PT, ld, rdiag, w, v, xs);
+    for (int k = tid; k < w; k += nthr) {
+        xp[f + k] = xs[k];
+        out[perm[f + k]] = xs[k];
     }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kFactorBlock)
+k_bwd_groups(const int32_t* __restrict__ nodes, const int32_t* __restrict__ gptr, SnView S,
+             const double* __restrict__ L, double* __restrict__ xp, const int32_t* __restrict__ perm,
+             double* __restrict__ out) {
+    extern __shared__ double lds[];
+    for (int i = gptr[blockIdx.x]; i < gptr[blockIdx.x + 1]; ++i) bwd_one(nodes[i], S, L, xp, perm, out, lds);
 }
 
 }  // namespace
 
 hipError_t linalg_configure(size_t max_lds_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor_level<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_level<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_bwd_level<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
+    const void* fns[] = {reinterpret_cast<const void*>(k_factor_groups<true>),
+                         reinterpret_cast<const void*>(k_fwd_groups), reinterpret_cast<const void*>(k_bwd_groups)};
+    for (const void* fn : fns) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-void launch_factor_level(bool lds, const int32_t* nodes, int count, size_t lds_bytes, const SnView& S,
-                         const double* kv, double eta, double* L, double* U, int* fail, double* gscratch,
-                         int64_t gstride, hipStream_t st) {
-    if (count <= 0) return;
+void launch_factor_groups(bool lds, const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes,
+                          const SnView& S, const double* kv, double eta, double* L, double* U, int* fail,
+                          double* gscratch, int64_t gstride, hipStream_t st) {
+    if (groups <= 0) return;
     if (lds)
-        hipLaunchKernelGGL(k_factor_level<true>, dim3(count), dim3(kFactorBlock), lds_bytes, st, nodes, S, kv,
-                           eta, L, U, fail, gscratch, gstride);
+        hipLaunchKernelGGL(k_factor_groups<true>, dim3(groups), dim3(kFactorBlock), lds_bytes, st, nodes, gptr, S,
+                           kv, eta, L, U, fail, gscratch, gstride);
     else
-        hipLaunchKernelGGL(k_factor_level<false>, dim3(count), dim3(kFactorBlock), 0, st, nodes, S, kv, eta, L,
-                           U, fail, gscratch, gstride);
+        hipLaunchKernelGGL(k_factor_groups<false>, dim3(groups), dim3(kFactorBlock), kRelInts * sizeof(int32_t), st,
+                           nodes, gptr, S, kv, eta, L, U, fail, gscratch, gstride);
 }
 
-void launch_fwd_level(bool stage, const int32_t* nodes, int count, size_t lds_bytes, const SnView& S,
-                      const double* L, double* uvec, const double* rhs, const int32_t* perm, double* xp,
-                      hipStream_t st) {
-    if (count <= 0) return;
-    if (stage)
-        hipLaunchKernelGGL(k_fwd_level<true>, dim3(count), dim3(kFactorBlock), lds_bytes, st, nodes, S, L, uvec,
-                           rhs, perm, xp);
-    else
-        hipLaunchKernelGGL(k_fwd_level<false>, dim3(count), dim3(kFactorBlock), lds_bytes, st, nodes, S, L,
-                           uvec, rhs, perm, xp);
+void launch_fwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
+                       const double* L, double* uvec, const double* rhs, const int32_t* perm, double* xp,
+                       hipStream_t st) {
+    if (groups <= 0) return;
+    hipLaunchKernelGGL(k_fwd_groups, dim3(groups), dim3(kFactorBlock), lds_bytes, st, nodes, gptr, S, L, uvec, rhs,
+                       perm, xp);
 }
 
-void launch_bwd_level(bool stage, const int32_t* nodes, int count, size_t lds_bytes, const SnView& S,
-                      const double* L, double* xp, const int32_t* perm, double* out, hipStream_t st) {
-    if (count <= 0) return;
-    if (stage)
-        hipLaunchKernelGGL(k_bwd_level<true>, dim3(count), dim3(kFactorBlock), lds_bytes, st, nodes, S, L, xp,
-                           perm, out);
-    else
-        hipLaunchKernelGGL(k_bwd_level<false>, dim3(count), dim3(kFactorBlock), lds_bytes, st, nodes, S, L, xp,
-                           perm, out);
+void launch_bwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
+                       const double* L, double* xp, const int32_t* perm, double* out, hipStream_t st) {
+    if (groups <= 0) return;
+    hipLaunchKernelGGL(k_bwd_groups, dim3(groups), dim3(kFactorBlock), lds_bytes, st, nodes, gptr, S, L, xp, perm,
+                       out);
 }
 
 }  // namespace nmpc

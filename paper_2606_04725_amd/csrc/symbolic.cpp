@@ -350,8 +350,8 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
         const int32_t* re = &sym.sn_rows[sym.sn_rows_ptr[s + 1]];
         const int32_t* it = std::lower_bound(rb, re, pi);
         if (it == re || *it != pi) throw std::runtime_error("KKT entry outside the factor pattern");
-        const int64_t mr = re - rb;
-        sym.k_fpos[t] = (int32_t)((it - rb) + (int64_t)(pj - sym.sn_ptr[s]) * mr);
+        const int64_t ld = (re - rb) | 1;   // fronts use an odd leading dimension
+        sym.k_fpos[t] = (int32_t)((it - rb) + (int64_t)(pj - sym.sn_ptr[s]) * ld);
         const int32_t oi = sym.perm[pi], oj = sym.perm[pj];
         sym.k_orow[t] = std::max(oi, oj);
         sym.k_ocol[t] = std::min(oi, oj);
