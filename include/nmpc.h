@@ -205,6 +205,26 @@ nmpc_status nmpc_linear_solve(nmpc_problem* p, const double* b, double* x);
  * side -r1 - G^T (Q r4 - r2). */
 nmpc_status nmpc_assemble(nmpc_problem* p, double mu, double* k_vals, double* rhs);
 
+/* Sensitivities of the last solution: the lifted barrier KKT conditions of
+ * Section 3.2 (eqs. 8-9 for the lifted problem of eq. 16) are differentiated by
+ * the implicit function theorem and condensed as in eqs. (14) and (17), so
+ * K dy/dp = -d(grad f)/dp - J_c^T (Q+ + Q-) dc/dp - J_d^T Q_d dd/dp with K the
+ * condensed matrix at the returned iterate.  K is assembled and factored once
+ * (kept until the next solve, iterate or parameter change) and reused by every
+ * call; one forward/back solve per seed.
+ * nmpc_adjoint: gradient of seed_u1 . u1* + seed_obj * f* (vector-Jacobian
+ * product) with respect to x0 (grad_x0[nx]), the setpoint (grad_setpoint:
+ * distillation (xD*, xB*)), the disturbance trajectory (grad_traj[H]) and
+ * u_prev (grad_uprev[nu]); outputs may be NULL, seed_u1 may not.  Host arrays.
+ * BAD_ORDER without a solution; REG_FAIL (positive) when K needed eta > 0 to
+ * factor (the gradient is then that of the regularized system). */
+nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj, double* grad_x0,
+                         double* grad_setpoint, double* grad_traj, double* grad_uprev);
+
+/* Jacobian d u1* / d x0 as an nu x nx row-major host matrix (nu solves with the
+ * kept factor; same conditions as nmpc_adjoint). */
+nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
+
 /* Thread-local message for the last error on this thread. */
 const char* nmpc_last_error(void);
 

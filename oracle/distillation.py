@@ -276,6 +276,42 @@ class DistillationOCP:
         Wl = sp.csr_matrix((data, (self.h_rows, self.h_cols)), shape=(self.n, self.n))
         return (Wl + sp.triu(Wl.T, k=1)).tocsr()
 
+    # ---- parameter derivatives (for sensitivities) ---------------------
+    def parameter_derivatives(self, y):
+        """Partial derivatives of the NLP functions with respect to each parameter
+        group, as dense arrays: for group g, dc[g] (m_c x n_g), dd[g] (m_d x n_g),
+        dgrad[g] (n x n_g) = d(grad f)/dp and df[g] (n_g,).
+        Groups: x0 (nx), setpoint (xD*, xB*), zF (H), u_prev (2)."""
+        X, R, V = self.split(y)
+        nx, H, n = self.nx, self.H, self.n
+        out = {}
+        # x0 enters c_1 = x_1 - x0 - dt rhs(x_1, u_1)
+        dc = np.zeros((self.m_c, nx))
+        dc[:nx, :] = -np.eye(nx)
+        out["x0"] = (dc, np.zeros((self.m_d, nx)), np.zeros((n, nx)), np.zeros(nx))
+        # setpoints enter f only
+        dg = np.zeros((n, 2))
+        for k in range(H):
+            dg[self.ix(k, 0), 0] = -2.0
+            dg[self.ix(k, nx - 1), 1] = -2.0
+        dfv = np.array([-2.0 * np.sum(X[:, 0] - self.xD_sp), -2.0 * np.sum(X[:, -1] - self.xB_sp)])
+        out["setpoint"] = (np.zeros((self.m_c, 2)), np.zeros((self.m_d, 2)), dg, dfv)
+        # feed composition zF_k enters rhs at the feed tray of stage k with weight F
+        dc = np.zeros((self.m_c, H))
+        for k in range(H):
+            dc[k * nx + self.fd, k] = -self.dt * self.F
+        out["zF"] = (dc, np.zeros((self.m_d, H)), np.zeros((n, H)), np.zeros(H))
+        # u_prev enters the first move penalty
+        dg = np.zeros((n, 2))
+        dg[self.iR(0), 0] = -2.0 * self.rho
+        dg[self.iV(0), 1] = -2.0 * self.rho
+        dfv = np.array([-2.0 * self.rho * (R[0] - self.u_prev[0]), -2.0 * self.rho * (V[0] - self.u_prev[1])])
+        out["u_prev"] = (np.zeros((self.m_c, 2)), np.zeros((self.m_d, 2)), dg, dfv)
+        return out
+
+    def u1_index(self):
+        return [self.iR(0), self.iV(0)]
+
     # ---- starting point ------------------------------------------------
     def initial_guess(self):
         """Cold start: every stage holds the measured state and the last control."""

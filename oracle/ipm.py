@@ -220,8 +220,13 @@ class LiftedIPM:
         return float(phi)
 
     # ---- main loop ----------------------------------------------------
-    def solve(self, start: IPMState, mu0: float, record=False):
+    def solve(self, start: IPMState, mu0: float, record=False, fixed_mu=False, tol=None):
+        """Algorithm 2 from ``start`` with initial barrier value mu0.  With
+        ``fixed_mu`` the barrier value is never decreased and the loop stops when
+        E_mu <= tol (Newton's method on one barrier problem, used for finite
+        differences of the barrier solution)."""
         o, nlp = self.o, self.nlp
+        tol = o.tol if tol is None else tol
         st = start.copy()
         mu = mu0
         nu = 1.0
@@ -240,7 +245,11 @@ class LiftedIPM:
                 status = 4
                 break
             E0 = self.errors(st, gf, c, d, Jc, Jd, 0.0)
-            if E0 <= o.tol:
+            if fixed_mu:
+                if self.errors(st, gf, c, d, Jc, Jd, mu) <= tol:
+                    status = 0
+                    break
+            elif E0 <= tol:
                 status = 0
                 break
             if it >= o.max_iter:
@@ -248,7 +257,7 @@ class LiftedIPM:
                 break
             # barrier update (eq. 27 inner test, Algorithm 2 outer loop)
             Emu = self.errors(st, gf, c, d, Jc, Jd, mu)
-            while Emu <= o.kappa_eps * mu and mu > o.mu_min:
+            while not fixed_mu and Emu <= o.kappa_eps * mu and mu > o.mu_min:
                 mu = max(o.mu_min, min(o.kappa_mu * mu, mu ** o.theta_mu))
                 Emu = self.errors(st, gf, c, d, Jc, Jd, mu)
             tau = max(o.tau_min, 1.0 - mu)

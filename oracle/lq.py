@@ -123,6 +123,22 @@ class LQOCP:
         blk[self.nx:, self.nx:] = 2.0 * self.R
         return sp.block_diag([blk] * self.H).tocsr()
 
+    def parameter_derivatives(self, y):
+        """Groups: x0 (nx) enters c_1 = x_1 - A x0 - B u_1; xs (nx) enters f."""
+        X, U = self.split(y)
+        nx, n = self.nx, self.n
+        dc = np.zeros((self.m_c, nx))
+        dc[:nx, :] = -self.A
+        dg = np.zeros((n, nx))
+        for k in range(self.H):
+            dg[k * self.ns:k * self.ns + nx, :] = -2.0 * self.Q
+        dfv = -2.0 * np.sum((X - self.xs) @ self.Q, axis=0)
+        return {"x0": (dc, np.zeros((0, nx)), np.zeros((n, nx)), np.zeros(nx)),
+                "xs": (np.zeros((self.m_c, nx)), np.zeros((0, nx)), dg, dfv)}
+
+    def u1_index(self):
+        return list(range(self.nx, self.ns))
+
     def initial_guess(self):
         y = np.zeros(self.n)
         for k in range(self.H):

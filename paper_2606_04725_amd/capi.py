@@ -68,6 +68,8 @@ SIGNATURES = {
     "nmpc_factor": (C.c_int32, [_P, _D, C.c_double, _I, _D]),
     "nmpc_linear_solve": (C.c_int32, [_P, _D, _D]),
     "nmpc_assemble": (C.c_int32, [_P, C.c_double, _D, _D]),
+    "nmpc_adjoint": (C.c_int32, [_P, _D, C.c_double, _D, _D, _D, _D]),
+    "nmpc_jacobian_u1_x0": (C.c_int32, [_P, _D]),
     "nmpc_last_error": (C.c_char_p, []),
     "nmpc_device_available": (C.c_int32, []),
 }

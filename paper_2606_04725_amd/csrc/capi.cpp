@@ -45,6 +45,26 @@ extern "C" {
 
 const char* nmpc_last_error(void) { return g_err.c_str(); }
 
+nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj, double* grad_x0,
+                         double* grad_setpoint, double* grad_traj, double* grad_uprev) {
+    if (!p || !seed_u1) return fail(NMPC_ERR_INVALID_ARG, "adjoint: NULL handle or seed");
+    if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "adjoint: no solution yet");
+    if (!std::isfinite(seed_obj) || !all_finite(seed_u1, p->impl.st.nu))
+        return fail(NMPC_ERR_INVALID_ARG, "adjoint: non-finite seed");
+    std::string err;
+    nmpc_status rc = nmpc::device_adjoint(p->impl, seed_u1, seed_obj, grad_x0, grad_setpoint, grad_traj,
+                                          grad_uprev, err);
+    return rc >= 0 ? rc : fail(rc, err);
+}
+
+nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac) {
+    if (!p || !jac) return fail(NMPC_ERR_INVALID_ARG, "jacobian_u1_x0: NULL argument");
+    if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0: no solution yet");
+    std::string err;
+    nmpc_status rc = nmpc::device_jacobian_u1_x0(p->impl, jac, err);
+    return rc >= 0 ? rc : fail(rc, err);
+}
+
 int32_t nmpc_device_available(void) { return nmpc::device_present() ? 1 : 0; }
 
 void nmpc_default_options(nmpc_options* o) {
@@ -199,6 +219,7 @@ nmpc_status nmpc_set_parameters(nmpc_problem* p, const double* x0, const double*
     if (traj) P.traj.assign(traj, traj + st.H);
     if (u_prev) P.u_prev.assign(u_prev, u_prev + st.nu);
     if (P.dev) {
+        nmpc::device_invalidate_adjoint(P);
         std::string err;
         nmpc_status rc = nmpc::device_set_parameters(P, err);
         if (rc != NMPC_OK) return fail(rc, err);

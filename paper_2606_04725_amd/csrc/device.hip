@@ -396,6 +396,66 @@ k_cold_duals(Vec V, double mu0, double sp, const double* __restrict__ c, const d
 
 __global__ void k_clear_flag(int* __restrict__ flag) { *flag = 0; }
 
+// ---- sensitivities ------------------------------------------------------------------
+constexpr int kMaxSeed = 16;
+struct Seed {
+    double u[kMaxSeed];
+};
+
+// rhs = seed_obj * grad f + S_u^T seed_u (first-stage controls at positions iu0 .. iu0 + nu)
+__global__ void __launch_bounds__(kBlock)
+k_adj_seed(int n, int iu0, int nu, const double* __restrict__ grad, double seed_obj, Seed seed,
+           double* __restrict__ rhs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double v = seed_obj * grad[j];
+    if (j >= iu0 && j < iu0 + nu) v += seed.u[j - iu0];
+    rhs[j] = v;
+}
+
+// Parameter contractions of w = K^{-1} seed for the distillation family (one block):
+//   x0:       (Q+ + Q-) (J w) on the stage-1 rows
+//   zF_k:     dt F (Q+ + Q-) (J w) on the feed-tray row of stage k
+//   xD*, xB*: 2 sum_k w(top|bottom state) - 2 seed_obj sum_k (state - setpoint)
+//   u_prev:   2 rho w(u_1) - 2 rho seed_obj (u_1 - u_prev)
+// out = [x0 (nx) | setpoint (2) | traj (H) | u_prev (2)]
+__global__ void __launch_bounds__(kBlock)
+k_adj_gather_distill(DistillDims D, DistillConst C, const double* __restrict__ y, const double* __restrict__ uprev,
+                     const double* __restrict__ w, const double* __restrict__ jv, const int32_t* __restrict__ jptr,
+                     const int32_t* __restrict__ jcol, const double* __restrict__ qeff, double seed_obj,
+                     double* __restrict__ out) {
+    __shared__ double sh[kMaxQ * kWaves];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < D.nx + D.H; t += kBlock) {
+        const int r = t < D.nx ? t : (t - D.nx) * D.nx + D.fd;
+        double jw = 0.0;
+        for (int q = jptr[r]; q < jptr[r + 1]; ++q) jw += jv[q] * w[jcol[q]];
+        const double v = qeff[r] * jw;
+        if (t < D.nx) out[t] = v;
+        else out[D.nx + 2 + (t - D.nx)] = C.dt * C.F * v;
+    }
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = tid; k < D.H; k += kBlock) {
+        const int top = k * D.ns, bot = k * D.ns + D.nx - 1;
+        a[0] += w[top];
+        a[1] += y[top] - C.xD;
+        a[2] += w[bot];
+        a[3] += y[bot] - C.xB;
+    }
+    Ops ops{4, {kSum, kSum, kSum, kSum}};
+    store_partials(a, ops, sh + 4 * kWaves, 1, sh);   // block sums land in sh[4 kWaves .. 4 kWaves + 4)
+    __syncthreads();
+    if (tid == 0) {
+        const double* r = sh + 4 * kWaves;
+        out[D.nx] = 2.0 * r[0] - 2.0 * seed_obj * r[1];
+        out[D.nx + 1] = 2.0 * r[2] - 2.0 * seed_obj * r[3];
+    }
+    if (tid < 2) {
+        const int iu = D.nx + tid;
+        out[D.nx + 2 + D.H + tid] = 2.0 * C.rho * w[iu] - 2.0 * C.rho * seed_obj * (y[iu] - uprev[tid]);
+    }
+}
+
 inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -445,7 +505,11 @@ struct Device {
     int part_blocks = 0;
     int max_width = 0;
     std::vector<void*> allocs;
-    hipEvent_t ev[10] = {};   // phase timers: eval, assemble, factor, solve, line search (start, end)
+    hipEvent_t ev[10] = {};
+    // sensitivities: factor of K at the returned iterate, kept until it changes
+    bool adj_ready = false;
+    double adj_eta = 0.0;
+    double *adj_rhs = nullptr, *adj_w = nullptr, *adj_out = nullptr;   // phase timers: eval, assemble, factor, solve, line search (start, end)
 };
 
 namespace {
@@ -643,6 +707,9 @@ nmpc_status device_init(Problem& p, std::string& err) {
     AL(D.yt, D.n); AL(D.st, D.ml);
     AL(D.kv, D.nnzk); AL(D.L, sy.stored_l); AL(D.U, sy.stored_u); AL(D.uvec, sy.stored_uv);
     AL(D.fail, 1);
+    AL(D.adj_rhs, D.n);
+    AL(D.adj_w, D.n);
+    AL(D.adj_out, st.nx + 4 + st.H);
     D.part_blocks = nblocks((int64_t)D.n + D.ml + D.m);
     AL(D.part, (size_t)kMaxQ * D.part_blocks);
     AL(D.scal, kMaxQ);
@@ -806,6 +873,7 @@ void solve(Device& D, const double* b, double* x) {
 nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err) {
     Device& D = *p.dev;
     D.vec.gamma = o.gamma;
+    D.adj_ready = false;
     r = nmpc_result{};
     double mu = warm ? o.mu0_warm : o.mu0_cold;
     if (!warm) {
@@ -976,6 +1044,7 @@ nmpc_status device_get_iterate(const Problem& p, double* y, double* s, double* o
 nmpc_status device_set_iterate(Problem& p, const double* y, const double* s, const double* om, const double* be,
                                const double* zl, const double* zu, std::string& err) {
     Device& D = *p.dev;
+    D.adj_ready = false;
     HIP_TRY(hipMemcpy(D.y, y, D.n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(D.s, s, D.ml * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(D.om, om, D.ml * sizeof(double), hipMemcpyHostToDevice));
@@ -1043,6 +1112,100 @@ nmpc_status device_assemble(Problem& p, double mu, double* kv, double* rhs, std:
     if (rhs) HIP_TRY(hipMemcpyAsync(rhs, D.rhs, D.n * sizeof(double), hipMemcpyDeviceToHost, D.stream));
     HIP_TRY(hipStreamSynchronize(D.stream));
     return NMPC_OK;
+}
+
+}  // namespace nmpc
+
+namespace nmpc {
+
+void device_invalidate_adjoint(Problem& p) {
+    if (p.dev) p.dev->adj_ready = false;
+}
+
+namespace {
+
+// Assemble and factor K at the handle's iterate (inertia correction as in the solve).
+nmpc_status adjoint_prepare(Problem& p, std::string& err) {
+    Device& D = *p.dev;
+    if (D.adj_ready) return NMPC_OK;
+    eval(D, true, D.y);
+    phaseA(D);
+    prep_and_assemble(D, 1.0);   // mu only enters r2, which the sensitivities do not use
+    HIP_TRY(hipGetLastError());
+    int failed = 0;
+    double eta = 0.0;
+    HIP_TRY(factor(D, 0.0, failed));
+    if (failed) {
+        nmpc_options o;
+        nmpc_default_options(&o);
+        eta = o.eta_first;
+        while (true) {
+            HIP_TRY(factor(D, eta, failed));
+            if (!failed) break;
+            eta *= o.kp_first;
+            if (eta > o.eta_max) {
+                err = "adjoint: the condensed matrix at the solution could not be factored";
+                return NMPC_ERR_INVALID_ARG;
+            }
+        }
+    }
+    D.adj_eta = eta;
+    D.adj_ready = true;
+    return NMPC_OK;
+}
+
+nmpc_status adjoint_apply(Problem& p, const double* seed_u1, double seed_obj, std::vector<double>& out,
+                          std::string& err) {
+    Device& D = *p.dev;
+    const Structure& st = p.st;
+    if (st.nu > kMaxSeed) {
+        err = "adjoint: too many controls per stage";
+        return NMPC_ERR_UNSUPPORTED;
+    }
+    Seed sd{};
+    for (int j = 0; j < st.nu; ++j) sd.u[j] = seed_u1[j];
+    hipLaunchKernelGGL(k_adj_seed, dim3(nblocks(D.n)), dim3(kBlock), 0, D.stream, D.n, st.nx, st.nu, D.grad,
+                       seed_obj, sd, D.adj_rhs);
+    solve(D, D.adj_rhs, D.adj_w);
+    hipLaunchKernelGGL(k_adj_gather_distill, dim3(1), dim3(kBlock), 0, D.stream, D.dd, D.dc, D.y, D.uprev, D.adj_w,
+                       D.jv, D.jptr, D.jcol, D.qeff, seed_obj, D.adj_out);
+    HIP_TRY(hipGetLastError());
+    out.resize(st.nx + 4 + st.H);
+    HIP_TRY(hipMemcpyAsync(out.data(), D.adj_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, D.stream));
+    HIP_TRY(hipStreamSynchronize(D.stream));
+    return NMPC_OK;
+}
+
+}  // namespace
+
+nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, double* gx0, double* gsp,
+                           double* gtraj, double* gup, std::string& err) {
+    nmpc_status rc = adjoint_prepare(p, err);
+    if (rc != NMPC_OK) return rc;
+    std::vector<double> out;
+    rc = adjoint_apply(p, seed_u1, seed_obj, out, err);
+    if (rc != NMPC_OK) return rc;
+    const Structure& st = p.st;
+    if (gx0) std::copy(out.begin(), out.begin() + st.nx, gx0);
+    if (gsp) std::copy(out.begin() + st.nx, out.begin() + st.nx + 2, gsp);
+    if (gtraj) std::copy(out.begin() + st.nx + 2, out.begin() + st.nx + 2 + st.H, gtraj);
+    if (gup) std::copy(out.begin() + st.nx + 2 + st.H, out.begin() + st.nx + 4 + st.H, gup);
+    return p.dev->adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
+}
+
+nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err) {
+    nmpc_status rc = adjoint_prepare(p, err);
+    if (rc != NMPC_OK) return rc;
+    const Structure& st = p.st;
+    std::vector<double> seed(st.nu, 0.0), out;
+    for (int j = 0; j < st.nu; ++j) {
+        std::fill(seed.begin(), seed.end(), 0.0);
+        seed[j] = 1.0;
+        rc = adjoint_apply(p, seed.data(), 0.0, out, err);
+        if (rc != NMPC_OK) return rc;
+        std::copy(out.begin(), out.begin() + st.nx, jac + (size_t)j * st.nx);
+    }
+    return p.dev->adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
 
 }  // namespace nmpc

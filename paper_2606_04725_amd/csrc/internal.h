@@ -87,6 +87,10 @@ nmpc_status device_factor(Problem& p, const double* kv, double eta, int32_t* ok,
                           std::string& err);
 nmpc_status device_linear_solve(Problem& p, const double* b, double* x, std::string& err);
 nmpc_status device_assemble(Problem& p, double mu, double* kv, double* rhs, std::string& err);
+nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, double* gx0, double* gsp,
+                           double* gtraj, double* gup, std::string& err);
+nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err);
+void device_invalidate_adjoint(Problem& p);
 bool device_present();
 
 }  // namespace nmpc

@@ -73,6 +73,7 @@ class Problem:
         nk = C.c_int64()
         _check(L.nmpc_sizes(h, C.byref(n), C.byref(mc), C.byref(md), C.byref(nx), C.byref(nu), C.byref(nk)))
         self.n, self.m_c, self.m_d, self.nx, self.nu = n.value, mc.value, md.value, nx.value, nu.value
+        self.horizon = structure.horizon
         self.nnz_k = nk.value
         self.ml = 2 * self.m_c + self.m_d
         self.analyzed = False
@@ -154,6 +155,21 @@ class Problem:
         n, ml = self.n, self.ml
         a = [_f64(y, n), _f64(s, ml), _f64(omega, ml), _f64(beta, ml), _f64(zL, n), _f64(zU, n)]
         _check(capi.lib().nmpc_set_iterate(self._h, *(_dp(v) for v in a)))
+
+    # ---- sensitivities ------------------------------------------------------
+    def adjoint(self, seed_u1, seed_obj=0.0, n_setpoint=2, n_traj=None):
+        """Vector-Jacobian product of seed_u1 . u1* + seed_obj f* with respect to
+        the parameters; returns (status, dict of gradients)."""
+        n_traj = self.horizon if n_traj is None else n_traj
+        gx, gs, gt, gu = np.empty(self.nx), np.empty(n_setpoint), np.empty(n_traj), np.empty(self.nu)
+        rc = _check(capi.lib().nmpc_adjoint(self._h, _dp(_f64(seed_u1, self.nu)), float(seed_obj), _dp(gx),
+                                            _dp(gs), _dp(gt), _dp(gu)))
+        return rc, dict(x0=gx, setpoint=gs, traj=gt, u_prev=gu)
+
+    def jacobian_u1_x0(self):
+        jac = np.empty((self.nu, self.nx))
+        rc = _check(capi.lib().nmpc_jacobian_u1_x0(self._h, _dp(jac)))
+        return rc, jac
 
     # ---- single steps -------------------------------------------------------
     def eval(self, y, lam, lam_d):
