@@ -24,6 +24,29 @@ import numpy as np
 HBM_PEAK_GBPS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "factor_distill_medium_hbm_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per factorization from the committed counter summary, or None
+    when the factorization kernels changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+        src = os.path.join(os.path.dirname(TRAFFIC_FILE), "..", kv["source_file"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["source_sha256"]:
+            return None
+        return float(kv["bytes_per_factorization"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else float("nan")
 
@@ -174,7 +197,7 @@ def main(argv=None):
         "phase_ms_per_resolve": {k: v / a.steps for k, v in phase.items()},
         "cholesky_gflops": gflops,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": measured_traffic(),
                      "kernel": "numeric supernodal factorization (all levels of one factorization)",
                      "bytes_per_unit": bytes_per_factor},
     }
