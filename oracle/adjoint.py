@@ -12,13 +12,24 @@ leaves
 
 with Q = beta / s on the lifted rows (the two lifted copies of an equality act
 as one penalty of weight Q+ + Q-).  Then du_1/dp = S_u dy/dp and
-df*/dp = df/dp + grad f^T dy/dp.  K is formed and factored here on its own
-(dense Cholesky), independently of the interior-point iterations.
+df*/dp = df/dp + grad f^T dy/dp.
+
+Near the solution the lifted weights are of order mu / gamma^2, so the
+condensed matrix formed in floating point carries the curvature W only to an
+absolute precision of about eps |J^T Q J|, which shows in the sensitivities at
+the 1e-5 level.  The oracle therefore solves the equivalent uncondensed system
+(the step before the elimination of the multiplier directions)
+
+    [ W + Sigma    J^T    ] [dy/dp ]   [ -d(grad f)/dp ]
+    [ J          -Q^{-1}  ] [dlam/dp] = [ -d(c, d)/dp   ]
+
+with a sparse LU factorization, independently of the interior-point code.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 def condensed_matrix(ipm, st):
@@ -39,19 +50,32 @@ def condensed_matrix(ipm, st):
     return K.toarray(), Jc, Jd, Qc, Qd
 
 
+def augmented_matrix(ipm, st):
+    """[[W + Sigma, J^T], [J, -Q^{-1}]] at st, J = [J_c; J_d], Q = (Q+ + Q-, Q_d)."""
+    nlp, mc = ipm.nlp, ipm.mc
+    lam = st.omega[:mc] - st.omega[mc:2 * mc]
+    W = nlp.hess(st.y, lam, st.omega[2 * mc:])
+    gL, gU = ipm.gaps(st.y)
+    sig = np.where(ipm.hasL, st.zL / gL, 0.0) + np.where(ipm.hasU, st.zU / gU, 0.0)
+    Q = st.beta / st.s
+    Qa = np.concatenate([Q[:mc] + Q[mc:2 * mc], Q[2 * mc:]])
+    J = sp.vstack([nlp.jac_c(st.y), nlp.jac_d(st.y)]).tocsr()
+    A = sp.bmat([[W + sp.diags(sig), J.T], [J, sp.diags(-1.0 / Qa)]]).tocsc()
+    return A, J, Qa
+
+
 def sensitivities(ipm, st):
     """dy/dp, du1/dp and df*/dp for every parameter group of the model."""
     nlp = ipm.nlp
-    K, Jc, Jd, Qc, Qd = condensed_matrix(ipm, st)
-    Lc = np.linalg.cholesky(K)
+    A, J, _ = augmented_matrix(ipm, st)
+    lu = spla.splu(A)
     gf = nlp.grad(st.y)
     iu = nlp.u1_index()
+    n = nlp.n
     out = {}
     for name, (dc, dd, dgrad, dfp) in nlp.parameter_derivatives(st.y).items():
-        b = -dgrad - Jc.T @ (Qc[:, None] * dc)
-        if ipm.md:
-            b = b - Jd.T @ (Qd[:, None] * dd)
-        dy = np.linalg.solve(Lc.T, np.linalg.solve(Lc, b))
+        rhs = -np.vstack([dgrad, dc, dd])
+        dy = lu.solve(np.asarray(rhs, dtype=np.float64))[:n, :]
         out[name] = dict(dy=dy, du1=dy[iu, :], df=dfp + gf @ dy)
     return out
 

@@ -20,12 +20,20 @@ One Newton iteration (eqs. 10-11, 14, 17, 22-25):
     dbeta = mu/s - beta - Q ds
     dzL = mu/(y-lb) - zL - Sigma_L dy,  dzU = mu/(ub-y) - zU + Sigma_U dy
 Step (eq. 26): one alpha for the whole primal-dual vector z, from a
-backtracking line search on an l1 merit started at the fraction-to-boundary
-limit of every positive quantity (s, bound gaps, beta, zL, zU).  A single step
-keeps omega - beta shrinking by (1 - alpha) per iteration; the lifted
-multipliers grow like mu / gamma away from the solution, so separate primal and
-dual steps would let that difference blow up.  Barrier update after the inner test (eq. 27),
-termination on the mu = 0 optimality error (eq. 28).
+backtracking line search started at the fraction-to-boundary limit of every
+positive quantity (s, bound gaps, beta, zL, zU).  A single step keeps
+omega - beta shrinking by (1 - alpha) per iteration; the lifted multipliers
+grow like mu / gamma away from the solution, so separate primal and dual steps
+would let that difference blow up.  The line search is the filter method of
+the interior-point reference the paper builds on (Waechter and Biegler): a
+trial point is judged by the constraint violation theta = |g^l + s|_1 and the
+barrier objective phi = f - mu (sum ln s + sum ln bound gaps) against a filter
+of (theta, phi) pairs that is reset whenever mu changes; an Armijo decrease of
+phi is required when theta is small and the step is a descent direction (the
+switching condition), sufficient decrease of theta or phi otherwise.  No
+second-order correction and no restoration phase: a step below the minimal
+step length ends the solve with status 2.  Barrier update after the inner test
+(eq. 27), termination on the mu = 0 optimality error (eq. 28).
 
 The constants the paper leaves open are fixed in ``IPMOptions``; the GPU library
 uses the same values.
@@ -63,6 +71,16 @@ class IPMOptions:
     km: float = 1.0 / 3.0
     bound_push: float = 1e-2
     slack_push: float = 1e-2
+    # filter line search
+    filter_gamma_theta: float = 1e-5
+    filter_gamma_phi: float = 1e-8
+    filter_s_theta: float = 1.1
+    filter_s_phi: float = 2.3
+    filter_delta: float = 1.0
+    alpha_min_frac: float = 0.05
+    theta_max_fact: float = 1e4
+    theta_min_fact: float = 1e-4
+    filter_cap: int = 128
 
 
 STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "regularization_fail",
@@ -208,16 +226,19 @@ class LiftedIPM:
             e.append(np.max(np.abs((gU * st.zU - mu)[self.hasU])))
         return float(max(e))
 
-    def merit(self, y, s, mu, nu):
-        nlp = self.nlp
+    def barrier_objective(self, y, s, mu, fval):
+        """phi_mu = f - mu sum ln s - mu sum ln(bound gaps)."""
         gL, gU = self.gaps(y)
-        phi = nlp.f(y) - mu * np.sum(np.log(s))
+        phi = fval - mu * np.sum(np.log(s))
         if np.any(self.hasL):
             phi -= mu * np.sum(np.log(gL[self.hasL]))
         if np.any(self.hasU):
             phi -= mu * np.sum(np.log(gU[self.hasU]))
-        phi += nu * np.sum(np.abs(self.g_lifted(nlp.cons_c(y), nlp.cons_d(y)) + s))
         return float(phi)
+
+    def violation(self, y, s):
+        """theta = |g^l(y) + s|_1."""
+        return float(np.sum(np.abs(self.g_lifted(self.nlp.cons_c(y), self.nlp.cons_d(y)) + s)))
 
     # ---- main loop ----------------------------------------------------
     def solve(self, start: IPMState, mu0: float, record=False, fixed_mu=False, tol=None):
@@ -229,8 +250,10 @@ class LiftedIPM:
         tol = o.tol if tol is None else tol
         st = start.copy()
         mu = mu0
-        nu = 1.0
         self.eta_last = 0.0
+        theta_max = theta_min = None
+        filt = []            # (theta, phi) pairs, insertion order
+        filt_mu = None
         trace = []
         status = 1
         it = 0
@@ -280,28 +303,59 @@ class LiftedIPM:
                 adu = min(adu, _ftb(st.zL[self.hasL], dzL[self.hasL], tau))
             if np.any(self.hasU):
                 adu = min(adu, _ftb(st.zU[self.hasU], dzU[self.hasU], tau))
-            # l1 merit line search (eq. 26)
-            nu = max(nu, float(np.max(np.abs(st.omega + dom))) + 1.0)
-            phi0 = self.merit(st.y, st.s, mu, nu)
+            # filter line search (eq. 26)
+            theta = float(np.sum(np.abs(r4)))
+            phi0 = self.barrier_objective(st.y, st.s, mu, f)
             Dphi = (float(gf @ dy) - mu * float(np.sum(ds / st.s))
                     - mu * float(np.sum(np.where(self.hasL, dy / gL, 0.0)))
-                    + mu * float(np.sum(np.where(self.hasU, dy / gU, 0.0)))
-                    - nu * float(np.sum(np.abs(r4))))
+                    + mu * float(np.sum(np.where(self.hasU, dy / gU, 0.0))))
+            if it == 0:
+                theta_max = o.theta_max_fact * max(1.0, theta)
+                theta_min = o.theta_min_fact * max(1.0, theta)
+            if mu != filt_mu:
+                filt = []
+                filt_mu = mu
+            g_th, g_ph, s_th, s_ph, dl = (o.filter_gamma_theta, o.filter_gamma_phi, o.filter_s_theta,
+                                          o.filter_s_phi, o.filter_delta)
+            if Dphi < 0.0:
+                amin = min(g_th, g_ph * theta / (-Dphi))
+                if theta <= theta_min:
+                    amin = min(amin, dl * theta ** s_th / (-Dphi) ** s_ph)
+            else:
+                amin = g_th
+            amin *= o.alpha_min_frac
             alpha = min(amax, adu)
             accepted = False
             trials = 0
-            for trials in range(1, o.ls_max + 1):
+            while alpha >= amin and trials < o.ls_max:
+                trials += 1
                 yt = st.y + alpha * dy
                 stt = st.s + alpha * ds
-                phit = self.merit(yt, stt, mu, nu)
-                if np.isfinite(phit) and phit <= phi0 + o.armijo * alpha * Dphi + 10.0 * EPS * abs(phi0):
-                    accepted = True
+                tht = self.violation(yt, stt)
+                pht = self.barrier_objective(yt, stt, mu, nlp.f(yt))
+                ok = np.isfinite(tht) and np.isfinite(pht) and tht < theta_max
+                if ok:
+                    ok = all(tht < tf or pht < pf for (tf, pf) in filt)
+                if ok:
+                    switching = (Dphi < 0.0 and theta <= theta_min
+                                 and alpha * (-Dphi) ** s_ph > dl * theta ** s_th)
+                    if switching:
+                        accepted = pht <= phi0 + o.armijo * alpha * Dphi + 10.0 * EPS * abs(phi0)
+                    else:
+                        accepted = tht <= (1.0 - g_th) * theta or pht <= phi0 - g_ph * theta
+                        if accepted:
+                            entry = ((1.0 - g_th) * theta, phi0 - g_ph * theta)
+                            filt = [e for e in filt if not (e[0] >= entry[0] and e[1] >= entry[1])]
+                            if len(filt) >= o.filter_cap:
+                                filt.pop(0)
+                            filt.append(entry)
+                if accepted:
                     break
                 alpha *= 0.5
             if record:
                 trace.append(dict(it=it, mu=mu, eta=eta, amax=amax, alpha=alpha, adu=adu,
-                                  E0=E0, Emu=Emu, trials=trials, phi=phi0, Dphi=Dphi, nu=nu,
-                                  dy_norm=float(np.max(np.abs(dy)))))
+                                  E0=E0, Emu=Emu, trials=trials, phi=phi0, Dphi=Dphi, theta=theta,
+                                  filter=len(filt), dy_norm=float(np.max(np.abs(dy)))))
             if not accepted:
                 status = 2
                 break

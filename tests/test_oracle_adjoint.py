@@ -97,3 +97,62 @@ def test_vjp_is_seeded_jacobian():
     g = vjp(ipm, res.state, np.array([0.3, -1.1]), 0.7)
     for k in sens:
         assert np.allclose(g[k], np.array([0.3, -1.1]) @ sens[k]["du1"] + 0.7 * sens[k]["df"])
+
+
+def test_condensed_and_uncondensed_sensitivities_agree():
+    """The condensed matrix of eqs. (14)/(17) and the uncondensed system give the
+    same sensitivities up to the rounding the condensation carries."""
+    from oracle.adjoint import condensed_matrix
+    w = distillation_workload("small", 3)
+    m = DistillationOCP.from_workload(w)
+    m.set_parameters(x0=w.x0, zF=w.zF(0), u_prev=w.u_prev0)
+    ipm, res = _solve_cold(m)
+    st = res.state
+    sens = sensitivities(ipm, st)
+    K, Jc, Jd, Qc, Qd = condensed_matrix(ipm, st)
+    dc, dd, dgrad, dfp = m.parameter_derivatives(st.y)["x0"]
+    dy = np.linalg.solve(K, -dgrad - Jc.T @ (Qc[:, None] * dc) - Jd.T @ (Qd[:, None] * dd))
+    assert np.max(np.abs(dy[m.u1_index(), :] - sens["x0"]["du1"])) <= 1e-4 * max(1.0, np.max(np.abs(dy)))
+
+
+def test_plate_sensitivities_match_central_differences():
+    from oracle.plate import PlateOCP
+    from workloads import plate_workload
+    w = plate_workload("large", 0, G=8, H=3)   # at G = 4 two segments drive the same corner node only
+    m = PlateOCP.from_workload(w)
+    ipm, res = _solve_cold(m)
+    mu = res.mu
+    st = ipm.solve(res.state, mu, fixed_mu=True, tol=1e-13).state
+    sens = sensitivities(ipm, st)
+    base = dict(x0=m.x0.copy(), setpoint=m.target.copy())
+    h = 1e-6
+    for group, idx in [("x0", 0), ("x0", 5), ("setpoint", 3), ("setpoint", 10)]:
+        vals = []
+        for sgn in (+1, -1):
+            v = base[group].copy()
+            v[idx] += sgn * h
+            m.set_parameters(**{group: v})
+            s2 = ipm.solve(st, mu, fixed_mu=True, tol=1e-13)
+            assert s2.status == 0
+            vals.append((m.u1(s2.state.y), m.f(s2.state.y)))
+        m.set_parameters(**{group: base[group]})
+        du_fd = (vals[0][0] - vals[1][0]) / (2 * h)
+        df_fd = (vals[0][1] - vals[1][1]) / (2 * h)
+        scale = max(1e-3, np.max(np.abs(du_fd)))
+        assert np.max(np.abs(sens[group]["du1"][:, idx] - du_fd)) <= 1e-5 * scale + 1e-7, (group, idx)
+        assert abs(sens[group]["df"][idx] - df_fd) <= 1e-5 * max(1e-3, abs(df_fd)) + 1e-7, (group, idx)
+
+
+def test_plate_setpoint_gradient_envelope_theorem():
+    """The target field enters only the objective: df*/dT*_p = -2 sum_k (T_kp - T*_p)
+    up to the barrier and lifting terms."""
+    from oracle.plate import PlateOCP
+    from workloads import plate_workload
+    w = plate_workload("large", 2, G=8, H=4)
+    m = PlateOCP.from_workload(w)
+    ipm, res = _solve_cold(m)
+    st = ipm.solve(res.state, res.mu, fixed_mu=True, tol=1e-13).state
+    sens = sensitivities(ipm, st)
+    T = st.y.reshape(m.H, m.ns)[:, :m.nx]
+    partial = -2.0 * np.sum(T - m.target[None, :], axis=0)
+    assert np.allclose(sens["setpoint"]["df"], partial, rtol=0, atol=1e-5)

@@ -4,6 +4,7 @@ import pytest
 
 from oracle.distillation import DistillationOCP
 from oracle.lq import LQOCP, random_lq
+from oracle.plate import PlateOCP
 from oracle.toy import ToyOCP
 
 H_CS = 1e-30
@@ -28,10 +29,12 @@ def _models():
     lq.set_parameters(x0=x0)
     toy = ToyOCP()
     toy.set_parameters(y0=0.7, tk=1.0)
-    return [d, lq, toy]
+    pl = PlateOCP(8, 3, 0.01)
+    pl.set_parameters(x0=rng.uniform(0.0, 0.5, pl.nx), target=rng.uniform(0.2, 0.8, pl.nx))
+    return [d, lq, toy, pl]
 
 
-@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1, 2, 3])
 def test_complex_step_derivatives(which):
     m = _models()[which]
     rng = np.random.default_rng(11)

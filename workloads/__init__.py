@@ -7,6 +7,7 @@ equations, so both the CPU oracle and the HIP path can take their inputs from it
 from .generators import (  # noqa: F401
     DistillationWorkload,
     distillation_workload,
+    batch_distillation_workloads,
     PlateWorkload,
     plate_workload,
     WORKLOADS,
