@@ -30,9 +30,13 @@ trial point is judged by the constraint violation theta = |g^l + s|_1 and the
 barrier objective phi = f - mu (sum ln s + sum ln bound gaps) against a filter
 of (theta, phi) pairs that is reset whenever mu changes; an Armijo decrease of
 phi is required when theta is small and the step is a descent direction (the
-switching condition), sufficient decrease of theta or phi otherwise.  No
-second-order correction and no restoration phase: a step below the minimal
-step length ends the solve with status 2.  Barrier update after the inner test
+switching condition), sufficient decrease of theta or phi otherwise.  When
+the first trial point is rejected and does not reduce theta, up to soc_max
+second-order corrections are tried: the step is recomputed with the same
+factor from the residual alpha r4 + (g^l + s) at the trial point (accumulated
+over corrections) and taken, with its own fraction-to-boundary step, if the
+filter accepts it.  No restoration phase: a step below the minimal step length
+ends the solve with status 2.  Barrier update after the inner test
 (eq. 27), termination on the mu = 0 optimality error (eq. 28).
 
 The constants the paper leaves open are fixed in ``IPMOptions``; the GPU library
@@ -81,6 +85,8 @@ class IPMOptions:
     theta_max_fact: float = 1e4
     theta_min_fact: float = 1e-4
     filter_cap: int = 128
+    soc_max: int = 4            # second-order corrections per line search
+    soc_kappa: float = 0.99     # each correction must reduce theta by this factor
 
 
 STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "regularization_fail",
@@ -327,31 +333,68 @@ class LiftedIPM:
             alpha = min(amax, adu)
             accepted = False
             trials = 0
+            soc_dir = None
+
+            def acceptable(tht, pht, a):
+                nonlocal filt
+                ok = np.isfinite(tht) and np.isfinite(pht) and tht < theta_max
+                if ok:
+                    ok = all(tht < tf or pht < pf for (tf, pf) in filt)
+                if not ok:
+                    return False
+                switching = (Dphi < 0.0 and theta <= theta_min and a * (-Dphi) ** s_ph > dl * theta ** s_th)
+                if switching:
+                    return pht <= phi0 + o.armijo * a * Dphi + 10.0 * EPS * abs(phi0)
+                acc = tht <= (1.0 - g_th) * theta or pht <= phi0 - g_ph * theta
+                if acc:
+                    entry = ((1.0 - g_th) * theta, phi0 - g_ph * theta)
+                    filt = [e for e in filt if not (e[0] >= entry[0] and e[1] >= entry[1])]
+                    if len(filt) >= o.filter_cap:
+                        filt.pop(0)
+                    filt.append(entry)
+                return acc
+
             while alpha >= amin and trials < o.ls_max:
                 trials += 1
                 yt = st.y + alpha * dy
                 stt = st.s + alpha * ds
                 tht = self.violation(yt, stt)
                 pht = self.barrier_objective(yt, stt, mu, nlp.f(yt))
-                ok = np.isfinite(tht) and np.isfinite(pht) and tht < theta_max
-                if ok:
-                    ok = all(tht < tf or pht < pf for (tf, pf) in filt)
-                if ok:
-                    switching = (Dphi < 0.0 and theta <= theta_min
-                                 and alpha * (-Dphi) ** s_ph > dl * theta ** s_th)
-                    if switching:
-                        accepted = pht <= phi0 + o.armijo * alpha * Dphi + 10.0 * EPS * abs(phi0)
-                    else:
-                        accepted = tht <= (1.0 - g_th) * theta or pht <= phi0 - g_ph * theta
-                        if accepted:
-                            entry = ((1.0 - g_th) * theta, phi0 - g_ph * theta)
-                            filt = [e for e in filt if not (e[0] >= entry[0] and e[1] >= entry[1])]
-                            if len(filt) >= o.filter_cap:
-                                filt.pop(0)
-                            filt.append(entry)
-                if accepted:
+                if acceptable(tht, pht, alpha):
+                    accepted = True
                     break
+                if trials == 1 and np.isfinite(tht) and tht >= theta and o.soc_max > 0:
+                    r4s = alpha * r4 + (self.g_lifted(nlp.cons_c(yt), nlp.cons_d(yt)) + stt)
+                    th_old = theta
+                    for _p in range(o.soc_max):
+                        d = self.soc_direction(r4s)
+                        a_s = _ftb(st.s, d[1], tau)
+                        if np.any(self.hasL):
+                            a_s = min(a_s, _ftb(gL[self.hasL], d[0][self.hasL], tau))
+                        if np.any(self.hasU):
+                            a_s = min(a_s, _ftb(gU[self.hasU], -d[0][self.hasU], tau))
+                        a_s = min(a_s, _ftb(st.beta, d[3], tau))
+                        if np.any(self.hasL):
+                            a_s = min(a_s, _ftb(st.zL[self.hasL], d[4][self.hasL], tau))
+                        if np.any(self.hasU):
+                            a_s = min(a_s, _ftb(st.zU[self.hasU], d[5][self.hasU], tau))
+                        ys, ss = st.y + a_s * d[0], st.s + a_s * d[1]
+                        ths = self.violation(ys, ss)
+                        phs = self.barrier_objective(ys, ss, mu, nlp.f(ys))
+                        if acceptable(ths, phs, alpha):
+                            soc_dir = d
+                            alpha = a_s
+                            accepted = True
+                            break
+                        if not np.isfinite(ths) or ths > o.soc_kappa * th_old:
+                            break
+                        r4s = a_s * r4s + (self.g_lifted(nlp.cons_c(ys), nlp.cons_d(ys)) + ss)
+                        th_old = ths
+                    if accepted:
+                        break
                 alpha *= 0.5
+            if soc_dir is not None:
+                dy, ds, dom, dbe, dzL, dzU = soc_dir
             if record:
                 trace.append(dict(it=it, mu=mu, eta=eta, amax=amax, alpha=alpha, adu=adu,
                                   E0=E0, Emu=Emu, trials=trials, phi=phi0, Dphi=Dphi, theta=theta,
@@ -408,6 +451,7 @@ class LiftedIPM:
                 if eta > o.eta_max:
                     return None
             self.eta_last = eta
+        self._soc_ctx = (r1, r2, Q, Jc, Jd, gL, gU, sigL, sigU, mu, st)
         dy = self.chol.solve(rhs)
         ds = -r4 - self.G(Jc, Jd, dy)
         dom = -r2 - Q * ds
@@ -416,6 +460,19 @@ class LiftedIPM:
         dzU = np.where(self.hasU, mu / gU - st.zU + sigU * dy, 0.0)
         return dict(dy=dy, ds=ds, domega=dom, dbeta=dbe, dzL=dzL, dzU=dzU, eta=eta,
                     K=K0, rhs=rhs, W=W, r1=r1, r2=r2, r4=r4, Q=Q, sigL=sigL, sigU=sigU)
+
+    def soc_direction(self, r4s):
+        """Directions of the last Newton step's system (same factor) with the
+        constraint residual r4 replaced by r4s (a second-order correction)."""
+        r1, r2, Q, Jc, Jd, gL, gU, sigL, sigU, mu, st = self._soc_ctx
+        rhs = -r1 - self.GT(Jc, Jd, Q * r4s - r2)
+        dy = self.chol.solve(rhs)
+        ds = -r4s - self.G(Jc, Jd, dy)
+        dom = -r2 - Q * ds
+        dbe = mu / st.s - st.beta - Q * ds
+        dzL = np.where(self.hasL, mu / gL - st.zL - sigL * dy, 0.0)
+        dzU = np.where(self.hasU, mu / gU - st.zU + sigU * dy, 0.0)
+        return dy, ds, dom, dbe, dzL, dzU
 
     def multipliers(self, st):
         """Equality multipliers of the original problem: lam = omega+ - omega-."""

@@ -4,15 +4,34 @@ Given the lower-triangular sparsity pattern of the condensed matrix K_c^l
 (diagonal included), compute
 
   * the fill-reducing permutation P (eq. 19).  The paper names minimum degree
-    and nested dissection without fixing one; the reading taken here is exact
+    and nested dissection without fixing one.  The readings taken here: exact
     minimum degree on the elimination graph (true degrees, no mass elimination,
     no absorption, no dense-row handling), ties broken by the smallest original
-    index, followed by a postorder of the elimination tree;
+    index, for the distillation family; lattice nested dissection (rule below)
+    for the plate family, whose condensed matrix is a three-dimensional
+    (stage x grid) lattice where minimum degree is slow and fills badly.  Either
+    is followed by a postorder of the elimination tree;
   * the elimination tree: parent(j) = min{ i > j : L_ij != 0 };
   * the column structures of L_P: struct(L_*j) = struct(K_P lower col j) united
     with struct(L_*c) minus {c} over the children c of j (Section 3.2.3);
   * fundamental supernodes and a relaxed amalgamation (rule below), which fix
     the stored pattern S_L including any explicit zeros.
+
+Lattice nested dissection.  The variables of stage t are lattice points
+(t, b, a) at index t ns + b G + a (a, b < G) followed by the stage's controls.
+A box [t0, t1) x [b0, b1) x [a0, a1) of lattice points, with the controls
+assigned to it, is ordered as follows.  If it holds at most ND_LEAF points, or
+no dimension can be cut, its points in increasing index, then its controls in
+increasing index.  Otherwise it is cut along one dimension by a separator slab
+of thickness 1 in time (extent >= 3 needed) or 2 in space (extent >= 4
+needed), since the condensed matrix couples stages only to their neighbours
+and grid nodes up to two steps apart.  The dimension with the fewest separator
+points wins, ties in the order time, b, a; the slab starts at
+lo + (extent - thickness) // 2.  A control of the box goes to the left
+(right) part if the lattice points it is coupled to in the matrix meet the
+left (right) part only, otherwise to the separator.  Order: left box, right
+box, the separator's points in increasing index, its controls in increasing
+index.
 
 Conventions: ``perm[k]`` is the original index of the k-th pivot (new -> old),
 ``iperm[v]`` is the pivot position of original index v (old -> new).
@@ -34,6 +53,7 @@ from __future__ import annotations
 import heapq
 import numpy as np
 
+ND_LEAF = 64
 AMALG_MAX_WIDTH = 64
 AMALG_SMALL = 8
 AMALG_ZERO_FRAC = 0.25
@@ -71,6 +91,66 @@ def min_degree_order(n, adj):
             heapq.heappush(heap, (len(s), a))
         adj[v] = set()
     assert len(order) == n
+    return np.array(order, dtype=np.int64)
+
+
+def lattice_nd_order(n, adj, H, G, ns):
+    """Lattice nested dissection (rule in the module docstring): perm (new -> old)."""
+    nx = G * G
+
+    def point(v):
+        t, l = divmod(v, ns)
+        return (t, l // G, l % G) if l < nx else None
+
+    ctrl_pts = {}
+    for t in range(H):
+        for l in range(nx, ns):
+            v = t * ns + l
+            ctrl_pts[v] = [pt for pt in (point(u) for u in adj[v]) if pt is not None]
+
+    def inside(pt, box):
+        (t0, t1), (b0, b1), (a0, a1) = box
+        return t0 <= pt[0] < t1 and b0 <= pt[1] < b1 and a0 <= pt[2] < a1
+
+    def points(box):
+        (t0, t1), (b0, b1), (a0, a1) = box
+        return [t * ns + b * G + a for t in range(t0, t1) for b in range(b0, b1) for a in range(a0, a1)]
+
+    order = []
+
+    def rec(box, ctrls):
+        ext = [hi - lo for lo, hi in box]
+        vol = ext[0] * ext[1] * ext[2]
+        cands = []
+        if ext[0] >= 3:
+            cands.append((ext[1] * ext[2], 0, 1))
+        if ext[1] >= 4:
+            cands.append((2 * ext[0] * ext[2], 1, 2))
+        if ext[2] >= 4:
+            cands.append((2 * ext[0] * ext[1], 2, 2))
+        if vol <= ND_LEAF or not cands:
+            order.extend(points(box))
+            order.extend(sorted(ctrls))
+            return
+        _, dim, th = min(cands)
+        lo, hi = box[dim]
+        pos = lo + (hi - lo - th) // 2
+        left = list(box); left[dim] = (lo, pos)
+        sep = list(box); sep[dim] = (pos, pos + th)
+        right = list(box); right[dim] = (pos + th, hi)
+        cl, cr, cs = [], [], []
+        for v in ctrls:
+            inl = any(inside(pt, left) for pt in ctrl_pts[v])
+            inr = any(inside(pt, right) for pt in ctrl_pts[v])
+            (cl if inl and not inr else cr if inr and not inl else cs).append(v)
+        rec(left, cl)
+        rec(right, cr)
+        order.extend(points(sep))
+        order.extend(sorted(cs))
+
+    rec([(0, H), (0, G), (0, G)], [t * ns + l for t in range(H) for l in range(nx, ns)])
+    if sorted(order) != list(range(n)):
+        raise AssertionError("nested dissection did not produce a permutation")
     return np.array(order, dtype=np.int64)
 
 
@@ -188,15 +268,20 @@ def amalgamate(starts, parent, struct, n):
     return snode_ptr, rows
 
 
-def analyze(n, rows, cols):
+def analyze(n, rows, cols, lattice=None):
     """Full symbolic analysis of a lower pattern (original indexing).
 
-    Returns a dict with perm, iperm, parent (column etree in final order),
-    colcount (per column of the exact factor), nnz_L (exact), snode_ptr,
-    snode_rows (row list per supernode, stored pattern), snode_parent.
+    lattice = (H, G, ns) selects the lattice nested dissection of a plate
+    transcription; otherwise exact minimum degree.  Returns a dict with perm,
+    iperm, parent (column etree in final order), colcount (per column of the
+    exact factor), nnz_L (exact), snode_ptr, snode_rows (row list per supernode,
+    stored pattern), snode_parent.
     """
     adj = adjacency_from_lower(n, rows, cols)
-    perm_md = min_degree_order(n, adj)
+    if lattice is not None:
+        perm_md = lattice_nd_order(n, adj, *lattice)
+    else:
+        perm_md = min_degree_order(n, adj)
     iperm_md = np.empty(n, dtype=np.int64)
     iperm_md[perm_md] = np.arange(n)
     colrows = permute_lower(rows, cols, iperm_md)

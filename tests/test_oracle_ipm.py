@@ -185,3 +185,19 @@ def test_inertia_correction_path():
     lam, om = ipm.multipliers(res.state)
     e = kkt_error(m, res.state.y, lam, om, res.state.zL, res.state.zU)
     assert e["max"] <= 1e-8
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_medium_cold_solve_converges(seed):
+    """The benchmark's 40-tray, 100-stage column: the filter line search with
+    second-order corrections converges from the cold start to the tolerance."""
+    from oracle.distillation import DistillationOCP
+    w = distillation_workload("medium", seed)
+    m = DistillationOCP.from_workload(w)
+    m.set_parameters(x0=w.x0, zF=w.zF(0), u_prev=w.u_prev0)
+    ipm = LiftedIPM(m)
+    res = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
+    assert res.status == 0 and res.iters <= 60
+    st = res.state
+    lam = st.omega[:m.m_c] - st.omega[m.m_c:2 * m.m_c]
+    assert kkt_error(m, st.y, lam, st.omega[2 * m.m_c:], st.zL, st.zU)["max"] <= 1e-8

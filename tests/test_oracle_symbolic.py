@@ -182,3 +182,45 @@ def test_analyze_invariants_distillation():
             assert set(rows_[s][l - f:].tolist()) <= set(rows_[p].tolist())
         else:
             assert len(rows_[s]) == l - f
+
+
+@pytest.mark.parametrize("G,H", [(4, 3), (8, 4)])
+def test_lattice_nested_dissection(G, H):
+    """The plate's nested dissection is a permutation, its factor pattern equals
+    brute-force dense elimination in that order, and it fills less than the
+    stage-major natural order once the lattice is not tiny (the reason to
+    dissect a 3-d lattice)."""
+    from oracle.plate import PlateOCP
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
+    n, iperm = m.n, a["iperm"]
+    assert sorted(a["perm"]) == list(range(n))
+    M, par_dense = _dense_symbolic(n, [iperm[i] for i in r], [iperm[j] for j in c])
+    assert np.array_equal(a["parent"], par_dense)
+    assert a["nnz_L"] == int(M.sum())
+    if G >= 8:   # on the smallest lattice the separators are most of the points
+        Mn, _ = _dense_symbolic(n, list(r), list(c))
+        assert a["nnz_L"] < int(Mn.sum())
+
+
+def test_lattice_nested_dissection_top_separator():
+    """A time cut of the stage lattice: with a slab of one stage the two halves
+    share no matrix entry, so the slab's columns come last and the elimination
+    tree has the two halves as separate subtrees below it."""
+    from oracle.plate import PlateOCP
+    G, H = 4, 7
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    adj = S.adjacency_from_lower(m.n, r, c)
+    perm = S.lattice_nd_order(m.n, adj, H, G, m.ns)
+    # box 7 x 4 x 4 = 112 points > leaf: time cut at 0 + (7 - 1) // 2 = 3 (16 points beat 2*7*4 = 56)
+    slab = [3 * m.ns + p for p in range(G * G)]
+    # the slab's points close the order, followed only by the controls no side holds alone
+    tail = perm[len(perm) - len(slab) - 16:].tolist()
+    assert set(slab) <= set(tail)
+    assert all(v % m.ns >= G * G for v in tail if v not in slab)
+    left = set(range(0, 3 * m.ns)) - set(slab)
+    right = set(range(4 * m.ns, m.n))
+    for i, j in zip(r, c):
+        assert not ((i in left and j in right) or (i in right and j in left))
