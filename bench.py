@@ -22,6 +22,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -89,6 +90,138 @@ def cpu_baseline(seed: int, budget_s: float):
             "p50_resolve_ms": _percentile([t * 1e3 for t in times], 50)}
 
 
+def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
+    """Batched form: 64 ragged distillation instances (trays U{20..60}, horizons
+    U{40..120}, alpha U(2,3), own setpoints and noise), one cold solve, then
+    `rounds` warm re-solve rounds; the same instances solved one by one on
+    separate handles are timed beside it.  Per-instance latency of a batched
+    re-solve is the wall time of the round it belongs to."""
+    from workloads import batch_distillation_workloads
+    ws = batch_distillation_workloads(count, base_seed)
+    opts = N.default_options(graph=0 if eager else 1)
+
+    def make():
+        ps = []
+        for w in ws:
+            q = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+            q.analyze()
+            q.set_parameters(w.x0, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
+            ps.append(q)
+        return ps
+
+    def params(q, w, u1, x1, k):
+        q.set_parameters(w.next_measurement(x1, k), setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(k + 1), u_prev=u1)
+
+    t0 = time.perf_counter()
+    pb = make()
+    t_an = time.perf_counter() - t0
+    b = N.Batch(pb)
+    t0 = time.perf_counter()
+    rc, _ = b.solve(warm=False, options=opts)
+    t_cold = time.perf_counter() - t0
+    fs = [q.first_stage() for q in pb]
+    lat_b, it_b, st_b = [], 0, []
+    t_begin = time.perf_counter()
+    for k in range(rounds):
+        t = time.perf_counter()
+        for q, w, (u1, x1) in zip(pb, ws, fs):
+            params(q, w, u1, x1, k)
+        rc, res = b.solve(warm=True, options=opts)
+        fs = [q.first_stage() for q in pb]
+        dt = time.perf_counter() - t
+        lat_b += [dt * 1e3] * count
+        it_b += sum(r.iters for r in res)
+        st_b += [r.status for r in res]
+    el_b = time.perf_counter() - t_begin
+    b.close()
+    ps = make()
+    for q in ps:
+        q.solve(warm=False, options=opts)
+    fs = [q.first_stage() for q in ps]
+    lat_s, it_s, st_s = [], 0, []
+    t_begin = time.perf_counter()
+    for k in range(rounds):
+        for i, (q, w) in enumerate(zip(ps, ws)):
+            t = time.perf_counter()
+            params(q, w, fs[i][0], fs[i][1], k)
+            r = q.solve(warm=True, options=opts)
+            fs[i] = q.first_stage()
+            lat_s.append((time.perf_counter() - t) * 1e3)
+            it_s += r.iters
+            st_s.append(r.status)
+    el_s = time.perf_counter() - t_begin
+    n_tot = sum(q.n for q in pb)
+    return {"workload": f"{count} distillation instances, trays U{{20..60}}, horizons U{{40..120}}, alpha U(2,3), "
+                        f"seeds {base_seed}..{base_seed + count - 1}, {rounds} warm re-solve rounds",
+            "n_total": n_tot, "analyze_s": t_an, "cold_batch_ms": t_cold * 1e3,
+            "resolves_per_s": count * rounds / el_b, "iters_per_s": it_b / el_b,
+            "p50_instance_ms": _percentile(lat_b, 50), "p99_instance_ms": _percentile(lat_b, 99),
+            "nonzero_status": sum(1 for s_ in st_b if s_ != 0),
+            "sequential": {"resolves_per_s": count * rounds / el_s, "iters_per_s": it_s / el_s,
+                           "p50_instance_ms": _percentile(lat_s, 50), "p99_instance_ms": _percentile(lat_s, 99),
+                           "nonzero_status": sum(1 for s_ in st_s if s_ != 0)},
+            "speedup_vs_sequential": el_s / el_b}
+
+
+def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
+    """Heated plate: G x G grid, horizon H, dt 0.01, 16 heaters in [0, 1],
+    T <= 1.5, Gaussian-bump target from the seed, T0 = 0.  One analyze and cold
+    solve, then warm re-solves where the plant is the model (the next
+    measurement is the predicted first-stage field).  With adjoint, after each
+    re-solve d u1*/d x0 (nu x G^2) and d f*/d setpoint (G^2) are computed."""
+    from workloads import plate_workload
+    w = plate_workload("large", seed, G=G, H=H)
+    p = N.Problem(N.plate_structure(G, H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi))
+    t0 = time.perf_counter()
+    p.analyze()
+    t_an = time.perf_counter() - t0
+    sym = p.symbolic_sizes()
+    p.set_parameters(w.T0, setpoint=w.target, u_prev=np.full(16, 0.5 * (w.u_lo + w.u_hi)))
+    opts = N.default_options(timing=1, graph=0 if eager else 1)
+    t0 = time.perf_counter()
+    r0 = p.solve(warm=False, options=opts)
+    t_cold = time.perf_counter() - t0
+    u1, x1 = p.first_stage()
+    lat, lat_adj, lat_vjp, iters, facts, ms_fact, statuses = [], [], [], 0, 0, 0.0, []
+    for k in range(resolves):
+        t = time.perf_counter()
+        p.set_parameters(x1, u_prev=u1)
+        r = p.solve(warm=True, options=opts)
+        u1, x1 = p.first_stage()
+        lat.append((time.perf_counter() - t) * 1e3)
+        iters += r.iters
+        facts += r.factorizations
+        ms_fact += r.ms_factor
+        statuses.append(r.status)
+        if adjoint:
+            t = time.perf_counter()
+            rc, J = p.jacobian_u1_x0()
+            lat_adj.append((time.perf_counter() - t) * 1e3)
+            t = time.perf_counter()
+            rc2, g = p.adjoint(np.zeros(16), 1.0)
+            lat_vjp.append((time.perf_counter() - t) * 1e3)
+    tot = sum(lat) / 1e3
+    flops = float(sym["flops"])
+    achieved = (facts * flops / (ms_fact * 1e-3)) / 1e12 if ms_fact > 0 else None
+    out = {"workload": f"heated plate {G}x{G}, horizon {H}, dt {w.dt}, 16 heaters, seed {seed}, "
+                       f"{resolves} warm re-solves (plant = model)",
+           "n": p.n, "nnz_l": sym["nnz_l"], "supernodes": sym["n_supernodes"], "analyze_ms": t_an * 1e3,
+           "cold_solve_ms": t_cold * 1e3, "cold_iters": r0.iters, "cold_status": r0.status,
+           "p50_resolve_ms": _percentile(lat, 50), "p99_resolve_ms": _percentile(lat, 99),
+           "iters_per_s": iters / tot if tot > 0 else None, "iters_per_resolve": iters / max(1, resolves),
+           "nonzero_status": sum(1 for s_ in statuses if s_ != 0),
+           "factor_ms": ms_fact / facts if facts else None,
+           "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                        "kernel": "numeric supernodal factorization (all launches of one factorization)",
+                        "flops_per_unit": flops}}
+    if adjoint:
+        out["adjoint"] = {"p50_jacobian_u1_x0_ms": _percentile(lat_adj, 50),
+                          "p50_objective_setpoint_gradient_ms": _percentile(lat_vjp, 50),
+                          "jacobian_shape": [16, G * G]}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +230,12 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched form")
+    ap.add_argument("--batch-only", action="store_true", help="only run the 64-instance batched form")
+    ap.add_argument("--no-plate", action="store_true", help="skip the heated-plate workloads")
+    ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
+    ap.add_argument("--adjoint-grid", type=int, default=64, help="grid of the differentiated form (64 in the full run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 10 times (counter calibration)")
     a = ap.parse_args(argv)
@@ -121,6 +260,14 @@ def main(argv=None):
     if not torch.cuda.is_available() or not N.device_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if a.batch_only:
+        print(json.dumps({"batched": run_batched(N, eager=a.eager)}), flush=True)
+        return 0
+    if a.plate_only:
+        print(json.dumps({"plate": run_plate(N, eager=a.eager),
+                          "plate_adjoint": run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True,
+                                                     eager=a.eager)}), flush=True)
+        return 0
     w = distillation_workload("medium", a.seed, n_resolves=a.warmup + a.steps + 1)
     p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
     sp = [w.xD_sp, w.xB_sp]
@@ -130,13 +277,14 @@ def main(argv=None):
     t_an = time.perf_counter() - t0
     p.set_parameters(w.x0, setpoint=sp, traj=w.zF(0), u_prev=w.u_prev0)
     r0 = p.solve(warm=False)
-    sol = p.solution()
+    u1, x1 = p.first_stage()
+    sol = {"u1": u1, "x1": x1}
     t_first = time.perf_counter() - t0
     if r0.status != 0:
         print(f"bench.py: cold solve failed with status {r0.status}", file=sys.stderr)
         return 1
     sym = p.symbolic_sizes()
-    opts = N.default_options(timing=1)
+    opts = N.default_options(timing=1, graph=0 if a.eager else 1)
 
     def resolve(k):
         nonlocal sol
@@ -144,7 +292,8 @@ def main(argv=None):
         t = time.perf_counter()
         p.set_parameters(x0, setpoint=sp, traj=w.zF(k + 1), u_prev=sol["u1"])
         res = p.solve(warm=True, options=opts)
-        sol = p.solution()
+        u1, x1 = p.first_stage()
+        sol = {"u1": u1, "x1": x1}
         return res, time.perf_counter() - t
 
     for k in range(a.warmup):
@@ -201,6 +350,11 @@ def main(argv=None):
                      "kernel": "numeric supernodal factorization (all levels of one factorization)",
                      "bytes_per_unit": bytes_per_factor},
     }
+    if not a.no_batch:
+        out["batched"] = run_batched(N, eager=a.eager)
+    if not a.no_plate:
+        out["plate"] = run_plate(N, eager=a.eager)
+        out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.seed, a.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -66,10 +66,13 @@ typedef struct nmpc_structure {
     double move_penalty; /* rho on |u_k - u_{k-1}|^2 */
     double x_lo, x_hi;   /* mole-fraction bounds */
     double u_lo, u_hi;   /* bounds on R and V */
-    /* heated plate (Section 4.2 family) */
-    int32_t grid;        /* G: G x G interior nodes */
+    /* heated plate (Section 4.2 family): G x G interior nodes (G a multiple of 4),
+     * 16 Dirichlet heater segments (4 per edge), conductivity 1 + cond_slope T
+     * averaged over each face, tracking objective sum_k sum_p (T_kp - T*_p)^2 */
+    int32_t grid;        /* G */
     double t_hi;         /* upper temperature bound */
     double c_lo, c_hi;   /* heater control bounds */
+    double cond_slope;   /* conductivity slope */
 } nmpc_structure;
 
 /* Interior-point constants (the paper leaves them open; see the design notes).
@@ -87,7 +90,21 @@ typedef struct nmpc_options {
     double kappa_sigma;
     double eta_first, eta_min, eta_max, kp_first, kp, km;
     double bound_push, slack_push;
+    /* filter line search (eq. 26 step, filter method of the cited interior-point
+     * reference): sufficient-decrease margins gamma_theta, gamma_phi; switching
+     * exponents s_theta, s_phi and factor delta; minimal step as a fraction of
+     * the switching bound; theta_max / theta_min as factors of the first
+     * iterate's violation; at most filter_cap entries (oldest dropped) */
+    double filter_gamma_theta, filter_gamma_phi, filter_s_theta, filter_s_phi, filter_delta;
+    double alpha_min_frac, theta_max_fact, theta_min_fact;
+    int32_t filter_cap;
+    /* second-order corrections of a rejected first trial point: at most soc_max,
+     * each must reduce the violation by the factor soc_kappa (0 disables them) */
+    int32_t soc_max;
+    double soc_kappa;
     int32_t timing;      /* 1: record HIP events around each phase (device times in nmpc_result) */
+    int32_t graph;       /* 1 (default): capture one pass of the method as a HIP graph and replay it;
+                            0: launch every kernel of every pass from the host */
 } nmpc_options;
 
 typedef struct nmpc_result {
@@ -99,6 +116,9 @@ typedef struct nmpc_result {
     double ms_total;     /* host wall time of the call */
     double ms_eval, ms_assemble, ms_factor, ms_solve, ms_linesearch; /* device phase times (0 unless timing enabled) */
     int32_t factor_launches; /* kernel launches spent in numeric factorizations */
+    int32_t passes;      /* passes enqueued: one per Newton iteration, plus one per extra
+                            factorization attempt or trial point (of the slowest instance of a batch) */
+    int32_t timing_lost; /* passes whose phase times could not be read (then left out of ms_*) */
 } nmpc_result;
 
 typedef struct nmpc_problem nmpc_problem;
@@ -150,9 +170,11 @@ nmpc_status nmpc_export_patterns(const nmpc_problem* p, int32_t* j_rows, int32_t
 
 /* Parameters p_k of the next solve (eq. 4), host arrays copied before return:
  * x0[nx] measured initial state; setpoint: distillation (xD*, xB*), plate
- * target field [G*G]; traj: distillation feed composition zF[H] (NULL keeps
- * the previous one); u_prev[nu]: control applied before stage 1 (NULL keeps
- * the previous one).  Errors: INVALID_ARG on NULL x0 or non-finite values. */
+ * target field [G*G] (NULL keeps the previous one); traj: distillation feed
+ * composition zF[H] (NULL keeps the previous one; the plate has none);
+ * u_prev[nu]: control applied before stage 1 (NULL keeps the previous one; the
+ * plate uses it only for the cold-start guess).  Errors: INVALID_ARG on NULL
+ * x0 or non-finite values. */
 nmpc_status nmpc_set_parameters(nmpc_problem* p, const double* x0, const double* setpoint,
                                 const double* traj, const double* u_prev);
 
@@ -214,8 +236,10 @@ nmpc_status nmpc_assemble(nmpc_problem* p, double mu, double* k_vals, double* rh
  * call; one forward/back solve per seed.
  * nmpc_adjoint: gradient of seed_u1 . u1* + seed_obj * f* (vector-Jacobian
  * product) with respect to x0 (grad_x0[nx]), the setpoint (grad_setpoint:
- * distillation (xD*, xB*)), the disturbance trajectory (grad_traj[H]) and
- * u_prev (grad_uprev[nu]); outputs may be NULL, seed_u1 may not.  Host arrays.
+ * distillation (xD*, xB*), plate the target field [G*G]), the disturbance
+ * trajectory (grad_traj: distillation zF[H]; untouched for the plate) and
+ * u_prev (grad_uprev[nu]; zeros for the plate); outputs may be NULL, seed_u1
+ * may not.  Host arrays.
  * BAD_ORDER without a solution; REG_FAIL (positive) when K needed eta > 0 to
  * factor (the gradient is then that of the regularized system). */
 nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj, double* grad_x0,
@@ -224,6 +248,28 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
 /* Jacobian d u1* / d x0 as an nu x nx row-major host matrix (nu solves with the
  * kept factor; same conditions as nmpc_adjoint). */
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
+
+/* Batches (the batched form): several analyzed problems, of any sizes, solved
+ * together.  Every kernel of a pass covers all instances at once (block ->
+ * instance tables, one launch per level of the deepest supernodal schedule),
+ * the method's decisions are taken per instance on the device, and an instance
+ * that has converged idles while the others continue.  Each instance's
+ * arithmetic is the same as in its own nmpc_solve.
+ * nmpc_batch_create: problems[count] (distinct, analyzed, each with a device)
+ * are referenced, not copied or owned: they must outlive the batch, and their
+ * parameters are still set with nmpc_set_parameters.  Errors: INVALID_ARG
+ * (NULL, count < 1, duplicates), BAD_ORDER (a problem not analyzed),
+ * NO_DEVICE. */
+typedef struct nmpc_batch nmpc_batch;
+nmpc_status nmpc_batch_create(nmpc_problem* const* problems, int32_t count, nmpc_batch** out);
+/* Solve every instance (Algorithm 2 per instance); warm as in nmpc_solve, for
+ * all instances.  per_instance[count] (may be NULL) receives each instance's
+ * result; the phase times are those of the whole batch.  Returns the largest
+ * instance status, or an error.  Afterwards each problem's solution is read
+ * with nmpc_get_solution. */
+nmpc_status nmpc_batch_solve(nmpc_batch* b, int32_t warm, const nmpc_options* opts, nmpc_result* per_instance);
+/* Release the batch (not its problems).  NULL is a no-op. */
+void nmpc_batch_destroy(nmpc_batch* b);
 
 /* Thread-local message for the last error on this thread. */
 const char* nmpc_last_error(void);

@@ -22,7 +22,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnmpc.so")
 ARCH = "gfx950"
 
-SOURCES = ["family.cpp", "symbolic.cpp", "capi.cpp", "kernels_model.hip", "kernels_linalg.hip", "device.hip"]
+SOURCES = ["family.cpp", "symbolic.cpp", "capi.cpp", "kernels_model.hip", "kernels_ipm.hip", "kernels_linalg.hip",
+           "kernels_big.hip", "device.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

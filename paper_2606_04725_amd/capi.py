@@ -23,7 +23,8 @@ class nmpc_structure(C.Structure):
                 ("n_trays", C.c_int32), ("alpha", C.c_double), ("feed_flow", C.c_double),
                 ("move_penalty", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("u_lo", C.c_double), ("u_hi", C.c_double),
-                ("grid", C.c_int32), ("t_hi", C.c_double), ("c_lo", C.c_double), ("c_hi", C.c_double)]
+                ("grid", C.c_int32), ("t_hi", C.c_double), ("c_lo", C.c_double), ("c_hi", C.c_double),
+                ("cond_slope", C.c_double)]
 
 
 class nmpc_options(C.Structure):
@@ -33,7 +34,12 @@ class nmpc_options(C.Structure):
                 ("armijo", C.c_double), ("ls_max", C.c_int32), ("max_iter", C.c_int32),
                 ("kappa_sigma", C.c_double), ("eta_first", C.c_double), ("eta_min", C.c_double),
                 ("eta_max", C.c_double), ("kp_first", C.c_double), ("kp", C.c_double), ("km", C.c_double),
-                ("bound_push", C.c_double), ("slack_push", C.c_double), ("timing", C.c_int32)]
+                ("bound_push", C.c_double), ("slack_push", C.c_double),
+                ("filter_gamma_theta", C.c_double), ("filter_gamma_phi", C.c_double),
+                ("filter_s_theta", C.c_double), ("filter_s_phi", C.c_double), ("filter_delta", C.c_double),
+                ("alpha_min_frac", C.c_double), ("theta_max_fact", C.c_double), ("theta_min_fact", C.c_double),
+                ("filter_cap", C.c_int32), ("soc_max", C.c_int32), ("soc_kappa", C.c_double),
+                ("timing", C.c_int32), ("graph", C.c_int32)]
 
 
 class nmpc_result(C.Structure):
@@ -41,7 +47,8 @@ class nmpc_result(C.Structure):
                 ("ls_trials", C.c_int32), ("mu", C.c_double), ("eta", C.c_double), ("E0", C.c_double),
                 ("objective", C.c_double), ("ms_total", C.c_double), ("ms_eval", C.c_double),
                 ("ms_assemble", C.c_double), ("ms_factor", C.c_double), ("ms_solve", C.c_double),
-                ("ms_linesearch", C.c_double), ("factor_launches", C.c_int32)]
+                ("ms_linesearch", C.c_double), ("factor_launches", C.c_int32), ("passes", C.c_int32),
+                ("timing_lost", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -70,6 +77,9 @@ SIGNATURES = {
     "nmpc_assemble": (C.c_int32, [_P, C.c_double, _D, _D]),
     "nmpc_adjoint": (C.c_int32, [_P, _D, C.c_double, _D, _D, _D, _D]),
     "nmpc_jacobian_u1_x0": (C.c_int32, [_P, _D]),
+    "nmpc_batch_create": (C.c_int32, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
+    "nmpc_batch_solve": (C.c_int32, [_P, C.c_int32, C.POINTER(nmpc_options), C.POINTER(nmpc_result)]),
+    "nmpc_batch_destroy": (None, [_P]),
     "nmpc_last_error": (C.c_char_p, []),
     "nmpc_device_available": (C.c_int32, []),
 }

@@ -6,6 +6,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -13,6 +14,11 @@ using nmpc::Problem;
 
 struct nmpc_problem {
     Problem impl;
+};
+
+struct nmpc_batch {
+    nmpc::Batch* impl = nullptr;
+    std::vector<nmpc_problem*> members;
 };
 
 namespace {
@@ -27,6 +33,15 @@ bool all_finite(const double* v, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(v[i])) return false;
     return true;
+}
+
+bool resolve_options(const nmpc_options* opts, nmpc_options& o) {
+    nmpc_default_options(&o);
+    if (opts) o = *opts;
+    return o.tol > 0 && o.gamma > 0 && o.mu_min > 0 && o.max_iter >= 0 && o.ls_max >= 1 && o.mu0_cold > 0 &&
+           o.mu0_warm > 0 && o.eta_first > 0 && o.kp_first > 1 && o.kp > 1 && o.eta_max > 0 && o.filter_cap >= 1 &&
+           o.filter_cap <= nmpc::kFilterCapacity && o.alpha_min_frac > 0 &&
+           o.soc_max >= 0 && o.soc_kappa > 0;
 }
 
 template <class F>
@@ -90,7 +105,19 @@ void nmpc_default_options(nmpc_options* o) {
     o->km = 1.0 / 3.0;
     o->bound_push = 1e-2;
     o->slack_push = 1e-2;
+    o->filter_gamma_theta = 1e-5;
+    o->filter_gamma_phi = 1e-8;
+    o->filter_s_theta = 1.1;
+    o->filter_s_phi = 2.3;
+    o->filter_delta = 1.0;
+    o->alpha_min_frac = 0.05;
+    o->theta_max_fact = 1e4;
+    o->theta_min_fact = 1e-4;
+    o->filter_cap = 128;
+    o->soc_max = 4;
+    o->soc_kappa = 0.99;
     o->timing = 0;
+    o->graph = 1;
 }
 
 nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
@@ -101,7 +128,8 @@ nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
         std::string err;
         if (!nmpc::build_structure(*s, h->impl.st, err)) {
             delete h;
-            return fail(s->family == NMPC_FAMILY_DISTILLATION ? NMPC_ERR_INVALID_ARG : NMPC_ERR_UNSUPPORTED, err);
+            const bool known = s->family == NMPC_FAMILY_DISTILLATION || s->family == NMPC_FAMILY_HEATED_PLATE;
+            return fail(known ? NMPC_ERR_INVALID_ARG : NMPC_ERR_UNSUPPORTED, err);
         }
         const auto& st = h->impl.st;
         h->impl.x0.assign(st.nx, 0.5);
@@ -111,6 +139,10 @@ nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
         if (s->family == NMPC_FAMILY_DISTILLATION) {
             h->impl.setpoint = {0.95, 0.05};
             h->impl.u_prev = {2.0, 2.5};
+        } else {                               // plate: zero field, zero target, mid-range heaters
+            h->impl.x0.assign(st.nx, 0.0);
+            h->impl.setpoint.assign(st.nx, 0.0);
+            h->impl.u_prev.assign(st.nu, 0.5 * (s->c_lo + s->c_hi));
         }
         *out = h;
         return NMPC_OK;
@@ -233,10 +265,7 @@ nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, 
     if (!nmpc::device_present() || !p->impl.dev) return fail(NMPC_ERR_NO_DEVICE, "solve: no HIP device");
     if (warm && !p->impl.have_iterate) return fail(NMPC_ERR_BAD_ORDER, "solve: warm start without a previous iterate");
     nmpc_options o;
-    nmpc_default_options(&o);
-    if (opts) o = *opts;
-    if (!(o.tol > 0) || !(o.gamma > 0) || !(o.mu_min > 0) || o.max_iter < 0 || o.ls_max < 1)
-        return fail(NMPC_ERR_INVALID_ARG, "solve: invalid options");
+    if (!resolve_options(opts, o)) return fail(NMPC_ERR_INVALID_ARG, "solve: invalid options");
     return guarded([&]() -> nmpc_status {
         nmpc_result r{};
         std::string err;
@@ -255,6 +284,11 @@ nmpc_status nmpc_get_solution(const nmpc_problem* p, double* y, double* lam, dou
                               double* zU, double* u1, double* x1) {
     if (!p) return fail(NMPC_ERR_INVALID_ARG, "get_solution: NULL handle");
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "get_solution: no solution yet");
+    if (!y && !lam && !omega_d && !zL && !zU) {   // first-stage values only: two small copies
+        std::string err;
+        nmpc_status rc = nmpc::device_get_first_stage(p->impl, u1, x1, err);
+        return rc == NMPC_OK ? rc : fail(rc, err);
+    }
     return guarded([&]() -> nmpc_status {
         const auto& st = p->impl.st;
         const int ml = 2 * st.m_c + st.m_d;
@@ -346,6 +380,67 @@ nmpc_status nmpc_assemble(nmpc_problem* p, double mu, double* k_vals, double* rh
     std::string err;
     nmpc_status rc = nmpc::device_assemble(p->impl, mu, k_vals, rhs, err);
     return rc == NMPC_OK ? rc : fail(rc, err);
+}
+
+nmpc_status nmpc_batch_create(nmpc_problem* const* problems, int32_t count, nmpc_batch** out) {
+    if (!problems || !out || count < 1) return fail(NMPC_ERR_INVALID_ARG, "batch_create: NULL argument or count < 1");
+    *out = nullptr;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!problems[i]) return fail(NMPC_ERR_INVALID_ARG, "batch_create: NULL problem");
+        for (int32_t j = 0; j < i; ++j)
+            if (problems[j] == problems[i]) return fail(NMPC_ERR_INVALID_ARG, "batch_create: a problem appears twice");
+    }
+    std::vector<Problem*> ps;
+    for (int32_t i = 0; i < count; ++i) {
+        nmpc_problem* q = problems[i];
+        if (!q->impl.analyzed) return fail(NMPC_ERR_BAD_ORDER, "batch_create: every problem must be analyzed");
+        if (!q->impl.dev) return fail(NMPC_ERR_NO_DEVICE, "batch_create: no HIP device");
+        ps.push_back(&q->impl);
+    }
+    return guarded([&]() -> nmpc_status {
+        auto* b = new nmpc_batch();
+        std::string err;
+        nmpc_status rc = nmpc::batch_create(ps, b->impl, err);
+        if (rc != NMPC_OK) {
+            delete b;
+            return fail(rc, err);
+        }
+        b->members.assign(problems, problems + count);
+        *out = b;
+        return NMPC_OK;
+    });
+}
+
+nmpc_status nmpc_batch_solve(nmpc_batch* b, int32_t warm, const nmpc_options* opts, nmpc_result* per_instance) {
+    if (!b || !b->impl) return fail(NMPC_ERR_INVALID_ARG, "batch_solve: NULL batch");
+    if (warm)
+        for (auto* q : b->members)
+            if (!q->impl.have_iterate)
+                return fail(NMPC_ERR_BAD_ORDER, "batch_solve: warm start without a previous iterate");
+    nmpc_options o;
+    if (!resolve_options(opts, o)) return fail(NMPC_ERR_INVALID_ARG, "batch_solve: invalid options");
+    return guarded([&]() -> nmpc_status {
+        std::vector<nmpc_result> r(b->members.size());
+        std::string err;
+        auto t0 = std::chrono::steady_clock::now();
+        nmpc_status rc = nmpc::batch_solve(*b->impl, warm, o, r.data(), err);
+        auto t1 = std::chrono::steady_clock::now();
+        if (rc < 0) return fail(rc, err);
+        const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        for (size_t i = 0; i < r.size(); ++i) {
+            r[i].ms_total = ms;
+            b->members[i]->impl.have_iterate = true;
+            nmpc::device_invalidate_adjoint(b->members[i]->impl);
+        }
+        if (per_instance) std::copy(r.begin(), r.end(), per_instance);
+        return rc;
+    });
+}
+
+void nmpc_batch_destroy(nmpc_batch* b) {
+    if (!b) return;
+    nmpc::batch_free(b->impl);
+    delete b;
 }
 
 }  // extern "C"

@@ -1,23 +1,27 @@
-// Device buffers, IPM vector kernels and the host-side driver of Algorithm 2.
+// Device buffers of a problem, batches of problems, and the host side of
+// Algorithm 2.
 //
 // Every step of an iteration runs on the GPU: model evaluation, residuals and
 // optimality errors (eqs. 11, 27-28), condensed assembly (eqs. 14, 17), the
 // supernodal factorization with inertia correction (eqs. 12-13, 20-21), the
 // forward/back solves (eqs. 22-25), recovery of the other directions, the
-// fraction-to-boundary rule and the line search (eq. 26).  The host reads a
-// handful of reduced scalars per phase to take the same decisions as the
-// method's description: barrier update, regularization, step acceptance.
+// fraction-to-boundary rule and the line search (eq. 26).  The scalar
+// decisions (barrier update, regularization, step acceptance) are taken on the
+// device too, per instance, by the decision kernels.  The host enqueues passes:
+// in one pass every running instance moves through one Newton iteration (or
+// one more factorization attempt, or one more trial point, when its last one
+// failed), so instances of a batch never wait for each other.  A pass needs no
+// host decision, so it is captured once as a HIP graph and replayed; after
+// each pass the host reads one integer, the number of instances still running.
 //
-// Reductions are two-level and deterministic: each block reduces its slice in
-// a fixed tree order into a partial buffer, then one block reduces the
-// partials in block order.
+// A problem's own solve is a batch of one; a user batch groups the device state
+// of several analyzed problems and runs the same passes over all of them, so
+// an instance's arithmetic is the same alone or batched.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstring>
-#include <limits>
 #include <string>
 #include <vector>
 
@@ -26,515 +30,387 @@
 
 namespace nmpc {
 
+static_assert(kFilterCapMax == kFilterCapacity, "filter capacity of the options check and of the device storage");
+
 #define HIP_TRY(call)                                                                 \
     do {                                                                              \
         hipError_t e_ = (call);                                                       \
         if (e_ != hipSuccess) {                                                       \
             err = std::string(#call) + ": " + hipGetErrorString(e_);                  \
-            return NMPC_ERR_HIP;                                                      \
+            return e_ == hipErrorOutOfMemory ? NMPC_ERR_OOM : NMPC_ERR_HIP;           \
         }                                                                             \
     } while (0)
 
-namespace {
-
-constexpr int kMaxQ = 12;
-enum Op : int { kSum = 0, kMax = 1, kMin = 2 };
-
-__device__ inline double combine(int op, double a, double b) {
-    return op == kSum ? a + b : (op == kMax ? fmax(a, b) : fmin(a, b));
-}
-
-struct Ops {
-    int q;
-    int op[kMaxQ];
+// Launch schedule of one instance: a list of steps.  A group step is a list of
+// groups (supernodes walked in order by one workgroup, in sched_nodes order);
+// a large-supernode step is a task list for one of the kernels of the
+// multi-workgroup path (BigKind).
+enum StepKind : int { kStepGroupFactor = 100, kStepGroupFwd = 101, kStepGroupBwd = 102 };
+struct LocalGroup {
+    int begin, end;
+    size_t lds_factor, lds_solve;   // shared-memory bytes the group needs
+};
+struct Step {
+    int kind = 0;
+    std::vector<LocalGroup> groups;
+    std::vector<int4> tasks;        // x (the instance) is filled in by the batch
+    size_t lds = 0;                 // shared memory of a large-supernode solve kernel
 };
 
-constexpr int kWaves = kBlock / 64;
-
-// Butterfly reduction across the 64 lanes of a wave (fixed pattern).
-__device__ inline double wave_reduce(double v, int op) {
-    for (int off = 32; off > 0; off >>= 1) v = combine(op, v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Reduce every quantity over the block (waves, then the per-wave results in
-// wave order) and let thread q write quantity q's block result to part.
-__device__ void store_partials(const double* v, const Ops& ops, double* part, int nblk, double* sh) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = 0; q < ops.q; ++q) {
-        const double r = wave_reduce(v[q], ops.op[q]);
-        if (lane == 0) sh[q * kWaves + wv] = r;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < ops.q) {
-        const int q = threadIdx.x;
-        double acc = sh[q * kWaves];
-        for (int w = 1; w < kWaves; ++w) acc = combine(ops.op[q], acc, sh[q * kWaves + w]);
-        part[(int64_t)q * nblk + blockIdx.x] = acc;
-    }
-}
-
-__device__ inline double ident(int op) {
-    return op == kSum ? 0.0 : (op == kMax ? -INFINITY : INFINITY);
-}
-
-__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ part, int nblk, Ops ops,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[kMaxQ * kWaves];
-    double v[kMaxQ];
-    for (int q = 0; q < ops.q; ++q) {
-        double acc = ident(ops.op[q]);
-        for (int b = threadIdx.x; b < nblk; b += kBlock) acc = combine(ops.op[q], acc, part[(int64_t)q * nblk + b]);
-        v[q] = acc;
-    }
-    store_partials(v, ops, out, 1, sh);
-}
-
-struct Vec {
-    int n, mc, md, ml;
-    double gamma;
-    const double* lb;
-    const double* ub;
-};
-
-__device__ inline bool hasL(const Vec& V, int j) { return V.lb[j] > -INFINITY; }
-__device__ inline bool hasU(const Vec& V, int j) { return V.ub[j] < INFINITY; }
-
-__device__ inline double lifted_g(const Vec& V, const double* c, const double* d, int r) {
-    if (r < V.mc) return c[r] - V.gamma;
-    if (r < 2 * V.mc) return -c[r - V.mc] - V.gamma;
-    return d[r - 2 * V.mc];
-}
-
-// ---- phase A: optimality-error ingredients at the current iterate --------------
-// q: 0 f(sum) 1 dual(max) 2 |omega-beta|(max) 3 |g+s|(max) 4 sb max 5 sb min
-//    6 gL zL max 7 gL zL min 8 gU zU max 9 gU zU min 10 non-finite count(sum)
-__global__ void __launch_bounds__(kBlock)
-k_phaseA(Vec V, const double* __restrict__ y, const double* __restrict__ s, const double* __restrict__ om,
-         const double* __restrict__ be, const double* __restrict__ zl, const double* __restrict__ zu,
-         const double* __restrict__ grad, const double* __restrict__ fterm, const double* __restrict__ c,
-         const double* __restrict__ d, const double* __restrict__ jv, const int32_t* __restrict__ jt_ptr,
-         const int32_t* __restrict__ jt_slot, const int32_t* __restrict__ jt_row, double* __restrict__ gtw,
-         double* __restrict__ part, Ops ops) {
-    __shared__ double sh[kMaxQ * kWaves];
-    double q[11] = {0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, 0.0};
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < V.n) {
-        const int j = t;
-        double acc = 0.0;
-        for (int e = jt_ptr[j]; e < jt_ptr[j + 1]; ++e) {
-            const int r = jt_row[e];
-            const double lam = r < V.mc ? om[r] - om[V.mc + r] : om[V.mc + r];
-            acc += jv[jt_slot[e]] * lam;
-        }
-        gtw[j] = acc;
-        const bool hl = hasL(V, j), hu = hasU(V, j);
-        const double dual = grad[j] + acc - (hl ? zl[j] : 0.0) + (hu ? zu[j] : 0.0);
-        q[0] = fterm[j];
-        q[1] = fabs(dual);
-        if (hl) {
-            const double p = (y[j] - V.lb[j]) * zl[j];
-            q[6] = p;
-            q[7] = p;
-        }
-        if (hu) {
-            const double p = (V.ub[j] - y[j]) * zu[j];
-            q[8] = p;
-            q[9] = p;
-        }
-        if (!isfinite(fterm[j]) || !isfinite(grad[j])) q[10] = 1.0;
-    } else if (t < V.n + V.ml) {
-        const int r = t - V.n;
-        const double g = lifted_g(V, c, d, r);
-        q[2] = fabs(om[r] - be[r]);
-        q[3] = fabs(g + s[r]);
-        q[4] = s[r] * be[r];
-        q[5] = q[4];
-        if (!isfinite(g)) q[10] = 1.0;
-    }
-    store_partials(q, ops, part, gridDim.x, sh);
-}
-
-// ---- phase B: condensed system ingredients --------------------------------------
-// per original row r: lifted Q, r2, r4 and their combinations
-//   c row r:  qeff = Q+ + Q-,  vcomb = (Q+ r4+ - r2+) - (Q- r4- - r2-)
-//   d row r:  qeff = Q,        vcomb = Q r4 - r2
-__global__ void __launch_bounds__(kBlock)
-k_rows_prep(Vec V, double mu, const double* __restrict__ s, const double* __restrict__ om,
-            const double* __restrict__ be, const double* __restrict__ c, const double* __restrict__ d,
-            double* __restrict__ Q, double* __restrict__ r2, double* __restrict__ r4, double* __restrict__ qeff,
-            double* __restrict__ vcomb) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = V.mc + V.md;
-    if (r >= m) return;
-    if (r < V.mc) {
-        const int a = r, b = V.mc + r;
-        const double Qa = be[a] / s[a], Qb = be[b] / s[b];
-        const double r2a = om[a] - mu / s[a], r2b = om[b] - mu / s[b];
-        const double r4a = lifted_g(V, c, d, a) + s[a], r4b = lifted_g(V, c, d, b) + s[b];
-        Q[a] = Qa; Q[b] = Qb;
-        r2[a] = r2a; r2[b] = r2b;
-        r4[a] = r4a; r4[b] = r4b;
-        qeff[r] = Qa + Qb;
-        vcomb[r] = (Qa * r4a - r2a) - (Qb * r4b - r2b);
-    } else {
-        const int a = V.mc + r;
-        const double Qa = be[a] / s[a];
-        const double r2a = om[a] - mu / s[a];
-        const double r4a = lifted_g(V, c, d, a) + s[a];
-        Q[a] = Qa; r2[a] = r2a; r4[a] = r4a;
-        qeff[r] = Qa;
-        vcomb[r] = Qa * r4a - r2a;
-    }
-}
-
-// per variable: Sigma, and rhs = -r1 - G^T (Q r4 - r2), r1 = grad + G^T omega - mu/gL + mu/gU
-__global__ void __launch_bounds__(kBlock)
-k_var_prep(Vec V, double mu, const double* __restrict__ y, const double* __restrict__ zl,
-           const double* __restrict__ zu, const double* __restrict__ grad, const double* __restrict__ gtw,
-           const double* __restrict__ jv, const int32_t* __restrict__ jt_ptr, const int32_t* __restrict__ jt_slot,
-           const int32_t* __restrict__ jt_row, const double* __restrict__ vcomb, double* __restrict__ sig,
-           double* __restrict__ rhs) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= V.n) return;
-    const bool hl = hasL(V, j), hu = hasU(V, j);
-    const double gl = hl ? y[j] - V.lb[j] : 1.0;
-    const double gu = hu ? V.ub[j] - y[j] : 1.0;
-    sig[j] = (hl ? zl[j] / gl : 0.0) + (hu ? zu[j] / gu : 0.0);
-    const double r1 = grad[j] + gtw[j] - (hl ? mu / gl : 0.0) + (hu ? mu / gu : 0.0);
-    double acc = 0.0;
-    for (int e = jt_ptr[j]; e < jt_ptr[j + 1]; ++e) acc += jv[jt_slot[e]] * vcomb[jt_row[e]];
-    rhs[j] = -r1 - acc;
-}
-
-// K slot values: W + Sigma + J^T diag(qeff) J, gathered per slot (no atomics)
-__global__ void __launch_bounds__(kBlock)
-k_assemble(int64_t nk, const int32_t* __restrict__ wslot, const int32_t* __restrict__ kdiag,
-           const int32_t* __restrict__ kc_ptr, const int32_t* __restrict__ kc_a, const int32_t* __restrict__ kc_b,
-           const int32_t* __restrict__ kc_r, const double* __restrict__ wv, const double* __restrict__ sig,
-           const double* __restrict__ jv, const double* __restrict__ qeff, double* __restrict__ kv) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nk) return;
-    const int ws = wslot[t], dg = kdiag[t];
-    double v = ws >= 0 ? wv[ws] : 0.0;
-    if (dg >= 0) v += sig[dg];
-    for (int e = kc_ptr[t]; e < kc_ptr[t + 1]; ++e) v += jv[kc_a[e]] * qeff[kc_r[e]] * jv[kc_b[e]];
-    kv[t] = v;
-}
-
-__device__ inline double ftb(double v, double dv, double tau) { return dv < 0.0 ? (-tau * v) / dv : INFINITY; }
-
-// ---- phase E: remaining directions and step / merit ingredients ------------------
-// q: 0 alpha_primal(min) 1 alpha_dual(min) 2 |omega+domega|(max) 3 grad.dy 4 sum ds/s
-//    5 sum dy/gL 6 sum dy/gU 7 |r4|_1 8 sum ln s 9 sum ln gL 10 sum ln gU
-__global__ void __launch_bounds__(kBlock)
-k_phaseE(Vec V, double mu, double tau, const double* __restrict__ y, const double* __restrict__ s,
-         const double* __restrict__ om, const double* __restrict__ be, const double* __restrict__ zl,
-         const double* __restrict__ zu, const double* __restrict__ grad, const double* __restrict__ dy,
-         const double* __restrict__ Q, const double* __restrict__ r2, const double* __restrict__ r4,
-         const double* __restrict__ jv, const int32_t* __restrict__ jptr, const int32_t* __restrict__ jcol,
-         double* __restrict__ ds, double* __restrict__ dom, double* __restrict__ dbe, double* __restrict__ dzl,
-         double* __restrict__ dzu, double* __restrict__ part, Ops ops) {
-    __shared__ double sh[kMaxQ * kWaves];
-    double q[11] = {INFINITY, INFINITY, -INFINITY, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = V.mc + V.md;
-    if (t < m) {
-        const int r = t;
-        double jdy = 0.0;
-        for (int p = jptr[r]; p < jptr[r + 1]; ++p) jdy += jv[p] * dy[jcol[p]];
-        const int nl = r < V.mc ? 2 : 1;
-        for (int h = 0; h < nl; ++h) {
-            const int l = r < V.mc ? (h == 0 ? r : V.mc + r) : V.mc + r;
-            const double sgn = (r < V.mc && h == 1) ? -1.0 : 1.0;
-            const double dsl = -r4[l] - sgn * jdy;
-            const double doml = -r2[l] - Q[l] * dsl;
-            const double dbel = mu / s[l] - be[l] - Q[l] * dsl;
-            ds[l] = dsl;
-            dom[l] = doml;
-            dbe[l] = dbel;
-            q[0] = fmin(q[0], ftb(s[l], dsl, tau));
-            q[1] = fmin(q[1], ftb(be[l], dbel, tau));
-            q[2] = fmax(q[2], fabs(om[l] + doml));
-            q[4] += dsl / s[l];
-            q[7] += fabs(r4[l]);
-            q[8] += log(s[l]);
-        }
-    } else if (t < m + V.n) {
-        const int j = t - m;
-        const bool hl = hasL(V, j), hu = hasU(V, j);
-        const double gl = hl ? y[j] - V.lb[j] : 1.0;
-        const double gu = hu ? V.ub[j] - y[j] : 1.0;
-        const double dyj = dy[j];
-        const double dzlj = hl ? mu / gl - zl[j] - (zl[j] / gl) * dyj : 0.0;
-        const double dzuj = hu ? mu / gu - zu[j] + (zu[j] / gu) * dyj : 0.0;
-        dzl[j] = dzlj;
-        dzu[j] = dzuj;
-        q[3] = grad[j] * dyj;
-        if (hl) {
-            q[0] = fmin(q[0], ftb(gl, dyj, tau));
-            q[1] = fmin(q[1], ftb(zl[j], dzlj, tau));
-            q[5] = dyj / gl;
-            q[9] = log(gl);
-        }
-        if (hu) {
-            q[0] = fmin(q[0], ftb(gu, -dyj, tau));
-            q[1] = fmin(q[1], ftb(zu[j], dzuj, tau));
-            q[6] = dyj / gu;
-            q[10] = log(gu);
-        }
-    }
-    store_partials(q, ops, part, gridDim.x, sh);
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_trial_point(int n, int ml, double alpha, const double* __restrict__ y, const double* __restrict__ dy,
-              const double* __restrict__ s, const double* __restrict__ ds, double* __restrict__ yt,
-              double* __restrict__ st) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) yt[t] = y[t] + alpha * dy[t];
-    if (t < ml) st[t] = s[t] + alpha * ds[t];
-}
-
-// merit ingredients at the trial point
-// q: 0 f(sum) 1 sum ln s 2 sum ln gL 3 sum ln gU 4 |g+s|_1 5 non-finite count
-__global__ void __launch_bounds__(kBlock)
-k_phaseT(Vec V, const double* __restrict__ yt, const double* __restrict__ st, const double* __restrict__ fterm,
-         const double* __restrict__ c, const double* __restrict__ d, double* __restrict__ part, Ops ops) {
-    __shared__ double sh[kMaxQ * kWaves];
-    double q[6] = {0, 0, 0, 0, 0, 0};
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < V.n) {
-        const int j = t;
-        q[0] = fterm[j];
-        if (hasL(V, j)) q[2] = log(yt[j] - V.lb[j]);
-        if (hasU(V, j)) q[3] = log(V.ub[j] - yt[j]);
-        if (!isfinite(fterm[j])) q[5] = 1.0;
-    } else if (t < V.n + V.ml) {
-        const int r = t - V.n;
-        const double g = lifted_g(V, c, d, r);
-        q[1] = log(st[r]);
-        q[4] = fabs(g + st[r]);
-        if (!isfinite(g)) q[5] = 1.0;
-    }
-    store_partials(q, ops, part, gridDim.x, sh);
-}
-
-// z <- z + alpha dz, then keep beta, zL, zU within kappa_sigma of mu / (slack or gap)
-__global__ void __launch_bounds__(kBlock)
-k_update(Vec V, double alpha, double mu, double ks, double* __restrict__ y, double* __restrict__ s,
-         double* __restrict__ om, double* __restrict__ be, double* __restrict__ zl, double* __restrict__ zu,
-         const double* __restrict__ dy, const double* __restrict__ ds, const double* __restrict__ dom,
-         const double* __restrict__ dbe, const double* __restrict__ dzl, const double* __restrict__ dzu) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < V.n) {
-        const int j = t;
-        const double yn = y[j] + alpha * dy[j];
-        y[j] = yn;
-        if (hasL(V, j)) {
-            const double gl = yn - V.lb[j];
-            const double z = zl[j] + alpha * dzl[j];
-            zl[j] = fmin(fmax(z, mu / (ks * gl)), ks * mu / gl);
-        } else {
-            zl[j] = 0.0;
-        }
-        if (hasU(V, j)) {
-            const double gu = V.ub[j] - yn;
-            const double z = zu[j] + alpha * dzu[j];
-            zu[j] = fmin(fmax(z, mu / (ks * gu)), ks * mu / gu);
-        } else {
-            zu[j] = 0.0;
-        }
-    }
-    if (t < V.ml) {
-        const int r = t;
-        const double sn = s[r] + alpha * ds[r];
-        s[r] = sn;
-        om[r] = om[r] + alpha * dom[r];
-        const double b = be[r] + alpha * dbe[r];
-        be[r] = fmin(fmax(b, mu / (ks * sn)), ks * mu / sn);
-    }
-}
-
-// cold start: push y into the bounds' interior (bound_push of magnitude and range)
-__global__ void __launch_bounds__(kBlock)
-k_push_bounds(Vec V, double bp, double* __restrict__ y) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= V.n) return;
-    const bool hl = hasL(V, j), hu = hasU(V, j);
-    double pl = hl ? bp * fmax(1.0, fabs(V.lb[j])) : 0.0;
-    double pu = hu ? bp * fmax(1.0, fabs(V.ub[j])) : 0.0;
-    if (hl && hu) {
-        const double rng = V.ub[j] - V.lb[j];
-        pl = fmin(pl, 0.5 * bp * rng);
-        pu = fmin(pu, 0.5 * bp * rng);
-    }
-    double v = y[j];
-    if (hl) v = fmax(v, V.lb[j] + pl);
-    if (hu) v = fmin(v, V.ub[j] - pu);
-    y[j] = v;
-}
-
-// cold start: slacks, multipliers centred at mu0
-__global__ void __launch_bounds__(kBlock)
-k_cold_duals(Vec V, double mu0, double sp, const double* __restrict__ c, const double* __restrict__ d,
-             const double* __restrict__ y, double* __restrict__ s, double* __restrict__ om, double* __restrict__ be,
-             double* __restrict__ zl, double* __restrict__ zu) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < V.ml) {
-        const double g = lifted_g(V, c, d, t);
-        const double sv = fmax(-g, sp * fmax(1.0, fabs(g)));
-        s[t] = sv;
-        om[t] = 0.0;
-        be[t] = mu0 / sv;
-    }
-    if (t < V.n) {
-        zl[t] = hasL(V, t) ? mu0 / (y[t] - V.lb[t]) : 0.0;
-        zu[t] = hasU(V, t) ? mu0 / (V.ub[t] - y[t]) : 0.0;
-    }
-}
-
-__global__ void k_clear_flag(int* __restrict__ flag) { *flag = 0; }
-
-// ---- sensitivities ------------------------------------------------------------------
-constexpr int kMaxSeed = 16;
-struct Seed {
-    double u[kMaxSeed];
-};
-
-// rhs = seed_obj * grad f + S_u^T seed_u (first-stage controls at positions iu0 .. iu0 + nu)
-__global__ void __launch_bounds__(kBlock)
-k_adj_seed(int n, int iu0, int nu, const double* __restrict__ grad, double seed_obj, Seed seed,
-           double* __restrict__ rhs) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    double v = seed_obj * grad[j];
-    if (j >= iu0 && j < iu0 + nu) v += seed.u[j - iu0];
-    rhs[j] = v;
-}
-
-// Parameter contractions of w = K^{-1} seed for the distillation family (one block):
-//   x0:       (Q+ + Q-) (J w) on the stage-1 rows
-//   zF_k:     dt F (Q+ + Q-) (J w) on the feed-tray row of stage k
-//   xD*, xB*: 2 sum_k w(top|bottom state) - 2 seed_obj sum_k (state - setpoint)
-//   u_prev:   2 rho w(u_1) - 2 rho seed_obj (u_1 - u_prev)
-// out = [x0 (nx) | setpoint (2) | traj (H) | u_prev (2)]
-__global__ void __launch_bounds__(kBlock)
-k_adj_gather_distill(DistillDims D, DistillConst C, const double* __restrict__ y, const double* __restrict__ uprev,
-                     const double* __restrict__ w, const double* __restrict__ jv, const int32_t* __restrict__ jptr,
-                     const int32_t* __restrict__ jcol, const double* __restrict__ qeff, double seed_obj,
-                     double* __restrict__ out) {
-    __shared__ double sh[kMaxQ * kWaves];
-    const int tid = threadIdx.x;
-    for (int t = tid; t < D.nx + D.H; t += kBlock) {
-        const int r = t < D.nx ? t : (t - D.nx) * D.nx + D.fd;
-        double jw = 0.0;
-        for (int q = jptr[r]; q < jptr[r + 1]; ++q) jw += jv[q] * w[jcol[q]];
-        const double v = qeff[r] * jw;
-        if (t < D.nx) out[t] = v;
-        else out[D.nx + 2 + (t - D.nx)] = C.dt * C.F * v;
-    }
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = tid; k < D.H; k += kBlock) {
-        const int top = k * D.ns, bot = k * D.ns + D.nx - 1;
-        a[0] += w[top];
-        a[1] += y[top] - C.xD;
-        a[2] += w[bot];
-        a[3] += y[bot] - C.xB;
-    }
-    Ops ops{4, {kSum, kSum, kSum, kSum}};
-    store_partials(a, ops, sh + 4 * kWaves, 1, sh);   // block sums land in sh[4 kWaves .. 4 kWaves + 4)
-    __syncthreads();
-    if (tid == 0) {
-        const double* r = sh + 4 * kWaves;
-        out[D.nx] = 2.0 * r[0] - 2.0 * seed_obj * r[1];
-        out[D.nx + 1] = 2.0 * r[2] - 2.0 * seed_obj * r[3];
-    }
-    if (tid < 2) {
-        const int iu = D.nx + tid;
-        out[D.nx + 2 + D.H + tid] = 2.0 * C.rho * w[iu] - 2.0 * C.rho * seed_obj * (y[iu] - uprev[tid]);
-    }
-}
-
-inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
-
-}  // namespace
-
-// ==================================================================================
 struct Device {
+    const Problem* owner = nullptr;
     hipStream_t stream = nullptr;
-    int n = 0, mc = 0, md = 0, ml = 0, m = 0;
-    int64_t nnzj = 0, nnzw = 0, nnzk = 0;
-    DistillDims dd{};
-    DistillConst dc{};
-    Vec vec{};
-    // structure
-    int32_t *jptr = nullptr, *jcol = nullptr, *jt_ptr = nullptr, *jt_slot = nullptr, *jt_row = nullptr;
-    double *lb = nullptr, *ub = nullptr;
-    // symbolic
-    int32_t *perm = nullptr, *sn_ptr = nullptr, *rows = nullptr, *child_ptr = nullptr, *child_list = nullptr;
-    int32_t *level_list = nullptr, *rel = nullptr, *k_ptr = nullptr, *k_fpos = nullptr;
-    int64_t *rows_ptr = nullptr, *l_off = nullptr, *u_off = nullptr, *uv_off = nullptr, *rel_off = nullptr;
-    int32_t *k_wslot = nullptr, *k_diag = nullptr, *kc_ptr = nullptr, *kc_a = nullptr, *kc_b = nullptr,
-            *kc_r = nullptr;
-    // launch schedule of the supernodal tree: forward (leaves to root) and backward
-    struct Launch {
-        int gptr_off, groups;
-        size_t lds_factor, lds_solve, lds_vec;
-    };
-    std::vector<Launch> fwd_launches, bwd_launches;
-    int32_t *sched_nodes = nullptr, *sched_gptr = nullptr;
-    bool front_in_lds = true;
-    double* gscratch = nullptr;
-    int64_t gstride = 0;
-    SnView S{};
-    // parameters
-    double *x0 = nullptr, *zF = nullptr, *uprev = nullptr;
-    // iterate and work
-    double *y = nullptr, *s = nullptr, *om = nullptr, *be = nullptr, *zl = nullptr, *zu = nullptr;
-    double *c = nullptr, *d = nullptr, *jv = nullptr, *wv = nullptr, *grad = nullptr, *fterm = nullptr;
-    double *gtw = nullptr, *sig = nullptr, *rhs = nullptr, *dy = nullptr, *xp = nullptr;
-    double *Q = nullptr, *r2 = nullptr, *r4 = nullptr, *qeff = nullptr, *vcomb = nullptr;
-    double *ds = nullptr, *dom = nullptr, *dbe = nullptr, *dzl = nullptr, *dzu = nullptr;
-    double *yt = nullptr, *st = nullptr;
-    double *kv = nullptr, *L = nullptr, *U = nullptr, *uvec = nullptr;
-    int* fail = nullptr;
-    double *part = nullptr, *scal = nullptr;
-    double* hscal = nullptr;   // pinned
-    int* hfail = nullptr;      // pinned
-    int part_blocks = 0;
-    int max_width = 0;
+    InstPtrs hI{};                 // host copy of the instance descriptor
+    std::vector<Step> fac, fwd, bwd;
+    int fac_launches = 0;          // kernel launches of one factorization
+    int64_t stored_l = 0, nnzj = 0, nnzw = 0;
     std::vector<void*> allocs;
-    hipEvent_t ev[10] = {};
+    Batch* self = nullptr;         // batch of one over this problem
     // sensitivities: factor of K at the returned iterate, kept until it changes
     bool adj_ready = false;
     double adj_eta = 0.0;
-    double *adj_rhs = nullptr, *adj_w = nullptr, *adj_out = nullptr;   // phase timers: eval, assemble, factor, solve, line search (start, end)
+    double gamma_last = 1e-9;
+};
+
+// Emitted kernel launch of a batch schedule: a group launch (groups[off ..
+// off + count)) or a large-supernode step (tasks[off .. off + count)).
+struct BLaunch {
+    int kind, off, count;
+    bool lds;
+    size_t bytes;
+};
+
+struct Batch {
+    std::vector<Device*> members;
+    int ninst = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    InstPtrs* dI = nullptr;
+    Ctl* ctl = nullptr;
+    IpmSpaces spaces{};
+    Group* groups = nullptr;
+    int4* tasks = nullptr;
+    std::vector<BLaunch> fac, fwd, bwd;
+    bool has_distill = false, has_plate = false;
+    int* running = nullptr;        // device
+    int* hrunning = nullptr;       // pinned
+    Ctl* hctl = nullptr;           // pinned
+    hipEvent_t ev[6] = {};
+    hipGraph_t graph[2] = {nullptr, nullptr};        // untimed, timed
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    DevOpts graph_opts[2] = {};                       // options the graphs were captured with
+    bool graph_failed[2] = {false, false};
+    std::vector<void*> allocs;
 };
 
 namespace {
 
+constexpr int kMediumFront = 256;   // largest front one workgroup factors in a global buffer
+
+inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
 template <class T>
-hipError_t dalloc(Device& D, T*& p, size_t count) {
+hipError_t dalloc(std::vector<void*>& allocs, T*& p, size_t count) {
     void* v = nullptr;
     hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(T));
     if (e == hipSuccess) {
-        D.allocs.push_back(v);
+        allocs.push_back(v);
         p = static_cast<T*>(v);
     }
     return e;
 }
 
 template <class T>
-hipError_t upload(Device& D, T*& p, const std::vector<T>& h) {
-    hipError_t e = dalloc(D, p, h.size());
+hipError_t upload(std::vector<void*>& allocs, T*& p, const std::vector<T>& h) {
+    hipError_t e = dalloc(allocs, p, h.size());
     if (e != hipSuccess) return e;
     if (!h.empty()) e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
     return e;
 }
 
+template <class T>
+hipError_t upload_c(std::vector<void*>& allocs, const T*& p, const std::vector<T>& h) {
+    T* q = nullptr;
+    hipError_t e = upload(allocs, q, h);
+    p = q;
+    return e;
+}
+
+DevOpts dev_opts(const nmpc_options& o) {
+    DevOpts d;
+    std::memset(&d, 0, sizeof(d));   // padding too: the struct is compared bytewise
+    d.tol = o.tol;
+    d.mu_min = o.mu_min;
+    d.kappa_eps = o.kappa_eps;
+    d.kappa_mu = o.kappa_mu;
+    d.theta_mu = o.theta_mu;
+    d.tau_min = o.tau_min;
+    d.armijo = o.armijo;
+    d.kappa_sigma = o.kappa_sigma;
+    d.eta_first = o.eta_first;
+    d.eta_min = o.eta_min;
+    d.eta_max = o.eta_max;
+    d.kp_first = o.kp_first;
+    d.kp = o.kp;
+    d.km = o.km;
+    d.g_theta = o.filter_gamma_theta;
+    d.g_phi = o.filter_gamma_phi;
+    d.s_theta = o.filter_s_theta;
+    d.s_phi = o.filter_s_phi;
+    d.delta = o.filter_delta;
+    d.amin_frac = o.alpha_min_frac;
+    d.theta_max_fact = o.theta_max_fact;
+    d.theta_min_fact = o.theta_min_fact;
+    d.soc_kappa = o.soc_kappa;
+    d.ls_max = o.ls_max;
+    d.max_iter = o.max_iter;
+    d.filter_cap = o.filter_cap;
+    d.soc_max = o.soc_max;
+    return d;
+}
+
+size_t lds_limit_bytes() {
+    int dev = 0, lds_max = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return (size_t)lds_max;
+}
+
+void batch_release(Batch* B) {
+    if (!B) return;
+    for (int k = 0; k < 2; ++k) {
+        if (B->exec[k]) (void)hipGraphExecDestroy(B->exec[k]);
+        if (B->graph[k]) (void)hipGraphDestroy(B->graph[k]);
+    }
+    for (void* a : B->allocs) (void)hipFree(a);
+    if (B->hrunning) (void)hipHostFree(B->hrunning);
+    if (B->hctl) (void)hipHostFree(B->hctl);
+    for (auto e : B->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+}
+
+// Build the device tables of a batch over the given instances.
+nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream, Batch*& out, std::string& err) {
+    Batch* B = new Batch();
+    B->members = members;
+    B->ninst = (int)members.size();
+    auto bail = [&](nmpc_status rc) {
+        batch_release(B);
+        out = nullptr;
+        return rc;
+    };
+#define BTRY(call)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+            return bail(e_ == hipErrorOutOfMemory ? NMPC_ERR_OOM : NMPC_ERR_HIP);      \
+        }                                                                              \
+    } while (0)
+    if (stream) {
+        B->stream = stream;
+    } else {
+        BTRY(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
+        B->own_stream = true;
+    }
+    const int ni = B->ninst;
+    BTRY(dalloc(B->allocs, B->ctl, ni));
+    std::vector<InstPtrs> hI(ni);
+    for (int i = 0; i < ni; ++i) {
+        hI[i] = members[i]->hI;
+        hI[i].ctl = B->ctl + i;
+        if (hI[i].family == NMPC_FAMILY_DISTILLATION) B->has_distill = true;
+        if (hI[i].family == NMPC_FAMILY_HEATED_PLATE) B->has_plate = true;
+    }
+    BTRY(upload(B->allocs, B->dI, hI));
+    // index spaces
+    for (int k = 0; k < kNumSpaces; ++k) {
+        std::vector<int32_t> binst, bfirst(ni + 1, 0);
+        for (int i = 0; i < ni; ++i) {
+            bfirst[i] = (int32_t)binst.size();
+            const int nb = std::max(1, nblocks(space_size(hI[i], k)));
+            for (int b = 0; b < nb; ++b) binst.push_back(i);
+        }
+        bfirst[ni] = (int32_t)binst.size();
+        Space& sp = B->spaces.sp[k];
+        sp.blocks = (int)binst.size();
+        BTRY(upload_c(B->allocs, sp.binst, binst));
+        BTRY(upload_c(B->allocs, sp.bfirst, bfirst));
+    }
+    // schedules: step j of the batch holds step j of every instance (the
+    // forward lists aligned at the leaves, the backward lists at the roots), one
+    // launch per kind; factor groups split by whether their fronts fit in shared
+    // memory
+    const size_t lim = lds_limit_bytes();
+    std::vector<Group> gl;
+    std::vector<int4> tl;
+    auto merge = [&](std::vector<BLaunch>& dst, std::vector<Step> Device::*list) {
+        size_t len = 0;
+        for (auto* D : members) len = std::max(len, (D->*list).size());
+        for (size_t j = 0; j < len; ++j) {
+            std::vector<Group> g_lds, g_glob, g_sol;
+            size_t b_lds = 0, b_sol = 0;
+            int gkind = 0;
+            std::vector<std::vector<int4>> by_kind(16);
+            std::vector<size_t> kind_lds(16, 0);
+            for (int i = 0; i < ni; ++i) {
+                const auto& L = members[i]->*list;
+                if (j >= L.size()) continue;
+                const Step& st = L[j];
+                if (st.kind >= kStepGroupFactor) {
+                    gkind = st.kind;
+                    int slot = 0;
+                    for (const auto& g : st.groups) {
+                        if (st.kind == kStepGroupFactor) {
+                            if (g.lds_factor <= lim) {
+                                g_lds.push_back(Group{i, g.begin, g.end, 0});
+                                b_lds = std::max(b_lds, g.lds_factor);
+                            } else {
+                                g_glob.push_back(Group{i, g.begin, g.end, slot++});
+                            }
+                        } else {
+                            g_sol.push_back(Group{i, g.begin, g.end, 0});
+                            b_sol = std::max(b_sol, g.lds_solve);
+                        }
+                    }
+                } else {
+                    for (int4 t : st.tasks) {
+                        t.x = i;
+                        by_kind[st.kind].push_back(t);
+                    }
+                    kind_lds[st.kind] = std::max(kind_lds[st.kind], st.lds);
+                }
+            }
+            auto emit_groups = [&](const std::vector<Group>& g, int kind, bool lds, size_t bytes) {
+                if (g.empty()) return;
+                dst.push_back(BLaunch{kind, (int)gl.size(), (int)g.size(), lds, bytes});
+                gl.insert(gl.end(), g.begin(), g.end());
+            };
+            emit_groups(g_lds, kStepGroupFactor, true, b_lds);
+            emit_groups(g_glob, kStepGroupFactor, false, 0);
+            emit_groups(g_sol, gkind, true, b_sol);
+            for (int k = 0; k < 16; ++k) {
+                if (by_kind[k].empty()) continue;
+                dst.push_back(BLaunch{k, (int)tl.size(), (int)by_kind[k].size(), false, kind_lds[k]});
+                tl.insert(tl.end(), by_kind[k].begin(), by_kind[k].end());
+            }
+        }
+    };
+    merge(B->fac, &Device::fac);
+    merge(B->fwd, &Device::fwd);
+    merge(B->bwd, &Device::bwd);
+    BTRY(upload(B->allocs, B->groups, gl));
+    BTRY(upload(B->allocs, B->tasks, tl));
+    BTRY(linalg_configure(lim));   // the device maximum, so every batch's launches fit
+    BTRY(big_configure());
+    BTRY(dalloc(B->allocs, B->running, 1));
+    BTRY(hipHostMalloc((void**)&B->hrunning, sizeof(int), hipHostMallocDefault));
+    BTRY(hipHostMalloc((void**)&B->hctl, sizeof(Ctl) * ni, hipHostMallocDefault));
+    for (auto& e : B->ev) BTRY(hipEventCreate(&e));
+#undef BTRY
+    out = B;
+    return NMPC_OK;
+}
+
+// ---- building blocks ------------------------------------------------------------
+void eval(Batch& B, bool full, int src, int pred) {
+    if (B.has_distill) launch_eval_distill(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
+    if (B.has_plate) launch_eval_plate(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
+}
+
+void run_launch(Batch& B, const BLaunch& L, int pred, double eta_force, int which) {
+    switch (L.kind) {
+        case kStepGroupFactor:
+            launch_factor_groups(L.lds, pred, eta_force, B.dI, B.groups + L.off, L.count, L.bytes, B.stream);
+            break;
+        case kStepGroupFwd:
+            launch_fwd_groups(pred, which, B.dI, B.groups + L.off, L.count, L.bytes, B.stream);
+            break;
+        case kStepGroupBwd:
+            launch_bwd_groups(pred, which, B.dI, B.groups + L.off, L.count, L.bytes, B.stream);
+            break;
+        default:
+            launch_big(L.kind, pred, eta_force, which, B.dI, B.tasks + L.off, L.count, L.bytes, B.stream);
+    }
+}
+
+void factor_launches(Batch& B, int pred, double eta_force) {
+    for (const auto& L : B.fac) run_launch(B, L, pred, eta_force, 0);
+}
+
+void solve_launches(Batch& B, int pred, int which) {
+    for (const auto& L : B.fwd) run_launch(B, L, pred, 0.0, which);
+    for (const auto& L : B.bwd) run_launch(B, L, pred, 0.0, which);
+}
+
+// One pass of Algorithm 2 over every running instance.
+void enqueue_pass(Batch& B, const DevOpts& o, bool timed) {
+    hipStream_t st = B.stream;
+    auto mark = [&](int k) {
+        if (timed) (void)hipEventRecord(B.ev[k], st);
+    };
+    mark(0);
+    eval(B, true, kSrcIter, kPhA);
+    launch_phaseA(B.dI, B.spaces, B.ninst, kPhA, o, true, st);
+    mark(1);
+    launch_assemble(B.dI, B.spaces, kPhB, st);
+    mark(2);
+    factor_launches(B, kPredFactor, 0.0);
+    launch_decideF(B.dI, B.ninst, o, st);
+    mark(3);
+    solve_launches(B, kPhS, 0);
+    launch_phaseE(B.dI, B.spaces, B.ninst, o, st);
+    mark(4);
+    launch_trial(B.dI, B.spaces, st);
+    eval(B, false, kSrcTrial, kPhT);
+    launch_phaseT(B.dI, B.spaces, B.ninst, o, st);
+    if (o.soc_max > 0) {
+        launch_soc_prepare(B.dI, B.spaces, st);
+        solve_launches(B, kPhC, 4);
+        launch_soc_step(B.dI, B.spaces, B.ninst, st);
+        eval(B, false, kSrcTrial, kPhC);
+        launch_soc_decide(B.dI, B.spaces, B.ninst, o, st);
+    }
+    launch_update(B.dI, B.spaces, B.ninst, o, B.running, st);
+    mark(5);
+}
+
+// Capture one pass as a graph (once per batch and timing mode).
+hipError_t ensure_graph(Batch& B, const DevOpts& o, bool timed) {
+    const int k = timed ? 1 : 0;
+    if (B.exec[k] && std::memcmp(&B.graph_opts[k], &o, sizeof(DevOpts)) == 0) return hipSuccess;
+    if (B.exec[k]) {   // options changed: the kernels' arguments are part of the graph
+        (void)hipGraphExecDestroy(B.exec[k]);
+        (void)hipGraphDestroy(B.graph[k]);
+        B.exec[k] = nullptr;
+        B.graph[k] = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    enqueue_pass(B, o, timed);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(B.stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    B.graph[k] = g;
+    B.exec[k] = x;
+    B.graph_opts[k] = o;
+    return hipSuccess;
+}
+
 }  // namespace
 
+// ==================================================================================
 bool device_present() {
     int cnt = 0;
     if (hipGetDeviceCount(&cnt) != hipSuccess) return false;
@@ -544,11 +420,9 @@ bool device_present() {
 void device_free(Problem& p) {
     if (!p.dev) return;
     Device& D = *p.dev;
+    if (D.stream) (void)hipStreamSynchronize(D.stream);
+    batch_release(D.self);
     for (void* a : D.allocs) (void)hipFree(a);
-    if (D.hscal) (void)hipHostFree(D.hscal);
-    if (D.hfail) (void)hipHostFree(D.hfail);
-    for (auto evv : D.ev)
-        if (evv) (void)hipEventDestroy(evv);
     if (D.stream) (void)hipStreamDestroy(D.stream);
     delete p.dev;
     p.dev = nullptr;
@@ -560,520 +434,575 @@ nmpc_status device_init(Problem& p, std::string& err) {
     const Symbolic& sy = p.sym;
     p.dev = new Device();
     Device& D = *p.dev;
-    auto fail_cleanup = [&](nmpc_status rc) {
+    D.owner = &p;
+    auto bail = [&](nmpc_status rc) {
         device_free(p);
         return rc;
     };
-    hipError_t e = hipStreamCreate(&D.stream);
-    if (e != hipSuccess) {
-        err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
-        return fail_cleanup(NMPC_ERR_HIP);
-    }
-    D.n = st.n;
-    D.mc = st.m_c;
-    D.md = st.m_d;
-    D.ml = 2 * st.m_c + st.m_d;
-    D.m = st.m_c + st.m_d;
+#define DTRY(call)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+            return bail(e_ == hipErrorOutOfMemory ? NMPC_ERR_OOM : NMPC_ERR_HIP);      \
+        }                                                                              \
+    } while (0)
+    DTRY(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking));
+    InstPtrs& I = D.hI;
+    I.family = st.desc.family;
+    I.n = st.n;
+    I.mc = st.m_c;
+    I.md = st.m_d;
+    I.ml = 2 * st.m_c + st.m_d;
+    I.m = st.m_c + st.m_d;
+    I.nx = st.nx;
+    I.nu = st.nu;
+    I.H = st.H;
+    I.nnzk = (int64_t)sy.k_fpos.size();
     D.nnzj = (int64_t)st.jcol.size();
     D.nnzw = (int64_t)st.wrow.size();
-    D.nnzk = (int64_t)sy.k_fpos.size();
+    D.stored_l = sy.stored_l;
     const nmpc_structure& s = st.desc;
-    D.dd.N = s.n_trays;
-    D.dd.nx = s.n_trays + 2;
-    D.dd.ns = s.n_trays + 4;
-    D.dd.H = s.horizon;
-    D.dd.fd = s.n_trays / 2;
-    D.dc.dt = s.dt;
-    D.dc.alpha = s.alpha;
-    D.dc.F = s.feed_flow;
-    D.dc.rho = s.move_penalty;
-    // LDS budget of the fronts
-    int dev = 0, lds_max = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    const size_t lds_limit = (size_t)lds_max;
-    // Schedule: every level below the narrow top is one launch with one group per
-    // supernode; the top levels that hold at most kTailWidth supernodes each form
-    // a single group walked by one workgroup (a chain costs one launch).
-    constexpr int kTailWidth = 2;
-    int tail = sy.depth;
-    while (tail > 0 && sy.level_ptr[tail] - sy.level_ptr[tail - 1] <= kTailWidth) --tail;
-    if (sy.depth - tail < 2) tail = sy.depth;
-    std::vector<int32_t> nodes, gptr;
-    auto sizes = [&](int sn, size_t& fac, size_t& sol, size_t& vec) {
-        const size_t mr = (size_t)(sy.sn_rows_ptr[sn + 1] - sy.sn_rows_ptr[sn]);
-        const size_t w = (size_t)(sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]);
-        fac = std::max(fac, mr * (mr | 1) * sizeof(double) + kRelInts * sizeof(int32_t));
-        sol = std::max(sol, (mr * (w | 1) + mr + 2 * w) * sizeof(double));
-        vec = std::max(vec, mr * sizeof(double));
+    I.dd.N = s.n_trays;
+    I.dd.nx = s.n_trays + 2;
+    I.dd.ns = s.n_trays + 4;
+    I.dd.H = s.horizon;
+    I.dd.fd = s.n_trays / 2;
+    I.dc.dt = s.dt;
+    I.dc.alpha = s.alpha;
+    I.dc.F = s.feed_flow;
+    I.dc.rho = s.move_penalty;
+    if (st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
+        I.pd.G = s.grid;
+        I.pd.nx = s.grid * s.grid;
+        I.pd.ns = I.pd.nx + 16;
+        I.pd.H = s.horizon;
+        I.pd.q = s.grid / 4;
+        I.pc.dt = s.dt;
+        I.pc.kap = 0.5 * s.cond_slope;
+        I.pc.inv_h2 = (double)(s.grid + 1) * (double)(s.grid + 1);
+        I.nsp = I.pd.nx;
+        I.ntr = 0;
+    } else {
+        I.nsp = 2;
+        I.ntr = st.H;
+    }
+    // Supernode classes.  Small: the front fits in shared memory (one workgroup
+    // factors it there).  Medium: it does not, but has at most kMediumFront rows
+    // (one workgroup factors it in a global buffer).  Large: the multi-workgroup
+    // path works on it in place.  Solves use one workgroup when the panel fits
+    // in shared memory, the multi-workgroup path otherwise.
+    const size_t lim = lds_limit_bytes();
+    const int nsn = sy.nsn;
+    std::vector<char> big_fac(nsn, 0), big_sol(nsn, 0);
+    auto rows_of = [&](int sn) { return (int64_t)(sy.sn_rows_ptr[sn + 1] - sy.sn_rows_ptr[sn]); };
+    auto width_of = [&](int sn) { return (int64_t)(sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]); };
+    auto fac_bytes = [&](int sn) {
+        const size_t mr = (size_t)rows_of(sn);
+        return mr * (mr | 1) * sizeof(double) + kRelInts * sizeof(int32_t);
     };
-    auto add_launch = [&](std::vector<Device::Launch>& out, const std::vector<std::vector<int32_t>>& groups) {
-        Device::Launch L{(int)gptr.size(), (int)groups.size(), 0, 0, 0};
-        for (const auto& g : groups) {
-            gptr.push_back((int32_t)nodes.size());
-            for (int32_t sn : g) {
-                nodes.push_back(sn);
-                sizes(sn, L.lds_factor, L.lds_solve, L.lds_vec);
-            }
+    auto sol_bytes = [&](int sn) {
+        const size_t mr = (size_t)rows_of(sn), w = (size_t)width_of(sn);
+        return (mr * (w | 1) + mr + 2 * w) * sizeof(double);
+    };
+    int medium_max = 0;
+    for (int sn = 0; sn < nsn; ++sn) {
+        const int64_t mr = rows_of(sn);
+        big_fac[sn] = fac_bytes(sn) > lim && mr > kMediumFront;
+        big_sol[sn] = sol_bytes(sn) > lim;
+        if (!big_fac[sn] && fac_bytes(sn) > lim) medium_max = std::max<int>(medium_max, (int)mr);
+        if ((size_t)width_of(sn) * sizeof(double) > lim) {
+            err = "supernode wider than the shared-memory solve buffer; unsupported";
+            return bail(NMPC_ERR_UNSUPPORTED);
         }
-        gptr.push_back((int32_t)nodes.size());
-        out.push_back(L);
+    }
+    // Schedule: per level (bottom-up) one group step for its small and medium
+    // supernodes and the step sequence of the large path for its large ones; the
+    // top levels that hold at most kTailWidth supernodes, none large, form a
+    // single group walked by one workgroup (a chain costs one launch).
+    constexpr int kTailWidth = 2;
+    auto level_all_small = [&](int Lv) {
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i)
+            if (big_fac[sy.level_list[i]] || big_sol[sy.level_list[i]]) return false;
+        return true;
+    };
+    int tail = sy.depth;
+    while (tail > 0 && sy.level_ptr[tail] - sy.level_ptr[tail - 1] <= kTailWidth && level_all_small(tail - 1)) --tail;
+    if (sy.depth - tail < 2) tail = sy.depth;
+    std::vector<int32_t> nodes;
+    auto make_group = [&](const std::vector<int32_t>& sns) {
+        LocalGroup g{(int)nodes.size(), 0, 0, 0};
+        for (int32_t sn : sns) {
+            nodes.push_back(sn);
+            g.lds_factor = std::max(g.lds_factor, fac_bytes(sn));
+            g.lds_solve = std::max(g.lds_solve, sol_bytes(sn));
+        }
+        g.end = (int)nodes.size();
+        return g;
+    };
+    auto ceil_div = [](int64_t a, int64_t b) { return (int)((a + b - 1) / b); };
+    const int RB = big_row_block(), TL = big_tile(), SR = big_solve_rows(), SC = big_solve_cols();
+    auto push = [&](std::vector<Step>& dst, int kind, std::vector<int4>&& t, size_t lds = 0) {
+        if (t.empty()) return;
+        Step stp;
+        stp.kind = kind;
+        stp.tasks = std::move(t);
+        stp.lds = lds;
+        dst.push_back(std::move(stp));
+    };
+    auto big_factor_steps = [&](const std::vector<int32_t>& bigs) {
+        std::vector<int4> t;
+        for (int32_t sn : bigs)
+            for (int j = 0; j < rows_of(sn); ++j) t.push_back(int4{0, sn, j, 0});
+        push(D.fac, kBigInit, std::move(t));
+        int maxch = 0;
+        for (int32_t sn : bigs) maxch = std::max(maxch, sy.child_ptr[sn + 1] - sy.child_ptr[sn]);
+        for (int r = 0; r < maxch; ++r) {
+            std::vector<int4> e;
+            for (int32_t sn : bigs) {
+                if (sy.child_ptr[sn] + r >= sy.child_ptr[sn + 1]) continue;
+                const int c = sy.child_list[sy.child_ptr[sn] + r];
+                const int nc = (int)(rows_of(c) - width_of(c));
+                for (int jc = 0; jc < nc; ++jc) e.push_back(int4{0, sn, r, jc});
+            }
+            push(D.fac, kBigExtend, std::move(e));
+        }
+        int64_t wmax = 0;
+        for (int32_t sn : bigs) wmax = std::max(wmax, width_of(sn));
+        for (int64_t kb = 0; kb < wmax; kb += kBigPanel) {
+            std::vector<int4> po, tr, up;
+            for (int32_t sn : bigs) {
+                const int64_t w = width_of(sn), m = rows_of(sn);
+                if (kb >= w) continue;
+                const int64_t pw = std::min<int64_t>(kBigPanel, w - kb);
+                po.push_back(int4{0, sn, (int)kb, 0});
+                const int64_t below = m - kb - pw;
+                for (int rb = 0; rb < ceil_div(below, RB); ++rb) tr.push_back(int4{0, sn, (int)kb, rb});
+                const int T = ceil_div(below, TL);
+                for (int tt = 0; tt < T * (T + 1) / 2; ++tt) up.push_back(int4{0, sn, (int)kb, tt});
+            }
+            push(D.fac, kBigPotrf, std::move(po));
+            push(D.fac, kBigTrsm, std::move(tr));
+            push(D.fac, kBigUpdate, std::move(up));
+        }
     };
     std::vector<int32_t> tail_nodes;
     for (int Lv = tail; Lv < sy.depth; ++Lv)
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) tail_nodes.push_back(sy.level_list[i]);
     for (int Lv = 0; Lv < tail; ++Lv) {
-        std::vector<std::vector<int32_t>> g;
-        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) g.push_back({sy.level_list[i]});
-        add_launch(D.fwd_launches, g);
-    }
-    if (!tail_nodes.empty()) add_launch(D.fwd_launches, {tail_nodes});
-    if (!tail_nodes.empty()) add_launch(D.bwd_launches, {std::vector<int32_t>(tail_nodes.rbegin(), tail_nodes.rend())});
-    for (int Lv = tail - 1; Lv >= 0; --Lv) {
-        std::vector<std::vector<int32_t>> g;
-        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) g.push_back({sy.level_list[i]});
-        add_launch(D.bwd_launches, g);
-    }
-    size_t need_factor = 0, need_solve = 0;
-    for (const auto& L : D.fwd_launches) {
-        need_factor = std::max(need_factor, L.lds_factor);
-        need_solve = std::max(need_solve, L.lds_solve);
-    }
-    D.front_in_lds = need_factor <= lds_limit;
-    if (sy.max_front > kRelInts) {
-        err = "front larger than the relative-position buffer; unsupported front size";
-        return fail_cleanup(NMPC_ERR_UNSUPPORTED);
-    }
-    if (need_solve > lds_limit) {
-        err = "supernode panel exceeds shared memory; unsupported front size";
-        return fail_cleanup(NMPC_ERR_UNSUPPORTED);
-    }
-    for (int sn = 0; sn < sy.nsn; ++sn) D.max_width = std::max(D.max_width, sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]);
-
-    int max_groups = 0;
-    for (const auto& L : D.fwd_launches) max_groups = std::max(max_groups, L.groups);
-    e = linalg_configure(std::min(lds_limit, std::max(need_factor, need_solve)));
-    if (e != hipSuccess) {
-        err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
-        return fail_cleanup(NMPC_ERR_HIP);
-    }
-#define UP(ptr, vec)                                                      \
-    if ((e = upload(D, ptr, vec)) != hipSuccess) {                        \
-        err = std::string("upload " #vec ": ") + hipGetErrorString(e);    \
-        return fail_cleanup(e == hipErrorOutOfMemory ? NMPC_ERR_OOM : NMPC_ERR_HIP); \
-    }
-#define AL(ptr, count)                                                    \
-    if ((e = dalloc(D, ptr, count)) != hipSuccess) {                      \
-        err = std::string("hipMalloc " #ptr ": ") + hipGetErrorString(e); \
-        return fail_cleanup(e == hipErrorOutOfMemory ? NMPC_ERR_OOM : NMPC_ERR_HIP); \
-    }
-    UP(D.jptr, st.jptr);
-    UP(D.jcol, st.jcol);
-    UP(D.jt_ptr, sy.jt_ptr);
-    UP(D.jt_slot, sy.jt_slot);
-    UP(D.jt_row, sy.jt_row);
-    std::vector<double> lbv(st.lb), ubv(st.ub);
-    UP(D.lb, lbv);
-    UP(D.ub, ubv);
-    UP(D.perm, sy.perm);
-    UP(D.sn_ptr, sy.sn_ptr);
-    UP(D.rows_ptr, sy.sn_rows_ptr);
-    UP(D.rows, sy.sn_rows);
-    UP(D.child_ptr, sy.child_ptr);
-    UP(D.child_list, sy.child_list);
-    UP(D.sched_nodes, nodes);
-    UP(D.sched_gptr, gptr);
-    UP(D.l_off, sy.l_off);
-    UP(D.u_off, sy.u_off);
-    UP(D.uv_off, sy.uv_off);
-    UP(D.rel_off, sy.rel_off);
-    UP(D.rel, sy.rel);
-    UP(D.k_ptr, sy.k_ptr);
-    UP(D.k_fpos, sy.k_fpos);
-    UP(D.k_wslot, sy.k_wslot);
-    UP(D.k_diag, sy.k_diag);
-    UP(D.kc_ptr, sy.kc_ptr);
-    UP(D.kc_a, sy.kc_a);
-    UP(D.kc_b, sy.kc_b);
-    UP(D.kc_r, sy.kc_r);
-    AL(D.x0, st.nx);
-    AL(D.zF, st.H);
-    AL(D.uprev, st.nu);
-    AL(D.y, D.n); AL(D.s, D.ml); AL(D.om, D.ml); AL(D.be, D.ml); AL(D.zl, D.n); AL(D.zu, D.n);
-    AL(D.c, D.mc); AL(D.d, D.md); AL(D.jv, D.nnzj); AL(D.wv, D.nnzw); AL(D.grad, D.n); AL(D.fterm, D.n);
-    AL(D.gtw, D.n); AL(D.sig, D.n); AL(D.rhs, D.n); AL(D.dy, D.n); AL(D.xp, D.n);
-    AL(D.Q, D.ml); AL(D.r2, D.ml); AL(D.r4, D.ml); AL(D.qeff, D.m); AL(D.vcomb, D.m);
-    AL(D.ds, D.ml); AL(D.dom, D.ml); AL(D.dbe, D.ml); AL(D.dzl, D.n); AL(D.dzu, D.n);
-    AL(D.yt, D.n); AL(D.st, D.ml);
-    AL(D.kv, D.nnzk); AL(D.L, sy.stored_l); AL(D.U, sy.stored_u); AL(D.uvec, sy.stored_uv);
-    AL(D.fail, 1);
-    AL(D.adj_rhs, D.n);
-    AL(D.adj_w, D.n);
-    AL(D.adj_out, st.nx + 4 + st.H);
-    D.part_blocks = nblocks((int64_t)D.n + D.ml + D.m);
-    AL(D.part, (size_t)kMaxQ * D.part_blocks);
-    AL(D.scal, kMaxQ);
-    if (!D.front_in_lds) {
-        D.gstride = (int64_t)sy.max_front * (sy.max_front | 1);
-        AL(D.gscratch, (size_t)D.gstride * max_groups);
-    }
-#undef UP
-#undef AL
-    e = hipHostMalloc((void**)&D.hscal, kMaxQ * sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        err = std::string("hipHostMalloc: ") + hipGetErrorString(e);
-        return fail_cleanup(NMPC_ERR_HIP);
-    }
-    e = hipHostMalloc((void**)&D.hfail, sizeof(int), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        err = std::string("hipHostMalloc: ") + hipGetErrorString(e);
-        return fail_cleanup(NMPC_ERR_HIP);
-    }
-    for (auto& evv : D.ev) {
-        e = hipEventCreate(&evv);
-        if (e != hipSuccess) {
-            err = std::string("hipEventCreate: ") + hipGetErrorString(e);
-            return fail_cleanup(NMPC_ERR_HIP);
+        Step gf, gs;
+        gf.kind = kStepGroupFactor;
+        gs.kind = kStepGroupFwd;
+        std::vector<int32_t> bigs;
+        std::vector<int4> fd, fb;
+        size_t fl = 0;
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
+            const int32_t sn = sy.level_list[i];
+            if (big_fac[sn]) bigs.push_back(sn);
+            else gf.groups.push_back(make_group({sn}));
+            if (big_sol[sn]) {
+                fd.push_back(int4{0, sn, 0, 0});
+                fl = std::max(fl, (size_t)width_of(sn) * sizeof(double));
+                for (int rb = 0; rb < ceil_div(rows_of(sn) - width_of(sn), SR); ++rb) fb.push_back(int4{0, sn, rb, 0});
+            } else {
+                gs.groups.push_back(make_group({sn}));
+            }
         }
+        if (!gf.groups.empty()) D.fac.push_back(gf);
+        big_factor_steps(bigs);
+        if (!gs.groups.empty()) D.fwd.push_back(gs);
+        push(D.fwd, kBigFwdDiag, std::move(fd), fl);
+        push(D.fwd, kBigFwdBelow, std::move(fb), fl);
     }
-    D.vec.n = D.n;
-    D.vec.mc = D.mc;
-    D.vec.md = D.md;
-    D.vec.ml = D.ml;
-    D.vec.lb = D.lb;
-    D.vec.ub = D.ub;
-    D.vec.gamma = 1e-9;
-    D.S.sn_ptr = D.sn_ptr;
-    D.S.rows_ptr = D.rows_ptr;
-    D.S.rows = D.rows;
-    D.S.child_ptr = D.child_ptr;
-    D.S.child_list = D.child_list;
-    D.S.l_off = D.l_off;
-    D.S.u_off = D.u_off;
-    D.S.uv_off = D.uv_off;
-    D.S.rel_off = D.rel_off;
-    D.S.rel = D.rel;
-    D.S.k_ptr = D.k_ptr;
-    D.S.k_fpos = D.k_fpos;
+    if (!tail_nodes.empty()) {
+        Step gf, gs, gb;
+        gf.kind = kStepGroupFactor;
+        gs.kind = kStepGroupFwd;
+        gb.kind = kStepGroupBwd;
+        gf.groups.push_back(make_group(tail_nodes));
+        gs.groups.push_back(gf.groups.back());
+        gb.groups.push_back(make_group(std::vector<int32_t>(tail_nodes.rbegin(), tail_nodes.rend())));
+        D.fac.push_back(gf);
+        D.fwd.push_back(gs);
+        D.bwd.push_back(gb);
+    }
+    for (int Lv = tail - 1; Lv >= 0; --Lv) {
+        Step gb;
+        gb.kind = kStepGroupBwd;
+        std::vector<int4> bb, bd;
+        size_t bl = 0;
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
+            const int32_t sn = sy.level_list[i];
+            if (big_sol[sn]) {
+                bd.push_back(int4{0, sn, 0, 0});
+                bl = std::max(bl, (size_t)width_of(sn) * sizeof(double));
+                if (rows_of(sn) > width_of(sn))
+                    for (int cb = 0; cb < ceil_div(width_of(sn), SC); ++cb) bb.push_back(int4{0, sn, cb, 0});
+            } else {
+                gb.groups.push_back(make_group({sn}));
+            }
+        }
+        if (!gb.groups.empty()) D.bwd.push_back(gb);
+        push(D.bwd, kBigBwdBelow, std::move(bb));
+        push(D.bwd, kBigBwdDiag, std::move(bd), bl);
+    }
+    D.fac_launches = 0;
+    for (const auto& stp : D.fac) {
+        if (stp.kind != kStepGroupFactor) {
+            ++D.fac_launches;
+            continue;
+        }
+        bool in_lds = false, global = false;
+        for (const auto& g : stp.groups) (g.lds_factor <= lim ? in_lds : global) = true;
+        D.fac_launches += (int)in_lds + (int)global;
+    }
+    for (int sn = 0; sn < nsn; ++sn)
+        if (!big_fac[sn] && rows_of(sn) > kRelInts) {
+            err = "internal: a front handled by one workgroup exceeds the relative-position buffer";
+            return bail(NMPC_ERR_UNSUPPORTED);
+        }
+    // global front buffers for the medium groups of one step
+    int max_global = 0;
+    for (const auto& stp : D.fac) {
+        if (stp.kind != kStepGroupFactor) continue;
+        int cnt = 0;
+        for (const auto& g : stp.groups)
+            if (g.lds_factor > lim) ++cnt;
+        max_global = std::max(max_global, cnt);
+    }
+    const int64_t gstride = max_global > 0 ? (int64_t)medium_max * (medium_max | 1) : 0;
+    I.gstride = gstride;
+    std::vector<void*>& A = D.allocs;
+    DTRY(upload_c(A, I.jptr, st.jptr));
+    DTRY(upload_c(A, I.jcol, st.jcol));
+    DTRY(upload_c(A, I.jt_ptr, sy.jt_ptr));
+    DTRY(upload_c(A, I.jt_slot, sy.jt_slot));
+    DTRY(upload_c(A, I.jt_row, sy.jt_row));
+    DTRY(upload_c(A, I.lb, st.lb));
+    DTRY(upload_c(A, I.ub, st.ub));
+    DTRY(upload_c(A, I.perm, sy.perm));
+    DTRY(upload_c(A, I.S.sn_ptr, sy.sn_ptr));
+    DTRY(upload_c(A, I.S.rows_ptr, sy.sn_rows_ptr));
+    DTRY(upload_c(A, I.S.rows, sy.sn_rows));
+    DTRY(upload_c(A, I.S.child_ptr, sy.child_ptr));
+    DTRY(upload_c(A, I.S.child_list, sy.child_list));
+    DTRY(upload_c(A, I.S.l_off, sy.l_off));
+    DTRY(upload_c(A, I.S.u_off, sy.u_off));
+    DTRY(upload_c(A, I.S.uv_off, sy.uv_off));
+    DTRY(upload_c(A, I.S.rel_off, sy.rel_off));
+    DTRY(upload_c(A, I.S.rel, sy.rel));
+    DTRY(upload_c(A, I.S.k_ptr, sy.k_ptr));
+    DTRY(upload_c(A, I.S.k_fpos, sy.k_fpos));
+    DTRY(upload_c(A, I.kcol_ptr, sy.kcol_ptr));
+    DTRY(upload_c(A, I.S.sched_nodes, nodes));
+    DTRY(upload_c(A, I.k_wslot, sy.k_wslot));
+    DTRY(upload_c(A, I.k_diag, sy.k_diag));
+    DTRY(upload_c(A, I.kc_ptr, sy.kc_ptr));
+    DTRY(upload_c(A, I.kc_a, sy.kc_a));
+    DTRY(upload_c(A, I.kc_b, sy.kc_b));
+    DTRY(upload_c(A, I.kc_r, sy.kc_r));
+    double *x0 = nullptr, *zF = nullptr, *up = nullptr, *setp = nullptr;
+    DTRY(dalloc(A, x0, st.nx));
+    DTRY(dalloc(A, zF, st.H));
+    DTRY(dalloc(A, up, st.nu));
+    DTRY(dalloc(A, setp, std::max<size_t>(2, p.setpoint.size())));
+    I.x0 = x0;
+    I.zF = zF;
+    I.uprev = up;
+    I.setp = setp;
+    const int n = I.n, ml = I.ml, m = I.m, mc = I.mc, md = I.md;
+    DTRY(dalloc(A, I.y, n)); DTRY(dalloc(A, I.s, ml)); DTRY(dalloc(A, I.om, ml)); DTRY(dalloc(A, I.be, ml));
+    DTRY(dalloc(A, I.zl, n)); DTRY(dalloc(A, I.zu, n));
+    DTRY(dalloc(A, I.c, mc)); DTRY(dalloc(A, I.d, md)); DTRY(dalloc(A, I.jv, D.nnzj)); DTRY(dalloc(A, I.wv, D.nnzw));
+    DTRY(dalloc(A, I.grad, n)); DTRY(dalloc(A, I.fterm, n)); DTRY(dalloc(A, I.gtw, n)); DTRY(dalloc(A, I.sig, n));
+    DTRY(dalloc(A, I.rhs, n)); DTRY(dalloc(A, I.dy, n)); DTRY(dalloc(A, I.xp, n));
+    DTRY(dalloc(A, I.Q, ml)); DTRY(dalloc(A, I.r2, ml)); DTRY(dalloc(A, I.r4, ml)); DTRY(dalloc(A, I.qeff, m));
+    DTRY(dalloc(A, I.vcomb, m));
+    DTRY(dalloc(A, I.ds, ml)); DTRY(dalloc(A, I.dom, ml)); DTRY(dalloc(A, I.dbe, ml));
+    DTRY(dalloc(A, I.dzl, n)); DTRY(dalloc(A, I.dzu, n)); DTRY(dalloc(A, I.yt, n)); DTRY(dalloc(A, I.st, ml));
+    DTRY(dalloc(A, I.r1v, n)); DTRY(dalloc(A, I.r4s, ml)); DTRY(dalloc(A, I.vcomb_s, m)); DTRY(dalloc(A, I.rhs_s, n));
+    DTRY(dalloc(A, I.dy_s, n)); DTRY(dalloc(A, I.ds_s, ml)); DTRY(dalloc(A, I.dom_s, ml)); DTRY(dalloc(A, I.dbe_s, ml));
+    DTRY(dalloc(A, I.dzl_s, n)); DTRY(dalloc(A, I.dzu_s, n));
+    DTRY(dalloc(A, I.kv, I.nnzk)); DTRY(dalloc(A, I.L, sy.stored_l)); DTRY(dalloc(A, I.U, sy.stored_u));
+    DTRY(dalloc(A, I.uvec, sy.stored_uv));
+    DTRY(dalloc(A, I.adj_rhs, n)); DTRY(dalloc(A, I.adj_w, n));
+    DTRY(dalloc(A, I.adj_out, st.nx + I.nsp + I.ntr + st.nu));
+    DTRY(dalloc(A, I.adj_b, n)); DTRY(dalloc(A, I.adj_d, n)); DTRY(dalloc(A, I.adj_lam, m));
+    DTRY(dalloc(A, I.adj_qr, m));
+    DTRY(dalloc(A, I.bsum, n));
+    {
+        // Hessian rows with both triangles, slots in increasing order per row
+        std::vector<int32_t> cnt(n + 1, 0), wf_ptr(n + 1, 0);
+        const size_t nw = st.wrow.size();
+        for (size_t e = 0; e < nw; ++e) {
+            cnt[st.wrow[e]]++;
+            if (st.wrow[e] != st.wcol[e]) cnt[st.wcol[e]]++;
+        }
+        for (int j = 0; j < n; ++j) wf_ptr[j + 1] = wf_ptr[j] + cnt[j];
+        std::vector<int32_t> wf_slot(wf_ptr[n]), wf_col(wf_ptr[n]), fill(wf_ptr.begin(), wf_ptr.end() - 1);
+        for (size_t e = 0; e < nw; ++e) {
+            const int r = st.wrow[e], c = st.wcol[e];
+            wf_slot[fill[r]] = (int32_t)e;
+            wf_col[fill[r]++] = c;
+            if (r != c) {
+                wf_slot[fill[c]] = (int32_t)e;
+                wf_col[fill[c]++] = r;
+            }
+        }
+        DTRY(upload_c(A, I.wf_ptr, wf_ptr));
+        DTRY(upload_c(A, I.wf_slot, wf_slot));
+        DTRY(upload_c(A, I.wf_col, wf_col));
+    }
+    int pblocks = 0;
+    for (int k = 0; k < kNumSpaces; ++k) pblocks = std::max(pblocks, nblocks(space_size(I, k)));
+    DTRY(dalloc(A, I.part, (size_t)kMaxQ * std::max(1, pblocks)));
+    DTRY(dalloc(A, I.filter, (size_t)2 * kFilterCapMax));
+    if (gstride > 0) DTRY(dalloc(A, I.gscratch, (size_t)gstride * max_global));
+#undef DTRY
+    std::vector<Device*> one{&D};
+    nmpc_status rc = batch_build(one, D.stream, D.self, err);
+    if (rc != NMPC_OK) return bail(rc);
     std::string e2;
-    nmpc_status rc = device_set_parameters(p, e2);
+    rc = device_set_parameters(p, e2);
     if (rc != NMPC_OK) {
         err = e2;
-        return fail_cleanup(rc);
+        return bail(rc);
     }
     return NMPC_OK;
 }
 
 nmpc_status device_set_parameters(Problem& p, std::string& err) {
     Device& D = *p.dev;
-    HIP_TRY(hipMemcpyAsync(D.x0, p.x0.data(), p.x0.size() * sizeof(double), hipMemcpyHostToDevice, D.stream));
-    HIP_TRY(hipMemcpyAsync(D.zF, p.traj.data(), p.traj.size() * sizeof(double), hipMemcpyHostToDevice, D.stream));
-    HIP_TRY(hipMemcpyAsync(D.uprev, p.u_prev.data(), p.u_prev.size() * sizeof(double), hipMemcpyHostToDevice,
+    const InstPtrs& I = D.hI;
+    std::vector<double> sp(p.setpoint);
+    if (sp.size() < 2) sp.resize(2, 0.0);
+    HIP_TRY(hipMemcpyAsync((void*)I.x0, p.x0.data(), p.x0.size() * sizeof(double), hipMemcpyHostToDevice, D.stream));
+    HIP_TRY(hipMemcpyAsync((void*)I.zF, p.traj.data(), p.traj.size() * sizeof(double), hipMemcpyHostToDevice,
                            D.stream));
+    HIP_TRY(hipMemcpyAsync((void*)I.uprev, p.u_prev.data(), p.u_prev.size() * sizeof(double),
+                           hipMemcpyHostToDevice, D.stream));
+    HIP_TRY(hipMemcpyAsync((void*)I.setp, sp.data(), sp.size() * sizeof(double), hipMemcpyHostToDevice, D.stream));
     HIP_TRY(hipStreamSynchronize(D.stream));
-    D.dc.xD = p.setpoint.size() > 0 ? p.setpoint[0] : 0.0;
-    D.dc.xB = p.setpoint.size() > 1 ? p.setpoint[1] : 0.0;
     return NMPC_OK;
 }
 
-// ---- building blocks used by the driver ----------------------------------------
+// ---- Algorithm 2 over a batch --------------------------------------------------------
+nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* res, std::string& err) {
+    const int ni = B.ninst;
+    const DevOpts dop = dev_opts(o);
+    const bool timed = o.timing != 0;
+    hipStream_t st = B.stream;
+    for (int i = 0; i < ni; ++i) {
+        Ctl c{};
+        c.mu = warm ? o.mu0_warm : o.mu0_cold;
+        c.tau = std::max(o.tau_min, 1.0 - c.mu);
+        c.E0 = INFINITY;
+        c.filter_mu = std::nan("");
+        c.gamma = o.gamma;
+        c.status = kStatusRunning;
+        c.phase = kPhA;
+        B.hctl[i] = c;
+        B.members[i]->adj_ready = false;
+        B.members[i]->gamma_last = o.gamma;
+    }
+    HIP_TRY(hipMemcpyAsync(B.ctl, B.hctl, sizeof(Ctl) * ni, hipMemcpyHostToDevice, st));
+    if (!warm) {
+        // initial guess: every stage holds the measured state and the last control
+        std::vector<std::vector<double>> guesses(ni);
+        for (int i = 0; i < ni; ++i) {
+            const Problem& p = *B.members[i]->owner;
+            const int nx = p.st.nx, nu = p.st.nu, ns = nx + nu;
+            auto& yg = guesses[i];
+            yg.assign(p.st.n, 0.0);
+            for (int k = 0; k < p.st.H; ++k) {
+                for (int j = 0; j < nx; ++j) yg[k * ns + j] = p.x0[j];
+                for (int j = 0; j < nu; ++j) yg[k * ns + nx + j] = p.u_prev[j];
+            }
+            HIP_TRY(hipMemcpyAsync(B.members[i]->hI.y, yg.data(), yg.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, st));
+        }
+        launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, false, st);
+        eval(B, false, kSrcIter, kPredAll);
+        launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, true, st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));   // the host guesses must outlive their copies
+    }
+    double ms[5] = {0, 0, 0, 0, 0};
+    const int k = timed ? 1 : 0;
+    bool use_graph = o.graph != 0 && !B.graph_failed[k];
+    if (use_graph && ensure_graph(B, dop, timed) != hipSuccess) {
+        (void)hipGetLastError();
+        B.graph_failed[k] = true;
+        use_graph = false;
+    }
+    // every pass moves each running instance by one iteration, factorization
+    // attempt or trial point; the method bounds all three
+    const long max_passes = (long)(o.max_iter + 1) * (o.ls_max + 64) + 8;
+    long passes = 0;
+    int timing_lost = 0;
+    while (true) {
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(B.exec[k], st));
+        } else {
+            enqueue_pass(B, dop, timed);
+            HIP_TRY(hipGetLastError());
+        }
+        HIP_TRY(hipMemcpyAsync(B.hrunning, B.running, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ++passes;
+        if (timed) {
+            bool lost = false;
+            for (int ph = 0; ph < 5; ++ph) {
+                float t = 0.0f;
+                if (hipEventElapsedTime(&t, B.ev[ph], B.ev[ph + 1]) == hipSuccess) {
+                    ms[ph] += t;
+                } else {
+                    (void)hipGetLastError();
+                    lost = true;
+                }
+            }
+            if (lost && use_graph) {   // events inside the graph did not time: launch eagerly from now on
+                B.graph_failed[k] = true;
+                use_graph = false;
+                ++timing_lost;
+            }
+        }
+        if (*B.hrunning == 0) break;
+        if (passes >= max_passes) {
+            err = "solve: pass limit reached with instances still running";
+            return NMPC_ERR_HIP;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(B.hctl, B.ctl, sizeof(Ctl) * ni, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int worst = NMPC_OK;
+    for (int i = 0; i < ni; ++i) {
+        const Ctl& c = B.hctl[i];
+        nmpc_result r{};
+        r.status = c.status;
+        r.iters = c.it;
+        r.factorizations = c.factorizations;
+        r.ls_trials = c.ls_trials;
+        r.mu = c.mu;
+        r.eta = c.eta;
+        r.E0 = c.E0;
+        r.objective = c.f;
+        r.ms_eval = ms[0];
+        r.ms_assemble = ms[1];
+        r.ms_factor = ms[2];
+        r.ms_solve = ms[3];
+        r.ms_linesearch = ms[4];
+        r.factor_launches = c.factorizations * B.members[i]->fac_launches;
+        r.passes = (int)passes;
+        r.timing_lost = timing_lost;
+        res[i] = r;
+        worst = std::max(worst, (int)c.status);
+    }
+    return worst;
+}
+
+nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err) {
+    return batch_solve(*p.dev->self, warm, o, &r, err);
+}
+
+nmpc_status batch_create(const std::vector<Problem*>& ps, Batch*& out, std::string& err) {
+    std::vector<Device*> members;
+    for (Problem* p : ps) members.push_back(p->dev);
+    return batch_build(members, nullptr, out, err);
+}
+
+void batch_free(Batch* b) {
+    if (b && b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+}
+
+int batch_size(const Batch& b) { return b.ninst; }
+
+// ---- single-problem entry points -------------------------------------------------------
 namespace {
 
-void eval(Device& D, bool full, const double* y) {
-    launch_eval_distill(full, D.dd, D.dc, y, D.x0, D.zF, D.uprev, D.om, D.jptr, D.mc, D.c, D.d, D.jv, D.wv,
-                        D.grad, D.fterm, D.stream);
-}
-
-Ops make_ops(std::initializer_list<int> l) {
-    Ops o{};
-    o.q = 0;
-    for (int v : l) o.op[o.q++] = v;
-    return o;
-}
-
-const Ops kOpsA = make_ops({kSum, kMax, kMax, kMax, kMax, kMin, kMax, kMin, kMax, kMin, kSum});
-const Ops kOpsE = make_ops({kMin, kMin, kMax, kSum, kSum, kSum, kSum, kSum, kSum, kSum, kSum});
-const Ops kOpsT = make_ops({kSum, kSum, kSum, kSum, kSum, kSum});
-
-hipError_t fetch_scalars(Device& D, int q) {
-    hipError_t e = hipMemcpyAsync(D.hscal, D.scal, q * sizeof(double), hipMemcpyDeviceToHost, D.stream);
+// Control block of a batch of one for the direct entry points (mu, gamma).
+hipError_t set_ctl(Batch& B, double mu, double gamma) {
+    Ctl c{};
+    c.mu = mu;
+    c.gamma = gamma;
+    c.status = NMPC_OK;
+    c.phase = kPhDone;
+    B.hctl[0] = c;
+    hipError_t e = hipMemcpyAsync(B.ctl, B.hctl, sizeof(Ctl), hipMemcpyHostToDevice, B.stream);
     if (e != hipSuccess) return e;
-    return hipStreamSynchronize(D.stream);
+    return hipStreamSynchronize(B.stream);
 }
 
-void phaseA(Device& D) {
-    const int nb = nblocks((int64_t)D.n + D.ml);
-    hipLaunchKernelGGL(k_phaseA, dim3(nb), dim3(kBlock), 0, D.stream, D.vec, D.y, D.s, D.om, D.be, D.zl, D.zu,
-                       D.grad, D.fterm, D.c, D.d, D.jv, D.jt_ptr, D.jt_slot, D.jt_row, D.gtw, D.part, kOpsA);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, D.stream, D.part, nb, kOpsA, D.scal);
-}
-
-void prep_and_assemble(Device& D, double mu) {
-    hipLaunchKernelGGL(k_rows_prep, dim3(nblocks(D.m)), dim3(kBlock), 0, D.stream, D.vec, mu, D.s, D.om, D.be,
-                       D.c, D.d, D.Q, D.r2, D.r4, D.qeff, D.vcomb);
-    hipLaunchKernelGGL(k_var_prep, dim3(nblocks(D.n)), dim3(kBlock), 0, D.stream, D.vec, mu, D.y, D.zl, D.zu,
-                       D.grad, D.gtw, D.jv, D.jt_ptr, D.jt_slot, D.jt_row, D.vcomb, D.sig, D.rhs);
-    hipLaunchKernelGGL(k_assemble, dim3(nblocks(D.nnzk)), dim3(kBlock), 0, D.stream, D.nnzk, D.k_wslot, D.k_diag,
-                       D.kc_ptr, D.kc_a, D.kc_b, D.kc_r, D.wv, D.sig, D.jv, D.qeff, D.kv);
-}
-
-enum Phase { kPhEval = 0, kPhAssemble = 1, kPhFactor = 2, kPhSolve = 3, kPhSearch = 4 };
-
-struct Timer {
-    Device* D;
-    bool on;
-    double ms[5] = {0, 0, 0, 0, 0};
-    void begin(int ph) {
-        if (on) (void)hipEventRecord(D->ev[2 * ph], D->stream);
-    }
-    void end(int ph) {
-        if (on) (void)hipEventRecord(D->ev[2 * ph + 1], D->stream);
-    }
-    // call once the stream has passed end(ph)
-    void collect(int ph) {
-        if (!on) return;
-        float t = 0.0f;
-        if (hipEventElapsedTime(&t, D->ev[2 * ph], D->ev[2 * ph + 1]) == hipSuccess) ms[ph] += t;
-    }
-};
-
-// NumCholesky (eq. 20) of kv + eta I; returns the failure flag.
-hipError_t factor(Device& D, double eta, int& failed, Timer* tm = nullptr, int* launches = nullptr) {
-    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, D.stream, D.fail);
-    hipError_t e = hipSuccess;
-    if (tm) tm->begin(kPhFactor);
-    for (const auto& Lc : D.fwd_launches)
-        launch_factor_groups(D.front_in_lds, D.sched_nodes, D.sched_gptr + Lc.gptr_off, Lc.groups, Lc.lds_factor, D.S,
-                             D.kv, eta, D.L, D.U, D.fail, D.gscratch, D.gstride, D.stream);
-    if (tm) tm->end(kPhFactor);
-    if (launches) *launches += (int)D.fwd_launches.size();
-    e = hipGetLastError();
+// NumCholesky (eq. 20) of kv + eta I for a batch of one; returns the failure flag.
+hipError_t factor_once(Batch& B, double eta, int& failed) {
+    launch_set_fail(B.dI, 1, 0, B.stream);
+    factor_launches(B, kPredAll, eta);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(D.hfail, D.fail, sizeof(int), hipMemcpyDeviceToHost, D.stream);
+    e = hipMemcpyAsync(B.hctl, B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, B.stream);
     if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(D.stream);
-    if (tm) tm->collect(kPhFactor);
-    failed = *D.hfail;
+    e = hipStreamSynchronize(B.stream);
+    failed = B.hctl[0].fail;
     return e;
-}
-
-// Solve with the current factor: b (original order) -> x (original order).
-void solve(Device& D, const double* b, double* x) {
-    for (const auto& Lc : D.fwd_launches)
-        launch_fwd_groups(D.sched_nodes, D.sched_gptr + Lc.gptr_off, Lc.groups, Lc.lds_solve, D.S, D.L, D.uvec, b,
-                          D.perm, D.xp, D.stream);
-    for (const auto& Lc : D.bwd_launches)
-        launch_bwd_groups(D.sched_nodes, D.sched_gptr + Lc.gptr_off, Lc.groups, Lc.lds_solve, D.S, D.L, D.xp, D.perm,
-                          x, D.stream);
 }
 
 }  // namespace
 
-// ---- Algorithm 2 -------------------------------------------------------------------
-nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err) {
-    Device& D = *p.dev;
-    D.vec.gamma = o.gamma;
-    D.adj_ready = false;
-    r = nmpc_result{};
-    double mu = warm ? o.mu0_warm : o.mu0_cold;
-    if (!warm) {
-        // initial guess: every stage holds the measured state and the last control
-        std::vector<double> yg(D.n);
-        const int nx = p.st.nx, nu = p.st.nu, ns = nx + nu;
-        for (int k = 0; k < p.st.H; ++k) {
-            for (int i = 0; i < nx; ++i) yg[k * ns + i] = p.x0[i];
-            for (int i = 0; i < nu; ++i) yg[k * ns + nx + i] = p.u_prev[i];
-        }
-        HIP_TRY(hipMemcpyAsync(D.y, yg.data(), D.n * sizeof(double), hipMemcpyHostToDevice, D.stream));
-        hipLaunchKernelGGL(k_push_bounds, dim3(nblocks(D.n)), dim3(kBlock), 0, D.stream, D.vec, o.bound_push, D.y);
-        eval(D, false, D.y);
-        hipLaunchKernelGGL(k_cold_duals, dim3(nblocks(std::max(D.n, D.ml))), dim3(kBlock), 0, D.stream, D.vec, mu,
-                           o.slack_push, D.c, D.d, D.y, D.s, D.om, D.be, D.zl, D.zu);
-        HIP_TRY(hipGetLastError());
-    }
-    double nu = 1.0, eta_last = 0.0, eta = 0.0, E0 = INFINITY, f = 0.0;
-    int it = 0, status = NMPC_MAX_ITER;
-    Timer tm{&D, o.timing != 0};
-    const double eps = std::numeric_limits<double>::epsilon();
-    while (true) {
-        tm.begin(kPhEval);
-        eval(D, true, D.y);
-        phaseA(D);
-        tm.end(kPhEval);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(fetch_scalars(D, kOpsA.q));
-        tm.collect(kPhEval);
-        const double* A = D.hscal;
-        f = A[0];
-        const double dual = A[1], sinf = A[2], prim = A[3], sbmax = A[4], sbmin = A[5];
-        const double lzmax = A[6], lzmin = A[7], uzmax = A[8], uzmin = A[9];
-        if (A[10] > 0.0 || !std::isfinite(f)) {
-            status = NMPC_NONFINITE;
-            break;
-        }
-        auto Emu = [&](double m_) {
-            double e = std::max(std::max(dual, sinf), std::max(prim, std::max(sbmax - m_, m_ - sbmin)));
-            if (lzmax > -INFINITY) e = std::max(e, std::max(lzmax - m_, m_ - lzmin));
-            if (uzmax > -INFINITY) e = std::max(e, std::max(uzmax - m_, m_ - uzmin));
-            return e;
-        };
-        E0 = Emu(0.0);
-        if (E0 <= o.tol) {
-            status = NMPC_OK;
-            break;
-        }
-        if (it >= o.max_iter) {
-            status = NMPC_MAX_ITER;
-            break;
-        }
-        double em = Emu(mu);
-        while (em <= o.kappa_eps * mu && mu > o.mu_min) {
-            mu = std::max(o.mu_min, std::min(o.kappa_mu * mu, std::pow(mu, o.theta_mu)));
-            em = Emu(mu);
-        }
-        const double tau = std::max(o.tau_min, 1.0 - mu);
-        tm.begin(kPhAssemble);
-        prep_and_assemble(D, mu);
-        tm.end(kPhAssemble);
-        HIP_TRY(hipGetLastError());
-        int failed = 0;
-        eta = 0.0;
-        HIP_TRY(factor(D, 0.0, failed, &tm, &r.factor_launches));
-        tm.collect(kPhAssemble);
-        r.factorizations++;
-        if (failed) {
-            eta = eta_last == 0.0 ? o.eta_first : std::max(o.eta_min, o.km * eta_last);
-            bool ok = false;
-            while (true) {
-                HIP_TRY(factor(D, eta, failed, &tm, &r.factor_launches));
-                r.factorizations++;
-                if (!failed) {
-                    ok = true;
-                    break;
-                }
-                eta *= eta_last == 0.0 ? o.kp_first : o.kp;
-                if (eta > o.eta_max) break;
-            }
-            if (!ok) {
-                status = NMPC_REG_FAIL;
-                break;
-            }
-            eta_last = eta;
-        }
-        tm.begin(kPhSolve);
-        solve(D, D.rhs, D.dy);
-        tm.end(kPhSolve);
-        const int nbE = nblocks((int64_t)D.m + D.n);
-        hipLaunchKernelGGL(k_phaseE, dim3(nbE), dim3(kBlock), 0, D.stream, D.vec, mu, tau, D.y, D.s, D.om, D.be,
-                           D.zl, D.zu, D.grad, D.dy, D.Q, D.r2, D.r4, D.jv, D.jptr, D.jcol, D.ds, D.dom, D.dbe,
-                           D.dzl, D.dzu, D.part, kOpsE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, D.stream, D.part, nbE, kOpsE, D.scal);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(fetch_scalars(D, kOpsE.q));
-        tm.collect(kPhSolve);
-        const double* E = D.hscal;
-        const double amax = std::min(1.0, E[0]);
-        const double adu = std::min(1.0, E[1]);
-        nu = std::max(nu, E[2] + 1.0);
-        const double gfdy = E[3], dsos = E[4], dyogl = E[5], dyogu = E[6], r4l1 = E[7];
-        const double lns = E[8], lngl = E[9], lngu = E[10];
-        const double phi0 = f - mu * lns - mu * lngl - mu * lngu + nu * r4l1;
-        const double dphi = gfdy - mu * dsos - mu * dyogl + mu * dyogu - nu * r4l1;
-        double alpha = std::min(amax, adu);
-        bool accepted = false;
-        const int nbT = nblocks((int64_t)D.n + D.ml);
-        for (int tr = 1; tr <= o.ls_max; ++tr) {
-            r.ls_trials++;
-            tm.begin(kPhSearch);
-            hipLaunchKernelGGL(k_trial_point, dim3(nblocks(std::max(D.n, D.ml))), dim3(kBlock), 0, D.stream, D.n,
-                               D.ml, alpha, D.y, D.dy, D.s, D.ds, D.yt, D.st);
-            eval(D, false, D.yt);
-            hipLaunchKernelGGL(k_phaseT, dim3(nbT), dim3(kBlock), 0, D.stream, D.vec, D.yt, D.st, D.fterm, D.c, D.d,
-                               D.part, kOpsT);
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, D.stream, D.part, nbT, kOpsT, D.scal);
-            tm.end(kPhSearch);
-            HIP_TRY(hipGetLastError());
-            HIP_TRY(fetch_scalars(D, kOpsT.q));
-            tm.collect(kPhSearch);
-            const double* T = D.hscal;
-            const double phit = T[0] - mu * T[1] - mu * T[2] - mu * T[3] + nu * T[4];
-            if (T[5] == 0.0 && std::isfinite(phit) &&
-                phit <= phi0 + o.armijo * alpha * dphi + 10.0 * eps * std::fabs(phi0)) {
-                accepted = true;
-                break;
-            }
-            alpha *= 0.5;
-        }
-        if (!accepted) {
-            status = NMPC_LINESEARCH_FAIL;
-            break;
-        }
-        hipLaunchKernelGGL(k_update, dim3(nblocks(std::max(D.n, D.ml))), dim3(kBlock), 0, D.stream, D.vec, alpha,
-                           mu, o.kappa_sigma, D.y, D.s, D.om, D.be, D.zl, D.zu, D.dy, D.ds, D.dom, D.dbe, D.dzl,
-                           D.dzu);
-        HIP_TRY(hipGetLastError());
-        ++it;
-    }
-    HIP_TRY(hipStreamSynchronize(D.stream));
-    r.status = status;
-    r.iters = it;
-    r.mu = mu;
-    r.eta = eta;
-    r.E0 = E0;
-    r.objective = f;
-    r.ms_eval = tm.ms[kPhEval];
-    r.ms_assemble = tm.ms[kPhAssemble];
-    r.ms_factor = tm.ms[kPhFactor];
-    r.ms_solve = tm.ms[kPhSolve];
-    r.ms_linesearch = tm.ms[kPhSearch];
-    return status;
-}
-
 nmpc_status device_get_iterate(const Problem& p, double* y, double* s, double* om, double* be, double* zl,
                                double* zu, std::string& err) {
-    const Device& D = *p.dev;
-    HIP_TRY(hipMemcpy(y, D.y, D.n * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(s, D.s, D.ml * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(om, D.om, D.ml * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(be, D.be, D.ml * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(zl, D.zl, D.n * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(zu, D.zu, D.n * sizeof(double), hipMemcpyDeviceToHost));
+    const InstPtrs& I = p.dev->hI;
+    HIP_TRY(hipMemcpy(y, I.y, I.n * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(s, I.s, I.ml * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(om, I.om, I.ml * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(be, I.be, I.ml * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(zl, I.zl, I.n * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(zu, I.zu, I.n * sizeof(double), hipMemcpyDeviceToHost));
+    return NMPC_OK;
+}
+
+nmpc_status device_get_first_stage(const Problem& p, double* u1, double* x1, std::string& err) {
+    const InstPtrs& I = p.dev->hI;
+    if (u1) HIP_TRY(hipMemcpy(u1, I.y + I.nx, I.nu * sizeof(double), hipMemcpyDeviceToHost));
+    if (x1) HIP_TRY(hipMemcpy(x1, I.y, I.nx * sizeof(double), hipMemcpyDeviceToHost));
     return NMPC_OK;
 }
 
 nmpc_status device_set_iterate(Problem& p, const double* y, const double* s, const double* om, const double* be,
                                const double* zl, const double* zu, std::string& err) {
     Device& D = *p.dev;
+    const InstPtrs& I = D.hI;
     D.adj_ready = false;
-    HIP_TRY(hipMemcpy(D.y, y, D.n * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(D.s, s, D.ml * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(D.om, om, D.ml * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(D.be, be, D.ml * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(D.zl, zl, D.n * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(D.zu, zu, D.n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.y, y, I.n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.s, s, I.ml * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.om, om, I.ml * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.be, be, I.ml * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.zl, zl, I.n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.zu, zu, I.n * sizeof(double), hipMemcpyHostToDevice));
     return NMPC_OK;
 }
 
 nmpc_status device_eval(Problem& p, const double* y, const double* lam, const double* lam_d, double* f,
                         double* grad, double* c, double* d, double* jv, double* wv, std::string& err) {
     Device& D = *p.dev;
+    Batch& B = *D.self;
+    const InstPtrs& I = D.hI;
     // stage the multipliers as a lifted omega: omega+ = lam, omega- = 0, omega_d = lam_d
-    std::vector<double> om(D.ml, 0.0);
-    for (int r = 0; r < D.mc; ++r) om[r] = lam[r];
-    for (int r = 0; r < D.md; ++r) om[2 * D.mc + r] = lam_d[r];
-    HIP_TRY(hipMemcpyAsync(D.yt, y, D.n * sizeof(double), hipMemcpyHostToDevice, D.stream));
-    HIP_TRY(hipMemcpyAsync(D.dom, om.data(), D.ml * sizeof(double), hipMemcpyHostToDevice, D.stream));
-    launch_eval_distill(true, D.dd, D.dc, D.yt, D.x0, D.zF, D.uprev, D.dom, D.jptr, D.mc, D.c, D.d, D.jv, D.wv,
-                        D.grad, D.fterm, D.stream);
+    std::vector<double> om(I.ml, 0.0);
+    for (int r = 0; r < I.mc; ++r) om[r] = lam[r];
+    for (int r = 0; r < I.md; ++r) om[2 * I.mc + r] = lam_d[r];
+    HIP_TRY(hipMemcpyAsync(I.yt, y, I.n * sizeof(double), hipMemcpyHostToDevice, B.stream));
+    HIP_TRY(hipMemcpyAsync(I.dom, om.data(), I.ml * sizeof(double), hipMemcpyHostToDevice, B.stream));
+    eval(B, true, kSrcUser, kPredAll);
     HIP_TRY(hipGetLastError());
-    std::vector<double> ft(D.n);
-    HIP_TRY(hipMemcpyAsync(ft.data(), D.fterm, D.n * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    if (grad) HIP_TRY(hipMemcpyAsync(grad, D.grad, D.n * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    if (c) HIP_TRY(hipMemcpyAsync(c, D.c, D.mc * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    if (d && D.md) HIP_TRY(hipMemcpyAsync(d, D.d, D.md * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    if (jv) HIP_TRY(hipMemcpyAsync(jv, D.jv, D.nnzj * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    if (wv) HIP_TRY(hipMemcpyAsync(wv, D.wv, D.nnzw * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    HIP_TRY(hipStreamSynchronize(D.stream));
+    std::vector<double> ft(I.n);
+    HIP_TRY(hipMemcpyAsync(ft.data(), I.fterm, I.n * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    if (grad) HIP_TRY(hipMemcpyAsync(grad, I.grad, I.n * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    if (c) HIP_TRY(hipMemcpyAsync(c, I.c, I.mc * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    if (d && I.md) HIP_TRY(hipMemcpyAsync(d, I.d, I.md * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    if (jv) HIP_TRY(hipMemcpyAsync(jv, I.jv, D.nnzj * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    if (wv) HIP_TRY(hipMemcpyAsync(wv, I.wv, D.nnzw * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    HIP_TRY(hipStreamSynchronize(B.stream));
     if (f) {
         double acc = 0.0;
         for (double v : ft) acc += v;
@@ -1084,39 +1013,51 @@ nmpc_status device_eval(Problem& p, const double* y, const double* lam, const do
 
 nmpc_status device_factor(Problem& p, const double* kv, double eta, int32_t* ok, double* lv, std::string& err) {
     Device& D = *p.dev;
-    HIP_TRY(hipMemcpyAsync(D.kv, kv, D.nnzk * sizeof(double), hipMemcpyHostToDevice, D.stream));
+    Batch& B = *D.self;
+    D.adj_ready = false;
+    HIP_TRY(hipMemcpyAsync(D.hI.kv, kv, D.hI.nnzk * sizeof(double), hipMemcpyHostToDevice, B.stream));
     int failed = 0;
-    HIP_TRY(factor(D, eta, failed));
+    HIP_TRY(factor_once(B, eta, failed));
     *ok = failed ? 0 : 1;
-    if (lv) HIP_TRY(hipMemcpy(lv, D.L, p.sym.stored_l * sizeof(double), hipMemcpyDeviceToHost));
+    if (lv) HIP_TRY(hipMemcpy(lv, D.hI.L, D.stored_l * sizeof(double), hipMemcpyDeviceToHost));
     return NMPC_OK;
 }
 
 nmpc_status device_linear_solve(Problem& p, const double* b, double* x, std::string& err) {
     Device& D = *p.dev;
-    HIP_TRY(hipMemcpyAsync(D.yt, b, D.n * sizeof(double), hipMemcpyHostToDevice, D.stream));
-    solve(D, D.yt, D.dzl);
+    Batch& B = *D.self;
+    HIP_TRY(hipMemcpyAsync(D.hI.yt, b, D.hI.n * sizeof(double), hipMemcpyHostToDevice, B.stream));
+    solve_launches(B, kPredAll, 1);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(x, D.dzl, D.n * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    HIP_TRY(hipStreamSynchronize(D.stream));
+    HIP_TRY(hipMemcpyAsync(x, D.hI.dzl, D.hI.n * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    HIP_TRY(hipStreamSynchronize(B.stream));
     return NMPC_OK;
 }
+
+namespace {
+// eval, G^T omega and the condensed system at the handle's iterate
+hipError_t assemble_here(Device& D, double mu) {
+    Batch& B = *D.self;
+    hipError_t e = set_ctl(B, mu, D.gamma_last);
+    if (e != hipSuccess) return e;
+    eval(B, true, kSrcIter, kPredAll);
+    DevOpts unused{};
+    launch_phaseA(B.dI, B.spaces, 1, kPredAll, unused, false, B.stream);
+    launch_assemble(B.dI, B.spaces, kPredAll, B.stream);
+    return hipGetLastError();
+}
+}  // namespace
 
 nmpc_status device_assemble(Problem& p, double mu, double* kv, double* rhs, std::string& err) {
     Device& D = *p.dev;
-    eval(D, true, D.y);
-    phaseA(D);
-    prep_and_assemble(D, mu);
-    HIP_TRY(hipGetLastError());
-    if (kv) HIP_TRY(hipMemcpyAsync(kv, D.kv, D.nnzk * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    if (rhs) HIP_TRY(hipMemcpyAsync(rhs, D.rhs, D.n * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    HIP_TRY(hipStreamSynchronize(D.stream));
+    Batch& B = *D.self;
+    D.adj_ready = false;
+    HIP_TRY(assemble_here(D, mu));
+    if (kv) HIP_TRY(hipMemcpyAsync(kv, D.hI.kv, D.hI.nnzk * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    if (rhs) HIP_TRY(hipMemcpyAsync(rhs, D.hI.rhs, D.hI.n * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    HIP_TRY(hipStreamSynchronize(B.stream));
     return NMPC_OK;
 }
-
-}  // namespace nmpc
-
-namespace nmpc {
 
 void device_invalidate_adjoint(Problem& p) {
     if (p.dev) p.dev->adj_ready = false;
@@ -1124,23 +1065,23 @@ void device_invalidate_adjoint(Problem& p) {
 
 namespace {
 
+constexpr int kAdjRefine = 2;   // refinement steps per sensitivity solve
+
 // Assemble and factor K at the handle's iterate (inertia correction as in the solve).
 nmpc_status adjoint_prepare(Problem& p, std::string& err) {
     Device& D = *p.dev;
     if (D.adj_ready) return NMPC_OK;
-    eval(D, true, D.y);
-    phaseA(D);
-    prep_and_assemble(D, 1.0);   // mu only enters r2, which the sensitivities do not use
-    HIP_TRY(hipGetLastError());
+    Batch& B = *D.self;
+    HIP_TRY(assemble_here(D, 1.0));   // mu only enters r2, which the sensitivities do not use
     int failed = 0;
     double eta = 0.0;
-    HIP_TRY(factor(D, 0.0, failed));
+    HIP_TRY(factor_once(B, 0.0, failed));
     if (failed) {
         nmpc_options o;
         nmpc_default_options(&o);
         eta = o.eta_first;
         while (true) {
-            HIP_TRY(factor(D, eta, failed));
+            HIP_TRY(factor_once(B, eta, failed));
             if (!failed) break;
             eta *= o.kp_first;
             if (eta > o.eta_max) {
@@ -1157,22 +1098,27 @@ nmpc_status adjoint_prepare(Problem& p, std::string& err) {
 nmpc_status adjoint_apply(Problem& p, const double* seed_u1, double seed_obj, std::vector<double>& out,
                           std::string& err) {
     Device& D = *p.dev;
+    Batch& B = *D.self;
     const Structure& st = p.st;
     if (st.nu > kMaxSeed) {
         err = "adjoint: too many controls per stage";
         return NMPC_ERR_UNSUPPORTED;
     }
-    Seed sd{};
-    for (int j = 0; j < st.nu; ++j) sd.u[j] = seed_u1[j];
-    hipLaunchKernelGGL(k_adj_seed, dim3(nblocks(D.n)), dim3(kBlock), 0, D.stream, D.n, st.nx, st.nu, D.grad,
-                       seed_obj, sd, D.adj_rhs);
-    solve(D, D.adj_rhs, D.adj_w);
-    hipLaunchKernelGGL(k_adj_gather_distill, dim3(1), dim3(kBlock), 0, D.stream, D.dd, D.dc, D.y, D.uprev, D.adj_w,
-                       D.jv, D.jptr, D.jcol, D.qeff, seed_obj, D.adj_out);
+    launch_adj_seed(B.dI, B.spaces.sp[kSpN], seed_u1, st.nu, seed_obj, B.stream);
+    solve_launches(B, kPredAll, 2);
+    // refinement against the uncondensed system: the condensed matrix rounds the
+    // curvature next to the lifted weights, the uncondensed residual does not
+    launch_adj_refine(0, B.dI, B.spaces, D.adj_eta, B.stream);
+    for (int r = 0; r < kAdjRefine; ++r) {
+        launch_adj_refine(1, B.dI, B.spaces, D.adj_eta, B.stream);
+        solve_launches(B, kPredAll, 3);
+        launch_adj_refine(2, B.dI, B.spaces, D.adj_eta, B.stream);
+    }
+    launch_adj_gather(B.dI, D.hI.family, D.hI.nx, seed_obj, B.stream);
     HIP_TRY(hipGetLastError());
-    out.resize(st.nx + 4 + st.H);
-    HIP_TRY(hipMemcpyAsync(out.data(), D.adj_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, D.stream));
-    HIP_TRY(hipStreamSynchronize(D.stream));
+    out.resize(st.nx + D.hI.nsp + D.hI.ntr + st.nu);
+    HIP_TRY(hipMemcpyAsync(out.data(), D.hI.adj_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, B.stream));
+    HIP_TRY(hipStreamSynchronize(B.stream));
     return NMPC_OK;
 }
 
@@ -1186,10 +1132,12 @@ nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, d
     rc = adjoint_apply(p, seed_u1, seed_obj, out, err);
     if (rc != NMPC_OK) return rc;
     const Structure& st = p.st;
-    if (gx0) std::copy(out.begin(), out.begin() + st.nx, gx0);
-    if (gsp) std::copy(out.begin() + st.nx, out.begin() + st.nx + 2, gsp);
-    if (gtraj) std::copy(out.begin() + st.nx + 2, out.begin() + st.nx + 2 + st.H, gtraj);
-    if (gup) std::copy(out.begin() + st.nx + 2 + st.H, out.begin() + st.nx + 4 + st.H, gup);
+    const int nsp = p.dev->hI.nsp, ntr = p.dev->hI.ntr;
+    auto o = out.begin();
+    if (gx0) std::copy(o, o + st.nx, gx0);
+    if (gsp) std::copy(o + st.nx, o + st.nx + nsp, gsp);
+    if (gtraj && ntr) std::copy(o + st.nx + nsp, o + st.nx + nsp + ntr, gtraj);
+    if (gup) std::copy(o + st.nx + nsp + ntr, o + st.nx + nsp + ntr + st.nu, gup);
     return p.dev->adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "distill_layout.h"
+#include "plate_layout.h"
 #include "internal.h"
 
 namespace nmpc {
@@ -108,12 +109,71 @@ static bool build_distillation(const nmpc_structure& s, Structure& st, std::stri
     return true;
 }
 
+static bool build_plate(const nmpc_structure& s, Structure& st, std::string& err) {
+    if (s.grid < 4 || s.grid % 4 != 0 || s.horizon < 1 || !(s.dt > 0) || !(s.c_lo < s.c_hi) ||
+        !(s.cond_slope >= 0) || !(s.t_hi > -INFINITY)) {
+        err = "plate: need grid a positive multiple of 4, horizon >= 1, dt > 0, c_lo < c_hi, cond_slope >= 0";
+        return false;
+    }
+    PlateDims D;
+    D.G = s.grid;
+    D.nx = D.G * D.G;
+    D.ns = D.nx + 16;
+    D.H = s.horizon;
+    D.q = D.G / 4;
+    st.nx = D.nx;
+    st.nu = 16;
+    st.H = D.H;
+    st.n = D.H * D.ns;
+    st.m_c = D.H * D.nx;
+    st.m_d = 0;
+    st.jptr.assign(st.m_c + 1, 0);
+    st.jcol.clear();
+    for (int k = 0; k < D.H; ++k)
+        for (int p = 0; p < D.nx; ++p) {
+            const int b = p / D.G, a = p - b * D.G, base = k * D.ns;
+            if (k > 0) st.jcol.push_back((k - 1) * D.ns + p);
+            if (b > 0) st.jcol.push_back(base + p - D.G);
+            if (a > 0) st.jcol.push_back(base + p - 1);
+            st.jcol.push_back(base + p);
+            if (a < D.G - 1) st.jcol.push_back(base + p + 1);
+            if (b < D.G - 1) st.jcol.push_back(base + p + D.G);
+            if (b == 0) st.jcol.push_back(base + D.nx + 0 * 4 + a / D.q);
+            if (a == D.G - 1) st.jcol.push_back(base + D.nx + 1 * 4 + b / D.q);
+            if (b == D.G - 1) st.jcol.push_back(base + D.nx + 2 * 4 + a / D.q);
+            if (a == 0) st.jcol.push_back(base + D.nx + 3 * 4 + b / D.q);
+            const int row = k * D.nx + p;
+            st.jptr[row + 1] = (int)st.jcol.size();
+            if (st.jptr[row + 1] - st.jptr[row] != pl_row_nnz(D, k, p)) {
+                err = "internal: plate row layout mismatch";
+                return false;
+            }
+        }
+    st.jrow.resize(st.jcol.size());
+    for (int r = 0; r < st.m_c; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) st.jrow[p] = r;
+    st.wrow.resize(st.n);
+    st.wcol.resize(st.n);
+    for (int j = 0; j < st.n; ++j) st.wrow[j] = st.wcol[j] = j;
+    st.lb.assign(st.n, 0.0);
+    st.ub.assign(st.n, 0.0);
+    for (int k = 0; k < D.H; ++k)
+        for (int j = 0; j < D.ns; ++j) {
+            const bool is_t = j < D.nx;
+            st.lb[k * D.ns + j] = is_t ? -INFINITY : s.c_lo;
+            st.ub[k * D.ns + j] = is_t ? s.t_hi : s.c_hi;
+        }
+    return true;
+}
+
 bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) {
     out = Structure();
     out.desc = s;
     bool ok = false;
     if (s.family == NMPC_FAMILY_DISTILLATION) {
         ok = build_distillation(s, out, err);
+    } else if (s.family == NMPC_FAMILY_HEATED_PLATE) {
+        ok = build_plate(s, out, err);
     } else {
         err = "unsupported problem family";
         return false;

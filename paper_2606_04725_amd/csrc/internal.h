@@ -40,13 +40,14 @@ struct Symbolic {
     int max_front = 0;
     // storage offsets
     std::vector<int64_t> l_off;               // rows * width panel per supernode
-    std::vector<int64_t> u_off;               // (rows - width)^2 update block per supernode
+    std::vector<int64_t> u_off;               // (rows - width)^2 update block per supernode, in a reused pool
     std::vector<int64_t> uv_off;              // (rows - width) update vector per supernode
     std::vector<int64_t> rel_off;             // relative positions of below rows in the parent
     std::vector<int32_t> rel;
     int64_t stored_l = 0, stored_u = 0, stored_uv = 0;
     // KKT slots in factor order (sorted by permuted column, then row)
     std::vector<int32_t> k_ptr;               // per supernode
+    std::vector<int32_t> kcol_ptr;            // per permuted column
     std::vector<int32_t> k_fpos;              // position in the supernode front (r + c * (rows | 1): odd leading dimension)
     std::vector<int32_t> k_orow, k_ocol;      // original (row, col), row >= col
     std::vector<int32_t> k_wslot;             // Hessian slot or -1
@@ -56,7 +57,10 @@ struct Symbolic {
     std::vector<int32_t> jt_ptr, jt_slot, jt_row;
 };
 
+constexpr int kFilterCapacity = 256;   // largest filter_cap an instance's filter storage holds
+
 struct Device;   // device-side buffers, defined in the HIP translation unit
+struct Batch;    // instances solved together, defined in the HIP translation unit
 
 struct Problem {
     Structure st;
@@ -79,6 +83,7 @@ nmpc_status device_set_parameters(Problem& p, std::string& err);
 nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err);
 nmpc_status device_get_iterate(const Problem& p, double* y, double* s, double* om, double* be,
                                double* zl, double* zu, std::string& err);
+nmpc_status device_get_first_stage(const Problem& p, double* u1, double* x1, std::string& err);
 nmpc_status device_set_iterate(Problem& p, const double* y, const double* s, const double* om,
                                const double* be, const double* zl, const double* zu, std::string& err);
 nmpc_status device_eval(Problem& p, const double* y, const double* lam, const double* lam_d, double* f,
@@ -91,6 +96,10 @@ nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, d
                            double* gtraj, double* gup, std::string& err);
 nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err);
 void device_invalidate_adjoint(Problem& p);
+nmpc_status batch_create(const std::vector<Problem*>& ps, Batch*& out, std::string& err);
+void batch_free(Batch* b);
+int batch_size(const Batch& b);
+nmpc_status batch_solve(Batch& b, int warm, const nmpc_options& o, nmpc_result* res, std::string& err);
 bool device_present();
 
 }  // namespace nmpc

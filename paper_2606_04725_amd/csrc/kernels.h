@@ -1,25 +1,35 @@
-// Launch wrappers shared by the device translation units.  Each kernel file
-// exposes plain host functions so no kernel symbol crosses a translation unit.
+// Device-side structures and launch wrappers shared by the HIP translation
+// units.  Every kernel works on a batch of instances (a single solve is a
+// batch of one): per-instance pointers live in an InstPtrs array and the
+// per-instance interior-point decisions in a Ctl block, both in device memory,
+// so that a pass of the method needs no host decision and can be captured as a
+// graph.  Each kernel file exposes plain host launch functions so no kernel
+// symbol crosses a translation unit.
 #ifndef NMPC_KERNELS_H
 #define NMPC_KERNELS_H
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "../../include/nmpc.h"
 #include "distill_layout.h"
+#include "plate_layout.h"
 
 namespace nmpc {
 
 constexpr int kBlock = 256;          // threads per block of every vector kernel
-constexpr int kFactorBlock = 256;    // threads per supernode front
+constexpr int kFactorBlock = 256;    // threads per supernode group
 constexpr int kPanel = 8;            // pivot columns per blocked step of a front
 constexpr int kRelInts = 512;        // shared-memory ints reserved ahead of a front (relative positions)
+constexpr int kMaxQ = 12;            // reduced quantities per phase
+constexpr int kMaxSeed = 16;         // controls per stage the sensitivity seed can hold
+constexpr int kFilterCapMax = 256;   // filter entries an instance can hold
 
 struct DistillConst {
-    double dt, alpha, F, rho, xD, xB;
+    double dt, alpha, F, rho;
 };
 
-// Per-supernode read-only symbolic data on the device.
+// Per-supernode read-only symbolic data of one instance.
 struct SnView {
     const int32_t* sn_ptr;
     const int64_t* rows_ptr;
@@ -33,32 +43,221 @@ struct SnView {
     const int32_t* rel;
     const int32_t* k_ptr;
     const int32_t* k_fpos;
+    const int32_t* sched_nodes;   // supernodes in launch-schedule order
 };
 
-// Model evaluation (Section 4.1 family), one thread per (stage, variable).
-// full = true: c, d, Jacobian, Hessian of the Lagrangian (multipliers from om),
-// gradient and objective terms; full = false: c, d and objective terms only.
-void launch_eval_distill(bool full, const DistillDims& D, const DistillConst& C, const double* y,
-                         const double* x0, const double* zF, const double* uprev, const double* om,
-                         const int32_t* jptr, int mc, double* c, double* d, double* jv, double* wv,
-                         double* grad, double* fterm, hipStream_t st);
+// Phases of one Newton iteration of Algorithm 2 for one instance:
+//   A  evaluate, optimality errors, convergence test, barrier update
+//   B  condensed assembly (eqs. 14, 17), then the first factorization (eta = 0)
+//   F  factorization retried with a larger eta (inertia correction)
+//   S  solves (eqs. 22-25), remaining directions, fraction to the boundary (eq. 26)
+//   T  one trial point of the backtracking line search
+//   C  one second-order correction of the first trial point
+//   U  accepted step: update, next iteration
+enum Phase : int { kPhA = 0, kPhB = 1, kPhF = 2, kPhS = 3, kPhT = 4, kPhC = 5, kPhU = 6, kPhDone = 7 };
+// predicate values of the launch wrappers: a phase, or one of these
+constexpr int kPredAll = -1;       // every instance, whatever its phase
+constexpr int kPredFactor = 100;   // phases B and F
 
-// Numeric multifrontal Cholesky (eqs. 20-21) of a list of supernode groups:
-// workgroup b factors nodes[gptr[b] .. gptr[b+1]) in order.  lds: every front
-// fits in shared memory (bytes = lds_bytes), otherwise fronts live in gscratch.
-void launch_factor_groups(bool lds, const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes,
-                          const SnView& S, const double* kv, double eta, double* L, double* U, int* fail,
-                          double* gscratch, int64_t gstride, hipStream_t st);
-// Forward substitution (eq. 23) over groups, permutation of the rhs fused;
-// lds_bytes holds one front-length vector.
-void launch_fwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
-                       const double* L, double* uvec, const double* rhs, const int32_t* perm, double* xp,
+constexpr int kStatusRunning = -1;
+
+// Interior-point state of one instance, read and written on the device.
+struct Ctl {
+    double mu, tau, alpha, eta, eta_last, f, E0, gamma;
+    // filter line search: violation and barrier objective at the iterate, the
+    // directional derivative of phi, the minimal step, the theta bounds and the
+    // barrier value the filter belongs to
+    double theta, phi0, dphi, amin, theta_max, theta_min, filter_mu;
+    // second-order corrections: first trial step, last correction's step and violation
+    double alpha0, soc_a, soc_theta;
+    int filter_n;        // entries in the instance's filter
+    int soc_p;           // corrections done in the current line search
+    int use_soc;         // the accepted step is the correction's
+    int status;          // kStatusRunning or a final nmpc status
+    int phase;
+    int it;              // accepted Newton steps
+    int fail;            // set by the factorization: a pivot is not positive and finite
+    int trials;          // trial points of the current line search
+    int factorizations, ls_trials;
+};
+
+__host__ __device__ inline bool ctl_active(const Ctl* c, int pred) {
+    if (pred == kPredAll) return true;
+    const int ph = c->phase;
+    if (pred == kPredFactor) return ph == kPhB || ph == kPhF;
+    return ph == pred;
+}
+
+// Everything a kernel needs to know about one instance.
+struct InstPtrs {
+    int family;
+    int n, mc, md, ml, m, nx, nu, H;
+    int64_t nnzk;
+    DistillDims dd;
+    DistillConst dc;
+    PlateDims pd;
+    PlateConst pc;
+    int nsp, ntr;       // setpoint and disturbance-trajectory lengths of the family
+    // structure
+    const int32_t *jptr, *jcol, *jt_ptr, *jt_slot, *jt_row;
+    const double *lb, *ub;
+    const int32_t* perm;
+    SnView S;
+    const int32_t *k_wslot, *k_diag, *kc_ptr, *kc_a, *kc_b, *kc_r;
+    // parameters
+    const double *x0, *zF, *uprev, *setp;
+    // iterate and work vectors
+    double *y, *s, *om, *be, *zl, *zu;
+    double *c, *d, *jv, *wv, *grad, *fterm, *gtw, *sig, *rhs, *dy, *xp;
+    double *Q, *r2, *r4, *qeff, *vcomb;
+    double *ds, *dom, *dbe, *dzl, *dzu, *yt, *st;
+    // second-order correction: r1 of the step, corrected residual and its
+    // row combinations, right-hand side and directions
+    double *r1v, *r4s, *vcomb_s, *rhs_s, *dy_s, *ds_s, *dom_s, *dbe_s, *dzl_s, *dzu_s;
+    double *kv, *L, *U, *uvec;
+    double *adj_rhs, *adj_w, *adj_out, *adj_b, *adj_d, *adj_lam, *adj_qr;
+    const int32_t *wf_ptr, *wf_slot, *wf_col;   // Hessian rows, both triangles: (slot, column)
+    double* gscratch;
+    int64_t gstride;
+    const int32_t* kcol_ptr;   // KKT slots of each permuted column: [kcol_ptr[j], kcol_ptr[j + 1])
+    double* bsum;     // large-supernode backward solves: rows-below products per column
+    double* part;     // reduction partials: kMaxQ rows of this instance's blocks
+    double* filter;   // (theta, phi) pairs, kFilterCapMax of them
+    Ctl* ctl;
+};
+
+// Right-hand side and solution of the solves: 0 rhs -> dy (Newton step),
+// 1 yt -> dzl (single-solve entry point), 2 adj_rhs -> adj_w (sensitivities),
+// 3 adj_rhs -> adj_d (refinement corrections of the sensitivities),
+// 4 rhs_s -> dy_s (second-order correction).
+__host__ __device__ inline const double* solve_in(const InstPtrs& I, int which) {
+    return which == 0 ? I.rhs : (which == 1 ? I.yt : (which == 4 ? I.rhs_s : I.adj_rhs));
+}
+__host__ __device__ inline double* solve_out(const InstPtrs& I, int which) {
+    return which == 0 ? I.dy : (which == 1 ? I.dzl : (which == 2 ? I.adj_w : (which == 3 ? I.adj_d : I.dy_s)));
+}
+
+// Block -> instance map of one index space.  Instance i owns blocks
+// [bfirst[i], bfirst[i + 1]); binst[b] is the instance of block b.
+struct Space {
+    const int32_t* binst;
+    const int32_t* bfirst;
+    int blocks;
+};
+enum SpaceKind : int { kSpN = 0, kSpNML = 1, kSpM = 2, kSpK = 3, kSpMN = 4, kSpMax = 5, kNumSpaces = 6 };
+// size of an instance in each space
+__host__ __device__ inline int64_t space_size(const InstPtrs& I, int kind) {
+    switch (kind) {
+        case kSpN: return I.n;
+        case kSpNML: return (int64_t)I.n + I.ml;
+        case kSpM: return I.m;
+        case kSpK: return I.nnzk;
+        case kSpMN: return (int64_t)I.m + I.n;
+        default: return I.n > I.ml ? I.n : I.ml;
+    }
+}
+
+// Instance of the calling block and the block's index within that instance.
+__device__ inline int block_inst(const Space& sp, int& local_block) {
+    const int i = sp.binst[blockIdx.x];
+    local_block = (int)blockIdx.x - sp.bfirst[i];
+    return i;
+}
+
+// Interior-point constants the device decisions use.
+struct DevOpts {
+    double tol, mu_min, kappa_eps, kappa_mu, theta_mu, tau_min, armijo, kappa_sigma;
+    double eta_first, eta_min, eta_max, kp_first, kp, km;
+    double g_theta, g_phi, s_theta, s_phi, delta, amin_frac, theta_max_fact, theta_min_fact, soc_kappa;
+    int ls_max, max_iter, filter_cap, soc_max;
+};
+
+// One group of supernodes of one instance: sched_nodes[begin .. end), walked in
+// order by one workgroup; slot selects the workgroup's global front buffer.
+struct Group {
+    int inst, begin, end, slot;
+};
+
+// ---- model evaluation (kernels_model.hip) -------------------------------------------
+// Source of the point and multipliers: the iterate (y, om), the trial point
+// (yt; values only), or a caller-given point staged in (yt, dom).
+enum EvalSrc : int { kSrcIter = 0, kSrcTrial = 1, kSrcUser = 2 };
+// full: c, d, Jacobian values, Lagrangian Hessian values, gradient and objective
+// terms; otherwise c, d and objective terms.  Space kSpN, one lane per variable.
+void launch_eval_distill(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st);
+void launch_eval_plate(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st);
+
+// ---- interior-point vector kernels and decisions (kernels_ipm.hip) ----------------
+struct IpmSpaces {
+    Space sp[kNumSpaces];
+};
+void launch_phaseA(const InstPtrs* I, const IpmSpaces& S, int ninst, int pred, const DevOpts& o, bool decide,
+                   hipStream_t st);
+void launch_assemble(const InstPtrs* I, const IpmSpaces& S, int pred, hipStream_t st);
+void launch_decideF(const InstPtrs* I, int ninst, const DevOpts& o, hipStream_t st);
+void launch_phaseE(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, hipStream_t st);
+void launch_trial(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
+void launch_phaseT(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, hipStream_t st);
+// second-order correction, before its solve (rows, right-hand side) and after
+// it (directions and step bound, trial point), then its acceptance test
+void launch_soc_prepare(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
+void launch_soc_step(const InstPtrs* I, const IpmSpaces& S, int ninst, hipStream_t st);
+void launch_soc_decide(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, hipStream_t st);
+// update of the accepted instances, then close the pass: running count -> *running
+void launch_update(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, int* running,
+                   hipStream_t st);
+void launch_cold_start(const InstPtrs* I, const IpmSpaces& S, double bound_push, double slack_push, double mu0,
+                       bool after_eval, hipStream_t st);
+void launch_set_fail(const InstPtrs* I, int ninst, int value, hipStream_t st);
+// sensitivities: rhs = seed_obj grad f + S_u^T seed_u, and the parameter contractions
+void launch_adj_seed(const InstPtrs* I, const Space& spN, const double* seed_u, int nu, double seed_obj,
+                     hipStream_t st);
+// out = [x0 (nx) | setpoint (nsp) | trajectory (ntr) | u_prev (nu)] for instance 0
+void launch_adj_gather(const InstPtrs* I, int family, int nx, double seed_obj, hipStream_t st);
+// Refinement of w = K^{-1} b against the uncondensed system [K0 J^T; J -Q^{-1}]
+// (K0 = W + Sigma + eta I): start sets lam = Q J w; residual forms
+// adj_rhs = b - K0 w - J^T lam + J^T qr with qr = lam - Q J w; update adds the
+// correction adj_d: w += d, lam += Q J d - qr.
+void launch_adj_refine(int step, const InstPtrs* I, const IpmSpaces& S, double eta, hipStream_t st);
+
+// ---- numeric factorization and solves (kernels_linalg.hip) -------------------------
+// Multifrontal Cholesky (eqs. 20-21) of a list of groups, one workgroup per
+// group, for instances matching pred (kPredFactor during a solve) with eta
+// from the control block, or every instance with eta_force (pred kPredAll).
+// lds: fronts in shared memory (lds_bytes), else in the instance's gscratch.
+void launch_factor_groups(bool lds, int pred, double eta_force, const InstPtrs* I, const Group* g, int groups,
+                          size_t lds_bytes, hipStream_t st);
+// Forward (eq. 23, rhs permutation fused) and back (eqs. 24-25, inverse
+// permutation fused) substitution over groups, vectors chosen by which.
+void launch_fwd_groups(int pred, int which, const InstPtrs* I, const Group* g, int groups, size_t lds_bytes,
                        hipStream_t st);
-// Back substitution (eqs. 24-25) over groups, inverse permutation fused.
-void launch_bwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
-                       const double* L, double* xp, const int32_t* perm, double* out, hipStream_t st);
+void launch_bwd_groups(int pred, int which, const InstPtrs* I, const Group* g, int groups, size_t lds_bytes,
+                       hipStream_t st);
 // Raise the dynamic shared-memory limit of the front kernels (once per process).
 hipError_t linalg_configure(size_t max_lds_bytes);
+
+// ---- large supernodes (kernels_big.hip) ---------------------------------------------
+constexpr int kBigPanel = 64;   // pivot columns per panel step of a large front
+enum BigKind : int {
+    kBigInit = 1,       // task (inst, s, column, -)
+    kBigExtend = 2,     // task (inst, s, child position, child column)
+    kBigPotrf = 3,      // task (inst, s, kb, -)
+    kBigTrsm = 4,       // task (inst, s, kb, row block)
+    kBigUpdate = 5,     // task (inst, s, kb, lower-triangle tile)
+    kBigFwdDiag = 6,    // task (inst, s, -, -)
+    kBigFwdBelow = 7,   // task (inst, s, row block, -)
+    kBigBwdBelow = 8,   // task (inst, s, column block, -)
+    kBigBwdDiag = 9     // task (inst, s, -, -)
+};
+// One step for every task of a list (predicate and eta as for the groups;
+// which selects the solve vectors); lds_bytes: the diagonal solves' w values.
+void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs* I, const int4* tasks, int count,
+                size_t lds_bytes, hipStream_t st);
+hipError_t big_configure();
+int big_row_block();
+int big_tile();
+int big_solve_rows();
+int big_solve_cols();
 
 }  // namespace nmpc
 

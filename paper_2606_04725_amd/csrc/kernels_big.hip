@@ -1,0 +1,437 @@
+// Large supernodes: numeric factorization and solves (eqs. 20-25) spread over
+// many workgroups.  A front that does not fit in shared memory is assembled
+// and factored in place in its final storage: column j < w of the front is
+// column j of the supernode's L panel (m x w, leading dimension m) and the
+// trailing block is the update block handed to the parent ((m - w) x (m - w),
+// leading dimension m - w).  Every launch covers one step for all large
+// supernodes of one tree level (of every instance of a batch), described by a
+// task list; every sum is taken in a fixed order, so results do not depend on
+// how tasks are scheduled.
+//
+// Factorization of one level: zero the fronts and scatter the KKT entries
+// (+ eta on the diagonal); add the children's update blocks, one child per
+// launch; then per panel of kBigPanel pivot columns: factor the diagonal block
+// (one workgroup per front), solve the rows below it (rows split over
+// workgroups), and take the rank-kBigPanel update of the trailing lower
+// triangle on the matrix cores (64 x 64 tiles over workgroups, one
+// v_mfma_f64_16x16x4f64 per 4 columns).
+//
+// Solves: forward, one workgroup gathers the right-hand side and the children's
+// update vectors and solves with the diagonal block, then the rows below are a
+// GEMV split over workgroups; backward, the transposed GEMV with the rows below
+// is split over column blocks, then one workgroup solves with the transposed
+// diagonal block.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace nmpc {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRowBlock = 128;   // TRSM rows per workgroup
+constexpr int kTile = 64;        // trailing-update tile
+constexpr int kSolveRows = 256;  // GEMV rows per workgroup
+constexpr int kSolveCols = 64;   // transposed-GEMV columns per workgroup
+constexpr size_t kBigTrsmLds = sizeof(double) * (kBigPanel * (kBigPanel + 1) + kRowBlock * (kBigPanel + 1) + kBigPanel);
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct Front {
+    double* L;     // panel, leading dimension m
+    double* U;     // update block, leading dimension m - w
+    int f, w, m;
+};
+
+__device__ inline Front front_of(const InstPtrs& I, int s) {
+    Front F;
+    F.f = I.S.sn_ptr[s];
+    F.w = I.S.sn_ptr[s + 1] - F.f;
+    F.m = (int)(I.S.rows_ptr[s + 1] - I.S.rows_ptr[s]);
+    F.L = I.L + I.S.l_off[s];
+    F.U = I.U + I.S.u_off[s];
+    return F;
+}
+
+// address of front entry (i, j), i >= j
+__device__ inline double* at(const Front& F, int i, int j) {
+    return j < F.w ? F.L + i + (int64_t)j * F.m : F.U + (i - F.w) + (int64_t)(j - F.w) * (F.m - F.w);
+}
+
+// ---- factorization ---------------------------------------------------------------
+// task (inst, s, j, -): zero column j of the front, then scatter the KKT slots
+// of column j (j < w), eta added on the diagonal.
+__global__ void __launch_bounds__(kBlock)
+k_big_init(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, double eta_force) {
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const double eta = pred == kPredAll ? eta_force : I.ctl->eta;
+    const Front F = front_of(I, tk.y);
+    const int j = tk.z;
+    for (int i = j + threadIdx.x; i < F.m; i += blockDim.x) *at(F, i, j) = 0.0;
+    if (j >= F.w) return;
+    __syncthreads();
+    const int ld = F.m | 1;
+    const int col = F.f + j;
+    for (int t = I.kcol_ptr[col] + threadIdx.x; t < I.kcol_ptr[col + 1]; t += blockDim.x) {
+        const int r = I.S.k_fpos[t] % ld;
+        double v = I.kv[t];
+        if (r == j) v += eta;
+        F.L[r + (int64_t)j * F.m] = v;
+    }
+}
+
+// task (inst, s, child position, child column jc): add column jc of the child's
+// update block into the front through the child's relative row positions.
+__global__ void __launch_bounds__(kBlock)
+k_big_extend(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int c = I.S.child_list[I.S.child_ptr[tk.y] + tk.z];
+    const int wc = I.S.sn_ptr[c + 1] - I.S.sn_ptr[c];
+    const int nc = (int)(I.S.rows_ptr[c + 1] - I.S.rows_ptr[c]) - wc;
+    const double* Uc = I.U + I.S.u_off[c];
+    const int32_t* rel = I.S.rel + I.S.rel_off[c];
+    const int jc = tk.w;
+    const int rj = rel[jc];
+    for (int ic = jc + threadIdx.x; ic < nc; ic += blockDim.x) *at(F, rel[ic], rj) += Uc[ic + (int64_t)jc * nc];
+}
+
+// task (inst, s, kb, -): factor the diagonal block D of columns [kb, kb + pw)
+// in shared memory (right-looking, column by column) and store it.  A pivot
+// that is not positive and finite sets the instance's failure flag (eq. 12) and
+// the arithmetic continues with pivot 1.
+__global__ void __launch_bounds__(kBlock)
+k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    __shared__ double D[kBigPanel * (kBigPanel + 1)];
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int kb = tk.z;
+    const int pw = min(kBigPanel, F.w - kb);
+    constexpr int ldd = kBigPanel + 1;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < pw * pw; e += blockDim.x) {
+        const int i = e % pw, j = e / pw;
+        D[i + j * ldd] = i >= j ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int k = 0; k < pw; ++k) {
+        double piv = D[k + k * ldd];
+        if (!(piv > 0.0) || !(piv < INFINITY)) {
+            bad = true;
+            piv = 1.0;
+        }
+        const double d = sqrt(piv);
+        __syncthreads();   // every thread has read the pivot
+        if (tid == 0) D[k + k * ldd] = d;
+        for (int i = k + 1 + tid; i < pw; i += blockDim.x) D[i + k * ldd] /= d;
+        __syncthreads();
+        const int rem = pw - k - 1;
+        for (int e = tid; e < rem * rem; e += blockDim.x) {
+            const int i = k + 1 + e % rem, j = k + 1 + e / rem;
+            if (i >= j) D[i + j * ldd] = fma(-D[i + k * ldd], D[j + k * ldd], D[i + j * ldd]);
+        }
+        __syncthreads();
+    }
+    if (bad && tid == 0) I.ctl->fail = 1;
+    for (int e = tid; e < pw * pw; e += blockDim.x) {
+        const int i = e % pw, j = e / pw;
+        if (i >= j) F.L[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
+    }
+}
+
+// task (inst, s, kb, row block): solve x D^T = a for the rows
+// [kb + pw + rb kRowBlock, ...) below the factored diagonal block, one row per
+// thread, rows and D staged in shared memory.
+__global__ void __launch_bounds__(kBlock)
+k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    extern __shared__ double smem[];   // kBigTrsmLds bytes: D, X, rd
+    double* D = smem;
+    double* X = D + kBigPanel * (kBigPanel + 1);
+    double* rd = X + kRowBlock * (kBigPanel + 1);
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int kb = tk.z;
+    const int pw = min(kBigPanel, F.w - kb);
+    constexpr int ldd = kBigPanel + 1;
+    const int tid = threadIdx.x;
+    const int r0 = kb + pw + tk.w * kRowBlock;
+    const int nr = min(kRowBlock, F.m - r0);
+    if (nr <= 0) return;
+    for (int e = tid; e < pw * pw; e += blockDim.x) {
+        const int i = e % pw, j = e / pw;
+        if (i >= j) D[i + j * ldd] = F.L[(kb + i) + (int64_t)(kb + j) * F.m];
+    }
+    for (int e = tid; e < nr * pw; e += blockDim.x) {
+        const int i = e % nr, k = e / nr;
+        X[i * ldd + k] = F.L[(r0 + i) + (int64_t)(kb + k) * F.m];
+    }
+    __syncthreads();
+    for (int k = tid; k < pw; k += blockDim.x) rd[k] = 1.0 / D[k + k * ldd];
+    __syncthreads();
+    if (tid < nr) {
+        double* x = X + tid * ldd;
+        for (int k = 0; k < pw; ++k) {
+            double s = x[k];
+            for (int j = 0; j < k; ++j) s = fma(-x[j], D[k + j * ldd], s);
+            x[k] = s * rd[k];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * pw; e += blockDim.x) {
+        const int i = e % nr, k = e / nr;
+        F.L[(r0 + i) + (int64_t)(kb + k) * F.m] = X[i * ldd + k];
+    }
+}
+
+// task (inst, s, kb, tile): C -= A B^T on one 64 x 64 lower-triangle tile of the
+// trailing block (rows and columns from kb + pw), A and B the panel rows of the
+// tile's rows and columns.  Wave v computes the 32 x 32 quarter (v / 2, v % 2).
+__global__ void __launch_bounds__(kBlock)
+k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int kb = tk.z;
+    const int pw = min(kBigPanel, F.w - kb);
+    const int t0 = kb + pw;
+    int ti = (int)((sqrt(8.0 * tk.w + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tk.w) ++ti;
+    while (ti * (ti + 1) / 2 > tk.w) --ti;
+    const int tj = tk.w - ti * (ti + 1) / 2;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int i0 = t0 + kTile * ti + 32 * (wv >> 1);
+    const int j0 = t0 + kTile * tj + 32 * (wv & 1);
+    if (j0 >= F.m || i0 >= F.m || j0 > i0 + 31) return;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k4 = 0; k4 < pw; k4 += 4) {
+        const int kk = k4 + lk;
+        const double* col = F.L + (int64_t)(kb + kk) * F.m;
+        double av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int r = i0 + 16 * a + li;
+            av[a] = (kk < pw && r < F.m) ? col[r] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int c = j0 + 16 * b + li;
+            bv[b] = (kk < pw && c < F.m) ? col[c] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 16 * a + 4 * r + lk, j = j0 + 16 * b + li;
+                if (i < F.m && j <= i) *at(F, i, j) -= acc[a][b][r];
+            }
+}
+
+// ---- solves ------------------------------------------------------------------------
+// forward, task (inst, s): v = P b over the supernode's rows plus the children's
+// update vectors; x = L_dd^{-1} v[0, w) into xp; v[w, m) into the update vector.
+__global__ void __launch_bounds__(kBlock)
+k_bigfwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
+    extern __shared__ double v[];   // w values
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int s = tk.y, tid = threadIdx.x, nthr = blockDim.x;
+    const double* rhs = solve_in(I, which);
+    double* us = I.uvec + I.S.uv_off[s];
+    for (int k = tid; k < F.w; k += nthr) v[k] = rhs[I.perm[F.f + k]];
+    for (int i = tid; i < F.m - F.w; i += nthr) us[i] = 0.0;
+    __syncthreads();
+    for (int ci = I.S.child_ptr[s]; ci < I.S.child_ptr[s + 1]; ++ci) {
+        const int c = I.S.child_list[ci];
+        const int nc = (int)(I.S.uv_off[c + 1] - I.S.uv_off[c]);
+        const double* uc = I.uvec + I.S.uv_off[c];
+        const int32_t* rc = I.S.rel + I.S.rel_off[c];
+        for (int i = tid; i < nc; i += nthr) {
+            const int p = rc[i];
+            if (p < F.w) v[p] += uc[i];
+            else us[p - F.w] += uc[i];
+        }
+        __syncthreads();
+    }
+    // blocked forward substitution, 64 columns per block: wave 0 solves the
+    // block's triangle (lane j owns row b0 + j), then every thread updates the
+    // rows below the block inside the diagonal part
+    for (int b0 = 0; b0 < F.w; b0 += kWave) {
+        const int b1 = min(F.w, b0 + kWave);
+        if (tid < kWave) {
+            const int j = b0 + tid;
+            double vj = j < b1 ? v[j] : 0.0;
+            for (int k = b0; k < b1; ++k) {
+                const double xk = __shfl(vj, k - b0, kWave) / F.L[k + (int64_t)k * F.m];
+                if (j == k) vj = xk;
+                else if (j > k && j < b1) vj = fma(-F.L[j + (int64_t)k * F.m], xk, vj);
+            }
+            if (j < b1) v[j] = vj;
+        }
+        __syncthreads();
+        for (int i = b1 + tid; i < F.w; i += nthr) {
+            double acc = v[i];
+            for (int k = b0; k < b1; ++k) acc = fma(-F.L[i + (int64_t)k * F.m], v[k], acc);
+            v[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < F.w; k += nthr) I.xp[F.f + k] = v[k];
+}
+
+// forward, task (inst, s, row block): rows below the diagonal block,
+// u[i] -= L[w + i, 0:w) x.
+__global__ void __launch_bounds__(kBlock)
+k_bigfwd_below(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    extern __shared__ double x[];   // w values
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    for (int k = threadIdx.x; k < F.w; k += blockDim.x) x[k] = I.xp[F.f + k];
+    __syncthreads();
+    const int i = F.w + tk.z * kSolveRows + threadIdx.x;
+    if (i >= F.m) return;
+    double* us = I.uvec + I.S.uv_off[tk.y];
+    double acc = us[i - F.w];
+    for (int k = 0; k < F.w; ++k) acc = fma(-F.L[i + (int64_t)k * F.m], x[k], acc);
+    us[i - F.w] = acc;
+}
+
+// backward, task (inst, s, column block): bsum[f + k] = L[w:m, k]^T x(rows below)
+// for the block's columns; wave v takes columns k0 + v, k0 + v + 4, ..., lanes
+// walk the rows (a butterfly sums the lanes).
+__global__ void __launch_bounds__(kBlock)
+k_bigbwd_below(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int32_t* rows = I.S.rows + I.S.rows_ptr[tk.y];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int k0 = tk.z * kSolveCols;
+    for (int k = k0 + wv; k < min(F.w, k0 + kSolveCols); k += nw) {
+        double acc = 0.0;
+        for (int i = F.w + lane; i < F.m; i += kWave) acc = fma(F.L[i + (int64_t)k * F.m], I.xp[rows[i]], acc);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) I.bsum[F.f + k] = acc;
+    }
+}
+
+// backward, task (inst, s): v = xp[f, f + w) - bsum; solve L_dd^T x = v by
+// blocks from the last (wave 0 solves a block's triangle, then every thread
+// updates the earlier rows with the block's rows of L); writes xp and the
+// unpermuted solution.
+__global__ void __launch_bounds__(kBlock)
+k_bigbwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
+    extern __shared__ double v[];   // w values
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool has_below = F.m > F.w;
+    for (int k = tid; k < F.w; k += nthr) v[k] = I.xp[F.f + k] - (has_below ? I.bsum[F.f + k] : 0.0);
+    __syncthreads();
+    const int nblk = (F.w + kWave - 1) / kWave;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int b0 = bi * kWave, b1 = min(F.w, b0 + kWave);
+        if (tid < kWave) {
+            const int j = b0 + tid;
+            double vj = j < b1 ? v[j] : 0.0;
+            for (int k = b1 - 1; k >= b0; --k) {
+                const double xk = __shfl(vj, k - b0, kWave) / F.L[k + (int64_t)k * F.m];
+                if (j == k) vj = xk;
+                else if (j >= b0 && j < k) vj = fma(-F.L[k + (int64_t)j * F.m], xk, vj);
+            }
+            if (j < b1) v[j] = vj;
+        }
+        __syncthreads();
+        for (int c = tid; c < b0; c += nthr) {
+            double acc = v[c];
+            const double* lc = F.L + (int64_t)c * F.m;
+            for (int i = b0; i < b1; ++i) acc = fma(-lc[i], v[i], acc);
+            v[c] = acc;
+        }
+        __syncthreads();
+    }
+    double* out = solve_out(I, which);
+    for (int k = tid; k < F.w; k += nthr) {
+        I.xp[F.f + k] = v[k];
+        out[I.perm[F.f + k]] = v[k];
+    }
+}
+
+}  // namespace
+
+hipError_t big_configure() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_big_trsm), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kBigTrsmLds);
+}
+
+int big_row_block() { return kRowBlock; }
+int big_tile() { return kTile; }
+int big_solve_rows() { return kSolveRows; }
+int big_solve_cols() { return kSolveCols; }
+
+void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs* I, const int4* tasks, int count,
+                size_t lds_bytes, hipStream_t st) {
+    if (count <= 0) return;
+    switch (kind) {
+        case kBigInit:
+            hipLaunchKernelGGL(k_big_init, dim3(count), dim3(kBlock), 0, st, I, tasks, pred, eta_force);
+            break;
+        case kBigExtend:
+            hipLaunchKernelGGL(k_big_extend, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
+            break;
+        case kBigPotrf:
+            hipLaunchKernelGGL(k_big_potrf, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
+            break;
+        case kBigTrsm:
+            hipLaunchKernelGGL(k_big_trsm, dim3(count), dim3(kBlock), kBigTrsmLds, st, I, tasks, pred);
+            break;
+        case kBigUpdate:
+            hipLaunchKernelGGL(k_big_update, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
+            break;
+        case kBigFwdDiag:
+            hipLaunchKernelGGL(k_bigfwd_diag, dim3(count), dim3(kBlock), lds_bytes, st, I, tasks, pred, which);
+            break;
+        case kBigFwdBelow:
+            hipLaunchKernelGGL(k_bigfwd_below, dim3(count), dim3(kSolveRows), lds_bytes, st, I, tasks, pred);
+            break;
+        case kBigBwdBelow:
+            hipLaunchKernelGGL(k_bigbwd_below, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
+            break;
+        case kBigBwdDiag:
+            hipLaunchKernelGGL(k_bigbwd_diag, dim3(count), dim3(kBlock), lds_bytes, st, I, tasks, pred, which);
+            break;
+        default:
+            break;
+    }
+}
+
+}  // namespace nmpc

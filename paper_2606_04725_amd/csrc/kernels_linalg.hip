@@ -209,16 +209,18 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
 
 template <bool Lds>
 __global__ void __launch_bounds__(kFactorBlock)
-k_factor_groups(const int32_t* __restrict__ nodes, const int32_t* __restrict__ gptr, SnView S,
-                const double* __restrict__ kv, double eta, double* __restrict__ L, double* __restrict__ U,
-                int* __restrict__ fail, double* __restrict__ gscratch, int64_t gstride) {
+k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, int pred, double eta_force) {
     extern __shared__ double lds[];
-    // shared memory: the front (Lds) then kRelInts relative positions; global
-    // scratch holds the front otherwise
-    double* F = Lds ? lds + kRelInts / 2 : gscratch + (int64_t)blockIdx.x * gstride;
+    const Group g = groups[blockIdx.x];
+    const InstPtrs& I = Ia[g.inst];
+    if (!ctl_active(I.ctl, pred)) return;
+    const double eta = pred == kPredAll ? eta_force : I.ctl->eta;
+    // shared memory: kRelInts relative positions, then the front (Lds); the
+    // instance's global scratch holds the front otherwise
+    double* F = Lds ? lds + kRelInts / 2 : I.gscratch + (int64_t)g.slot * I.gstride;
     int32_t* rcl = reinterpret_cast<int32_t*>(lds);
-    for (int i = gptr[blockIdx.x]; i < gptr[blockIdx.x + 1]; ++i)
-        factor_one<Lds>(nodes[i], S, kv, eta, L, U, fail, F, rcl);
+    for (int i = g.begin; i < g.end; ++i)
+        factor_one<Lds>(I.S.sched_nodes[i], I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F, rcl);
 }
 
 // Triangular solves with one supernode's panel P (m x w, column-major, lower
@@ -332,11 +334,13 @@ __device__ void fwd_one(int s, const SnView& S, const double* __restrict__ L, do
 }
 
 __global__ void __launch_bounds__(kFactorBlock)
-k_fwd_groups(const int32_t* __restrict__ nodes, const int32_t* __restrict__ gptr, SnView S,
-             const double* __restrict__ L, double* __restrict__ uvec, const double* __restrict__ rhs,
-             const int32_t* __restrict__ perm, double* __restrict__ xp) {
+k_fwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, int pred, int which) {
     extern __shared__ double lds[];
-    for (int i = gptr[blockIdx.x]; i < gptr[blockIdx.x + 1]; ++i) fwd_one(nodes[i], S, L, uvec, rhs, perm, xp, lds);
+    const Group g = groups[blockIdx.x];
+    const InstPtrs& I = Ia[g.inst];
+    if (!ctl_active(I.ctl, pred)) return;
+    for (int i = g.begin; i < g.end; ++i)
+        fwd_one(I.S.sched_nodes[i], I.S, I.L, I.uvec, solve_in(I, which), I.perm, I.xp, lds);
 }
 
 // Back substitution L^T x = v for one supernode, after all its ancestors:
@@ -397,11 +401,12 @@ __device__ void bwd_one(int s, const SnView& S, const double* __restrict__ L, do
 }
 
 __global__ void __launch_bounds__(kFactorBlock)
-k_bwd_groups(const int32_t* __restrict__ nodes, const int32_t* __restrict__ gptr, SnView S,
-             const double* __restrict__ L, double* __restrict__ xp, const int32_t* __restrict__ perm,
-             double* __restrict__ out) {
+k_bwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, int pred, int which) {
     extern __shared__ double lds[];
-    for (int i = gptr[blockIdx.x]; i < gptr[blockIdx.x + 1]; ++i) bwd_one(nodes[i], S, L, xp, perm, out, lds);
+    const Group g = groups[blockIdx.x];
+    const InstPtrs& I = Ia[g.inst];
+    if (!ctl_active(I.ctl, pred)) return;
+    for (int i = g.begin; i < g.end; ++i) bwd_one(I.S.sched_nodes[i], I.S, I.L, I.xp, I.perm, solve_out(I, which), lds);
 }
 
 }  // namespace
@@ -416,31 +421,27 @@ hipError_t linalg_configure(size_t max_lds_bytes) {
     return hipSuccess;
 }
 
-void launch_factor_groups(bool lds, const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes,
-                          const SnView& S, const double* kv, double eta, double* L, double* U, int* fail,
-                          double* gscratch, int64_t gstride, hipStream_t st) {
+void launch_factor_groups(bool lds, int pred, double eta_force, const InstPtrs* I, const Group* g, int groups,
+                          size_t lds_bytes, hipStream_t st) {
     if (groups <= 0) return;
     if (lds)
-        hipLaunchKernelGGL(k_factor_groups<true>, dim3(groups), dim3(kFactorBlock), lds_bytes, st, nodes, gptr, S,
-                           kv, eta, L, U, fail, gscratch, gstride);
+        hipLaunchKernelGGL(k_factor_groups<true>, dim3(groups), dim3(kFactorBlock), lds_bytes, st, I, g, pred,
+                           eta_force);
     else
         hipLaunchKernelGGL(k_factor_groups<false>, dim3(groups), dim3(kFactorBlock), kRelInts * sizeof(int32_t), st,
-                           nodes, gptr, S, kv, eta, L, U, fail, gscratch, gstride);
+                           I, g, pred, eta_force);
 }
 
-void launch_fwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
-                       const double* L, double* uvec, const double* rhs, const int32_t* perm, double* xp,
+void launch_fwd_groups(int pred, int which, const InstPtrs* I, const Group* g, int groups, size_t lds_bytes,
                        hipStream_t st) {
     if (groups <= 0) return;
-    hipLaunchKernelGGL(k_fwd_groups, dim3(groups), dim3(kFactorBlock), lds_bytes, st, nodes, gptr, S, L, uvec, rhs,
-                       perm, xp);
+    hipLaunchKernelGGL(k_fwd_groups, dim3(groups), dim3(kFactorBlock), lds_bytes, st, I, g, pred, which);
 }
 
-void launch_bwd_groups(const int32_t* nodes, const int32_t* gptr, int groups, size_t lds_bytes, const SnView& S,
-                       const double* L, double* xp, const int32_t* perm, double* out, hipStream_t st) {
+void launch_bwd_groups(int pred, int which, const InstPtrs* I, const Group* g, int groups, size_t lds_bytes,
+                       hipStream_t st) {
     if (groups <= 0) return;
-    hipLaunchKernelGGL(k_bwd_groups, dim3(groups), dim3(kFactorBlock), lds_bytes, st, nodes, gptr, S, L, xp, perm,
-                       out);
+    hipLaunchKernelGGL(k_bwd_groups, dim3(groups), dim3(kFactorBlock), lds_bytes, st, I, g, pred, which);
 }
 
 }  // namespace nmpc

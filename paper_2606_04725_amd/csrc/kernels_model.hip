@@ -1,6 +1,7 @@
 // SIMD model evaluation (eq. 3): every (stage, variable) pair of the
 // distillation transcription is one lane; the stage-major layout makes the
-// loads of neighbouring trays and of the previous stage coalesced.
+// loads of neighbouring trays and of the previous stage coalesced.  Blocks map
+// to instances through the kSpN space, so one launch evaluates a whole batch.
 #include "kernels.h"
 
 namespace nmpc {
@@ -22,13 +23,27 @@ __device__ inline Vle vle(double a, double x) {
 
 template <bool Full>
 __global__ void __launch_bounds__(kBlock)
-k_eval_distill(DistillDims D, DistillConst C, const double* __restrict__ y, const double* __restrict__ x0,
-               const double* __restrict__ zF, const double* __restrict__ uprev, const double* __restrict__ om,
-               const int32_t* __restrict__ jptr, int mc, double* __restrict__ c, double* __restrict__ d,
-               double* __restrict__ jv, double* __restrict__ wv, double* __restrict__ grad,
-               double* __restrict__ fterm) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+k_eval_distill(const InstPtrs* __restrict__ Ia, Space sp, int src, int pred) {
+    int lb;
+    const int inst = block_inst(sp, lb);
+    const InstPtrs& I = Ia[inst];
+    if (I.family != NMPC_FAMILY_DISTILLATION || !ctl_active(I.ctl, pred)) return;
+    const DistillDims D = I.dd;
+    const DistillConst C = I.dc;
+    const int t = lb * kBlock + threadIdx.x;
     if (t >= D.H * D.ns) return;
+    const double* __restrict__ y = src == kSrcIter ? I.y : I.yt;
+    const double* __restrict__ om = src == kSrcUser ? I.dom : I.om;
+    const double* __restrict__ x0 = I.x0;
+    const double xD = I.setp[0], xB = I.setp[1];
+    double* __restrict__ c = I.c;
+    double* __restrict__ d = I.d;
+    double* __restrict__ jv = I.jv;
+    double* __restrict__ wv = I.wv;
+    double* __restrict__ grad = I.grad;
+    double* __restrict__ fterm = I.fterm;
+    const int32_t* __restrict__ jptr = I.jptr;
+    const int mc = I.mc;
     const int k = t / D.ns;
     const int j = t - k * D.ns;
     const double* Y = y + (int64_t)k * D.ns;
@@ -52,7 +67,7 @@ k_eval_distill(DistillDims D, DistillConst C, const double* __restrict__ y, cons
             const double lin = i <= fd ? R : R + F;
             const double lout = i < fd ? R : R + F;
             f = lin * xm - lout * xi + V * (vq.y - vi.y);
-            if (i == fd) f += F * zF[k];
+            if (i == fd) f += F * I.zF[k];
             dm = lin;
             dself = -lout - V * vi.yp;
             dq = V * vq.yp;
@@ -68,8 +83,8 @@ k_eval_distill(DistillDims D, DistillConst C, const double* __restrict__ y, cons
         const int row = k * D.nx + i;
         c[row] = xi - xprev - dt * f;
         double ft = 0.0;
-        if (i == 0) ft = (xi - C.xD) * (xi - C.xD);
-        if (i == D.nx - 1) ft = (xi - C.xB) * (xi - C.xB);
+        if (i == 0) ft = (xi - xD) * (xi - xD);
+        if (i == D.nx - 1) ft = (xi - xB) * (xi - xB);
         fterm[t] = ft;
         if (Full) {
             int p = jptr[row];
@@ -97,12 +112,12 @@ k_eval_distill(DistillDims D, DistillConst C, const double* __restrict__ y, cons
             wv[o + i] = wdiag;
             wv[o + D.nx + i] = wR;
             wv[o + 2 * D.nx + 1 + i] = wV;
-            grad[t] = i == 0 ? 2.0 * (xi - C.xD) : (i == D.nx - 1 ? 2.0 * (xi - C.xB) : 0.0);
+            grad[t] = i == 0 ? 2.0 * (xi - xD) : (i == D.nx - 1 ? 2.0 * (xi - xB) : 0.0);
         }
     } else {
         const bool isR = j == D.nx;
         const double u = isR ? R : V;
-        const double up = k > 0 ? y[(int64_t)(k - 1) * D.ns + j] : uprev[j - D.nx];
+        const double up = k > 0 ? y[(int64_t)(k - 1) * D.ns + j] : I.uprev[j - D.nx];
         const double mv = u - up;
         fterm[t] = C.rho * mv * mv;
         if (isR) d[2 * k] = R - V;
@@ -120,20 +135,112 @@ k_eval_distill(DistillDims D, DistillConst C, const double* __restrict__ y, cons
     }
 }
 
+// Heated plate: one lane per variable.  A temperature lane evaluates its
+// node's residual row, Jacobian row, objective term, gradient and Hessian
+// diagonal; a control lane its Hessian diagonal (sum over the nodes its ghost
+// cells border).  The flux from q into p is [(T_q - T_p) + kap (T_q^2 - T_p^2)] / h^2.
+template <bool Full>
+__global__ void __launch_bounds__(kBlock)
+k_eval_plate(const InstPtrs* __restrict__ Ia, Space sp, int src, int pred) {
+    int lb;
+    const int inst = block_inst(sp, lb);
+    const InstPtrs& I = Ia[inst];
+    if (I.family != NMPC_FAMILY_HEATED_PLATE || !ctl_active(I.ctl, pred)) return;
+    const PlateDims D = I.pd;
+    const PlateConst C = I.pc;
+    const int t = lb * kBlock + threadIdx.x;
+    if (t >= D.H * D.ns) return;
+    const double* __restrict__ y = src == kSrcIter ? I.y : I.yt;
+    const double* __restrict__ om = src == kSrcUser ? I.dom : I.om;
+    const int k = t / D.ns;
+    const int l = t - k * D.ns;
+    const double* Y = y + (int64_t)k * D.ns;
+    const double* U = Y + D.nx;
+    const double s2 = C.dt * C.inv_h2;   // dt / h^2
+    const double kap = C.kap;
+    const int G = D.G, mc = I.mc;
+    if (l < D.nx) {
+        const int p = l, b = p / G, a = p - b * G;
+        const double Tp = Y[p];
+        const double Tprev = k > 0 ? y[(int64_t)(k - 1) * D.ns + p] : I.x0[p];
+        // neighbours in the Jacobian's column order: interior then ghost (segment order)
+        double nbv[4];
+        int nn = 0;
+        if (b > 0) nbv[nn++] = Y[p - G];
+        if (a > 0) nbv[nn++] = Y[p - 1];
+        const int n_lo = nn;
+        if (a < G - 1) nbv[nn++] = Y[p + 1];
+        if (b < G - 1) nbv[nn++] = Y[p + G];
+        int sg[2];
+        int ng = 0;
+        if (b == 0) sg[ng++] = a / D.q;
+        if (a == G - 1) sg[ng++] = 4 + b / D.q;
+        if (b == G - 1) sg[ng++] = 8 + a / D.q;
+        if (a == 0) sg[ng++] = 12 + b / D.q;
+        double flux = 0.0;
+        for (int e = 0; e < nn; ++e) flux += (nbv[e] - Tp) + kap * (nbv[e] * nbv[e] - Tp * Tp);
+        for (int e = 0; e < ng; ++e) {
+            const double us = U[sg[e]];
+            flux += (us - Tp) + kap * (us * us - Tp * Tp);
+        }
+        const int row = k * D.nx + p;
+        I.c[row] = Tp - Tprev - s2 * flux;
+        const double tgt = I.setp[p];
+        I.fterm[t] = (Tp - tgt) * (Tp - tgt);
+        if (Full) {
+            I.grad[t] = 2.0 * (Tp - tgt);
+            double* jv = I.jv + I.jptr[row];
+            int q = 0;
+            if (k > 0) jv[q++] = -1.0;
+            for (int e = 0; e < n_lo; ++e) jv[q++] = -s2 * (1.0 + 2.0 * kap * nbv[e]);
+            jv[q++] = 1.0 + s2 * (nn + ng) * (1.0 + 2.0 * kap * Tp);
+            for (int e = n_lo; e < nn; ++e) jv[q++] = -s2 * (1.0 + 2.0 * kap * nbv[e]);
+            for (int e = 0; e < ng; ++e) jv[q++] = -s2 * (1.0 + 2.0 * kap * U[sg[e]]);
+            // Hessian diagonal: objective, own row (-kap T_p^2 once per neighbour),
+            // interior neighbours' rows (+kap T_p^2 each)
+            const double* lp = om + (int64_t)k * D.nx;
+            const double* ln = om + mc + (int64_t)k * D.nx;
+            double wd = 2.0 + 2.0 * kap * s2 * (nn + ng) * (lp[p] - ln[p]);
+            if (b > 0) wd -= 2.0 * kap * s2 * (lp[p - G] - ln[p - G]);
+            if (a > 0) wd -= 2.0 * kap * s2 * (lp[p - 1] - ln[p - 1]);
+            if (a < G - 1) wd -= 2.0 * kap * s2 * (lp[p + 1] - ln[p + 1]);
+            if (b < G - 1) wd -= 2.0 * kap * s2 * (lp[p + G] - ln[p + G]);
+            I.wv[t] = wd;
+        }
+    } else {
+        I.fterm[t] = 0.0;
+        if (Full) {
+            I.grad[t] = 0.0;
+            // nodes bordering the ghost cells of segment s
+            const int s = l - D.nx, e = s >> 2, j0 = (s & 3) * D.q;
+            const double* lp = om + (int64_t)k * D.nx;
+            const double* ln = om + mc + (int64_t)k * D.nx;
+            double acc = 0.0;
+            for (int j = j0; j < j0 + D.q; ++j) {
+                const int p = e == 0 ? j : (e == 1 ? j * G + (G - 1) : (e == 2 ? (G - 1) * G + j : j * G));
+                acc += lp[p] - ln[p];
+            }
+            I.wv[t] = -2.0 * kap * s2 * acc;
+        }
+    }
+}
+
 }  // namespace
 
-void launch_eval_distill(bool full, const DistillDims& D, const DistillConst& C, const double* y,
-                         const double* x0, const double* zF, const double* uprev, const double* om,
-                         const int32_t* jptr, int mc, double* c, double* d, double* jv, double* wv,
-                         double* grad, double* fterm, hipStream_t st) {
-    const int total = D.H * D.ns;
-    const int blocks = (total + kBlock - 1) / kBlock;
+void launch_eval_plate(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st) {
+    if (sp.blocks <= 0) return;
     if (full)
-        hipLaunchKernelGGL(k_eval_distill<true>, dim3(blocks), dim3(kBlock), 0, st, D, C, y, x0, zF, uprev, om,
-                           jptr, mc, c, d, jv, wv, grad, fterm);
+        hipLaunchKernelGGL(k_eval_plate<true>, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp, src, pred);
     else
-        hipLaunchKernelGGL(k_eval_distill<false>, dim3(blocks), dim3(kBlock), 0, st, D, C, y, x0, zF, uprev,
-                           om, jptr, mc, c, d, jv, wv, grad, fterm);
+        hipLaunchKernelGGL(k_eval_plate<false>, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp, src, pred);
+}
+
+void launch_eval_distill(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st) {
+    if (sp.blocks <= 0) return;
+    if (full)
+        hipLaunchKernelGGL(k_eval_distill<true>, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp, src, pred);
+    else
+        hipLaunchKernelGGL(k_eval_distill<false>, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp, src, pred);
 }
 
 }  // namespace nmpc

@@ -3,7 +3,17 @@
 //
 //  1. Fill-reducing ordering P: exact minimum degree on the elimination graph
 //     of the condensed matrix pattern (true degrees, no mass elimination, no
-//     element absorption); ties go to the smallest original index.
+//     element absorption; ties go to the smallest original index) for the
+//     distillation family; lattice nested dissection for the plate family,
+//     whose condensed matrix is a (stage x grid) lattice: a box of lattice
+//     points is cut by a slab one stage thick or two grid lines thick (the
+//     matrix couples neighbouring stages and nodes up to two steps apart),
+//     along the dimension with the fewest slab points (ties: time, row,
+//     column), the slab starting at lo + (extent - thickness) / 2; boxes of at
+//     most kNdLeaf points, or with no cuttable dimension, are leaves.  A control
+//     follows the side holding every lattice point it is coupled to, else the
+//     slab.  Order: left box, right box, slab points, slab controls; inside a
+//     leaf, points then controls, each in increasing index.
 //  2. Elimination tree parent(j) = min{i > j : L_ij != 0} and column
 //     structures struct(L_*j) = struct(K_P lower col j) united with the
 //     structures of j's children minus the children themselves.
@@ -20,6 +30,7 @@
 //     bottom-up level schedule of the supernodal tree.
 #include <algorithm>
 #include <cstdint>
+#include <map>
 #include <queue>
 #include <stdexcept>
 #include <utility>
@@ -31,6 +42,7 @@ namespace nmpc {
 namespace {
 
 constexpr int kAmalgMaxWidth = 64;
+constexpr int kNdLeaf = 64;
 constexpr int kAmalgSmall = 8;
 
 using Adj = std::vector<std::vector<int32_t>>;
@@ -74,6 +86,91 @@ std::vector<int32_t> min_degree(int n, Adj adj) {
     if ((int)order.size() != n) throw std::runtime_error("minimum degree: incomplete order");
     return order;
 }
+
+// Lattice nested dissection of a stage-major (stage x G x G grid) + controls
+// transcription (returns perm, new -> old).
+struct NdBox {
+    int lo[3], hi[3];   // stage, grid row b, grid column a
+};
+
+class LatticeNd {
+  public:
+    LatticeNd(int n, int H, int G, int ns, const std::vector<std::pair<int32_t, int32_t>>& ent)
+        : n_(n), H_(H), G_(G), ns_(ns), nx_(G * G), pts_(n) {
+        for (auto [i, j] : ent) {
+            if (i == j) continue;
+            if (is_ctrl(i) && !is_ctrl(j)) pts_[i].push_back(j);
+            if (is_ctrl(j) && !is_ctrl(i)) pts_[j].push_back(i);
+        }
+    }
+    std::vector<int32_t> order() {
+        std::vector<int32_t> ctrls;
+        for (int v = 0; v < n_; ++v)
+            if (is_ctrl(v)) ctrls.push_back(v);
+        NdBox b{{0, 0, 0}, {H_, G_, G_}};
+        out_.clear();
+        out_.reserve(n_);
+        rec(b, ctrls);
+        return out_;
+    }
+
+  private:
+    bool is_ctrl(int v) const { return v % ns_ >= nx_; }
+    bool inside(int v, const NdBox& b) const {
+        const int t = v / ns_, l = v % ns_, r = l / G_, c = l % G_;
+        return t >= b.lo[0] && t < b.hi[0] && r >= b.lo[1] && r < b.hi[1] && c >= b.lo[2] && c < b.hi[2];
+    }
+    void emit_points(const NdBox& b) {
+        for (int t = b.lo[0]; t < b.hi[0]; ++t)
+            for (int r = b.lo[1]; r < b.hi[1]; ++r)
+                for (int c = b.lo[2]; c < b.hi[2]; ++c) out_.push_back(t * ns_ + r * G_ + c);
+    }
+    void rec(const NdBox& b, std::vector<int32_t>& ctrls) {
+        const int64_t e0 = b.hi[0] - b.lo[0], e1 = b.hi[1] - b.lo[1], e2 = b.hi[2] - b.lo[2];
+        int64_t best = -1;
+        int dim = -1, th = 0;
+        auto consider = [&](int64_t size, int d, int t) {
+            if (best < 0 || size < best) {
+                best = size;
+                dim = d;
+                th = t;
+            }
+        };
+        if (e0 >= 3) consider(e1 * e2, 0, 1);
+        if (e1 >= 4) consider(2 * e0 * e2, 1, 2);
+        if (e2 >= 4) consider(2 * e0 * e1, 2, 2);
+        if (e0 * e1 * e2 <= kNdLeaf || dim < 0) {
+            emit_points(b);
+            std::sort(ctrls.begin(), ctrls.end());
+            out_.insert(out_.end(), ctrls.begin(), ctrls.end());
+            return;
+        }
+        const int lo = b.lo[dim], hi = b.hi[dim];
+        const int pos = lo + (hi - lo - th) / 2;
+        NdBox left = b, sep = b, right = b;
+        left.hi[dim] = pos;
+        sep.lo[dim] = pos;
+        sep.hi[dim] = pos + th;
+        right.lo[dim] = pos + th;
+        std::vector<int32_t> cl, cr, cs;
+        for (int32_t v : ctrls) {
+            bool inl = false, inr = false;
+            for (int32_t q : pts_[v]) {
+                inl = inl || inside(q, left);
+                inr = inr || inside(q, right);
+            }
+            (inl && !inr ? cl : (inr && !inl ? cr : cs)).push_back(v);
+        }
+        rec(left, cl);
+        rec(right, cr);
+        emit_points(sep);
+        std::sort(cs.begin(), cs.end());
+        out_.insert(out_.end(), cs.begin(), cs.end());
+    }
+    int n_, H_, G_, ns_, nx_;
+    std::vector<std::vector<int32_t>> pts_;   // lattice points coupled to each control
+    std::vector<int32_t> out_;
+};
 
 // Lower pattern of P K P^T as sorted per-column row lists (diagonal included).
 Adj permute_lower(int n, const std::vector<std::pair<int32_t, int32_t>>& ent,
@@ -164,18 +261,25 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     for (int j = 0; j < n; ++j) ent.push_back({j, j});
     std::sort(ent.begin(), ent.end());
     ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
-    // ---- 1. exact minimum degree ----------------------------------------------
-    Adj adj(n);
-    for (auto [i, j] : ent)
-        if (i != j) {
-            adj[i].push_back(j);
-            adj[j].push_back(i);
+    // ---- 1. fill-reducing ordering ----------------------------------------------
+    std::vector<int32_t> perm_md;
+    if (st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
+        LatticeNd nd(n, st.H, st.desc.grid, n / st.H, ent);
+        perm_md = nd.order();
+        if ((int)perm_md.size() != n) throw std::runtime_error("nested dissection: incomplete order");
+    } else {
+        Adj adj(n);
+        for (auto [i, j] : ent)
+            if (i != j) {
+                adj[i].push_back(j);
+                adj[j].push_back(i);
+            }
+        for (auto& a : adj) {
+            std::sort(a.begin(), a.end());
+            a.erase(std::unique(a.begin(), a.end()), a.end());
         }
-    for (auto& a : adj) {
-        std::sort(a.begin(), a.end());
-        a.erase(std::unique(a.begin(), a.end()), a.end());
+        perm_md = min_degree(n, std::move(adj));
     }
-    std::vector<int32_t> perm_md = min_degree(n, std::move(adj));
     std::vector<int32_t> iperm(n);
     for (int k = 0; k < n; ++k) iperm[perm_md[k]] = k;
     // ---- 2-3. etree, postorder, final order -----------------------------------
@@ -283,7 +387,9 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
         std::vector<int32_t> fill(sym.level_ptr.begin(), sym.level_ptr.end() - 1);
         for (int s = 0; s < nsn; ++s) sym.level_list[fill[lev[s]]++] = s;
     }
-    // storage offsets
+    // storage offsets: panels and update vectors back to back; update blocks in
+    // a pool where a block lives from its supernode's level until its parent's
+    // level has run (best-fit reuse of released blocks)
     sym.l_off.assign(nsn + 1, 0);
     sym.u_off.assign(nsn + 1, 0);
     sym.uv_off.assign(nsn + 1, 0);
@@ -292,13 +398,67 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
         const int64_t w = sym.sn_ptr[s + 1] - sym.sn_ptr[s];
         const int64_t mr = sym.sn_rows_ptr[s + 1] - sym.sn_rows_ptr[s];
         sym.l_off[s + 1] = sym.l_off[s] + mr * w;
-        sym.u_off[s + 1] = sym.u_off[s] + (mr - w) * (mr - w);
         sym.uv_off[s + 1] = sym.uv_off[s] + (mr - w);
         sym.max_front = std::max<int>(sym.max_front, (int)mr);
     }
     sym.stored_l = sym.l_off[nsn];
-    sym.stored_u = sym.u_off[nsn];
     sym.stored_uv = sym.uv_off[nsn];
+    {
+        std::vector<std::vector<int32_t>> born(sym.depth + 1), freed(sym.depth + 2);
+        for (int s = 0; s < nsn; ++s) {
+            born[lev[s]].push_back(s);
+            const int end = sym.sn_parent[s] >= 0 ? lev[sym.sn_parent[s]] : lev[s];
+            freed[end + 1].push_back(s);
+        }
+        std::map<int64_t, int64_t> holes;   // offset -> size
+        int64_t top = 0;
+        auto ublock = [&](int s) {
+            const int64_t w = sym.sn_ptr[s + 1] - sym.sn_ptr[s];
+            const int64_t mr = sym.sn_rows_ptr[s + 1] - sym.sn_rows_ptr[s];
+            return (mr - w) * (mr - w);
+        };
+        for (int L = 0; L <= sym.depth; ++L) {
+            for (int32_t s : freed[L]) {
+                const int64_t sz = ublock(s);
+                if (sz == 0) continue;
+                auto it = holes.emplace(sym.u_off[s], sz).first;
+                auto nx = std::next(it);
+                if (nx != holes.end() && it->first + it->second == nx->first) {
+                    it->second += nx->second;
+                    holes.erase(nx);
+                }
+                if (it != holes.begin()) {
+                    auto pv = std::prev(it);
+                    if (pv->first + pv->second == it->first) {
+                        pv->second += it->second;
+                        holes.erase(it);
+                    }
+                }
+            }
+            if (L == sym.depth) break;
+            for (int32_t s : born[L]) {
+                const int64_t sz = ublock(s);
+                if (sz == 0) {
+                    sym.u_off[s] = 0;
+                    continue;
+                }
+                auto best = holes.end();
+                for (auto it = holes.begin(); it != holes.end(); ++it)
+                    if (it->second >= sz && (best == holes.end() || it->second < best->second)) best = it;
+                if (best == holes.end()) {
+                    sym.u_off[s] = top;
+                    top += sz;
+                } else {
+                    sym.u_off[s] = best->first;
+                    const int64_t rest = best->second - sz, off = best->first + sz;
+                    holes.erase(best);
+                    if (rest > 0) holes.emplace(off, rest);
+                }
+            }
+        }
+        sym.stored_u = top;
+        sym.u_off[nsn] = top;
+    }
     // relative positions of each supernode's below rows inside its parent's rows
     sym.rel_off.assign(nsn + 1, 0);
     for (int s = 0; s < nsn; ++s) sym.rel_off[s + 1] = sym.rel_off[s] + (sym.uv_off[s + 1] - sym.uv_off[s]);
@@ -343,6 +503,7 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     sym.k_wslot.assign(nk, -1);
     sym.k_diag.assign(nk, -1);
     sym.k_ptr.assign(nsn + 1, 0);
+    sym.kcol_ptr.assign(n + 1, 0);
     for (int64_t t = 0; t < nk; ++t) {
         const int32_t pj = (int32_t)(keys[t] / nn), pi = (int32_t)(keys[t] % nn);
         const int s = col2sn[pj];
@@ -357,8 +518,10 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
         sym.k_ocol[t] = std::min(oi, oj);
         if (pi == pj) sym.k_diag[t] = oi;
         sym.k_ptr[s + 1]++;
+        sym.kcol_ptr[pj + 1]++;
     }
     for (int s = 0; s < nsn; ++s) sym.k_ptr[s + 1] += sym.k_ptr[s];
+    for (int j = 0; j < n; ++j) sym.kcol_ptr[j + 1] += sym.kcol_ptr[j];
     for (size_t e = 0; e < st.wrow.size(); ++e) {
         const int32_t t = slot_of(st.wrow[e], st.wcol[e]);
         if (sym.k_wslot[t] >= 0) throw std::runtime_error("duplicate Hessian slot");

@@ -61,6 +61,14 @@ def distillation_structure(N, H, dt, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0,
     return s
 
 
+def plate_structure(G, H, dt, cond_slope=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0):
+    s = nmpc_structure()
+    s.family = capi.NMPC_FAMILY_HEATED_PLATE
+    s.horizon, s.dt, s.grid = H, dt, G
+    s.t_hi, s.c_lo, s.c_hi, s.cond_slope = t_hi, c_lo, c_hi, cond_slope
+    return s
+
+
 class Problem:
     """One transcribed OCP structure: create -> analyze -> set_parameters -> solve."""
 
@@ -74,6 +82,7 @@ class Problem:
         _check(L.nmpc_sizes(h, C.byref(n), C.byref(mc), C.byref(md), C.byref(nx), C.byref(nu), C.byref(nk)))
         self.n, self.m_c, self.m_d, self.nx, self.nu = n.value, mc.value, md.value, nx.value, nu.value
         self.horizon = structure.horizon
+        self.family = structure.family
         self.nnz_k = nk.value
         self.ml = 2 * self.m_c + self.m_d
         self.analyzed = False
@@ -137,6 +146,12 @@ class Problem:
         _check(rc)
         return r
 
+    def first_stage(self):
+        """(u1, x1) of the last solution: two small device-to-host copies."""
+        u1, x1 = np.empty(self.nu), np.empty(self.nx)
+        _check(capi.lib().nmpc_get_solution(self._h, None, None, None, None, None, _dp(u1), _dp(x1)))
+        return u1, x1
+
     def solution(self):
         y, zl, zu = np.empty(self.n), np.empty(self.n), np.empty(self.n)
         lam, om_d = np.empty(self.m_c), np.empty(max(self.m_d, 1))
@@ -157,10 +172,13 @@ class Problem:
         _check(capi.lib().nmpc_set_iterate(self._h, *(_dp(v) for v in a)))
 
     # ---- sensitivities ------------------------------------------------------
-    def adjoint(self, seed_u1, seed_obj=0.0, n_setpoint=2, n_traj=None):
+    def adjoint(self, seed_u1, seed_obj=0.0):
         """Vector-Jacobian product of seed_u1 . u1* + seed_obj f* with respect to
-        the parameters; returns (status, dict of gradients)."""
-        n_traj = self.horizon if n_traj is None else n_traj
+        the parameters; returns (status, dict of gradients).  Distillation:
+        setpoint (xD*, xB*), traj zF[H]; plate: setpoint = target field, no traj."""
+        plate = self.family == capi.NMPC_FAMILY_HEATED_PLATE
+        n_setpoint = self.nx if plate else 2
+        n_traj = 0 if plate else self.horizon
         gx, gs, gt, gu = np.empty(self.nx), np.empty(n_setpoint), np.empty(n_traj), np.empty(self.nu)
         rc = _check(capi.lib().nmpc_adjoint(self._h, _dp(_f64(seed_u1, self.nu)), float(seed_obj), _dp(gx),
                                             _dp(gs), _dp(gt), _dp(gu)))
@@ -201,6 +219,36 @@ class Problem:
         kv, rhs = np.empty(self.nnz_k), np.empty(self.n)
         _check(capi.lib().nmpc_assemble(self._h, float(mu), _dp(kv), _dp(rhs)))
         return kv, rhs
+
+
+class Batch:
+    """Several analyzed problems solved together (the batched form).  The batch
+    references its problems; keep them alive while it exists."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[q._h.value for q in self.problems])
+        h = C.c_void_p()
+        _check(capi.lib().nmpc_batch_create(arr, len(self.problems), C.byref(h)))
+        self._h = h
+
+    def solve(self, warm=False, options: nmpc_options | None = None):
+        """Returns (status, [nmpc_result per instance])."""
+        res = (nmpc_result * len(self.problems))()
+        rc = _check(capi.lib().nmpc_batch_solve(self._h, 1 if warm else 0,
+                                                None if options is None else C.byref(options), res))
+        return rc, list(res)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().nmpc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_available() -> bool:

@@ -59,6 +59,26 @@ def test_symbolic_bit_exact_batch_instance_sizes():
     _symbolic_parity(big.N, big.H, big.alpha)
 
 
+@pytest.mark.parametrize("G,H", [(4, 3), (8, 4), (12, 7), (16, 10)])
+def test_plate_symbolic_bit_exact_vs_oracle(G, H):
+    from oracle.plate import PlateOCP
+    p = N.Problem(N.plate_structure(G, H, 0.01))
+    p.analyze()
+    lib = p.export_symbolic()
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
+    for key in ("perm", "parent", "colcount", "snode_ptr"):
+        assert np.array_equal(lib[key], a[key if key != "snode_ptr" else "snode_ptr"]), key
+    rp = lib["snode_rows_ptr"]
+    for s_, rows in enumerate(a["snode_rows"]):
+        assert np.array_equal(lib["snode_rows"][rp[s_]:rp[s_ + 1]], rows)
+    pat = p.patterns()
+    assert set(zip(pat["k_rows"], pat["k_cols"])) == set(zip(r, c))
+    assert set(zip(pat["j_rows"], pat["j_cols"])) == set(zip(m.jc_rows, m.jc_cols))
+    assert set(zip(pat["w_rows"], pat["w_cols"])) == set(zip(m.h_rows, m.h_cols))
+
+
 def test_create_rejects_bad_structures():
     s = N.distillation_structure(10, 20, 0.1, 2.5)
     s.horizon = 0
@@ -109,5 +129,21 @@ def test_default_options_match_oracle():
     ref = IPMOptions()
     for name in ("tol", "gamma", "mu0_cold", "mu0_warm", "mu_min", "kappa_eps", "kappa_mu", "theta_mu",
                  "tau_min", "armijo", "ls_max", "max_iter", "kappa_sigma", "eta_first", "eta_min", "eta_max",
-                 "kp_first", "kp", "km", "bound_push", "slack_push"):
+                 "kp_first", "kp", "km", "bound_push", "slack_push", "filter_gamma_theta", "filter_gamma_phi",
+                 "filter_s_theta", "filter_s_phi", "filter_delta", "alpha_min_frac", "theta_max_fact",
+                 "theta_min_fact", "filter_cap", "soc_max", "soc_kappa"):
         assert getattr(o, name) == pytest.approx(getattr(ref, name), rel=0, abs=0), name
+
+
+def test_batch_create_argument_errors():
+    from paper_2606_04725_amd import capi
+    L = capi.lib()
+    import ctypes as C
+    p = N.Problem(N.distillation_structure(4, 3, 0.1, 2.5))
+    h = C.c_void_p()
+    arr = (C.c_void_p * 2)(p._h.value, p._h.value)
+    assert L.nmpc_batch_create(arr, 2, C.byref(h)) == capi.NMPC_ERR_INVALID_ARG
+    assert L.nmpc_batch_create(arr, 0, C.byref(h)) == capi.NMPC_ERR_INVALID_ARG
+    assert L.nmpc_batch_create(arr, 1, C.byref(h)) == capi.NMPC_ERR_BAD_ORDER
+    assert L.nmpc_batch_solve(None, 0, None, None) == capi.NMPC_ERR_INVALID_ARG
+    L.nmpc_batch_destroy(None)
