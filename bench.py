@@ -105,6 +105,7 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
         for w in ws:
             q = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
             q.analyze()
+            q.autotune(reps=2)
             q.set_parameters(w.x0, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
             ps.append(q)
         return ps
@@ -275,6 +276,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     p.analyze()
     t_an = time.perf_counter() - t0
+    tuned = p.autotune(reps=3)
     p.set_parameters(w.x0, setpoint=sp, traj=w.zF(0), u_prev=w.u_prev0)
     r0 = p.solve(warm=False)
     u1, x1 = p.first_stage()
@@ -342,6 +344,7 @@ def main(argv=None):
         "iters_per_resolve": iters / a.steps,
         "first_solve_ms": t_first * 1e3,
         "analyze_ms": t_an * 1e3,
+        "autotuned_launches": tuned,
         "nonzero_status": sum(1 for s in statuses if s != 0),
         "phase_ms_per_resolve": {k: v / a.steps for k, v in phase.items()},
         "cholesky_gflops": gflops,

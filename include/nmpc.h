@@ -51,6 +51,12 @@ enum {
 
 enum { NMPC_FAMILY_DISTILLATION = 1, NMPC_FAMILY_HEATED_PLATE = 2 };
 
+/* Fill-reducing ordering of the analysis (eq. 19): nested dissection of the
+ * family's stage structure (default: one-stage separators for the
+ * distillation column, stage x grid slabs for the plate), or exact minimum
+ * degree of the condensed matrix's elimination graph. */
+enum { NMPC_ORDER_NESTED_DISSECTION = 0, NMPC_ORDER_MIN_DEGREE = 1 };
+
 /* Problem structure: everything that fixes the sparsity pattern of the
  * transcribed OCP (eq. 6) and its constant data.  Parameters that change
  * between re-solves (x0, setpoints, disturbance trajectories, last control) go
@@ -73,6 +79,7 @@ typedef struct nmpc_structure {
     double t_hi;         /* upper temperature bound */
     double c_lo, c_hi;   /* heater control bounds */
     double cond_slope;   /* conductivity slope */
+    int32_t ordering;    /* NMPC_ORDER_* */
 } nmpc_structure;
 
 /* Interior-point constants (the paper leaves them open; see the design notes).
@@ -248,6 +255,18 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
 /* Jacobian d u1* / d x0 as an nu x nx row-major host matrix (nu solves with the
  * kept factor; same conditions as nmpc_adjoint). */
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
+
+/* Autotuner of the supernode front kernels (the batched form's tile shapes):
+ * for every factor launch of the problem's schedule, time each variant of the
+ * one-workgroup front kernel (threads per workgroup 128 / 256 / 512, panel
+ * width 4 / 8) on a diagonally dominant matrix with the problem's pattern and
+ * keep the fastest; the symbolic partition is not changed.  Choices are cached
+ * per structure hash for the life of the process, so problems of equal
+ * structure are tuned once.  reps: timed repetitions per variant (>= 1);
+ * *changed (may be NULL): launches whose variant is not the default.
+ * Overwrites the held factor (sensitivities refactor).  Requires
+ * nmpc_analyze and a device; call before nmpc_batch_create for a batch. */
+nmpc_status nmpc_autotune(nmpc_problem* p, int32_t reps, int32_t* changed);
 
 /* Batches (the batched form): several analyzed problems, of any sizes, solved
  * together.  Every kernel of a pass covers all instances at once (block ->

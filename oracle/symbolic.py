@@ -4,18 +4,27 @@ Given the lower-triangular sparsity pattern of the condensed matrix K_c^l
 (diagonal included), compute
 
   * the fill-reducing permutation P (eq. 19).  The paper names minimum degree
-    and nested dissection without fixing one.  The readings taken here: exact
-    minimum degree on the elimination graph (true degrees, no mass elimination,
-    no absorption, no dense-row handling), ties broken by the smallest original
-    index, for the distillation family; lattice nested dissection (rule below)
-    for the plate family, whose condensed matrix is a three-dimensional
-    (stage x grid) lattice where minimum degree is slow and fills badly.  Either
-    is followed by a postorder of the elimination tree;
+    and nested dissection without fixing one.  The readings taken here: nested
+    dissection of the stage structure by default -- stage nested dissection for
+    the distillation family (its stages couple only to their neighbours, so one
+    stage separates the horizon: a shallow elimination tree, whose critical
+    path is what a GPU factorization waits on), lattice nested dissection
+    (rule below) for the plate family, whose condensed matrix is a
+    three-dimensional (stage x grid) lattice -- and, as an option, exact
+    minimum degree on the elimination graph (true degrees, no mass
+    elimination, no absorption, no dense-row handling), ties broken by the
+    smallest original index.  Every ordering is followed by a postorder of the
+    elimination tree;
   * the elimination tree: parent(j) = min{ i > j : L_ij != 0 };
   * the column structures of L_P: struct(L_*j) = struct(K_P lower col j) united
     with struct(L_*c) minus {c} over the children c of j (Section 3.2.3);
   * fundamental supernodes and a relaxed amalgamation (rule below), which fix
     the stored pattern S_L including any explicit zeros.
+
+Stage nested dissection.  A range [t0, t1) of stages with fewer than three
+stages is ordered as is (increasing index); otherwise stage
+pos = t0 + (t1 - t0 - 1) // 2 separates it: left range, right range, then the
+variables of stage pos in increasing index.
 
 Lattice nested dissection.  The variables of stage t are lattice points
 (t, b, a) at index t ns + b G + a (a, b < G) followed by the stage's controls.
@@ -91,6 +100,23 @@ def min_degree_order(n, adj):
             heapq.heappush(heap, (len(s), a))
         adj[v] = set()
     assert len(order) == n
+    return np.array(order, dtype=np.int64)
+
+
+def stage_nd_order(H, ns):
+    """Stage nested dissection (rule in the module docstring): perm (new -> old)."""
+    order = []
+
+    def rec(t0, t1):
+        if t1 - t0 < 3:
+            order.extend(range(t0 * ns, t1 * ns))
+            return
+        pos = t0 + (t1 - t0 - 1) // 2
+        rec(t0, pos)
+        rec(pos + 1, t1)
+        order.extend(range(pos * ns, (pos + 1) * ns))
+
+    rec(0, H)
     return np.array(order, dtype=np.int64)
 
 
@@ -268,11 +294,12 @@ def amalgamate(starts, parent, struct, n):
     return snode_ptr, rows
 
 
-def analyze(n, rows, cols, lattice=None):
+def analyze(n, rows, cols, lattice=None, stages=None):
     """Full symbolic analysis of a lower pattern (original indexing).
 
     lattice = (H, G, ns) selects the lattice nested dissection of a plate
-    transcription; otherwise exact minimum degree.  Returns a dict with perm,
+    transcription, stages = (H, ns) the stage nested dissection of a
+    stage-major transcription; otherwise exact minimum degree.  Returns a dict with perm,
     iperm, parent (column etree in final order), colcount (per column of the
     exact factor), nnz_L (exact), snode_ptr, snode_rows (row list per supernode,
     stored pattern), snode_parent.
@@ -280,6 +307,8 @@ def analyze(n, rows, cols, lattice=None):
     adj = adjacency_from_lower(n, rows, cols)
     if lattice is not None:
         perm_md = lattice_nd_order(n, adj, *lattice)
+    elif stages is not None:
+        perm_md = stage_nd_order(*stages)
     else:
         perm_md = min_degree_order(n, adj)
     iperm_md = np.empty(n, dtype=np.int64)

@@ -16,6 +16,7 @@ NMPC_MAX_ITER, NMPC_LINESEARCH_FAIL, NMPC_REG_FAIL, NMPC_NONFINITE = 1, 2, 3, 4
 NMPC_ERR_INVALID_ARG, NMPC_ERR_BAD_ORDER, NMPC_ERR_STRUCT_MISMATCH = -1, -2, -3
 NMPC_ERR_NO_DEVICE, NMPC_ERR_HIP, NMPC_ERR_OOM, NMPC_ERR_UNSUPPORTED = -4, -5, -6, -7
 NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE = 1, 2
+NMPC_ORDER_NESTED_DISSECTION, NMPC_ORDER_MIN_DEGREE = 0, 1
 
 
 class nmpc_structure(C.Structure):
@@ -24,7 +25,7 @@ class nmpc_structure(C.Structure):
                 ("move_penalty", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("u_lo", C.c_double), ("u_hi", C.c_double),
                 ("grid", C.c_int32), ("t_hi", C.c_double), ("c_lo", C.c_double), ("c_hi", C.c_double),
-                ("cond_slope", C.c_double)]
+                ("cond_slope", C.c_double), ("ordering", C.c_int32)]
 
 
 class nmpc_options(C.Structure):
@@ -77,6 +78,7 @@ SIGNATURES = {
     "nmpc_assemble": (C.c_int32, [_P, C.c_double, _D, _D]),
     "nmpc_adjoint": (C.c_int32, [_P, _D, C.c_double, _D, _D, _D, _D]),
     "nmpc_jacobian_u1_x0": (C.c_int32, [_P, _D]),
+    "nmpc_autotune": (C.c_int32, [_P, C.c_int32, _I]),
     "nmpc_batch_create": (C.c_int32, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
     "nmpc_batch_solve": (C.c_int32, [_P, C.c_int32, C.POINTER(nmpc_options), C.POINTER(nmpc_result)]),
     "nmpc_batch_destroy": (None, [_P]),

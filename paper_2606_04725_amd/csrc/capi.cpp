@@ -80,6 +80,20 @@ nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac) {
     return rc >= 0 ? rc : fail(rc, err);
 }
 
+nmpc_status nmpc_autotune(nmpc_problem* p, int32_t reps, int32_t* changed) {
+    if (!p || reps < 1) return fail(NMPC_ERR_INVALID_ARG, "autotune: NULL handle or reps < 1");
+    if (!p->impl.analyzed) return fail(NMPC_ERR_BAD_ORDER, "autotune: call nmpc_analyze first");
+    if (!p->impl.dev) return fail(NMPC_ERR_NO_DEVICE, "autotune: no HIP device");
+    return guarded([&]() -> nmpc_status {
+        std::string err;
+        int c = 0;
+        nmpc_status rc = nmpc::device_autotune(p->impl, reps, &c, err);
+        if (rc != NMPC_OK) return fail(rc, err);
+        if (changed) *changed = c;
+        return NMPC_OK;
+    });
+}
+
 int32_t nmpc_device_available(void) { return nmpc::device_present() ? 1 : 0; }
 
 void nmpc_default_options(nmpc_options* o) {

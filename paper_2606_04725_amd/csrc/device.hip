@@ -22,7 +22,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -52,6 +54,7 @@ struct LocalGroup {
 };
 struct Step {
     int kind = 0;
+    int variant = 0;                // front-kernel variant of a group factor step (autotuned)
     std::vector<LocalGroup> groups;
     std::vector<int4> tasks;        // x (the instance) is filled in by the batch
     size_t lds = 0;                 // shared memory of a large-supernode solve kernel
@@ -78,6 +81,8 @@ struct BLaunch {
     int kind, off, count;
     bool lds;
     size_t bytes;
+    int variant;
+    int step;       // index of the instances' step it comes from
 };
 
 struct Batch {
@@ -252,15 +257,23 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
         for (size_t j = 0; j < len; ++j) {
             std::vector<Group> g_lds, g_glob, g_sol;
             size_t b_lds = 0, b_sol = 0;
-            int gkind = 0;
-            std::vector<std::vector<int4>> by_kind(16);
-            std::vector<size_t> kind_lds(16, 0);
+            int gkind = 0, variant = 0, vfront = -1;
+            std::vector<std::vector<int4>> by_kind(32);
+            std::vector<size_t> kind_lds(32, 0);
             for (int i = 0; i < ni; ++i) {
                 const auto& L = members[i]->*list;
                 if (j >= L.size()) continue;
                 const Step& st = L[j];
                 if (st.kind >= kStepGroupFactor) {
                     gkind = st.kind;
+                    if (st.kind == kStepGroupFactor) {   // the variant tuned for the largest front
+                        int mx = 0;
+                        for (const auto& g : st.groups) mx = std::max<int>(mx, (int)g.lds_factor);
+                        if (mx > vfront) {
+                            vfront = mx;
+                            variant = st.variant;
+                        }
+                    }
                     int slot = 0;
                     for (const auto& g : st.groups) {
                         if (st.kind == kStepGroupFactor) {
@@ -285,15 +298,15 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
             }
             auto emit_groups = [&](const std::vector<Group>& g, int kind, bool lds, size_t bytes) {
                 if (g.empty()) return;
-                dst.push_back(BLaunch{kind, (int)gl.size(), (int)g.size(), lds, bytes});
+                dst.push_back(BLaunch{kind, (int)gl.size(), (int)g.size(), lds, bytes, variant, (int)j});
                 gl.insert(gl.end(), g.begin(), g.end());
             };
             emit_groups(g_lds, kStepGroupFactor, true, b_lds);
             emit_groups(g_glob, kStepGroupFactor, false, 0);
             emit_groups(g_sol, gkind, true, b_sol);
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < 32; ++k) {
                 if (by_kind[k].empty()) continue;
-                dst.push_back(BLaunch{k, (int)tl.size(), (int)by_kind[k].size(), false, kind_lds[k]});
+                dst.push_back(BLaunch{k, (int)tl.size(), (int)by_kind[k].size(), false, kind_lds[k], 0, (int)j});
                 tl.insert(tl.end(), by_kind[k].begin(), by_kind[k].end());
             }
         }
@@ -323,7 +336,8 @@ void eval(Batch& B, bool full, int src, int pred) {
 void run_launch(Batch& B, const BLaunch& L, int pred, double eta_force, int which) {
     switch (L.kind) {
         case kStepGroupFactor:
-            launch_factor_groups(L.lds, pred, eta_force, B.dI, B.groups + L.off, L.count, L.bytes, B.stream);
+            launch_factor_groups(L.lds, L.variant, pred, eta_force, B.dI, B.groups + L.off, L.count, L.bytes,
+                                 B.stream);
             break;
         case kStepGroupFwd:
             launch_fwd_groups(pred, which, B.dI, B.groups + L.off, L.count, L.bytes, B.stream);
@@ -569,20 +583,35 @@ nmpc_status device_init(Problem& p, std::string& err) {
         }
         int64_t wmax = 0;
         for (int32_t sn : bigs) wmax = std::max(wmax, width_of(sn));
-        for (int64_t kb = 0; kb < wmax; kb += kBigPanel) {
-            std::vector<int4> po, tr, up;
+        for (int64_t kb = 0; kb < wmax; kb += kBigOuter) {
+            for (int64_t ki = kb; ki < std::min<int64_t>(wmax, kb + kBigOuter); ki += kBigPanel) {
+                std::vector<int4> po, tr, up;
+                for (int32_t sn : bigs) {
+                    const int64_t w = width_of(sn), m = rows_of(sn);
+                    if (ki >= w) continue;
+                    const int64_t pw = std::min<int64_t>(kBigPanel, w - ki);
+                    po.push_back(int4{0, sn, (int)ki, 0});
+                    const int64_t below = m - ki - pw;
+                    for (int rb = 0; rb < ceil_div(below, RB); ++rb) tr.push_back(int4{0, sn, (int)ki, rb});
+                    const int64_t cend = std::min<int64_t>(w, kb + kBigOuter), t0 = ki + pw;
+                    if (cend > t0) {   // the rest of the outer panel
+                        const int trn = ceil_div(m - t0, TL), tcn = ceil_div(cend - t0, TL);
+                        for (int ti = 0; ti < trn; ++ti)
+                            for (int tj = 0; tj < tcn && tj <= ti; ++tj) up.push_back(int4{0, sn, (int)ki, ti * tcn + tj});
+                    }
+                }
+                push(D.fac, kBigPotrf, std::move(po));
+                push(D.fac, kBigTrsm, std::move(tr));
+                push(D.fac, kBigUpdateInner, std::move(up));
+            }
+            std::vector<int4> up;
             for (int32_t sn : bigs) {
                 const int64_t w = width_of(sn), m = rows_of(sn);
                 if (kb >= w) continue;
-                const int64_t pw = std::min<int64_t>(kBigPanel, w - kb);
-                po.push_back(int4{0, sn, (int)kb, 0});
-                const int64_t below = m - kb - pw;
-                for (int rb = 0; rb < ceil_div(below, RB); ++rb) tr.push_back(int4{0, sn, (int)kb, rb});
-                const int T = ceil_div(below, TL);
+                const int64_t kw = std::min<int64_t>(kBigOuter, w - kb);
+                const int T = ceil_div(m - kb - kw, TL);
                 for (int tt = 0; tt < T * (T + 1) / 2; ++tt) up.push_back(int4{0, sn, (int)kb, tt});
             }
-            push(D.fac, kBigPotrf, std::move(po));
-            push(D.fac, kBigTrsm, std::move(tr));
             push(D.fac, kBigUpdate, std::move(up));
         }
     };
@@ -1154,6 +1183,135 @@ nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err) {
         std::copy(out.begin(), out.begin() + st.nx, jac + (size_t)j * st.nx);
     }
     return p.dev->adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
+}
+
+}  // namespace nmpc
+
+namespace nmpc {
+
+// ---- autotuner of the front-kernel variants --------------------------------------------
+namespace {
+
+std::mutex g_tune_mutex;
+std::unordered_map<uint64_t, std::vector<int>> g_tune_cache;   // structure hash -> variant per factor step
+
+uint64_t fnv(uint64_t h, const void* data, size_t bytes) {
+    const unsigned char* c = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Hash of everything the factor launches depend on: the supernode partition,
+// the row lists and the step sequence.
+uint64_t structure_hash(const Problem& p) {
+    const Symbolic& sy = p.sym;
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, sy.sn_ptr.data(), sy.sn_ptr.size() * sizeof(int32_t));
+    h = fnv(h, sy.sn_rows_ptr.data(), sy.sn_rows_ptr.size() * sizeof(int64_t));
+    h = fnv(h, sy.sn_rows.data(), sy.sn_rows.size() * sizeof(int32_t));
+    for (const auto& stp : p.dev->fac) h = fnv(h, &stp.kind, sizeof(int));
+    return h;
+}
+
+void apply_variants(Device& D, const std::vector<int>& v) {
+    for (size_t j = 0; j < D.fac.size() && j < v.size(); ++j) D.fac[j].variant = v[j];
+    Batch& B = *D.self;
+    for (auto& L : B.fac)
+        if (L.kind == kStepGroupFactor && L.step < (int)v.size()) L.variant = v[L.step];
+    for (int k = 0; k < 2; ++k) {   // the kernels' variants are part of the captured graphs
+        if (B.exec[k]) (void)hipGraphExecDestroy(B.exec[k]);
+        if (B.graph[k]) (void)hipGraphDestroy(B.graph[k]);
+        B.exec[k] = nullptr;
+        B.graph[k] = nullptr;
+    }
+}
+
+}  // namespace
+
+nmpc_status device_autotune(Problem& p, int reps, int* changed, std::string& err) {
+    Device& D = *p.dev;
+    Batch& B = *D.self;
+    const uint64_t key = structure_hash(p);
+    std::vector<int> best(D.fac.size(), 0);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) best = it->second;
+    }
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        cached = g_tune_cache.count(key) != 0;
+    }
+    if (!cached) {
+        // a symmetric diagonally dominant matrix on the problem's pattern: every
+        // variant factors it without failure, and the timing does not depend on values
+        const Symbolic& sy = p.sym;
+        const int64_t nk = (int64_t)sy.k_orow.size();
+        std::vector<double> kv(nk, 0.0), rowsum(p.st.n, 0.0);
+        for (int64_t t = 0; t < nk; ++t) {
+            if (sy.k_diag[t] >= 0) continue;
+            const double v = 0.01 * (double)((t * 2654435761ull) % 1000 + 1) / 1000.0;
+            kv[t] = v;
+            rowsum[sy.k_orow[t]] += v;
+            rowsum[sy.k_ocol[t]] += v;
+        }
+        for (int64_t t = 0; t < nk; ++t)
+            if (sy.k_diag[t] >= 0) kv[t] = 1.0 + rowsum[sy.k_diag[t]];
+        HIP_TRY(hipMemcpy(D.hI.kv, kv.data(), nk * sizeof(double), hipMemcpyHostToDevice));
+        const size_t nl = B.fac.size();
+        std::vector<hipEvent_t> ev(nl + 1);
+        for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+        std::vector<std::vector<double>> t_step(kFactorVariants, std::vector<double>(D.fac.size(), 0.0));
+        nmpc_status rc = NMPC_OK;
+        for (int v = 0; v < kFactorVariants && rc == NMPC_OK; ++v) {
+            std::vector<double> tmin(nl, INFINITY);
+            for (int r = 0; r < reps + 1 && rc == NMPC_OK; ++r) {   // the first run warms up
+                launch_set_fail(B.dI, 1, 0, B.stream);
+                for (size_t i = 0; i < nl; ++i) {
+                    BLaunch L = B.fac[i];
+                    if (L.kind == kStepGroupFactor) L.variant = v;
+                    (void)hipEventRecord(ev[i], B.stream);
+                    run_launch(B, L, kPredAll, 0.0, 0);
+                }
+                (void)hipEventRecord(ev[nl], B.stream);
+                if (hipStreamSynchronize(B.stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+                    err = "autotune: a factor launch failed";
+                    rc = NMPC_ERR_HIP;
+                    break;
+                }
+                if (r == 0) continue;
+                for (size_t i = 0; i < nl; ++i) {
+                    float ms = 0.0f;
+                    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) tmin[i] = std::min(tmin[i], (double)ms);
+                    else (void)hipGetLastError();
+                }
+            }
+            for (size_t i = 0; i < nl; ++i)
+                if (B.fac[i].kind == kStepGroupFactor && B.fac[i].step < (int)D.fac.size())
+                    t_step[v][B.fac[i].step] += tmin[i];
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        if (rc != NMPC_OK) return rc;
+        for (size_t j = 0; j < D.fac.size(); ++j) {
+            if (D.fac[j].kind != kStepGroupFactor) continue;
+            int bv = 0;
+            for (int v = 1; v < kFactorVariants; ++v)
+                if (t_step[v][j] < t_step[bv][j]) bv = v;
+            best[j] = bv;
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache[key] = best;
+    }
+    apply_variants(D, best);
+    D.adj_ready = false;   // the tuning runs overwrote the factor
+    int nchg = 0;
+    for (size_t j = 0; j < D.fac.size(); ++j) nchg += D.fac[j].kind == kStepGroupFactor && best[j] != 0;
+    if (changed) *changed = nchg;
+    return NMPC_OK;
 }
 
 }  // namespace nmpc

@@ -169,6 +169,10 @@ static bool build_plate(const nmpc_structure& s, Structure& st, std::string& err
 bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) {
     out = Structure();
     out.desc = s;
+    if (s.ordering != NMPC_ORDER_NESTED_DISSECTION && s.ordering != NMPC_ORDER_MIN_DEGREE) {
+        err = "unknown ordering";
+        return false;
+    }
     bool ok = false;
     if (s.family == NMPC_FAMILY_DISTILLATION) {
         ok = build_distillation(s, out, err);

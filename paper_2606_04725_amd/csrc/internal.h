@@ -96,6 +96,7 @@ nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, d
                            double* gtraj, double* gup, std::string& err);
 nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err);
 void device_invalidate_adjoint(Problem& p);
+nmpc_status device_autotune(Problem& p, int reps, int* changed, std::string& err);
 nmpc_status batch_create(const std::vector<Problem*>& ps, Batch*& out, std::string& err);
 void batch_free(Batch* b);
 int batch_size(const Batch& b);

@@ -225,8 +225,11 @@ void launch_adj_refine(int step, const InstPtrs* I, const IpmSpaces& S, double e
 // group, for instances matching pred (kPredFactor during a solve) with eta
 // from the control block, or every instance with eta_force (pred kPredAll).
 // lds: fronts in shared memory (lds_bytes), else in the instance's gscratch.
-void launch_factor_groups(bool lds, int pred, double eta_force, const InstPtrs* I, const Group* g, int groups,
-                          size_t lds_bytes, hipStream_t st);
+// variant: (threads per workgroup, panel width) = 0 (256, 8), 1 (512, 8),
+// 2 (128, 8), 3 (256, 4), 4 (512, 4); the same arithmetic up to the panel width.
+constexpr int kFactorVariants = 5;
+void launch_factor_groups(bool lds, int variant, int pred, double eta_force, const InstPtrs* I, const Group* g,
+                          int groups, size_t lds_bytes, hipStream_t st);
 // Forward (eq. 23, rhs permutation fused) and back (eqs. 24-25, inverse
 // permutation fused) substitution over groups, vectors chosen by which.
 void launch_fwd_groups(int pred, int which, const InstPtrs* I, const Group* g, int groups, size_t lds_bytes,
@@ -238,6 +241,7 @@ hipError_t linalg_configure(size_t max_lds_bytes);
 
 // ---- large supernodes (kernels_big.hip) ---------------------------------------------
 constexpr int kBigPanel = 64;   // pivot columns per panel step of a large front
+constexpr int kBigOuter = 256;  // columns per outer panel (one trailing update each)
 enum BigKind : int {
     kBigInit = 1,       // task (inst, s, column, -)
     kBigExtend = 2,     // task (inst, s, child position, child column)
@@ -247,7 +251,8 @@ enum BigKind : int {
     kBigFwdDiag = 6,    // task (inst, s, -, -)
     kBigFwdBelow = 7,   // task (inst, s, row block, -)
     kBigBwdBelow = 8,   // task (inst, s, column block, -)
-    kBigBwdDiag = 9     // task (inst, s, -, -)
+    kBigBwdDiag = 9,    // task (inst, s, -, -)
+    kBigUpdateInner = 10  // task (inst, s, ki, rectangular tile)
 };
 // One step for every task of a list (predicate and eta as for the groups;
 // which selects the solve vectors); lds_bytes: the diagonal solves' w values.

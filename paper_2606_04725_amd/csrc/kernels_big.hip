@@ -10,11 +10,13 @@
 //
 // Factorization of one level: zero the fronts and scatter the KKT entries
 // (+ eta on the diagonal); add the children's update blocks, one child per
-// launch; then per panel of kBigPanel pivot columns: factor the diagonal block
-// (one workgroup per front), solve the rows below it (rows split over
-// workgroups), and take the rank-kBigPanel update of the trailing lower
-// triangle on the matrix cores (64 x 64 tiles over workgroups, one
-// v_mfma_f64_16x16x4f64 per 4 columns).
+// launch; then per outer panel of kBigOuter columns, per inner panel of
+// kBigPanel columns: factor the diagonal block (one workgroup per front), solve
+// the rows below it (rows split over workgroups), and update the rest of the
+// outer panel; then one rank-kBigOuter update of the trailing lower triangle.
+// Updates run on the matrix cores (64 x 64 tiles over workgroups, one
+// v_mfma_f64_16x16x4f64 per 4 columns); the outer panel keeps the update
+// blocks' read-modify-write traffic to one pass per kBigOuter columns.
 //
 // Solves: forward, one workgroup gathers the right-hand side and the children's
 // update vectors and solves with the diagonal block, then the rows below are a
@@ -193,45 +195,66 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
     }
 }
 
-// task (inst, s, kb, tile): C -= A B^T on one 64 x 64 lower-triangle tile of the
-// trailing block (rows and columns from kb + pw), A and B the panel rows of the
-// tile's rows and columns.  Wave v computes the 32 x 32 quarter (v / 2, v % 2).
+// Tiles of one launch are handed out XCD by XCD: workgroups are dealt to the 8
+// XCDs round-robin, so tile b % 8 * (n / 8) + b / 8 keeps neighbouring tiles
+// (which share panel rows) on one XCD and its L2.
+__device__ inline int xcd_tile(int b, int n) {
+    const int full = (n / 8) * 8;
+    return b < full ? (b % 8) * (n / 8) + b / 8 : b;
+}
+
+// C -= A B^T on one 64 x 64 tile, A and B the panel columns [k0, k0 + kw) of
+// the tile's rows and columns.  Outer (Inner = false), task (inst, s, kb, tile):
+// the lower triangle of the trailing block from kb + kw, kw = min(kBigOuter,
+// w - kb).  Inner, task (inst, s, ki, tile): the rest of ki's outer panel,
+// rows from ki + kw to m, columns [ki + kw, outer panel end), kw =
+// min(kBigPanel, w - ki).  Wave v computes the 32 x 32 quarter (v / 2, v % 2).
+template <bool Inner>
 __global__ void __launch_bounds__(kBlock)
 k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
-    const int4 tk = tasks[blockIdx.x];
+    const int4 tk = tasks[xcd_tile(blockIdx.x, gridDim.x)];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
     const Front F = front_of(I, tk.y);
-    const int kb = tk.z;
-    const int pw = min(kBigPanel, F.w - kb);
-    const int t0 = kb + pw;
-    int ti = (int)((sqrt(8.0 * tk.w + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= tk.w) ++ti;
-    while (ti * (ti + 1) / 2 > tk.w) --ti;
-    const int tj = tk.w - ti * (ti + 1) / 2;
+    const int k0 = tk.z;
+    const int kw = min(Inner ? kBigPanel : kBigOuter, F.w - k0);
+    const int t0 = k0 + kw;
+    int ti, tj;
+    if (Inner) {
+        const int cend = min(F.w, k0 - k0 % kBigOuter + kBigOuter);
+        const int tc = (cend - t0 + kTile - 1) / kTile;
+        ti = tk.w / tc;
+        tj = tk.w - ti * tc;
+    } else {
+        ti = (int)((sqrt(8.0 * tk.w + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= tk.w) ++ti;
+        while (ti * (ti + 1) / 2 > tk.w) --ti;
+        tj = tk.w - ti * (ti + 1) / 2;
+    }
+    const int cmax = Inner ? min(F.w, k0 - k0 % kBigOuter + kBigOuter) : F.m;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
     const int i0 = t0 + kTile * ti + 32 * (wv >> 1);
     const int j0 = t0 + kTile * tj + 32 * (wv & 1);
-    if (j0 >= F.m || i0 >= F.m || j0 > i0 + 31) return;
+    if (j0 >= cmax || i0 >= F.m || j0 > i0 + 31) return;
     f64x4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int k4 = 0; k4 < pw; k4 += 4) {
+    for (int k4 = 0; k4 < kw; k4 += 4) {
         const int kk = k4 + lk;
-        const double* col = F.L + (int64_t)(kb + kk) * F.m;
+        const double* col = F.L + (int64_t)(k0 + kk) * F.m;
         double av[2], bv[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int r = i0 + 16 * a + li;
-            av[a] = (kk < pw && r < F.m) ? col[r] : 0.0;
+            av[a] = (kk < kw && r < F.m) ? col[r] : 0.0;
         }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int c = j0 + 16 * b + li;
-            bv[b] = (kk < pw && c < F.m) ? col[c] : 0.0;
+            bv[b] = (kk < kw && c < cmax) ? col[c] : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -245,7 +268,7 @@ k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + 16 * a + 4 * r + lk, j = j0 + 16 * b + li;
-                if (i < F.m && j <= i) *at(F, i, j) -= acc[a][b][r];
+                if (i < F.m && j <= i && j < cmax) *at(F, i, j) -= acc[a][b][r];
             }
 }
 
@@ -415,7 +438,10 @@ void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs*
             hipLaunchKernelGGL(k_big_trsm, dim3(count), dim3(kBlock), kBigTrsmLds, st, I, tasks, pred);
             break;
         case kBigUpdate:
-            hipLaunchKernelGGL(k_big_update, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
+            hipLaunchKernelGGL(k_big_update<false>, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
+            break;
+        case kBigUpdateInner:
+            hipLaunchKernelGGL(k_big_update<true>, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
         case kBigFwdDiag:
             hipLaunchKernelGGL(k_bigfwd_diag, dim3(count), dim3(kBlock), lds_bytes, st, I, tasks, pred, which);

@@ -49,29 +49,30 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Right-looking partial Cholesky of the first w columns of an m x m front in
 // shared memory (column-major, lower triangle, leading dimension ld, odd so that
-// a stride-ld walk touches distinct banks), kPanel pivot columns at a time:
-//  1. every thread factors the kPanel x kPanel diagonal block itself, in
-//     registers (identical arithmetic in every thread, no communication);
+// a stride-ld walk touches distinct banks), P pivot columns at a time:
+//  1. every thread factors the P x P diagonal block itself, in registers
+//     (identical arithmetic in every thread, no communication);
 //  2. every row below the block solves its own row of the panel against it;
-//  3. the rest of the front takes the rank-kPanel update on the matrix cores:
+//  3. the rest of the front takes the rank-P update on the matrix cores:
 //     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
 // A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
 // numerically positive definite); the arithmetic continues with pivot 1.
+template <int P>
 __device__ void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
     const int li = lane & 15, lk = lane >> 4;
-    for (int kb = 0; kb < w; kb += kPanel) {
-        const int kw = min(kPanel, w - kb);
-        double d[kPanel][kPanel];
+    for (int kb = 0; kb < w; kb += P) {
+        const int kw = min(P, w - kb);
+        double d[P][P];
 #pragma unroll
-        for (int i = 0; i < kPanel; ++i)
+        for (int i = 0; i < P; ++i)
 #pragma unroll
-            for (int j = 0; j < kPanel; ++j)
+            for (int j = 0; j < P; ++j)
                 d[i][j] = (j <= i && i < kw) ? F[(kb + i) + (kb + j) * ld] : (i == j ? 1.0 : 0.0);
         bool bad = false;
 #pragma unroll
-        for (int k = 0; k < kPanel; ++k) {
+        for (int k = 0; k < P; ++k) {
             double piv = d[k][k];
             if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
                 bad = true;
@@ -81,36 +82,36 @@ __device__ void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
             const double inv = 1.0 / sq;
             d[k][k] = sq;
 #pragma unroll
-            for (int i = k + 1; i < kPanel; ++i) d[i][k] *= inv;
+            for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
 #pragma unroll
-            for (int j = k + 1; j < kPanel; ++j)
+            for (int j = k + 1; j < P; ++j)
 #pragma unroll
-                for (int i = j; i < kPanel; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
+                for (int i = j; i < P; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
         }
         if (bad && tid == 0) *fail = 1;
-        double rd[kPanel];
+        double rd[P];
 #pragma unroll
-        for (int k = 0; k < kPanel; ++k) rd[k] = 1.0 / d[k][k];
+        for (int k = 0; k < P; ++k) rd[k] = 1.0 / d[k][k];
         __syncthreads();   // every thread has read the diagonal block before it is overwritten
 #pragma unroll
-        for (int i = 0; i < kPanel; ++i)
+        for (int i = 0; i < P; ++i)
             if (tid == i && i < kw) {
 #pragma unroll
                 for (int j = 0; j <= i; ++j) F[(kb + i) + (kb + j) * ld] = d[i][j];
             }
         for (int r = kb + kw + tid; r < m; r += nthr) {
-            double a[kPanel];
+            double a[P];
 #pragma unroll
-            for (int j = 0; j < kPanel; ++j) a[j] = j < kw ? F[r + (kb + j) * ld] : 0.0;
+            for (int j = 0; j < P; ++j) a[j] = j < kw ? F[r + (kb + j) * ld] : 0.0;
 #pragma unroll
-            for (int k = 0; k < kPanel; ++k) {
+            for (int k = 0; k < P; ++k) {
                 double s = a[k];
 #pragma unroll
                 for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
                 a[k] = s * rd[k];
             }
 #pragma unroll
-            for (int j = 0; j < kPanel; ++j)
+            for (int j = 0; j < P; ++j)
                 if (j < kw) F[r + (kb + j) * ld] = a[j];
         }
         __syncthreads();
@@ -127,7 +128,7 @@ __device__ void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
                 const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int s4 = 0; s4 < kPanel / 4; ++s4) {
+                for (int s4 = 0; s4 < P / 4; ++s4) {
                     const int kk = 4 * s4 + lk;
                     const double* col = F + (kb + kk) * ld;
                     const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
@@ -146,7 +147,7 @@ __device__ void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
 }
 
 // One supernode: assemble the front, factor it, store the L panel and update.
-template <bool Lds>
+template <bool Lds, int P>
 __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv, double eta, double* __restrict__ L,
                            double* __restrict__ U, int* __restrict__ fail, double* F, int32_t* rcl) {
     const int f = S.sn_ptr[s];
@@ -195,7 +196,7 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
         }
         __syncthreads();
     }
-    partial_cholesky(F, m, ld, w, fail);
+    partial_cholesky<P>(F, m, ld, w, fail);
     double* Ls = L + S.l_off[s];
     for (int jc = wv; jc < w; jc += nw)
         for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = F[i + jc * ld];
@@ -207,8 +208,9 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
     __syncthreads();   // the front buffer is reused by the next supernode of the group
 }
 
-template <bool Lds>
-__global__ void __launch_bounds__(kFactorBlock)
+// Variants (threads per workgroup, panel width) the autotuner chooses from.
+template <bool Lds, int Threads, int P>
+__global__ void __launch_bounds__(Threads)
 k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, int pred, double eta_force) {
     extern __shared__ double lds[];
     const Group g = groups[blockIdx.x];
@@ -220,7 +222,7 @@ k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ group
     double* F = Lds ? lds + kRelInts / 2 : I.gscratch + (int64_t)g.slot * I.gstride;
     int32_t* rcl = reinterpret_cast<int32_t*>(lds);
     for (int i = g.begin; i < g.end; ++i)
-        factor_one<Lds>(I.S.sched_nodes[i], I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F, rcl);
+        factor_one<Lds, P>(I.S.sched_nodes[i], I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F, rcl);
 }
 
 // Triangular solves with one supernode's panel P (m x w, column-major, lower
@@ -412,7 +414,11 @@ k_bwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, 
 }  // namespace
 
 hipError_t linalg_configure(size_t max_lds_bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(k_factor_groups<true>),
+    const void* fns[] = {reinterpret_cast<const void*>(k_factor_groups<true, 256, 8>),
+                         reinterpret_cast<const void*>(k_factor_groups<true, 512, 8>),
+                         reinterpret_cast<const void*>(k_factor_groups<true, 128, 8>),
+                         reinterpret_cast<const void*>(k_factor_groups<true, 256, 4>),
+                         reinterpret_cast<const void*>(k_factor_groups<true, 512, 4>),
                          reinterpret_cast<const void*>(k_fwd_groups), reinterpret_cast<const void*>(k_bwd_groups)};
     for (const void* fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
@@ -421,15 +427,27 @@ hipError_t linalg_configure(size_t max_lds_bytes) {
     return hipSuccess;
 }
 
-void launch_factor_groups(bool lds, int pred, double eta_force, const InstPtrs* I, const Group* g, int groups,
-                          size_t lds_bytes, hipStream_t st) {
-    if (groups <= 0) return;
+template <int Threads, int P>
+void launch_variant(bool lds, int pred, double eta_force, const InstPtrs* I, const Group* g, int groups,
+                    size_t lds_bytes, hipStream_t st) {
     if (lds)
-        hipLaunchKernelGGL(k_factor_groups<true>, dim3(groups), dim3(kFactorBlock), lds_bytes, st, I, g, pred,
+        hipLaunchKernelGGL((k_factor_groups<true, Threads, P>), dim3(groups), dim3(Threads), lds_bytes, st, I, g, pred,
                            eta_force);
     else
-        hipLaunchKernelGGL(k_factor_groups<false>, dim3(groups), dim3(kFactorBlock), kRelInts * sizeof(int32_t), st,
-                           I, g, pred, eta_force);
+        hipLaunchKernelGGL((k_factor_groups<false, Threads, P>), dim3(groups), dim3(Threads),
+                           kRelInts * sizeof(int32_t), st, I, g, pred, eta_force);
+}
+
+void launch_factor_groups(bool lds, int variant, int pred, double eta_force, const InstPtrs* I, const Group* g,
+                          int groups, size_t lds_bytes, hipStream_t st) {
+    if (groups <= 0) return;
+    switch (variant) {
+        case 1: launch_variant<512, 8>(lds, pred, eta_force, I, g, groups, lds_bytes, st); break;
+        case 2: launch_variant<128, 8>(lds, pred, eta_force, I, g, groups, lds_bytes, st); break;
+        case 3: launch_variant<256, 4>(lds, pred, eta_force, I, g, groups, lds_bytes, st); break;
+        case 4: launch_variant<512, 4>(lds, pred, eta_force, I, g, groups, lds_bytes, st); break;
+        default: launch_variant<256, 8>(lds, pred, eta_force, I, g, groups, lds_bytes, st); break;
+    }
 }
 
 void launch_fwd_groups(int pred, int which, const InstPtrs* I, const Group* g, int groups, size_t lds_bytes,

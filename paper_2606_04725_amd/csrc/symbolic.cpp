@@ -1,11 +1,14 @@
 // SymCholesky on the host (Section 3.2.3, eqs. 18-19, Fig. 1), computed once
 // per problem structure and reused by every numeric factorization.
 //
-//  1. Fill-reducing ordering P: exact minimum degree on the elimination graph
-//     of the condensed matrix pattern (true degrees, no mass elimination, no
-//     element absorption; ties go to the smallest original index) for the
-//     distillation family; lattice nested dissection for the plate family,
-//     whose condensed matrix is a (stage x grid) lattice: a box of lattice
+//  1. Fill-reducing ordering P (NMPC_ORDER_* of the structure).  Minimum
+//     degree: exact, on the elimination graph of the condensed matrix pattern
+//     (true degrees, no mass elimination, no element absorption; ties go to the
+//     smallest original index).  Nested dissection, the default: for the
+//     distillation family by stages (a range of fewer than three stages keeps
+//     its order, otherwise its middle stage t0 + (t1 - t0 - 1) / 2 separates
+//     it: left range, right range, separator stage); for the plate family on
+//     the (stage x grid) lattice of its condensed matrix: a box of lattice
 //     points is cut by a slab one stage thick or two grid lines thick (the
 //     matrix couples neighbouring stages and nodes up to two steps apart),
 //     along the dimension with the fewest slab points (ties: time, row,
@@ -172,6 +175,36 @@ class LatticeNd {
     std::vector<int32_t> out_;
 };
 
+// Stage nested dissection of a stage-major transcription (perm, new -> old).
+std::vector<int32_t> stage_nd(int H, int ns) {
+    std::vector<int32_t> out;
+    out.reserve((size_t)H * ns);
+    struct Frame {   // a range of stages and how far its order has got
+        int t0, t1, state;
+    };
+    std::vector<Frame> st{{0, H, 0}};
+    while (!st.empty()) {
+        Frame& f = st.back();
+        if (f.t1 - f.t0 < 3) {
+            for (int v = f.t0 * ns; v < f.t1 * ns; ++v) out.push_back(v);
+            st.pop_back();
+            continue;
+        }
+        const int pos = f.t0 + (f.t1 - f.t0 - 1) / 2;
+        if (f.state == 0) {
+            f.state = 1;
+            st.push_back({f.t0, pos, 0});
+        } else if (f.state == 1) {
+            f.state = 2;
+            st.push_back({pos + 1, f.t1, 0});
+        } else {
+            for (int v = pos * ns; v < (pos + 1) * ns; ++v) out.push_back(v);
+            st.pop_back();
+        }
+    }
+    return out;
+}
+
 // Lower pattern of P K P^T as sorted per-column row lists (diagonal included).
 Adj permute_lower(int n, const std::vector<std::pair<int32_t, int32_t>>& ent,
                   const std::vector<int32_t>& iperm) {
@@ -263,7 +296,9 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
     // ---- 1. fill-reducing ordering ----------------------------------------------
     std::vector<int32_t> perm_md;
-    if (st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
+    if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_DISTILLATION) {
+        perm_md = stage_nd(st.H, n / st.H);
+    } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
         LatticeNd nd(n, st.H, st.desc.grid, n / st.H, ent);
         perm_md = nd.order();
         if ((int)perm_md.size() != n) throw std::runtime_error("nested dissection: incomplete order");

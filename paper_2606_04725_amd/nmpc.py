@@ -53,16 +53,20 @@ def default_options(**over) -> nmpc_options:
     return o
 
 
-def distillation_structure(N, H, dt, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0):
+def distillation_structure(N, H, dt, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0,
+                           ordering=capi.NMPC_ORDER_NESTED_DISSECTION):
     s = nmpc_structure()
+    s.ordering = ordering
     s.family = capi.NMPC_FAMILY_DISTILLATION
     s.horizon, s.dt, s.n_trays, s.alpha, s.feed_flow = H, dt, N, alpha, F
     s.move_penalty, s.x_lo, s.x_hi, s.u_lo, s.u_hi = rho, x_lo, x_hi, u_lo, u_hi
     return s
 
 
-def plate_structure(G, H, dt, cond_slope=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0):
+def plate_structure(G, H, dt, cond_slope=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0,
+                    ordering=capi.NMPC_ORDER_NESTED_DISSECTION):
     s = nmpc_structure()
+    s.ordering = ordering
     s.family = capi.NMPC_FAMILY_HEATED_PLATE
     s.horizon, s.dt, s.grid = H, dt, G
     s.t_hi, s.c_lo, s.c_hi, s.cond_slope = t_hi, c_lo, c_hi, cond_slope
@@ -170,6 +174,13 @@ class Problem:
         n, ml = self.n, self.ml
         a = [_f64(y, n), _f64(s, ml), _f64(omega, ml), _f64(beta, ml), _f64(zL, n), _f64(zU, n)]
         _check(capi.lib().nmpc_set_iterate(self._h, *(_dp(v) for v in a)))
+
+    def autotune(self, reps=3):
+        """Choose the front-kernel variant of every factor launch by timing;
+        returns the number of launches that left the default variant."""
+        ch = C.c_int32()
+        _check(capi.lib().nmpc_autotune(self._h, int(reps), C.byref(ch)))
+        return ch.value
 
     # ---- sensitivities ------------------------------------------------------
     def adjoint(self, seed_u1, seed_obj=0.0):

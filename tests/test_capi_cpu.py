@@ -20,13 +20,14 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(capi.SIGNATURES)
 
 
-def _symbolic_parity(Ntr, H, alpha=2.5):
-    p = N.Problem(N.distillation_structure(Ntr, H, 0.1, alpha))
+def _symbolic_parity(Ntr, H, alpha=2.5, ordering=N.capi.NMPC_ORDER_NESTED_DISSECTION):
+    p = N.Problem(N.distillation_structure(Ntr, H, 0.1, alpha, ordering=ordering))
     p.analyze()
     lib = p.export_symbolic()
     m = DistillationOCP(Ntr, H, 0.1, alpha)
     r, c = S.kkt_lower_pattern(m)
-    a = S.analyze(m.n, r, c)
+    nd = ordering == N.capi.NMPC_ORDER_NESTED_DISSECTION
+    a = S.analyze(m.n, r, c, stages=(m.H, m.ns) if nd else None)
     assert np.array_equal(lib["perm"], a["perm"])
     assert np.array_equal(lib["parent"], a["parent"])
     assert np.array_equal(lib["colcount"], a["colcount"])
@@ -49,6 +50,11 @@ def _symbolic_parity(Ntr, H, alpha=2.5):
 @pytest.mark.parametrize("Ntr,H", [(2, 1), (3, 4), (10, 20), (7, 13), (40, 100)])
 def test_symbolic_bit_exact_vs_oracle(Ntr, H):
     _symbolic_parity(Ntr, H)
+
+
+@pytest.mark.parametrize("Ntr,H", [(2, 1), (3, 4), (10, 20), (40, 100)])
+def test_symbolic_bit_exact_vs_oracle_min_degree(Ntr, H):
+    _symbolic_parity(Ntr, H, ordering=N.capi.NMPC_ORDER_MIN_DEGREE)
 
 
 @pytest.mark.slow

@@ -146,3 +146,29 @@ def test_full_batch_sampled():
     assert rc == 0
     assert max(r.iters for r in res) < 60
     b.close()
+
+
+def test_autotuned_solve_keeps_parity():
+    """The autotuner only picks among variants of the front kernel: the solve
+    after tuning still matches the oracle, and a second problem of the same
+    structure takes the cached choice."""
+    w = distillation_workload("small", 7, N=25, H=33, n_resolves=1)
+    _note("autotune N=25 H=33")
+    p = _problem(w)
+    p.autotune(reps=2)
+    r = p.solve(warm=False)
+    assert r.status == 0
+    m = DistillationOCP.from_workload(w)
+    m.set_parameters(x0=w.x0, zF=w.zF(0), u_prev=w.u_prev0)
+    ipm = LiftedIPM(m)
+    ref = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
+    assert ref.status == 0 and r.iters == ref.iters
+    sol = p.solution()
+    assert np.max(np.abs(sol["y"] - ref.state.y)) / max(1.0, np.max(np.abs(ref.state.y))) <= 1e-6
+    q = _problem(w)
+    import time
+    t = time.perf_counter()
+    q.autotune(reps=2)
+    assert time.perf_counter() - t < 0.5
+    r2 = q.solve(warm=False)
+    assert r2.iters == r.iters and np.array_equal(q.solution()["y"], sol["y"])

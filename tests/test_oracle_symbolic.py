@@ -224,3 +224,27 @@ def test_lattice_nested_dissection_top_separator():
     right = set(range(4 * m.ns, m.n))
     for i, j in zip(r, c):
         assert not ((i in left and j in right) or (i in right and j in left))
+
+
+@pytest.mark.parametrize("N_,H", [(4, 7), (6, 12)])
+def test_stage_nested_dissection(N_, H):
+    """Stage nested dissection of the column: a permutation whose factor pattern
+    equals dense elimination in that order; the middle stage separates the two
+    halves (no matrix entry between them), and the elimination tree is shallow
+    (its depth in columns is at most the separator stages times the stage size
+    plus a leaf range)."""
+    from oracle.distillation import DistillationOCP
+    m = DistillationOCP(N_, H, 0.1, 2.5)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c, stages=(m.H, m.ns))
+    n, iperm = m.n, a["iperm"]
+    assert sorted(a["perm"]) == list(range(n))
+    M, par_dense = _dense_symbolic(n, [iperm[i] for i in r], [iperm[j] for j in c])
+    assert np.array_equal(a["parent"], par_dense)
+    assert a["nnz_L"] == int(M.sum())
+    order = S.stage_nd_order(H, m.ns)
+    mid = (H - 1) // 2
+    assert list(order[-m.ns:]) == list(range(mid * m.ns, (mid + 1) * m.ns))
+    for i, j in zip(r, c):
+        ti, tj = i // m.ns, j // m.ns
+        assert not ((ti < mid < tj) or (tj < mid < ti))
