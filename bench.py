@@ -118,8 +118,9 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
     t_an = time.perf_counter() - t0
     b = N.Batch(pb)
     t0 = time.perf_counter()
-    rc, _ = b.solve(warm=False, options=opts)
+    rc, res0 = b.solve(warm=False, options=opts)
     t_cold = time.perf_counter() - t0
+    cold_bad = [i for i, r in enumerate(res0) if r.status != 0]
     fs = [q.first_stage() for q in pb]
     lat_b, it_b, st_b = [], 0, []
     t_begin = time.perf_counter()
@@ -155,6 +156,7 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
     return {"workload": f"{count} distillation instances, trays U{{20..60}}, horizons U{{40..120}}, alpha U(2,3), "
                         f"seeds {base_seed}..{base_seed + count - 1}, {rounds} warm re-solve rounds",
             "n_total": n_tot, "analyze_s": t_an, "cold_batch_ms": t_cold * 1e3,
+            "cold_iters_max": max(r.iters for r in res0), "cold_nonzero_status": cold_bad,
             "resolves_per_s": count * rounds / el_b, "iters_per_s": it_b / el_b,
             "p50_instance_ms": _percentile(lat_b, 50), "p99_instance_ms": _percentile(lat_b, 99),
             "nonzero_status": sum(1 for s_ in st_b if s_ != 0),

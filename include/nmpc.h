@@ -109,6 +109,12 @@ typedef struct nmpc_options {
      * each must reduce the violation by the factor soc_kappa (0 disables them) */
     int32_t soc_max;
     double soc_kappa;
+    /* 1 (default): when the filter rejects every trial point down to the minimal
+     * step, backtrack once more from the fraction-to-boundary step on the l1
+     * merit phi + nu theta (Armijo; nu >= max |omega + d_omega| + 1, never
+     * decreased within a solve), empty the filter on acceptance; 0: end the
+     * solve with NMPC_LINESEARCH_FAIL there */
+    int32_t merit_fallback;
     int32_t timing;      /* 1: record HIP events around each phase (device times in nmpc_result) */
     int32_t graph;       /* 1 (default): capture one pass of the method as a HIP graph and replay it;
                             0: launch every kernel of every pass from the host */

@@ -87,6 +87,7 @@ class IPMOptions:
     filter_cap: int = 128
     soc_max: int = 4            # second-order corrections per line search
     soc_kappa: float = 0.99     # each correction must reduce theta by this factor
+    merit_fallback: int = 1     # l1-merit backtracking when the filter rejects every trial
 
 
 STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "regularization_fail",
@@ -260,6 +261,7 @@ class LiftedIPM:
         theta_max = theta_min = None
         filt = []            # (theta, phi) pairs, insertion order
         filt_mu = None
+        nu = 1.0
         trace = []
         status = 1
         it = 0
@@ -393,12 +395,28 @@ class LiftedIPM:
                     if accepted:
                         break
                 alpha *= 0.5
+            merit = False
+            if not accepted and o.merit_fallback:
+                nu = max(nu, float(np.max(np.abs(st.omega + dom))) + 1.0)
+                m0 = phi0 + nu * theta
+                Dm = Dphi - nu * theta
+                alpha = min(amax, adu)
+                for _t in range(o.ls_max):
+                    trials += 1
+                    yt = st.y + alpha * dy
+                    stt = st.s + alpha * ds
+                    mt = self.barrier_objective(yt, stt, mu, nlp.f(yt)) + nu * self.violation(yt, stt)
+                    if np.isfinite(mt) and mt <= m0 + o.armijo * alpha * Dm + 10.0 * EPS * abs(m0):
+                        accepted = merit = True
+                        filt = []
+                        break
+                    alpha *= 0.5
             if soc_dir is not None:
                 dy, ds, dom, dbe, dzL, dzU = soc_dir
             if record:
                 trace.append(dict(it=it, mu=mu, eta=eta, amax=amax, alpha=alpha, adu=adu,
                                   E0=E0, Emu=Emu, trials=trials, phi=phi0, Dphi=Dphi, theta=theta,
-                                  filter=len(filt), dy_norm=float(np.max(np.abs(dy)))))
+                                  filter=len(filt), merit=merit, dy_norm=float(np.max(np.abs(dy)))))
             if not accepted:
                 status = 2
                 break

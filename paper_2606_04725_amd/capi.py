@@ -40,7 +40,7 @@ class nmpc_options(C.Structure):
                 ("filter_s_theta", C.c_double), ("filter_s_phi", C.c_double), ("filter_delta", C.c_double),
                 ("alpha_min_frac", C.c_double), ("theta_max_fact", C.c_double), ("theta_min_fact", C.c_double),
                 ("filter_cap", C.c_int32), ("soc_max", C.c_int32), ("soc_kappa", C.c_double),
-                ("timing", C.c_int32), ("graph", C.c_int32)]
+                ("merit_fallback", C.c_int32), ("timing", C.c_int32), ("graph", C.c_int32)]
 
 
 class nmpc_result(C.Structure):

@@ -41,7 +41,8 @@ bool resolve_options(const nmpc_options* opts, nmpc_options& o) {
     return o.tol > 0 && o.gamma > 0 && o.mu_min > 0 && o.max_iter >= 0 && o.ls_max >= 1 && o.mu0_cold > 0 &&
            o.mu0_warm > 0 && o.eta_first > 0 && o.kp_first > 1 && o.kp > 1 && o.eta_max > 0 && o.filter_cap >= 1 &&
            o.filter_cap <= nmpc::kFilterCapacity && o.alpha_min_frac > 0 &&
-           o.soc_max >= 0 && o.soc_kappa > 0;
+           o.soc_max >= 0 && o.soc_kappa > 0 &&
+           (o.merit_fallback == 0 || o.merit_fallback == 1);
 }
 
 template <class F>
@@ -130,6 +131,7 @@ void nmpc_default_options(nmpc_options* o) {
     o->filter_cap = 128;
     o->soc_max = 4;
     o->soc_kappa = 0.99;
+    o->merit_fallback = 1;
     o->timing = 0;
     o->graph = 1;
 }

@@ -171,6 +171,7 @@ DevOpts dev_opts(const nmpc_options& o) {
     d.max_iter = o.max_iter;
     d.filter_cap = o.filter_cap;
     d.soc_max = o.soc_max;
+    d.merit_fallback = o.merit_fallback;
     return d;
 }
 
@@ -827,6 +828,7 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
         c.tau = std::max(o.tau_min, 1.0 - c.mu);
         c.E0 = INFINITY;
         c.filter_mu = std::nan("");
+        c.nu = 1.0;
         c.gamma = o.gamma;
         c.status = kStatusRunning;
         c.phase = kPhA;
@@ -866,7 +868,7 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
     }
     // every pass moves each running instance by one iteration, factorization
     // attempt or trial point; the method bounds all three
-    const long max_passes = (long)(o.max_iter + 1) * (o.ls_max + 64) + 8;
+    const long max_passes = (long)(o.max_iter + 1) * (2L * o.ls_max + o.soc_max + 64) + 8;
     long passes = 0;
     int timing_lost = 0;
     while (true) {

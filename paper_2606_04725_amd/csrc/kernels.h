@@ -70,6 +70,11 @@ struct Ctl {
     double theta, phi0, dphi, amin, theta_max, theta_min, filter_mu;
     // second-order corrections: first trial step, last correction's step and violation
     double alpha0, soc_a, soc_theta;
+    // l1-merit fallback: first step of the search, max |omega + d_omega| of the
+    // direction, the penalty (kept over the solve)
+    double amax0, om_max, nu;
+    int ls_merit;        // the current search runs on the l1 merit
+    int merit_trials;    // trial points of the merit search
     int filter_n;        // entries in the instance's filter
     int soc_p;           // corrections done in the current line search
     int use_soc;         // the accepted step is the correction's
@@ -169,7 +174,7 @@ struct DevOpts {
     double tol, mu_min, kappa_eps, kappa_mu, theta_mu, tau_min, armijo, kappa_sigma;
     double eta_first, eta_min, eta_max, kp_first, kp, km;
     double g_theta, g_phi, s_theta, s_phi, delta, amin_frac, theta_max_fact, theta_min_fact, soc_kappa;
-    int ls_max, max_iter, filter_cap, soc_max;
+    int ls_max, max_iter, filter_cap, soc_max, merit_fallback;
 };
 
 // One group of supernodes of one instance: sched_nodes[begin .. end), walked in

@@ -291,8 +291,23 @@ __global__ void k_decideF(const InstPtrs* __restrict__ Ia, int ninst, DevOpts o)
 
 __device__ inline double ftb(double v, double dv, double tau) { return dv < 0.0 ? (-tau * v) / dv : INFINITY; }
 
+// The filter search found no acceptable point: restart the backtracking from
+// the fraction-to-boundary step on the l1 merit phi + nu theta, or stop.
+__device__ void filter_search_failed(Ctl* c, const DevOpts& o) {
+    if (o.merit_fallback && o.ls_max > 0) {
+        c->ls_merit = 1;
+        c->merit_trials = 0;
+        c->nu = fmax(c->nu, c->om_max + 1.0);
+        c->alpha = c->amax0;
+        c->phase = kPhT;
+    } else {
+        c->status = NMPC_LINESEARCH_FAIL;
+        c->phase = kPhDone;
+    }
+}
+
 // ---- phase S: remaining directions and step / merit ingredients ------------------
-// q: 0 alpha_primal(min) 1 alpha_dual(min) 2 (unused, max) 3 grad.dy 4 sum ds/s
+// q: 0 alpha_primal(min) 1 alpha_dual(min) 2 max |omega + d_omega| 3 grad.dy 4 sum ds/s
 //    5 sum dy/gL 6 sum dy/gU 7 |r4|_1 8 sum ln s 9 sum ln gL 10 sum ln gU
 __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ Ia, Space sp) {
     __shared__ double sh[kMaxQ * kWaves];
@@ -319,6 +334,7 @@ __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ 
             I.dom[l] = doml;
             I.dbe[l] = dbel;
             q[0] = fmin(q[0], ftb(sl, dsl, tau));
+            q[2] = fmax(q[2], fabs(I.om[l] + doml));
             q[1] = fmin(q[1], ftb(I.be[l], dbel, tau));
             q[4] += dsl / sl;
             q[7] += fabs(I.r4[l]);
@@ -396,11 +412,13 @@ __global__ void __launch_bounds__(kBlock) k_decideE(const InstPtrs* __restrict__
     c->alpha = alpha;
     c->trials = 0;
     c->use_soc = 0;
+    c->amax0 = alpha;
+    c->om_max = E[2];
+    c->ls_merit = 0;
     if (alpha >= amin && o.ls_max > 0) {
         c->phase = kPhT;
     } else {
-        c->status = NMPC_LINESEARCH_FAIL;
-        c->phase = kPhDone;
+        filter_search_failed(c, o);
     }
 }
 
@@ -486,8 +504,10 @@ __device__ bool filter_accepts(const InstPtrs& I, Ctl* c, const DevOpts& o, doub
 }
 
 // Trial point verdict; a rejected first trial that does not reduce theta goes
-// to the second-order corrections, otherwise alpha is halved, and the search
-// stops when alpha falls below the minimal step or the trial budget is spent.
+// to the second-order corrections, otherwise alpha is halved, and the filter
+// search ends when alpha falls below the minimal step or the trial budget is
+// spent.  In the merit search (after a failed filter search) the test is
+// Armijo on phi + nu theta, with its own budget of trials.
 __global__ void __launch_bounds__(kBlock) k_decideT(const InstPtrs* __restrict__ Ia, Space sp, DevOpts o) {
     __shared__ double sh[kMaxQ * kWaves];
     __shared__ double T[kMaxQ];
@@ -502,6 +522,23 @@ __global__ void __launch_bounds__(kBlock) k_decideT(const InstPtrs* __restrict__
     c->trials += 1;
     const double pht = T[0] - mu * T[1] - mu * T[2] - mu * T[3];
     const double tht = T[4];
+    if (c->ls_merit) {
+        const double eps = 2.220446049250313e-16;
+        const double m0 = c->phi0 + c->nu * c->theta, dm = c->dphi - c->nu * c->theta;
+        const double mt = pht + c->nu * tht;
+        c->merit_trials += 1;
+        if (T[5] == 0.0 && isfinite(mt) && mt <= m0 + o.armijo * alpha * dm + 10.0 * eps * fabs(m0)) {
+            c->filter_n = 0;
+            c->phase = kPhU;
+            return;
+        }
+        c->alpha = 0.5 * alpha;
+        if (c->merit_trials >= o.ls_max) {
+            c->status = NMPC_LINESEARCH_FAIL;
+            c->phase = kPhDone;
+        }
+        return;
+    }
     if (filter_accepts(I, c, o, tht, pht, T[5] == 0.0, alpha)) {
         c->phase = kPhU;
         return;
@@ -515,10 +552,7 @@ __global__ void __launch_bounds__(kBlock) k_decideT(const InstPtrs* __restrict__
     }
     const double next = 0.5 * alpha;
     c->alpha = next;
-    if (next < c->amin || c->trials >= o.ls_max) {
-        c->status = NMPC_LINESEARCH_FAIL;
-        c->phase = kPhDone;
-    }
+    if (next < c->amin || c->trials >= o.ls_max) filter_search_failed(c, o);
 }
 
 // ---- second-order corrections --------------------------------------------------------
@@ -666,8 +700,7 @@ __global__ void __launch_bounds__(kBlock) k_decideC(const InstPtrs* __restrict__
     const double next = 0.5 * c->alpha0;
     c->alpha = next;
     if (next < c->amin || c->trials >= o.ls_max) {
-        c->status = NMPC_LINESEARCH_FAIL;
-        c->phase = kPhDone;
+        filter_search_failed(c, o);
     } else {
         c->phase = kPhT;
     }
@@ -852,9 +885,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_update(const InstPtrs* __restric
     if (t < I.n) I.adj_w[t] += I.adj_d[t];
 }
 
-// Parameter contractions of w = K^{-1} seed for the distillation family (one block):
-//   x0:       (Q+ + Q-) (J w) on the stage-1 rows
-//   zF_k:     dt F (Q+ + Q-) (J w) on the feed-tray row of stage k
+// Parameter contractions of w = K^{-1} seed for the distillation family (one block),
+// with lam = (Q+ + Q-) (J w) the refined multiplier of the uncondensed solve
+// (recomputing Q (J w) from w would multiply the rounding of J w by Q):
+//   x0:       lam on the stage-1 rows
+//   zF_k:     dt F lam on the feed-tray row of stage k
 //   xD*, xB*: 2 sum_k w(top|bottom state) - 2 seed_obj sum_k (state - setpoint)
 //   u_prev:   2 rho w(u_1) - 2 rho seed_obj (u_1 - u_prev)
 // out = [x0 (nx) | setpoint (2) | traj (H) | u_prev (2)]
@@ -869,9 +904,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_distill(const InstPtrs* _
     const int tid = threadIdx.x;
     for (int t = tid; t < D.nx + D.H; t += kBlock) {
         const int r = t < D.nx ? t : (t - D.nx) * D.nx + D.fd;
-        double jw = 0.0;
-        for (int q = I.jptr[r]; q < I.jptr[r + 1]; ++q) jw += I.jv[q] * w[I.jcol[q]];
-        const double v = I.qeff[r] * jw;
+        const double v = I.adj_lam[r];
         if (t < D.nx) out[t] = v;
         else out[D.nx + 2 + (t - D.nx)] = C.dt * C.F * v;
     }
@@ -900,7 +933,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_distill(const InstPtrs* _
 }
 
 // Parameter contractions of w = K^{-1} seed for the plate family:
-//   x0_p:  (Q+ + Q-) (J w) on the stage-1 row of node p
+//   x0_p:  lam = (Q+ + Q-) (J w), the refined multiplier, on the stage-1 row of node p
 //   T*_p:  2 sum_k w(T_kp) - 2 seed_obj sum_k (T_kp - T*_p)
 //   u_prev: 0 (it enters no function of the problem)
 // out = [x0 (nx) | setpoint (nx) | u_prev (16)]; one thread per node.
@@ -911,9 +944,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_plate(const InstPtrs* __r
     double* out = I.adj_out;
     if (p < I.nu) out[2 * D.nx + p] = 0.0;
     if (p >= D.nx) return;
-    double jw = 0.0;
-    for (int q = I.jptr[p]; q < I.jptr[p + 1]; ++q) jw += I.jv[q] * I.adj_w[I.jcol[q]];
-    out[p] = I.qeff[p] * jw;
+    out[p] = I.adj_lam[p];
     double sw = 0.0, sd = 0.0;
     const double tgt = I.setp[p];
     for (int k = 0; k < D.H; ++k) {

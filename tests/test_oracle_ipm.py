@@ -201,3 +201,28 @@ def test_medium_cold_solve_converges(seed):
     st = res.state
     lam = st.omega[:m.m_c] - st.omega[m.m_c:2 * m.m_c]
     assert kkt_error(m, st.y, lam, st.omega[2 * m.m_c:], st.zL, st.zU)["max"] <= 1e-8
+
+
+def test_merit_fallback_rescues_filter_stall():
+    """A ragged-batch column (22 trays, 45 stages) on which the filter search
+    stalls: the Newton direction ascends phi while theta barely moves, so every
+    trial down to the minimal step is rejected.  Without the fallback the solve
+    ends in a line-search failure; with it one l1-merit step gets through, the
+    filter restarts empty and the solve reaches a KKT point of the original
+    problem."""
+    from workloads import batch_distillation_workloads
+    w = batch_distillation_workloads(64, 1000)[7]
+    assert (w.N, w.H) == (22, 45)
+    m = DistillationOCP.from_workload(w)
+    m.set_parameters(x0=w.x0, zF=w.zF(0), u_prev=w.u_prev0)
+    off = LiftedIPM(m, IPMOptions(merit_fallback=0))
+    r0 = off.solve(off.cold_start(m.initial_guess(), off.o.mu0_cold), off.o.mu0_cold)
+    assert r0.status == 2
+    ipm = LiftedIPM(m)
+    res = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold, record=True)
+    assert res.status == 0
+    used = [t["it"] for t in res.trace if t["merit"]]
+    assert len(used) >= 1 and used[0] == r0.iters
+    st = res.state
+    lam = st.omega[:m.m_c] - st.omega[m.m_c:2 * m.m_c]
+    assert kkt_error(m, st.y, lam, st.omega[2 * m.m_c:], st.zL, st.zU)["max"] <= 1e-8
