@@ -48,6 +48,11 @@ def measured_traffic():
         return None
 
 
+def _progress(msg):
+    """One line on stderr per finished stage (long runs report as they go)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else float("nan")
 
@@ -116,11 +121,13 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
     t0 = time.perf_counter()
     pb = make()
     t_an = time.perf_counter() - t0
+    _progress(f"batch: {count} problems analyzed and tuned")
     b = N.Batch(pb)
     t0 = time.perf_counter()
     rc, res0 = b.solve(warm=False, options=opts)
     t_cold = time.perf_counter() - t0
     cold_bad = [i for i, r in enumerate(res0) if r.status != 0]
+    _progress(f"batch: cold solve done, {len(cold_bad)} nonzero status")
     fs = [q.first_stage() for q in pb]
     lat_b, it_b, st_b = [], 0, []
     t_begin = time.perf_counter()
@@ -136,6 +143,7 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
         st_b += [r.status for r in res]
     el_b = time.perf_counter() - t_begin
     b.close()
+    _progress("batch: batched re-solves done")
     ps = make()
     for q in ps:
         q.solve(warm=False, options=opts)
@@ -152,6 +160,7 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
             it_s += r.iters
             st_s.append(r.status)
     el_s = time.perf_counter() - t_begin
+    _progress("batch: one-by-one re-solves done")
     n_tot = sum(q.n for q in pb)
     return {"workload": f"{count} distillation instances, trays U{{20..60}}, horizons U{{40..120}}, alpha U(2,3), "
                         f"seeds {base_seed}..{base_seed + count - 1}, {rounds} warm re-solve rounds",
@@ -184,6 +193,7 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
     t0 = time.perf_counter()
     r0 = p.solve(warm=False, options=opts)
     t_cold = time.perf_counter() - t0
+    _progress(f"plate {G}x{G}x{H}: cold solve status {r0.status}, {r0.iters} iterations")
     u1, x1 = p.first_stage()
     lat, lat_adj, lat_vjp, iters, facts, ms_fact, statuses = [], [], [], 0, 0, 0.0, []
     for k in range(resolves):
@@ -203,6 +213,7 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
             t = time.perf_counter()
             rc2, g = p.adjoint(np.zeros(16), 1.0)
             lat_vjp.append((time.perf_counter() - t) * 1e3)
+        _progress(f"plate {G}x{G}x{H}: re-solve {k + 1}/{resolves} status {r.status}")
     tot = sum(lat) / 1e3
     flops = float(sym["flops"])
     achieved = (facts * flops / (ms_fact * 1e-3)) / 1e12 if ms_fact > 0 else None
@@ -238,6 +249,8 @@ def main(argv=None):
     ap.add_argument("--batch-only", action="store_true", help="only run the 64-instance batched form")
     ap.add_argument("--no-plate", action="store_true", help="skip the heated-plate workloads")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
+    ap.add_argument("--plate-case", choices=("plain", "adjoint", "both"), default="both",
+                    help="with --plate-only: the 32x32x50 plate, the differentiated plate, or both")
     ap.add_argument("--adjoint-grid", type=int, default=64, help="grid of the differentiated form (64 in the full run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 10 times (counter calibration)")
@@ -267,9 +280,12 @@ def main(argv=None):
         print(json.dumps({"batched": run_batched(N, eager=a.eager)}), flush=True)
         return 0
     if a.plate_only:
-        print(json.dumps({"plate": run_plate(N, eager=a.eager),
-                          "plate_adjoint": run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True,
-                                                     eager=a.eager)}), flush=True)
+        out = {}
+        if a.plate_case in ("plain", "both"):
+            out["plate"] = run_plate(N, eager=a.eager)
+        if a.plate_case in ("adjoint", "both"):
+            out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
+        print(json.dumps(out), flush=True)
         return 0
     w = distillation_workload("medium", a.seed, n_resolves=a.warmup + a.steps + 1)
     p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
@@ -287,6 +303,7 @@ def main(argv=None):
     if r0.status != 0:
         print(f"bench.py: cold solve failed with status {r0.status}", file=sys.stderr)
         return 1
+    _progress(f"distillation: analyze + cold solve {t_first:.2f} s, {r0.iters} iterations")
     sym = p.symbolic_sizes()
     opts = N.default_options(timing=1, graph=0 if a.eager else 1)
 
@@ -320,6 +337,7 @@ def main(argv=None):
             phase[key] += getattr(res, "ms_" + key)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_begin
+    _progress(f"distillation: {a.steps} timed re-solves in {elapsed:.2f} s")
     nk = int(p.nnz_k)
     bytes_per_factor = 8.0 * (nk + sym["nnz_l"])
     achieved = (facts * bytes_per_factor / (ms_fact * 1e-3)) / 1e9 if ms_fact > 0 else None
@@ -361,6 +379,7 @@ def main(argv=None):
         out["plate"] = run_plate(N, eager=a.eager)
         out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
     if not a.no_cpu_baseline:
+        _progress("cpu baseline (oracle) starts")
         out["cpu_baseline"] = cpu_baseline(a.seed, a.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
