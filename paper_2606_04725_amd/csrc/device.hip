@@ -318,7 +318,7 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
     BTRY(upload(B->allocs, B->groups, gl));
     BTRY(upload(B->allocs, B->tasks, tl));
     BTRY(linalg_configure(lim));   // the device maximum, so every batch's launches fit
-    BTRY(big_configure());
+    BTRY(big_configure(lim));
     BTRY(dalloc(B->allocs, B->running, 1));
     BTRY(hipHostMalloc((void**)&B->hrunning, sizeof(int), hipHostMallocDefault));
     BTRY(hipHostMalloc((void**)&B->hctl, sizeof(Ctl) * ni, hipHostMallocDefault));
@@ -526,7 +526,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
         big_fac[sn] = fac_bytes(sn) > lim && mr > kMediumFront;
         big_sol[sn] = sol_bytes(sn) > lim;
         if (!big_fac[sn] && fac_bytes(sn) > lim) medium_max = std::max<int>(medium_max, (int)mr);
-        if ((size_t)width_of(sn) * sizeof(double) > lim) {
+        if (big_solve_lds(width_of(sn)) > lim) {
             err = "supernode wider than the shared-memory solve buffer; unsupported";
             return bail(NMPC_ERR_UNSUPPORTED);
         }
@@ -625,14 +625,15 @@ nmpc_status device_init(Problem& p, std::string& err) {
         gs.kind = kStepGroupFwd;
         std::vector<int32_t> bigs;
         std::vector<int4> fd, fb;
-        size_t fl = 0;
+        size_t fl = 0, fbl = 0;
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
             const int32_t sn = sy.level_list[i];
             if (big_fac[sn]) bigs.push_back(sn);
             else gf.groups.push_back(make_group({sn}));
             if (big_sol[sn]) {
                 fd.push_back(int4{0, sn, 0, 0});
-                fl = std::max(fl, (size_t)width_of(sn) * sizeof(double));
+                fl = std::max(fl, big_solve_lds(width_of(sn)));
+                fbl = std::max(fbl, (size_t)width_of(sn) * sizeof(double));
                 for (int rb = 0; rb < ceil_div(rows_of(sn) - width_of(sn), SR); ++rb) fb.push_back(int4{0, sn, rb, 0});
             } else {
                 gs.groups.push_back(make_group({sn}));
@@ -642,7 +643,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
         big_factor_steps(bigs);
         if (!gs.groups.empty()) D.fwd.push_back(gs);
         push(D.fwd, kBigFwdDiag, std::move(fd), fl);
-        push(D.fwd, kBigFwdBelow, std::move(fb), fl);
+        push(D.fwd, kBigFwdBelow, std::move(fb), fbl);
     }
     if (!tail_nodes.empty()) {
         Step gf, gs, gb;
@@ -665,7 +666,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
             const int32_t sn = sy.level_list[i];
             if (big_sol[sn]) {
                 bd.push_back(int4{0, sn, 0, 0});
-                bl = std::max(bl, (size_t)width_of(sn) * sizeof(double));
+                bl = std::max(bl, big_solve_lds(width_of(sn)));
                 if (rows_of(sn) > width_of(sn))
                     for (int cb = 0; cb < ceil_div(width_of(sn), SC); ++cb) bb.push_back(int4{0, sn, cb, 0});
             } else {

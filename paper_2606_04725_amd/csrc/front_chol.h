@@ -1,0 +1,113 @@
+// Dense partial Cholesky of a front held in shared memory, shared by the
+// small-front kernels and the diagonal blocks of the large-front path.
+#pragma once
+
+#include <cmath>
+
+namespace nmpc {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCholWave = 64;
+
+// Right-looking partial Cholesky of the first w columns of an m x m front in
+// shared memory (column-major, lower triangle, leading dimension ld, odd so that
+// a stride-ld walk touches distinct banks), P pivot columns at a time:
+//  1. every thread factors the P x P diagonal block itself, in registers
+//     (identical arithmetic in every thread, no communication);
+//  2. every row below the block solves its own row of the panel against it;
+//  3. the rest of the front takes the rank-P update on the matrix cores:
+//     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
+// A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
+// numerically positive definite); the arithmetic continues with pivot 1.
+template <int P>
+__device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int kb = 0; kb < w; kb += P) {
+        const int kw = min(P, w - kb);
+        double d[P][P];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = 0; j < P; ++j)
+                d[i][j] = (j <= i && i < kw) ? F[(kb + i) + (kb + j) * ld] : (i == j ? 1.0 : 0.0);
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double piv = d[k][k];
+            if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
+                bad = true;
+                piv = 1.0;
+            }
+            const double sq = sqrt(piv);
+            const double inv = 1.0 / sq;
+            d[k][k] = sq;
+#pragma unroll
+            for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
+#pragma unroll
+            for (int j = k + 1; j < P; ++j)
+#pragma unroll
+                for (int i = j; i < P; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
+        }
+        if (bad && tid == 0) *fail = 1;
+        double rd[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) rd[k] = 1.0 / d[k][k];
+        __syncthreads();   // every thread has read the diagonal block before it is overwritten
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            if (tid == i && i < kw) {
+#pragma unroll
+                for (int j = 0; j <= i; ++j) F[(kb + i) + (kb + j) * ld] = d[i][j];
+            }
+        for (int r = kb + kw + tid; r < m; r += nthr) {
+            double a[P];
+#pragma unroll
+            for (int j = 0; j < P; ++j) a[j] = j < kw ? F[r + (kb + j) * ld] : 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s = a[k];
+#pragma unroll
+                for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
+                a[k] = s * rd[k];
+            }
+#pragma unroll
+            for (int j = 0; j < P; ++j)
+                if (j < kw) F[r + (kb + j) * ld] = a[j];
+        }
+        __syncthreads();
+        const int t0 = kb + kw;
+        const int T = m - t0;
+        if (T > 0) {
+            const int nt = (T + 15) / 16;
+            const int ntiles = nt * (nt + 1) / 2;
+            for (int tile = wv; tile < ntiles; tile += nw) {
+                int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+                while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+                while (ti * (ti + 1) / 2 > tile) --ti;
+                const int tj = tile - ti * (ti + 1) / 2;
+                const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s4 = 0; s4 < P / 4; ++s4) {
+                    const int kk = 4 * s4 + lk;
+                    const double* col = F + (kb + kk) * ld;
+                    const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
+                    const double b = (kk < kw && j0 + li < m) ? col[j0 + li] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ir = i0 + 4 * r + lk, jc = j0 + li;
+                    if (ir < m && jc <= ir) F[ir + jc * ld] -= acc[r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+
+}  // namespace nmpc

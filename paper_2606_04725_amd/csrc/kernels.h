@@ -263,7 +263,8 @@ enum BigKind : int {
 // which selects the solve vectors); lds_bytes: the diagonal solves' w values.
 void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs* I, const int4* tasks, int count,
                 size_t lds_bytes, hipStream_t st);
-hipError_t big_configure();
+hipError_t big_configure(size_t lds_limit);
+size_t big_solve_lds(int64_t w);   // shared memory of a large supernode's diagonal solve
 int big_row_block();
 int big_tile();
 int big_solve_rows();

@@ -26,19 +26,18 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "front_chol.h"
 
 namespace nmpc {
 
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kRowBlock = 128;   // TRSM rows per workgroup
+constexpr int kRowBlock = kBlock;   // TRSM rows per workgroup (one per thread)
 constexpr int kTile = 64;        // trailing-update tile
 constexpr int kSolveRows = 256;  // GEMV rows per workgroup
-constexpr int kSolveCols = 64;   // transposed-GEMV columns per workgroup
-constexpr size_t kBigTrsmLds = sizeof(double) * (kBigPanel * (kBigPanel + 1) + kRowBlock * (kBigPanel + 1) + kBigPanel);
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kSolveCols = 16;   // transposed-GEMV columns per workgroup
+constexpr int kTri = kWave * (kWave + 1);   // a staged 64 x 64 triangle, leading dimension 65
 
 struct Front {
     double* L;     // panel, leading dimension m
@@ -104,12 +103,13 @@ k_big_extend(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
 }
 
 // task (inst, s, kb, -): factor the diagonal block D of columns [kb, kb + pw)
-// in shared memory (right-looking, column by column) and store it.  A pivot
+// in shared memory (panel-blocked, see partial_cholesky) and store it.  A pivot
 // that is not positive and finite sets the instance's failure flag (eq. 12) and
 // the arithmetic continues with pivot 1.
 __global__ void __launch_bounds__(kBlock)
 k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
-    __shared__ double D[kBigPanel * (kBigPanel + 1)];
+    static_assert(kBigPanel == kWave, "diagonal blocks are staged as 64 x 64 triangles");
+    __shared__ double D[kTri];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
@@ -117,47 +117,26 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
     const int kb = tk.z;
     const int pw = min(kBigPanel, F.w - kb);
     constexpr int ldd = kBigPanel + 1;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < pw * pw; e += blockDim.x) {
-        const int i = e % pw, j = e / pw;
-        D[i + j * ldd] = i >= j ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+    for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
+        const int i = e % kBigPanel, j = e / kBigPanel;
+        D[i + j * ldd] = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
     }
     __syncthreads();
-    bool bad = false;
-    for (int k = 0; k < pw; ++k) {
-        double piv = D[k + k * ldd];
-        if (!(piv > 0.0) || !(piv < INFINITY)) {
-            bad = true;
-            piv = 1.0;
-        }
-        const double d = sqrt(piv);
-        __syncthreads();   // every thread has read the pivot
-        if (tid == 0) D[k + k * ldd] = d;
-        for (int i = k + 1 + tid; i < pw; i += blockDim.x) D[i + k * ldd] /= d;
-        __syncthreads();
-        const int rem = pw - k - 1;
-        for (int e = tid; e < rem * rem; e += blockDim.x) {
-            const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-            if (i >= j) D[i + j * ldd] = fma(-D[i + k * ldd], D[j + k * ldd], D[i + j * ldd]);
-        }
-        __syncthreads();
-    }
-    if (bad && tid == 0) I.ctl->fail = 1;
-    for (int e = tid; e < pw * pw; e += blockDim.x) {
-        const int i = e % pw, j = e / pw;
-        if (i >= j) F.L[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
+    partial_cholesky<8>(D, pw, ldd, pw, &I.ctl->fail);
+    for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
+        const int i = e % kBigPanel, j = e / kBigPanel;
+        if (i < pw && j <= i) F.L[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
     }
 }
 
 // task (inst, s, kb, row block): solve x D^T = a for the rows
 // [kb + pw + rb kRowBlock, ...) below the factored diagonal block, one row per
-// thread, rows and D staged in shared memory.
+// thread against D and the reciprocals of its diagonal in shared memory (every
+// lane reads the same entry).
 __global__ void __launch_bounds__(kBlock)
 k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
-    extern __shared__ double smem[];   // kBigTrsmLds bytes: D, X, rd
-    double* D = smem;
-    double* X = D + kBigPanel * (kBigPanel + 1);
-    double* rd = X + kRowBlock * (kBigPanel + 1);
+    __shared__ double D[kTri];
+    __shared__ double rd[kBigPanel];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
@@ -167,31 +146,39 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
     constexpr int ldd = kBigPanel + 1;
     const int tid = threadIdx.x;
     const int r0 = kb + pw + tk.w * kRowBlock;
-    const int nr = min(kRowBlock, F.m - r0);
-    if (nr <= 0) return;
-    for (int e = tid; e < pw * pw; e += blockDim.x) {
-        const int i = e % pw, j = e / pw;
-        if (i >= j) D[i + j * ldd] = F.L[(kb + i) + (int64_t)(kb + j) * F.m];
-    }
-    for (int e = tid; e < nr * pw; e += blockDim.x) {
-        const int i = e % nr, k = e / nr;
-        X[i * ldd + k] = F.L[(r0 + i) + (int64_t)(kb + k) * F.m];
+    if (r0 >= F.m) return;
+    for (int e = tid; e < kBigPanel * kBigPanel; e += blockDim.x) {
+        const int i = e % kBigPanel, j = e / kBigPanel;
+        D[i + j * ldd] = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
     }
     __syncthreads();
-    for (int k = tid; k < pw; k += blockDim.x) rd[k] = 1.0 / D[k + k * ldd];
+    if (tid < kBigPanel) rd[tid] = tid < pw ? 1.0 / D[tid + tid * ldd] : 1.0;
     __syncthreads();
-    if (tid < nr) {
-        double* x = X + tid * ldd;
-        for (int k = 0; k < pw; ++k) {
-            double s = x[k];
-            for (int j = 0; j < k; ++j) s = fma(-x[j], D[k + j * ldd], s);
-            x[k] = s * rd[k];
+    const int r = r0 + tid;
+    if (r >= F.m) return;
+    double* row = F.L + r + (int64_t)kb * F.m;
+    if (pw == kBigPanel) {
+        // full panel: the row in registers (unconditional accesses keep the
+        // unrolled solve in one block of straight-line code)
+        double x[kBigPanel];
+#pragma unroll
+        for (int k = 0; k < kBigPanel; ++k) x[k] = row[(int64_t)k * F.m];
+#pragma unroll
+        for (int k = 0; k < kBigPanel; ++k) {
+            double acc = x[k];
+#pragma unroll
+            for (int j = 0; j < k; ++j) acc = fma(-x[j], D[k + j * ldd], acc);
+            x[k] = acc * rd[k];
         }
-    }
-    __syncthreads();
-    for (int e = tid; e < nr * pw; e += blockDim.x) {
-        const int i = e % nr, k = e / nr;
-        F.L[(r0 + i) + (int64_t)(kb + k) * F.m] = X[i * ldd + k];
+#pragma unroll
+        for (int k = 0; k < kBigPanel; ++k) row[(int64_t)k * F.m] = x[k];
+    } else {
+        // the last, narrower panel of a supernode: in place
+        for (int k = 0; k < pw; ++k) {
+            double acc = row[(int64_t)k * F.m];
+            for (int j = 0; j < k; ++j) acc = fma(-row[(int64_t)j * F.m], D[k + j * ldd], acc);
+            row[(int64_t)k * F.m] = acc * rd[k];
+        }
     }
 }
 
@@ -273,11 +260,23 @@ k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
 }
 
 // ---- solves ------------------------------------------------------------------------
+// Stage the lower triangle of the diagonal block [b0, b0 + bw)^2 of L in T
+// (leading dimension kWave + 1); the caller synchronizes.
+__device__ inline void stage_triangle(const Front& F, int b0, int bw, double* T) {
+    for (int e = threadIdx.x; e < kWave * kWave; e += blockDim.x) {
+        const int i = e % kWave, j = e / kWave;
+        if (i < bw && j <= i) T[i + j * (kWave + 1)] = F.L[(b0 + i) + (int64_t)(b0 + j) * F.m];
+    }
+}
+
 // forward, task (inst, s): v = P b over the supernode's rows plus the children's
 // update vectors; x = L_dd^{-1} v[0, w) into xp; v[w, m) into the update vector.
+// Shared memory: a staged 64 x 64 triangle, then w values.
 __global__ void __launch_bounds__(kBlock)
 k_bigfwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
-    extern __shared__ double v[];   // w values
+    extern __shared__ double smem[];
+    double* T = smem;
+    double* v = smem + kTri;
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
@@ -300,20 +299,22 @@ k_bigfwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, i
         }
         __syncthreads();
     }
-    // blocked forward substitution, 64 columns per block: wave 0 solves the
-    // block's triangle (lane j owns row b0 + j), then every thread updates the
-    // rows below the block inside the diagonal part
+    // blocked forward substitution, 64 columns per block: the block's triangle
+    // is staged in shared memory, wave 0 solves it (lane j owns row b0 + j),
+    // then every thread updates the rows below the block inside the diagonal part
     for (int b0 = 0; b0 < F.w; b0 += kWave) {
-        const int b1 = min(F.w, b0 + kWave);
+        const int bw = min(kWave, F.w - b0), b1 = b0 + bw;
+        stage_triangle(F, b0, bw, T);
+        __syncthreads();
         if (tid < kWave) {
-            const int j = b0 + tid;
-            double vj = j < b1 ? v[j] : 0.0;
-            for (int k = b0; k < b1; ++k) {
-                const double xk = __shfl(vj, k - b0, kWave) / F.L[k + (int64_t)k * F.m];
+            const int j = tid;
+            double vj = j < bw ? v[b0 + j] : 0.0;
+            for (int k = 0; k < bw; ++k) {
+                const double xk = __shfl(vj, k, kWave) / T[k + k * (kWave + 1)];
                 if (j == k) vj = xk;
-                else if (j > k && j < b1) vj = fma(-F.L[j + (int64_t)k * F.m], xk, vj);
+                else if (j > k && j < bw) vj = fma(-T[j + k * (kWave + 1)], xk, vj);
             }
-            if (j < b1) v[j] = vj;
+            if (j < bw) v[b0 + j] = vj;
         }
         __syncthreads();
         for (int i = b1 + tid; i < F.w; i += nthr) {
@@ -366,12 +367,15 @@ k_bigbwd_below(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, 
 }
 
 // backward, task (inst, s): v = xp[f, f + w) - bsum; solve L_dd^T x = v by
-// blocks from the last (wave 0 solves a block's triangle, then every thread
-// updates the earlier rows with the block's rows of L); writes xp and the
-// unpermuted solution.
+// blocks from the last (the block's triangle staged in shared memory, wave 0
+// solves it, then every thread updates the earlier rows with the block's rows
+// of L); writes xp and the unpermuted solution.  Shared memory: a staged
+// triangle, then w values.
 __global__ void __launch_bounds__(kBlock)
 k_bigbwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
-    extern __shared__ double v[];   // w values
+    extern __shared__ double smem[];
+    double* T = smem;
+    double* v = smem + kTri;
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
@@ -379,19 +383,20 @@ k_bigbwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, i
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool has_below = F.m > F.w;
     for (int k = tid; k < F.w; k += nthr) v[k] = I.xp[F.f + k] - (has_below ? I.bsum[F.f + k] : 0.0);
-    __syncthreads();
     const int nblk = (F.w + kWave - 1) / kWave;
     for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int b0 = bi * kWave, b1 = min(F.w, b0 + kWave);
+        const int b0 = bi * kWave, bw = min(kWave, F.w - b0), b1 = b0 + bw;
+        stage_triangle(F, b0, bw, T);
+        __syncthreads();
         if (tid < kWave) {
-            const int j = b0 + tid;
-            double vj = j < b1 ? v[j] : 0.0;
-            for (int k = b1 - 1; k >= b0; --k) {
-                const double xk = __shfl(vj, k - b0, kWave) / F.L[k + (int64_t)k * F.m];
+            const int j = tid;
+            double vj = j < bw ? v[b0 + j] : 0.0;
+            for (int k = bw - 1; k >= 0; --k) {
+                const double xk = __shfl(vj, k, kWave) / T[k + k * (kWave + 1)];
                 if (j == k) vj = xk;
-                else if (j >= b0 && j < k) vj = fma(-F.L[k + (int64_t)j * F.m], xk, vj);
+                else if (j < k) vj = fma(-T[k + j * (kWave + 1)], xk, vj);
             }
-            if (j < b1) v[j] = vj;
+            if (j < bw) v[b0 + j] = vj;
         }
         __syncthreads();
         for (int c = tid; c < b0; c += nthr) {
@@ -411,10 +416,20 @@ k_bigbwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, i
 
 }  // namespace
 
-hipError_t big_configure() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_big_trsm), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kBigTrsmLds);
+hipError_t big_configure(size_t lds_limit) {
+    // the diagonal solves hold a staged triangle and the supernode's w values,
+    // the forward GEMV the w solved values
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bigfwd_diag),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bigfwd_below), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_limit);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_bigbwd_diag),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
 }
+
+size_t big_solve_lds(int64_t w) { return sizeof(double) * ((size_t)kTri + (size_t)w); }
 
 int big_row_block() { return kRowBlock; }
 int big_tile() { return kTile; }
@@ -435,7 +450,7 @@ void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs*
             hipLaunchKernelGGL(k_big_potrf, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
         case kBigTrsm:
-            hipLaunchKernelGGL(k_big_trsm, dim3(count), dim3(kBlock), kBigTrsmLds, st, I, tasks, pred);
+            hipLaunchKernelGGL(k_big_trsm, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
         case kBigUpdate:
             hipLaunchKernelGGL(k_big_update<false>, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
