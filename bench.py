@@ -196,6 +196,7 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
     _progress(f"plate {G}x{G}x{H}: cold solve status {r0.status}, {r0.iters} iterations")
     u1, x1 = p.first_stage()
     lat, lat_adj, lat_vjp, iters, facts, ms_fact, statuses = [], [], [], 0, 0, 0.0, []
+    phase = dict(eval=0.0, assemble=0.0, factor=0.0, solve=0.0, linesearch=0.0)
     for k in range(resolves):
         t = time.perf_counter()
         p.set_parameters(x1, u_prev=u1)
@@ -206,6 +207,8 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
         facts += r.factorizations
         ms_fact += r.ms_factor
         statuses.append(r.status)
+        for key in phase:
+            phase[key] += getattr(r, "ms_" + key)
         if adjoint:
             t = time.perf_counter()
             rc, J = p.jacobian_u1_x0()
@@ -225,6 +228,7 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
            "iters_per_s": iters / tot if tot > 0 else None, "iters_per_resolve": iters / max(1, resolves),
            "nonzero_status": sum(1 for s_ in statuses if s_ != 0),
            "factor_ms": ms_fact / facts if facts else None,
+           "phase_ms_per_resolve": {k_: v / max(1, resolves) for k_, v in phase.items()},
            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None, "traffic": None,
                         "kernel": "numeric supernodal factorization (all launches of one factorization)",

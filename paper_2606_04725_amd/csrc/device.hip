@@ -512,9 +512,14 @@ nmpc_status device_init(Problem& p, std::string& err) {
     std::vector<char> big_fac(nsn, 0), big_sol(nsn, 0);
     auto rows_of = [&](int sn) { return (int64_t)(sy.sn_rows_ptr[sn + 1] - sy.sn_rows_ptr[sn]); };
     auto width_of = [&](int sn) { return (int64_t)(sy.sn_ptr[sn + 1] - sy.sn_ptr[sn]); };
+    // a shared-memory front is its packed lower triangle; a global one is square
+    auto packed_bytes = [&](int sn) {
+        const size_t mr = (size_t)rows_of(sn);
+        return mr * (mr + 1) / 2 * sizeof(double);
+    };
     auto fac_bytes = [&](int sn) {
         const size_t mr = (size_t)rows_of(sn);
-        return mr * (mr | 1) * sizeof(double) + kRelInts * sizeof(int32_t);
+        return packed_bytes(sn) <= lim ? packed_bytes(sn) : mr * (mr | 1) * sizeof(double);
     };
     auto sol_bytes = [&](int sn) {
         const size_t mr = (size_t)rows_of(sn), w = (size_t)width_of(sn);
@@ -687,11 +692,21 @@ nmpc_status device_init(Problem& p, std::string& err) {
         for (const auto& g : stp.groups) (g.lds_factor <= lim ? in_lds : global) = true;
         D.fac_launches += (int)in_lds + (int)global;
     }
-    for (int sn = 0; sn < nsn; ++sn)
-        if (!big_fac[sn] && rows_of(sn) > kRelInts) {
-            err = "internal: a front handled by one workgroup exceeds the relative-position buffer";
-            return bail(NMPC_ERR_UNSUPPORTED);
+    // front positions of the original entries: the large path keeps r + c (m | 1);
+    // a one-workgroup front takes its own layout (packed lower in shared memory,
+    // square with leading dimension m | 1 in a global buffer), a diagonal entry
+    // complemented (it takes + eta)
+    std::vector<int32_t> k_fpos = sy.k_fpos;
+    for (int sn = 0; sn < nsn; ++sn) {
+        if (big_fac[sn]) continue;
+        const int64_t mr = rows_of(sn), ld = mr | 1;
+        const bool packed = packed_bytes(sn) <= lim;
+        for (int32_t t = sy.k_ptr[sn]; t < sy.k_ptr[sn + 1]; ++t) {
+            const int64_t pos = sy.k_fpos[t], r = pos % ld, c = pos / ld;
+            const int64_t q = packed ? c * mr - c * (c + 1) / 2 + r : pos;
+            k_fpos[t] = r == c ? ~(int32_t)q : (int32_t)q;
         }
+    }
     // global front buffers for the medium groups of one step
     int max_global = 0;
     for (const auto& stp : D.fac) {
@@ -723,7 +738,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(upload_c(A, I.S.rel_off, sy.rel_off));
     DTRY(upload_c(A, I.S.rel, sy.rel));
     DTRY(upload_c(A, I.S.k_ptr, sy.k_ptr));
-    DTRY(upload_c(A, I.S.k_fpos, sy.k_fpos));
+    DTRY(upload_c(A, I.S.k_fpos, k_fpos));
     DTRY(upload_c(A, I.kcol_ptr, sy.kcol_ptr));
     DTRY(upload_c(A, I.S.sched_nodes, nodes));
     DTRY(upload_c(A, I.k_wslot, sy.k_wslot));

@@ -10,9 +10,22 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCholWave = 64;
 
-// Right-looking partial Cholesky of the first w columns of an m x m front in
-// shared memory (column-major, lower triangle, leading dimension ld, odd so that
-// a stride-ld walk touches distinct banks), P pivot columns at a time:
+// Index maps of a front's lower triangle: base(j) + i is the position of
+// entry (i, j), i >= j.
+struct SquareIdx {   // column-major, leading dimension ld
+    int ld;
+    __device__ int base(int j) const { return j * ld; }
+    __device__ int operator()(int i, int j) const { return i + j * ld; }
+};
+struct PackedIdx {   // lower triangle packed by columns: column j holds rows j .. m-1
+    int m;
+    __device__ int base(int j) const { return j * m - ((j * (j + 1)) >> 1); }
+    __device__ int operator()(int i, int j) const { return base(j) + i; }
+};
+
+// Right-looking partial Cholesky of the first w columns of an m x m front
+// (lower triangle, positions given by the index map ix; only entries i >= j are
+// touched), P pivot columns at a time:
 //  1. every thread factors the P x P diagonal block itself, in registers
 //     (identical arithmetic in every thread, no communication);
 //  2. every row below the block solves its own row of the panel against it;
@@ -20,8 +33,8 @@ constexpr int kCholWave = 64;
 //     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
 // A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
 // numerically positive definite); the arithmetic continues with pivot 1.
-template <int P>
-__device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fail) {
+template <int P, class Idx>
+__device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
     const int li = lane & 15, lk = lane >> 4;
@@ -32,7 +45,7 @@ __device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fa
         for (int i = 0; i < P; ++i)
 #pragma unroll
             for (int j = 0; j < P; ++j)
-                d[i][j] = (j <= i && i < kw) ? F[(kb + i) + (kb + j) * ld] : (i == j ? 1.0 : 0.0);
+                d[i][j] = (j <= i && i < kw) ? F[ix(kb + i, kb + j)] : (i == j ? 1.0 : 0.0);
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -60,12 +73,12 @@ __device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fa
         for (int i = 0; i < P; ++i)
             if (tid == i && i < kw) {
 #pragma unroll
-                for (int j = 0; j <= i; ++j) F[(kb + i) + (kb + j) * ld] = d[i][j];
+                for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
             }
         for (int r = kb + kw + tid; r < m; r += nthr) {
             double a[P];
 #pragma unroll
-            for (int j = 0; j < P; ++j) a[j] = j < kw ? F[r + (kb + j) * ld] : 0.0;
+            for (int j = 0; j < P; ++j) a[j] = j < kw ? F[ix(r, kb + j)] : 0.0;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 double s = a[k];
@@ -75,7 +88,7 @@ __device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fa
             }
 #pragma unroll
             for (int j = 0; j < P; ++j)
-                if (j < kw) F[r + (kb + j) * ld] = a[j];
+                if (j < kw) F[ix(r, kb + j)] = a[j];
         }
         __syncthreads();
         const int t0 = kb + kw;
@@ -93,7 +106,7 @@ __device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fa
 #pragma unroll
                 for (int s4 = 0; s4 < P / 4; ++s4) {
                     const int kk = 4 * s4 + lk;
-                    const double* col = F + (kb + kk) * ld;
+                    const double* col = F + ix.base(kb + kk);
                     const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
                     const double b = (kk < kw && j0 + li < m) ? col[j0 + li] : 0.0;
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
@@ -101,7 +114,7 @@ __device__ inline void partial_cholesky(double* F, int m, int ld, int w, int* fa
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int ir = i0 + 4 * r + lk, jc = j0 + li;
-                    if (ir < m && jc <= ir) F[ir + jc * ld] -= acc[r];
+                    if (ir < m && jc <= ir) F[ix(ir, jc)] -= acc[r];
                 }
             }
         }

@@ -20,7 +20,6 @@ namespace nmpc {
 constexpr int kBlock = 256;          // threads per block of every vector kernel
 constexpr int kFactorBlock = 256;    // threads per supernode group
 constexpr int kPanel = 8;            // pivot columns per blocked step of a front
-constexpr int kRelInts = 512;        // shared-memory ints reserved ahead of a front (relative positions)
 constexpr int kMaxQ = 12;            // reduced quantities per phase
 constexpr int kMaxSeed = 16;         // controls per stage the sensitivity seed can hold
 constexpr int kFilterCapMax = 256;   // filter entries an instance can hold

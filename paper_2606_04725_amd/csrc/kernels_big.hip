@@ -122,7 +122,7 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
         D[i + j * ldd] = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
     }
     __syncthreads();
-    partial_cholesky<8>(D, pw, ldd, pw, &I.ctl->fail);
+    partial_cholesky<8>(D, SquareIdx{ldd}, pw, pw, &I.ctl->fail);
     for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
         const int i = e % kBigPanel, j = e / kBigPanel;
         if (i < pw && j <= i) F.L[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];

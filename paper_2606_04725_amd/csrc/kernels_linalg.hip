@@ -13,6 +13,7 @@
 // walked by one workgroup, so a chain of fronts costs one launch.  Every sum is
 // taken in a fixed order, so results do not depend on scheduling.
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 #include "front_chol.h"
@@ -46,64 +47,130 @@ __device__ void g2s(T* dst, const T* __restrict__ src, int64_t n) {
     }
 }
 
+// Entry e of the lower triangle of an n x n matrix packed by columns, as (i, j).
+__device__ inline void unpack_lower(int e, int n, int& i, int& j) {
+    const double b = 2.0 * n + 1.0;
+    int c = (int)((b - sqrt(b * b - 8.0 * e)) * 0.5);
+    c = max(0, min(c, n - 1));
+    while (c > 0 && c * n - ((c * (c - 1)) >> 1) > e) --c;
+    while (c + 1 < n && (c + 1) * n - (((c + 1) * c) >> 1) <= e) ++c;
+    j = c;
+    i = c + (e - (c * n - ((c * (c - 1)) >> 1)));
+}
+
+// Loads of one round of a child's update block: entries e0 + tid + u nthr of
+// its packed lower triangle (ne entries), each as a value and its position in
+// the parent front (through the child's relative row positions).
+template <class Idx>
+__device__ inline void child_round(const double* __restrict__ Uc, const int32_t* __restrict__ rel, int nc, int ne,
+                                   int e0, Idx ix, double (&v)[kBatch], int (&pos)[kBatch]) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+        const int e = e0 + tid + u * nthr;
+        pos[u] = -1;
+        v[u] = 0.0;
+        if (e < ne) {
+            int i, j;
+            unpack_lower(e, nc, i, j);
+            v[u] = Uc[i + (int64_t)j * nc];
+            pos[u] = ix(rel[i], rel[j]);
+        }
+    }
+}
+
 // One supernode: assemble the front, factor it, store the L panel and update.
+// Shared-memory fronts are packed lower triangles; the global buffer of a
+// medium front is square with an odd leading dimension.
 template <bool Lds, int P>
 __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv, double eta, double* __restrict__ L,
-                           double* __restrict__ U, int* __restrict__ fail, double* F, int32_t* rcl) {
+                           double* __restrict__ U, int* __restrict__ fail, double* F) {
+    using Idx = typename std::conditional<Lds, PackedIdx, SquareIdx>::type;
     const int f = S.sn_ptr[s];
     const int w = S.sn_ptr[s + 1] - f;
     const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
-    const int ld = m | 1;
+    Idx ix;
+    if constexpr (Lds) ix.m = m; else ix.ld = m | 1;
     const int nb = m - w;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
-    const int mm = m * ld;
-    for (int e = tid; e < mm; e += nthr) F[e] = 0.0;
+    const int fsize = Lds ? (m * (m + 1)) / 2 : m * (m | 1);
+    for (int e = tid; e < fsize; e += nthr) F[e] = 0.0;
+    // first round of the first child's update block in flight while the front
+    // is cleared and the original entries are placed
+    const int c0 = S.child_ptr[s], c1 = S.child_ptr[s + 1];
+    double va[kBatch];
+    int pa[kBatch];
+    int ci = c0, nc = 0, ne = 0, e0 = 0;
+    const double* Uc = nullptr;
+    const int32_t* rel = nullptr;
+    auto open_child = [&](int k) {
+        const int c = S.child_list[k];
+        const int wc = S.sn_ptr[c + 1] - S.sn_ptr[c];
+        nc = (int)(S.rows_ptr[c + 1] - S.rows_ptr[c]) - wc;
+        ne = (nc * (nc + 1)) / 2;
+        Uc = U + S.u_off[c];
+        rel = S.rel + S.rel_off[c];
+        e0 = 0;
+    };
+    if (ci < c1) {
+        open_child(ci);
+        child_round(Uc, rel, nc, ne, e0, ix, va, pa);
+    }
     __syncthreads();
-    // original entries of the condensed matrix in this supernode's columns (+ eta I);
-    // positions are r + c * (m | 1)
+    // original entries of the condensed matrix in this supernode's columns; a
+    // diagonal entry's position is stored complemented and takes + eta
     for (int t = S.k_ptr[s] + tid; t < S.k_ptr[s + 1]; t += nthr) {
-        const int pos = S.k_fpos[t];
+        int pos = S.k_fpos[t];
         double v = kv[t];
-        if (pos % (ld + 1) == 0) v += eta;
+        if (pos < 0) {
+            pos = ~pos;
+            v += eta;
+        }
         F[pos] = v;
     }
     __syncthreads();
-    // extend-add of the children's update blocks, children in fixed order; each
-    // wave walks columns, lanes walk rows, kBatch columns in flight
-    for (int ci = S.child_ptr[s]; ci < S.child_ptr[s + 1]; ++ci) {
-        const int c = S.child_list[ci];
-        const int wc = S.sn_ptr[c + 1] - S.sn_ptr[c];
-        const int nc = (int)(S.rows_ptr[c + 1] - S.rows_ptr[c]) - wc;
-        const double* Uc = U + S.u_off[c];
-        g2s(rcl, S.rel + S.rel_off[c], nc);
-        __syncthreads();
-        for (int jb = wv; jb < nc; jb += nw * kBatch) {
-            for (int ib = lane; ib < nc; ib += kWave) {
-                double v[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int jj = jb + u * nw;
-                    v[u] = (jj < nc && ib >= jj) ? Uc[ib + jj * nc] : 0.0;
-                }
-                const int ri = rcl[ib];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int jj = jb + u * nw;
-                    if (jj < nc && ib >= jj) F[ri + rcl[jj] * ld] += v[u];
-                }
-            }
+    // extend-add of the children's update blocks in fixed order, one round of
+    // kBatch entries per thread at a time; the next round's loads are issued
+    // before the current round is added, and children are separated by barriers
+    // (two children can add into the same entry)
+    while (ci < c1) {
+        double vb[kBatch];
+        int pb[kBatch];
+        int cn = ci;
+        bool next = true;
+        if (e0 + nthr * kBatch < ne) {
+            e0 += nthr * kBatch;
+        } else if (ci + 1 < c1) {
+            cn = ci + 1;
+        } else {
+            next = false;
         }
-        __syncthreads();
+        const bool new_child = cn != ci;
+        if (next) {
+            if (new_child) open_child(cn);
+            child_round(Uc, rel, nc, ne, e0, ix, vb, pb);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (pa[u] >= 0) F[pa[u]] += va[u];
+        if (new_child || !next) __syncthreads();
+        if (!next) break;
+        ci = cn;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            va[u] = vb[u];
+            pa[u] = pb[u];
+        }
     }
-    partial_cholesky<P>(F, m, ld, w, fail);
+    partial_cholesky<P>(F, ix, m, w, fail);
     double* Ls = L + S.l_off[s];
     for (int jc = wv; jc < w; jc += nw)
-        for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = F[i + jc * ld];
+        for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = i >= jc ? F[ix(i, jc)] : 0.0;
     if (nb > 0) {
         double* Us = U + S.u_off[s];
         for (int jj = wv; jj < nb; jj += nw)
-            for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[(w + ii) + (w + jj) * ld];
+            for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[ix(w + ii, w + jj)];
     }
     __syncthreads();   // the front buffer is reused by the next supernode of the group
 }
@@ -117,12 +184,10 @@ k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ group
     const InstPtrs& I = Ia[g.inst];
     if (!ctl_active(I.ctl, pred)) return;
     const double eta = pred == kPredAll ? eta_force : I.ctl->eta;
-    // shared memory: kRelInts relative positions, then the front (Lds); the
-    // instance's global scratch holds the front otherwise
-    double* F = Lds ? lds + kRelInts / 2 : I.gscratch + (int64_t)g.slot * I.gstride;
-    int32_t* rcl = reinterpret_cast<int32_t*>(lds);
+    // the front: shared memory, or the instance's global scratch for medium fronts
+    double* F = Lds ? lds : I.gscratch + (int64_t)g.slot * I.gstride;
     for (int i = g.begin; i < g.end; ++i)
-        factor_one<Lds, P>(I.S.sched_nodes[i], I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F, rcl);
+        factor_one<Lds, P>(I.S.sched_nodes[i], I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F);
 }
 
 // Triangular solves with one supernode's panel P (m x w, column-major, lower
@@ -334,8 +399,8 @@ void launch_variant(bool lds, int pred, double eta_force, const InstPtrs* I, con
         hipLaunchKernelGGL((k_factor_groups<true, Threads, P>), dim3(groups), dim3(Threads), lds_bytes, st, I, g, pred,
                            eta_force);
     else
-        hipLaunchKernelGGL((k_factor_groups<false, Threads, P>), dim3(groups), dim3(Threads),
-                           kRelInts * sizeof(int32_t), st, I, g, pred, eta_force);
+        hipLaunchKernelGGL((k_factor_groups<false, Threads, P>), dim3(groups), dim3(Threads), 0, st, I, g, pred,
+                           eta_force);
 }
 
 void launch_factor_groups(bool lds, int variant, int pred, double eta_force, const InstPtrs* I, const Group* g,
