@@ -318,7 +318,6 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
     BTRY(upload(B->allocs, B->groups, gl));
     BTRY(upload(B->allocs, B->tasks, tl));
     BTRY(linalg_configure(lim));   // the device maximum, so every batch's launches fit
-    BTRY(big_configure(lim));
     BTRY(dalloc(B->allocs, B->running, 1));
     BTRY(hipHostMalloc((void**)&B->hrunning, sizeof(int), hipHostMallocDefault));
     BTRY(hipHostMalloc((void**)&B->hctl, sizeof(Ctl) * ni, hipHostMallocDefault));
@@ -531,10 +530,6 @@ nmpc_status device_init(Problem& p, std::string& err) {
         big_fac[sn] = fac_bytes(sn) > lim && mr > kMediumFront;
         big_sol[sn] = sol_bytes(sn) > lim;
         if (!big_fac[sn] && fac_bytes(sn) > lim) medium_max = std::max<int>(medium_max, (int)mr);
-        if (big_solve_lds(width_of(sn)) > lim) {
-            err = "supernode wider than the shared-memory solve buffer; unsupported";
-            return bail(NMPC_ERR_UNSUPPORTED);
-        }
     }
     // Schedule: per level (bottom-up) one group step for its small and medium
     // supernodes and the step sequence of the large path for its large ones; the
@@ -561,7 +556,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
         return g;
     };
     auto ceil_div = [](int64_t a, int64_t b) { return (int)((a + b - 1) / b); };
-    const int RB = big_row_block(), TL = big_tile(), SR = big_solve_rows(), SC = big_solve_cols();
+    const int RB = big_row_block(), TL = big_tile(), SR = big_solve_rows(), SC = big_solve_cols(), CH = big_chunk();
     auto push = [&](std::vector<Step>& dst, int kind, std::vector<int4>&& t, size_t lds = 0) {
         if (t.empty()) return;
         Step stp;
@@ -628,27 +623,31 @@ nmpc_status device_init(Problem& p, std::string& err) {
         Step gf, gs;
         gf.kind = kStepGroupFactor;
         gs.kind = kStepGroupFwd;
-        std::vector<int32_t> bigs;
-        std::vector<int4> fd, fb;
-        size_t fl = 0, fbl = 0;
+        std::vector<int32_t> bigs, bsol;
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
             const int32_t sn = sy.level_list[i];
             if (big_fac[sn]) bigs.push_back(sn);
             else gf.groups.push_back(make_group({sn}));
-            if (big_sol[sn]) {
-                fd.push_back(int4{0, sn, 0, 0});
-                fl = std::max(fl, big_solve_lds(width_of(sn)));
-                fbl = std::max(fbl, (size_t)width_of(sn) * sizeof(double));
-                for (int rb = 0; rb < ceil_div(rows_of(sn) - width_of(sn), SR); ++rb) fb.push_back(int4{0, sn, rb, 0});
-            } else {
-                gs.groups.push_back(make_group({sn}));
-            }
+            if (big_sol[sn]) bsol.push_back(sn);
+            else gs.groups.push_back(make_group({sn}));
         }
         if (!gf.groups.empty()) D.fac.push_back(gf);
         big_factor_steps(bigs);
         if (!gs.groups.empty()) D.fwd.push_back(gs);
-        push(D.fwd, kBigFwdDiag, std::move(fd), fl);
-        push(D.fwd, kBigFwdBelow, std::move(fb), fbl);
+        int64_t nch = 0;
+        for (int32_t sn : bsol) nch = std::max<int64_t>(nch, ceil_div(width_of(sn), CH));
+        for (int c = 0; c < nch; ++c) {
+            std::vector<int4> tri, gv;
+            for (int32_t sn : bsol) {
+                const int64_t w = width_of(sn), m = rows_of(sn), c0 = (int64_t)c * CH;
+                if (c0 >= w) continue;
+                tri.push_back(int4{0, sn, c, 0});
+                const int64_t c1 = std::min<int64_t>(w, c0 + CH);
+                for (int rb = 0; rb < ceil_div(m - c1, SR); ++rb) gv.push_back(int4{0, sn, c, rb});
+            }
+            push(D.fwd, kBigFwdTri, std::move(tri));
+            push(D.fwd, kBigFwdGemv, std::move(gv));
+        }
     }
     if (!tail_nodes.empty()) {
         Step gf, gs, gb;
@@ -665,13 +664,12 @@ nmpc_status device_init(Problem& p, std::string& err) {
     for (int Lv = tail - 1; Lv >= 0; --Lv) {
         Step gb;
         gb.kind = kStepGroupBwd;
-        std::vector<int4> bb, bd;
-        size_t bl = 0;
+        std::vector<int4> bb;
+        std::vector<int32_t> bsol;
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
             const int32_t sn = sy.level_list[i];
             if (big_sol[sn]) {
-                bd.push_back(int4{0, sn, 0, 0});
-                bl = std::max(bl, big_solve_lds(width_of(sn)));
+                bsol.push_back(sn);
                 if (rows_of(sn) > width_of(sn))
                     for (int cb = 0; cb < ceil_div(width_of(sn), SC); ++cb) bb.push_back(int4{0, sn, cb, 0});
             } else {
@@ -680,7 +678,19 @@ nmpc_status device_init(Problem& p, std::string& err) {
         }
         if (!gb.groups.empty()) D.bwd.push_back(gb);
         push(D.bwd, kBigBwdBelow, std::move(bb));
-        push(D.bwd, kBigBwdDiag, std::move(bd), bl);
+        int64_t nch = 0;
+        for (int32_t sn : bsol) nch = std::max<int64_t>(nch, ceil_div(width_of(sn), CH));
+        for (int64_t c = nch - 1; c >= 0; --c) {
+            std::vector<int4> tri, gt;
+            for (int32_t sn : bsol) {
+                const int64_t w = width_of(sn), c0 = c * CH;
+                if (c0 >= w) continue;
+                tri.push_back(int4{0, sn, (int)c, 0});
+                for (int cb = 0; cb < ceil_div(c0, SC); ++cb) gt.push_back(int4{0, sn, (int)c, cb});
+            }
+            push(D.bwd, kBigBwdTri, std::move(tri));
+            push(D.bwd, kBigBwdGemvT, std::move(gt));
+        }
     }
     D.fac_launches = 0;
     for (const auto& stp : D.fac) {

@@ -252,22 +252,22 @@ enum BigKind : int {
     kBigPotrf = 3,      // task (inst, s, kb, -)
     kBigTrsm = 4,       // task (inst, s, kb, row block)
     kBigUpdate = 5,     // task (inst, s, kb, lower-triangle tile)
-    kBigFwdDiag = 6,    // task (inst, s, -, -)
-    kBigFwdBelow = 7,   // task (inst, s, row block, -)
+    kBigFwdTri = 6,     // task (inst, s, chunk, -)
+    kBigFwdGemv = 7,    // task (inst, s, chunk, row block)
     kBigBwdBelow = 8,   // task (inst, s, column block, -)
-    kBigBwdDiag = 9,    // task (inst, s, -, -)
-    kBigUpdateInner = 10  // task (inst, s, ki, rectangular tile)
+    kBigBwdTri = 9,     // task (inst, s, chunk, -)
+    kBigUpdateInner = 10,  // task (inst, s, ki, rectangular tile)
+    kBigBwdGemvT = 11   // task (inst, s, chunk, column block)
 };
 // One step for every task of a list (predicate and eta as for the groups;
-// which selects the solve vectors); lds_bytes: the diagonal solves' w values.
+// which selects the solve vectors).
 void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs* I, const int4* tasks, int count,
                 size_t lds_bytes, hipStream_t st);
-hipError_t big_configure(size_t lds_limit);
-size_t big_solve_lds(int64_t w);   // shared memory of a large supernode's diagonal solve
 int big_row_block();
 int big_tile();
 int big_solve_rows();
 int big_solve_cols();
+int big_chunk();   // columns per chunk of a large supernode's solves
 
 }  // namespace nmpc
 

@@ -163,12 +163,13 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
         double x[kBigPanel];
 #pragma unroll
         for (int k = 0; k < kBigPanel; ++k) x[k] = row[(int64_t)k * F.m];
+        // column by column (right-looking): the updates of one step are
+        // independent, so the dependency chain is 64 steps long, not 2016
 #pragma unroll
         for (int k = 0; k < kBigPanel; ++k) {
-            double acc = x[k];
+            x[k] *= rd[k];
 #pragma unroll
-            for (int j = 0; j < k; ++j) acc = fma(-x[j], D[k + j * ldd], acc);
-            x[k] = acc * rd[k];
+            for (int j = k + 1; j < kBigPanel; ++j) x[j] = fma(-x[k], D[j + k * ldd], x[j]);
         }
 #pragma unroll
         for (int k = 0; k < kBigPanel; ++k) row[(int64_t)k * F.m] = x[k];
@@ -260,6 +261,17 @@ k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
 }
 
 // ---- solves ------------------------------------------------------------------------
+// The columns of a large supernode are solved kChunk at a time.  Forward: one
+// workgroup solves the chunk's triangle (the first chunk also gathers the
+// right-hand side over the supernode's columns into xp and the rows below into
+// its update vector, adding the children's update vectors), then the rows after
+// the chunk (the rest of the diagonal part and the rows below) take the chunk's
+// GEMV, split over workgroups.  Backward, from the last chunk: the rows below
+// contribute L[w:m, k]^T x(rows below) to bsum (transposed GEMV), each chunk's
+// triangle is solved by one workgroup, then the columns before the chunk take
+// its transposed GEMV into bsum.  Sums over chunks run in a fixed order.
+constexpr int kChunk = 256;
+
 // Stage the lower triangle of the diagonal block [b0, b0 + bw)^2 of L in T
 // (leading dimension kWave + 1); the caller synchronizes.
 __device__ inline void stage_triangle(const Front& F, int b0, int bw, double* T) {
@@ -269,42 +281,43 @@ __device__ inline void stage_triangle(const Front& F, int b0, int bw, double* T)
     }
 }
 
-// forward, task (inst, s): v = P b over the supernode's rows plus the children's
-// update vectors; x = L_dd^{-1} v[0, w) into xp; v[w, m) into the update vector.
-// Shared memory: a staged 64 x 64 triangle, then w values.
+// forward, task (inst, s, chunk c): x[c0, c1) = L[c0:c1, c0:c1]^{-1} v[c0, c1)
+// in xp, by blocks of 64 columns (the block's triangle staged in shared memory,
+// wave 0 solves it, then the chunk's later rows take the block's update).
 __global__ void __launch_bounds__(kBlock)
-k_bigfwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
-    extern __shared__ double smem[];
-    double* T = smem;
-    double* v = smem + kTri;
+k_bigfwd_tri(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
+    __shared__ double T[kTri];
+    __shared__ double v[kChunk];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
     const Front F = front_of(I, tk.y);
     const int s = tk.y, tid = threadIdx.x, nthr = blockDim.x;
-    const double* rhs = solve_in(I, which);
-    double* us = I.uvec + I.S.uv_off[s];
-    for (int k = tid; k < F.w; k += nthr) v[k] = rhs[I.perm[F.f + k]];
-    for (int i = tid; i < F.m - F.w; i += nthr) us[i] = 0.0;
-    __syncthreads();
-    for (int ci = I.S.child_ptr[s]; ci < I.S.child_ptr[s + 1]; ++ci) {
-        const int c = I.S.child_list[ci];
-        const int nc = (int)(I.S.uv_off[c + 1] - I.S.uv_off[c]);
-        const double* uc = I.uvec + I.S.uv_off[c];
-        const int32_t* rc = I.S.rel + I.S.rel_off[c];
-        for (int i = tid; i < nc; i += nthr) {
-            const int p = rc[i];
-            if (p < F.w) v[p] += uc[i];
-            else us[p - F.w] += uc[i];
-        }
+    double* xs = I.xp + F.f;
+    if (tk.z == 0) {
+        const double* rhs = solve_in(I, which);
+        double* us = I.uvec + I.S.uv_off[s];
+        for (int k = tid; k < F.w; k += nthr) xs[k] = rhs[I.perm[F.f + k]];
+        for (int i = tid; i < F.m - F.w; i += nthr) us[i] = 0.0;
         __syncthreads();
+        for (int ci = I.S.child_ptr[s]; ci < I.S.child_ptr[s + 1]; ++ci) {
+            const int c = I.S.child_list[ci];
+            const int nc = (int)(I.S.uv_off[c + 1] - I.S.uv_off[c]);
+            const double* uc = I.uvec + I.S.uv_off[c];
+            const int32_t* rc = I.S.rel + I.S.rel_off[c];
+            for (int i = tid; i < nc; i += nthr) {
+                const int p = rc[i];
+                if (p < F.w) xs[p] += uc[i];
+                else us[p - F.w] += uc[i];
+            }
+            __syncthreads();
+        }
     }
-    // blocked forward substitution, 64 columns per block: the block's triangle
-    // is staged in shared memory, wave 0 solves it (lane j owns row b0 + j),
-    // then every thread updates the rows below the block inside the diagonal part
-    for (int b0 = 0; b0 < F.w; b0 += kWave) {
-        const int bw = min(kWave, F.w - b0), b1 = b0 + bw;
-        stage_triangle(F, b0, bw, T);
+    const int c0 = tk.z * kChunk, cw = min(kChunk, F.w - c0);
+    for (int k = tid; k < cw; k += nthr) v[k] = xs[c0 + k];
+    for (int b0 = 0; b0 < cw; b0 += kWave) {
+        const int bw = min(kWave, cw - b0), b1 = b0 + bw;
+        stage_triangle(F, c0 + b0, bw, T);
         __syncthreads();
         if (tid < kWave) {
             const int j = tid;
@@ -317,33 +330,36 @@ k_bigfwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, i
             if (j < bw) v[b0 + j] = vj;
         }
         __syncthreads();
-        for (int i = b1 + tid; i < F.w; i += nthr) {
+        for (int i = b1 + tid; i < cw; i += nthr) {
             double acc = v[i];
-            for (int k = b0; k < b1; ++k) acc = fma(-F.L[i + (int64_t)k * F.m], v[k], acc);
+            for (int k = b0; k < b1; ++k) acc = fma(-F.L[(c0 + i) + (int64_t)(c0 + k) * F.m], v[k], acc);
             v[i] = acc;
         }
         __syncthreads();
     }
-    for (int k = tid; k < F.w; k += nthr) I.xp[F.f + k] = v[k];
+    for (int k = tid; k < cw; k += nthr) xs[c0 + k] = v[k];
 }
 
-// forward, task (inst, s, row block): rows below the diagonal block,
-// u[i] -= L[w + i, 0:w) x.
+// forward, task (inst, s, chunk c, row block): rows i >= c1 of the block (one
+// per thread): v[i] -= L[i, c0:c1) x[c0, c1), in xp (i < w) or in the update
+// vector (i >= w).
 __global__ void __launch_bounds__(kBlock)
-k_bigfwd_below(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
-    extern __shared__ double x[];   // w values
+k_bigfwd_gemv(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    __shared__ double x[kChunk];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
     const Front F = front_of(I, tk.y);
-    for (int k = threadIdx.x; k < F.w; k += blockDim.x) x[k] = I.xp[F.f + k];
+    const int c0 = tk.z * kChunk, cw = min(kChunk, F.w - c0), c1 = c0 + cw;
+    for (int k = threadIdx.x; k < cw; k += blockDim.x) x[k] = I.xp[F.f + c0 + k];
     __syncthreads();
-    const int i = F.w + tk.z * kSolveRows + threadIdx.x;
+    const int i = c1 + tk.w * kSolveRows + threadIdx.x;
     if (i >= F.m) return;
-    double* us = I.uvec + I.S.uv_off[tk.y];
-    double acc = us[i - F.w];
-    for (int k = 0; k < F.w; ++k) acc = fma(-F.L[i + (int64_t)k * F.m], x[k], acc);
-    us[i - F.w] = acc;
+    const double* Li = F.L + i + (int64_t)c0 * F.m;
+    double acc = 0.0;
+    for (int k = 0; k < cw; ++k) acc = fma(Li[(int64_t)k * F.m], x[k], acc);
+    if (i < F.w) I.xp[F.f + i] -= acc;
+    else I.uvec[I.S.uv_off[tk.y] + (i - F.w)] -= acc;
 }
 
 // backward, task (inst, s, column block): bsum[f + k] = L[w:m, k]^T x(rows below)
@@ -366,27 +382,30 @@ k_bigbwd_below(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, 
     }
 }
 
-// backward, task (inst, s): v = xp[f, f + w) - bsum; solve L_dd^T x = v by
-// blocks from the last (the block's triangle staged in shared memory, wave 0
-// solves it, then every thread updates the earlier rows with the block's rows
-// of L); writes xp and the unpermuted solution.  Shared memory: a staged
-// triangle, then w values.
+// Whether bsum of a chunk's columns holds contributions: rows below the
+// supernode, or a later chunk.
+__device__ inline bool bsum_live(const Front& F, int c) { return F.m > F.w || (c + 1) * kChunk < F.w; }
+
+// backward, task (inst, s, chunk c): v = xp[c0, c1) - bsum; solve
+// L[c0:c1, c0:c1]^T x = v by blocks of 64 from the last (the block's triangle
+// staged in shared memory, wave 0 solves it, then the chunk's earlier columns
+// take the block's rows of L); writes xp and the unpermuted solution.
 __global__ void __launch_bounds__(kBlock)
-k_bigbwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
-    extern __shared__ double smem[];
-    double* T = smem;
-    double* v = smem + kTri;
+k_bigbwd_tri(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
+    __shared__ double T[kTri];
+    __shared__ double v[kChunk];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
     const Front F = front_of(I, tk.y);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const bool has_below = F.m > F.w;
-    for (int k = tid; k < F.w; k += nthr) v[k] = I.xp[F.f + k] - (has_below ? I.bsum[F.f + k] : 0.0);
-    const int nblk = (F.w + kWave - 1) / kWave;
+    const int c0 = tk.z * kChunk, cw = min(kChunk, F.w - c0);
+    const bool live = bsum_live(F, tk.z);
+    for (int k = tid; k < cw; k += nthr) v[k] = I.xp[F.f + c0 + k] - (live ? I.bsum[F.f + c0 + k] : 0.0);
+    const int nblk = (cw + kWave - 1) / kWave;
     for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int b0 = bi * kWave, bw = min(kWave, F.w - b0), b1 = b0 + bw;
-        stage_triangle(F, b0, bw, T);
+        const int b0 = bi * kWave, bw = min(kWave, cw - b0), b1 = b0 + bw;
+        stage_triangle(F, c0 + b0, bw, T);
         __syncthreads();
         if (tid < kWave) {
             const int j = tid;
@@ -401,40 +420,51 @@ k_bigbwd_diag(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, i
         __syncthreads();
         for (int c = tid; c < b0; c += nthr) {
             double acc = v[c];
-            const double* lc = F.L + (int64_t)c * F.m;
+            const double* lc = F.L + (int64_t)(c0 + c) * F.m + c0;
             for (int i = b0; i < b1; ++i) acc = fma(-lc[i], v[i], acc);
             v[c] = acc;
         }
         __syncthreads();
     }
     double* out = solve_out(I, which);
-    for (int k = tid; k < F.w; k += nthr) {
-        I.xp[F.f + k] = v[k];
-        out[I.perm[F.f + k]] = v[k];
+    for (int k = tid; k < cw; k += nthr) {
+        I.xp[F.f + c0 + k] = v[k];
+        out[I.perm[F.f + c0 + k]] = v[k];
+    }
+}
+
+// backward, task (inst, s, chunk c, column block): for the block's columns
+// k < c0, bsum[f + k] (+)= L[c0:c1, k]^T x[c0, c1) (the first contribution of a
+// supernode without rows below sets it); wave per column, lanes over the rows.
+__global__ void __launch_bounds__(kBlock)
+k_bigbwd_gemvt(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
+    __shared__ double x[kChunk];
+    const int4 tk = tasks[blockIdx.x];
+    const InstPtrs& I = Ia[tk.x];
+    if (!ctl_active(I.ctl, pred)) return;
+    const Front F = front_of(I, tk.y);
+    const int c0 = tk.z * kChunk, cw = min(kChunk, F.w - c0);
+    for (int k = threadIdx.x; k < cw; k += blockDim.x) x[k] = I.xp[F.f + c0 + k];
+    __syncthreads();
+    const bool live = bsum_live(F, tk.z);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int k0 = tk.w * kSolveCols;
+    for (int k = k0 + wv; k < min(c0, k0 + kSolveCols); k += nw) {
+        const double* lk = F.L + (int64_t)k * F.m + c0;
+        double acc = 0.0;
+        for (int i = lane; i < cw; i += kWave) acc = fma(lk[i], x[i], acc);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) I.bsum[F.f + k] = (live ? I.bsum[F.f + k] : 0.0) + acc;
     }
 }
 
 }  // namespace
 
-hipError_t big_configure(size_t lds_limit) {
-    // the diagonal solves hold a staged triangle and the supernode's w values,
-    // the forward GEMV the w solved values
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bigfwd_diag),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bigfwd_below), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_limit);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_bigbwd_diag),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
-}
-
-size_t big_solve_lds(int64_t w) { return sizeof(double) * ((size_t)kTri + (size_t)w); }
-
 int big_row_block() { return kRowBlock; }
 int big_tile() { return kTile; }
 int big_solve_rows() { return kSolveRows; }
 int big_solve_cols() { return kSolveCols; }
+int big_chunk() { return kChunk; }
 
 void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs* I, const int4* tasks, int count,
                 size_t lds_bytes, hipStream_t st) {
@@ -458,17 +488,20 @@ void launch_big(int kind, int pred, double eta_force, int which, const InstPtrs*
         case kBigUpdateInner:
             hipLaunchKernelGGL(k_big_update<true>, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
-        case kBigFwdDiag:
-            hipLaunchKernelGGL(k_bigfwd_diag, dim3(count), dim3(kBlock), lds_bytes, st, I, tasks, pred, which);
+        case kBigFwdTri:
+            hipLaunchKernelGGL(k_bigfwd_tri, dim3(count), dim3(kBlock), 0, st, I, tasks, pred, which);
             break;
-        case kBigFwdBelow:
-            hipLaunchKernelGGL(k_bigfwd_below, dim3(count), dim3(kSolveRows), lds_bytes, st, I, tasks, pred);
+        case kBigFwdGemv:
+            hipLaunchKernelGGL(k_bigfwd_gemv, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
         case kBigBwdBelow:
             hipLaunchKernelGGL(k_bigbwd_below, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
-        case kBigBwdDiag:
-            hipLaunchKernelGGL(k_bigbwd_diag, dim3(count), dim3(kBlock), lds_bytes, st, I, tasks, pred, which);
+        case kBigBwdTri:
+            hipLaunchKernelGGL(k_bigbwd_tri, dim3(count), dim3(kBlock), 0, st, I, tasks, pred, which);
+            break;
+        case kBigBwdGemvT:
+            hipLaunchKernelGGL(k_bigbwd_gemvt, dim3(count), dim3(kBlock), 0, st, I, tasks, pred);
             break;
         default:
             break;

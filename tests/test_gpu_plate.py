@@ -13,7 +13,7 @@ import scipy.sparse as sp
 
 from oracle import symbolic as S
 from oracle.adjoint import sensitivities
-from oracle.ipm import LiftedIPM
+from oracle.ipm import IPMState, LiftedIPM
 from oracle.kkt import kkt_error
 from oracle.plate import PlateOCP
 from paper_2606_04725_amd import nmpc as N
@@ -30,6 +30,30 @@ def _note(msg):
 def _close(a, b, tol):
     a, b = np.asarray(a), np.asarray(b)
     return float(np.max(np.abs(a - b))) / max(1.0, float(np.max(np.abs(b)))) <= tol
+
+
+def _assert_parity(m, ipm, sol, r, ref):
+    """GPU solve against the oracle's.  The barrier update is a threshold test
+    (E_mu <= kappa_eps mu); near a tie, rounding can take it the other way on
+    the two sides, and the runs then stop at barrier values one step apart.
+    Bound-active variables sit at y ~ mu / z there, so the iterates differ by
+    O(mu / z) and only the certificate is comparable: the KKT conditions of the
+    original problem and the optimal value.  With the same final barrier value
+    the iterates match to 1e-6."""
+    e = kkt_error(m, sol["y"], sol["lam"], np.zeros(0), sol["zL"], sol["zU"])
+    assert e["max"] <= 1e-8, e
+    f_ref = m.f(ref.state.y)
+    assert abs(m.f(sol["y"]) - f_ref) <= 1e-7 * max(1.0, abs(f_ref))
+    lam_ref = ref.state.omega[:m.m_c] - ref.state.omega[m.m_c:2 * m.m_c]
+    if r.mu == ref.mu:
+        assert r.iters == ref.iters
+        assert _close(sol["y"], ref.state.y, 1e-6)
+        assert _close(sol["lam"], lam_ref, 1e-6)
+    else:
+        o = ipm.o
+        step = lambda mu: max(o.mu_min, min(o.kappa_mu * mu, mu ** o.theta_mu))
+        assert step(r.mu) == ref.mu or step(ref.mu) == r.mu, (r.mu, ref.mu)
+        assert abs(r.iters - ref.iters) <= 2
 
 
 def _pair(G, H, seed=0):
@@ -113,21 +137,17 @@ def test_plate_solve_matches_oracle(G, H, seed):
     assert ref.status == 0
     r = p.solve(warm=False)
     assert r.status == 0
-    assert r.iters == ref.iters
     sol = p.solution()
-    assert _close(sol["y"], ref.state.y, 1e-6)
-    lam_ref = ref.state.omega[:m.m_c] - ref.state.omega[m.m_c:2 * m.m_c]
-    assert _close(sol["lam"], lam_ref, 1e-6)
-    e = kkt_error(m, sol["y"], sol["lam"], np.zeros(0), sol["zL"], sol["zU"])
-    assert e["max"] <= 1e-8, e
-    # warm re-solve after one plant step
+    _assert_parity(m, ipm, sol, r, ref)
+    # warm re-solve after one plant step, both sides from the GPU's iterate
     x1 = m.step(m.x0, sol["u1"])
     m.set_parameters(x0=x1)
     p.set_parameters(x1)
-    ref2 = ipm.solve(ref.state, ipm.o.mu0_warm)
+    it = p.get_iterate()
+    ref2 = ipm.solve(IPMState(it["y"], it["s"], it["omega"], it["beta"], it["zL"], it["zU"]), ipm.o.mu0_warm)
     r2 = p.solve(warm=True)
-    assert ref2.status == 0 and r2.status == 0 and r2.iters == ref2.iters
-    assert _close(p.solution()["y"], ref2.state.y, 1e-6)
+    assert ref2.status == 0 and r2.status == 0
+    _assert_parity(m, ipm, p.solution(), r2, ref2)
 
 
 def test_plate_adjoint_matches_oracle():
