@@ -97,13 +97,15 @@ struct Batch {
     int4* tasks = nullptr;
     std::vector<BLaunch> fac, fwd, bwd;
     bool has_distill = false, has_plate = false;
-    int* running = nullptr;        // device
-    int* hrunning = nullptr;       // pinned
+    int* running = nullptr;        // device: instances running, instances waiting for corrections
+    int* hrunning = nullptr;       // pinned copy
     Ctl* hctl = nullptr;           // pinned
-    hipEvent_t ev[6] = {};
-    hipGraph_t graph[2] = {nullptr, nullptr};        // untimed, timed
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    DevOpts graph_opts[2] = {};                       // options the graphs were captured with
+    hipEvent_t ev[8] = {};
+    // captured graphs, index timed + 2 * part: part 0 the pass, part 1 the
+    // second-order corrections (replayed only when an instance waits for them)
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    DevOpts graph_opts[4] = {};                       // options the graphs were captured with
     bool graph_failed[2] = {false, false};
     std::vector<void*> allocs;
 };
@@ -184,7 +186,7 @@ size_t lds_limit_bytes() {
 
 void batch_release(Batch* B) {
     if (!B) return;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (B->exec[k]) (void)hipGraphExecDestroy(B->exec[k]);
         if (B->graph[k]) (void)hipGraphDestroy(B->graph[k]);
     }
@@ -318,8 +320,8 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
     BTRY(upload(B->allocs, B->groups, gl));
     BTRY(upload(B->allocs, B->tasks, tl));
     BTRY(linalg_configure(lim));   // the device maximum, so every batch's launches fit
-    BTRY(dalloc(B->allocs, B->running, 1));
-    BTRY(hipHostMalloc((void**)&B->hrunning, sizeof(int), hipHostMallocDefault));
+    BTRY(dalloc(B->allocs, B->running, 2));
+    BTRY(hipHostMalloc((void**)&B->hrunning, 2 * sizeof(int), hipHostMallocDefault));
     BTRY(hipHostMalloc((void**)&B->hctl, sizeof(Ctl) * ni, hipHostMallocDefault));
     for (auto& e : B->ev) BTRY(hipEventCreate(&e));
 #undef BTRY
@@ -359,7 +361,10 @@ void solve_launches(Batch& B, int pred, int which) {
     for (const auto& L : B.bwd) run_launch(B, L, pred, 0.0, which);
 }
 
-// One pass of Algorithm 2 over every running instance.
+// One pass of Algorithm 2 over every running instance.  An instance whose first
+// trial point asks for second-order corrections waits in phase C; the
+// corrections run in their own part, enqueued before the next pass only when
+// some instance waits (most passes need none).
 void enqueue_pass(Batch& B, const DevOpts& o, bool timed) {
     hipStream_t st = B.stream;
     auto mark = [&](int k) {
@@ -380,20 +385,26 @@ void enqueue_pass(Batch& B, const DevOpts& o, bool timed) {
     launch_trial(B.dI, B.spaces, st);
     eval(B, false, kSrcTrial, kPhT);
     launch_phaseT(B.dI, B.spaces, B.ninst, o, st);
-    if (o.soc_max > 0) {
-        launch_soc_prepare(B.dI, B.spaces, st);
-        solve_launches(B, kPhC, 4);
-        launch_soc_step(B.dI, B.spaces, B.ninst, st);
-        eval(B, false, kSrcTrial, kPhC);
-        launch_soc_decide(B.dI, B.spaces, B.ninst, o, st);
-    }
     launch_update(B.dI, B.spaces, B.ninst, o, B.running, st);
     mark(5);
 }
 
-// Capture one pass as a graph (once per batch and timing mode).
-hipError_t ensure_graph(Batch& B, const DevOpts& o, bool timed) {
-    const int k = timed ? 1 : 0;
+void enqueue_corrections(Batch& B, const DevOpts& o, bool timed) {
+    hipStream_t st = B.stream;
+    if (timed) (void)hipEventRecord(B.ev[6], st);
+    launch_soc_prepare(B.dI, B.spaces, st);
+    solve_launches(B, kPhC, 4);
+    launch_soc_step(B.dI, B.spaces, B.ninst, st);
+    eval(B, false, kSrcTrial, kPhC);
+    launch_soc_decide(B.dI, B.spaces, B.ninst, o, st);
+    launch_update(B.dI, B.spaces, B.ninst, o, B.running, st);
+    if (timed) (void)hipEventRecord(B.ev[7], st);
+}
+
+// Capture one part (0: the pass, 1: the corrections) as a graph, once per
+// batch, timing mode and options.
+hipError_t ensure_graph(Batch& B, const DevOpts& o, bool timed, int part) {
+    const int k = (timed ? 1 : 0) + 2 * part;
     if (B.exec[k] && std::memcmp(&B.graph_opts[k], &o, sizeof(DevOpts)) == 0) return hipSuccess;
     if (B.exec[k]) {   // options changed: the kernels' arguments are part of the graph
         (void)hipGraphExecDestroy(B.exec[k]);
@@ -403,7 +414,8 @@ hipError_t ensure_graph(Batch& B, const DevOpts& o, bool timed) {
     }
     hipError_t e = hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    enqueue_pass(B, o, timed);
+    if (part == 0) enqueue_pass(B, o, timed);
+    else enqueue_corrections(B, o, timed);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(B.stream, &g);
     if (e != hipSuccess) {
@@ -887,7 +899,8 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
     double ms[5] = {0, 0, 0, 0, 0};
     const int k = timed ? 1 : 0;
     bool use_graph = o.graph != 0 && !B.graph_failed[k];
-    if (use_graph && ensure_graph(B, dop, timed) != hipSuccess) {
+    if (use_graph && (ensure_graph(B, dop, timed, 0) != hipSuccess ||
+                      (o.soc_max > 0 && ensure_graph(B, dop, timed, 1) != hipSuccess))) {
         (void)hipGetLastError();
         B.graph_failed[k] = true;
         use_graph = false;
@@ -897,22 +910,30 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
     const long max_passes = (long)(o.max_iter + 1) * (2L * o.ls_max + o.soc_max + 64) + 8;
     long passes = 0;
     int timing_lost = 0;
+    bool corrections = false;   // an instance waits for second-order corrections
     while (true) {
+        if (corrections) {
+            if (use_graph) HIP_TRY(hipGraphLaunch(B.exec[k + 2], st));
+            else enqueue_corrections(B, dop, timed);
+        }
         if (use_graph) {
             HIP_TRY(hipGraphLaunch(B.exec[k], st));
         } else {
             enqueue_pass(B, dop, timed);
             HIP_TRY(hipGetLastError());
         }
-        HIP_TRY(hipMemcpyAsync(B.hrunning, B.running, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(B.hrunning, B.running, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         ++passes;
         if (timed) {
             bool lost = false;
-            for (int ph = 0; ph < 5; ++ph) {
+            for (int ph = 0; ph < 6; ++ph) {
+                if (ph == 5 && !corrections) break;
                 float t = 0.0f;
-                if (hipEventElapsedTime(&t, B.ev[ph], B.ev[ph + 1]) == hipSuccess) {
-                    ms[ph] += t;
+                const hipError_t te = ph < 5 ? hipEventElapsedTime(&t, B.ev[ph], B.ev[ph + 1])
+                                             : hipEventElapsedTime(&t, B.ev[6], B.ev[7]);
+                if (te == hipSuccess) {
+                    ms[ph < 5 ? ph : 4] += t;   // corrections count as line search
                 } else {
                     (void)hipGetLastError();
                     lost = true;
@@ -924,7 +945,8 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
                 ++timing_lost;
             }
         }
-        if (*B.hrunning == 0) break;
+        corrections = B.hrunning[1] > 0;
+        if (B.hrunning[0] == 0) break;
         if (passes >= max_passes) {
             err = "solve: pass limit reached with instances still running";
             return NMPC_ERR_HIP;
@@ -1249,7 +1271,7 @@ void apply_variants(Device& D, const std::vector<int>& v) {
     Batch& B = *D.self;
     for (auto& L : B.fac)
         if (L.kind == kStepGroupFactor && L.step < (int)v.size()) L.variant = v[L.step];
-    for (int k = 0; k < 2; ++k) {   // the kernels' variants are part of the captured graphs
+    for (int k = 0; k < 4; ++k) {   // the kernels' variants are part of the captured graphs
         if (B.exec[k]) (void)hipGraphExecDestroy(B.exec[k]);
         if (B.graph[k]) (void)hipGraphDestroy(B.graph[k]);
         B.exec[k] = nullptr;

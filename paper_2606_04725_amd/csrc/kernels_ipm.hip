@@ -753,10 +753,10 @@ __global__ void __launch_bounds__(kBlock) k_update(const InstPtrs* __restrict__ 
 // End of a pass: accepted instances start their next iteration; count the
 // instances still running.
 __global__ void __launch_bounds__(kBlock) k_pass_end(const InstPtrs* __restrict__ Ia, int ninst, int* running) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
+    __shared__ int cnt, csoc;
+    if (threadIdx.x == 0) cnt = csoc = 0;
     __syncthreads();
-    int mine = 0;
+    int mine = 0, soc = 0;
     for (int i = threadIdx.x; i < ninst; i += kBlock) {
         Ctl* c = Ia[i].ctl;
         if (c->phase == kPhU) {
@@ -764,10 +764,15 @@ __global__ void __launch_bounds__(kBlock) k_pass_end(const InstPtrs* __restrict_
             c->phase = kPhA;
         }
         if (c->phase != kPhDone) ++mine;
+        if (c->phase == kPhC) ++soc;
     }
     if (mine) atomicAdd(&cnt, mine);
+    if (soc) atomicAdd(&csoc, soc);
     __syncthreads();
-    if (threadIdx.x == 0) *running = cnt;
+    if (threadIdx.x == 0) {
+        running[0] = cnt;
+        running[1] = csoc;
+    }
 }
 
 // cold start: push y into the bounds' interior (bound_push of magnitude and range)
