@@ -65,6 +65,7 @@ struct Device {
     hipStream_t stream = nullptr;
     InstPtrs hI{};                 // host copy of the instance descriptor
     std::vector<Step> fac, fwd, bwd;
+    std::vector<Step> fwd_rest;   // forward steps of the supernodes whose Newton-step forward solve is not fused
     int fac_launches = 0;          // kernel launches of one factorization
     int64_t stored_l = 0, nnzj = 0, nnzw = 0;
     std::vector<void*> allocs;
@@ -95,7 +96,7 @@ struct Batch {
     IpmSpaces spaces{};
     Group* groups = nullptr;
     int4* tasks = nullptr;
-    std::vector<BLaunch> fac, fwd, bwd;
+    std::vector<BLaunch> fac, fwd, bwd, fwd_rest;
     bool has_distill = false, has_plate = false;
     int* running = nullptr;        // device: instances running, instances waiting for corrections
     int* hrunning = nullptr;       // pinned copy
@@ -112,7 +113,6 @@ struct Batch {
 
 namespace {
 
-constexpr int kMediumFront = 256;   // largest front one workgroup factors in a global buffer
 
 inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -316,6 +316,7 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
     };
     merge(B->fac, &Device::fac);
     merge(B->fwd, &Device::fwd);
+    merge(B->fwd_rest, &Device::fwd_rest);
     merge(B->bwd, &Device::bwd);
     BTRY(upload(B->allocs, B->groups, gl));
     BTRY(upload(B->allocs, B->tasks, tl));
@@ -356,8 +357,10 @@ void factor_launches(Batch& B, int pred, double eta_force) {
     for (const auto& L : B.fac) run_launch(B, L, pred, eta_force, 0);
 }
 
-void solve_launches(Batch& B, int pred, int which) {
-    for (const auto& L : B.fwd) run_launch(B, L, pred, 0.0, which);
+// which == 0 in a pass: the factorization already ran the forward solve of the
+// fused supernodes, only the rest remain
+void solve_launches(Batch& B, int pred, int which, bool fused_done = false) {
+    for (const auto& L : fused_done ? B.fwd_rest : B.fwd) run_launch(B, L, pred, 0.0, which);
     for (const auto& L : B.bwd) run_launch(B, L, pred, 0.0, which);
 }
 
@@ -379,7 +382,7 @@ void enqueue_pass(Batch& B, const DevOpts& o, bool timed) {
     factor_launches(B, kPredFactor, 0.0);
     launch_decideF(B.dI, B.ninst, o, st);
     mark(3);
-    solve_launches(B, kPhS, 0);
+    solve_launches(B, kPhS, 0, true);
     launch_phaseE(B.dI, B.spaces, B.ninst, o, st);
     mark(4);
     launch_trial(B.dI, B.spaces, st);
@@ -528,9 +531,10 @@ nmpc_status device_init(Problem& p, std::string& err) {
         const size_t mr = (size_t)rows_of(sn);
         return mr * (mr + 1) / 2 * sizeof(double);
     };
+    // plus m values of the fused forward solve (shared memory in both cases)
     auto fac_bytes = [&](int sn) {
-        const size_t mr = (size_t)rows_of(sn);
-        return packed_bytes(sn) <= lim ? packed_bytes(sn) : mr * (mr | 1) * sizeof(double);
+        const size_t mr = (size_t)rows_of(sn), vb = mr * sizeof(double);
+        return packed_bytes(sn) + vb <= lim ? packed_bytes(sn) + vb : mr * (mr | 1) * sizeof(double);
     };
     auto sol_bytes = [&](int sn) {
         const size_t mr = (size_t)rows_of(sn), w = (size_t)width_of(sn);
@@ -543,11 +547,22 @@ nmpc_status device_init(Problem& p, std::string& err) {
         big_sol[sn] = sol_bytes(sn) > lim;
         if (!big_fac[sn] && fac_bytes(sn) > lim) medium_max = std::max<int>(medium_max, (int)mr);
     }
+    // Fused forward solves: a one-workgroup supernode whose whole subtree is
+    // one-workgroup as well runs the Newton step's forward solve right after its
+    // factorization (its children's update vectors are ready by then).
+    std::vector<int32_t> fused(nsn, 0);
+    for (int Lv = 0; Lv < sy.depth; ++Lv)
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
+            const int32_t sn = sy.level_list[i];
+            bool ok = !big_fac[sn] && !big_sol[sn];
+            for (int c = sy.child_ptr[sn]; ok && c < sy.child_ptr[sn + 1]; ++c) ok = fused[sy.child_list[c]] != 0;
+            fused[sn] = ok ? 1 : 0;
+        }
     // Schedule: per level (bottom-up) one group step for its small and medium
     // supernodes and the step sequence of the large path for its large ones; the
-    // top levels that hold at most kTailWidth supernodes, none large, form a
+    // top levels that hold at most kTailWidth supernodes (a chain), none large, form a
     // single group walked by one workgroup (a chain costs one launch).
-    constexpr int kTailWidth = 2;
+    constexpr int kTailWidth = 1;
     auto level_all_small = [&](int Lv) {
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i)
             if (big_fac[sy.level_list[i]] || big_sol[sy.level_list[i]]) return false;
@@ -632,20 +647,26 @@ nmpc_status device_init(Problem& p, std::string& err) {
     for (int Lv = tail; Lv < sy.depth; ++Lv)
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) tail_nodes.push_back(sy.level_list[i]);
     for (int Lv = 0; Lv < tail; ++Lv) {
-        Step gf, gs;
+        Step gf, gs, gr;
         gf.kind = kStepGroupFactor;
         gs.kind = kStepGroupFwd;
+        gr.kind = kStepGroupFwd;
         std::vector<int32_t> bigs, bsol;
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
             const int32_t sn = sy.level_list[i];
             if (big_fac[sn]) bigs.push_back(sn);
             else gf.groups.push_back(make_group({sn}));
-            if (big_sol[sn]) bsol.push_back(sn);
-            else gs.groups.push_back(make_group({sn}));
+            if (big_sol[sn]) {
+                bsol.push_back(sn);
+            } else {
+                gs.groups.push_back(make_group({sn}));
+                if (!fused[sn]) gr.groups.push_back(gs.groups.back());
+            }
         }
         if (!gf.groups.empty()) D.fac.push_back(gf);
         big_factor_steps(bigs);
         if (!gs.groups.empty()) D.fwd.push_back(gs);
+        if (!gr.groups.empty()) D.fwd_rest.push_back(gr);
         int64_t nch = 0;
         for (int32_t sn : bsol) nch = std::max<int64_t>(nch, ceil_div(width_of(sn), CH));
         for (int c = 0; c < nch; ++c) {
@@ -657,6 +678,8 @@ nmpc_status device_init(Problem& p, std::string& err) {
                 const int64_t c1 = std::min<int64_t>(w, c0 + CH);
                 for (int rb = 0; rb < ceil_div(m - c1, SR); ++rb) gv.push_back(int4{0, sn, c, rb});
             }
+            push(D.fwd_rest, kBigFwdTri, std::vector<int4>(tri));
+            push(D.fwd_rest, kBigFwdGemv, std::vector<int4>(gv));
             push(D.fwd, kBigFwdTri, std::move(tri));
             push(D.fwd, kBigFwdGemv, std::move(gv));
         }
@@ -668,6 +691,15 @@ nmpc_status device_init(Problem& p, std::string& err) {
         gb.kind = kStepGroupBwd;
         gf.groups.push_back(make_group(tail_nodes));
         gs.groups.push_back(gf.groups.back());
+        std::vector<int32_t> rest;
+        for (int32_t sn : tail_nodes)
+            if (!fused[sn]) rest.push_back(sn);
+        if (!rest.empty()) {
+            Step gr;
+            gr.kind = kStepGroupFwd;
+            gr.groups.push_back(make_group(rest));
+            D.fwd_rest.push_back(gr);
+        }
         gb.groups.push_back(make_group(std::vector<int32_t>(tail_nodes.rbegin(), tail_nodes.rend())));
         D.fac.push_back(gf);
         D.fwd.push_back(gs);
@@ -722,7 +754,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     for (int sn = 0; sn < nsn; ++sn) {
         if (big_fac[sn]) continue;
         const int64_t mr = rows_of(sn), ld = mr | 1;
-        const bool packed = packed_bytes(sn) <= lim;
+        const bool packed = fac_bytes(sn) <= lim;
         for (int32_t t = sy.k_ptr[sn]; t < sy.k_ptr[sn + 1]; ++t) {
             const int64_t pos = sy.k_fpos[t], r = pos % ld, c = pos / ld;
             const int64_t q = packed ? c * mr - c * (c + 1) / 2 + r : pos;
@@ -763,6 +795,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(upload_c(A, I.S.k_fpos, k_fpos));
     DTRY(upload_c(A, I.kcol_ptr, sy.kcol_ptr));
     DTRY(upload_c(A, I.S.sched_nodes, nodes));
+    DTRY(upload_c(A, I.S.fused, fused));
     DTRY(upload_c(A, I.k_wslot, sy.k_wslot));
     DTRY(upload_c(A, I.k_diag, sy.k_diag));
     DTRY(upload_c(A, I.kc_ptr, sy.kc_ptr));

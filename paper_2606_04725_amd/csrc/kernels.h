@@ -20,6 +20,7 @@ namespace nmpc {
 constexpr int kBlock = 256;          // threads per block of every vector kernel
 constexpr int kFactorBlock = 256;    // threads per supernode group
 constexpr int kPanel = 8;            // pivot columns per blocked step of a front
+constexpr int kMediumFront = 256;    // largest front one workgroup factors in a global buffer
 constexpr int kMaxQ = 12;            // reduced quantities per phase
 constexpr int kMaxSeed = 16;         // controls per stage the sensitivity seed can hold
 constexpr int kFilterCapMax = 256;   // filter entries an instance can hold
@@ -43,6 +44,7 @@ struct SnView {
     const int32_t* k_ptr;
     const int32_t* k_fpos;
     const int32_t* sched_nodes;   // supernodes in launch-schedule order
+    const int32_t* fused;         // 1: the Newton step's forward solve runs inside the factor kernel
 };
 
 // Phases of one Newton iteration of Algorithm 2 for one instance:

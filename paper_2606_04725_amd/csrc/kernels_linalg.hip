@@ -79,12 +79,65 @@ __device__ inline void child_round(const double* __restrict__ Uc, const int32_t*
     }
 }
 
+// Forward substitution for one supernode with its factored front still in F
+// (the Newton step's right-hand side, fused into the factorization): v gathers
+// the permuted right-hand side of the supernode's columns and the children's
+// update vectors, x = L_dd^{-1} v[0, w) goes to xp, v[w, m) - L_below x to the
+// supernode's update vector.  Columns go kPanel at a time: every thread solves
+// the small diagonal block itself from broadcast reads, then updates the rows
+// it owns.
+template <class Idx>
+__device__ void forward_in_front(int s, const SnView& S, const double* F, Idx ix, int m, int w,
+                                 const double* __restrict__ rhs, const int32_t* __restrict__ perm,
+                                 double* __restrict__ xp, double* __restrict__ uvec, double* v) {
+    const int f = S.sn_ptr[s];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int i = tid; i < m; i += nthr) v[i] = i < w ? rhs[perm[f + i]] : 0.0;
+    __syncthreads();
+    for (int ci = S.child_ptr[s]; ci < S.child_ptr[s + 1]; ++ci) {
+        const int c = S.child_list[ci];
+        const int nc = (int)(S.uv_off[c + 1] - S.uv_off[c]);
+        const double* uc = uvec + S.uv_off[c];
+        const int32_t* rc = S.rel + S.rel_off[c];
+        for (int i = tid; i < nc; i += nthr) v[rc[i]] += uc[i];
+        __syncthreads();
+    }
+    for (int kb = 0; kb < w; kb += kPanel) {
+        const int kw = min(kPanel, w - kb);
+        double x[kPanel];
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) {
+            double acc = k < kw ? v[kb + k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < k; ++j)
+                if (k < kw) acc = fma(-F[ix(kb + k, kb + j)], x[j], acc);
+            x[k] = k < kw ? acc / F[ix(kb + k, kb + k)] : 0.0;
+        }
+        if (tid < kw) {
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k)
+                if (k == tid) xp[f + kb + k] = x[k];
+        }
+        for (int r = kb + kw + tid; r < m; r += nthr) {
+            double acc = v[r];
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j)
+                if (j < kw) acc = fma(-F[ix(r, kb + j)], x[j], acc);
+            v[r] = acc;
+        }
+        __syncthreads();
+    }
+    double* us = uvec + S.uv_off[s];
+    for (int i = w + tid; i < m; i += nthr) us[i - w] = v[i];
+}
+
 // One supernode: assemble the front, factor it, store the L panel and update.
 // Shared-memory fronts are packed lower triangles; the global buffer of a
 // medium front is square with an odd leading dimension.
 template <bool Lds, int P>
 __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv, double eta, double* __restrict__ L,
-                           double* __restrict__ U, int* __restrict__ fail, double* F) {
+                           double* __restrict__ U, int* __restrict__ fail, double* F, double* v, const InstPtrs& I,
+                           bool fwd) {
     using Idx = typename std::conditional<Lds, PackedIdx, SquareIdx>::type;
     const int f = S.sn_ptr[s];
     const int w = S.sn_ptr[s + 1] - f;
@@ -172,6 +225,7 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
         for (int jj = wv; jj < nb; jj += nw)
             for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[ix(w + ii, w + jj)];
     }
+    if (fwd && S.fused[s]) forward_in_front(s, S, F, ix, m, w, I.rhs, I.perm, I.xp, I.uvec, v);
     __syncthreads();   // the front buffer is reused by the next supernode of the group
 }
 
@@ -184,10 +238,16 @@ k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ group
     const InstPtrs& I = Ia[g.inst];
     if (!ctl_active(I.ctl, pred)) return;
     const double eta = pred == kPredAll ? eta_force : I.ctl->eta;
-    // the front: shared memory, or the instance's global scratch for medium fronts
+    // the front: shared memory, or the instance's global scratch for medium
+    // fronts; then the fused forward solve's vector in shared memory
     double* F = Lds ? lds : I.gscratch + (int64_t)g.slot * I.gstride;
-    for (int i = g.begin; i < g.end; ++i)
-        factor_one<Lds, P>(I.S.sched_nodes[i], I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F);
+    const bool fwd = pred == kPredFactor;   // in a pass: the Newton step's right-hand side is assembled
+    for (int i = g.begin; i < g.end; ++i) {
+        const int s = I.S.sched_nodes[i];
+        const int m = (int)(I.S.rows_ptr[s + 1] - I.S.rows_ptr[s]);
+        double* v = Lds ? lds + (m * (m + 1)) / 2 : lds;
+        factor_one<Lds, P>(s, I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F, v, I, fwd);
+    }
 }
 
 // Triangular solves with one supernode's panel P (m x w, column-major, lower
@@ -399,8 +459,8 @@ void launch_variant(bool lds, int pred, double eta_force, const InstPtrs* I, con
         hipLaunchKernelGGL((k_factor_groups<true, Threads, P>), dim3(groups), dim3(Threads), lds_bytes, st, I, g, pred,
                            eta_force);
     else
-        hipLaunchKernelGGL((k_factor_groups<false, Threads, P>), dim3(groups), dim3(Threads), 0, st, I, g, pred,
-                           eta_force);
+        hipLaunchKernelGGL((k_factor_groups<false, Threads, P>), dim3(groups), dim3(Threads),
+                           kMediumFront * sizeof(double), st, I, g, pred, eta_force);
 }
 
 void launch_factor_groups(bool lds, int variant, int pred, double eta_force, const InstPtrs* I, const Group* g,
