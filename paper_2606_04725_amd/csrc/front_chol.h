@@ -33,8 +33,14 @@ struct PackedIdx {   // lower triangle packed by columns: column j holds rows j 
 //     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
 // A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
 // numerically positive definite); the arithmetic continues with pivot 1.
+// With fv, a forward substitution rides along: fv (shared memory, m values)
+// holds the right-hand side over the front's rows; each panel's x = D^{-1}
+// fv[panel] is formed from the registers holding D and written to xo, and
+// every row below takes fv[r] -= L[r, panel] x in step 2.  On return fv[w, m)
+// is the update vector of the rows below.
 template <int P, class Idx>
-__device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail) {
+__device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
+                                        double* xo = nullptr) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
     const int li = lane & 15, lk = lane >> 4;
@@ -68,6 +74,19 @@ __device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fa
         double rd[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) rd[k] = 1.0 / d[k][k];
+        double xk[P];
+        if (fv) {   // fv[kb, kb + kw) is final: every earlier panel updated it before the last barrier
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double acc = k < kw ? fv[kb + k] : 0.0;
+#pragma unroll
+                for (int j = 0; j < k; ++j) acc = fma(-d[k][j], xk[j], acc);
+                xk[k] = k < kw ? acc * rd[k] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                if (k == tid && k < kw) xo[kb + k] = xk[k];
+        }
         __syncthreads();   // every thread has read the diagonal block before it is overwritten
 #pragma unroll
         for (int i = 0; i < P; ++i)
@@ -89,6 +108,12 @@ __device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fa
 #pragma unroll
             for (int j = 0; j < P; ++j)
                 if (j < kw) F[ix(r, kb + j)] = a[j];
+            if (fv) {
+                double acc = fv[r];
+#pragma unroll
+                for (int j = 0; j < P; ++j) acc = fma(-a[j], xk[j], acc);
+                fv[r] = acc;
+            }
         }
         __syncthreads();
         const int t0 = kb + kw;

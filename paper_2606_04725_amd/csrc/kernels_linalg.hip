@@ -79,58 +79,6 @@ __device__ inline void child_round(const double* __restrict__ Uc, const int32_t*
     }
 }
 
-// Forward substitution for one supernode with its factored front still in F
-// (the Newton step's right-hand side, fused into the factorization): v gathers
-// the permuted right-hand side of the supernode's columns and the children's
-// update vectors, x = L_dd^{-1} v[0, w) goes to xp, v[w, m) - L_below x to the
-// supernode's update vector.  Columns go kPanel at a time: every thread solves
-// the small diagonal block itself from broadcast reads, then updates the rows
-// it owns.
-template <class Idx>
-__device__ void forward_in_front(int s, const SnView& S, const double* F, Idx ix, int m, int w,
-                                 const double* __restrict__ rhs, const int32_t* __restrict__ perm,
-                                 double* __restrict__ xp, double* __restrict__ uvec, double* v) {
-    const int f = S.sn_ptr[s];
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int i = tid; i < m; i += nthr) v[i] = i < w ? rhs[perm[f + i]] : 0.0;
-    __syncthreads();
-    for (int ci = S.child_ptr[s]; ci < S.child_ptr[s + 1]; ++ci) {
-        const int c = S.child_list[ci];
-        const int nc = (int)(S.uv_off[c + 1] - S.uv_off[c]);
-        const double* uc = uvec + S.uv_off[c];
-        const int32_t* rc = S.rel + S.rel_off[c];
-        for (int i = tid; i < nc; i += nthr) v[rc[i]] += uc[i];
-        __syncthreads();
-    }
-    for (int kb = 0; kb < w; kb += kPanel) {
-        const int kw = min(kPanel, w - kb);
-        double x[kPanel];
-#pragma unroll
-        for (int k = 0; k < kPanel; ++k) {
-            double acc = k < kw ? v[kb + k] : 0.0;
-#pragma unroll
-            for (int j = 0; j < k; ++j)
-                if (k < kw) acc = fma(-F[ix(kb + k, kb + j)], x[j], acc);
-            x[k] = k < kw ? acc / F[ix(kb + k, kb + k)] : 0.0;
-        }
-        if (tid < kw) {
-#pragma unroll
-            for (int k = 0; k < kPanel; ++k)
-                if (k == tid) xp[f + kb + k] = x[k];
-        }
-        for (int r = kb + kw + tid; r < m; r += nthr) {
-            double acc = v[r];
-#pragma unroll
-            for (int j = 0; j < kPanel; ++j)
-                if (j < kw) acc = fma(-F[ix(r, kb + j)], x[j], acc);
-            v[r] = acc;
-        }
-        __syncthreads();
-    }
-    double* us = uvec + S.uv_off[s];
-    for (int i = w + tid; i < m; i += nthr) us[i - w] = v[i];
-}
-
 // One supernode: assemble the front, factor it, store the L panel and update.
 // Shared-memory fronts are packed lower triangles; the global buffer of a
 // medium front is square with an odd leading dimension.
@@ -149,6 +97,11 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
     const int fsize = Lds ? (m * (m + 1)) / 2 : m * (m | 1);
     for (int e = tid; e < fsize; e += nthr) F[e] = 0.0;
+    // fused forward solve of the Newton step: v over the front's rows starts
+    // from the permuted right-hand side of the supernode's columns
+    const bool fw = fwd && S.fused[s];
+    if (fw)
+        for (int i = tid; i < m; i += nthr) v[i] = i < w ? I.rhs[I.perm[f + i]] : 0.0;
     // first round of the first child's update block in flight while the front
     // is cleared and the original entries are placed
     const int c0 = S.child_ptr[s], c1 = S.child_ptr[s + 1];
@@ -166,9 +119,16 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
         rel = S.rel + S.rel_off[c];
         e0 = 0;
     };
+    int cur_c = -1, cur_nc = 0;          // the child whose round is in va / pa
+    const int32_t* cur_rel = nullptr;
+    bool cur_first = false;
     if (ci < c1) {
         open_child(ci);
         child_round(Uc, rel, nc, ne, e0, ix, va, pa);
+        cur_c = S.child_list[ci];
+        cur_nc = nc;
+        cur_rel = rel;
+        cur_first = true;
     }
     __syncthreads();
     // original entries of the condensed matrix in this supernode's columns; a
@@ -207,8 +167,18 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
             if (pa[u] >= 0) F[pa[u]] += va[u];
+        if (fw && cur_first) {   // the child's update vector, with its first round
+            const double* uc = I.uvec + S.uv_off[cur_c];
+            for (int i = tid; i < cur_nc; i += nthr) v[cur_rel[i]] += uc[i];
+        }
         if (new_child || !next) __syncthreads();
         if (!next) break;
+        cur_first = new_child;
+        if (new_child) {
+            cur_c = S.child_list[cn];
+            cur_nc = nc;
+            cur_rel = rel;
+        }
         ci = cn;
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -216,7 +186,7 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
             pa[u] = pb[u];
         }
     }
-    partial_cholesky<P>(F, ix, m, w, fail);
+    partial_cholesky<P>(F, ix, m, w, fail, fw ? v : nullptr, fw ? I.xp + f : nullptr);
     double* Ls = L + S.l_off[s];
     for (int jc = wv; jc < w; jc += nw)
         for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = i >= jc ? F[ix(i, jc)] : 0.0;
@@ -225,7 +195,10 @@ __device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv
         for (int jj = wv; jj < nb; jj += nw)
             for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[ix(w + ii, w + jj)];
     }
-    if (fwd && S.fused[s]) forward_in_front(s, S, F, ix, m, w, I.rhs, I.perm, I.xp, I.uvec, v);
+    if (fw && nb > 0) {
+        double* us = I.uvec + S.uv_off[s];
+        for (int i = w + tid; i < m; i += nthr) us[i - w] = v[i];
+    }
     __syncthreads();   // the front buffer is reused by the next supernode of the group
 }
 
@@ -372,10 +345,12 @@ k_fwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, 
 
 // Back substitution L^T x = v for one supernode, after all its ancestors:
 // subtract the contribution of the rows below (already final), then solve
-// with the transposed diagonal block; writes x unpermuted.  The panel is
-// staged transposed (leading dimension w | 1) so that a thread per column
-// reads consecutive shared-memory words.
-// Shared memory: panel (m (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
+// with the transposed diagonal block; writes x unpermuted.  The rows below
+// are read straight from the panel, one wave per column (contiguous, lanes over
+// rows, a butterfly sums them); only the diagonal block is staged, transposed
+// (leading dimension w | 1), so that a thread per column reads consecutive
+// shared-memory words in the blocked solve.
+// Shared memory: diagonal block (w (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
 __device__ void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
                         const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
     const int f = S.sn_ptr[s];
@@ -383,40 +358,26 @@ __device__ void bwd_one(int s, const SnView& S, const double* __restrict__ L, do
     const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
     const int nb = m - w;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
     const int ld = w | 1;
     double* PT = lds;
-    double* rdiag = PT + (int64_t)m * ld;
+    double* rdiag = PT + (int64_t)w * ld;
     double* xb = rdiag + w;
     double* v = xb + nb;
     double* xs = v + w;
-    {
-        const double* Ls = L + S.l_off[s];
-        const int64_t lw = (int64_t)m * w;
-        for (int64_t base = 0; base < lw; base += (int64_t)nthr * kBatch) {
-            double t[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int64_t e = base + tid + (int64_t)u * nthr;
-                t[u] = e < lw ? Ls[e] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int64_t e = base + tid + (int64_t)u * nthr;
-                if (e < lw) {
-                    const int c = (int)(e / m), r = (int)(e - (int64_t)c * m);
-                    PT[c + (int64_t)r * ld] = t[u];
-                }
-            }
-        }
-        for (int k = tid; k < w; k += nthr) rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
-    }
+    const double* Ls = L + S.l_off[s];
+    for (int c = wv; c < w; c += nw)
+        for (int r = c + lane; r < w; r += kWave) PT[c + r * ld] = Ls[r + (int64_t)c * m];
+    for (int k = tid; k < w; k += nthr) rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
     const int32_t* rows = S.rows + S.rows_ptr[s];
     for (int i = tid; i < nb; i += nthr) xb[i] = xp[rows[w + i]];
     __syncthreads();
-    for (int jc = tid; jc < w; jc += nthr) {
-        double acc = xp[f + jc];
-        for (int i = 0; i < nb; ++i) acc = fma(-PT[jc + (int64_t)(w + i) * ld], xb[i], acc);
-        v[jc] = acc;
+    for (int jc = wv; jc < w; jc += nw) {
+        const double* col = Ls + (int64_t)jc * m + w;
+        double acc = 0.0;
+        for (int i = lane; i < nb; i += kWave) acc = fma(col[i], xb[i], acc);
+        for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) v[jc] = xp[f + jc] - acc;
     }
     __syncthreads();
     blocked_backward(PT, ld, rdiag, w, v, xs);
