@@ -39,7 +39,7 @@ struct PackedIdx {   // lower triangle packed by columns: column j holds rows j 
 // every row below takes fv[r] -= L[r, panel] x in step 2.  On return fv[w, m)
 // is the update vector of the rows below.
 template <int P, class Idx>
-__device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
+__device__ __attribute__((always_inline)) inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
                                         double* xo = nullptr) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
@@ -52,6 +52,7 @@ __device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fa
 #pragma unroll
             for (int j = 0; j < P; ++j)
                 d[i][j] = (j <= i && i < kw) ? F[ix(kb + i, kb + j)] : (i == j ? 1.0 : 0.0);
+        double rinv[P];
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -60,9 +61,11 @@ __device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fa
                 bad = true;
                 piv = 1.0;
             }
-            const double sq = sqrt(piv);
-            const double inv = 1.0 / sq;
-            d[k][k] = sq;
+            // one reciprocal square root per pivot: d_kk = piv / sqrt(piv), and the
+            // reciprocal doubles as the row solves' 1 / d_kk
+            const double inv = rsqrt(piv);
+            rinv[k] = inv;
+            d[k][k] = piv * inv;
 #pragma unroll
             for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
 #pragma unroll
@@ -73,7 +76,7 @@ __device__ inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fa
         if (bad && tid == 0) *fail = 1;
         double rd[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) rd[k] = 1.0 / d[k][k];
+        for (int k = 0; k < P; ++k) rd[k] = k < kw ? rinv[k] : 1.0;
         double xk[P];
         if (fv) {   // fv[kb, kb + kw) is final: every earlier panel updated it before the last barrier
 #pragma unroll

@@ -48,7 +48,7 @@ __device__ void g2s(T* dst, const T* __restrict__ src, int64_t n) {
 }
 
 // Entry e of the lower triangle of an n x n matrix packed by columns, as (i, j).
-__device__ inline void unpack_lower(int e, int n, int& i, int& j) {
+__device__ __attribute__((always_inline)) inline void unpack_lower(int e, int n, int& i, int& j) {
     const double b = 2.0 * n + 1.0;
     int c = (int)((b - sqrt(b * b - 8.0 * e)) * 0.5);
     c = max(0, min(c, n - 1));
@@ -62,7 +62,7 @@ __device__ inline void unpack_lower(int e, int n, int& i, int& j) {
 // its packed lower triangle (ne entries), each as a value and its position in
 // the parent front (through the child's relative row positions).
 template <class Idx>
-__device__ inline void child_round(const double* __restrict__ Uc, const int32_t* __restrict__ rel, int nc, int ne,
+__device__ __attribute__((always_inline)) inline void child_round(const double* __restrict__ Uc, const int32_t* __restrict__ rel, int nc, int ne,
                                    int e0, Idx ix, double (&v)[kBatch], int (&pos)[kBatch]) {
     const int tid = threadIdx.x, nthr = blockDim.x;
 #pragma unroll
@@ -83,7 +83,7 @@ __device__ inline void child_round(const double* __restrict__ Uc, const int32_t*
 // Shared-memory fronts are packed lower triangles; the global buffer of a
 // medium front is square with an odd leading dimension.
 template <bool Lds, int P>
-__device__ void factor_one(int s, const SnView& S, const double* __restrict__ kv, double eta, double* __restrict__ L,
+__device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S, const double* __restrict__ kv, double eta, double* __restrict__ L,
                            double* __restrict__ U, int* __restrict__ fail, double* F, double* v, const InstPtrs& I,
                            bool fwd) {
     using Idx = typename std::conditional<Lds, PackedIdx, SquareIdx>::type;
@@ -231,7 +231,7 @@ k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ group
 
 // Forward: v[0:m) holds b; on return xs[0:w) = L_dd^{-1} b[0:w) and
 // v[w:m) = b[w:m) - L_below xs.
-__device__ void blocked_forward(const double* P, const double* rdiag, int m, int w, double* v, double* xs) {
+__device__ __attribute__((always_inline)) void blocked_forward(const double* P, const double* rdiag, int m, int w, double* v, double* xs) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int kb = 0; kb < w; kb += kPanel) {
         const int kw = min(kPanel, w - kb);
@@ -262,7 +262,7 @@ __device__ void blocked_forward(const double* P, const double* rdiag, int m, int
 
 // Backward: v[0:w) holds the right-hand side of L_dd^T x = v; on return
 // xs[0:w) = x.  PT is the panel transposed: PT[c + r * ld] = L(r, c).
-__device__ void blocked_backward(const double* PT, int ld, const double* rdiag, int w, double* v, double* xs) {
+__device__ __attribute__((always_inline)) void blocked_backward(const double* PT, int ld, const double* rdiag, int w, double* v, double* xs) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nblk = (w + kPanel - 1) / kPanel;
     for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -294,7 +294,7 @@ __device__ void blocked_backward(const double* PT, int ld, const double* rdiag, 
 }
 
 // Stage one panel and the reciprocals of its diagonal in shared memory.
-__device__ void stage_panel(const double* __restrict__ Ls, int m, int w, double* P, double* rdiag) {
+__device__ __attribute__((always_inline)) void stage_panel(const double* __restrict__ Ls, int m, int w, double* P, double* rdiag) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     g2s(P, Ls, (int64_t)m * w);
     for (int k = tid; k < w; k += nthr) rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
@@ -304,7 +304,7 @@ __device__ void stage_panel(const double* __restrict__ Ls, int m, int w, double*
 // its columns, add the children's update vectors, solve with the diagonal
 // block, then form the update vector of its rows below.
 // Shared memory: panel (m w) + rdiag (w) + v (m) + xs (w).
-__device__ void fwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ uvec,
+__device__ __attribute__((always_inline)) void fwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ uvec,
                         const double* __restrict__ rhs, const int32_t* __restrict__ perm, double* __restrict__ xp,
                         double* lds) {
     const int f = S.sn_ptr[s];
@@ -346,12 +346,12 @@ k_fwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, 
 // Back substitution L^T x = v for one supernode, after all its ancestors:
 // subtract the contribution of the rows below (already final), then solve
 // with the transposed diagonal block; writes x unpermuted.  The rows below
-// are read straight from the panel, one wave per column (contiguous, lanes over
+// are read straight from the panel, 16 lanes per column (contiguous, lanes over
 // rows, a butterfly sums them); only the diagonal block is staged, transposed
 // (leading dimension w | 1), so that a thread per column reads consecutive
 // shared-memory words in the blocked solve.
 // Shared memory: diagonal block (w (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
-__device__ void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
+__device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
                         const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
     const int f = S.sn_ptr[s];
     const int w = S.sn_ptr[s + 1] - f;
@@ -372,12 +372,15 @@ __device__ void bwd_one(int s, const SnView& S, const double* __restrict__ L, do
     const int32_t* rows = S.rows + S.rows_ptr[s];
     for (int i = tid; i < nb; i += nthr) xb[i] = xp[rows[w + i]];
     __syncthreads();
-    for (int jc = wv; jc < w; jc += nw) {
+    // 16 lanes per column: nthr / 16 columns in flight, each lane's loads issued together
+    constexpr int kSub = 16;
+    const int sub = tid % kSub;
+    for (int jc = tid / kSub; jc < w; jc += nthr / kSub) {
         const double* col = Ls + (int64_t)jc * m + w;
         double acc = 0.0;
-        for (int i = lane; i < nb; i += kWave) acc = fma(col[i], xb[i], acc);
-        for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-        if (lane == 0) v[jc] = xp[f + jc] - acc;
+        for (int i = sub; i < nb; i += kSub) acc = fma(col[i], xb[i], acc);
+        for (int off = kSub / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSub);
+        if (sub == 0) v[jc] = xp[f + jc] - acc;
     }
     __syncthreads();
     blocked_backward(PT, ld, rdiag, w, v, xs);
