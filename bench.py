@@ -31,7 +31,8 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 def measured_traffic():
     """HBM bytes per factorization from the committed counter summary, or None
-    when the factorization kernels changed since the counters were taken."""
+    when a source of the factorization kernels changed since the counters were
+    taken (the summary lists the files and their SHA-256)."""
     import hashlib
     try:
         kv = {}
@@ -40,9 +41,13 @@ def measured_traffic():
                 continue
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-        src = os.path.join(os.path.dirname(TRAFFIC_FILE), "..", kv["source_file"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["source_sha256"]:
+        root = os.path.join(os.path.dirname(TRAFFIC_FILE), "..")
+        files, shas = kv["source_file"].split(), kv["source_sha256"].split()
+        if len(files) != len(shas):
             return None
+        for f, h in zip(files, shas):
+            if hashlib.sha256(open(os.path.join(root, f), "rb").read()).hexdigest() != h:
+                return None
         return float(kv["bytes_per_factorization"])
     except (OSError, KeyError, ValueError):
         return None

@@ -262,6 +262,29 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
  * kept factor; same conditions as nmpc_adjoint). */
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
 
+/* Device-pointer variants (Algorithm 1's parameter update, the solution read
+ * and the sensitivities without a host round trip, e.g. for tensors that live
+ * on the GPU).  Every pointer is a device address on the handle's GPU, owned by
+ * the caller; stream is a hipStream_t of the caller (NULL = the null stream).
+ * The library's work waits for everything already enqueued on stream and the
+ * work enqueued on stream afterwards waits for the library's, so buffers may
+ * be reused in stream order; the calls do not synchronize the host.
+ * Values are not checked on the host: a non-finite parameter shows up as the
+ * solve's NMPC_NONFINITE.  Requires nmpc_analyze (BAD_ORDER otherwise).
+ *
+ * nmpc_set_parameters_dev: as nmpc_set_parameters (NULL keeps the previous
+ *   setpoint / traj / u_prev; x0 may not be NULL).
+ * nmpc_get_solution_dev: as nmpc_get_solution, into device buffers.
+ * nmpc_adjoint_dev: as nmpc_adjoint; seed_u1[nu] and seed_obj (one value) are
+ *   device pointers (NULL = zero).  The first sensitivity call after a solve
+ *   factors K at the solution and waits for the library's stream once. */
+nmpc_status nmpc_set_parameters_dev(nmpc_problem* p, const double* x0, const double* setpoint,
+                                    const double* traj, const double* u_prev, void* stream);
+nmpc_status nmpc_get_solution_dev(const nmpc_problem* p, double* y, double* lam, double* omega_d,
+                                  double* zL, double* zU, double* u1, double* x1, void* stream);
+nmpc_status nmpc_adjoint_dev(nmpc_problem* p, const double* seed_u1, const double* seed_obj, double* grad_x0,
+                             double* grad_setpoint, double* grad_traj, double* grad_uprev, void* stream);
+
 /* Autotuner of the supernode front kernels (the batched form's tile shapes):
  * for every factor launch of the problem's schedule, time each variant of the
  * one-workgroup front kernel (threads per workgroup 128 / 256 / 512, panel

@@ -77,6 +77,10 @@ SIGNATURES = {
     "nmpc_linear_solve": (C.c_int32, [_P, _D, _D]),
     "nmpc_assemble": (C.c_int32, [_P, C.c_double, _D, _D]),
     "nmpc_adjoint": (C.c_int32, [_P, _D, C.c_double, _D, _D, _D, _D]),
+    # device pointers and the caller's stream as plain addresses (0 = NULL)
+    "nmpc_set_parameters_dev": (C.c_int32, [_P] + [C.c_void_p] * 5),
+    "nmpc_get_solution_dev": (C.c_int32, [_P] + [C.c_void_p] * 8),
+    "nmpc_adjoint_dev": (C.c_int32, [_P] + [C.c_void_p] * 7),
     "nmpc_jacobian_u1_x0": (C.c_int32, [_P, _D]),
     "nmpc_autotune": (C.c_int32, [_P, C.c_int32, _I]),
     "nmpc_batch_create": (C.c_int32, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
@@ -96,6 +100,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2606_04725_amd.build` (needs hipcc)")
+        # One HIP runtime per process: torch ships its own libamdhip64 (same
+        # SONAME, found through its own directory).  Loaded first, it also
+        # serves this library; loaded after this library it would come up as a
+        # second runtime that sees no device, so torch goes first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         h = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(h, name)

@@ -81,6 +81,35 @@ nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac) {
     return rc >= 0 ? rc : fail(rc, err);
 }
 
+nmpc_status nmpc_set_parameters_dev(nmpc_problem* p, const double* x0, const double* setpoint, const double* traj,
+                                    const double* u_prev, void* stream) {
+    if (!p || !x0) return fail(NMPC_ERR_INVALID_ARG, "set_parameters_dev: NULL handle or x0");
+    if (!p->impl.analyzed || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "set_parameters_dev: call nmpc_analyze first");
+    nmpc::device_invalidate_adjoint(p->impl);
+    std::string err;
+    nmpc_status rc = nmpc::device_set_parameters_dev(p->impl, x0, setpoint, traj, u_prev, stream, err);
+    return rc == NMPC_OK ? rc : fail(rc, err);
+}
+
+nmpc_status nmpc_get_solution_dev(const nmpc_problem* p, double* y, double* lam, double* omega_d, double* zL,
+                                  double* zU, double* u1, double* x1, void* stream) {
+    if (!p) return fail(NMPC_ERR_INVALID_ARG, "get_solution_dev: NULL handle");
+    if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "get_solution_dev: no solution yet");
+    std::string err;
+    nmpc_status rc = nmpc::device_get_solution_dev(p->impl, y, lam, omega_d, zL, zU, u1, x1, stream, err);
+    return rc == NMPC_OK ? rc : fail(rc, err);
+}
+
+nmpc_status nmpc_adjoint_dev(nmpc_problem* p, const double* seed_u1, const double* seed_obj, double* grad_x0,
+                             double* grad_setpoint, double* grad_traj, double* grad_uprev, void* stream) {
+    if (!p) return fail(NMPC_ERR_INVALID_ARG, "adjoint_dev: NULL handle");
+    if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "adjoint_dev: no solution yet");
+    std::string err;
+    nmpc_status rc = nmpc::device_adjoint_dev(p->impl, seed_u1, seed_obj, grad_x0, grad_setpoint, grad_traj,
+                                              grad_uprev, stream, err);
+    return rc >= 0 ? rc : fail(rc, err);
+}
+
 nmpc_status nmpc_autotune(nmpc_problem* p, int32_t reps, int32_t* changed) {
     if (!p || reps < 1) return fail(NMPC_ERR_INVALID_ARG, "autotune: NULL handle or reps < 1");
     if (!p->impl.analyzed) return fail(NMPC_ERR_BAD_ORDER, "autotune: call nmpc_analyze first");

@@ -74,6 +74,8 @@ struct Device {
     bool adj_ready = false;
     double adj_eta = 0.0;
     double gamma_last = 1e-9;
+    // ordering against a caller's stream (the entry points taking device pointers)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 // Emitted kernel launch of a batch schedule: a group launch (groups[off ..
@@ -452,6 +454,8 @@ void device_free(Problem& p) {
     if (D.stream) (void)hipStreamSynchronize(D.stream);
     batch_release(D.self);
     for (void* a : D.allocs) (void)hipFree(a);
+    if (D.ev_in) (void)hipEventDestroy(D.ev_in);
+    if (D.ev_out) (void)hipEventDestroy(D.ev_out);
     if (D.stream) (void)hipStreamDestroy(D.stream);
     delete p.dev;
     p.dev = nullptr;
@@ -477,6 +481,8 @@ nmpc_status device_init(Problem& p, std::string& err) {
         }                                                                              \
     } while (0)
     DTRY(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking));
+    DTRY(hipEventCreateWithFlags(&D.ev_in, hipEventDisableTiming));
+    DTRY(hipEventCreateWithFlags(&D.ev_out, hipEventDisableTiming));
     InstPtrs& I = D.hI;
     I.family = st.desc.family;
     I.n = st.n;
@@ -828,6 +834,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(dalloc(A, I.uvec, sy.stored_uv));
     DTRY(dalloc(A, I.adj_rhs, n)); DTRY(dalloc(A, I.adj_w, n));
     DTRY(dalloc(A, I.adj_out, st.nx + I.nsp + I.ntr + st.nu));
+    DTRY(dalloc(A, I.adj_seed, st.nu + 1));
     DTRY(dalloc(A, I.adj_b, n)); DTRY(dalloc(A, I.adj_d, n)); DTRY(dalloc(A, I.adj_lam, m));
     DTRY(dalloc(A, I.adj_qr, m));
     DTRY(dalloc(A, I.bsum, n));
@@ -909,25 +916,11 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
     }
     HIP_TRY(hipMemcpyAsync(B.ctl, B.hctl, sizeof(Ctl) * ni, hipMemcpyHostToDevice, st));
     if (!warm) {
-        // initial guess: every stage holds the measured state and the last control
-        std::vector<std::vector<double>> guesses(ni);
-        for (int i = 0; i < ni; ++i) {
-            const Problem& p = *B.members[i]->owner;
-            const int nx = p.st.nx, nu = p.st.nu, ns = nx + nu;
-            auto& yg = guesses[i];
-            yg.assign(p.st.n, 0.0);
-            for (int k = 0; k < p.st.H; ++k) {
-                for (int j = 0; j < nx; ++j) yg[k * ns + j] = p.x0[j];
-                for (int j = 0; j < nu; ++j) yg[k * ns + nx + j] = p.u_prev[j];
-            }
-            HIP_TRY(hipMemcpyAsync(B.members[i]->hI.y, yg.data(), yg.size() * sizeof(double),
-                                   hipMemcpyHostToDevice, st));
-        }
+        launch_cold_guess(B.dI, B.spaces.sp[kSpN], st);   // every stage: the measured state, the last control
         launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, false, st);
         eval(B, false, kSrcIter, kPredAll);
         launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, true, st);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipStreamSynchronize(st));   // the host guesses must outlive their copies
     }
     double ms[5] = {0, 0, 0, 0, 0};
     const int k = timed ? 1 : 0;
@@ -1207,16 +1200,16 @@ nmpc_status adjoint_prepare(Problem& p, std::string& err) {
     return NMPC_OK;
 }
 
-nmpc_status adjoint_apply(Problem& p, const double* seed_u1, double seed_obj, std::vector<double>& out,
-                          std::string& err) {
+// Sensitivity solve for the seed already placed in adj_seed (on the library's
+// stream): rhs, solve, refinement, parameter contractions into adj_out.
+nmpc_status adjoint_run(Problem& p, std::string& err) {
     Device& D = *p.dev;
     Batch& B = *D.self;
-    const Structure& st = p.st;
-    if (st.nu > kMaxSeed) {
+    if (p.st.nu > kMaxSeed) {
         err = "adjoint: too many controls per stage";
         return NMPC_ERR_UNSUPPORTED;
     }
-    launch_adj_seed(B.dI, B.spaces.sp[kSpN], seed_u1, st.nu, seed_obj, B.stream);
+    launch_adj_seed(B.dI, B.spaces.sp[kSpN], B.stream);
     solve_launches(B, kPredAll, 2);
     // refinement against the uncondensed system: the condensed matrix rounds the
     // curvature next to the lifted weights, the uncondensed residual does not
@@ -1226,12 +1219,41 @@ nmpc_status adjoint_apply(Problem& p, const double* seed_u1, double seed_obj, st
         solve_launches(B, kPredAll, 3);
         launch_adj_refine(2, B.dI, B.spaces, D.adj_eta, B.stream);
     }
-    launch_adj_gather(B.dI, D.hI.family, D.hI.nx, seed_obj, B.stream);
+    launch_adj_gather(B.dI, D.hI.family, D.hI.nx, B.stream);
     HIP_TRY(hipGetLastError());
-    out.resize(st.nx + D.hI.nsp + D.hI.ntr + st.nu);
-    HIP_TRY(hipMemcpyAsync(out.data(), D.hI.adj_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, B.stream));
-    HIP_TRY(hipStreamSynchronize(B.stream));
     return NMPC_OK;
+}
+
+nmpc_status adjoint_apply(Problem& p, const double* seed_u1, double seed_obj, std::vector<double>& out,
+                          std::string& err) {
+    Device& D = *p.dev;
+    const Structure& st = p.st;
+    std::vector<double> sb(st.nu + 1, 0.0);
+    for (int j = 0; j < st.nu; ++j) sb[j] = seed_u1 ? seed_u1[j] : 0.0;
+    sb[st.nu] = seed_obj;
+    HIP_TRY(hipMemcpyAsync(D.hI.adj_seed, sb.data(), sb.size() * sizeof(double), hipMemcpyHostToDevice, D.stream));
+    nmpc_status rc = adjoint_run(p, err);
+    if (rc != NMPC_OK) return rc;
+    out.resize(st.nx + D.hI.nsp + D.hI.ntr + st.nu);
+    HIP_TRY(hipMemcpyAsync(out.data(), D.hI.adj_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, D.stream));
+    HIP_TRY(hipStreamSynchronize(D.stream));
+    return NMPC_OK;
+}
+
+// The library's stream waits for the work already on the caller's stream ...
+hipError_t join_in(Device& D, hipStream_t caller) {
+    hipError_t e = hipEventRecord(D.ev_in, caller);
+    return e != hipSuccess ? e : hipStreamWaitEvent(D.stream, D.ev_in, 0);
+}
+
+// ... and the caller's stream waits for the library's work enqueued since.
+hipError_t join_out(Device& D, hipStream_t caller) {
+    hipError_t e = hipEventRecord(D.ev_out, D.stream);
+    return e != hipSuccess ? e : hipStreamWaitEvent(caller, D.ev_out, 0);
+}
+
+hipError_t copy_d2d(double* dst, const double* src, size_t n, hipStream_t st) {
+    return (dst && src && n) ? hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st) : hipSuccess;
 }
 
 }  // namespace
@@ -1251,6 +1273,61 @@ nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, d
     if (gtraj && ntr) std::copy(o + st.nx + nsp, o + st.nx + nsp + ntr, gtraj);
     if (gup) std::copy(o + st.nx + nsp + ntr, o + st.nx + nsp + ntr + st.nu, gup);
     return p.dev->adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
+}
+
+nmpc_status device_set_parameters_dev(Problem& p, const double* x0, const double* setpoint, const double* traj,
+                                     const double* u_prev, void* caller_stream, std::string& err) {
+    const hipStream_t caller = static_cast<hipStream_t>(caller_stream);
+    Device& D = *p.dev;
+    const InstPtrs& I = D.hI;
+    HIP_TRY(join_in(D, caller));
+    // the parameter buffers are read-only for the kernels, owned by the library
+    HIP_TRY(copy_d2d(const_cast<double*>(I.x0), x0, (size_t)I.nx, D.stream));
+    HIP_TRY(copy_d2d(const_cast<double*>(I.setp), setpoint, (size_t)I.nsp, D.stream));
+    HIP_TRY(copy_d2d(const_cast<double*>(I.zF), traj, (size_t)I.ntr, D.stream));
+    HIP_TRY(copy_d2d(const_cast<double*>(I.uprev), u_prev, (size_t)I.nu, D.stream));
+    HIP_TRY(join_out(D, caller));
+    return NMPC_OK;
+}
+
+nmpc_status device_get_solution_dev(const Problem& p, double* y, double* lam, double* omega_d, double* zl,
+                                    double* zu, double* u1, double* x1, void* caller_stream, std::string& err) {
+    const hipStream_t caller = static_cast<hipStream_t>(caller_stream);
+    Device& D = *p.dev;
+    const InstPtrs& I = D.hI;
+    HIP_TRY(join_in(D, caller));
+    HIP_TRY(copy_d2d(y, I.y, (size_t)I.n, D.stream));
+    HIP_TRY(copy_d2d(zl, I.zl, (size_t)I.n, D.stream));
+    HIP_TRY(copy_d2d(zu, I.zu, (size_t)I.n, D.stream));
+    HIP_TRY(copy_d2d(u1, I.y + I.nx, (size_t)I.nu, D.stream));
+    HIP_TRY(copy_d2d(x1, I.y, (size_t)I.nx, D.stream));
+    if (lam || omega_d) launch_export_duals(D.self->dI, lam, omega_d, std::max(I.mc, I.md), D.stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(join_out(D, caller));
+    return NMPC_OK;
+}
+
+nmpc_status device_adjoint_dev(Problem& p, const double* seed_u1, const double* seed_obj, double* gx0, double* gsp,
+                               double* gtraj, double* gup, void* caller_stream, std::string& err) {
+    const hipStream_t caller = static_cast<hipStream_t>(caller_stream);
+    nmpc_status rc = adjoint_prepare(p, err);   // once per solution; may wait for the library's stream
+    if (rc != NMPC_OK) return rc;
+    Device& D = *p.dev;
+    const InstPtrs& I = D.hI;
+    HIP_TRY(join_in(D, caller));
+    if (seed_u1) HIP_TRY(copy_d2d(I.adj_seed, seed_u1, (size_t)I.nu, D.stream));
+    else HIP_TRY(hipMemsetAsync(I.adj_seed, 0, I.nu * sizeof(double), D.stream));
+    if (seed_obj) HIP_TRY(copy_d2d(I.adj_seed + I.nu, seed_obj, 1, D.stream));
+    else HIP_TRY(hipMemsetAsync(I.adj_seed + I.nu, 0, sizeof(double), D.stream));
+    rc = adjoint_run(p, err);
+    if (rc != NMPC_OK) return rc;
+    const size_t nx = I.nx, nsp = I.nsp, ntr = I.ntr;
+    HIP_TRY(copy_d2d(gx0, I.adj_out, nx, D.stream));
+    HIP_TRY(copy_d2d(gsp, I.adj_out + nx, nsp, D.stream));
+    HIP_TRY(copy_d2d(gtraj, I.adj_out + nx + nsp, ntr, D.stream));
+    HIP_TRY(copy_d2d(gup, I.adj_out + nx + nsp + ntr, (size_t)I.nu, D.stream));
+    HIP_TRY(join_out(D, caller));
+    return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
 
 nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err) {

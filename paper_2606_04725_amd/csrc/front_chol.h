@@ -123,12 +123,16 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
         const int T = m - t0;
         if (T > 0) {
             const int nt = (T + 15) / 16;
-            const int ntiles = nt * (nt + 1) / 2;
-            for (int tile = wv; tile < ntiles; tile += nw) {
-                int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-                while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-                while (ti * (ti + 1) / 2 > tile) --ti;
-                const int tj = tile - ti * (ti + 1) / 2;
+            // lower-triangle tiles in row order, dealt to the waves round-robin
+            int owner = 0, ti = 0, tj = -1;
+            for (int tt = 0; tt < nt * (nt + 1) / 2; ++tt) {
+                if (++tj > ti) {
+                    ++ti;
+                    tj = 0;
+                }
+                const int mine = owner == wv;
+                owner = owner + 1 == nw ? 0 : owner + 1;
+                if (!mine) continue;
                 const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll

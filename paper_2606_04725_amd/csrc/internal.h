@@ -80,6 +80,14 @@ void symbolic_analyze(const Structure& st, Symbolic& sym);
 nmpc_status device_init(Problem& p, std::string& err);
 void device_free(Problem& p);
 nmpc_status device_set_parameters(Problem& p, std::string& err);
+// Entry points on device pointers, ordered after the work on the caller's
+// stream; the caller's stream is ordered after them (no host synchronization).
+nmpc_status device_set_parameters_dev(Problem& p, const double* x0, const double* setpoint, const double* traj,
+                                     const double* u_prev, void* caller, std::string& err);
+nmpc_status device_get_solution_dev(const Problem& p, double* y, double* lam, double* omega_d, double* zl,
+                                    double* zu, double* u1, double* x1, void* caller, std::string& err);
+nmpc_status device_adjoint_dev(Problem& p, const double* seed_u1, const double* seed_obj, double* gx0, double* gsp,
+                               double* gtraj, double* gup, void* caller, std::string& err);
 nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err);
 nmpc_status device_get_iterate(const Problem& p, double* y, double* s, double* om, double* be,
                                double* zl, double* zu, std::string& err);

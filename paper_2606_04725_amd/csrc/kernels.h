@@ -122,6 +122,7 @@ struct InstPtrs {
     double *r1v, *r4s, *vcomb_s, *rhs_s, *dy_s, *ds_s, *dom_s, *dbe_s, *dzl_s, *dzu_s;
     double *kv, *L, *U, *uvec;
     double *adj_rhs, *adj_w, *adj_out, *adj_b, *adj_d, *adj_lam, *adj_qr;
+    double* adj_seed;   // seed of the sensitivities: u1 part (nu values), then the objective's
     const int32_t *wf_ptr, *wf_slot, *wf_col;   // Hessian rows, both triangles: (slot, column)
     double* gscratch;
     int64_t gstride;
@@ -216,10 +217,12 @@ void launch_cold_start(const InstPtrs* I, const IpmSpaces& S, double bound_push,
                        bool after_eval, hipStream_t st);
 void launch_set_fail(const InstPtrs* I, int ninst, int value, hipStream_t st);
 // sensitivities: rhs = seed_obj grad f + S_u^T seed_u, and the parameter contractions
-void launch_adj_seed(const InstPtrs* I, const Space& spN, const double* seed_u, int nu, double seed_obj,
-                     hipStream_t st);
+void launch_adj_seed(const InstPtrs* I, const Space& spN, hipStream_t st);   // seed from adj_seed
+void launch_cold_guess(const InstPtrs* I, const Space& spN, hipStream_t st);
+// lam = omega+ - omega- and the inequality multipliers of instance 0 into caller buffers (NULL skips)
+void launch_export_duals(const InstPtrs* I, double* lam, double* om_d, int rows, hipStream_t st);
 // out = [x0 (nx) | setpoint (nsp) | trajectory (ntr) | u_prev (nu)] for instance 0
-void launch_adj_gather(const InstPtrs* I, int family, int nx, double seed_obj, hipStream_t st);
+void launch_adj_gather(const InstPtrs* I, int family, int nx, hipStream_t st);
 // Refinement of w = K^{-1} b against the uncondensed system [K0 J^T; J -Q^{-1}]
 // (K0 = W + Sigma + eta I): start sets lam = Q J w; residual forms
 // adj_rhs = b - K0 w - J^T lam + J^T qr with qr = lam - Q J w; update adds the

@@ -823,22 +823,28 @@ __global__ void k_set_fail(const InstPtrs* __restrict__ Ia, int ninst, int value
 }
 
 // ---- sensitivities ------------------------------------------------------------------
-struct Seed {
-    double u[kMaxSeed];
-};
-
-// rhs = seed_obj * grad f + S_u^T seed_u (first-stage controls at positions nx .. nx + nu)
-__global__ void __launch_bounds__(kBlock) k_adj_seed(const InstPtrs* __restrict__ Ia, Space sp, Seed seed,
-                                                    double seed_obj) {
+// rhs = seed_obj * grad f + S_u^T seed_u (first-stage controls at positions nx .. nx + nu);
+// the seed sits in adj_seed (u part, then seed_obj)
+__global__ void __launch_bounds__(kBlock) k_adj_seed(const InstPtrs* __restrict__ Ia, Space sp) {
     int lb;
     const int inst = block_inst(sp, lb);
     const InstPtrs& I = Ia[inst];
     const int j = lb * kBlock + threadIdx.x;
     if (j >= I.n) return;
-    double v = seed_obj * I.grad[j];
-    if (j >= I.nx && j < I.nx + I.nu) v += seed.u[j - I.nx];
+    double v = I.adj_seed[I.nu] * I.grad[j];
+    if (j >= I.nx && j < I.nx + I.nu) v += I.adj_seed[j - I.nx];
     I.adj_b[j] = v;
     I.adj_rhs[j] = v;
+}
+
+// cold start, first guess: every stage holds the measured state and the last control
+__global__ void __launch_bounds__(kBlock) k_cold_guess(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    const int j = lb * kBlock + threadIdx.x;
+    if (j >= I.n) return;
+    const int ns = I.nx + I.nu, r = j % ns;
+    I.y[j] = r < I.nx ? I.x0[r] : I.uprev[r - I.nx];
 }
 
 __device__ inline double row_dot(const InstPtrs& I, int r, const double* __restrict__ v) {
@@ -898,9 +904,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_update(const InstPtrs* __restric
 //   xD*, xB*: 2 sum_k w(top|bottom state) - 2 seed_obj sum_k (state - setpoint)
 //   u_prev:   2 rho w(u_1) - 2 rho seed_obj (u_1 - u_prev)
 // out = [x0 (nx) | setpoint (2) | traj (H) | u_prev (2)]
-__global__ void __launch_bounds__(kBlock) k_adj_gather_distill(const InstPtrs* __restrict__ Ia, double seed_obj) {
+__global__ void __launch_bounds__(kBlock) k_adj_gather_distill(const InstPtrs* __restrict__ Ia) {
     __shared__ double sh[kMaxQ * kWaves];
     const InstPtrs& I = Ia[0];
+    const double seed_obj = I.adj_seed[I.nu];
     const DistillDims D = I.dd;
     const DistillConst C = I.dc;
     const double* w = I.adj_w;
@@ -942,8 +949,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_distill(const InstPtrs* _
 //   T*_p:  2 sum_k w(T_kp) - 2 seed_obj sum_k (T_kp - T*_p)
 //   u_prev: 0 (it enters no function of the problem)
 // out = [x0 (nx) | setpoint (nx) | u_prev (16)]; one thread per node.
-__global__ void __launch_bounds__(kBlock) k_adj_gather_plate(const InstPtrs* __restrict__ Ia, double seed_obj) {
+__global__ void __launch_bounds__(kBlock) k_adj_gather_plate(const InstPtrs* __restrict__ Ia) {
     const InstPtrs& I = Ia[0];
+    const double seed_obj = I.adj_seed[I.nu];
     const PlateDims D = I.pd;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     double* out = I.adj_out;
@@ -1031,11 +1039,25 @@ void launch_set_fail(const InstPtrs* I, int ninst, int value, hipStream_t st) {
     hipLaunchKernelGGL(k_set_fail, dim3((ninst + 63) / 64), dim3(64), 0, st, I, ninst, value);
 }
 
-void launch_adj_seed(const InstPtrs* I, const Space& spN, const double* seed_u, int nu, double seed_obj,
-                     hipStream_t st) {
-    Seed sd{};
-    for (int j = 0; j < nu && j < kMaxSeed; ++j) sd.u[j] = seed_u[j];
-    hipLaunchKernelGGL(k_adj_seed, dim3(spN.blocks), dim3(kBlock), 0, st, I, spN, sd, seed_obj);
+void launch_adj_seed(const InstPtrs* I, const Space& spN, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_seed, dim3(spN.blocks), dim3(kBlock), 0, st, I, spN);
+}
+
+// lam = omega+ - omega- (equality multipliers of the original problem) and the
+// multipliers of the inequality rows, written to caller buffers (instance 0)
+__global__ void __launch_bounds__(kBlock) k_export_duals(const InstPtrs* __restrict__ Ia, double* lam, double* om_d) {
+    const InstPtrs& I = Ia[0];
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (lam && r < I.mc) lam[r] = I.om[r] - I.om[I.mc + r];
+    if (om_d && r < I.md) om_d[r] = I.om[2 * I.mc + r];
+}
+
+void launch_export_duals(const InstPtrs* I, double* lam, double* om_d, int rows, hipStream_t st) {
+    if (rows > 0) hipLaunchKernelGGL(k_export_duals, dim3((rows + kBlock - 1) / kBlock), dim3(kBlock), 0, st, I, lam, om_d);
+}
+
+void launch_cold_guess(const InstPtrs* I, const Space& spN, hipStream_t st) {
+    hipLaunchKernelGGL(k_cold_guess, dim3(spN.blocks), dim3(kBlock), 0, st, I, spN);
 }
 
 void launch_adj_refine(int step, const InstPtrs* I, const IpmSpaces& S, double eta, hipStream_t st) {
@@ -1050,11 +1072,11 @@ void launch_adj_refine(int step, const InstPtrs* I, const IpmSpaces& S, double e
     }
 }
 
-void launch_adj_gather(const InstPtrs* I, int family, int nx, double seed_obj, hipStream_t st) {
+void launch_adj_gather(const InstPtrs* I, int family, int nx, hipStream_t st) {
     if (family == NMPC_FAMILY_HEATED_PLATE)
-        hipLaunchKernelGGL(k_adj_gather_plate, dim3((nx + kBlock - 1) / kBlock), dim3(kBlock), 0, st, I, seed_obj);
+        hipLaunchKernelGGL(k_adj_gather_plate, dim3((nx + kBlock - 1) / kBlock), dim3(kBlock), 0, st, I);
     else
-        hipLaunchKernelGGL(k_adj_gather_distill, dim3(1), dim3(kBlock), 0, st, I, seed_obj);
+        hipLaunchKernelGGL(k_adj_gather_distill, dim3(1), dim3(kBlock), 0, st, I);
 }
 
 }  // namespace nmpc

@@ -195,6 +195,30 @@ class Problem:
                                             _dp(gs), _dp(gt), _dp(gu)))
         return rc, dict(x0=gx, setpoint=gs, traj=gt, u_prev=gu)
 
+    # ---- device-pointer variants ----------------------------------------------
+    # Addresses of float64 device buffers on the handle's GPU (0 = NULL) and the
+    # caller's hipStream_t (0 = null stream); ordered on that stream, no host sync.
+    @property
+    def n_setpoint(self):
+        return self.nx if self.family == capi.NMPC_FAMILY_HEATED_PLATE else 2
+
+    @property
+    def n_traj(self):
+        return 0 if self.family == capi.NMPC_FAMILY_HEATED_PLATE else self.horizon
+
+    def set_parameters_dev(self, x0, setpoint=0, traj=0, u_prev=0, stream=0):
+        _check(capi.lib().nmpc_set_parameters_dev(self._h, x0 or None, setpoint or None, traj or None,
+                                                  u_prev or None, stream or None))
+
+    def solution_dev(self, y=0, lam=0, omega_d=0, zL=0, zU=0, u1=0, x1=0, stream=0):
+        _check(capi.lib().nmpc_get_solution_dev(self._h, y or None, lam or None, omega_d or None, zL or None,
+                                                zU or None, u1 or None, x1 or None, stream or None))
+
+    def adjoint_dev(self, seed_u1=0, seed_obj=0, grad_x0=0, grad_setpoint=0, grad_traj=0, grad_u_prev=0, stream=0):
+        return _check(capi.lib().nmpc_adjoint_dev(self._h, seed_u1 or None, seed_obj or None, grad_x0 or None,
+                                                  grad_setpoint or None, grad_traj or None, grad_u_prev or None,
+                                                  stream or None))
+
     def jacobian_u1_x0(self):
         jac = np.empty((self.nu, self.nx))
         rc = _check(capi.lib().nmpc_jacobian_u1_x0(self._h, _dp(jac)))
