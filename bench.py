@@ -180,6 +180,43 @@ def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
             "speedup_vs_sequential": el_s / el_b}
 
 
+def run_small(N, seeds=20, resolves=5, eager=False):
+    """Small column (10 trays, horizon 20, dt 0.1): per seed one analyze + cold
+    solve (reported apart), then warm re-solves with the plant stepped by the
+    model plus measurement noise; p50 / p99 over the warm re-solves."""
+    from workloads import distillation_workload
+    opts = N.default_options(graph=0 if eager else 1)
+    lat, first, iters, statuses = [], [], 0, []
+    t_all = 0.0
+    for seed in range(seeds):
+        w = distillation_workload("small", seed, n_resolves=resolves + 1)
+        t0 = time.perf_counter()
+        p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+        p.analyze()
+        sp = [w.xD_sp, w.xB_sp]
+        p.set_parameters(w.x0, setpoint=sp, traj=w.zF(0), u_prev=w.u_prev0)
+        r0 = p.solve(warm=False, options=opts)
+        u1, x1 = p.first_stage()
+        first.append((time.perf_counter() - t0) * 1e3)
+        statuses.append(r0.status)
+        for k in range(resolves):
+            t = time.perf_counter()
+            p.set_parameters(w.next_measurement(x1, k), setpoint=sp, traj=w.zF(k + 1), u_prev=u1)
+            r = p.solve(warm=True, options=opts)
+            u1, x1 = p.first_stage()
+            dt = time.perf_counter() - t
+            lat.append(dt * 1e3)
+            t_all += dt
+            iters += r.iters
+            statuses.append(r.status)
+        p.close()
+    _progress(f"small column: {seeds} seeds x {resolves} warm re-solves")
+    return {"workload": f"distillation 10 trays, horizon 20, dt 0.1, seeds 0..{seeds - 1}, {resolves} warm re-solves each",
+            "p50_resolve_ms": _percentile(lat, 50), "p99_resolve_ms": _percentile(lat, 99),
+            "iters_per_s": iters / t_all, "iters_per_resolve": iters / len(lat),
+            "p50_first_solve_ms": _percentile(first, 50), "nonzero_status": sum(1 for s_ in statuses if s_ != 0)}
+
+
 def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
     """Heated plate: G x G grid, horizon H, dt 0.01, 16 heaters in [0, 1],
     T <= 1.5, Gaussian-bump target from the seed, T0 = 0.  One analyze and cold
@@ -382,6 +419,7 @@ def main(argv=None):
                      "kernel": "numeric supernodal factorization (all levels of one factorization)",
                      "bytes_per_unit": bytes_per_factor},
     }
+    out["small"] = run_small(N, eager=a.eager)
     if not a.no_batch:
         out["batched"] = run_batched(N, eager=a.eager)
     if not a.no_plate:

@@ -123,16 +123,14 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
         const int T = m - t0;
         if (T > 0) {
             const int nt = (T + 15) / 16;
-            // lower-triangle tiles in row order, dealt to the waves round-robin
-            int owner = 0, ti = 0, tj = -1;
-            for (int tt = 0; tt < nt * (nt + 1) / 2; ++tt) {
-                if (++tj > ti) {
-                    ++ti;
-                    tj = 0;
-                }
-                const int mine = owner == wv;
-                owner = owner + 1 == nw ? 0 : owner + 1;
-                if (!mine) continue;
+            // lower-triangle tiles in row order, dealt to the waves round-robin;
+            // tile t sits in row ti with ti (ti + 1) / 2 <= t (single-precision root,
+            // then integer correction)
+            for (int tt = wv; tt < nt * (nt + 1) / 2; tt += nw) {
+                int ti = (int)((sqrtf(8.0f * (float)tt + 1.0f) - 1.0f) * 0.5f);
+                while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
+                while (ti * (ti + 1) / 2 > tt) --ti;
+                const int tj = tt - ti * (ti + 1) / 2;
                 const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
