@@ -33,7 +33,7 @@ namespace nmpc {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kRowBlock = kBlock;   // TRSM rows per workgroup (one per thread)
+constexpr int kRowBlock = kBlock / 4;   // TRSM rows per workgroup (four lanes per row)
 constexpr int kTile = 64;        // trailing-update tile
 constexpr int kSolveRows = 256;  // GEMV rows per workgroup
 constexpr int kSolveCols = 16;   // transposed-GEMV columns per workgroup
@@ -129,13 +129,36 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
     }
 }
 
+// Value v of lane SRC of each group of four lanes, in every lane of the group
+// (DPP quad permutation: no shared memory, no wait).
+template <int SRC>
+__device__ inline double quad_bcast(double v) {
+    constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double quad_bcast(double v, int src) {
+    switch (src) {
+        case 0: return quad_bcast<0>(v);
+        case 1: return quad_bcast<1>(v);
+        case 2: return quad_bcast<2>(v);
+        default: return quad_bcast<3>(v);
+    }
+}
+
 // task (inst, s, kb, row block): solve x D^T = a for the rows
-// [kb + pw + rb kRowBlock, ...) below the factored diagonal block, one row per
-// thread against D and the reciprocals of its diagonal in shared memory (every
-// lane reads the same entry).
+// [kb + pw + rb kRowBlock, ...) below the factored diagonal block.  Four lanes
+// share a row, lane q holding its entries 16 q .. 16 q + 15 in registers; per
+// column k the lane holding x_k scales it by 1 / d_kk, a quad permutation hands
+// it to the other three, and each lane updates its 16 entries with the strict
+// lower part of D from shared memory (zero on and above the diagonal, so the
+// updates need no branches).  A narrower last panel is solved in place, one
+// lane per row.
 __global__ void __launch_bounds__(kBlock)
 k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
-    __shared__ double D[kTri];
+    __shared__ double D[kTri];   // strict lower triangle
     __shared__ double rd[kBigPanel];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
@@ -149,32 +172,34 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
     if (r0 >= F.m) return;
     for (int e = tid; e < kBigPanel * kBigPanel; e += blockDim.x) {
         const int i = e % kBigPanel, j = e / kBigPanel;
-        D[i + j * ldd] = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+        const double v = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+        D[i + j * ldd] = i == j ? 0.0 : v;
+        if (i == j) rd[i] = i < pw ? 1.0 / v : 1.0;
     }
     __syncthreads();
-    if (tid < kBigPanel) rd[tid] = tid < pw ? 1.0 / D[tid + tid * ldd] : 1.0;
-    __syncthreads();
-    const int r = r0 + tid;
-    if (r >= F.m) return;
+    const int g = tid / 4, q = tid % 4;
+    const int r = r0 + g;
+    if (r >= F.m) return;   // all four lanes of a row leave together
     double* row = F.L + r + (int64_t)kb * F.m;
     if (pw == kBigPanel) {
-        // full panel: the row in registers (unconditional accesses keep the
-        // unrolled solve in one block of straight-line code)
-        double x[kBigPanel];
+        double x[16];
+        const double* rq = row + (int64_t)(16 * q) * F.m;
 #pragma unroll
-        for (int k = 0; k < kBigPanel; ++k) x[k] = row[(int64_t)k * F.m];
-        // column by column (right-looking): the updates of one step are
-        // independent, so the dependency chain is 64 steps long, not 2016
+        for (int i = 0; i < 16; ++i) x[i] = rq[(int64_t)i * F.m];
 #pragma unroll
         for (int k = 0; k < kBigPanel; ++k) {
-            x[k] *= rd[k];
+            const int qk = k / 16, kk = k % 16;
+            x[kk] *= q == qk ? rd[k] : 1.0;
+            const double xk = quad_bcast(x[kk], qk);
+            const double* dk = D + 16 * q + k * ldd;
 #pragma unroll
-            for (int j = k + 1; j < kBigPanel; ++j) x[j] = fma(-x[k], D[j + k * ldd], x[j]);
+            for (int i = 0; i < 16; ++i) x[i] = fma(-xk, dk[i], x[i]);
         }
 #pragma unroll
-        for (int k = 0; k < kBigPanel; ++k) row[(int64_t)k * F.m] = x[k];
-    } else {
-        // the last, narrower panel of a supernode: in place
+        for (int i = 0; i < 16; ++i) const_cast<double*>(rq)[(int64_t)i * F.m] = x[i];
+    } else if (q == 0) {
+        // the last, narrower panel of a supernode: in place; D's diagonal was
+        // zeroed, its reciprocal is in rd
         for (int k = 0; k < pw; ++k) {
             double acc = row[(int64_t)k * F.m];
             for (int j = 0; j < k; ++j) acc = fma(-row[(int64_t)j * F.m], D[k + j * ldd], acc);
