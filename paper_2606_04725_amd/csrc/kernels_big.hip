@@ -38,6 +38,22 @@ constexpr int kTile = 64;        // trailing-update tile
 constexpr int kSolveRows = 256;  // GEMV rows per workgroup
 constexpr int kSolveCols = 16;   // transposed-GEMV columns per workgroup
 constexpr int kTri = kWave * (kWave + 1);   // a staged 64 x 64 triangle, leading dimension 65
+constexpr int kStage = kWave * kWave / kBlock;   // entries of a 64 x 64 block staged per thread
+constexpr int kUpdateDepth = 8;  // 4-column steps of an update tile whose loads are in flight together
+constexpr int kExtendDepth = 4;  // child rows per thread whose loads are in flight together
+
+// Loads through a pointer in the global address space are global (not flat)
+// instructions: they count only against the vector-memory counter, so waits
+// for shared memory do not also wait for them.
+typedef __attribute__((address_space(1))) double gdouble;
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* global(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
 
 struct Front {
     double* L;     // panel, leading dimension m
@@ -99,7 +115,26 @@ k_big_extend(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
     const int32_t* rel = I.S.rel + I.S.rel_off[c];
     const int jc = tk.w;
     const int rj = rel[jc];
-    for (int ic = jc + threadIdx.x; ic < nc; ic += blockDim.x) *at(F, rel[ic], rj) += Uc[ic + (int64_t)jc * nc];
+    const auto* uc = global(Uc) + (int64_t)jc * nc;
+    const auto* rg = global(rel);
+    // kExtendDepth rows per thread at a time: their loads are issued together
+    // (distinct rows of the child land on distinct entries of the front)
+    for (int ic0 = jc + threadIdx.x; ic0 < nc; ic0 += kExtendDepth * kBlock) {
+        int rr[kExtendDepth];
+        double uv[kExtendDepth], tv[kExtendDepth];
+#pragma unroll
+        for (int u = 0; u < kExtendDepth; ++u) {
+            const int ic = ic0 + u * kBlock;
+            rr[u] = ic < nc ? rg[ic] : 0;
+            uv[u] = ic < nc ? uc[ic] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kExtendDepth; ++u)
+            tv[u] = ic0 + u * kBlock < nc ? *global(at(F, rr[u], rj)) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kExtendDepth; ++u)
+            if (ic0 + u * kBlock < nc) *global(at(F, rr[u], rj)) = tv[u] + uv[u];
+    }
 }
 
 // task (inst, s, kb, -): factor the diagonal block D of columns [kb, kb + pw)
@@ -117,15 +152,24 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
     const int kb = tk.z;
     const int pw = min(kBigPanel, F.w - kb);
     constexpr int ldd = kBigPanel + 1;
-    for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
-        const int i = e % kBigPanel, j = e / kBigPanel;
-        D[i + j * ldd] = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+    {
+        double t[kStage];
+#pragma unroll
+        for (int s = 0; s < kStage; ++s) {
+            const int e = threadIdx.x + s * kBlock, i = e % kBigPanel, j = e / kBigPanel;
+            t[s] = (i < pw && j <= i) ? global(F.L)[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < kStage; ++s) {
+            const int e = threadIdx.x + s * kBlock;
+            D[e % kBigPanel + (e / kBigPanel) * ldd] = t[s];
+        }
     }
     __syncthreads();
     partial_cholesky<8>(D, SquareIdx{ldd}, pw, pw, &I.ctl->fail);
     for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
         const int i = e % kBigPanel, j = e / kBigPanel;
-        if (i < pw && j <= i) F.L[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
+        if (i < pw && j <= i) global(F.L)[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
     }
 }
 
@@ -170,20 +214,28 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
     const int tid = threadIdx.x;
     const int r0 = kb + pw + tk.w * kRowBlock;
     if (r0 >= F.m) return;
-    for (int e = tid; e < kBigPanel * kBigPanel; e += blockDim.x) {
-        const int i = e % kBigPanel, j = e / kBigPanel;
-        const double v = (i < pw && j <= i) ? F.L[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
-        D[i + j * ldd] = i == j ? 0.0 : v;
-        if (i == j) rd[i] = i < pw ? 1.0 / v : 1.0;
+    {
+        double t[kStage];
+#pragma unroll
+        for (int s = 0; s < kStage; ++s) {
+            const int e = tid + s * kBlock, i = e % kBigPanel, j = e / kBigPanel;
+            t[s] = (i < pw && j <= i) ? global(F.L)[(kb + i) + (int64_t)(kb + j) * F.m] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < kStage; ++s) {
+            const int e = tid + s * kBlock, i = e % kBigPanel, j = e / kBigPanel;
+            D[i + j * ldd] = i == j ? 0.0 : t[s];
+            if (i == j) rd[i] = i < pw ? 1.0 / t[s] : 1.0;
+        }
     }
     __syncthreads();
     const int g = tid / 4, q = tid % 4;
     const int r = r0 + g;
     if (r >= F.m) return;   // all four lanes of a row leave together
-    double* row = F.L + r + (int64_t)kb * F.m;
+    gdouble* row = global(F.L) + r + (int64_t)kb * F.m;
     if (pw == kBigPanel) {
         double x[16];
-        const double* rq = row + (int64_t)(16 * q) * F.m;
+        gdouble* rq = row + (int64_t)(16 * q) * F.m;
 #pragma unroll
         for (int i = 0; i < 16; ++i) x[i] = rq[(int64_t)i * F.m];
 #pragma unroll
@@ -196,7 +248,7 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
             for (int i = 0; i < 16; ++i) x[i] = fma(-xk, dk[i], x[i]);
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) const_cast<double*>(rq)[(int64_t)i * F.m] = x[i];
+        for (int i = 0; i < 16; ++i) rq[(int64_t)i * F.m] = x[i];
     } else if (q == 0) {
         // the last, narrower panel of a supernode: in place; D's diagonal was
         // zeroed, its reciprocal is in rd
@@ -255,24 +307,33 @@ k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int k4 = 0; k4 < kw; k4 += 4) {
-        const int kk = k4 + lk;
-        const double* col = F.L + (int64_t)(k0 + kk) * F.m;
-        double av[2], bv[2];
+    // kUpdateDepth steps of 4 columns are loaded before their products, so the
+    // loads of a step overlap one another instead of each waiting in turn
+    // (columns past kw load zeros and add nothing)
+    const gdouble* Lg = global(F.L);
+    bool rok[2], cok[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int r = i0 + 16 * a + li;
-            av[a] = (kk < kw && r < F.m) ? col[r] : 0.0;
+    for (int a = 0; a < 2; ++a) rok[a] = i0 + 16 * a + li < F.m;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) cok[b] = j0 + 16 * b + li < cmax;
+    for (int k4 = 0; k4 < kw; k4 += 4 * kUpdateDepth) {
+        double av[kUpdateDepth][2], bv[kUpdateDepth][2];
+#pragma unroll
+        for (int u = 0; u < kUpdateDepth; ++u) {
+            const int kk = k4 + 4 * u + lk;
+            const gdouble* col = Lg + (int64_t)(k0 + kk) * F.m;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[u][a] = (kk < kw && rok[a]) ? col[i0 + 16 * a + li] : 0.0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[u][b] = (kk < kw && cok[b]) ? col[j0 + 16 * b + li] : 0.0;
         }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int c = j0 + 16 * b + li;
-            bv[b] = (kk < kw && c < cmax) ? col[c] : 0.0;
-        }
+        for (int u = 0; u < kUpdateDepth; ++u)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][a], bv[u][b], acc[a][b], 0, 0, 0);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -281,7 +342,7 @@ k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + 16 * a + 4 * r + lk, j = j0 + 16 * b + li;
-                if (i < F.m && j <= i && j < cmax) *at(F, i, j) -= acc[a][b][r];
+                if (i < F.m && j <= i && j < cmax) *global(at(F, i, j)) -= acc[a][b][r];
             }
 }
 
@@ -298,12 +359,29 @@ k_big_update(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
 constexpr int kChunk = 256;
 
 // Stage the lower triangle of the diagonal block [b0, b0 + bw)^2 of L in T
-// (leading dimension kWave + 1); the caller synchronizes.
-__device__ inline void stage_triangle(const Front& F, int b0, int bw, double* T) {
-    for (int e = threadIdx.x; e < kWave * kWave; e += blockDim.x) {
-        const int i = e % kWave, j = e / kWave;
-        if (i < bw && j <= i) T[i + j * (kWave + 1)] = F.L[(b0 + i) + (int64_t)(b0 + j) * F.m];
+// (leading dimension kWave + 1) and the reciprocals of its diagonal in rd (1
+// past bw); every load of a thread is issued before the first store.  The
+// caller synchronizes.
+__device__ inline void stage_triangle(const Front& F, int b0, int bw, double* T, double* rd) {
+    double t[kStage];
+#pragma unroll
+    for (int s = 0; s < kStage; ++s) {
+        const int e = threadIdx.x + s * kBlock, i = e % kWave, j = e / kWave;
+        t[s] = (i < bw && j <= i) ? global(F.L)[(b0 + i) + (int64_t)(b0 + j) * F.m] : 0.0;
     }
+#pragma unroll
+    for (int s = 0; s < kStage; ++s) {
+        const int e = threadIdx.x + s * kBlock, i = e % kWave, j = e / kWave;
+        if (j <= i) T[i + j * (kWave + 1)] = t[s];
+        if (i == j) rd[i] = i < bw ? 1.0 / t[s] : 1.0;
+    }
+}
+
+// Value of v in lane k of the wave, in every lane (k wave-uniform).
+__device__ inline double lane_value(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
 }
 
 // forward, task (inst, s, chunk c): x[c0, c1) = L[c0:c1, c0:c1]^{-1} v[c0, c1)
@@ -312,6 +390,7 @@ __device__ inline void stage_triangle(const Front& F, int b0, int bw, double* T)
 __global__ void __launch_bounds__(kBlock)
 k_bigfwd_tri(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
     __shared__ double T[kTri];
+    __shared__ double rd[kWave];
     __shared__ double v[kChunk];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
@@ -342,22 +421,31 @@ k_bigfwd_tri(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
     for (int k = tid; k < cw; k += nthr) v[k] = xs[c0 + k];
     for (int b0 = 0; b0 < cw; b0 += kWave) {
         const int bw = min(kWave, cw - b0), b1 = b0 + bw;
-        stage_triangle(F, c0 + b0, bw, T);
+        stage_triangle(F, c0 + b0, bw, T, rd);
         __syncthreads();
         if (tid < kWave) {
+            // lane j holds v_j; x_k leaves lane k through the scalar unit.  Lanes
+            // j >= bw carry zeros (rd = 1 there, their entries of T are unused).
             const int j = tid;
             double vj = j < bw ? v[b0 + j] : 0.0;
-            for (int k = 0; k < bw; ++k) {
-                const double xk = __shfl(vj, k, kWave) / T[k + k * (kWave + 1)];
-                if (j == k) vj = xk;
-                else if (j > k && j < bw) vj = fma(-T[j + k * (kWave + 1)], xk, vj);
+#pragma unroll
+            for (int k = 0; k < kWave; ++k) {
+                const double xk = lane_value(vj, k) * rd[k];
+                const double upd = fma(-T[j + k * (kWave + 1)], xk, vj);
+                vj = j == k ? xk : (j > k && j < bw ? upd : vj);
             }
             if (j < bw) v[b0 + j] = vj;
         }
         __syncthreads();
         for (int i = b1 + tid; i < cw; i += nthr) {
+            const gdouble* li = global(F.L) + (c0 + i) + (int64_t)(c0 + b0) * F.m;
             double acc = v[i];
-            for (int k = b0; k < b1; ++k) acc = fma(-F.L[(c0 + i) + (int64_t)(c0 + k) * F.m], v[k], acc);
+            if (bw == kWave) {
+#pragma unroll 32
+                for (int k = 0; k < kWave; ++k) acc = fma(-li[(int64_t)k * F.m], v[b0 + k], acc);
+            } else {
+                for (int k = 0; k < bw; ++k) acc = fma(-li[(int64_t)k * F.m], v[b0 + k], acc);
+            }
             v[i] = acc;
         }
         __syncthreads();
@@ -380,8 +468,9 @@ k_bigfwd_gemv(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, i
     __syncthreads();
     const int i = c1 + tk.w * kSolveRows + threadIdx.x;
     if (i >= F.m) return;
-    const double* Li = F.L + i + (int64_t)c0 * F.m;
+    const gdouble* Li = global(F.L) + i + (int64_t)c0 * F.m;
     double acc = 0.0;
+#pragma unroll 16
     for (int k = 0; k < cw; ++k) acc = fma(Li[(int64_t)k * F.m], x[k], acc);
     if (i < F.w) I.xp[F.f + i] -= acc;
     else I.uvec[I.S.uv_off[tk.y] + (i - F.w)] -= acc;
@@ -401,7 +490,8 @@ k_bigbwd_below(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, 
     const int k0 = tk.z * kSolveCols;
     for (int k = k0 + wv; k < min(F.w, k0 + kSolveCols); k += nw) {
         double acc = 0.0;
-        for (int i = F.w + lane; i < F.m; i += kWave) acc = fma(F.L[i + (int64_t)k * F.m], I.xp[rows[i]], acc);
+#pragma unroll 4
+        for (int i = F.w + lane; i < F.m; i += kWave) acc = fma(global(F.L)[i + (int64_t)k * F.m], global(I.xp)[rows[i]], acc);
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
         if (lane == 0) I.bsum[F.f + k] = acc;
     }
@@ -418,6 +508,7 @@ __device__ inline bool bsum_live(const Front& F, int c) { return F.m > F.w || (c
 __global__ void __launch_bounds__(kBlock)
 k_bigbwd_tri(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred, int which) {
     __shared__ double T[kTri];
+    __shared__ double rd[kWave];
     __shared__ double v[kChunk];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
@@ -429,24 +520,31 @@ k_bigbwd_tri(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
     for (int k = tid; k < cw; k += nthr) v[k] = I.xp[F.f + c0 + k] - (live ? I.bsum[F.f + c0 + k] : 0.0);
     const int nblk = (cw + kWave - 1) / kWave;
     for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int b0 = bi * kWave, bw = min(kWave, cw - b0), b1 = b0 + bw;
-        stage_triangle(F, c0 + b0, bw, T);
+        const int b0 = bi * kWave, bw = min(kWave, cw - b0);
+        stage_triangle(F, c0 + b0, bw, T, rd);
         __syncthreads();
         if (tid < kWave) {
+            // lane j holds v_j; rows k >= bw are skipped (x_k of a zero lane is 0)
             const int j = tid;
             double vj = j < bw ? v[b0 + j] : 0.0;
-            for (int k = bw - 1; k >= 0; --k) {
-                const double xk = __shfl(vj, k, kWave) / T[k + k * (kWave + 1)];
-                if (j == k) vj = xk;
-                else if (j < k) vj = fma(-T[k + j * (kWave + 1)], xk, vj);
+#pragma unroll
+            for (int k = kWave - 1; k >= 0; --k) {
+                const double xk = lane_value(vj, k) * rd[k];
+                const double upd = fma(-T[k + j * (kWave + 1)], xk, vj);
+                vj = j == k ? xk : (j < k && k < bw ? upd : vj);
             }
             if (j < bw) v[b0 + j] = vj;
         }
         __syncthreads();
         for (int c = tid; c < b0; c += nthr) {
             double acc = v[c];
-            const double* lc = F.L + (int64_t)(c0 + c) * F.m + c0;
-            for (int i = b0; i < b1; ++i) acc = fma(-lc[i], v[i], acc);
+            const gdouble* lc = global(F.L) + (int64_t)(c0 + c) * F.m + c0 + b0;
+            if (bw == kWave) {
+#pragma unroll 32
+                for (int i = 0; i < kWave; ++i) acc = fma(-lc[i], v[b0 + i], acc);
+            } else {
+                for (int i = 0; i < bw; ++i) acc = fma(-lc[i], v[b0 + i], acc);
+            }
             v[c] = acc;
         }
         __syncthreads();
@@ -475,7 +573,7 @@ k_bigbwd_gemvt(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, 
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int k0 = tk.w * kSolveCols;
     for (int k = k0 + wv; k < min(c0, k0 + kSolveCols); k += nw) {
-        const double* lk = F.L + (int64_t)k * F.m + c0;
+        const gdouble* lk = global(F.L) + (int64_t)k * F.m + c0;
         double acc = 0.0;
         for (int i = lane; i < cw; i += kWave) acc = fma(lk[i], x[i], acc);
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
