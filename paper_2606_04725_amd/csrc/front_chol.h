@@ -23,99 +23,94 @@ struct PackedIdx {   // lower triangle packed by columns: column j holds rows j 
     __device__ int operator()(int i, int j) const { return base(j) + i; }
 };
 
-// Right-looking partial Cholesky of the first w columns of an m x m front
-// (lower triangle, positions given by the index map ix; only entries i >= j are
-// touched), P pivot columns at a time:
-//  1. every thread factors the P x P diagonal block itself, in registers
-//     (identical arithmetic in every thread, no communication);
-//  2. every row below the block solves its own row of the panel against it;
-//  3. the rest of the front takes the rank-P update on the matrix cores:
-//     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
-// A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
-// numerically positive definite); the arithmetic continues with pivot 1.
-// With fv, a forward substitution rides along: fv (shared memory, m values)
-// holds the right-hand side over the front's rows; each panel's x = D^{-1}
-// fv[panel] is formed from the registers holding D and written to xo, and
-// every row below takes fv[r] -= L[r, panel] x in step 2.  On return fv[w, m)
-// is the update vector of the rows below.
+// One panel step: pivot columns [kb, kb + kw), kw <= P (a full panel is
+// called with kw = P as a constant, so its bounds checks fold away).
 template <int P, class Idx>
-__device__ __attribute__((always_inline)) inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
-                                        double* xo = nullptr) {
+__device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx ix, int m, int kb, int kw, int* fail,
+                                                                double* fv, double* xo) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
     const int li = lane & 15, lk = lane >> 4;
-    for (int kb = 0; kb < w; kb += P) {
-        const int kw = min(P, w - kb);
+    {
+        // steps 1 and 2 run only in waves that own a row below the block (and
+        // wave 0, which stores the block): the others would repeat the block's
+        // factorization for nothing on a SIMD that a working wave shares
+        const bool rows_here = wv == 0 || kb + kw + wv * kCholWave < m;
         double d[P][P];
+        double rinv[P], rd[P], xk[P];
+        if (rows_here) {
 #pragma unroll
-        for (int i = 0; i < P; ++i)
+            for (int i = 0; i < P; ++i)
 #pragma unroll
-            for (int j = 0; j < P; ++j)
-                d[i][j] = (j <= i && i < kw) ? F[ix(kb + i, kb + j)] : (i == j ? 1.0 : 0.0);
-        double rinv[P];
-        bool bad = false;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            double piv = d[k][k];
-            if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
-                bad = true;
-                piv = 1.0;
-            }
-            // one reciprocal square root per pivot: d_kk = piv / sqrt(piv), and the
-            // reciprocal doubles as the row solves' 1 / d_kk
-            const double inv = rsqrt(piv);
-            rinv[k] = inv;
-            d[k][k] = piv * inv;
-#pragma unroll
-            for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
-#pragma unroll
-            for (int j = k + 1; j < P; ++j)
-#pragma unroll
-                for (int i = j; i < P; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
-        }
-        if (bad && tid == 0) *fail = 1;
-        double rd[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) rd[k] = k < kw ? rinv[k] : 1.0;
-        double xk[P];
-        if (fv) {   // fv[kb, kb + kw) is final: every earlier panel updated it before the last barrier
+                for (int j = 0; j < P; ++j)
+                    d[i][j] = (j <= i && i < kw) ? F[ix(kb + i, kb + j)] : (i == j ? 1.0 : 0.0);
+            bool bad = false;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                double acc = k < kw ? fv[kb + k] : 0.0;
+                double piv = d[k][k];
+                if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
+                    bad = true;
+                    piv = 1.0;
+                }
+                // one reciprocal square root per pivot: d_kk = piv / sqrt(piv), and the
+                // reciprocal doubles as the row solves' 1 / d_kk
+                const double inv = rsqrt(piv);
+                rinv[k] = inv;
+                d[k][k] = piv * inv;
 #pragma unroll
-                for (int j = 0; j < k; ++j) acc = fma(-d[k][j], xk[j], acc);
-                xk[k] = k < kw ? acc * rd[k] : 0.0;
+                for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
+#pragma unroll
+                for (int j = k + 1; j < P; ++j)
+#pragma unroll
+                    for (int i = j; i < P; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
             }
+            if (bad && tid == 0) *fail = 1;
 #pragma unroll
-            for (int k = 0; k < P; ++k)
-                if (k == tid && k < kw) xo[kb + k] = xk[k];
+            for (int k = 0; k < P; ++k) rd[k] = k < kw ? rinv[k] : 1.0;
+            if (fv) {   // fv[kb, kb + kw) is final: every earlier panel updated it before the last barrier
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    double acc = k < kw ? fv[kb + k] : 0.0;
+#pragma unroll
+                    for (int j = 0; j < k; ++j) acc = fma(-d[k][j], xk[j], acc);
+                    xk[k] = k < kw ? acc * rd[k] : 0.0;
+                }
+                if (tid < kw) {   // thread k stores x_k (picked from the registers by selects)
+                    double x = xk[0];
+#pragma unroll
+                    for (int k = 1; k < P; ++k) x = tid == k ? xk[k] : x;
+                    xo[kb + tid] = x;
+                }
+            }
         }
         __syncthreads();   // every thread has read the diagonal block before it is overwritten
+        if (rows_here) {
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-            if (tid == i && i < kw) {
+            for (int i = 0; i < P; ++i)
+                if (tid == i && i < kw) {
 #pragma unroll
-                for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
-            }
-        for (int r = kb + kw + tid; r < m; r += nthr) {
-            double a[P];
+                    for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
+                }
+            for (int r = kb + kw + tid; r < m; r += nthr) {
+                double a[P];
 #pragma unroll
-            for (int j = 0; j < P; ++j) a[j] = j < kw ? F[ix(r, kb + j)] : 0.0;
+                for (int j = 0; j < P; ++j) a[j] = j < kw ? F[ix(r, kb + j)] : 0.0;
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double s = a[k];
+                for (int k = 0; k < P; ++k) {
+                    double s = a[k];
 #pragma unroll
-                for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
-                a[k] = s * rd[k];
-            }
+                    for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
+                    a[k] = s * rd[k];
+                }
 #pragma unroll
-            for (int j = 0; j < P; ++j)
-                if (j < kw) F[ix(r, kb + j)] = a[j];
-            if (fv) {
-                double acc = fv[r];
+                for (int j = 0; j < P; ++j)
+                    if (j < kw) F[ix(r, kb + j)] = a[j];
+                if (fv) {
+                    double acc = fv[r];
 #pragma unroll
-                for (int j = 0; j < P; ++j) acc = fma(-a[j], xk[j], acc);
-                fv[r] = acc;
+                    for (int j = 0; j < P; ++j) acc = fma(-a[j], xk[j], acc);
+                    fv[r] = acc;
+                }
             }
         }
         __syncthreads();
@@ -152,5 +147,31 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
     }
 }
 
+// Right-looking partial Cholesky of the first w columns of an m x m front
+// (lower triangle, positions given by the index map ix; only entries i >= j are
+// touched), P pivot columns at a time:
+//  1. every thread of a wave that owns rows below the block (and of wave 0)
+//     factors the P x P diagonal block itself, in registers (identical
+//     arithmetic in every such thread, no communication);
+//  2. every row below the block solves its own row of the panel against it;
+//  3. the rest of the front takes the rank-P update on the matrix cores:
+//     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
+// A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
+// numerically positive definite); the arithmetic continues with pivot 1.
+// With fv, a forward substitution rides along: fv (shared memory, m values)
+// holds the right-hand side over the front's rows; each panel's x = D^{-1}
+// fv[panel] is formed from the registers holding D and written to xo, and
+// every row below takes fv[r] -= L[r, panel] x in step 2.  On return fv[w, m)
+// is the update vector of the rows below.
+template <int P, class Idx>
+__device__ __attribute__((always_inline)) inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
+                                        double* xo = nullptr) {
+    for (int kb = 0; kb < w; kb += P) {
+        if (w - kb >= P)
+            panel_step<P>(F, ix, m, kb, P, fail, fv, xo);
+        else
+            panel_step<P>(F, ix, m, kb, w - kb, fail, fv, xo);
+    }
+}
 
 }  // namespace nmpc

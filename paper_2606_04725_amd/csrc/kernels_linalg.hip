@@ -47,10 +47,12 @@ __device__ void g2s(T* dst, const T* __restrict__ src, int64_t n) {
     }
 }
 
-// Entry e of the lower triangle of an n x n matrix packed by columns, as (i, j).
+// Entry e of the lower triangle of an n x n matrix packed by columns, as (i, j)
+// (n <= 256 here, so b^2 - 8e is exact in single precision; the integer steps
+// correct the rounded root).
 __device__ __attribute__((always_inline)) inline void unpack_lower(int e, int n, int& i, int& j) {
-    const double b = 2.0 * n + 1.0;
-    int c = (int)((b - sqrt(b * b - 8.0 * e)) * 0.5);
+    const float b = 2.0f * (float)n + 1.0f;
+    int c = (int)((b - sqrtf(b * b - 8.0f * (float)e)) * 0.5f);
     c = max(0, min(c, n - 1));
     while (c > 0 && c * n - ((c * (c - 1)) >> 1) > e) --c;
     while (c + 1 < n && (c + 1) * n - (((c + 1) * c) >> 1) <= e) ++c;
@@ -59,22 +61,30 @@ __device__ __attribute__((always_inline)) inline void unpack_lower(int e, int n,
 }
 
 // Loads of one round of a child's update block: entries e0 + tid + u nthr of
-// its packed lower triangle (ne entries), each as a value and its position in
-// the parent front (through the child's relative row positions).
-template <class Idx>
+// its packed lower triangle (ne entries), each as a value and the front rows of
+// its row and column (the child's relative row positions; -1: no entry).  The
+// front position is formed only when the entry is added, so the round's loads
+// stay in flight until then.
+struct ChildRound {
+    double v[kBatch];
+    int ri[kBatch], rj[kBatch];
+};
+
 __device__ __attribute__((always_inline)) inline void child_round(const double* __restrict__ Uc, const int32_t* __restrict__ rel, int nc, int ne,
-                                   int e0, Idx ix, double (&v)[kBatch], int (&pos)[kBatch]) {
+                                   int e0, ChildRound& r) {
     const int tid = threadIdx.x, nthr = blockDim.x;
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
         const int e = e0 + tid + u * nthr;
-        pos[u] = -1;
-        v[u] = 0.0;
+        r.ri[u] = -1;
+        r.rj[u] = 0;
+        r.v[u] = 0.0;
         if (e < ne) {
             int i, j;
             unpack_lower(e, nc, i, j);
-            v[u] = Uc[i + (int64_t)j * nc];
-            pos[u] = ix(rel[i], rel[j]);
+            r.v[u] = Uc[i + (int64_t)j * nc];
+            r.ri[u] = rel[i];
+            r.rj[u] = rel[j];
         }
     }
 }
@@ -95,18 +105,11 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
     const int nb = m - w;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
-    const int fsize = Lds ? (m * (m + 1)) / 2 : m * (m | 1);
-    for (int e = tid; e < fsize; e += nthr) F[e] = 0.0;
-    // fused forward solve of the Newton step: v over the front's rows starts
-    // from the permuted right-hand side of the supernode's columns
     const bool fw = fwd && S.fused[s];
-    if (fw)
-        for (int i = tid; i < m; i += nthr) v[i] = i < w ? I.rhs[I.perm[f + i]] : 0.0;
-    // first round of the first child's update block in flight while the front
-    // is cleared and the original entries are placed
+    // first round of the first child's update block and the first original
+    // entries in flight while the front is cleared
     const int c0 = S.child_ptr[s], c1 = S.child_ptr[s + 1];
-    double va[kBatch];
-    int pa[kBatch];
+    ChildRound ra;
     int ci = c0, nc = 0, ne = 0, e0 = 0;
     const double* Uc = nullptr;
     const int32_t* rel = nullptr;
@@ -119,37 +122,54 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
         rel = S.rel + S.rel_off[c];
         e0 = 0;
     };
-    int cur_c = -1, cur_nc = 0;          // the child whose round is in va / pa
+    int cur_c = -1, cur_nc = 0;          // the child whose round is in ra
     const int32_t* cur_rel = nullptr;
     bool cur_first = false;
     if (ci < c1) {
         open_child(ci);
-        child_round(Uc, rel, nc, ne, e0, ix, va, pa);
+        child_round(Uc, rel, nc, ne, e0, ra);
         cur_c = S.child_list[ci];
         cur_nc = nc;
         cur_rel = rel;
         cur_first = true;
     }
+    // original entries of the condensed matrix in this supernode's columns, the
+    // first kBatch per thread loaded with the child's round; a diagonal entry's
+    // position is stored complemented and takes + eta
+    const int kt0 = S.k_ptr[s], kt1 = S.k_ptr[s + 1];
+    int kp[kBatch];
+    double kx[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+        const int t = kt0 + tid + u * nthr;
+        kp[u] = t < kt1 ? S.k_fpos[t] : 0;
+        kx[u] = t < kt1 ? kv[t] : 0.0;
+    }
+    const int fsize = Lds ? (m * (m + 1)) / 2 : m * (m | 1);
+    for (int e = tid; e < fsize; e += nthr) F[e] = 0.0;
+    // fused forward solve of the Newton step: v over the front's rows starts
+    // from the permuted right-hand side of the supernode's columns
+    if (fw)
+        for (int i = tid; i < m; i += nthr) v[i] = i < w ? I.rhs[I.perm[f + i]] : 0.0;
     __syncthreads();
-    // original entries of the condensed matrix in this supernode's columns; a
-    // diagonal entry's position is stored complemented and takes + eta
-    for (int t = S.k_ptr[s] + tid; t < S.k_ptr[s + 1]; t += nthr) {
-        int pos = S.k_fpos[t];
-        double v = kv[t];
+    auto place = [&](int pos, double v) {
         if (pos < 0) {
             pos = ~pos;
             v += eta;
         }
         F[pos] = v;
-    }
+    };
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+        if (kt0 + tid + u * nthr < kt1) place(kp[u], kx[u]);
+    for (int t = kt0 + tid + kBatch * nthr; t < kt1; t += nthr) place(S.k_fpos[t], kv[t]);
     __syncthreads();
     // extend-add of the children's update blocks in fixed order, one round of
     // kBatch entries per thread at a time; the next round's loads are issued
     // before the current round is added, and children are separated by barriers
     // (two children can add into the same entry)
     while (ci < c1) {
-        double vb[kBatch];
-        int pb[kBatch];
+        ChildRound rb;
         int cn = ci;
         bool next = true;
         if (e0 + nthr * kBatch < ne) {
@@ -162,11 +182,11 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
         const bool new_child = cn != ci;
         if (next) {
             if (new_child) open_child(cn);
-            child_round(Uc, rel, nc, ne, e0, ix, vb, pb);
+            child_round(Uc, rel, nc, ne, e0, rb);
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
-            if (pa[u] >= 0) F[pa[u]] += va[u];
+            if (ra.ri[u] >= 0) F[ix(ra.ri[u], ra.rj[u])] += ra.v[u];
         if (fw && cur_first) {   // the child's update vector, with its first round
             const double* uc = I.uvec + S.uv_off[cur_c];
             for (int i = tid; i < cur_nc; i += nthr) v[cur_rel[i]] += uc[i];
@@ -180,11 +200,7 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
             cur_rel = rel;
         }
         ci = cn;
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            va[u] = vb[u];
-            pa[u] = pb[u];
-        }
+        ra = rb;
     }
     partial_cholesky<P>(F, ix, m, w, fail, fw ? v : nullptr, fw ? I.xp + f : nullptr);
     double* Ls = L + S.l_off[s];
