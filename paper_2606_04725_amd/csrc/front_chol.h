@@ -11,22 +11,41 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kCholWave = 64;
 
 // Index maps of a front's lower triangle: base(j) + i is the position of
-// entry (i, j), i >= j.
+// entry (i, j), i >= j.  Front orders stay far below 2^12, so the products
+// fit the full-rate 24-bit multiplier.
 struct SquareIdx {   // column-major, leading dimension ld
     int ld;
-    __device__ int base(int j) const { return j * ld; }
-    __device__ int operator()(int i, int j) const { return i + j * ld; }
+    __device__ int base(int j) const { return __mul24(j, ld); }
+    __device__ int operator()(int i, int j) const { return i + base(j); }
 };
 struct PackedIdx {   // lower triangle packed by columns: column j holds rows j .. m-1
     int m;
-    __device__ int base(int j) const { return j * m - ((j * (j + 1)) >> 1); }
+    __device__ int base(int j) const { return __mul24(j, m) - (__mul24(j, j + 1) >> 1); }
     __device__ int operator()(int i, int j) const { return base(j) + i; }
 };
 
-// One panel step: pivot columns [kb, kb + kw), kw <= P (a full panel is
-// called with kw = P as a constant, so its bounds checks fold away).
+// Tiles of a lower trapezoid of nt tile rows and nc <= nt tile columns, in
+// row order: the triangle of the first nc rows, then nc tiles per row.
+__device__ inline int tile_count(int nt, int nc) { return (__mul24(nc, nc + 1) >> 1) + __mul24(nt - nc, nc); }
+__device__ inline void tile_of(int tt, int nc, int& ti, int& tj) {
+    const int tri = __mul24(nc, nc + 1) >> 1;
+    if (tt < tri) {   // tile row ti holds tiles ti (ti + 1) / 2 ...: single-precision root, integer correction
+        ti = (int)((sqrtf(8.0f * (float)tt + 1.0f) - 1.0f) * 0.5f);
+        while ((__mul24(ti + 1, ti + 2) >> 1) <= tt) ++ti;
+        while ((__mul24(ti, ti + 1) >> 1) > tt) --ti;
+        tj = tt - (__mul24(ti, ti + 1) >> 1);
+    } else {
+        const int r = tt - tri;
+        ti = nc + r / nc;
+        tj = r - __mul24(ti - nc, nc);
+    }
+}
+
+// One panel step: pivot columns [kb, kb + kw) of the w to factor, kw <= P (a
+// full panel is called with kw = P as a constant, so its bounds checks fold
+// away).
 template <int P, class Idx>
-__device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx ix, int m, int kb, int kw, int* fail,
+__device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx ix, int m, int w, int kb, int kw, int* fail,
                                                                 double* fv, double* xo) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
@@ -114,18 +133,14 @@ __device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx 
             }
         }
         __syncthreads();
+        // step 3, restricted to the columns [t0, w) still to be factored: the
+        // update block (columns w and on) takes all w columns at once at the end
         const int t0 = kb + kw;
-        const int T = m - t0;
-        if (T > 0) {
-            const int nt = (T + 15) / 16;
-            // lower-triangle tiles in row order, dealt to the waves round-robin;
-            // tile t sits in row ti with ti (ti + 1) / 2 <= t (single-precision root,
-            // then integer correction)
-            for (int tt = wv; tt < nt * (nt + 1) / 2; tt += nw) {
-                int ti = (int)((sqrtf(8.0f * (float)tt + 1.0f) - 1.0f) * 0.5f);
-                while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
-                while (ti * (ti + 1) / 2 > tt) --ti;
-                const int tj = tt - ti * (ti + 1) / 2;
+        if (t0 < w) {
+            const int nt = (m - t0 + 15) / 16, nc = (w - t0 + 15) / 16;
+            for (int tt = wv; tt < tile_count(nt, nc); tt += nw) {
+                int ti, tj;
+                tile_of(tt, nc, ti, tj);
                 const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -133,18 +148,50 @@ __device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx 
                     const int kk = 4 * s4 + lk;
                     const double* col = F + ix.base(kb + kk);
                     const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
-                    const double b = (kk < kw && j0 + li < m) ? col[j0 + li] : 0.0;
+                    const double b = (kk < kw && j0 + li < w) ? col[j0 + li] : 0.0;
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int ir = i0 + 4 * r + lk, jc = j0 + li;
-                    if (ir < m && jc <= ir) F[ix(ir, jc)] -= acc[r];
+                    if (ir < m && jc <= ir && jc < w) F[ix(ir, jc)] -= acc[r];
                 }
             }
         }
         __syncthreads();
     }
+}
+
+// The update block of the front (rows and columns [w, m)) minus L21 L21^T,
+// L21 = the panel's rows [w, m): lower-triangle 16 x 16 tiles over the waves,
+// one v_mfma_f64_16x16x4f64 per 4 panel columns, each entry read and written
+// once.
+template <class Idx>
+__device__ __attribute__((always_inline)) inline void update_block(double* F, Idx ix, int m, int w) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (m - w + 15) / 16;
+    for (int tt = wv; tt < tile_count(nt, nt); tt += nw) {
+        int ti, tj;
+        tile_of(tt, nt, ti, tj);
+        const int i0 = w + 16 * ti, j0 = w + 16 * tj;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k4 = 0; k4 < w; k4 += 4) {
+            const int kk = k4 + lk;
+            const double* col = F + ix.base(kk);
+            const double a = (kk < w && i0 + li < m) ? col[i0 + li] : 0.0;
+            const double b = (kk < w && j0 + li < m) ? col[j0 + li] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ir = i0 + 4 * r + lk, jc = j0 + li;
+            if (ir < m && jc <= ir) F[ix(ir, jc)] -= acc[r];
+        }
+    }
+    __syncthreads();
 }
 
 // Right-looking partial Cholesky of the first w columns of an m x m front
@@ -154,8 +201,11 @@ __device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx 
 //     factors the P x P diagonal block itself, in registers (identical
 //     arithmetic in every such thread, no communication);
 //  2. every row below the block solves its own row of the panel against it;
-//  3. the rest of the front takes the rank-P update on the matrix cores:
-//     16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot columns.
+//  3. the panel's remaining columns take the rank-P update on the matrix
+//     cores: 16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot
+//     columns;
+// and after the last panel the update block (rows and columns w and on) takes
+// the rank-w update of all panel columns at once.
 // A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
 // numerically positive definite); the arithmetic continues with pivot 1.
 // With fv, a forward substitution rides along: fv (shared memory, m values)
@@ -168,10 +218,11 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
                                         double* xo = nullptr) {
     for (int kb = 0; kb < w; kb += P) {
         if (w - kb >= P)
-            panel_step<P>(F, ix, m, kb, P, fail, fv, xo);
+            panel_step<P>(F, ix, m, w, kb, P, fail, fv, xo);
         else
-            panel_step<P>(F, ix, m, kb, w - kb, fail, fv, xo);
+            panel_step<P>(F, ix, m, w, kb, w - kb, fail, fv, xo);
     }
+    if (m > w) update_block(F, ix, m, w);
 }
 
 }  // namespace nmpc

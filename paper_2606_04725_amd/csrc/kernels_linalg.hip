@@ -65,14 +65,29 @@ __device__ __attribute__((always_inline)) inline void unpack_lower(int e, int n,
 // its row and column (the child's relative row positions; -1: no entry).  The
 // front position is formed only when the entry is added, so the round's loads
 // stay in flight until then.
+// A child's first round can also carry the first kUvec nthr entries of its
+// update vector (fused forward solve).
+constexpr int kUvec = 2;
 struct ChildRound {
     double v[kBatch];
     int ri[kBatch], rj[kBatch];
+    double uv[kUvec];
+    int ur[kUvec];
 };
 
 __device__ __attribute__((always_inline)) inline void child_round(const double* __restrict__ Uc, const int32_t* __restrict__ rel, int nc, int ne,
-                                   int e0, ChildRound& r) {
+                                   int e0, ChildRound& r, const double* __restrict__ uvec = nullptr) {
     const int tid = threadIdx.x, nthr = blockDim.x;
+#pragma unroll
+    for (int u = 0; u < kUvec; ++u) {
+        const int i = tid + u * nthr;
+        r.ur[u] = -1;
+        r.uv[u] = 0.0;
+        if (uvec && i < nc) {
+            r.uv[u] = uvec[i];
+            r.ur[u] = rel[i];
+        }
+    }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
         const int e = e0 + tid + u * nthr;
@@ -127,7 +142,7 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
     bool cur_first = false;
     if (ci < c1) {
         open_child(ci);
-        child_round(Uc, rel, nc, ne, e0, ra);
+        child_round(Uc, rel, nc, ne, e0, ra, fw ? I.uvec + S.uv_off[S.child_list[ci]] : nullptr);
         cur_c = S.child_list[ci];
         cur_nc = nc;
         cur_rel = rel;
@@ -182,14 +197,17 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
         const bool new_child = cn != ci;
         if (next) {
             if (new_child) open_child(cn);
-            child_round(Uc, rel, nc, ne, e0, rb);
+            child_round(Uc, rel, nc, ne, e0, rb, fw && new_child ? I.uvec + S.uv_off[S.child_list[cn]] : nullptr);
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
             if (ra.ri[u] >= 0) F[ix(ra.ri[u], ra.rj[u])] += ra.v[u];
         if (fw && cur_first) {   // the child's update vector, with its first round
+#pragma unroll
+            for (int u = 0; u < kUvec; ++u)
+                if (ra.ur[u] >= 0) v[ra.ur[u]] += ra.uv[u];
             const double* uc = I.uvec + S.uv_off[cur_c];
-            for (int i = tid; i < cur_nc; i += nthr) v[cur_rel[i]] += uc[i];
+            for (int i = tid + kUvec * nthr; i < cur_nc; i += nthr) v[cur_rel[i]] += uc[i];
         }
         if (new_child || !next) __syncthreads();
         if (!next) break;

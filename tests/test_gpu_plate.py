@@ -33,11 +33,14 @@ def _close(a, b, tol):
 
 
 def _assert_parity(m, ipm, sol, r, ref):
-    """GPU solve against the oracle's.  The barrier update is a threshold test
-    (E_mu <= kappa_eps mu); near a tie, rounding can take it the other way on
-    the two sides, and the runs then stop at barrier values one step apart.
-    Bound-active variables sit at y ~ mu / z there, so the iterates differ by
-    O(mu / z) and only the certificate is comparable: the KKT conditions of the
+    """GPU solve against the oracle's.  The barrier update (E_mu <= kappa_eps
+    mu) and the filter's acceptance tests are threshold tests; near a tie,
+    rounding (the factorization sums in another order than the oracle's dense
+    solve) can take one the other way on the two sides.  A flipped acceptance
+    costs an iteration or two on the way to the same barrier value; a flipped
+    barrier update ends the runs at barrier values one step apart, where
+    bound-active variables sit at y ~ mu / z, so the iterates differ by O(mu /
+    z) and only the certificate is comparable: the KKT conditions of the
     original problem and the optimal value.  With the same final barrier value
     the iterates match to 1e-6."""
     e = kkt_error(m, sol["y"], sol["lam"], np.zeros(0), sol["zL"], sol["zU"])
@@ -49,7 +52,7 @@ def _assert_parity(m, ipm, sol, r, ref):
     # host's may round differently)
     same = lambda a, b: abs(a - b) <= 1e-12 * max(a, b)
     if same(r.mu, ref.mu):
-        assert r.iters == ref.iters
+        assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
         assert _close(sol["y"], ref.state.y, 1e-6)
         assert _close(sol["lam"], lam_ref, 1e-6)
     else:
