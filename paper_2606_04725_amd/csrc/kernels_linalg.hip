@@ -257,14 +257,12 @@ k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ group
     }
 }
 
-// Triangular solves with one supernode's panel P (m x w, column-major, lower
-// w x w diagonal block first), staged in shared memory together with the
+// Forward solve with one supernode's panel P (m x w, column-major, lower w x w
+// diagonal block first), staged in shared memory together with the
 // reciprocals of its diagonal.  Columns go kPanel at a time: every thread
 // solves the small diagonal block itself from broadcast reads, then updates
-// the rows (forward) or columns (backward) it owns; one barrier per block.
-
-// Forward: v[0:m) holds b; on return xs[0:w) = L_dd^{-1} b[0:w) and
-// v[w:m) = b[w:m) - L_below xs.
+// the rows it owns; one barrier per block.  v[0:m) holds b; on return xs[0:w) =
+// L_dd^{-1} b[0:w) and v[w:m) = b[w:m) - L_below xs.
 __device__ __attribute__((always_inline)) void blocked_forward(const double* P, const double* rdiag, int m, int w, double* v, double* xs) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int kb = 0; kb < w; kb += kPanel) {
@@ -289,39 +287,6 @@ __device__ __attribute__((always_inline)) void blocked_forward(const double* P, 
             for (int j = 0; j < kPanel; ++j)
                 if (j < kw) acc = fma(-P[r + (int64_t)(kb + j) * m], x[j], acc);
             v[r] = acc;
-        }
-        __syncthreads();
-    }
-}
-
-// Backward: v[0:w) holds the right-hand side of L_dd^T x = v; on return
-// xs[0:w) = x.  PT is the panel transposed: PT[c + r * ld] = L(r, c).
-__device__ __attribute__((always_inline)) void blocked_backward(const double* PT, int ld, const double* rdiag, int w, double* v, double* xs) {
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int nblk = (w + kPanel - 1) / kPanel;
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int kb = bi * kPanel;
-        const int kw = min(kPanel, w - kb);
-        double x[kPanel];
-#pragma unroll
-        for (int k = kPanel - 1; k >= 0; --k) {
-            double s = k < kw ? v[kb + k] : 0.0;
-#pragma unroll
-            for (int j = k + 1; j < kPanel; ++j)
-                if (j < kw) s = fma(-PT[(kb + k) + (int64_t)(kb + j) * ld], x[j], s);
-            x[k] = k < kw ? s * rdiag[kb + k] : 0.0;
-        }
-        if (tid < kw) {
-#pragma unroll
-            for (int k = 0; k < kPanel; ++k)
-                if (k == tid) xs[kb + k] = x[k];
-        }
-        for (int jc = tid; jc < kb; jc += nthr) {
-            double acc = v[jc];
-#pragma unroll
-            for (int q = 0; q < kPanel; ++q)
-                if (q < kw) acc = fma(-PT[jc + (int64_t)(kb + q) * ld], x[q], acc);
-            v[jc] = acc;
         }
         __syncthreads();
     }
@@ -377,14 +342,27 @@ k_fwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, 
         fwd_one(I.S.sched_nodes[i], I.S, I.L, I.uvec, solve_in(I, which), I.perm, I.xp, lds);
 }
 
+// Value of v in lane k of the wave, in every lane (k wave-uniform).
+__device__ __attribute__((always_inline)) inline double lane_value(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
 // Back substitution L^T x = v for one supernode, after all its ancestors:
 // subtract the contribution of the rows below (already final), then solve
-// with the transposed diagonal block; writes x unpermuted.  The rows below
-// are read straight from the panel, 16 lanes per column (contiguous, lanes over
-// rows, a butterfly sums them); only the diagonal block is staged, transposed
-// (leading dimension w | 1), so that a thread per column reads consecutive
-// shared-memory words in the blocked solve.
+// with the transposed diagonal block; writes x unpermuted.  Every global load
+// is issued before the first shared-memory store: the diagonal block (staged
+// transposed, leading dimension w | 1, kBatch entries per thread per round),
+// its diagonal, the supernode's entries of xp, the solution of the rows below
+// (gathered through the row list) and the output permutation.  The rows below
+// are then read straight from the panel, 16 lanes per column and kBwdCols
+// columns per lane group at once (a butterfly sums the lanes).  The diagonal
+// block is solved by wave 0, 64 columns at a time from the last: lane j holds
+// v_j, x_k leaves lane k through the scalar unit, and the earlier columns take
+// the block's contribution before the next block.
 // Shared memory: diagonal block (w (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
+constexpr int kBwdCols = 4;
 __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
                         const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
     const int f = S.sn_ptr[s];
@@ -392,7 +370,7 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
     const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
     const int nb = m - w;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
     const int ld = w | 1;
     double* PT = lds;
     double* rdiag = PT + (int64_t)w * ld;
@@ -400,25 +378,94 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
     double* v = xb + nb;
     double* xs = v + w;
     const double* Ls = L + S.l_off[s];
-    for (int c = wv; c < w; c += nw)
-        for (int r = c + lane; r < w; r += kWave) PT[c + r * ld] = Ls[r + (int64_t)c * m];
-    for (int k = tid; k < w; k += nthr) rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
     const int32_t* rows = S.rows + S.rows_ptr[s];
-    for (int i = tid; i < nb; i += nthr) xb[i] = xp[rows[w + i]];
-    __syncthreads();
-    // 16 lanes per column: nthr / 16 columns in flight, each lane's loads issued together
-    constexpr int kSub = 16;
-    const int sub = tid % kSub;
-    for (int jc = tid / kSub; jc < w; jc += nthr / kSub) {
-        const double* col = Ls + (int64_t)jc * m + w;
-        double acc = 0.0;
-        for (int i = sub; i < nb; i += kSub) acc = fma(col[i], xb[i], acc);
-        for (int off = kSub / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSub);
-        if (sub == 0) v[jc] = xp[f + jc] - acc;
+    const int ri = tid < nb ? rows[w + tid] : 0;
+    const double dg = tid < w ? Ls[tid + (int64_t)tid * m] : 1.0;
+    const double xv = tid < w ? xp[f + tid] : 0.0;
+    const int pk = tid < w ? perm[f + tid] : 0;
+    const int ww = w * w;
+    for (int e0 = 0; e0 < ww; e0 += nthr * kBatch) {
+        double t[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + tid + u * nthr, c = e / w, r = e - c * w;
+            t[u] = (e < ww && r >= c) ? Ls[r + (int64_t)c * m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + tid + u * nthr, c = e / w, r = e - c * w;
+            if (e < ww && r >= c) PT[c + r * ld] = t[u];
+        }
+    }
+    if (tid < nb) xb[tid] = xp[ri];
+    if (tid < w) {
+        rdiag[tid] = 1.0 / dg;
+        v[tid] = xv;
+    }
+    // the panel fits in shared memory, so w < nthr; a narrow supernode can have
+    // more rows below than threads
+    for (int i = tid + nthr; i < nb; i += nthr) xb[i] = xp[rows[w + i]];
+    for (int k = tid + nthr; k < w; k += nthr) {
+        rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
+        v[k] = xp[f + k];
     }
     __syncthreads();
-    blocked_backward(PT, ld, rdiag, w, v, xs);
-    for (int k = tid; k < w; k += nthr) {
+    constexpr int kSub = 16;
+    const int sub = tid % kSub, grp = tid / kSub, ngrp = nthr / kSub;
+    for (int jc0 = grp; jc0 < w; jc0 += kBwdCols * ngrp) {
+        double acc[kBwdCols];
+        const double* col[kBwdCols];
+#pragma unroll
+        for (int u = 0; u < kBwdCols; ++u) {
+            const int jc = jc0 + u * ngrp;
+            acc[u] = 0.0;
+            col[u] = Ls + (int64_t)(jc < w ? jc : 0) * m + w;
+        }
+#pragma unroll 2
+        for (int i = sub; i < nb; i += kSub) {
+            const double xbi = xb[i];
+#pragma unroll
+            for (int u = 0; u < kBwdCols; ++u)
+                if (jc0 + u * ngrp < w) acc[u] = fma(col[u][i], xbi, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kBwdCols; ++u) {
+            for (int off = kSub / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, kSub);
+            const int jc = jc0 + u * ngrp;
+            if (sub == 0 && jc < w) v[jc] -= acc[u];
+        }
+    }
+    __syncthreads();
+    for (int b0 = ((w - 1) / kWave) * kWave; b0 >= 0; b0 -= kWave) {
+        const int bw = min(kWave, w - b0);
+        if (wv == 0) {
+            const int j = lane;
+            double vj = j < bw ? v[b0 + j] : 0.0;
+#pragma unroll
+            for (int k = kWave - 1; k >= 0; --k) {
+                if (k < bw) {   // wave-uniform
+                    const double xk = lane_value(vj, k) * rdiag[b0 + k];
+                    const double upd = fma(-PT[(b0 + j) + (b0 + k) * ld], xk, vj);
+                    vj = j == k ? xk : (j < k ? upd : vj);
+                }
+            }
+            if (j < bw) xs[b0 + j] = vj;
+        }
+        __syncthreads();
+        if (b0 > 0) {   // columns before the block: v[c] -= L(block, c)^T x(block)
+            for (int c = tid; c < b0; c += nthr) {
+                double acc = v[c];
+                for (int q = 0; q < bw; ++q) acc = fma(-PT[c + (b0 + q) * ld], xs[b0 + q], acc);
+                v[c] = acc;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid < w) {
+        xp[f + tid] = xs[tid];
+        out[pk] = xs[tid];
+    }
+    for (int k = tid + nthr; k < w; k += nthr) {
         xp[f + k] = xs[k];
         out[perm[f + k]] = xs[k];
     }
