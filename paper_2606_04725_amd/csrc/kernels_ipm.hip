@@ -83,6 +83,27 @@ __device__ void finalize_partials(const double* part, int nb, const Ops& ops, do
     __syncthreads();
 }
 
+// acc + sum of term(index(e)) over the entries e in [e0, e1), added in entry
+// order; a batch of kGather entries loads its indices, then its values, before
+// the first addition (past e1 a batch repeats entry e0, whose terms it drops).
+constexpr int kGather = 8;
+template <class Index, class Term>
+__device__ __attribute__((always_inline)) inline double gather_sum(int e0, int e1, double acc, Index index, Term term) {
+    using Ix = decltype(index(0));
+    for (int eb = e0; eb < e1; eb += kGather) {
+        Ix ix[kGather];
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) ix[u] = index(eb + u < e1 ? eb + u : e0);
+        double t[kGather];
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) t[u] = term(ix[u]);
+#pragma unroll
+        for (int u = 0; u < kGather; ++u)
+            if (eb + u < e1) acc += t[u];
+    }
+    return acc;
+}
+
 __device__ inline bool hasL(const InstPtrs& I, int j) { return I.lb[j] > -INFINITY; }
 __device__ inline bool hasU(const InstPtrs& I, int j) { return I.ub[j] < INFINITY; }
 
@@ -108,12 +129,13 @@ __global__ void __launch_bounds__(kBlock) k_phaseA(const InstPtrs* __restrict__ 
     const int t = lb * kBlock + threadIdx.x;
     if (t < I.n) {
         const int j = t;
-        double acc = 0.0;
-        for (int e = I.jt_ptr[j]; e < I.jt_ptr[j + 1]; ++e) {
-            const int r = I.jt_row[e];
-            const double lam = r < I.mc ? I.om[r] - I.om[I.mc + r] : I.om[I.mc + r];
-            acc += I.jv[I.jt_slot[e]] * lam;
-        }
+        const double acc = gather_sum(
+            I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
+            [&](int2 rs) {
+                const int r = rs.x;
+                const double lam = r < I.mc ? I.om[r] - I.om[I.mc + r] : I.om[I.mc + r];
+                return I.jv[rs.y] * lam;
+            });
         I.gtw[j] = acc;
         const bool hl = hasL(I, j), hu = hasU(I, j);
         const double zl = hl ? I.zl[j] : 0.0, zu = hu ? I.zu[j] : 0.0;
@@ -240,8 +262,9 @@ __global__ void __launch_bounds__(kBlock) k_var_prep(const InstPtrs* __restrict_
     const double gu = hu ? I.ub[j] - I.y[j] : 1.0;
     I.sig[j] = (hl ? I.zl[j] / gl : 0.0) + (hu ? I.zu[j] / gu : 0.0);
     const double r1 = I.grad[j] + I.gtw[j] - (hl ? mu / gl : 0.0) + (hu ? mu / gu : 0.0);
-    double acc = 0.0;
-    for (int e = I.jt_ptr[j]; e < I.jt_ptr[j + 1]; ++e) acc += I.jv[I.jt_slot[e]] * I.vcomb[I.jt_row[e]];
+    const double acc = gather_sum(
+        I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
+        [&](int2 rs) { return I.jv[rs.y] * I.vcomb[rs.x]; });
     I.r1v[j] = r1;
     I.rhs[j] = -r1 - acc;
 }
@@ -257,7 +280,9 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const InstPtrs* __restrict_
     const int ws = I.k_wslot[t], dg = I.k_diag[t];
     double v = ws >= 0 ? I.wv[ws] : 0.0;
     if (dg >= 0) v += I.sig[dg];
-    for (int e = I.kc_ptr[t]; e < I.kc_ptr[t + 1]; ++e) v += I.jv[I.kc_a[e]] * I.qeff[I.kc_r[e]] * I.jv[I.kc_b[e]];
+    v = gather_sum(
+        I.kc_ptr[t], I.kc_ptr[t + 1], v, [&](int e) { return int3{I.kc_a[e], I.kc_r[e], I.kc_b[e]}; },
+        [&](int3 arb) { return I.jv[arb.x] * I.qeff[arb.y] * I.jv[arb.z]; });
     I.kv[t] = v;
 }
 
@@ -592,8 +617,9 @@ __global__ void __launch_bounds__(kBlock) k_soc_vars(const InstPtrs* __restrict_
     if (!ctl_active(I.ctl, kPhC)) return;
     const int j = lb * kBlock + threadIdx.x;
     if (j >= I.n) return;
-    double acc = 0.0;
-    for (int e = I.jt_ptr[j]; e < I.jt_ptr[j + 1]; ++e) acc += I.jv[I.jt_slot[e]] * I.vcomb_s[I.jt_row[e]];
+    const double acc = gather_sum(
+        I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
+        [&](int2 rs) { return I.jv[rs.y] * I.vcomb_s[rs.x]; });
     I.rhs_s[j] = -I.r1v[j] - acc;
 }
 
