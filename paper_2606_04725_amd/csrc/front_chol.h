@@ -101,15 +101,9 @@ __device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx 
                     xo[kb + tid] = x;
                 }
             }
-        }
-        __syncthreads();   // every thread has read the diagonal block before it is overwritten
-        if (rows_here) {
-#pragma unroll
-            for (int i = 0; i < P; ++i)
-                if (tid == i && i < kw) {
-#pragma unroll
-                    for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
-                }
+            // step 2 follows at once: it reads only rows below the block, and
+            // the factored block is stored after the next barrier, when every
+            // wave has read the block's original entries
             for (int r = kb + kw + tid; r < m; r += nthr) {
                 double a[P];
 #pragma unroll
@@ -133,6 +127,13 @@ __device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx 
             }
         }
         __syncthreads();
+        // the factored diagonal block (nothing reads it before the front is stored)
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            if (tid == i && i < kw) {
+#pragma unroll
+                for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
+            }
         // step 3, restricted to the columns [t0, w) still to be factored: the
         // update block (columns w and on) takes all w columns at once at the end
         const int t0 = kb + kw;
