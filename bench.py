@@ -292,6 +292,7 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched form")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-column leg (10 trays, horizon 20)")
     ap.add_argument("--batch-only", action="store_true", help="only run the 64-instance batched form")
     ap.add_argument("--no-plate", action="store_true", help="skip the heated-plate workloads")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
@@ -419,7 +420,8 @@ def main(argv=None):
                      "kernel": "numeric supernodal factorization (all levels of one factorization)",
                      "bytes_per_unit": bytes_per_factor},
     }
-    out["small"] = run_small(N, eager=a.eager)
+    if not a.no_small:
+        out["small"] = run_small(N, eager=a.eager)
     if not a.no_batch:
         out["batched"] = run_batched(N, eager=a.eager)
     if not a.no_plate:
