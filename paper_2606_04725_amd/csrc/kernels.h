@@ -250,7 +250,7 @@ hipError_t linalg_configure(size_t max_lds_bytes);
 
 // ---- large supernodes (kernels_big.hip) ---------------------------------------------
 constexpr int kBigPanel = 64;   // pivot columns per panel step of a large front
-constexpr int kBigOuter = 256;  // columns per outer panel (one trailing update each)
+constexpr int kBigOuter = 512;  // columns per outer panel (one trailing update each)
 enum BigKind : int {
     kBigInit = 1,       // task (inst, s, column, -)
     kBigExtend = 2,     // task (inst, s, child position, child column)
