@@ -258,8 +258,12 @@ nmpc_status nmpc_assemble(nmpc_problem* p, double mu, double* k_vals, double* rh
 nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj, double* grad_x0,
                          double* grad_setpoint, double* grad_traj, double* grad_uprev);
 
-/* Jacobian d u1* / d x0 as an nu x nx row-major host matrix (nu solves with the
- * kept factor; same conditions as nmpc_adjoint). */
+/* Jacobian d u1* / d x0 as an nu x nx row-major host matrix: row k is the
+ * x0 gradient nmpc_adjoint returns for seed_u1 = e_k, seed_obj = 0 (the same
+ * arithmetic).  The nu seeds are solved together with the kept factor, every
+ * launch covering all of them; the first call after analysis allocates their
+ * vectors (about 8 (5 n + 2 m + update vectors) bytes per seed), later calls
+ * reuse them.  Same conditions as nmpc_adjoint. */
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
 
 /* Device-pointer variants (Algorithm 1's parameter update, the solution read

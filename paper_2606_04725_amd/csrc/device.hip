@@ -76,6 +76,13 @@ struct Device {
     double gamma_last = 1e-9;
     // ordering against a caller's stream (the entry points taking device pointers)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // the nu seeds of the u1 / x0 Jacobian solved together: a batch whose
+    // instances share this problem's factor, iterate and structure and own only
+    // the vectors a sensitivity solve writes (contiguous, seed k at offset k size)
+    Batch* seeds = nullptr;
+    std::vector<Device*> seed_devs;
+    double* seed_vals = nullptr;   // nu x (nu + 1) seeds
+    double* seed_lam = nullptr;    // nu x m multipliers; row k's first nx entries are d u1_k / d x0
 };
 
 // Emitted kernel launch of a batch schedule: a group launch (groups[off ..
@@ -453,6 +460,8 @@ void device_free(Problem& p) {
     Device& D = *p.dev;
     if (D.stream) (void)hipStreamSynchronize(D.stream);
     batch_release(D.self);
+    batch_release(D.seeds);
+    for (Device* c : D.seed_devs) delete c;
     for (void* a : D.allocs) (void)hipFree(a);
     if (D.ev_in) (void)hipEventDestroy(D.ev_in);
     if (D.ev_out) (void)hipEventDestroy(D.ev_out);
@@ -1330,19 +1339,95 @@ nmpc_status device_adjoint_dev(Problem& p, const double* seed_u1, const double* 
     return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
 
+namespace {
+
+// The seed batch of the Jacobian (built once per problem): nu instance
+// descriptors copied from the problem's, each with its own right-hand sides,
+// solution, solve workspace (xp, update vectors, column sums) and multipliers.
+nmpc_status seeds_build(Problem& p, std::string& err) {
+    Device& D = *p.dev;
+    if (D.seeds) return NMPC_OK;
+    for (Device* c : D.seed_devs) delete c;   // an earlier attempt that failed
+    D.seed_devs.clear();
+    const int K = p.st.nu;
+    const int64_t n = D.hI.n, m = D.hI.m, nuv = p.sym.stored_uv;
+    const int64_t nout = p.st.nx + D.hI.nsp + D.hI.ntr + p.st.nu;
+    double *xp, *bsum, *uvec, *rhs, *w, *b, *d, *qr, *out;
+    HIP_TRY(dalloc(D.allocs, xp, K * n));
+    HIP_TRY(dalloc(D.allocs, bsum, K * n));
+    HIP_TRY(dalloc(D.allocs, uvec, K * std::max<int64_t>(nuv, 1)));
+    HIP_TRY(dalloc(D.allocs, rhs, K * n));
+    HIP_TRY(dalloc(D.allocs, w, K * n));
+    HIP_TRY(dalloc(D.allocs, b, K * n));
+    HIP_TRY(dalloc(D.allocs, d, K * n));
+    HIP_TRY(dalloc(D.allocs, D.seed_lam, K * m));
+    HIP_TRY(dalloc(D.allocs, qr, K * m));
+    HIP_TRY(dalloc(D.allocs, out, K * nout));
+    HIP_TRY(dalloc(D.allocs, D.seed_vals, (int64_t)K * (K + 1)));
+    for (int k = 0; k < K; ++k) {
+        Device* c = new Device();
+        c->owner = &p;
+        c->hI = D.hI;
+        InstPtrs& I = c->hI;
+        I.xp = xp + k * n;
+        I.bsum = bsum + k * n;
+        I.uvec = uvec + k * std::max<int64_t>(nuv, 1);
+        I.adj_rhs = rhs + k * n;
+        I.adj_w = w + k * n;
+        I.adj_b = b + k * n;
+        I.adj_d = d + k * n;
+        I.adj_lam = D.seed_lam + k * m;
+        I.adj_qr = qr + k * m;
+        I.adj_out = out + k * nout;
+        I.adj_seed = D.seed_vals + (int64_t)k * (K + 1);
+        c->fac = D.fac;
+        c->fwd = D.fwd;
+        c->bwd = D.bwd;
+        c->fwd_rest = D.fwd_rest;
+        D.seed_devs.push_back(c);
+    }
+    const nmpc_status rc = batch_build(D.seed_devs, D.stream, D.seeds, err);
+    if (rc != NMPC_OK) {   // the descriptors go; their vectors stay with the problem's allocations
+        for (Device* c : D.seed_devs) delete c;
+        D.seed_devs.clear();
+    }
+    return rc;
+}
+
+}  // namespace
+
+// Row k of d u1 / d x0 is the sensitivity for the seed e_k (the same arithmetic
+// as nmpc_adjoint with that seed): all nu seeds go through one sequence of
+// launches, each launch covering every seed.
 nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err) {
     nmpc_status rc = adjoint_prepare(p, err);
     if (rc != NMPC_OK) return rc;
     const Structure& st = p.st;
-    std::vector<double> seed(st.nu, 0.0), out;
-    for (int j = 0; j < st.nu; ++j) {
-        std::fill(seed.begin(), seed.end(), 0.0);
-        seed[j] = 1.0;
-        rc = adjoint_apply(p, seed.data(), 0.0, out, err);
-        if (rc != NMPC_OK) return rc;
-        std::copy(out.begin(), out.begin() + st.nx, jac + (size_t)j * st.nx);
+    if (st.nu > kMaxSeed) {
+        err = "adjoint: too many controls per stage";
+        return NMPC_ERR_UNSUPPORTED;
     }
-    return p.dev->adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
+    rc = seeds_build(p, err);
+    if (rc != NMPC_OK) return rc;
+    Device& D = *p.dev;
+    Batch& S = *D.seeds;
+    const int K = st.nu;
+    std::vector<double> sv((size_t)K * (K + 1), 0.0);
+    for (int k = 0; k < K; ++k) sv[(size_t)k * (K + 1) + k] = 1.0;
+    HIP_TRY(hipMemcpyAsync(D.seed_vals, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, D.stream));
+    launch_adj_seed(S.dI, S.spaces.sp[kSpN], S.stream);
+    solve_launches(S, kPredAll, 2);
+    launch_adj_refine(0, S.dI, S.spaces, D.adj_eta, S.stream);
+    for (int r = 0; r < kAdjRefine; ++r) {
+        launch_adj_refine(1, S.dI, S.spaces, D.adj_eta, S.stream);
+        solve_launches(S, kPredAll, 3);
+        launch_adj_refine(2, S.dI, S.spaces, D.adj_eta, S.stream);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpy2DAsync(jac, st.nx * sizeof(double), D.seed_lam, (size_t)D.hI.m * sizeof(double),
+                             st.nx * sizeof(double), K, hipMemcpyDeviceToHost, D.stream));
+    HIP_TRY(hipStreamSynchronize(D.stream));
+    return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
 
 }  // namespace nmpc

@@ -77,6 +77,41 @@ def test_adjoint_after_solve_and_repeat_calls():
     assert np.allclose(J[0], g1["x0"], rtol=1e-12, atol=1e-15)
 
 
+def _plate_problem(G, H):
+    from workloads import plate_workload
+    w = plate_workload("large", 0, G=G, H=H)
+    p = N.Problem(N.plate_structure(G, H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi))
+    p.analyze()
+    p.set_parameters(w.T0, setpoint=w.target, u_prev=np.full(16, 0.5))
+    return p
+
+
+@pytest.mark.parametrize("family", ["distillation", "plate"])
+def test_jacobian_rows_are_the_seeded_adjoints(family):
+    """The Jacobian solves its nu seeds together (one batch of launches over
+    instances that share the factor); row k must be exactly what the
+    single-seed adjoint returns for e_k.  The 16 x 10 plate has supernodes on
+    the multi-workgroup solve path, so its launches carry tasks of every seed."""
+    _note(f"jacobian rows against seeded adjoints, {family}")
+    if family == "distillation":
+        w = distillation_workload("small", 1)
+        p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+        p.analyze()
+        p.set_parameters(w.x0, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
+    else:
+        p = _plate_problem(16, 10)
+    r = p.solve()
+    assert r.status == 0
+    for rep in range(2):   # the seed batch is built on the first call and reused
+        rc, J = p.jacobian_u1_x0()
+        assert rc == 0
+        for k in range(p.nu):
+            e = np.zeros(p.nu)
+            e[k] = 1.0
+            _, g = p.adjoint(e, 0.0)
+            assert np.array_equal(J[k], g["x0"]), (rep, k, float(np.max(np.abs(J[k] - g["x0"]))))
+
+
 def test_autograd_function():
     _note("torch autograd")
     import torch
