@@ -661,7 +661,68 @@ nmpc_status device_init(Problem& p, std::string& err) {
     std::vector<int32_t> tail_nodes;
     for (int Lv = tail; Lv < sy.depth; ++Lv)
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) tail_nodes.push_back(sy.level_list[i]);
-    for (int Lv = 0; Lv < tail; ++Lv) {
+    // The bottom levels where every supernode has at most one child and none is
+    // large are chains: one workgroup walks each chain (leaf first in the
+    // factorization and forward solve, root first in the backward solve), one
+    // launch for all of those levels instead of one per level.
+    auto chain_level = [&](int Lv) {
+        for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
+            const int32_t sn = sy.level_list[i];
+            if (big_fac[sn] || big_sol[sn] || sy.child_ptr[sn + 1] - sy.child_ptr[sn] > 1) return false;
+        }
+        return true;
+    };
+    int chain_top = 0;
+    while (chain_top < tail && chain_level(chain_top)) ++chain_top;
+    if (chain_top < 2) chain_top = 0;
+    // Update blocks: the pool is planned per execution step, and the chained
+    // levels run as one step (a chain can reach its third level while another
+    // is still at its first), so they count as one level there.
+    std::vector<int64_t> u_off = sy.u_off;
+    int64_t stored_u = sy.stored_u;
+    if (chain_top > 0) {
+        std::vector<int> lev(nsn, 0);
+        for (int Lv = 0; Lv < sy.depth; ++Lv)
+            for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i)
+                lev[sy.level_list[i]] = std::max(Lv, chain_top - 1) - (chain_top - 1);
+        update_block_pool(sy, lev, u_off, stored_u);
+    }
+    std::vector<std::vector<int32_t>> chains;   // leaf first
+    if (chain_top > 0) {
+        std::vector<char> has_parent(nsn, 0);
+        for (int i = sy.level_ptr[0]; i < sy.level_ptr[chain_top]; ++i) {
+            const int32_t sn = sy.level_list[i];
+            for (int c = sy.child_ptr[sn]; c < sy.child_ptr[sn + 1]; ++c) has_parent[sy.child_list[c]] = 1;
+        }
+        for (int i = sy.level_ptr[0]; i < sy.level_ptr[chain_top]; ++i) {
+            int32_t x = sy.level_list[i];
+            if (has_parent[x]) continue;
+            std::vector<int32_t> ch;
+            while (true) {
+                ch.push_back(x);
+                if (sy.child_ptr[x + 1] == sy.child_ptr[x]) break;
+                x = sy.child_list[sy.child_ptr[x]];
+            }
+            std::reverse(ch.begin(), ch.end());
+            chains.push_back(std::move(ch));
+        }
+        Step gf, gs, gr;
+        gf.kind = kStepGroupFactor;
+        gs.kind = kStepGroupFwd;
+        gr.kind = kStepGroupFwd;
+        for (const auto& ch : chains) {
+            gf.groups.push_back(make_group(ch));
+            gs.groups.push_back(gf.groups.back());
+            std::vector<int32_t> rest;
+            for (int32_t sn : ch)
+                if (!fused[sn]) rest.push_back(sn);
+            if (!rest.empty()) gr.groups.push_back(make_group(rest));
+        }
+        D.fac.push_back(gf);
+        D.fwd.push_back(gs);
+        if (!gr.groups.empty()) D.fwd_rest.push_back(gr);
+    }
+    for (int Lv = chain_top; Lv < tail; ++Lv) {
         Step gf, gs, gr;
         gf.kind = kStepGroupFactor;
         gs.kind = kStepGroupFwd;
@@ -720,7 +781,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
         D.fwd.push_back(gs);
         D.bwd.push_back(gb);
     }
-    for (int Lv = tail - 1; Lv >= 0; --Lv) {
+    for (int Lv = tail - 1; Lv >= chain_top; --Lv) {
         Step gb;
         gb.kind = kStepGroupBwd;
         std::vector<int4> bb;
@@ -751,6 +812,12 @@ nmpc_status device_init(Problem& p, std::string& err) {
             push(D.bwd, kBigBwdGemvT, std::move(gt));
         }
     }
+    if (!chains.empty()) {
+        Step gb;
+        gb.kind = kStepGroupBwd;
+        for (const auto& ch : chains) gb.groups.push_back(make_group(std::vector<int32_t>(ch.rbegin(), ch.rend())));
+        D.bwd.push_back(gb);
+    }
     D.fac_launches = 0;
     for (const auto& stp : D.fac) {
         if (stp.kind != kStepGroupFactor) {
@@ -762,14 +829,22 @@ nmpc_status device_init(Problem& p, std::string& err) {
         D.fac_launches += (int)in_lds + (int)global;
     }
     // front positions of the original entries: the large path keeps r + c (m | 1);
-    // a one-workgroup front takes its own layout (packed lower in shared memory,
-    // square with leading dimension m | 1 in a global buffer), a diagonal entry
+    // a one-workgroup front takes the layout of its group (packed lower in shared
+    // memory; square with leading dimension m | 1 in a global buffer when any
+    // front of the group is too large for shared memory), a diagonal entry
     // complemented (it takes + eta)
+    std::vector<char> square(nsn, 0);
+    for (const auto& stp : D.fac) {
+        if (stp.kind != kStepGroupFactor) continue;
+        for (const auto& g : stp.groups)
+            if (g.lds_factor > lim)
+                for (int i = g.begin; i < g.end; ++i) square[nodes[i]] = 1;
+    }
     std::vector<int32_t> k_fpos = sy.k_fpos;
     for (int sn = 0; sn < nsn; ++sn) {
         if (big_fac[sn]) continue;
         const int64_t mr = rows_of(sn), ld = mr | 1;
-        const bool packed = fac_bytes(sn) <= lim;
+        const bool packed = !square[sn];
         for (int32_t t = sy.k_ptr[sn]; t < sy.k_ptr[sn + 1]; ++t) {
             const int64_t pos = sy.k_fpos[t], r = pos % ld, c = pos / ld;
             const int64_t q = packed ? c * mr - c * (c + 1) / 2 + r : pos;
@@ -802,7 +877,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(upload_c(A, I.S.child_ptr, sy.child_ptr));
     DTRY(upload_c(A, I.S.child_list, sy.child_list));
     DTRY(upload_c(A, I.S.l_off, sy.l_off));
-    DTRY(upload_c(A, I.S.u_off, sy.u_off));
+    DTRY(upload_c(A, I.S.u_off, u_off));
     DTRY(upload_c(A, I.S.uv_off, sy.uv_off));
     DTRY(upload_c(A, I.S.rel_off, sy.rel_off));
     DTRY(upload_c(A, I.S.rel, sy.rel));
@@ -839,7 +914,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(dalloc(A, I.r1v, n)); DTRY(dalloc(A, I.r4s, ml)); DTRY(dalloc(A, I.vcomb_s, m)); DTRY(dalloc(A, I.rhs_s, n));
     DTRY(dalloc(A, I.dy_s, n)); DTRY(dalloc(A, I.ds_s, ml)); DTRY(dalloc(A, I.dom_s, ml)); DTRY(dalloc(A, I.dbe_s, ml));
     DTRY(dalloc(A, I.dzl_s, n)); DTRY(dalloc(A, I.dzu_s, n));
-    DTRY(dalloc(A, I.kv, I.nnzk)); DTRY(dalloc(A, I.L, sy.stored_l)); DTRY(dalloc(A, I.U, sy.stored_u));
+    DTRY(dalloc(A, I.kv, I.nnzk)); DTRY(dalloc(A, I.L, sy.stored_l)); DTRY(dalloc(A, I.U, stored_u));
     DTRY(dalloc(A, I.uvec, sy.stored_uv));
     DTRY(dalloc(A, I.adj_rhs, n)); DTRY(dalloc(A, I.adj_w, n));
     DTRY(dalloc(A, I.adj_out, st.nx + I.nsp + I.ntr + st.nu));

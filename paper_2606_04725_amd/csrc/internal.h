@@ -76,6 +76,9 @@ struct Problem {
 bool build_structure(const nmpc_structure& s, Structure& out, std::string& err);
 // SymCholesky (symbolic.cpp)
 void symbolic_analyze(const Structure& st, Symbolic& sym);
+// Update-block pool offsets for the given per-supernode execution steps.
+void update_block_pool(const Symbolic& sym, const std::vector<int>& lev, std::vector<int64_t>& u_off,
+                       int64_t& stored_u);
 // device side (device.hip)
 nmpc_status device_init(Problem& p, std::string& err);
 void device_free(Problem& p);

@@ -278,6 +278,73 @@ struct SNode {
 
 }  // namespace
 
+// Offsets of the update blocks ((rows - width)^2 doubles each) in a pool where
+// a block lives from its supernode's execution level until its parent's level
+// has run; released blocks are reused best-fit.  lev[s] is the step at which
+// supernode s runs: every supernode of a step must finish before the next step
+// starts, or a reused block could still be in use.
+void update_block_pool(const Symbolic& sym, const std::vector<int>& lev, std::vector<int64_t>& u_off,
+                       int64_t& stored_u) {
+    const int nsn = (int)sym.sn_ptr.size() - 1;
+    int depth = 0;
+    for (int s = 0; s < nsn; ++s) depth = std::max(depth, lev[s] + 1);
+    u_off.assign(nsn + 1, 0);
+    std::vector<std::vector<int32_t>> born(depth + 1), freed(depth + 2);
+    for (int s = 0; s < nsn; ++s) {
+        born[lev[s]].push_back(s);
+        const int end = sym.sn_parent[s] >= 0 ? lev[sym.sn_parent[s]] : lev[s];
+        freed[end + 1].push_back(s);
+    }
+    std::map<int64_t, int64_t> holes;   // offset -> size
+    int64_t top = 0;
+    auto ublock = [&](int s) {
+        const int64_t w = sym.sn_ptr[s + 1] - sym.sn_ptr[s];
+        const int64_t mr = sym.sn_rows_ptr[s + 1] - sym.sn_rows_ptr[s];
+        return (mr - w) * (mr - w);
+    };
+    for (int L = 0; L <= depth; ++L) {
+        for (int32_t s : freed[L]) {
+            const int64_t sz = ublock(s);
+            if (sz == 0) continue;
+            auto it = holes.emplace(u_off[s], sz).first;
+            auto nx = std::next(it);
+            if (nx != holes.end() && it->first + it->second == nx->first) {
+                it->second += nx->second;
+                holes.erase(nx);
+            }
+            if (it != holes.begin()) {
+                auto pv = std::prev(it);
+                if (pv->first + pv->second == it->first) {
+                    pv->second += it->second;
+                    holes.erase(it);
+                }
+            }
+        }
+        if (L == depth) break;
+        for (int32_t s : born[L]) {
+            const int64_t sz = ublock(s);
+            if (sz == 0) {
+                u_off[s] = 0;
+                continue;
+            }
+            auto best = holes.end();
+            for (auto it = holes.begin(); it != holes.end(); ++it)
+                if (it->second >= sz && (best == holes.end() || it->second < best->second)) best = it;
+            if (best == holes.end()) {
+                u_off[s] = top;
+                top += sz;
+            } else {
+                u_off[s] = best->first;
+                const int64_t rest = best->second - sz, off = best->first + sz;
+                holes.erase(best);
+                if (rest > 0) holes.emplace(off, rest);
+            }
+        }
+    }
+    stored_u = top;
+    u_off[nsn] = top;
+}
+
 void symbolic_analyze(const Structure& st, Symbolic& sym) {
     const int n = st.n;
     sym = Symbolic();
@@ -438,62 +505,7 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     }
     sym.stored_l = sym.l_off[nsn];
     sym.stored_uv = sym.uv_off[nsn];
-    {
-        std::vector<std::vector<int32_t>> born(sym.depth + 1), freed(sym.depth + 2);
-        for (int s = 0; s < nsn; ++s) {
-            born[lev[s]].push_back(s);
-            const int end = sym.sn_parent[s] >= 0 ? lev[sym.sn_parent[s]] : lev[s];
-            freed[end + 1].push_back(s);
-        }
-        std::map<int64_t, int64_t> holes;   // offset -> size
-        int64_t top = 0;
-        auto ublock = [&](int s) {
-            const int64_t w = sym.sn_ptr[s + 1] - sym.sn_ptr[s];
-            const int64_t mr = sym.sn_rows_ptr[s + 1] - sym.sn_rows_ptr[s];
-            return (mr - w) * (mr - w);
-        };
-        for (int L = 0; L <= sym.depth; ++L) {
-            for (int32_t s : freed[L]) {
-                const int64_t sz = ublock(s);
-                if (sz == 0) continue;
-                auto it = holes.emplace(sym.u_off[s], sz).first;
-                auto nx = std::next(it);
-                if (nx != holes.end() && it->first + it->second == nx->first) {
-                    it->second += nx->second;
-                    holes.erase(nx);
-                }
-                if (it != holes.begin()) {
-                    auto pv = std::prev(it);
-                    if (pv->first + pv->second == it->first) {
-                        pv->second += it->second;
-                        holes.erase(it);
-                    }
-                }
-            }
-            if (L == sym.depth) break;
-            for (int32_t s : born[L]) {
-                const int64_t sz = ublock(s);
-                if (sz == 0) {
-                    sym.u_off[s] = 0;
-                    continue;
-                }
-                auto best = holes.end();
-                for (auto it = holes.begin(); it != holes.end(); ++it)
-                    if (it->second >= sz && (best == holes.end() || it->second < best->second)) best = it;
-                if (best == holes.end()) {
-                    sym.u_off[s] = top;
-                    top += sz;
-                } else {
-                    sym.u_off[s] = best->first;
-                    const int64_t rest = best->second - sz, off = best->first + sz;
-                    holes.erase(best);
-                    if (rest > 0) holes.emplace(off, rest);
-                }
-            }
-        }
-        sym.stored_u = top;
-        sym.u_off[nsn] = top;
-    }
+    update_block_pool(sym, lev, sym.u_off, sym.stored_u);
     // relative positions of each supernode's below rows inside its parent's rows
     sym.rel_off.assign(nsn + 1, 0);
     for (int s = 0; s < nsn; ++s) sym.rel_off[s + 1] = sym.rel_off[s] + (sym.uv_off[s + 1] - sym.uv_off[s]);
