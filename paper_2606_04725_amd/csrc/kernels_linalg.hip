@@ -362,7 +362,8 @@ __device__ __attribute__((always_inline)) inline double lane_value(double v, int
 // v_j, x_k leaves lane k through the scalar unit, and the earlier columns take
 // the block's contribution before the next block.
 // Shared memory: diagonal block (w (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
-constexpr int kBwdCols = 4;
+constexpr int kBwdCols = 4;    // columns per 16-lane group in the rows-below product
+constexpr int kBwdDepth = 8;   // rows per lane whose loads are in flight together
 __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
                         const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
     const int f = S.sn_ptr[s];
@@ -421,12 +422,22 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
             acc[u] = 0.0;
             col[u] = Ls + (int64_t)(jc < w ? jc : 0) * m + w;
         }
-#pragma unroll 2
-        for (int i = sub; i < nb; i += kSub) {
-            const double xbi = xb[i];
+        // kBwdDepth rows per lane at a time, all their loads issued together
+        // (rows past nb load row nb - 1 and add zero; a column past w reads
+        // column 0 and is not stored)
+        for (int i0 = sub; i0 < nb; i0 += kSub * kBwdDepth) {
+            double lv[kBwdDepth][kBwdCols], xv[kBwdDepth];
 #pragma unroll
-            for (int u = 0; u < kBwdCols; ++u)
-                if (jc0 + u * ngrp < w) acc[u] = fma(col[u][i], xbi, acc[u]);
+            for (int t = 0; t < kBwdDepth; ++t) {
+                const int i = i0 + kSub * t, ic = min(i, nb - 1);
+                xv[t] = i < nb ? xb[ic] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kBwdCols; ++u) lv[t][u] = col[u][ic];
+            }
+#pragma unroll
+            for (int t = 0; t < kBwdDepth; ++t)
+#pragma unroll
+                for (int u = 0; u < kBwdCols; ++u) acc[u] = fma(lv[t][u], xv[t], acc[u]);
         }
 #pragma unroll
         for (int u = 0; u < kBwdCols; ++u) {
