@@ -562,14 +562,16 @@ nmpc_status device_init(Problem& p, std::string& err) {
         big_sol[sn] = sol_bytes(sn) > lim;
         if (!big_fac[sn] && fac_bytes(sn) > lim) medium_max = std::max<int>(medium_max, (int)mr);
     }
-    // Fused forward solves: a one-workgroup supernode whose whole subtree is
-    // one-workgroup as well runs the Newton step's forward solve right after its
-    // factorization (its children's update vectors are ready by then).
+    // Fused forward solves: a supernode whose children all run it runs the
+    // Newton step's forward solve with its factorization (their update vectors
+    // are ready by then): a one-workgroup front right after it, a large front
+    // panel by panel.  A one-workgroup front whose solve needs the large path
+    // keeps the separate solve.
     std::vector<int32_t> fused(nsn, 0);
     for (int Lv = 0; Lv < sy.depth; ++Lv)
         for (int i = sy.level_ptr[Lv]; i < sy.level_ptr[Lv + 1]; ++i) {
             const int32_t sn = sy.level_list[i];
-            bool ok = !big_fac[sn] && !big_sol[sn];
+            bool ok = big_fac[sn] || !big_sol[sn];
             for (int c = sy.child_ptr[sn]; ok && c < sy.child_ptr[sn + 1]; ++c) ok = fused[sy.child_list[c]] != 0;
             fused[sn] = ok ? 1 : 0;
         }
@@ -754,8 +756,13 @@ nmpc_status device_init(Problem& p, std::string& err) {
                 const int64_t c1 = std::min<int64_t>(w, c0 + CH);
                 for (int rb = 0; rb < ceil_div(m - c1, SR); ++rb) gv.push_back(int4{0, sn, c, rb});
             }
-            push(D.fwd_rest, kBigFwdTri, std::vector<int4>(tri));
-            push(D.fwd_rest, kBigFwdGemv, std::vector<int4>(gv));
+            std::vector<int4> tri_rest, gv_rest;   // the supernodes whose forward solve is not fused
+            for (const int4& t : tri)
+                if (!fused[t.y]) tri_rest.push_back(t);
+            for (const int4& t : gv)
+                if (!fused[t.y]) gv_rest.push_back(t);
+            push(D.fwd_rest, kBigFwdTri, std::move(tri_rest));
+            push(D.fwd_rest, kBigFwdGemv, std::move(gv_rest));
             push(D.fwd, kBigFwdTri, std::move(tri));
             push(D.fwd, kBigFwdGemv, std::move(gv));
         }

@@ -76,6 +76,18 @@ __device__ inline double* at(const Front& F, int i, int j) {
     return j < F.w ? F.L + i + (int64_t)j * F.m : F.U + (i - F.w) + (int64_t)(j - F.w) * (F.m - F.w);
 }
 
+// Fused forward substitution of the Newton step (eq. 23), run by the
+// factorization of a supernode whose whole subtree runs it: the vector over
+// the front's rows starts as the permuted right-hand side of its columns plus
+// the children's update vectors; each panel's solution replaces its entries,
+// and the rows below take the panel's product as their rows are solved.
+// Entry i lives in xp (i < w) or in the supernode's update vector (i >= w),
+// where the unfused solve leaves them too.
+__device__ inline bool fwd_fused(const InstPtrs& I, int s, int pred) { return pred == kPredFactor && I.S.fused[s]; }
+__device__ inline double* fwd_entry(const InstPtrs& I, const Front& F, int s, int i) {
+    return i < F.w ? I.xp + F.f + i : I.uvec + I.S.uv_off[s] + (i - F.w);
+}
+
 // ---- factorization ---------------------------------------------------------------
 // task (inst, s, j, -): zero column j of the front, then scatter the KKT slots
 // of column j (j < w), eta added on the diagonal.
@@ -87,6 +99,7 @@ k_big_init(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
     const double eta = pred == kPredAll ? eta_force : I.ctl->eta;
     const Front F = front_of(I, tk.y);
     const int j = tk.z;
+    if (threadIdx.x == 0 && fwd_fused(I, tk.y, pred)) *fwd_entry(I, F, tk.y, j) = j < F.w ? I.rhs[I.perm[F.f + j]] : 0.0;
     for (int i = j + threadIdx.x; i < F.m; i += blockDim.x) *at(F, i, j) = 0.0;
     if (j >= F.w) return;
     __syncthreads();
@@ -115,6 +128,7 @@ k_big_extend(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, in
     const int32_t* rel = I.S.rel + I.S.rel_off[c];
     const int jc = tk.w;
     const int rj = rel[jc];
+    if (threadIdx.x == 0 && fwd_fused(I, tk.y, pred)) *fwd_entry(I, F, tk.y, rj) += I.uvec[I.S.uv_off[c] + jc];
     const auto* uc = global(Uc) + (int64_t)jc * nc;
     const auto* rg = global(rel);
     // kExtendDepth rows per thread at a time: their loads are issued together
@@ -145,6 +159,7 @@ __global__ void __launch_bounds__(kBlock)
 k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
     static_assert(kBigPanel == kWave, "diagonal blocks are staged as 64 x 64 triangles");
     __shared__ double D[kTri];
+    __shared__ double fv[kBigPanel];   // the fused forward solve's entries of the panel
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
@@ -165,8 +180,10 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
             D[e % kBigPanel + (e / kBigPanel) * ldd] = t[s];
         }
     }
+    const bool fw = fwd_fused(I, tk.y, pred);
+    if (fw && (int)threadIdx.x < pw) fv[threadIdx.x] = *fwd_entry(I, F, tk.y, kb + threadIdx.x);
     __syncthreads();
-    partial_cholesky<8>(D, SquareIdx{ldd}, pw, pw, &I.ctl->fail);
+    partial_cholesky<8>(D, SquareIdx{ldd}, pw, pw, &I.ctl->fail, fw ? fv : nullptr, fw ? I.xp + F.f + kb : nullptr);
     for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
         const int i = e % kBigPanel, j = e / kBigPanel;
         if (i < pw && j <= i) global(F.L)[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
@@ -178,6 +195,15 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
 template <int SRC>
 __device__ inline double quad_bcast(double v) {
     constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// v of the lane whose index within the quad is the own one xor X (X = 1, 2).
+template <int X>
+__device__ inline double quad_xor(double v) {
+    constexpr int ctrl = X == 1 ? (1 | (0 << 2) | (3 << 4) | (2 << 6)) : (2 | (3 << 2) | (0 << 4) | (1 << 6));
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
@@ -249,14 +275,29 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) rq[(int64_t)i * F.m] = x[i];
+        if (fwd_fused(I, tk.y, pred)) {   // the row takes the panel's product with its solution
+            const double* xs = I.xp + F.f + kb + 16 * q;
+            double dot = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) dot = fma(x[i], xs[i], dot);
+            dot += quad_xor<1>(dot);
+            dot += quad_xor<2>(dot);
+            if (q == 0) *fwd_entry(I, F, tk.y, r) -= dot;
+        }
     } else if (q == 0) {
         // the last, narrower panel of a supernode: in place; D's diagonal was
         // zeroed, its reciprocal is in rd
+        const bool fw = fwd_fused(I, tk.y, pred);
+        const double* xs = I.xp + F.f + kb;
+        double dot = 0.0;
         for (int k = 0; k < pw; ++k) {
             double acc = row[(int64_t)k * F.m];
             for (int j = 0; j < k; ++j) acc = fma(-row[(int64_t)j * F.m], D[k + j * ldd], acc);
-            row[(int64_t)k * F.m] = acc * rd[k];
+            const double lk = acc * rd[k];
+            row[(int64_t)k * F.m] = lk;
+            if (fw) dot = fma(lk, xs[k], dot);
         }
+        if (fw) *fwd_entry(I, F, tk.y, r) -= dot;
     }
 }
 
