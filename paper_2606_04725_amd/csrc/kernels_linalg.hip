@@ -385,16 +385,22 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
     const double xv = tid < w ? xp[f + tid] : 0.0;
     const int pk = tid < w ? perm[f + tid] : 0;
     const int ww = w * w;
+    // entry e of the block is (r, c) = (e % w, e / w); the quotient through a
+    // single-precision reciprocal is exact here (e < w^2 <= 2^15, and (e + 1/2)
+    // / w stays at least 1 / (2 w) away from an integer)
+    const float rw = 1.0f / (float)w;
     for (int e0 = 0; e0 < ww; e0 += nthr * kBatch) {
         double t[kBatch];
+        int cc[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + tid + u * nthr, c = e / w, r = e - c * w;
+            const int e = e0 + tid + u * nthr, c = (int)(((float)e + 0.5f) * rw), r = e - c * w;
+            cc[u] = c;
             t[u] = (e < ww && r >= c) ? Ls[r + (int64_t)c * m] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + tid + u * nthr, c = e / w, r = e - c * w;
+            const int e = e0 + tid + u * nthr, c = cc[u], r = e - c * w;
             if (e < ww && r >= c) PT[c + r * ld] = t[u];
         }
     }
