@@ -190,46 +190,23 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
     }
 }
 
-// Value v of lane SRC of each group of four lanes, in every lane of the group
-// (DPP quad permutation: no shared memory, no wait).
-template <int SRC>
-__device__ inline double quad_bcast(double v) {
-    constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// v of the lane whose index within the quad is the own one xor X (X = 1, 2).
-template <int X>
-__device__ inline double quad_xor(double v) {
-    constexpr int ctrl = X == 1 ? (1 | (0 << 2) | (3 << 4) | (2 << 6)) : (2 | (3 << 2) | (0 << 4) | (1 << 6));
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ inline double quad_bcast(double v, int src) {
-    switch (src) {
-        case 0: return quad_bcast<0>(v);
-        case 1: return quad_bcast<1>(v);
-        case 2: return quad_bcast<2>(v);
-        default: return quad_bcast<3>(v);
-    }
-}
-
 // task (inst, s, kb, row block): solve x D^T = a for the rows
-// [kb + pw + rb kRowBlock, ...) below the factored diagonal block.  Four lanes
-// share a row, lane q holding its entries 16 q .. 16 q + 15 in registers; per
-// column k the lane holding x_k scales it by 1 / d_kk, a quad permutation hands
-// it to the other three, and each lane updates its 16 entries with the strict
-// lower part of D from shared memory (zero on and above the diagonal, so the
-// updates need no branches).  A narrower last panel is solved in place, one
-// lane per row.
+// [kb + pw + rb kRowBlock, ...) below the factored diagonal block D.  A full
+// panel goes by blocks of 16 columns (blocked substitution): wave v holds its
+// 16 rows in shared memory (leading dimension kLdx); for column block j the
+// wave takes the block's 16 x 16 tile in the matrix-core layout (lane (li, lk)
+// holds rows lk, lk + 4, lk + 8, lk + 12 of column li), subtracts the solved
+// blocks' products with D's strict lower blocks on v_mfma_f64_16x16x4f64, then
+// solves with D's 16 x 16 diagonal block column by column: the lanes of
+// column k scale it by 1 / d_kk and the value reaches the later columns'
+// lanes of its row by a shuffle.  A narrower last panel is solved in place,
+// one lane per row.
+constexpr int kLdx = 17;   // leading dimension of a wave's 16 rows in shared memory
 __global__ void __launch_bounds__(kBlock)
 k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int pred) {
     __shared__ double D[kTri];   // strict lower triangle
     __shared__ double rd[kBigPanel];
+    __shared__ double Xs[kBlock / kWave][kLdx * kBigPanel];
     const int4 tk = tasks[blockIdx.x];
     const InstPtrs& I = Ia[tk.x];
     if (!ctl_active(I.ctl, pred)) return;
@@ -255,39 +232,72 @@ k_big_trsm(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int 
         }
     }
     __syncthreads();
-    const int g = tid / 4, q = tid % 4;
-    const int r = r0 + g;
-    if (r >= F.m) return;   // all four lanes of a row leave together
-    gdouble* row = global(F.L) + r + (int64_t)kb * F.m;
+    const bool fw = fwd_fused(I, tk.y, pred);
     if (pw == kBigPanel) {
-        double x[16];
-        gdouble* rq = row + (int64_t)(16 * q) * F.m;
+        static_assert(kRowBlock == 16 * (kBlock / kWave), "a wave takes 16 rows of the block");
+        const int lane = tid & (kWave - 1), wv = tid / kWave, li = lane & 15, lk = lane >> 4;
+        const int rw = r0 + 16 * wv;
+        if (rw >= F.m) return;   // the whole wave (no barrier follows)
+        double* X = Xs[wv];
+        {
+            double t[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = rq[(int64_t)i * F.m];
+            for (int u = 0; u < 16; ++u) {
+                const int col = 4 * u + lk, r = rw + li;
+                t[u] = r < F.m ? global(F.L)[r + (int64_t)(kb + col) * F.m] : 0.0;
+            }
 #pragma unroll
-        for (int k = 0; k < kBigPanel; ++k) {
-            const int qk = k / 16, kk = k % 16;
-            x[kk] *= q == qk ? rd[k] : 1.0;
-            const double xk = quad_bcast(x[kk], qk);
-            const double* dk = D + 16 * q + k * ldd;
+            for (int u = 0; u < 16; ++u) X[li + (4 * u + lk) * kLdx] = t[u];
+        }
+        __builtin_amdgcn_wave_barrier();   // the wave's own shared-memory rows: program order suffices
 #pragma unroll
-            for (int i = 0; i < 16; ++i) x[i] = fma(-xk, dk[i], x[i]);
+        for (int j = 0; j < 4; ++j) {
+            f64x4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = X[(4 * r + lk) + (16 * j + li) * kLdx];
+#pragma unroll
+            for (int i = 0; i < j; ++i)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double av = -X[li + (16 * i + 4 * s + lk) * kLdx];
+                    const double bv = D[(16 * j + li) + (16 * i + 4 * s + lk) * ldd];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const double rdk = rd[16 * j + k];
+                const double dkl = D[(16 * j + li) + (16 * j + k) * ldd];   // zero unless li > k
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double own = li == k ? acc[r] * rdk : acc[r];
+                    const double xk = __shfl(own, (lane & ~15) | k, kWave);
+                    acc[r] = li > k ? fma(-xk, dkl, own) : own;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[(4 * r + lk) + (16 * j + li) * kLdx] = acc[r];
+            __builtin_amdgcn_wave_barrier();
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) rq[(int64_t)i * F.m] = x[i];
-        if (fwd_fused(I, tk.y, pred)) {   // the row takes the panel's product with its solution
-            const double* xs = I.xp + F.f + kb + 16 * q;
+        for (int u = 0; u < 16; ++u) {
+            const int col = 4 * u + lk, r = rw + li;
+            if (r < F.m) global(F.L)[r + (int64_t)(kb + col) * F.m] = X[li + col * kLdx];
+        }
+        if (fw) {   // each row takes the panel's product with its solution: lane (li, lk) sums 16 columns
+            const double* xs = I.xp + F.f + kb + 16 * lk;
             double dot = 0.0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) dot = fma(x[i], xs[i], dot);
-            dot += quad_xor<1>(dot);
-            dot += quad_xor<2>(dot);
-            if (q == 0) *fwd_entry(I, F, tk.y, r) -= dot;
+            for (int c = 0; c < 16; ++c) dot = fma(X[li + (16 * lk + c) * kLdx], xs[c], dot);
+            dot += __shfl_xor(dot, 16, kWave);
+            dot += __shfl_xor(dot, 32, kWave);
+            if (lk == 0 && rw + li < F.m) *fwd_entry(I, F, tk.y, rw + li) -= dot;
         }
-    } else if (q == 0) {
-        // the last, narrower panel of a supernode: in place; D's diagonal was
-        // zeroed, its reciprocal is in rd
-        const bool fw = fwd_fused(I, tk.y, pred);
+    } else if (tid < kRowBlock) {
+        // the last, narrower panel of a supernode: in place, one lane per row;
+        // D's diagonal was zeroed, its reciprocal is in rd
+        const int r = r0 + tid;
+        if (r >= F.m) return;
+        gdouble* row = global(F.L) + r + (int64_t)kb * F.m;
         const double* xs = I.xp + F.f + kb;
         double dot = 0.0;
         for (int k = 0; k < pw; ++k) {
