@@ -41,125 +41,122 @@ __device__ inline void tile_of(int tt, int nc, int& ti, int& tj) {
     }
 }
 
-// One panel step: pivot columns [kb, kb + kw) of the w to factor, kw <= P (a
-// full panel is called with kw = P as a constant, so its bounds checks fold
-// away).
+// Steps 1 and 2 of pivot columns [kb, kb + kw), kw <= P (a full panel is
+// called with kw = P as a constant, so its bounds checks fold away): d gets
+// the factored P x P pivot block, in the registers of every thread that takes
+// part (waves that own a row below the block, and wave 0, which stores the
+// block); the others would repeat the block's factorization for nothing on a
+// SIMD that a working wave shares.
 template <int P, class Idx>
-__device__ __attribute__((always_inline)) inline void panel_step(double* F, Idx ix, int m, int w, int kb, int kw, int* fail,
-                                                                double* fv, double* xo) {
+__device__ __attribute__((always_inline)) inline void panel_solve(double* F, Idx ix, int m, int kb, int kw, int* fail,
+                                                                 double* fv, double* xo, double (&d)[P][P]) {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & (kCholWave - 1), wv = tid / kCholWave, nw = nthr / kCholWave;
-    const int li = lane & 15, lk = lane >> 4;
-    {
-        // steps 1 and 2 run only in waves that own a row below the block (and
-        // wave 0, which stores the block): the others would repeat the block's
-        // factorization for nothing on a SIMD that a working wave shares
-        const bool rows_here = wv == 0 || kb + kw + wv * kCholWave < m;
-        double d[P][P];
-        double rinv[P], rd[P], xk[P];
-        if (rows_here) {
+    const int wv = tid / kCholWave;
+    if (!(wv == 0 || kb + kw + wv * kCholWave < m)) return;
+    double rinv[P], rd[P], xk[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i)
+    for (int i = 0; i < P; ++i)
 #pragma unroll
-                for (int j = 0; j < P; ++j)
-                    d[i][j] = (j <= i && i < kw) ? F[ix(kb + i, kb + j)] : (i == j ? 1.0 : 0.0);
-            bool bad = false;
+        for (int j = 0; j < P; ++j)
+            d[i][j] = (j <= i && i < kw) ? F[ix(kb + i, kb + j)] : (i == j ? 1.0 : 0.0);
+    bool bad = false;
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double piv = d[k][k];
-                if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
-                    bad = true;
-                    piv = 1.0;
-                }
-                // one reciprocal square root per pivot: d_kk = piv / sqrt(piv), and the
-                // reciprocal doubles as the row solves' 1 / d_kk
-                const double inv = rsqrt(piv);
-                rinv[k] = inv;
-                d[k][k] = piv * inv;
-#pragma unroll
-                for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
-#pragma unroll
-                for (int j = k + 1; j < P; ++j)
-#pragma unroll
-                    for (int i = j; i < P; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
-            }
-            if (bad && tid == 0) *fail = 1;
-#pragma unroll
-            for (int k = 0; k < P; ++k) rd[k] = k < kw ? rinv[k] : 1.0;
-            if (fv) {   // fv[kb, kb + kw) is final: every earlier panel updated it before the last barrier
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double acc = k < kw ? fv[kb + k] : 0.0;
-#pragma unroll
-                    for (int j = 0; j < k; ++j) acc = fma(-d[k][j], xk[j], acc);
-                    xk[k] = k < kw ? acc * rd[k] : 0.0;
-                }
-                if (tid < kw) {   // thread k stores x_k (picked from the registers by selects)
-                    double x = xk[0];
-#pragma unroll
-                    for (int k = 1; k < P; ++k) x = tid == k ? xk[k] : x;
-                    xo[kb + tid] = x;
-                }
-            }
-            // step 2 follows at once: it reads only rows below the block, and
-            // the factored block is stored after the next barrier, when every
-            // wave has read the block's original entries
-            for (int r = kb + kw + tid; r < m; r += nthr) {
-                double a[P];
-#pragma unroll
-                for (int j = 0; j < P; ++j) a[j] = j < kw ? F[ix(r, kb + j)] : 0.0;
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double s = a[k];
-#pragma unroll
-                    for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
-                    a[k] = s * rd[k];
-                }
-#pragma unroll
-                for (int j = 0; j < P; ++j)
-                    if (j < kw) F[ix(r, kb + j)] = a[j];
-                if (fv) {
-                    double acc = fv[r];
-#pragma unroll
-                    for (int j = 0; j < P; ++j) acc = fma(-a[j], xk[j], acc);
-                    fv[r] = acc;
-                }
-            }
+    for (int k = 0; k < P; ++k) {
+        double piv = d[k][k];
+        if (k < kw && (!(piv > 0.0) || !(piv < INFINITY))) {
+            bad = true;
+            piv = 1.0;
         }
-        __syncthreads();
-        // the factored diagonal block (nothing reads it before the front is stored)
+        // one reciprocal square root per pivot: d_kk = piv / sqrt(piv), and the
+        // reciprocal doubles as the row solves' 1 / d_kk
+        const double inv = rsqrt(piv);
+        rinv[k] = inv;
+        d[k][k] = piv * inv;
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-            if (tid == i && i < kw) {
+        for (int i = k + 1; i < P; ++i) d[i][k] *= inv;
 #pragma unroll
-                for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
-            }
-        // step 3, restricted to the columns [t0, w) still to be factored: the
-        // update block (columns w and on) takes all w columns at once at the end
-        const int t0 = kb + kw;
-        if (t0 < w) {
-            const int nt = (m - t0 + 15) / 16, nc = (w - t0 + 15) / 16;
-            for (int tt = wv; tt < tile_count(nt, nc); tt += nw) {
-                int ti, tj;
-                tile_of(tt, nc, ti, tj);
-                const int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
-                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int j = k + 1; j < P; ++j)
 #pragma unroll
-                for (int s4 = 0; s4 < P / 4; ++s4) {
-                    const int kk = 4 * s4 + lk;
-                    const double* col = F + ix.base(kb + kk);
-                    const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
-                    const double b = (kk < kw && j0 + li < w) ? col[j0 + li] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                }
+            for (int i = j; i < P; ++i) d[i][j] = fma(-d[i][k], d[j][k], d[i][j]);
+    }
+    if (bad && tid == 0) *fail = 1;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int ir = i0 + 4 * r + lk, jc = j0 + li;
-                    if (ir < m && jc <= ir && jc < w) F[ix(ir, jc)] -= acc[r];
-                }
-            }
+    for (int k = 0; k < P; ++k) rd[k] = k < kw ? rinv[k] : 1.0;
+    if (fv) {   // fv[kb, kb + kw) is final: every earlier panel updated it at least one barrier ago
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double acc = k < kw ? fv[kb + k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < k; ++j) acc = fma(-d[k][j], xk[j], acc);
+            xk[k] = k < kw ? acc * rd[k] : 0.0;
         }
-        __syncthreads();
+        if (tid < kw) {   // thread k stores x_k (picked from the registers by selects)
+            double x = xk[0];
+#pragma unroll
+            for (int k = 1; k < P; ++k) x = tid == k ? xk[k] : x;
+            xo[kb + tid] = x;
+        }
+    }
+    // step 2 follows at once: it reads only rows below the block, and the
+    // factored block is stored after the next barrier, when every wave has
+    // read the block's original entries
+    for (int r = kb + kw + tid; r < m; r += nthr) {
+        double a[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) a[j] = j < kw ? F[ix(r, kb + j)] : 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double s = a[k];
+#pragma unroll
+            for (int j = 0; j < k; ++j) s = fma(-a[j], d[k][j], s);
+            a[k] = s * rd[k];
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (j < kw) F[ix(r, kb + j)] = a[j];
+        if (fv) {
+            double acc = fv[r];
+#pragma unroll
+            for (int j = 0; j < P; ++j) acc = fma(-a[j], xk[j], acc);
+            fv[r] = acc;
+        }
+    }
+}
+
+// The factored pivot block into the front (thread i stores row i).
+template <int P, class Idx>
+__device__ __attribute__((always_inline)) inline void store_pivot_block(double* F, Idx ix, int kb, int kw,
+                                                                       const double (&d)[P][P]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (tid == i && i < kw) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
+        }
+}
+
+// Step 3 on one 16 x 16 tile (ti, tj) of the lower trapezoid right of and
+// below pivot columns [kb, kb + kw): rows [t0, m), columns [t0, w), t0 = kb +
+// kw.  One v_mfma_f64_16x16x4f64 per 4 pivot columns.
+template <int P, class Idx>
+__device__ __attribute__((always_inline)) inline void trapezoid_tile(double* F, Idx ix, int m, int w, int kb, int kw,
+                                                                    int ti, int tj) {
+    const int lane = threadIdx.x & (kCholWave - 1), li = lane & 15, lk = lane >> 4;
+    const int t0 = kb + kw, i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < P / 4; ++s4) {
+        const int kk = 4 * s4 + lk;
+        const double* col = F + ix.base(kb + kk);
+        const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
+        const double b = (kk < kw && j0 + li < w) ? col[j0 + li] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ir = i0 + 4 * r + lk, jc = j0 + li;
+        if (ir < m && jc <= ir && jc < w) F[ix(ir, jc)] -= acc[r];
     }
 }
 
@@ -203,8 +200,10 @@ __device__ __attribute__((always_inline)) inline void update_block(double* F, Id
 //     arithmetic in every such thread, no communication);
 //  2. every row below the block solves its own row of the panel against it;
 //  3. the panel's remaining columns take the rank-P update on the matrix
-//     cores: 16 x 16 output tiles, one v_mfma_f64_16x16x4f64 per 4 pivot
-//     columns;
+//     cores in 16 x 16 tiles: first the tile column holding the next pivot
+//     columns (P <= 16), then, after a barrier, the other tiles on the waves
+//     that have no rows of the next panel, while the waves that do run steps
+//     1 and 2 of the next panel (the two touch different columns);
 // and after the last panel the update block (rows and columns w and on) takes
 // the rank-w update of all panel columns at once.
 // A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
@@ -217,11 +216,38 @@ __device__ __attribute__((always_inline)) inline void update_block(double* F, Id
 template <int P, class Idx>
 __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
                                         double* xo = nullptr) {
-    for (int kb = 0; kb < w; kb += P) {
-        if (w - kb >= P)
-            panel_step<P>(F, ix, m, w, kb, P, fail, fv, xo);
-        else
-            panel_step<P>(F, ix, m, w, kb, w - kb, fail, fv, xo);
+    static_assert(P % 4 == 0 && P <= 16, "the next pivot columns lie in the first tile column");
+    const int wv = threadIdx.x / kCholWave, nw = blockDim.x / kCholWave;
+    double d[P][P];
+    if (w >= P)
+        panel_solve<P>(F, ix, m, 0, P, fail, fv, xo, d);
+    else if (w > 0)
+        panel_solve<P>(F, ix, m, 0, w, fail, fv, xo, d);
+    for (int kb = 0; kb < w; kb += P) {   // steps 1 and 2 of panel kb are done
+        const int kw = min(P, w - kb), t0 = kb + kw;
+        const int nt = (m - t0 + 15) / 16, nc = (w - t0 + 15) / 16;
+        __syncthreads();
+        store_pivot_block<P>(F, ix, kb, kw, d);
+        if (t0 < w)
+            for (int ti = wv; ti < nt; ti += nw) trapezoid_tile<P>(F, ix, m, w, kb, kw, ti, 0);
+        __syncthreads();
+        if (t0 < w) {
+            const int kw2 = min(P, w - t0);
+            // waves with rows of the next panel (wave 0 always takes part)
+            const int busy = min(nw, max(1, (m - t0 - kw2 + kCholWave - 1) / kCholWave));
+            const int rest = tile_count(nt - 1, nc - 1);
+            const int first = busy < nw ? wv - busy : wv, stride = busy < nw ? nw - busy : nw;
+            if (first >= 0)
+                for (int tt = first; tt < rest; tt += stride) {
+                    int ti, tj;
+                    tile_of(tt, nc - 1, ti, tj);
+                    trapezoid_tile<P>(F, ix, m, w, kb, kw, ti + 1, tj + 1);
+                }
+            if (kw2 == P)
+                panel_solve<P>(F, ix, m, t0, P, fail, fv, xo, d);
+            else
+                panel_solve<P>(F, ix, m, t0, kw2, fail, fv, xo, d);
+        }
     }
     if (m > w) update_block(F, ix, m, w);
 }
