@@ -384,6 +384,22 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
     const double dg = tid < w ? Ls[tid + (int64_t)tid * m] : 1.0;
     const double xv = tid < w ? xp[f + tid] : 0.0;
     const int pk = tid < w ? perm[f + tid] : 0;
+    // rows-below product: 16 lanes per column, kBwdCols columns per lane group;
+    // when it takes one pass (w <= kBwdCols * groups, nb <= kSub * kBwdDepth)
+    // the panel's values are loaded here, with everything else
+    constexpr int kSub = 16;
+    const int sub = tid % kSub, grp = tid / kSub, ngrp = nthr / kSub;
+    const bool one_pass = nb > 0 && w <= kBwdCols * ngrp && nb <= kSub * kBwdDepth;
+    double lp[kBwdDepth][kBwdCols];
+    if (one_pass && grp < w) {
+#pragma unroll
+        for (int u = 0; u < kBwdCols; ++u) {
+            const int jc = grp + u * ngrp;
+            const double* col = Ls + (int64_t)(jc < w ? jc : 0) * m + w;
+#pragma unroll
+            for (int t = 0; t < kBwdDepth; ++t) lp[t][u] = col[min(sub + kSub * t, nb - 1)];
+        }
+    }
     const int ww = w * w;
     // entry e of the block is (r, c) = (e % w, e / w); the quotient through a
     // single-precision reciprocal is exact here (e < w^2 <= 2^15, and (e + 1/2)
@@ -417,8 +433,26 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
         v[k] = xp[f + k];
     }
     __syncthreads();
-    constexpr int kSub = 16;
-    const int sub = tid % kSub, grp = tid / kSub, ngrp = nthr / kSub;
+    if (one_pass) {
+        if (grp < w) {   // uniform over each 16-lane group
+            double acc[kBwdCols];
+#pragma unroll
+            for (int u = 0; u < kBwdCols; ++u) acc[u] = 0.0;
+#pragma unroll
+            for (int t = 0; t < kBwdDepth; ++t) {
+                const int i = sub + kSub * t;
+                const double xv = i < nb ? xb[min(i, nb - 1)] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kBwdCols; ++u) acc[u] = fma(lp[t][u], xv, acc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kBwdCols; ++u) {
+                for (int off = kSub / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, kSub);
+                const int jc = grp + u * ngrp;
+                if (sub == 0 && jc < w) v[jc] -= acc[u];
+            }
+        }
+    } else
     for (int jc0 = grp; jc0 < w; jc0 += kBwdCols * ngrp) {
         double acc[kBwdCols];
         const double* col[kBwdCols];
