@@ -205,7 +205,8 @@ __device__ __attribute__((always_inline)) inline void update_block(double* F, Id
 //     that have no rows of the next panel, while the waves that do run steps
 //     1 and 2 of the next panel (the two touch different columns);
 // and after the last panel the update block (rows and columns w and on) takes
-// the rank-w update of all panel columns at once.
+// the rank-w update of all panel columns at once (unless the caller does so
+// itself, with_update = false, e.g. to store the panel meanwhile).
 // A pivot that is not positive and finite sets *fail (eq. 12: the matrix is not
 // numerically positive definite); the arithmetic continues with pivot 1.
 // With fv, a forward substitution rides along: fv (shared memory, m values)
@@ -215,7 +216,7 @@ __device__ __attribute__((always_inline)) inline void update_block(double* F, Id
 // is the update vector of the rows below.
 template <int P, class Idx>
 __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
-                                        double* xo = nullptr) {
+                                        double* xo = nullptr, bool with_update = true) {
     static_assert(P % 4 == 0 && P <= 16, "the next pivot columns lie in the first tile column");
     const int wv = threadIdx.x / kCholWave, nw = blockDim.x / kCholWave;
     double d[P][P];
@@ -249,7 +250,7 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
                 panel_solve<P>(F, ix, m, t0, kw2, fail, fv, xo, d);
         }
     }
-    if (m > w) update_block(F, ix, m, w);
+    if (with_update && m > w) update_block(F, ix, m, w);
 }
 
 }  // namespace nmpc
