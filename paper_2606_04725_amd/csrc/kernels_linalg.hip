@@ -104,6 +104,18 @@ __device__ __attribute__((always_inline)) inline void child_round(const double* 
     }
 }
 
+// The group's first supernode, or -1 when the instance is not in the launch's
+// phase.  Both reads are issued before either is waited for (groups are never
+// empty, so the schedule entry exists whatever the phase).
+__device__ __attribute__((always_inline)) inline int first_node(const InstPtrs& I, const Group& g, int pred) {
+    const int32_t* sched = I.S.sched_nodes;
+    const Ctl* c = I.ctl;   // every instance has its control block
+    const int s0 = sched[g.begin];
+    const int ph = c->phase;
+    const bool active = pred == kPredAll || (pred == kPredFactor ? (ph == kPhB || ph == kPhF) : ph == pred);
+    return active ? s0 : -1;
+}
+
 // One supernode: assemble the front, factor it, store the L panel and update.
 // Shared-memory fronts are packed lower triangles; the global buffer of a
 // medium front is square with an odd leading dimension.
@@ -246,14 +258,15 @@ k_factor_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ group
     extern __shared__ double lds[];
     const Group g = groups[blockIdx.x];
     const InstPtrs& I = Ia[g.inst];
-    if (!ctl_active(I.ctl, pred)) return;
+    const int s0 = first_node(I, g, pred);
+    if (s0 < 0) return;
     const double eta = pred == kPredAll ? eta_force : I.ctl->eta;
     // the front: shared memory, or the instance's global scratch for medium
     // fronts; then the fused forward solve's vector in shared memory
     double* F = Lds ? lds : I.gscratch + (int64_t)g.slot * I.gstride;
     const bool fwd = pred == kPredFactor;   // in a pass: the Newton step's right-hand side is assembled
     for (int i = g.begin; i < g.end; ++i) {
-        const int s = I.S.sched_nodes[i];
+        const int s = i == g.begin ? s0 : I.S.sched_nodes[i];
         const int m = (int)(I.S.rows_ptr[s + 1] - I.S.rows_ptr[s]);
         double* v = Lds ? lds + (m * (m + 1)) / 2 : lds;
         factor_one<Lds, P>(s, I.S, I.kv, eta, I.L, I.U, &I.ctl->fail, F, v, I, fwd);
@@ -340,9 +353,10 @@ k_fwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, 
     extern __shared__ double lds[];
     const Group g = groups[blockIdx.x];
     const InstPtrs& I = Ia[g.inst];
-    if (!ctl_active(I.ctl, pred)) return;
+    const int s0 = first_node(I, g, pred);
+    if (s0 < 0) return;
     for (int i = g.begin; i < g.end; ++i)
-        fwd_one(I.S.sched_nodes[i], I.S, I.L, I.uvec, solve_in(I, which), I.perm, I.xp, lds);
+        fwd_one(i == g.begin ? s0 : I.S.sched_nodes[i], I.S, I.L, I.uvec, solve_in(I, which), I.perm, I.xp, lds);
 }
 
 // Value of v in lane k of the wave, in every lane (k wave-uniform).
@@ -531,8 +545,10 @@ k_bwd_groups(const InstPtrs* __restrict__ Ia, const Group* __restrict__ groups, 
     extern __shared__ double lds[];
     const Group g = groups[blockIdx.x];
     const InstPtrs& I = Ia[g.inst];
-    if (!ctl_active(I.ctl, pred)) return;
-    for (int i = g.begin; i < g.end; ++i) bwd_one(I.S.sched_nodes[i], I.S, I.L, I.xp, I.perm, solve_out(I, which), lds);
+    const int s0 = first_node(I, g, pred);
+    if (s0 < 0) return;
+    for (int i = g.begin; i < g.end; ++i)
+        bwd_one(i == g.begin ? s0 : I.S.sched_nodes[i], I.S, I.L, I.xp, I.perm, solve_out(I, which), lds);
 }
 
 }  // namespace
