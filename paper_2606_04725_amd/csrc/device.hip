@@ -883,6 +883,16 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(upload_c(A, I.S.rows, sy.sn_rows));
     DTRY(upload_c(A, I.S.child_ptr, sy.child_ptr));
     DTRY(upload_c(A, I.S.child_list, sy.child_list));
+    {
+        std::vector<ChildRec> rec(sy.child_list.size());
+        for (size_t k = 0; k < rec.size(); ++k) {
+            const int c = sy.child_list[k];
+            const int wc = sy.sn_ptr[c + 1] - sy.sn_ptr[c];
+            rec[k] = ChildRec{u_off[c], sy.rel_off[c], sy.uv_off[c],
+                              (int32_t)(sy.sn_rows_ptr[c + 1] - sy.sn_rows_ptr[c]) - wc, c};
+        }
+        DTRY(upload_c(A, I.S.child_rec, rec));
+    }
     DTRY(upload_c(A, I.S.l_off, sy.l_off));
     DTRY(upload_c(A, I.S.u_off, u_off));
     DTRY(upload_c(A, I.S.uv_off, sy.uv_off));

@@ -30,12 +30,21 @@ struct DistillConst {
 };
 
 // Per-supernode read-only symbolic data of one instance.
+// What the extend-add of the child at one position of child_list reads:
+// its update block (u_off), its rows' positions in the parent (rel_off), its
+// update vector (uv_off) and its number of rows below its columns (nc).
+struct ChildRec {
+    int64_t u_off, rel_off, uv_off;
+    int32_t nc, child;
+};
+
 struct SnView {
     const int32_t* sn_ptr;
     const int64_t* rows_ptr;
     const int32_t* rows;
     const int32_t* child_ptr;
     const int32_t* child_list;
+    const ChildRec* child_rec;    // per child_list position
     const int64_t* l_off;
     const int64_t* u_off;
     const int64_t* uv_off;

@@ -140,22 +140,24 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
     int ci = c0, nc = 0, ne = 0, e0 = 0;
     const double* Uc = nullptr;
     const int32_t* rel = nullptr;
-    auto open_child = [&](int k) {
-        const int c = S.child_list[k];
-        const int wc = S.sn_ptr[c + 1] - S.sn_ptr[c];
-        nc = (int)(S.rows_ptr[c + 1] - S.rows_ptr[c]) - wc;
+    const double* uvc = nullptr;
+    auto open_child = [&](int k) {   // one record read per child
+        const ChildRec cr = S.child_rec[k];
+        nc = cr.nc;
         ne = (nc * (nc + 1)) / 2;
-        Uc = U + S.u_off[c];
-        rel = S.rel + S.rel_off[c];
+        Uc = U + cr.u_off;
+        rel = S.rel + cr.rel_off;
+        uvc = fw ? I.uvec + cr.uv_off : nullptr;
         e0 = 0;
     };
-    int cur_c = -1, cur_nc = 0;          // the child whose round is in ra
+    const double* cur_uv = nullptr;      // the child whose round is in ra
+    int cur_nc = 0;
     const int32_t* cur_rel = nullptr;
     bool cur_first = false;
     if (ci < c1) {
         open_child(ci);
-        child_round(Uc, rel, nc, ne, e0, ra, fw ? I.uvec + S.uv_off[S.child_list[ci]] : nullptr);
-        cur_c = S.child_list[ci];
+        child_round(Uc, rel, nc, ne, e0, ra, uvc);
+        cur_uv = uvc;
         cur_nc = nc;
         cur_rel = rel;
         cur_first = true;
@@ -209,7 +211,7 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
         const bool new_child = cn != ci;
         if (next) {
             if (new_child) open_child(cn);
-            child_round(Uc, rel, nc, ne, e0, rb, fw && new_child ? I.uvec + S.uv_off[S.child_list[cn]] : nullptr);
+            child_round(Uc, rel, nc, ne, e0, rb, new_child ? uvc : nullptr);
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
@@ -218,14 +220,13 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
 #pragma unroll
             for (int u = 0; u < kUvec; ++u)
                 if (ra.ur[u] >= 0) v[ra.ur[u]] += ra.uv[u];
-            const double* uc = I.uvec + S.uv_off[cur_c];
-            for (int i = tid + kUvec * nthr; i < cur_nc; i += nthr) v[cur_rel[i]] += uc[i];
+            for (int i = tid + kUvec * nthr; i < cur_nc; i += nthr) v[cur_rel[i]] += cur_uv[i];
         }
         if (new_child || !next) __syncthreads();
         if (!next) break;
         cur_first = new_child;
         if (new_child) {
-            cur_c = S.child_list[cn];
+            cur_uv = uvc;
             cur_nc = nc;
             cur_rel = rel;
         }
