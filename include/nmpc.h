@@ -118,6 +118,10 @@ typedef struct nmpc_options {
     int32_t timing;      /* 1: record HIP events around each phase (device times in nmpc_result) */
     int32_t graph;       /* 1 (default): capture one pass of the method as a HIP graph and replay it;
                             0: launch every kernel of every pass from the host */
+    int32_t fixed_mu;    /* 0 (default): Algorithm 2's barrier homotopy.  1: Newton's method on one
+                            barrier problem: mu stays at its initial value (mu0_warm / mu0_cold), and
+                            the solve ends when E_mu <= tol (eq. 27's inner test with tol in place
+                            of kappa_eps mu), e.g. to re-solve a barrier solution tightly */
 } nmpc_options;
 
 typedef struct nmpc_result {
@@ -253,8 +257,9 @@ nmpc_status nmpc_assemble(nmpc_problem* p, double mu, double* k_vals, double* rh
  * trajectory (grad_traj: distillation zF[H]; untouched for the plate) and
  * u_prev (grad_uprev[nu]; zeros for the plate); outputs may be NULL, seed_u1
  * may not.  Host arrays.
- * BAD_ORDER without a solution; REG_FAIL (positive) when K needed eta > 0 to
- * factor (the gradient is then that of the regularized system). */
+ * BAD_ORDER without a solution or when parameters were set after it;
+ * REG_FAIL (positive) when K needed eta > 0 to factor (the gradient is then
+ * that of the regularized system). */
 nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj, double* grad_x0,
                          double* grad_setpoint, double* grad_traj, double* grad_uprev);
 
@@ -265,6 +270,17 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
  * vectors (about 8 (5 n + 2 m + update vectors) bytes per seed), later calls
  * reuse them.  Same conditions as nmpc_adjoint. */
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
+
+/* Identity of the iterate the handle holds: *id counts the iterates it has
+ * taken (each nmpc_solve that returned a status >= 0, each batch solve it was
+ * part of, each nmpc_set_iterate; 0 before the first); *current (may be NULL)
+ * is 1 while no parameter has been set since, 0 otherwise.  The
+ * sensitivities differentiate the held iterate for the parameters it was
+ * computed with, so nmpc_adjoint, nmpc_adjoint_dev and nmpc_jacobian_u1_x0
+ * return BAD_ORDER when *current would be 0; a caller that differentiates
+ * later (e.g. an autograd backward) compares *id with the one it saw after
+ * its solve. */
+nmpc_status nmpc_solution_id(const nmpc_problem* p, int64_t* id, int32_t* current);
 
 /* Device-pointer variants (Algorithm 1's parameter update, the solution read
  * and the sensitivities without a host round trip, e.g. for tensors that live

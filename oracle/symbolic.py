@@ -294,6 +294,50 @@ def amalgamate(starts, parent, struct, n):
     return snode_ptr, rows
 
 
+def etree_liu(n, rows, cols, iperm):
+    """Elimination tree of P K P^T straight from the pattern (Liu's algorithm
+    with path compression; no column structures), for sizes where the column
+    structures of L do not fit in memory.  rows/cols: lower pattern in the
+    original indexing; iperm: old -> new.  parent(j) = min{i > j : L_ij != 0}:
+    row k of the permuted matrix is visited in increasing k; from every
+    earlier column i it touches, the walk climbs i's current ancestors to the
+    root of i's subtree, which becomes a child of k."""
+    a = np.asarray(iperm, dtype=np.int64)[np.asarray(rows, dtype=np.int64)]
+    b = np.asarray(iperm, dtype=np.int64)[np.asarray(cols, dtype=np.int64)]
+    hi, lo = np.maximum(a, b), np.minimum(a, b)
+    off = hi != lo
+    hi, lo = hi[off], lo[off]
+    order = np.lexsort((lo, hi))
+    hi, lo = hi[order].tolist(), lo[order].tolist()
+    parent = [-1] * n
+    anc = [-1] * n
+    for k, i in zip(hi, lo):
+        while True:
+            nxt = anc[i]
+            anc[i] = k
+            if nxt == -1:
+                parent[i] = k
+                break
+            if nxt == k:
+                break
+            i = nxt
+    return np.array(parent, dtype=np.int64)
+
+
+def final_permutation(n, rows, cols, lattice=None, stages=None):
+    """The permutation of ``analyze`` (ordering, then the postorder of its
+    elimination tree) without the column structures: perm (new -> old)."""
+    if lattice is not None:
+        perm_md = lattice_nd_order(n, adjacency_from_lower(n, rows, cols), *lattice)
+    elif stages is not None:
+        perm_md = stage_nd_order(*stages)
+    else:
+        perm_md = min_degree_order(n, adjacency_from_lower(n, rows, cols))
+    iperm_md = np.empty(n, dtype=np.int64)
+    iperm_md[perm_md] = np.arange(n)
+    return perm_md[postorder(etree_liu(n, rows, cols, iperm_md))]
+
+
 def analyze(n, rows, cols, lattice=None, stages=None):
     """Full symbolic analysis of a lower pattern (original indexing).
 

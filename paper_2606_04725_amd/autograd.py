@@ -3,7 +3,9 @@
 Forward runs nmpc_solve for the given parameters and returns the first-stage
 control u_1* and the optimal objective f*; backward calls the sensitivity
 entry point, which reuses the factorization of the condensed KKT matrix at the
-solution (one forward/back solve with refinement per backward call).  With
+solution (one forward/back solve with refinement per backward call).  The
+handle holds one solution at a time: backward raises when the problem was
+solved again, or its parameters changed, after the forward it belongs to.  With
 CUDA tensors the parameters, u_1*, the seeds and the gradients stay on the GPU
 (the *_dev entry points, ordered on torch's current stream); with CPU tensors
 they cross the C ABI as host arrays.
@@ -50,6 +52,7 @@ class NMPCSolve(torch.autograd.Function):
         else:
             u1 = torch.as_tensor(problem.first_stage()[0], dtype=torch.float64)
         ctx.problem = problem
+        ctx.solution_id = problem.solution_id()[0]
         ctx.cuda = cuda
         ctx.device = dev
         ctx.shapes = (setpoint is not None, traj is not None, u_prev is not None)
@@ -59,6 +62,13 @@ class NMPCSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_u1, g_f):
         p = ctx.problem
+        sid, current = p.solution_id()
+        if sid != ctx.solution_id or not current:
+            # the handle holds another solution (a later solve or parameter
+            # change on the same problem): its sensitivities are not this
+            # forward's
+            raise RuntimeError("NMPCSolve.backward: the problem was solved again or its parameters changed "
+                               "after this forward; use one problem per differentiated solve")
         has_sp, has_tr, has_up = ctx.shapes
         dev = ctx.device
         if ctx.cuda:

@@ -40,7 +40,8 @@ class nmpc_options(C.Structure):
                 ("filter_s_theta", C.c_double), ("filter_s_phi", C.c_double), ("filter_delta", C.c_double),
                 ("alpha_min_frac", C.c_double), ("theta_max_fact", C.c_double), ("theta_min_fact", C.c_double),
                 ("filter_cap", C.c_int32), ("soc_max", C.c_int32), ("soc_kappa", C.c_double),
-                ("merit_fallback", C.c_int32), ("timing", C.c_int32), ("graph", C.c_int32)]
+                ("merit_fallback", C.c_int32), ("timing", C.c_int32), ("graph", C.c_int32),
+                ("fixed_mu", C.c_int32)]
 
 
 class nmpc_result(C.Structure):
@@ -82,6 +83,7 @@ SIGNATURES = {
     "nmpc_get_solution_dev": (C.c_int32, [_P] + [C.c_void_p] * 8),
     "nmpc_adjoint_dev": (C.c_int32, [_P] + [C.c_void_p] * 7),
     "nmpc_jacobian_u1_x0": (C.c_int32, [_P, _D]),
+    "nmpc_solution_id": (C.c_int32, [_P, _L, _I]),
     "nmpc_autotune": (C.c_int32, [_P, C.c_int32, _I]),
     "nmpc_batch_create": (C.c_int32, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
     "nmpc_batch_solve": (C.c_int32, [_P, C.c_int32, C.POINTER(nmpc_options), C.POINTER(nmpc_result)]),

@@ -42,7 +42,7 @@ bool resolve_options(const nmpc_options* opts, nmpc_options& o) {
            o.mu0_warm > 0 && o.eta_first > 0 && o.kp_first > 1 && o.kp > 1 && o.eta_max > 0 && o.filter_cap >= 1 &&
            o.filter_cap <= nmpc::kFilterCapacity && o.alpha_min_frac > 0 &&
            o.soc_max >= 0 && o.soc_kappa > 0 &&
-           (o.merit_fallback == 0 || o.merit_fallback == 1);
+           (o.merit_fallback == 0 || o.merit_fallback == 1) && (o.fixed_mu == 0 || o.fixed_mu == 1);
 }
 
 template <class F>
@@ -65,6 +65,7 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
                          double* grad_setpoint, double* grad_traj, double* grad_uprev) {
     if (!p || !seed_u1) return fail(NMPC_ERR_INVALID_ARG, "adjoint: NULL handle or seed");
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "adjoint: no solution yet");
+    if (!p->impl.params_current) return fail(NMPC_ERR_BAD_ORDER, "adjoint: parameters changed since the last solve");
     if (!std::isfinite(seed_obj) || !all_finite(seed_u1, p->impl.st.nu))
         return fail(NMPC_ERR_INVALID_ARG, "adjoint: non-finite seed");
     std::string err;
@@ -76,6 +77,8 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac) {
     if (!p || !jac) return fail(NMPC_ERR_INVALID_ARG, "jacobian_u1_x0: NULL argument");
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0: no solution yet");
+    if (!p->impl.params_current)
+        return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0: parameters changed since the last solve");
     std::string err;
     nmpc_status rc = nmpc::device_jacobian_u1_x0(p->impl, jac, err);
     return rc >= 0 ? rc : fail(rc, err);
@@ -86,6 +89,7 @@ nmpc_status nmpc_set_parameters_dev(nmpc_problem* p, const double* x0, const dou
     if (!p || !x0) return fail(NMPC_ERR_INVALID_ARG, "set_parameters_dev: NULL handle or x0");
     if (!p->impl.analyzed || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "set_parameters_dev: call nmpc_analyze first");
     nmpc::device_invalidate_adjoint(p->impl);
+    p->impl.params_current = false;
     std::string err;
     nmpc_status rc = nmpc::device_set_parameters_dev(p->impl, x0, setpoint, traj, u_prev, stream, err);
     return rc == NMPC_OK ? rc : fail(rc, err);
@@ -104,6 +108,7 @@ nmpc_status nmpc_adjoint_dev(nmpc_problem* p, const double* seed_u1, const doubl
                              double* grad_setpoint, double* grad_traj, double* grad_uprev, void* stream) {
     if (!p) return fail(NMPC_ERR_INVALID_ARG, "adjoint_dev: NULL handle");
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "adjoint_dev: no solution yet");
+    if (!p->impl.params_current) return fail(NMPC_ERR_BAD_ORDER, "adjoint_dev: parameters changed since the last solve");
     std::string err;
     nmpc_status rc = nmpc::device_adjoint_dev(p->impl, seed_u1, seed_obj, grad_x0, grad_setpoint, grad_traj,
                                               grad_uprev, stream, err);
@@ -122,6 +127,13 @@ nmpc_status nmpc_autotune(nmpc_problem* p, int32_t reps, int32_t* changed) {
         if (changed) *changed = c;
         return NMPC_OK;
     });
+}
+
+nmpc_status nmpc_solution_id(const nmpc_problem* p, int64_t* id, int32_t* current) {
+    if (!p || !id) return fail(NMPC_ERR_INVALID_ARG, "solution_id: NULL argument");
+    *id = p->impl.solution_id;
+    if (current) *current = p->impl.params_current ? 1 : 0;
+    return NMPC_OK;
 }
 
 int32_t nmpc_device_available(void) { return nmpc::device_present() ? 1 : 0; }
@@ -163,6 +175,7 @@ void nmpc_default_options(nmpc_options* o) {
     o->merit_fallback = 1;
     o->timing = 0;
     o->graph = 1;
+    o->fixed_mu = 0;
 }
 
 nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
@@ -295,6 +308,7 @@ nmpc_status nmpc_set_parameters(nmpc_problem* p, const double* x0, const double*
     if (setpoint) P.setpoint.assign(setpoint, setpoint + nsp);
     if (traj) P.traj.assign(traj, traj + st.H);
     if (u_prev) P.u_prev.assign(u_prev, u_prev + st.nu);
+    P.params_current = false;
     if (P.dev) {
         nmpc::device_invalidate_adjoint(P);
         std::string err;
@@ -320,6 +334,8 @@ nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, 
         r.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
         if (rc < 0) return fail(rc, err);
         p->impl.have_iterate = true;
+        p->impl.params_current = true;
+        ++p->impl.solution_id;
         if (res) *res = r;
         return rc;
     });
@@ -384,6 +400,8 @@ nmpc_status nmpc_set_iterate(nmpc_problem* p, const double* y, const double* s, 
     nmpc_status rc = nmpc::device_set_iterate(p->impl, y, s, omega, beta, zL, zU, err);
     if (rc != NMPC_OK) return fail(rc, err);
     p->impl.have_iterate = true;
+    p->impl.params_current = true;
+    ++p->impl.solution_id;
     return NMPC_OK;
 }
 
@@ -475,6 +493,8 @@ nmpc_status nmpc_batch_solve(nmpc_batch* b, int32_t warm, const nmpc_options* op
         for (size_t i = 0; i < r.size(); ++i) {
             r[i].ms_total = ms;
             b->members[i]->impl.have_iterate = true;
+            b->members[i]->impl.params_current = true;
+            ++b->members[i]->impl.solution_id;
             nmpc::device_invalidate_adjoint(b->members[i]->impl);
         }
         if (per_instance) std::copy(r.begin(), r.end(), per_instance);

@@ -183,6 +183,7 @@ DevOpts dev_opts(const nmpc_options& o) {
     d.filter_cap = o.filter_cap;
     d.soc_max = o.soc_max;
     d.merit_fallback = o.merit_fallback;
+    d.fixed_mu = o.fixed_mu;
     return d;
 }
 

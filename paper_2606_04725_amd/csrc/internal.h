@@ -67,6 +67,10 @@ struct Problem {
     Symbolic sym;
     bool analyzed = false;
     bool have_iterate = false;
+    // the held iterate belongs to the parameters currently set (cleared by a
+    // parameter change, set by a solve or an explicit iterate)
+    bool params_current = false;
+    int64_t solution_id = 0;   // increases with every iterate the handle takes
     // parameters (host copies)
     std::vector<double> x0, setpoint, traj, u_prev;
     Device* dev = nullptr;

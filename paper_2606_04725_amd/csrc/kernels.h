@@ -185,7 +185,7 @@ struct DevOpts {
     double tol, mu_min, kappa_eps, kappa_mu, theta_mu, tau_min, armijo, kappa_sigma;
     double eta_first, eta_min, eta_max, kp_first, kp, km;
     double g_theta, g_phi, s_theta, s_phi, delta, amin_frac, theta_max_fact, theta_min_fact, soc_kappa;
-    int ls_max, max_iter, filter_cap, soc_max, merit_fallback;
+    int ls_max, max_iter, filter_cap, soc_max, merit_fallback, fixed_mu;
 };
 
 // One group of supernodes of one instance: sched_nodes[begin .. end), walked in

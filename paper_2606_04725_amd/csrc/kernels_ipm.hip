@@ -192,7 +192,8 @@ __global__ void __launch_bounds__(kBlock) k_decideA(const InstPtrs* __restrict__
     };
     const double E0 = Emu(0.0);
     c->E0 = E0;
-    if (E0 <= o.tol) {
+    // termination: eq. (28) on E_0, or, on one fixed barrier problem, E_mu
+    if ((o.fixed_mu ? Emu(c->mu) : E0) <= o.tol) {
         c->status = NMPC_OK;
         c->phase = kPhDone;
         return;
@@ -204,7 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_decideA(const InstPtrs* __restrict__
     }
     double mu = c->mu;
     double em = Emu(mu);
-    while (em <= o.kappa_eps * mu && mu > o.mu_min) {
+    while (!o.fixed_mu && em <= o.kappa_eps * mu && mu > o.mu_min) {
         mu = fmax(o.mu_min, fmin(o.kappa_mu * mu, pow(mu, o.theta_mu)));
         em = Emu(mu);
     }

@@ -219,6 +219,13 @@ class Problem:
                                                   grad_setpoint or None, grad_traj or None, grad_u_prev or None,
                                                   stream or None))
 
+    def solution_id(self):
+        """(id, current): id counts the iterates the handle has taken; current is
+        False once parameters were set after the last one."""
+        i, c = C.c_int64(), C.c_int32()
+        _check(capi.lib().nmpc_solution_id(self._h, C.byref(i), C.byref(c)))
+        return i.value, bool(c.value)
+
     def jacobian_u1_x0(self):
         jac = np.empty((self.nu, self.nx))
         rc = _check(capi.lib().nmpc_jacobian_u1_x0(self._h, _dp(jac)))

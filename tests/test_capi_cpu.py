@@ -85,6 +85,43 @@ def test_plate_symbolic_bit_exact_vs_oracle(G, H):
     assert set(zip(pat["w_rows"], pat["w_cols"])) == set(zip(m.h_rows, m.h_cols))
 
 
+def test_plate_symbolic_bit_exact_full_size():
+    """The 32 x 32 x 50 plate workload (n = 52,000): the whole analysis."""
+    from oracle.plate import PlateOCP
+    G, H = 32, 50
+    p = N.Problem(N.plate_structure(G, H, 0.01))
+    p.analyze()
+    lib = p.export_symbolic()
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
+    for key in ("perm", "parent", "colcount", "snode_ptr"):
+        assert np.array_equal(lib[key], a[key]), key
+    rp = lib["snode_rows_ptr"]
+    assert len(a["snode_rows"]) == lib["n_supernodes"]
+    for s_, rows in enumerate(a["snode_rows"]):
+        assert np.array_equal(lib["snode_rows"][rp[s_]:rp[s_ + 1]], rows)
+    assert lib["nnz_l"] == a["nnz_L"] and lib["flops"] == a["flops"]
+
+
+def test_plate_permutation_bit_exact_differentiated_size():
+    """The 64 x 64 x 100 plate (n = 411,200): the column structures of L
+    (6e8 entries) are out of reach of the oracle, so the contract there is the
+    permutation (ordering and elimination-tree postorder, from the pattern
+    alone) and its determinism across analyses."""
+    from oracle.plate import PlateOCP
+    G, H = 64, 100
+    p = N.Problem(N.plate_structure(G, H, 0.01))
+    p.analyze()
+    perm = p.export_symbolic()["perm"]
+    q = N.Problem(N.plate_structure(G, H, 0.01))
+    q.analyze()
+    assert np.array_equal(q.export_symbolic()["perm"], perm)
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    assert np.array_equal(perm, S.final_permutation(m.n, r, c, lattice=(H, G, m.ns)))
+
+
 def test_create_rejects_bad_structures():
     s = N.distillation_structure(10, 20, 0.1, 2.5)
     s.horizon = 0

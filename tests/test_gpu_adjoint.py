@@ -124,10 +124,47 @@ def test_autograd_function():
     u1, f = NMPCSolve.apply(p, x0, sp, tr, up, True)
     loss = 2.0 * u1[0] - u1[1] + 0.5 * f
     loss.backward()
-    # reference at the GPU's own solution
-    it = p.get_iterate()
-    st.y, st.s, st.omega, st.beta, st.zL, st.zU = (it[k] for k in ("y", "s", "omega", "beta", "zL", "zU"))
-    m.set_parameters(x0=w.x0)
+    # reference: the oracle's sensitivities at its own solution of the same
+    # parameters (the forward re-solved warm from that point on the GPU)
     sens = sensitivities(ipm, st)
     ref_x0 = np.array([2.0, -1.0]) @ sens["x0"]["du1"] + 0.5 * sens["x0"]["df"]
-    assert _rel(x0.grad.numpy(), ref_x0) <= TOL
+    assert _rel(x0.grad.numpy(), ref_x0) <= 1e-5
+    ref_sp = np.array([2.0, -1.0]) @ sens["setpoint"]["du1"] + 0.5 * sens["setpoint"]["df"]
+    assert _rel(sp.grad.numpy(), ref_sp) <= 1e-5
+
+
+def test_sensitivities_refuse_a_changed_problem():
+    """The handle holds one solution: after new parameters (without a solve) the
+    sensitivity entry points refuse, and an autograd backward whose forward's
+    solution has been replaced raises instead of differentiating another
+    solution."""
+    _note("stale sensitivities are refused")
+    import torch
+    from paper_2606_04725_amd import capi
+    from paper_2606_04725_amd.autograd import NMPCSolve
+    w = distillation_workload("small", 1)
+    p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+    p.analyze()
+    p.set_parameters(w.x0, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
+    assert p.solve().status == 0
+    sid, cur = p.solution_id()
+    assert cur and sid >= 1
+    p.set_parameters(w.x0 + 1e-3, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
+    assert p.solution_id() == (sid, False)
+    for call in (lambda: p.adjoint(np.ones(2), 0.0), p.jacobian_u1_x0):
+        with pytest.raises(N.NMPCError) as e:
+            call()
+        assert e.value.code == capi.NMPC_ERR_BAD_ORDER
+    assert p.solve(warm=True).status == 0
+    assert p.solution_id() == (sid + 1, True)
+    assert p.adjoint(np.ones(2), 0.0)[0] == 0
+    # two forwards on one problem, then the first one's backward
+    t = lambda v: torch.tensor(v, dtype=torch.float64)  # noqa: E731
+    x0a = t(w.x0).requires_grad_(True)
+    u1a, _ = NMPCSolve.apply(p, x0a, t([w.xD_sp, w.xB_sp]), t(w.zF(0)), t(w.u_prev0), True)
+    x0b = t(w.x0 + 1e-3).requires_grad_(True)
+    u1b, _ = NMPCSolve.apply(p, x0b, t([w.xD_sp, w.xB_sp]), t(w.zF(0)), t(w.u_prev0), True)
+    with pytest.raises(RuntimeError, match="solved again"):
+        u1a.sum().backward()
+    u1b.sum().backward()
+    assert torch.all(torch.isfinite(x0b.grad))

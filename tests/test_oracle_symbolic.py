@@ -101,6 +101,43 @@ def test_structure_matches_dense_elimination(seed):
         assert sorted(struct[j]) == list(np.nonzero(M[:, j])[0])
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_liu_etree_matches_dense_elimination(seed):
+    """The pattern-only elimination tree (Liu's algorithm) against brute-force
+    boolean elimination of the permuted matrix."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(5, 80))
+    dens = rng.uniform(0.02, 0.2)
+    rows, cols = [], []
+    for i in range(n):
+        for j in range(i + 1):
+            if i == j or rng.random() < dens:
+                rows.append(i)
+                cols.append(j)
+    perm = rng.permutation(n)
+    iperm = np.empty(n, dtype=int)
+    iperm[perm] = np.arange(n)
+    _, par_dense = _dense_symbolic(n, [iperm[r] for r in rows], [iperm[c] for c in cols])
+    assert np.array_equal(S.etree_liu(n, rows, cols, iperm), par_dense)
+
+
+def test_fig1_liu_etree():
+    lower, _, parent = _read_fig1()
+    rows = [r - 1 for c in lower for r in lower[c]]
+    cols = [c - 1 for c in lower for r in lower[c]]
+    par = S.etree_liu(6, rows, cols, np.arange(6))
+    assert [p + 1 if p >= 0 else 0 for p in par] == parent
+
+
+@pytest.mark.parametrize("G,H", [(4, 3), (8, 4), (12, 5)])
+def test_final_permutation_equals_full_analysis(G, H):
+    from oracle.plate import PlateOCP
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
+    assert np.array_equal(S.final_permutation(m.n, r, c, lattice=(H, G, m.ns)), a["perm"])
+
+
 def _check_min_degree(n, rows, cols, order):
     """Replay elimination on a dense boolean adjacency matrix and check that each
     pivot had the minimum current degree, with ties broken by smallest index."""
