@@ -248,11 +248,12 @@ class LiftedIPM:
         return float(np.sum(np.abs(self.g_lifted(self.nlp.cons_c(y), self.nlp.cons_d(y)) + s)))
 
     # ---- main loop ----------------------------------------------------
-    def solve(self, start: IPMState, mu0: float, record=False, fixed_mu=False, tol=None):
+    def solve(self, start: IPMState, mu0: float, record=False, fixed_mu=False, tol=None, progress=None):
         """Algorithm 2 from ``start`` with initial barrier value mu0.  With
         ``fixed_mu`` the barrier value is never decreased and the loop stops when
         E_mu <= tol (Newton's method on one barrier problem, used for finite
-        differences of the barrier solution)."""
+        differences of the barrier solution).  ``progress(it, mu, E0)``, when
+        given, is called once per iteration (logging only)."""
         o, nlp = self.o, self.nlp
         tol = o.tol if tol is None else tol
         st = start.copy()
@@ -276,6 +277,8 @@ class LiftedIPM:
                 status = 4
                 break
             E0 = self.errors(st, gf, c, d, Jc, Jd, 0.0)
+            if progress is not None:
+                progress(it, mu, E0)
             if fixed_mu:
                 if self.errors(st, gf, c, d, Jc, Jd, mu) <= tol:
                     status = 0

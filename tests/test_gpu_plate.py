@@ -18,52 +18,18 @@ from oracle.kkt import kkt_error
 from oracle.plate import PlateOCP
 from paper_2606_04725_amd import nmpc as N
 from workloads import plate_workload
+from plate_parity import PARITY_TOL, close, note, solve_pair, tighten_gpu, tighten_ref
 
 pytestmark = pytest.mark.gpu
 
 
-def _note(msg):
-    print(f"[gpu-case] {msg}", flush=True)
-    sys.stdout.flush()
-
-
-def _close(a, b, tol):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.max(np.abs(a - b))) / max(1.0, float(np.max(np.abs(b)))) <= tol
-
-
-# E_0 tolerance of the parity solves.  A cold start walks the barrier values
-# 0.1, 0.02, 2.83e-3, 1.50e-4, 1.84e-6, 2.5e-9 and then mu_min = 1e-9; at
-# 2.5e-9 the complementarity products s beta are about 2.5e-9, so E_0 cannot
-# fall below 2e-9 there, while at mu_min it settles near 1e-9.  Both sides
-# therefore stop at mu_min, on the same barrier problem, and their iterates are
-# comparable entry by entry (with the default 1e-8 a near-tie in the last
-# barrier update can stop one side a barrier step earlier).
-PARITY_TOL = 2e-9
+_note = note
+_close = close
 
 
 def _opts(**kw):
     from oracle.ipm import IPMOptions
     return IPMOptions(tol=PARITY_TOL, **kw)
-
-
-def _assert_parity(m, ipm, sol, r, ref):
-    """GPU solve against the oracle's, both ended on mu_min: y, lambda, zL and zU
-    within 1e-6 (relative to max(1, |ref|) per block), the original problem's
-    KKT error <= 1e-8 by the oracle's evaluator, equal objective.  The filter's
-    acceptance tests are threshold tests whose sums run in another order on the
-    two sides, so a near-tie can cost one side an extra iteration on the way to
-    the same barrier solution: the counts may differ by two."""
-    _note(f"iterations gpu {r.iters} oracle {ref.iters}; mu gpu {r.mu:.3e} oracle {ref.mu:.3e}")
-    assert r.mu == ipm.o.mu_min and ref.mu == ipm.o.mu_min, (r.mu, ref.mu)
-    e = kkt_error(m, sol["y"], sol["lam"], np.zeros(0), sol["zL"], sol["zU"])
-    assert e["max"] <= 1e-8, e
-    f_ref = m.f(ref.state.y)
-    assert abs(m.f(sol["y"]) - f_ref) <= 1e-8 * max(1.0, abs(f_ref))
-    lam_ref = ref.state.omega[:m.m_c] - ref.state.omega[m.m_c:2 * m.m_c]
-    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
-    for key, want in (("y", ref.state.y), ("lam", lam_ref), ("zL", ref.state.zL), ("zU", ref.state.zU)):
-        assert _close(sol[key], want, 1e-6), key
 
 
 def _pair(G, H, seed=0):
@@ -141,20 +107,16 @@ def test_plate_factor_and_solve_match_dense_cholesky(G, H):
 def _cold_and_warm(m, p, ipm):
     """Cold solve on both sides, then one plant step (from the oracle's u_1, so
     both sides get the same new x0) and a warm re-solve of each side from its
-    own previous iterate."""
-    gopts = N.default_options(tol=PARITY_TOL)
+    own previous (tightened) iterate."""
     ref = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
     assert ref.status == 0
-    r = p.solve(warm=False, options=gopts)
-    assert r.status == 0
-    _assert_parity(m, ipm, p.solution(), r, ref)
-    x1 = m.step(m.x0, m.u1(ref.state.y))
+    ref_t = solve_pair(m, p, ipm, ref, warm=False)
+    x1 = m.step(m.x0, m.u1(ref_t.state.y))
     m.set_parameters(x0=x1)
     p.set_parameters(x1)
-    ref2 = ipm.solve(ref.state, ipm.o.mu0_warm)
-    r2 = p.solve(warm=True, options=gopts)
-    assert ref2.status == 0 and r2.status == 0
-    _assert_parity(m, ipm, p.solution(), r2, ref2)
+    ref2 = ipm.solve(ref_t.state, ipm.o.mu0_warm)
+    assert ref2.status == 0
+    solve_pair(m, p, ipm, ref2, warm=True)
 
 
 @pytest.mark.parametrize("G,H,seed", [(8, 5, 1), (16, 10, 0)])
@@ -166,21 +128,23 @@ def test_plate_solve_matches_oracle(G, H, seed):
 
 @pytest.mark.parametrize("G,H", [(8, 3), (16, 10)])
 def test_plate_adjoint_matches_oracle(G, H):
-    """Sensitivities at the oracle's solution (placed on the GPU with
-    set_iterate): 16 x 10 takes the large-front solves.  Then the end-to-end
-    check: the GPU's sensitivities at its own cold solution against the
-    oracle's at its own (spec tolerance 1e-5)."""
+    """End to end: the GPU's sensitivities at its own cold solution (tightened
+    on its barrier problem) against the oracle's at its own (1e-5).  Then the
+    sensitivities at the oracle's point, placed on the GPU with set_iterate, at
+    1e-6: 16 x 10 takes the large-front solves."""
     _note(f"plate adjoint G={G} H={H}")
     w, m, p = _pair(G, H)
     ipm = LiftedIPM(m, _opts())
     ref = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
     assert ref.status == 0
+    ref = tighten_ref(ipm, ref)
     st = ref.state
     sens = sensitivities(ipm, st)
     rng = np.random.default_rng(4)
     su, so = rng.normal(size=16), float(rng.normal())
     r = p.solve(warm=False, options=N.default_options(tol=PARITY_TOL))
     assert r.status == 0
+    tighten_gpu(p, r.mu)
     rc, J_own = p.jacobian_u1_x0()
     assert rc == 0
     rc, g_own = p.adjoint(su, so)

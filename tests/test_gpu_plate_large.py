@@ -25,22 +25,20 @@ from oracle.kkt import kkt_error
 from oracle.plate import PlateOCP
 from paper_2606_04725_amd import nmpc as N
 from workloads import plate_workload
+from plate_parity import PARITY_TOL, certify, close, compare_tight, note, tighten_gpu, tighten_ref
 
 pytestmark = pytest.mark.gpu
 
-# E_0 tolerance that only mu_min can meet from a cold start (the barrier value
-# before it is 2.5e-9), so both sides end on the same barrier problem
-PARITY_TOL = 2e-9
+# Iteration counts of the 32 x 32 x 16 cold solve are not fixed by FP64
+# arithmetic: at mu = 1.84e-6 the filter line search spends a long stretch of
+# short steps whose accept/reject decisions are near-ties, and the oracle
+# itself takes 46 iterations from the cold start and 32, 33, 33, 33 from
+# starts perturbed by 1e-15 relative (four seeds).  The counts are only held
+# to that spread; the points are compared after tightening.
+ITERS_SLACK_32 = 16
 
-
-def _note(msg):
-    print(f"[gpu-case] {msg}", flush=True)
-    sys.stdout.flush()
-
-
-def _close(a, b, tol):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.max(np.abs(a - b))) / max(1.0, float(np.max(np.abs(b)))) <= tol
+_note = note
+_close = close
 
 
 def _problem(w, m):
@@ -52,38 +50,29 @@ def _problem(w, m):
 
 @pytest.fixture(scope="module")
 def plate32():
-    """The oracle's cold solve, sensitivities, plant step and warm re-solve of
-    the 32 x 32 x 16 plate (a few minutes of host time, computed once)."""
+    """The oracle's cold solve, its tightening on the final barrier problem,
+    sensitivities there, plant step, warm re-solve and its tightening, for the
+    32 x 32 x 16 plate (a few minutes of host time, computed once)."""
     w = plate_workload("large", 0, G=32, H=16)
     m = PlateOCP.from_workload(w)
     ipm = LiftedIPM(m, IPMOptions(tol=PARITY_TOL))
     _note("plate 32x32x16: oracle cold solve")
-    cold = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
+    log = lambda it, mu, E0: _note(f"oracle iteration {it}: mu {mu:.2e}, E0 {E0:.2e}")
+    cold = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold, progress=log)
     assert cold.status == 0
-    _note(f"oracle cold: {cold.iters} iterations; sensitivities")
-    sens = sensitivities(ipm, cold.state)
-    x1 = m.step(m.x0, m.u1(cold.state.y))
+    _note(f"oracle cold: {cold.iters} iterations; tightening")
+    cold_t = tighten_ref(ipm, cold)
+    _note("oracle sensitivities")
+    sens = sensitivities(ipm, cold_t.state)
+    x1 = m.step(m.x0, m.u1(cold_t.state.y))
     m.set_parameters(x0=x1)
     _note("oracle warm re-solve")
-    warm = ipm.solve(cold.state, ipm.o.mu0_warm)
+    warm = ipm.solve(cold_t.state, ipm.o.mu0_warm, progress=log)
     assert warm.status == 0
-    _note(f"oracle warm: {warm.iters} iterations")
+    _note(f"oracle warm: {warm.iters} iterations; tightening")
+    warm_t = tighten_ref(ipm, warm)
     m.set_parameters(x0=w.T0)
-    return dict(w=w, m=m, ipm=ipm, cold=cold, sens=sens, x1=x1, warm=warm)
-
-
-def _assert_parity(m, ipm, sol, r, ref):
-    """As the smaller plate cases: both runs end on mu_min; y, lambda, zL, zU
-    within 1e-6 per block; KKT error <= 1e-8 by the oracle's evaluator; the
-    filter's near-ties may cost either side up to two iterations."""
-    _note(f"iterations gpu {r.iters} oracle {ref.iters}")
-    assert r.mu == ipm.o.mu_min and ref.mu == ipm.o.mu_min, (r.mu, ref.mu)
-    e = kkt_error(m, sol["y"], sol["lam"], np.zeros(0), sol["zL"], sol["zU"])
-    assert e["max"] <= 1e-8, e
-    lam_ref = ref.state.omega[:m.m_c] - ref.state.omega[m.m_c:2 * m.m_c]
-    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
-    for key, want in (("y", ref.state.y), ("lam", lam_ref), ("zL", ref.state.zL), ("zU", ref.state.zU)):
-        assert _close(sol[key], want, 1e-6), key
+    return dict(w=w, m=m, ipm=ipm, cold=cold, cold_t=cold_t, sens=sens, x1=x1, warm=warm, warm_t=warm_t)
 
 
 @pytest.mark.timeout(900)
@@ -104,25 +93,30 @@ def test_plate32_cold_and_warm_match_oracle(plate32):
     r = p.solve(warm=False, options=gopts)
     assert r.status == 0
     m.set_parameters(x0=w.T0)
-    _assert_parity(m, ipm, p.solution(), r, plate32["cold"])
+    certify(m, ipm, p.solution(), r, plate32["cold"], ITERS_SLACK_32)
+    tighten_gpu(p, r.mu)
+    compare_tight(m, p.solution(), plate32["cold_t"])
     _note("gpu warm re-solve")
     p.set_parameters(plate32["x1"])
     r2 = p.solve(warm=True, options=gopts)
     assert r2.status == 0
     m.set_parameters(x0=plate32["x1"])
     try:
-        _assert_parity(m, ipm, p.solution(), r2, plate32["warm"])
+        certify(m, ipm, p.solution(), r2, plate32["warm"], ITERS_SLACK_32)
+        tighten_gpu(p, r2.mu)
+        compare_tight(m, p.solution(), plate32["warm_t"])
     finally:
         m.set_parameters(x0=w.T0)
 
 
 @pytest.mark.timeout(900)
 def test_plate32_sensitivities_match_oracle(plate32):
-    w, m, sens, st = plate32["w"], plate32["m"], plate32["sens"], plate32["cold"].state
+    w, m, sens, st = plate32["w"], plate32["m"], plate32["sens"], plate32["cold_t"].state
     p = _problem(w, m)
-    _note("plate 32x32x16: gpu cold solve, sensitivities at its own solution")
+    _note("plate 32x32x16: gpu cold solve, tightened, sensitivities at its own solution")
     r = p.solve(warm=False, options=N.default_options(tol=PARITY_TOL))
     assert r.status == 0
+    tighten_gpu(p, r.mu)
     rng = np.random.default_rng(11)
     su, so = rng.normal(size=16), float(rng.normal())
     rc, J = p.jacobian_u1_x0()
