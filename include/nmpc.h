@@ -271,6 +271,29 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
  * reuse them.  Same conditions as nmpc_adjoint. */
 nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac);
 
+/* Allocation-free variant of nmpc_jacobian_u1_x0, for callers that cannot
+ * allocate device memory while they call it (code under HIP stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  It allocates nothing
+ * (no hipMalloc, hipFree or allocating library call) on any call: the nu seeds
+ * are solved one after another, each with the same kernels and refinement as
+ * nmpc_jacobian_u1_x0, and the vectors they write live in one fixed device
+ * buffer of NMPC_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from
+ * its first use on that GPU until the process ends.
+ * jac: device pointer, nu x nx row-major, owned by the caller; stream: the
+ * caller's hipStream_t (NULL = the null stream), ordered as the *_dev entry
+ * points below.  Every call on one GPU shares that GPU's buffer and the
+ * buffer keeps the last call's contents (a call writes everything it reads
+ * there before reading it), so calls that overlap on one GPU race (two host
+ * threads, or two streams whose work can overlap): serialize them.  The first
+ * sensitivity call after a solve factors K at the solution and waits for the
+ * library's stream once.
+ * Errors: UNSUPPORTED when the problem needs more of the buffer than there is
+ * (about 8 (6 n + 2 m + update-vector entries) bytes; the 64 x 64 x 100 plate
+ * needs 91 MiB), then use nmpc_jacobian_u1_x0; otherwise as
+ * nmpc_jacobian_u1_x0. */
+#define NMPC_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+nmpc_status nmpc_jacobian_u1_x0_noalloc(nmpc_problem* p, double* jac, void* stream);
+
 /* Identity of the iterate the handle holds: *id counts the iterates it has
  * taken (each nmpc_solve that returned a status >= 0, each batch solve it was
  * part of, each nmpc_set_iterate; 0 before the first); *current (may be NULL)

@@ -84,6 +84,26 @@ nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac) {
     return rc >= 0 ? rc : fail(rc, err);
 }
 
+static_assert(nmpc::kNoAllocScratchBytes == NMPC_NOALLOC_SCRATCH_BYTES, "one size for the fixed buffer");
+
+nmpc_status nmpc_jacobian_u1_x0_noalloc(nmpc_problem* p, double* jac, void* stream) {
+    if (!p || !jac) return fail(NMPC_ERR_INVALID_ARG, "jacobian_u1_x0_noalloc: NULL argument");
+    if (!p->impl.analyzed) return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0_noalloc: call nmpc_analyze first");
+    const size_t need = nmpc::noalloc_scratch_bytes(p->impl);
+    if (need > nmpc::kNoAllocScratchBytes)
+        return fail(NMPC_ERR_UNSUPPORTED, "jacobian_u1_x0_noalloc: the problem needs " + std::to_string(need) +
+                                              " bytes of scratch, more than the fixed " +
+                                              std::to_string(nmpc::kNoAllocScratchBytes) +
+                                              "; use nmpc_jacobian_u1_x0");
+    if (!p->impl.dev) return fail(NMPC_ERR_NO_DEVICE, "jacobian_u1_x0_noalloc: no HIP device");
+    if (!p->impl.have_iterate) return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0_noalloc: no solution yet");
+    if (!p->impl.params_current)
+        return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0_noalloc: parameters changed since the last solve");
+    std::string err;
+    nmpc_status rc = nmpc::device_jacobian_u1_x0_noalloc(p->impl, jac, stream, err);
+    return rc >= 0 ? rc : fail(rc, err);
+}
+
 nmpc_status nmpc_set_parameters_dev(nmpc_problem* p, const double* x0, const double* setpoint, const double* traj,
                                     const double* u_prev, void* stream) {
     if (!p || !x0) return fail(NMPC_ERR_INVALID_ARG, "set_parameters_dev: NULL handle or x0");

@@ -83,6 +83,8 @@ struct Device {
     std::vector<Device*> seed_devs;
     double* seed_vals = nullptr;   // nu x (nu + 1) seeds
     double* seed_lam = nullptr;    // nu x m multipliers; row k's first nx entries are d u1_k / d x0
+    // this GPU's fixed buffer of the allocation-free Jacobian (resolved at set-up)
+    unsigned char* scratch = nullptr;
 };
 
 // Emitted kernel launch of a batch schedule: a group launch (groups[off ..
@@ -449,6 +451,37 @@ hipError_t ensure_graph(Batch& B, const DevOpts& o, bool timed, int part) {
 
 }  // namespace
 
+// ---- fixed device buffer of the allocation-free Jacobian ---------------------------
+// One seed's sensitivity vectors and the instance descriptor that points at
+// them.  Each GPU holds its own copy from the library's first use on it until
+// the process ends.  Host code uses the address hipGetSymbolAddress returns for
+// the current device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::vector<unsigned char*> g_scratch_ptr;   // per device ordinal, resolved once
+
+// Device address of the current device's copy of the buffer.
+hipError_t scratch_address(unsigned char*& out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 // ==================================================================================
 bool device_present() {
     int cnt = 0;
@@ -491,6 +524,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
         }                                                                              \
     } while (0)
     DTRY(hipStreamCreateWithFlags(&D.stream, hipStreamNonBlocking));
+    DTRY(scratch_address(D.scratch));
     DTRY(hipEventCreateWithFlags(&D.ev_in, hipEventDisableTiming));
     DTRY(hipEventCreateWithFlags(&D.ev_out, hipEventDisableTiming));
     InstPtrs& I = D.hI;
@@ -1520,6 +1554,123 @@ nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err) {
     HIP_TRY(hipMemcpy2DAsync(jac, st.nx * sizeof(double), D.seed_lam, (size_t)D.hI.m * sizeof(double),
                              st.nx * sizeof(double), K, hipMemcpyDeviceToHost, D.stream));
     HIP_TRY(hipStreamSynchronize(D.stream));
+    return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
+}
+
+// ---- the Jacobian without allocation ------------------------------------------------
+namespace {
+
+// Offsets (bytes, 256-aligned) of one seed's vectors in the fixed buffer: the
+// instance descriptor, then the vectors a sensitivity solve writes.
+struct NoAllocLayout {
+    size_t desc, xp, bsum, uvec, rhs, w, b, d, lam, qr, out, seed, total;
+};
+
+NoAllocLayout noalloc_layout(const Problem& p) {
+    const Structure& st = p.st;
+    const size_t n = (size_t)st.n, m = (size_t)(st.m_c + st.m_d);
+    const size_t nsp = st.desc.family == NMPC_FAMILY_HEATED_PLATE ? (size_t)st.nx : 2;
+    const size_t ntr = st.desc.family == NMPC_FAMILY_HEATED_PLATE ? 0 : (size_t)st.H;
+    const size_t nout = (size_t)st.nx + nsp + ntr + (size_t)st.nu;
+    const size_t nuv = std::max<size_t>((size_t)p.sym.stored_uv, 1);
+    NoAllocLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.desc = take(sizeof(InstPtrs));
+    L.xp = take(n * sizeof(double));
+    L.bsum = take(n * sizeof(double));
+    L.uvec = take(nuv * sizeof(double));
+    L.rhs = take(n * sizeof(double));
+    L.w = take(n * sizeof(double));
+    L.b = take(n * sizeof(double));
+    L.d = take(n * sizeof(double));
+    L.lam = take(m * sizeof(double));
+    L.qr = take(m * sizeof(double));
+    L.out = take(nout * sizeof(double));
+    L.seed = take(((size_t)st.nu + 1) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+// Places the scratch instance's descriptor and the seed e_k (objective seed 0).
+__global__ void k_noalloc_seed(InstPtrs J, InstPtrs* dst, int k) {
+    if (threadIdx.x == 0) *dst = J;
+    for (int i = threadIdx.x; i <= J.nu; i += blockDim.x) J.adj_seed[i] = i == k ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+size_t noalloc_scratch_bytes(const Problem& p) { return noalloc_layout(p).total; }
+
+// Row k of d u1 / d x0 as in device_jacobian_u1_x0 (seed e_k, the same kernels
+// and refinement), one seed after another through the problem's own launch
+// schedule, with the vectors the solves write in this GPU's fixed buffer.
+nmpc_status device_jacobian_u1_x0_noalloc(Problem& p, double* jac, void* caller_stream, std::string& err) {
+    const Structure& st = p.st;
+    if (st.nu > kMaxSeed) {
+        err = "adjoint: too many controls per stage";
+        return NMPC_ERR_UNSUPPORTED;
+    }
+    const NoAllocLayout Lo = noalloc_layout(p);
+    if (Lo.total > kNoAllocScratchBytes) {
+        err = "jacobian_u1_x0_noalloc: the problem needs " + std::to_string(Lo.total) +
+              " bytes of scratch, more than the fixed " + std::to_string(kNoAllocScratchBytes);
+        return NMPC_ERR_UNSUPPORTED;
+    }
+    nmpc_status rc = adjoint_prepare(p, err);   // once per solution; may wait for the library's stream
+    if (rc != NMPC_OK) return rc;
+    Device& D = *p.dev;
+    Batch& B = *D.self;
+    if (!D.scratch) {
+        err = "jacobian_u1_x0_noalloc: fixed buffer not resolved";
+        return NMPC_ERR_HIP;
+    }
+    const hipStream_t caller = static_cast<hipStream_t>(caller_stream);
+    unsigned char* base = D.scratch;
+    auto at = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+    // the host copy of the descriptor has no control block (each batch places
+    // its own); the kernels read the phase from it, so take the problem's
+    InstPtrs J = D.hI;
+    J.ctl = B.ctl;
+    if (!J.ctl || B.ninst != 1) {
+        err = "jacobian_u1_x0_noalloc: the problem's own schedule is not set up";
+        return NMPC_ERR_HIP;
+    }
+    J.xp = at(Lo.xp);
+    J.bsum = at(Lo.bsum);
+    J.uvec = at(Lo.uvec);
+    J.adj_rhs = at(Lo.rhs);
+    J.adj_w = at(Lo.w);
+    J.adj_b = at(Lo.b);
+    J.adj_d = at(Lo.d);
+    J.adj_lam = at(Lo.lam);
+    J.adj_qr = at(Lo.qr);
+    J.adj_out = at(Lo.out);
+    J.adj_seed = at(Lo.seed);
+    InstPtrs* dJ = reinterpret_cast<InstPtrs*>(base + Lo.desc);
+    HIP_TRY(join_in(D, caller));
+    InstPtrs* const own = B.dI;
+    for (int k = 0; k < st.nu; ++k) {
+        hipLaunchKernelGGL(k_noalloc_seed, dim3(1), dim3(64), 0, B.stream, J, dJ, k);
+        B.dI = dJ;   // the problem's launch schedule over the scratch instance
+        launch_adj_seed(B.dI, B.spaces.sp[kSpN], B.stream);
+        solve_launches(B, kPredAll, 2);
+        launch_adj_refine(0, B.dI, B.spaces, D.adj_eta, B.stream);
+        for (int r = 0; r < kAdjRefine; ++r) {
+            launch_adj_refine(1, B.dI, B.spaces, D.adj_eta, B.stream);
+            solve_launches(B, kPredAll, 3);
+            launch_adj_refine(2, B.dI, B.spaces, D.adj_eta, B.stream);
+        }
+        B.dI = own;
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(jac + (size_t)k * st.nx, J.adj_lam, st.nx * sizeof(double), hipMemcpyDeviceToDevice,
+                               B.stream));
+    }
+    HIP_TRY(join_out(D, caller));
     return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
 

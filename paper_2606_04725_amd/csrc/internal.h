@@ -110,6 +110,12 @@ nmpc_status device_assemble(Problem& p, double mu, double* kv, double* rhs, std:
 nmpc_status device_adjoint(Problem& p, const double* seed_u1, double seed_obj, double* gx0, double* gsp,
                            double* gtraj, double* gup, std::string& err);
 nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err);
+// Allocation-free Jacobian: its vectors live in a fixed per-GPU device buffer
+// of kNoAllocScratchBytes; noalloc_scratch_bytes is what a problem needs there
+// (host arithmetic on the structure and the symbolic analysis).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+size_t noalloc_scratch_bytes(const Problem& p);
+nmpc_status device_jacobian_u1_x0_noalloc(Problem& p, double* jac, void* caller, std::string& err);
 void device_invalidate_adjoint(Problem& p);
 nmpc_status device_autotune(Problem& p, int reps, int* changed, std::string& err);
 nmpc_status batch_create(const std::vector<Problem*>& ps, Batch*& out, std::string& err);

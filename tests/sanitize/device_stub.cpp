@@ -41,6 +41,8 @@ nmpc_status device_adjoint(Problem&, const double*, double, double*, double*, do
     return none(err);
 }
 nmpc_status device_jacobian_u1_x0(Problem&, double*, std::string& err) { return none(err); }
+size_t noalloc_scratch_bytes(const Problem&) { return 0; }
+nmpc_status device_jacobian_u1_x0_noalloc(Problem&, double*, void*, std::string& err) { return none(err); }
 nmpc_status device_autotune(Problem&, int, int*, std::string& err) { return none(err); }
 nmpc_status batch_create(const std::vector<Problem*>&, Batch*&, std::string& err) { return none(err); }
 void batch_free(Batch*) {}
