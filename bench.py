@@ -69,11 +69,46 @@ def cpu_baseline(seed: int, budget_s: float):
     from oracle.distillation import DistillationOCP
     from oracle.ipm import LiftedIPM
     from workloads import distillation_workload
+    import contextlib
+    # BLAS threads: the host's cores, bounded by the thread budget the
+    # environment gives this process (OMP_NUM_THREADS), set with threadpoolctl
+    want = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
+        limiter = threadpool_limits(limits=want)
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        blas = sorted({f"{i.get('internal_api')} {i.get('version')}" for i in threadpool_info()})
     except Exception:
-        threads = 1
+        limiter, threads, blas = contextlib.nullcontext(), 1, []
+    with limiter:
+        return _cpu_baseline(seed, budget_s, threads, blas)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _numpy_blas():
+    """numpy's build configuration, BLAS/LAPACK entries only."""
+    try:
+        cfg = np.show_config(mode="dicts")
+        deps = cfg.get("Build Dependencies", {})
+        return {k: {kk: vv for kk, vv in v.items() if kk in ("name", "version", "found")}
+                for k, v in deps.items() if k in ("blas", "lapack")}
+    except Exception:
+        return None
+
+
+def _cpu_baseline(seed, budget_s, threads, blas):
+    from oracle.distillation import DistillationOCP
+    from oracle.ipm import LiftedIPM
+    from workloads import distillation_workload
     w = distillation_workload("medium", seed)
     m = DistillationOCP.from_workload(w)
     ipm = LiftedIPM(m)
@@ -94,10 +129,129 @@ def cpu_baseline(seed: int, budget_s: float):
         r += 1
     tot = sum(times)
     return {"value": iters / tot if tot > 0 else None, "unit": "IPM iters/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "blas_threadpools": blas, "numpy_blas": _numpy_blas(),
             "sample": f"medium distillation seed {seed}: {len(times)} warm re-solves after one cold solve "
                       f"({iters} IPM iterations, {tot:.1f} s)",
             "p50_resolve_ms": _percentile([t * 1e3 for t in times], 50)}
+
+
+def run_ablation(N, make, params, resolves, label):
+    """The paper's structure-reuse ablation on one workload: the same closed
+    loop of re-solves run four ways, symbolic analysis once (the method) or
+    before every solve (a new handle analyzed each time, the warm start carried
+    over with the iterate), and warm or cold starts.  Times are host wall time
+    per re-solve, analysis and device set-up included where they run."""
+    out = {"workload": label, "resolves": resolves}
+    for every in (False, True):
+        for warm in (True, False):
+            p = make()
+            p.analyze()
+            params(p, -1, None, None)
+            r = p.solve(warm=False)
+            u1, x1 = p.first_stage()
+            lat, an, iters, bad = [], [], 0, 0
+            for k in range(resolves):
+                t = time.perf_counter()
+                if every:
+                    it = p.get_iterate() if warm else None
+                    p.close()
+                    p = make()
+                    ta = time.perf_counter()
+                    p.analyze()
+                    an.append((time.perf_counter() - ta) * 1e3)
+                    params(p, k, u1, x1)
+                    if warm:
+                        p.set_iterate(it["y"], it["s"], it["omega"], it["beta"], it["zL"], it["zU"])
+                else:
+                    params(p, k, u1, x1)
+                r = p.solve(warm=warm)
+                u1, x1 = p.first_stage()
+                lat.append((time.perf_counter() - t) * 1e3)
+                iters += r.iters
+                bad += r.status != 0
+            p.close()
+            key = ("analyze_every_solve" if every else "analyze_once") + ("_warm" if warm else "_cold")
+            out[key] = {"p50_resolve_ms": _percentile(lat, 50), "mean_resolve_ms": float(np.mean(lat)),
+                        "iters_per_resolve": iters / resolves, "nonzero_status": bad}
+            if every:
+                out[key]["mean_analyze_ms"] = float(np.mean(an))
+    base = out["analyze_once_warm"]["mean_resolve_ms"]
+    out["slowdown_vs_analyze_once_warm"] = {k: v["mean_resolve_ms"] / base for k, v in out.items()
+                                            if isinstance(v, dict) and "mean_resolve_ms" in v}
+    _progress(f"ablation: {label}")
+    return out
+
+
+def ablations(N):
+    from workloads import distillation_workload, plate_workload
+
+    def column(kind, resolves):
+        w = distillation_workload(kind, 0, n_resolves=resolves + 1)
+        sp = [w.xD_sp, w.xB_sp]
+
+        def make():
+            return N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+
+        def params(p, k, u1, x1):
+            if k < 0:
+                p.set_parameters(w.x0, setpoint=sp, traj=w.zF(0), u_prev=w.u_prev0)
+            else:
+                p.set_parameters(w.next_measurement(x1, k), setpoint=sp, traj=w.zF(k + 1), u_prev=u1)
+        return make, params, f"distillation {w.N} trays, horizon {w.H}, seed 0"
+
+    def plate(resolves):
+        w = plate_workload("large", 0)
+
+        def make():
+            return N.Problem(N.plate_structure(w.G, w.H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi))
+
+        def params(p, k, u1, x1):
+            if k < 0:
+                p.set_parameters(w.T0, setpoint=w.target, u_prev=np.full(16, 0.5 * (w.u_lo + w.u_hi)))
+            else:
+                p.set_parameters(x1, setpoint=w.target, u_prev=u1)
+        return make, params, f"heated plate {w.G}x{w.G}, horizon {w.H}, seed 0"
+
+    out = {}
+    for name, (mk, pr, lab), R in (("small", column("small", 5), 5), ("medium", column("medium", 10), 10),
+                                     ("plate", plate(3), 3)):
+        out[name] = run_ablation(N, mk, pr, R, lab)
+    return out
+
+
+def trisolve_rate(p, nnz_l, reps=20):
+    """Forward and back substitution with the held factor through
+    nmpc_linear_solve: host wall time per call (the right-hand side and the
+    solution cross PCIe, 16 n bytes) and 16 nnz(L) bytes (L read once forward,
+    once backward) over it."""
+    rng = np.random.default_rng(0)
+    b = rng.normal(size=p.n)
+    p.linear_solve(b)
+    t = time.perf_counter()
+    for _ in range(reps):
+        p.linear_solve(b)
+    dt = (time.perf_counter() - t) / reps
+    return {"ms_per_solve": dt * 1e3, "gbps": 16.0 * nnz_l / dt / 1e9, "bytes_per_solve": 16.0 * nnz_l,
+            "note": "host wall time incl. the 16 n bytes of right-hand side and solution over PCIe"}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes (read + write counted), HIP events."""
+    import torch
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes": 2 * n * 8, "ms": ms, "gbps": 2 * n * 8 / (ms * 1e-3) / 1e9}
 
 
 def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
@@ -237,27 +391,48 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
     t_cold = time.perf_counter() - t0
     _progress(f"plate {G}x{G}x{H}: cold solve status {r0.status}, {r0.iters} iterations")
     u1, x1 = p.first_stage()
-    lat, lat_adj, lat_vjp, iters, facts, ms_fact, statuses = [], [], [], 0, 0, 0.0, []
+    lat, lat_adj, lat_adj2, lat_vjp, iters, facts, ms_fact, statuses = [], [], [], [], 0, 0, 0.0, []
     phase = dict(eval=0.0, assemble=0.0, factor=0.0, solve=0.0, linesearch=0.0)
+    if adjoint:
+        import torch
+        from paper_2606_04725_amd.autograd import NMPCSolve
+        cuda = torch.device("cuda:0")
+        sp_t = torch.tensor(w.target, dtype=torch.float64, device=cuda, requires_grad=True)
     for k in range(resolves):
-        t = time.perf_counter()
-        p.set_parameters(x1, u_prev=u1)
-        r = p.solve(warm=True, options=opts)
-        u1, x1 = p.first_stage()
-        lat.append((time.perf_counter() - t) * 1e3)
+        if adjoint:
+            # the differentiated form: forward through the autograd function on
+            # device tensors, d f*/d setpoint by its backward (one adjoint
+            # solve), d u1*/d x0 by the 16-seed Jacobian of the same solution
+            x0_t = torch.tensor(x1, dtype=torch.float64, device=cuda, requires_grad=True)
+            up_t = torch.tensor(u1, dtype=torch.float64, device=cuda)
+            t = time.perf_counter()
+            u1_t, f_t = NMPCSolve.apply(p, x0_t, sp_t, None, up_t, True, opts)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t) * 1e3)
+            r = p.last_result
+            u1, x1 = p.first_stage()
+            t = time.perf_counter()
+            rc, J = p.jacobian_u1_x0()              # factors K at the solution, then 16 seeds
+            lat_adj.append((time.perf_counter() - t) * 1e3)
+            t = time.perf_counter()
+            rc, J2 = p.jacobian_u1_x0()             # the kept factor: solves only
+            lat_adj2.append((time.perf_counter() - t) * 1e3)
+            t = time.perf_counter()
+            (g_sp,) = torch.autograd.grad(f_t, sp_t)
+            torch.cuda.synchronize()
+            lat_vjp.append((time.perf_counter() - t) * 1e3)
+        else:
+            t = time.perf_counter()
+            p.set_parameters(x1, u_prev=u1)
+            r = p.solve(warm=True, options=opts)
+            u1, x1 = p.first_stage()
+            lat.append((time.perf_counter() - t) * 1e3)
         iters += r.iters
         facts += r.factorizations
         ms_fact += r.ms_factor
         statuses.append(r.status)
         for key in phase:
             phase[key] += getattr(r, "ms_" + key)
-        if adjoint:
-            t = time.perf_counter()
-            rc, J = p.jacobian_u1_x0()
-            lat_adj.append((time.perf_counter() - t) * 1e3)
-            t = time.perf_counter()
-            rc2, g = p.adjoint(np.zeros(16), 1.0)
-            lat_vjp.append((time.perf_counter() - t) * 1e3)
         _progress(f"plate {G}x{G}x{H}: re-solve {k + 1}/{resolves} status {r.status}")
     tot = sum(lat) / 1e3
     flops = float(sym["flops"])
@@ -276,9 +451,21 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
                         "kernel": "numeric supernodal factorization (all launches of one factorization)",
                         "flops_per_unit": flops}}
     if adjoint:
+        nnz_j = p.pattern_counts()[0]
+        adj_bytes = 2 * 8.0 * sym["nnz_l"] + 8.0 * 16 * (p.n + nnz_j)
+        solves_ms = _percentile(lat_adj2, 50)
         out["adjoint"] = {"p50_jacobian_u1_x0_ms": _percentile(lat_adj, 50),
+                          "p50_jacobian_u1_x0_kept_factor_ms": solves_ms,
                           "p50_objective_setpoint_gradient_ms": _percentile(lat_vjp, 50),
-                          "jacobian_shape": [16, G * G]}
+                          "jacobian_shape": [16, G * G],
+                          "jacobian_gbps": adj_bytes / (solves_ms * 1e-3) / 1e9,
+                          "jacobian_bytes": adj_bytes,
+                          "note": "forward through NMPCSolve on device tensors; d f/d setpoint by its backward; "
+                                  "the first Jacobian call after a solve factors K at the solution (the "
+                                  "interior-point method's last factor is one iterate earlier), the second "
+                                  "reuses that factor; GB/s = (2*8*nnz L + 8*16*(n + nnz J)) / kept-factor time"}
+    else:
+        out["trisolve"] = trisolve_rate(p, sym["nnz_l"])
     return out
 
 
@@ -295,6 +482,9 @@ def main(argv=None):
     ap.add_argument("--no-small", action="store_true", help="skip the small-column leg (10 trays, horizon 20)")
     ap.add_argument("--batch-only", action="store_true", help="only run the 64-instance batched form")
     ap.add_argument("--no-plate", action="store_true", help="skip the heated-plate workloads")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the analyze-once/every-solve and warm/cold ablation")
+    ap.add_argument("--ablation-only", action="store_true", help="only run the ablation")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
     ap.add_argument("--plate-case", choices=("plain", "adjoint", "both"), default="both",
                     help="with --plate-only: the 32x32x50 plate, the differentiated plate, or both")
@@ -323,6 +513,9 @@ def main(argv=None):
     if not torch.cuda.is_available() or not N.device_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if a.ablation_only:
+        print(json.dumps({"ablation": ablations(N)}), flush=True)
+        return 0
     if a.batch_only:
         print(json.dumps({"batched": run_batched(N, eager=a.eager)}), flush=True)
         return 0
@@ -420,6 +613,8 @@ def main(argv=None):
                      "kernel": "numeric supernodal factorization (all levels of one factorization)",
                      "bytes_per_unit": bytes_per_factor},
     }
+    out["trisolve"] = trisolve_rate(p, sym["nnz_l"])
+    out["measured_copy"] = copy_bandwidth()
     if not a.no_small:
         out["small"] = run_small(N, eager=a.eager)
     if not a.no_batch:
@@ -427,6 +622,8 @@ def main(argv=None):
     if not a.no_plate:
         out["plate"] = run_plate(N, eager=a.eager)
         out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
+    if not a.no_ablation:
+        out["ablation"] = ablations(N)
     if not a.no_cpu_baseline:
         _progress("cpu baseline (oracle) starts")
         out["cpu_baseline"] = cpu_baseline(a.seed, a.cpu_budget)

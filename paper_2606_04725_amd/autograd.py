@@ -31,10 +31,10 @@ def _ptr(t):
 
 
 class NMPCSolve(torch.autograd.Function):
-    """u1, f = NMPCSolve.apply(problem, x0, setpoint, traj, u_prev, warm)."""
+    """u1, f = NMPCSolve.apply(problem, x0, setpoint, traj, u_prev, warm[, options])."""
 
     @staticmethod
-    def forward(ctx, problem: N.Problem, x0, setpoint, traj, u_prev, warm: bool):
+    def forward(ctx, problem: N.Problem, x0, setpoint, traj, u_prev, warm: bool, options=None):
         cuda = x0.is_cuda
         dev = x0.device
         if cuda:
@@ -43,7 +43,7 @@ class NMPCSolve(torch.autograd.Function):
             problem.set_parameters_dev(*(_ptr(t) for t in xs), stream=stream)
         else:
             problem.set_parameters(_host(x0), setpoint=_host(setpoint), traj=_host(traj), u_prev=_host(u_prev))
-        res = problem.solve(warm=bool(warm))
+        res = problem.solve(warm=bool(warm), options=options)
         if res.status != 0:
             raise N.NMPCError(res.status, f"solve ended with status {res.status}")
         if cuda:
@@ -85,4 +85,4 @@ class NMPCSolve(torch.autograd.Function):
             _, gh = p.adjoint(seed, gobj)
             g = {k: torch.as_tensor(v, dtype=torch.float64, device=dev) for k, v in gh.items()}
         return (None, g["x0"], g["setpoint"] if has_sp else None, g["traj"] if has_tr else None,
-                g["u_prev"] if has_up else None, None)
+                g["u_prev"] if has_up else None, None, None)

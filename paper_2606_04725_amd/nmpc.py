@@ -90,6 +90,7 @@ class Problem:
         self.nnz_k = nk.value
         self.ml = 2 * self.m_c + self.m_d
         self.analyzed = False
+        self.last_result = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -148,6 +149,7 @@ class Problem:
         rc = capi.lib().nmpc_solve(self._h, 1 if warm else 0, None if options is None else C.byref(options),
                                    C.byref(r))
         _check(rc)
+        self.last_result = r
         return r
 
     def first_stage(self):
