@@ -57,6 +57,18 @@ enum { NMPC_FAMILY_DISTILLATION = 1, NMPC_FAMILY_HEATED_PLATE = 2 };
  * degree of the condensed matrix's elimination graph. */
 enum { NMPC_ORDER_NESTED_DISSECTION = 0, NMPC_ORDER_MIN_DEGREE = 1 };
 
+/* How the Newton system of Section 3.2 is made solvable by Cholesky (the two
+ * reformulations the section names).  LIFTED: Lifted-KKT, the equalities
+ * relaxed to |c| <= gamma and lifted into inequalities (eq. 16); the condensed
+ * matrix of eq. (17) is factored once per attempt.  HYKKT: the equalities kept
+ * exact; the condensed system of eq. (14) with its equality block is solved by
+ * the Cholesky factor of K_c + hykkt_gamma J_c^T J_c (same sparsity pattern
+ * and symbolic analysis) and conjugate gradients on the Schur complement
+ * J_c (K_c + hykkt_gamma J_c^T J_c)^{-1} J_c^T, one forward/back solve per CG
+ * iteration.  The iterate converges to the original problem's KKT point
+ * (no O(gamma) relaxation). */
+enum { NMPC_KKT_LIFTED = 0, NMPC_KKT_HYKKT = 1 };
+
 /* Problem structure: everything that fixes the sparsity pattern of the
  * transcribed OCP (eq. 6) and its constant data.  Parameters that change
  * between re-solves (x0, setpoints, disturbance trajectories, last control) go
@@ -122,6 +134,17 @@ typedef struct nmpc_options {
                             barrier problem: mu stays at its initial value (mu0_warm / mu0_cold), and
                             the solve ends when E_mu <= tol (eq. 27's inner test with tol in place
                             of kappa_eps mu), e.g. to re-solve a barrier solution tightly */
+    /* NMPC_KKT_* (default LIFTED).  HYKKT runs nmpc_solve only (not batches),
+     * launches its kernels from the host (graph ignored: the conjugate
+     * gradients take one host round trip per iteration) and uses no
+     * second-order corrections (soc_max ignored).  A warm HYKKT solve starts
+     * from a held Lifted-KKT iterate too (lambda = omega+ - omega-); a warm
+     * LIFTED solve from a HyKKT iterate is refused (BAD_ORDER), as are the
+     * sensitivities of a HyKKT solution. */
+    int32_t kkt;
+    double hykkt_gamma;  /* weight of J_c^T J_c in the HyKKT matrix (default 1e6) */
+    double hykkt_cg_tol; /* CG ends at |r|_2 <= hykkt_cg_tol |r_0|_2 (default 1e-12) */
+    int32_t hykkt_cg_max;/* CG iterations per solve (default 200) */
 } nmpc_options;
 
 typedef struct nmpc_result {
@@ -136,6 +159,7 @@ typedef struct nmpc_result {
     int32_t passes;      /* passes enqueued: one per Newton iteration, plus one per extra
                             factorization attempt or trial point (of the slowest instance of a batch) */
     int32_t timing_lost; /* passes whose phase times could not be read (then left out of ms_*) */
+    int32_t cg_iters;    /* HyKKT: conjugate-gradient iterations over the solve (0 for LIFTED) */
 } nmpc_result;
 
 typedef struct nmpc_problem nmpc_problem;

@@ -243,9 +243,13 @@ class LiftedIPM:
             phi -= mu * np.sum(np.log(gU[self.hasU]))
         return float(phi)
 
+    def constraint_residual(self, y, s):
+        """g^l(y) + s (r_4 of eq. 11 at y, s)."""
+        return self.g_lifted(self.nlp.cons_c(y), self.nlp.cons_d(y)) + s
+
     def violation(self, y, s):
         """theta = |g^l(y) + s|_1."""
-        return float(np.sum(np.abs(self.g_lifted(self.nlp.cons_c(y), self.nlp.cons_d(y)) + s)))
+        return float(np.sum(np.abs(self.constraint_residual(y, s))))
 
     # ---- main loop ----------------------------------------------------
     def solve(self, start: IPMState, mu0: float, record=False, fixed_mu=False, tol=None, progress=None):
@@ -369,7 +373,7 @@ class LiftedIPM:
                     accepted = True
                     break
                 if trials == 1 and np.isfinite(tht) and tht >= theta and o.soc_max > 0:
-                    r4s = alpha * r4 + (self.g_lifted(nlp.cons_c(yt), nlp.cons_d(yt)) + stt)
+                    r4s = alpha * r4 + self.constraint_residual(yt, stt)
                     th_old = theta
                     for _p in range(o.soc_max):
                         d = self.soc_direction(r4s)
@@ -393,7 +397,7 @@ class LiftedIPM:
                             break
                         if not np.isfinite(ths) or ths > o.soc_kappa * th_old:
                             break
-                        r4s = a_s * r4s + (self.g_lifted(nlp.cons_c(ys), nlp.cons_d(ys)) + ss)
+                        r4s = a_s * r4s + self.constraint_residual(ys, ss)
                         th_old = ths
                     if accepted:
                         break

@@ -17,6 +17,7 @@ NMPC_ERR_INVALID_ARG, NMPC_ERR_BAD_ORDER, NMPC_ERR_STRUCT_MISMATCH = -1, -2, -3
 NMPC_ERR_NO_DEVICE, NMPC_ERR_HIP, NMPC_ERR_OOM, NMPC_ERR_UNSUPPORTED = -4, -5, -6, -7
 NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE = 1, 2
 NMPC_ORDER_NESTED_DISSECTION, NMPC_ORDER_MIN_DEGREE = 0, 1
+NMPC_KKT_LIFTED, NMPC_KKT_HYKKT = 0, 1
 
 
 class nmpc_structure(C.Structure):
@@ -41,7 +42,8 @@ class nmpc_options(C.Structure):
                 ("alpha_min_frac", C.c_double), ("theta_max_fact", C.c_double), ("theta_min_fact", C.c_double),
                 ("filter_cap", C.c_int32), ("soc_max", C.c_int32), ("soc_kappa", C.c_double),
                 ("merit_fallback", C.c_int32), ("timing", C.c_int32), ("graph", C.c_int32),
-                ("fixed_mu", C.c_int32)]
+                ("fixed_mu", C.c_int32), ("kkt", C.c_int32), ("hykkt_gamma", C.c_double),
+                ("hykkt_cg_tol", C.c_double), ("hykkt_cg_max", C.c_int32)]
 
 
 class nmpc_result(C.Structure):
@@ -50,7 +52,7 @@ class nmpc_result(C.Structure):
                 ("objective", C.c_double), ("ms_total", C.c_double), ("ms_eval", C.c_double),
                 ("ms_assemble", C.c_double), ("ms_factor", C.c_double), ("ms_solve", C.c_double),
                 ("ms_linesearch", C.c_double), ("factor_launches", C.c_int32), ("passes", C.c_int32),
-                ("timing_lost", C.c_int32)]
+                ("timing_lost", C.c_int32), ("cg_iters", C.c_int32)]
 
 
 _P = C.c_void_p

@@ -42,7 +42,9 @@ bool resolve_options(const nmpc_options* opts, nmpc_options& o) {
            o.mu0_warm > 0 && o.eta_first > 0 && o.kp_first > 1 && o.kp > 1 && o.eta_max > 0 && o.filter_cap >= 1 &&
            o.filter_cap <= nmpc::kFilterCapacity && o.alpha_min_frac > 0 &&
            o.soc_max >= 0 && o.soc_kappa > 0 &&
-           (o.merit_fallback == 0 || o.merit_fallback == 1) && (o.fixed_mu == 0 || o.fixed_mu == 1);
+           (o.merit_fallback == 0 || o.merit_fallback == 1) && (o.fixed_mu == 0 || o.fixed_mu == 1) &&
+           (o.kkt == NMPC_KKT_LIFTED || o.kkt == NMPC_KKT_HYKKT) && o.hykkt_gamma > 0 && o.hykkt_cg_tol > 0 &&
+           o.hykkt_cg_max >= 1;
 }
 
 template <class F>
@@ -66,6 +68,7 @@ nmpc_status nmpc_adjoint(nmpc_problem* p, const double* seed_u1, double seed_obj
     if (!p || !seed_u1) return fail(NMPC_ERR_INVALID_ARG, "adjoint: NULL handle or seed");
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "adjoint: no solution yet");
     if (!p->impl.params_current) return fail(NMPC_ERR_BAD_ORDER, "adjoint: parameters changed since the last solve");
+    if (p->impl.iter_hyk) return fail(NMPC_ERR_BAD_ORDER, "adjoint: the sensitivities need a Lifted-KKT solution");
     if (!std::isfinite(seed_obj) || !all_finite(seed_u1, p->impl.st.nu))
         return fail(NMPC_ERR_INVALID_ARG, "adjoint: non-finite seed");
     std::string err;
@@ -79,6 +82,8 @@ nmpc_status nmpc_jacobian_u1_x0(nmpc_problem* p, double* jac) {
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0: no solution yet");
     if (!p->impl.params_current)
         return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0: parameters changed since the last solve");
+    if (p->impl.iter_hyk)
+        return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0: the sensitivities need a Lifted-KKT solution");
     std::string err;
     nmpc_status rc = nmpc::device_jacobian_u1_x0(p->impl, jac, err);
     return rc >= 0 ? rc : fail(rc, err);
@@ -99,6 +104,8 @@ nmpc_status nmpc_jacobian_u1_x0_noalloc(nmpc_problem* p, double* jac, void* stre
     if (!p->impl.have_iterate) return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0_noalloc: no solution yet");
     if (!p->impl.params_current)
         return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0_noalloc: parameters changed since the last solve");
+    if (p->impl.iter_hyk)
+        return fail(NMPC_ERR_BAD_ORDER, "jacobian_u1_x0_noalloc: the sensitivities need a Lifted-KKT solution");
     std::string err;
     nmpc_status rc = nmpc::device_jacobian_u1_x0_noalloc(p->impl, jac, stream, err);
     return rc >= 0 ? rc : fail(rc, err);
@@ -129,6 +136,7 @@ nmpc_status nmpc_adjoint_dev(nmpc_problem* p, const double* seed_u1, const doubl
     if (!p) return fail(NMPC_ERR_INVALID_ARG, "adjoint_dev: NULL handle");
     if (!p->impl.have_iterate || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "adjoint_dev: no solution yet");
     if (!p->impl.params_current) return fail(NMPC_ERR_BAD_ORDER, "adjoint_dev: parameters changed since the last solve");
+    if (p->impl.iter_hyk) return fail(NMPC_ERR_BAD_ORDER, "adjoint_dev: the sensitivities need a Lifted-KKT solution");
     std::string err;
     nmpc_status rc = nmpc::device_adjoint_dev(p->impl, seed_u1, seed_obj, grad_x0, grad_setpoint, grad_traj,
                                               grad_uprev, stream, err);
@@ -196,6 +204,10 @@ void nmpc_default_options(nmpc_options* o) {
     o->timing = 0;
     o->graph = 1;
     o->fixed_mu = 0;
+    o->kkt = NMPC_KKT_LIFTED;
+    o->hykkt_gamma = 1e6;
+    o->hykkt_cg_tol = 1e-12;
+    o->hykkt_cg_max = 200;
 }
 
 nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
@@ -345,6 +357,8 @@ nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, 
     if (warm && !p->impl.have_iterate) return fail(NMPC_ERR_BAD_ORDER, "solve: warm start without a previous iterate");
     nmpc_options o;
     if (!resolve_options(opts, o)) return fail(NMPC_ERR_INVALID_ARG, "solve: invalid options");
+    if (warm && o.kkt == NMPC_KKT_LIFTED && p->impl.iter_hyk)
+        return fail(NMPC_ERR_BAD_ORDER, "solve: a warm Lifted-KKT start needs a Lifted-KKT iterate (solve cold)");
     return guarded([&]() -> nmpc_status {
         nmpc_result r{};
         std::string err;
@@ -355,6 +369,7 @@ nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, 
         if (rc < 0) return fail(rc, err);
         p->impl.have_iterate = true;
         p->impl.params_current = true;
+        p->impl.iter_hyk = o.kkt == NMPC_KKT_HYKKT;
         ++p->impl.solution_id;
         if (res) *res = r;
         return rc;
@@ -421,6 +436,7 @@ nmpc_status nmpc_set_iterate(nmpc_problem* p, const double* y, const double* s, 
     if (rc != NMPC_OK) return fail(rc, err);
     p->impl.have_iterate = true;
     p->impl.params_current = true;
+    p->impl.iter_hyk = false;
     ++p->impl.solution_id;
     return NMPC_OK;
 }
@@ -502,6 +518,11 @@ nmpc_status nmpc_batch_solve(nmpc_batch* b, int32_t warm, const nmpc_options* op
                 return fail(NMPC_ERR_BAD_ORDER, "batch_solve: warm start without a previous iterate");
     nmpc_options o;
     if (!resolve_options(opts, o)) return fail(NMPC_ERR_INVALID_ARG, "batch_solve: invalid options");
+    if (o.kkt != NMPC_KKT_LIFTED) return fail(NMPC_ERR_UNSUPPORTED, "batch_solve: HyKKT solves one problem at a time");
+    if (warm)
+        for (auto* q : b->members)
+            if (q->impl.iter_hyk)
+                return fail(NMPC_ERR_BAD_ORDER, "batch_solve: a warm Lifted-KKT start needs a Lifted-KKT iterate");
     return guarded([&]() -> nmpc_status {
         std::vector<nmpc_result> r(b->members.size());
         std::string err;
@@ -514,6 +535,7 @@ nmpc_status nmpc_batch_solve(nmpc_batch* b, int32_t warm, const nmpc_options* op
             r[i].ms_total = ms;
             b->members[i]->impl.have_iterate = true;
             b->members[i]->impl.params_current = true;
+            b->members[i]->impl.iter_hyk = false;
             ++b->members[i]->impl.solution_id;
             nmpc::device_invalidate_adjoint(b->members[i]->impl);
         }

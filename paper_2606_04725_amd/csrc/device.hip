@@ -109,7 +109,8 @@ struct Batch {
     int4* tasks = nullptr;
     std::vector<BLaunch> fac, fwd, bwd, fwd_rest;
     bool has_distill = false, has_plate = false;
-    int* running = nullptr;        // device: instances running, instances waiting for corrections
+    int* running = nullptr;        // device: instances running, instances waiting for corrections,
+                                   // instances whose HyKKT conjugate gradients run
     int* hrunning = nullptr;       // pinned copy
     Ctl* hctl = nullptr;           // pinned
     hipEvent_t ev[8] = {};
@@ -186,6 +187,11 @@ DevOpts dev_opts(const nmpc_options& o) {
     d.soc_max = o.soc_max;
     d.merit_fallback = o.merit_fallback;
     d.fixed_mu = o.fixed_mu;
+    d.cg_tol = o.hykkt_cg_tol;
+    d.cg_max = o.hykkt_cg_max;
+    // each second-order correction would need its own conjugate-gradient
+    // solve: HyKKT runs without them
+    if (o.kkt == NMPC_KKT_HYKKT) d.soc_max = 0;
     return d;
 }
 
@@ -333,8 +339,8 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
     BTRY(upload(B->allocs, B->groups, gl));
     BTRY(upload(B->allocs, B->tasks, tl));
     BTRY(linalg_configure(lim));   // the device maximum, so every batch's launches fit
-    BTRY(dalloc(B->allocs, B->running, 2));
-    BTRY(hipHostMalloc((void**)&B->hrunning, 2 * sizeof(int), hipHostMallocDefault));
+    BTRY(dalloc(B->allocs, B->running, 3));
+    BTRY(hipHostMalloc((void**)&B->hrunning, 3 * sizeof(int), hipHostMallocDefault));
     BTRY(hipHostMalloc((void**)&B->hctl, sizeof(Ctl) * ni, hipHostMallocDefault));
     for (auto& e : B->ev) BTRY(hipEventCreate(&e));
 #undef BTRY
@@ -402,6 +408,47 @@ void enqueue_pass(Batch& B, const DevOpts& o, bool timed) {
     launch_phaseT(B.dI, B.spaces, B.ninst, o, st);
     launch_update(B.dI, B.spaces, B.ninst, o, B.running, st);
     mark(5);
+}
+
+// One pass of the HyKKT variant: as enqueue_pass up to the solve of the
+// right-hand side, then conjugate gradients on the Schur complement (one
+// iteration per host round trip, until no instance's CG runs; the device ends
+// each at cg_max), the final solve, and the rest of the pass.
+hipError_t enqueue_pass_hykkt(Batch& B, const DevOpts& o, bool timed) {
+    hipStream_t st = B.stream;
+    auto mark = [&](int k) {
+        if (timed) (void)hipEventRecord(B.ev[k], st);
+    };
+    mark(0);
+    eval(B, true, kSrcIter, kPhA);
+    launch_phaseA(B.dI, B.spaces, B.ninst, kPhA, o, true, st);
+    mark(1);
+    launch_assemble(B.dI, B.spaces, kPhB, st);
+    mark(2);
+    factor_launches(B, kPredFactor, 0.0);
+    launch_decideF(B.dI, B.ninst, o, st);
+    mark(3);
+    solve_launches(B, kPhS, 0, true);
+    launch_hk_cg_start(B.dI, B.spaces, B.ninst, o, B.running + 2, st);
+    for (int k = 0; k <= o.cg_max + 1; ++k) {
+        hipError_t e = hipMemcpyAsync(B.hrunning + 2, B.running + 2, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (B.hrunning[2] == 0) break;
+        launch_hk_cg_pre(B.dI, B.spaces, st);
+        solve_launches(B, kPhS, 5);
+        launch_hk_cg_post(B.dI, B.spaces, B.ninst, o, B.running + 2, st);
+    }
+    launch_hk_finish(B.dI, B.spaces, st);
+    solve_launches(B, kPhS, 0, false);
+    launch_phaseE(B.dI, B.spaces, B.ninst, o, st);
+    mark(4);
+    launch_trial(B.dI, B.spaces, st);
+    eval(B, false, kSrcTrial, kPhT);
+    launch_phaseT(B.dI, B.spaces, B.ninst, o, st);
+    launch_update(B.dI, B.spaces, B.ninst, o, B.running, st);
+    mark(5);
+    return hipGetLastError();
 }
 
 void enqueue_corrections(Batch& B, const DevOpts& o, bool timed) {
@@ -974,6 +1021,8 @@ nmpc_status device_init(Problem& p, std::string& err) {
     DTRY(dalloc(A, I.adj_b, n)); DTRY(dalloc(A, I.adj_d, n)); DTRY(dalloc(A, I.adj_lam, m));
     DTRY(dalloc(A, I.adj_qr, m));
     DTRY(dalloc(A, I.bsum, n));
+    DTRY(dalloc(A, I.hk_x, mc)); DTRY(dalloc(A, I.hk_r, mc)); DTRY(dalloc(A, I.hk_p, mc));
+    DTRY(dalloc(A, I.hk_sp, mc)); DTRY(dalloc(A, I.hk_t, n)); DTRY(dalloc(A, I.hk_w, n));
     {
         // Hessian rows with both triangles, slots in increasing order per row
         std::vector<int32_t> cnt(n + 1, 0), wf_ptr(n + 1, 0);
@@ -1035,9 +1084,12 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
     const int ni = B.ninst;
     const DevOpts dop = dev_opts(o);
     const bool timed = o.timing != 0;
+    const bool hyk = o.kkt == NMPC_KKT_HYKKT;
     hipStream_t st = B.stream;
     for (int i = 0; i < ni; ++i) {
         Ctl c{};
+        c.hyk = hyk ? 1 : 0;
+        c.hk_gamma = o.hykkt_gamma;
         c.mu = warm ? o.mu0_warm : o.mu0_cold;
         c.tau = std::max(o.tau_min, 1.0 - c.mu);
         c.E0 = INFINITY;
@@ -1051,6 +1103,14 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
         B.members[i]->gamma_last = o.gamma;
     }
     HIP_TRY(hipMemcpyAsync(B.ctl, B.hctl, sizeof(Ctl) * ni, hipMemcpyHostToDevice, st));
+    if (warm && hyk) {   // a held Lifted-KKT iterate becomes a HyKKT one
+        for (Device* m : B.members)
+            if (!m->owner->iter_hyk && ni != 1) {
+                err = "solve: HyKKT warm starts from Lifted-KKT iterates are for single problems";
+                return NMPC_ERR_UNSUPPORTED;
+            }
+        if (!B.members[0]->owner->iter_hyk) launch_hk_from_lifted(B.dI, B.spaces, st);
+    }
     if (!warm) {
         launch_cold_guess(B.dI, B.spaces.sp[kSpN], st);   // every stage: the measured state, the last control
         launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, false, st);
@@ -1060,7 +1120,7 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
     }
     double ms[5] = {0, 0, 0, 0, 0};
     const int k = timed ? 1 : 0;
-    bool use_graph = o.graph != 0 && !B.graph_failed[k];
+    bool use_graph = o.graph != 0 && !B.graph_failed[k] && !hyk;   // HyKKT: host-driven CG
     if (use_graph && (ensure_graph(B, dop, timed, 0) != hipSuccess ||
                       (o.soc_max > 0 && ensure_graph(B, dop, timed, 1) != hipSuccess))) {
         (void)hipGetLastError();
@@ -1080,6 +1140,8 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
         }
         if (use_graph) {
             HIP_TRY(hipGraphLaunch(B.exec[k], st));
+        } else if (hyk) {
+            HIP_TRY(enqueue_pass_hykkt(B, dop, timed));
         } else {
             enqueue_pass(B, dop, timed);
             HIP_TRY(hipGetLastError());
@@ -1136,6 +1198,7 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
         r.factor_launches = c.factorizations * B.members[i]->fac_launches;
         r.passes = (int)passes;
         r.timing_lost = timing_lost;
+        r.cg_iters = c.cg_total;
         res[i] = r;
         worst = std::max(worst, (int)c.status);
     }

@@ -70,6 +70,8 @@ struct Problem {
     // the held iterate belongs to the parameters currently set (cleared by a
     // parameter change, set by a solve or an explicit iterate)
     bool params_current = false;
+    // the held iterate is a HyKKT one (equality rows hold lambda, no slacks)
+    bool iter_hyk = false;
     int64_t solution_id = 0;   // increases with every iterate the handle takes
     // parameters (host copies)
     std::vector<double> x0, setpoint, traj, u_prev;

@@ -94,6 +94,12 @@ struct Ctl {
     int fail;            // set by the factorization: a pivot is not positive and finite
     int trials;          // trial points of the current line search
     int factorizations, ls_trials;
+    // HyKKT (equalities kept exact, Newton system by the Cholesky factor of
+    // K_gamma = K_c + hk_gamma J_c^T J_c and conjugate gradients on the Schur
+    // complement): mode flag, and the running CG of the current step
+    int hyk;
+    int cg_it, cg_done, cg_total;
+    double hk_gamma, cg_rr, cg_stop, cg_alpha, cg_beta;
 };
 
 __host__ __device__ inline bool ctl_active(const Ctl* c, int pred) {
@@ -139,18 +145,24 @@ struct InstPtrs {
     double* bsum;     // large-supernode backward solves: rows-below products per column
     double* part;     // reduction partials: kMaxQ rows of this instance's blocks
     double* filter;   // (theta, phi) pairs, kFilterCapMax of them
+    // HyKKT: CG iterate, residual, direction and S-product over the equality
+    // rows (m_c each); J_c^T p and its solve with the factor (n each)
+    double *hk_x, *hk_r, *hk_p, *hk_sp, *hk_t, *hk_w;
     Ctl* ctl;
 };
 
 // Right-hand side and solution of the solves: 0 rhs -> dy (Newton step),
 // 1 yt -> dzl (single-solve entry point), 2 adj_rhs -> adj_w (sensitivities),
 // 3 adj_rhs -> adj_d (refinement corrections of the sensitivities),
-// 4 rhs_s -> dy_s (second-order correction).
+// 4 rhs_s -> dy_s (second-order correction), 5 hk_t -> hk_w (HyKKT products
+// with K_gamma^{-1}).
 __host__ __device__ inline const double* solve_in(const InstPtrs& I, int which) {
-    return which == 0 ? I.rhs : (which == 1 ? I.yt : (which == 4 ? I.rhs_s : I.adj_rhs));
+    return which == 0 ? I.rhs : (which == 1 ? I.yt : (which == 4 ? I.rhs_s : (which == 5 ? I.hk_t : I.adj_rhs)));
 }
 __host__ __device__ inline double* solve_out(const InstPtrs& I, int which) {
-    return which == 0 ? I.dy : (which == 1 ? I.dzl : (which == 2 ? I.adj_w : (which == 3 ? I.adj_d : I.dy_s)));
+    return which == 0 ? I.dy
+                      : (which == 1 ? I.dzl
+                                    : (which == 2 ? I.adj_w : (which == 3 ? I.adj_d : (which == 5 ? I.hk_w : I.dy_s))));
 }
 
 // Block -> instance map of one index space.  Instance i owns blocks
@@ -186,6 +198,8 @@ struct DevOpts {
     double eta_first, eta_min, eta_max, kp_first, kp, km;
     double g_theta, g_phi, s_theta, s_phi, delta, amin_frac, theta_max_fact, theta_min_fact, soc_kappa;
     int ls_max, max_iter, filter_cap, soc_max, merit_fallback, fixed_mu;
+    double cg_tol;
+    int cg_max;
 };
 
 // One group of supernodes of one instance: sched_nodes[begin .. end), walked in
@@ -224,6 +238,19 @@ void launch_update(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOp
                    hipStream_t st);
 void launch_cold_start(const InstPtrs* I, const IpmSpaces& S, double bound_push, double slack_push, double mu0,
                        bool after_eval, hipStream_t st);
+// HyKKT step (instances in phase S with the HyKKT flag): CG start after the
+// solve of the right-hand side, one CG iteration as J_c^T p (pre), the solve
+// hk_t -> hk_w that the caller enqueues, and the rest of the iteration (post);
+// both write the number of instances whose CG still runs to *count.  finish:
+// the right-hand side of the final solve.  from_lifted: convert the held
+// Lifted-KKT iterate.
+void launch_hk_cg_start(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, int* count,
+                        hipStream_t st);
+void launch_hk_cg_pre(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
+void launch_hk_cg_post(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, int* count,
+                       hipStream_t st);
+void launch_hk_finish(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
+void launch_hk_from_lifted(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
 void launch_set_fail(const InstPtrs* I, int ninst, int value, hipStream_t st);
 // sensitivities: rhs = seed_obj grad f + S_u^T seed_u, and the parameter contractions
 void launch_adj_seed(const InstPtrs* I, const Space& spN, hipStream_t st);   // seed from adj_seed

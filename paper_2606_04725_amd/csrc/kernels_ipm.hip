@@ -155,12 +155,20 @@ __global__ void __launch_bounds__(kBlock) k_phaseA(const InstPtrs* __restrict__ 
         if (!isfinite(I.fterm[j]) || !isfinite(I.grad[j])) q[10] = 1.0;
     } else if (t < I.n + I.ml) {
         const int r = t - I.n;
-        const double g = lifted_g(I, gamma, r);
-        q[2] = fabs(I.om[r] - I.be[r]);
-        q[3] = fabs(g + I.s[r]);
-        q[4] = I.s[r] * I.be[r];
-        q[5] = q[4];
-        if (!isfinite(g)) q[10] = 1.0;
+        if (I.ctl->hyk && r < 2 * I.mc) {
+            // HyKKT: an equality row has no slack; its residual is c itself
+            if (r < I.mc) {
+                q[3] = fabs(I.c[r]);
+                if (!isfinite(I.c[r])) q[10] = 1.0;
+            }
+        } else {
+            const double g = lifted_g(I, gamma, r);
+            q[2] = fabs(I.om[r] - I.be[r]);
+            q[3] = fabs(g + I.s[r]);
+            q[4] = I.s[r] * I.be[r];
+            q[5] = q[4];
+            if (!isfinite(g)) q[10] = 1.0;
+        }
     }
     store_partials(q, kOpsA, I.part, nblocks_of(sp, inst), lb, sh);
 }
@@ -228,7 +236,16 @@ __global__ void __launch_bounds__(kBlock) k_rows_prep(const InstPtrs* __restrict
     const double mu = I.ctl->mu, gamma = I.ctl->gamma;
     const int r = lb * kBlock + threadIdx.x;
     if (r >= I.m) return;
-    if (r < I.mc) {
+    if (r < I.mc && I.ctl->hyk) {
+        // HyKKT: weight hk_gamma on J_c^T J_c, right-hand side b1 + hk_gamma J_c^T b2 with b2 = -c
+        const int a = r, b = I.mc + r;
+        const double g = I.ctl->hk_gamma;
+        I.Q[a] = 0.0; I.Q[b] = 0.0;
+        I.r2[a] = 0.0; I.r2[b] = 0.0;
+        I.r4[a] = I.c[r]; I.r4[b] = 0.0;
+        I.qeff[r] = g;
+        I.vcomb[r] = g * I.c[r];
+    } else if (r < I.mc) {
         const int a = r, b = I.mc + r;
         const double Qa = I.be[a] / I.s[a], Qb = I.be[b] / I.s[b];
         const double r2a = I.om[a] - mu / I.s[a], r2b = I.om[b] - mu / I.s[b];
@@ -344,7 +361,15 @@ __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ 
     const double mu = I.ctl->mu, tau = I.ctl->tau;
     double q[11] = {INFINITY, INFINITY, -INFINITY, 0, 0, 0, 0, 0, 0, 0, 0};
     const int t = lb * kBlock + threadIdx.x;
-    if (t < I.m) {
+    if (t < I.m && t < I.mc && I.ctl->hyk) {
+        // HyKKT: the equality multiplier moves by the CG solution; no slack
+        const int r = t, b = I.mc + r;
+        const double dl = I.hk_x[r];
+        I.ds[r] = 0.0; I.dom[r] = dl; I.dbe[r] = 0.0;
+        I.ds[b] = 0.0; I.dom[b] = 0.0; I.dbe[b] = 0.0;
+        q[2] = fabs(I.om[r] + dl);
+        q[7] = fabs(I.r4[r]);
+    } else if (t < I.m) {
         const int r = t;
         double jdy = 0.0;
         for (int p = I.jptr[r]; p < I.jptr[r + 1]; ++p) jdy += I.jv[p] * I.dy[I.jcol[p]];
@@ -478,10 +503,17 @@ __global__ void __launch_bounds__(kBlock) k_phaseT(const InstPtrs* __restrict__ 
         if (!isfinite(I.fterm[j])) q[5] = 1.0;
     } else if (t < I.n + I.ml) {
         const int r = t - I.n;
-        const double g = lifted_g(I, gamma, r);
-        q[1] = log(I.st[r]);
-        q[4] = fabs(g + I.st[r]);
-        if (!isfinite(g)) q[5] = 1.0;
+        if (I.ctl->hyk && r < 2 * I.mc) {
+            if (r < I.mc) {
+                q[4] = fabs(I.c[r]);
+                if (!isfinite(I.c[r])) q[5] = 1.0;
+            }
+        } else {
+            const double g = lifted_g(I, gamma, r);
+            q[1] = log(I.st[r]);
+            q[4] = fabs(g + I.st[r]);
+            if (!isfinite(g)) q[5] = 1.0;
+        }
     }
     store_partials(q, kOpsT, I.part, nblocks_of(sp, inst), lb, sh);
 }
@@ -767,7 +799,9 @@ __global__ void __launch_bounds__(kBlock) k_update(const InstPtrs* __restrict__ 
             I.zu[j] = 0.0;
         }
     }
-    if (t < I.ml) {
+    if (t < 2 * I.mc && I.ctl->hyk) {
+        if (t < I.mc) I.om[t] = I.om[t] + alpha * dom[t];   // HyKKT: lambda; no slack or slack dual
+    } else if (t < I.ml) {
         const int r = t;
         const double sn = I.s[r] + alpha * ds[r];
         I.s[r] = sn;
@@ -831,7 +865,11 @@ k_cold_duals(const InstPtrs* __restrict__ Ia, Space sp, double mu0, double spush
     const InstPtrs& I = Ia[inst];
     const double gamma = I.ctl->gamma;
     const int t = lb * kBlock + threadIdx.x;
-    if (t < I.ml) {
+    if (t < 2 * I.mc && I.ctl->hyk) {   // HyKKT: lambda = 0; the slack slots of equality rows stay inert
+        I.s[t] = 1.0;
+        I.om[t] = 0.0;
+        I.be[t] = 0.0;
+    } else if (t < I.ml) {
         const double g = lifted_g(I, gamma, t);
         const double sv = fmax(-g, spush * fmax(1.0, fabs(g)));
         I.s[t] = sv;
@@ -994,6 +1032,179 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_plate(const InstPtrs* __r
     out[D.nx + p] = 2.0 * sw - 2.0 * seed_obj * sd;
 }
 
+// ---- HyKKT: conjugate gradients on S = J_c K_gamma^{-1} J_c^T --------------------------
+// After the solve K_gamma w0 = b1 + gamma_h J_c^T b2 (w0 in dy), S x = J_c w0 - b2
+// (b2 = -c) is solved by CG from x = 0; every product with S is J_c^T p, one
+// solve with the factor (hk_t -> hk_w), then J_c w.  Equality rows only.
+constexpr Ops kOpsSum1{1, {kSum}};
+
+__device__ inline bool hk_step(const Ctl* c) { return c->phase == kPhS && c->hyk; }
+__device__ inline bool hk_cg_running(const Ctl* c) { return hk_step(c) && !c->cg_done; }
+
+// J_c^T v over the equality rows, for variable j
+__device__ inline double hk_jct(const InstPtrs& I, int j, const double* __restrict__ v) {
+    return gather_sum(
+        I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
+        [&](int2 rs) { return rs.x < I.mc ? I.jv[rs.y] * v[rs.x] : 0.0; });
+}
+
+// r = p = J_c w0 + c, x = 0; partial |r|^2
+__global__ void __launch_bounds__(kBlock) k_hk_cg_init(const InstPtrs* __restrict__ Ia, Space sp) {
+    __shared__ double sh[kMaxQ * kWaves];
+    int lb;
+    const int inst = block_inst(sp, lb);
+    const InstPtrs& I = Ia[inst];
+    if (!hk_step(I.ctl)) return;
+    double q[1] = {0.0};
+    const int r = lb * kBlock + threadIdx.x;
+    if (r < I.mc) {
+        const double b = row_dot(I, r, I.dy) + I.c[r];
+        I.hk_r[r] = b;
+        I.hk_p[r] = b;
+        I.hk_x[r] = 0.0;
+        q[0] = b * b;
+    }
+    store_partials(q, kOpsSum1, I.part, nblocks_of(sp, inst), lb, sh);
+}
+
+__global__ void __launch_bounds__(kBlock) k_hk_cg_begin(const InstPtrs* __restrict__ Ia, Space sp, DevOpts o) {
+    __shared__ double sh[kMaxQ * kWaves];
+    __shared__ double T[kMaxQ];
+    const int inst = blockIdx.x;
+    const InstPtrs& I = Ia[inst];
+    Ctl* c = I.ctl;
+    if (!hk_step(c)) return;
+    finalize_partials(I.part, nblocks_of(sp, inst), kOpsSum1, sh, T);
+    if (threadIdx.x != 0) return;
+    c->cg_rr = T[0];
+    c->cg_stop = o.cg_tol * sqrt(T[0]);
+    c->cg_it = 0;
+    c->cg_done = (T[0] == 0.0 || o.cg_max <= 0) ? 1 : 0;
+}
+
+// hk_t = J_c^T p
+__global__ void __launch_bounds__(kBlock) k_hk_jt(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    if (!hk_cg_running(I.ctl)) return;
+    const int j = lb * kBlock + threadIdx.x;
+    if (j < I.n) I.hk_t[j] = hk_jct(I, j, I.hk_p);
+}
+
+// Sp = J_c hk_w; partial p . Sp
+__global__ void __launch_bounds__(kBlock) k_hk_sp(const InstPtrs* __restrict__ Ia, Space sp) {
+    __shared__ double sh[kMaxQ * kWaves];
+    int lb;
+    const int inst = block_inst(sp, lb);
+    const InstPtrs& I = Ia[inst];
+    if (!hk_cg_running(I.ctl)) return;
+    double q[1] = {0.0};
+    const int r = lb * kBlock + threadIdx.x;
+    if (r < I.mc) {
+        const double v = row_dot(I, r, I.hk_w);
+        I.hk_sp[r] = v;
+        q[0] = I.hk_p[r] * v;
+    }
+    store_partials(q, kOpsSum1, I.part, nblocks_of(sp, inst), lb, sh);
+}
+
+__global__ void __launch_bounds__(kBlock) k_hk_cg_alpha(const InstPtrs* __restrict__ Ia, Space sp) {
+    __shared__ double sh[kMaxQ * kWaves];
+    __shared__ double T[kMaxQ];
+    const int inst = blockIdx.x;
+    const InstPtrs& I = Ia[inst];
+    Ctl* c = I.ctl;
+    if (!hk_cg_running(c)) return;
+    finalize_partials(I.part, nblocks_of(sp, inst), kOpsSum1, sh, T);
+    if (threadIdx.x == 0) c->cg_alpha = c->cg_rr / T[0];
+}
+
+// x += alpha p, r -= alpha Sp; partial |r|^2
+__global__ void __launch_bounds__(kBlock) k_hk_axpy(const InstPtrs* __restrict__ Ia, Space sp) {
+    __shared__ double sh[kMaxQ * kWaves];
+    int lb;
+    const int inst = block_inst(sp, lb);
+    const InstPtrs& I = Ia[inst];
+    if (!hk_cg_running(I.ctl)) return;
+    const double a = I.ctl->cg_alpha;
+    double q[1] = {0.0};
+    const int r = lb * kBlock + threadIdx.x;
+    if (r < I.mc) {
+        I.hk_x[r] += a * I.hk_p[r];
+        const double v = I.hk_r[r] - a * I.hk_sp[r];
+        I.hk_r[r] = v;
+        q[0] = v * v;
+    }
+    store_partials(q, kOpsSum1, I.part, nblocks_of(sp, inst), lb, sh);
+}
+
+// convergence (|r| <= cg_tol |b|) or the iteration limit; otherwise beta
+__global__ void __launch_bounds__(kBlock) k_hk_cg_beta(const InstPtrs* __restrict__ Ia, Space sp, DevOpts o) {
+    __shared__ double sh[kMaxQ * kWaves];
+    __shared__ double T[kMaxQ];
+    const int inst = blockIdx.x;
+    const InstPtrs& I = Ia[inst];
+    Ctl* c = I.ctl;
+    if (!hk_cg_running(c)) return;
+    finalize_partials(I.part, nblocks_of(sp, inst), kOpsSum1, sh, T);
+    if (threadIdx.x != 0) return;
+    const double rr = T[0];
+    c->cg_it += 1;
+    c->cg_total += 1;
+    if (sqrt(rr) <= c->cg_stop || c->cg_it >= o.cg_max) {
+        c->cg_done = 1;
+    } else {
+        c->cg_beta = rr / c->cg_rr;
+        c->cg_rr = rr;
+    }
+}
+
+// p = r + beta p
+__global__ void __launch_bounds__(kBlock) k_hk_pupd(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    if (!hk_cg_running(I.ctl)) return;
+    const int r = lb * kBlock + threadIdx.x;
+    if (r < I.mc) I.hk_p[r] = I.hk_r[r] + I.ctl->cg_beta * I.hk_p[r];
+}
+
+// instances whose CG still runs -> *count
+__global__ void __launch_bounds__(kBlock) k_hk_count(const InstPtrs* __restrict__ Ia, int ninst, int* count) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int i = threadIdx.x; i < ninst; i += kBlock) mine += hk_cg_running(Ia[i].ctl) ? 1 : 0;
+    if (mine) atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) *count = cnt;
+}
+
+// right-hand side of the final solve: b1 + gamma_h J_c^T b2 - J_c^T x
+__global__ void __launch_bounds__(kBlock) k_hk_finish(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    if (!hk_step(I.ctl)) return;
+    const int j = lb * kBlock + threadIdx.x;
+    if (j < I.n) I.rhs[j] -= hk_jct(I, j, I.hk_x);
+}
+
+// a Lifted-KKT iterate as a HyKKT one: lambda = omega+ - omega-, the equality
+// rows' slack slots inert
+__global__ void __launch_bounds__(kBlock) k_hk_from_lifted(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    const int r = lb * kBlock + threadIdx.x;
+    if (r >= I.mc) return;
+    const int b = I.mc + r;
+    I.om[r] = I.om[r] - I.om[b];
+    I.om[b] = 0.0;
+    I.s[r] = 1.0;
+    I.s[b] = 1.0;
+    I.be[r] = 0.0;
+    I.be[b] = 0.0;
+}
+
 }  // namespace
 
 void launch_phaseA(const InstPtrs* I, const IpmSpaces& S, int ninst, int pred, const DevOpts& o, bool decide,
@@ -1097,6 +1308,37 @@ void launch_adj_refine(int step, const InstPtrs* I, const IpmSpaces& S, double e
     } else {
         hipLaunchKernelGGL(k_adj_update, dim3(S.sp[kSpMax].blocks), dim3(kBlock), 0, st, I, S.sp[kSpMax]);
     }
+}
+
+void launch_hk_cg_start(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, int* count,
+                        hipStream_t st) {
+    const Space& sp = S.sp[kSpM];
+    hipLaunchKernelGGL(k_hk_cg_init, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp);
+    hipLaunchKernelGGL(k_hk_cg_begin, dim3(ninst), dim3(kBlock), 0, st, I, sp, o);
+    hipLaunchKernelGGL(k_hk_count, dim3(1), dim3(kBlock), 0, st, I, ninst, count);
+}
+
+void launch_hk_cg_pre(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
+    hipLaunchKernelGGL(k_hk_jt, dim3(S.sp[kSpN].blocks), dim3(kBlock), 0, st, I, S.sp[kSpN]);
+}
+
+void launch_hk_cg_post(const InstPtrs* I, const IpmSpaces& S, int ninst, const DevOpts& o, int* count,
+                       hipStream_t st) {
+    const Space& sp = S.sp[kSpM];
+    hipLaunchKernelGGL(k_hk_sp, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp);
+    hipLaunchKernelGGL(k_hk_cg_alpha, dim3(ninst), dim3(kBlock), 0, st, I, sp);
+    hipLaunchKernelGGL(k_hk_axpy, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp);
+    hipLaunchKernelGGL(k_hk_cg_beta, dim3(ninst), dim3(kBlock), 0, st, I, sp, o);
+    hipLaunchKernelGGL(k_hk_pupd, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp);
+    hipLaunchKernelGGL(k_hk_count, dim3(1), dim3(kBlock), 0, st, I, ninst, count);
+}
+
+void launch_hk_finish(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
+    hipLaunchKernelGGL(k_hk_finish, dim3(S.sp[kSpN].blocks), dim3(kBlock), 0, st, I, S.sp[kSpN]);
+}
+
+void launch_hk_from_lifted(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
+    hipLaunchKernelGGL(k_hk_from_lifted, dim3(S.sp[kSpM].blocks), dim3(kBlock), 0, st, I, S.sp[kSpM]);
 }
 
 void launch_adj_gather(const InstPtrs* I, int family, int nx, hipStream_t st) {
