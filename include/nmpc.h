@@ -92,6 +92,13 @@ typedef struct nmpc_structure {
     double c_lo, c_hi;   /* heater control bounds */
     double cond_slope;   /* conductivity slope */
     int32_t ordering;    /* NMPC_ORDER_* */
+    /* control horizon t_c <= t_p (Section 3.1, eqs. 4-5), distillation family:
+     * with 1 <= control_horizon < horizon the controls of the stages after it
+     * are held at its value, as equality rows u_k - u_{k-1} = 0 (the same
+     * feasible set as u_k = u_{control_horizon}) placed after the dynamics
+     * rows, R then V per stage; 0 (or >= horizon): every stage has its own
+     * control.  The plate family must leave it 0. */
+    int32_t control_horizon;
 } nmpc_structure;
 
 /* Interior-point constants (the paper leaves them open; see the design notes).
@@ -222,6 +229,10 @@ nmpc_status nmpc_set_parameters(nmpc_problem* p, const double* x0, const double*
 /* One NMPC solve (Algorithm 2).  warm = 0: cold start from x0 repeated over
  * the horizon with u_prev, mu = mu0_cold.  warm = 1: start from the last
  * iterate held by the handle (Algorithm 1, z_{k+1} <- z*_k) with mu0_warm.
+ * warm = 2: the same, shifted by one stage first (stage k takes stage k + 1's
+ * values of every stage-indexed quantity, the last stage keeps its own: the
+ * horizon has advanced by one stage since that solution).  An arbitrary
+ * warm start is placed with nmpc_set_iterate, then warm = 1.
  * opts NULL = defaults.  res may be NULL.  Returns NMPC_OK, a positive
  * outcome, or an error (BAD_ORDER before analyze or warm without a previous
  * solve; NO_DEVICE without a GPU). */

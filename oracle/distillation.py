@@ -20,6 +20,10 @@ Objective: sum_k (x_{k,0} - xD*)^2 + (x_{k,N+1} - xB*)^2 + rho |u_k - u_{k-1}|^2
 with u_0 the previously applied control (a parameter).
 Inequalities (g <= 0 form): R - V <= 0 (D >= 0), V - R - F <= 0 (B >= 0).
 Bounds: x in [0, 1], R, V in [0.5, 5].
+Control horizon (Section 3.1, eqs. 4-5): with Hc < H the controls are held at
+their value of stage Hc after it.  The hold is written as u_k - u_{k-1} = 0 for
+stages k = Hc+1..H (1-based), the same feasible set as u_k = u_Hc; these
+equality rows follow the H*nx dynamics rows, controls R then V per stage.
 
 Decision vector y is stage-major: stage k occupies y[k*ns:(k+1)*ns] with
 ns = N + 4, laid out [x_0 .. x_{N+1}, R, V].
@@ -34,14 +38,16 @@ import scipy.sparse as sp
 
 class DistillationOCP:
     def __init__(self, N, H, dt, alpha, F=1.0, xD_sp=0.95, xB_sp=0.05, rho=1e-2,
-                 x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0):
+                 x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0, Hc=None):
         self.N, self.H, self.dt = int(N), int(H), float(dt)
+        self.Hc = self.H if Hc is None or Hc <= 0 or Hc >= H else int(Hc)   # control horizon (stages)
         self.alpha, self.F, self.rho = float(alpha), float(F), float(rho)
         self.nx = self.N + 2
         self.nu = 2
         self.ns = self.nx + self.nu
         self.n = self.H * self.ns
-        self.m_c = self.H * self.nx
+        self.m_dyn = self.H * self.nx
+        self.m_c = self.m_dyn + self.nu * (self.H - self.Hc)
         self.m_d = 2 * self.H
         self.fd = self.N // 2
         lb = np.empty(self.n)
@@ -61,7 +67,7 @@ class DistillationOCP:
     @classmethod
     def from_workload(cls, w):
         m = cls(w.N, w.H, w.dt, w.alpha, F=w.F, xD_sp=w.xD_sp, xB_sp=w.xB_sp,
-                rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi, u_lo=w.u_lo, u_hi=w.u_hi)
+                rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi, u_lo=w.u_lo, u_hi=w.u_hi, Hc=getattr(w, "Hc", None))
         return m
 
     def set_parameters(self, x0=None, zF=None, u_prev=None, setpoint=None):
@@ -133,7 +139,10 @@ class DistillationOCP:
     def cons_c(self, y):
         X, R, V = self.split(y)
         Xp = np.vstack([self.x0[None, :], X[:-1]])
-        return (X - Xp - self.dt * self.rhs(X, R, V, self.zF)).reshape(-1)
+        dyn = (X - Xp - self.dt * self.rhs(X, R, V, self.zF)).reshape(-1)
+        hc = self.Hc
+        hold = np.stack([R[hc:] - R[hc - 1:-1], V[hc:] - V[hc - 1:-1]], axis=1).reshape(-1)
+        return np.concatenate([dyn, hold])
 
     def cons_d(self, y):
         _, R, V = self.split(y)
@@ -161,6 +170,11 @@ class DistillationOCP:
                 for c in sorted(cols):
                     jr.append(row)
                     jc.append(c)
+        for k in range(self.Hc, H):       # holds: u_k - u_{k-1}
+            for j, idx in enumerate((self.iR, self.iV)):
+                row = self.m_dyn + 2 * (k - self.Hc) + j
+                jr += [row, row]
+                jc += [idx(k - 1), idx(k)]
         self.jc_rows, self.jc_cols = np.array(jr), np.array(jc)
         dr, dc = [], []
         for k in range(H):
@@ -219,6 +233,11 @@ class DistillationOCP:
                     out[self.ix(k - 1, i)] = -1.0
                 for c, v in out.items():
                     vals[(row, c)] = v
+        for k in range(self.Hc, self.H):
+            for j, idx in enumerate((self.iR, self.iV)):
+                row = self.m_dyn + 2 * (k - self.Hc) + j
+                vals[(row, idx(k - 1))] = -1.0
+                vals[(row, idx(k))] = 1.0
         data = np.array([vals.get((r, c), 0.0) for r, c in zip(self.jc_rows, self.jc_cols)],
                         dtype=np.result_type(y, 1.0))
         return sp.csr_matrix((data, (self.jc_rows, self.jc_cols)), shape=(self.m_c, self.n))
@@ -232,7 +251,7 @@ class DistillationOCP:
         X, R, V = self.split(y)
         N, nx, dt, rho = self.N, self.nx, self.dt, self.rho
         _, yp, ypp = self._vle(X)
-        Lam = np.asarray(lam_c).reshape(self.H, nx)
+        Lam = np.asarray(lam_c)[:self.m_dyn].reshape(self.H, nx)   # the hold rows are linear
         vals = {}
 
         def add(i, j, v):

@@ -26,7 +26,7 @@ class nmpc_structure(C.Structure):
                 ("move_penalty", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("u_lo", C.c_double), ("u_hi", C.c_double),
                 ("grid", C.c_int32), ("t_hi", C.c_double), ("c_lo", C.c_double), ("c_hi", C.c_double),
-                ("cond_slope", C.c_double), ("ordering", C.c_int32)]
+                ("cond_slope", C.c_double), ("ordering", C.c_int32), ("control_horizon", C.c_int32)]
 
 
 class nmpc_options(C.Structure):

@@ -354,6 +354,7 @@ nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, 
     if (!p) return fail(NMPC_ERR_INVALID_ARG, "solve: NULL handle");
     if (!p->impl.analyzed) return fail(NMPC_ERR_BAD_ORDER, "solve: call nmpc_analyze first");
     if (!nmpc::device_present() || !p->impl.dev) return fail(NMPC_ERR_NO_DEVICE, "solve: no HIP device");
+    if (warm < 0 || warm > 2) return fail(NMPC_ERR_INVALID_ARG, "solve: warm must be 0, 1 or 2");
     if (warm && !p->impl.have_iterate) return fail(NMPC_ERR_BAD_ORDER, "solve: warm start without a previous iterate");
     nmpc_options o;
     if (!resolve_options(opts, o)) return fail(NMPC_ERR_INVALID_ARG, "solve: invalid options");
@@ -512,6 +513,7 @@ nmpc_status nmpc_batch_create(nmpc_problem* const* problems, int32_t count, nmpc
 
 nmpc_status nmpc_batch_solve(nmpc_batch* b, int32_t warm, const nmpc_options* opts, nmpc_result* per_instance) {
     if (!b || !b->impl) return fail(NMPC_ERR_INVALID_ARG, "batch_solve: NULL batch");
+    if (warm < 0 || warm > 2) return fail(NMPC_ERR_INVALID_ARG, "batch_solve: warm must be 0, 1 or 2");
     if (warm)
         for (auto* q : b->members)
             if (!q->impl.have_iterate)

@@ -594,6 +594,7 @@ nmpc_status device_init(Problem& p, std::string& err) {
     I.dd.ns = s.n_trays + 4;
     I.dd.H = s.horizon;
     I.dd.fd = s.n_trays / 2;
+    I.dd.hc = (s.control_horizon >= 1 && s.control_horizon < s.horizon) ? s.control_horizon : s.horizon;
     I.dc.dt = s.dt;
     I.dc.alpha = s.alpha;
     I.dc.F = s.feed_flow;
@@ -1103,6 +1104,7 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
         B.members[i]->gamma_last = o.gamma;
     }
     HIP_TRY(hipMemcpyAsync(B.ctl, B.hctl, sizeof(Ctl) * ni, hipMemcpyHostToDevice, st));
+    if (warm == 2) launch_shift(B.dI, B.spaces, st);   // shifted warm start
     if (warm && hyk) {   // a held Lifted-KKT iterate becomes a HyKKT one
         for (Device* m : B.members)
             if (!m->owner->iter_hyk && ni != 1) {

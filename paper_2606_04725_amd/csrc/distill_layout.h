@@ -3,7 +3,10 @@
 // Variables are stage-major: stage k (0-based, k = 0..H-1 for stages 1..H)
 // holds [x_0 .. x_{N+1}, R, V], ns = N + 4 entries, at k * ns.
 // Equality rows c: row k * nx + i (nx = N + 2) is the implicit-Euler residual
-// of state i at stage k.  Inequality rows d: m_c + 2k (R - V <= 0) and
+// of state i at stage k.  With a control horizon (stages hc..H-1 held),
+// equality rows H nx + 2 (k - hc) + j, k = hc..H-1, j = 0 (R) / 1 (V), are the
+// holds u_{k,j} - u_{k-1,j} = 0 (two slots: u_{k-1,j} then u_{k,j}); hc = H
+// without holds.  Inequality rows d: m_c + 2k (R - V <= 0) and
 // m_c + 2k + 1 (V - R - F <= 0).
 //
 // Jacobian rows are stored CSR with columns ascending; row (k, i) holds, in
@@ -25,6 +28,7 @@
 
 struct DistillDims {
     int N, nx, ns, H, fd;
+    int hc;   // first held stage (0-based) of the control horizon; H: no holds
 };
 
 __host__ __device__ inline int dl_row_nnz(const DistillDims& D, int k, int i) {

@@ -34,8 +34,8 @@ static void finish_k_count(Structure& st) {
 
 static bool build_distillation(const nmpc_structure& s, Structure& st, std::string& err) {
     if (s.n_trays < 2 || s.horizon < 1 || !(s.dt > 0) || !(s.alpha > 1.0) || !(s.feed_flow >= 0) ||
-        !(s.x_lo < s.x_hi) || !(s.u_lo < s.u_hi) || !(s.move_penalty >= 0)) {
-        err = "distillation: need n_trays >= 2, horizon >= 1, dt > 0, alpha > 1, valid bounds";
+        !(s.x_lo < s.x_hi) || !(s.u_lo < s.u_hi) || !(s.move_penalty >= 0) || s.control_horizon < 0) {
+        err = "distillation: need n_trays >= 2, horizon >= 1, dt > 0, alpha > 1, valid bounds, control_horizon >= 0";
         return false;
     }
     DistillDims D;
@@ -44,11 +44,12 @@ static bool build_distillation(const nmpc_structure& s, Structure& st, std::stri
     D.ns = D.nx + 2;
     D.H = s.horizon;
     D.fd = D.N / 2;
+    D.hc = (s.control_horizon >= 1 && s.control_horizon < s.horizon) ? s.control_horizon : s.horizon;
     st.nx = D.nx;
     st.nu = 2;
     st.H = D.H;
     st.n = D.H * D.ns;
-    st.m_c = D.H * D.nx;
+    st.m_c = D.H * D.nx + 2 * (D.H - D.hc);
     st.m_d = 2 * D.H;
     const int m = st.m_c + st.m_d;
     st.jptr.assign(m + 1, 0);
@@ -69,6 +70,12 @@ static bool build_distillation(const nmpc_structure& s, Structure& st, std::stri
                 err = "internal: distillation row layout mismatch";
                 return false;
             }
+        }
+    for (int k = D.hc; k < D.H; ++k)     // control-horizon holds u_k - u_{k-1}
+        for (int j = 0; j < 2; ++j) {
+            st.jcol.push_back((k - 1) * D.ns + D.nx + j);
+            st.jcol.push_back(k * D.ns + D.nx + j);
+            st.jptr[D.H * D.nx + 2 * (k - D.hc) + j + 1] = (int)st.jcol.size();
         }
     for (int k = 0; k < D.H; ++k)
         for (int r = 0; r < 2; ++r) {
@@ -111,8 +118,9 @@ static bool build_distillation(const nmpc_structure& s, Structure& st, std::stri
 
 static bool build_plate(const nmpc_structure& s, Structure& st, std::string& err) {
     if (s.grid < 4 || s.grid % 4 != 0 || s.horizon < 1 || !(s.dt > 0) || !(s.c_lo < s.c_hi) ||
-        !(s.cond_slope >= 0) || !(s.t_hi > -INFINITY)) {
-        err = "plate: need grid a positive multiple of 4, horizon >= 1, dt > 0, c_lo < c_hi, cond_slope >= 0";
+        !(s.cond_slope >= 0) || !(s.t_hi > -INFINITY) || s.control_horizon != 0) {
+        err = "plate: need grid a positive multiple of 4, horizon >= 1, dt > 0, c_lo < c_hi, cond_slope >= 0, "
+              "control_horizon 0";
         return false;
     }
     PlateDims D;

@@ -251,6 +251,9 @@ void launch_hk_cg_post(const InstPtrs* I, const IpmSpaces& S, int ninst, const D
                        hipStream_t st);
 void launch_hk_finish(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
 void launch_hk_from_lifted(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
+// shifted warm start: every stage-indexed quantity of the held iterate moves
+// one stage earlier, the last stage keeps its own
+void launch_shift(const InstPtrs* I, const IpmSpaces& S, hipStream_t st);
 void launch_set_fail(const InstPtrs* I, int ninst, int value, hipStream_t st);
 // sensitivities: rhs = seed_obj grad f + S_u^T seed_u, and the parameter contractions
 void launch_adj_seed(const InstPtrs* I, const Space& spN, hipStream_t st);   // seed from adj_seed

@@ -1032,6 +1032,64 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_plate(const InstPtrs* __r
     out[D.nx + p] = 2.0 * sw - 2.0 * seed_obj * sd;
 }
 
+// ---- shifted warm start -----------------------------------------------------------------
+// Stage k takes stage k + 1's values, the last stage keeps its own: variables by
+// stages of nx + nu; lifted rows [plus | minus | inequality] with the dynamics
+// rows by stages of nx, the hold rows of the control horizon by held stages of
+// two, the inequality rows by stages of two.
+__device__ inline int shift_src_var(const InstPtrs& I, int j) {
+    const int ns = I.nx + I.nu, k = j / ns;
+    return k < I.H - 1 ? j + ns : j;
+}
+
+__device__ inline int shift_src_row(const InstPtrs& I, int l) {
+    if (l >= 2 * I.mc) {
+        const int k = (l - 2 * I.mc) / 2;
+        return k < I.H - 1 ? l + 2 : l;
+    }
+    const int r = l >= I.mc ? l - I.mc : l;
+    const int dyn = I.H * I.nx;
+    if (r < dyn) return r / I.nx < I.H - 1 ? l + I.nx : l;
+    const int hc = I.family == NMPC_FAMILY_DISTILLATION ? I.dd.hc : I.H;
+    return hc + (r - dyn) / 2 < I.H - 1 ? l + 2 : l;
+}
+
+// gather the shifted iterate into the trial / direction buffers ...
+__global__ void __launch_bounds__(kBlock) k_shift_gather(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    const int t = lb * kBlock + threadIdx.x;
+    if (t < I.n) {
+        const int j = shift_src_var(I, t);
+        I.yt[t] = I.y[j];
+        I.dzl[t] = I.zl[j];
+        I.dzu[t] = I.zu[j];
+    }
+    if (t < I.ml) {
+        const int l = shift_src_row(I, t);
+        I.st[t] = I.s[l];
+        I.dom[t] = I.om[l];
+        I.dbe[t] = I.be[l];
+    }
+}
+
+// ... and take it as the iterate
+__global__ void __launch_bounds__(kBlock) k_shift_take(const InstPtrs* __restrict__ Ia, Space sp) {
+    int lb;
+    const InstPtrs& I = Ia[block_inst(sp, lb)];
+    const int t = lb * kBlock + threadIdx.x;
+    if (t < I.n) {
+        I.y[t] = I.yt[t];
+        I.zl[t] = I.dzl[t];
+        I.zu[t] = I.dzu[t];
+    }
+    if (t < I.ml) {
+        I.s[t] = I.st[t];
+        I.om[t] = I.dom[t];
+        I.be[t] = I.dbe[t];
+    }
+}
+
 // ---- HyKKT: conjugate gradients on S = J_c K_gamma^{-1} J_c^T --------------------------
 // After the solve K_gamma w0 = b1 + gamma_h J_c^T b2 (w0 in dy), S x = J_c w0 - b2
 // (b2 = -c) is solved by CG from x = 0; every product with S is J_c^T p, one
@@ -1335,6 +1393,12 @@ void launch_hk_cg_post(const InstPtrs* I, const IpmSpaces& S, int ninst, const D
 
 void launch_hk_finish(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
     hipLaunchKernelGGL(k_hk_finish, dim3(S.sp[kSpN].blocks), dim3(kBlock), 0, st, I, S.sp[kSpN]);
+}
+
+void launch_shift(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
+    const Space& sp = S.sp[kSpMax];
+    hipLaunchKernelGGL(k_shift_gather, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp);
+    hipLaunchKernelGGL(k_shift_take, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp);
 }
 
 void launch_hk_from_lifted(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {

@@ -122,6 +122,15 @@ k_eval_distill(const InstPtrs* __restrict__ Ia, Space sp, int src, int pred) {
         fterm[t] = C.rho * mv * mv;
         if (isR) d[2 * k] = R - V;
         else d[2 * k + 1] = V - R - F;
+        if (k >= D.hc) {   // control horizon: hold u_k = u_{k-1}
+            const int row = D.H * D.nx + 2 * (k - D.hc) + (isR ? 0 : 1);
+            c[row] = mv;
+            if (Full) {
+                const int p = jptr[row];
+                jv[p] = -1.0;
+                jv[p + 1] = 1.0;
+            }
+        }
         if (Full) {
             const double un = k < D.H - 1 ? y[(int64_t)(k + 1) * D.ns + j] : 0.0;
             grad[t] = 2.0 * C.rho * mv - (k < D.H - 1 ? 2.0 * C.rho * (un - u) : 0.0);

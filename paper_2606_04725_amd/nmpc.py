@@ -54,9 +54,10 @@ def default_options(**over) -> nmpc_options:
 
 
 def distillation_structure(N, H, dt, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0,
-                           ordering=capi.NMPC_ORDER_NESTED_DISSECTION):
+                           ordering=capi.NMPC_ORDER_NESTED_DISSECTION, control_horizon=0):
     s = nmpc_structure()
     s.ordering = ordering
+    s.control_horizon = control_horizon
     s.family = capi.NMPC_FAMILY_DISTILLATION
     s.horizon, s.dt, s.n_trays, s.alpha, s.feed_flow = H, dt, N, alpha, F
     s.move_penalty, s.x_lo, s.x_hi, s.u_lo, s.u_hi = rho, x_lo, x_hi, u_lo, u_hi
@@ -146,7 +147,8 @@ class Problem:
 
     def solve(self, warm=False, options: nmpc_options | None = None) -> nmpc_result:
         r = nmpc_result()
-        rc = capi.lib().nmpc_solve(self._h, 1 if warm else 0, None if options is None else C.byref(options),
+        w = 2 if warm == "shift" else (1 if warm else 0)
+        rc = capi.lib().nmpc_solve(self._h, w, None if options is None else C.byref(options),
                                    C.byref(r))
         _check(rc)
         self.last_result = r
@@ -279,7 +281,7 @@ class Batch:
     def solve(self, warm=False, options: nmpc_options | None = None):
         """Returns (status, [nmpc_result per instance])."""
         res = (nmpc_result * len(self.problems))()
-        rc = _check(capi.lib().nmpc_batch_solve(self._h, 1 if warm else 0,
+        rc = _check(capi.lib().nmpc_batch_solve(self._h, 2 if warm == "shift" else (1 if warm else 0),
                                                 None if options is None else C.byref(options), res))
         return rc, list(res)
 

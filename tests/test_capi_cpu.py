@@ -20,11 +20,12 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(capi.SIGNATURES)
 
 
-def _symbolic_parity(Ntr, H, alpha=2.5, ordering=N.capi.NMPC_ORDER_NESTED_DISSECTION):
-    p = N.Problem(N.distillation_structure(Ntr, H, 0.1, alpha, ordering=ordering))
+def _symbolic_parity(Ntr, H, alpha=2.5, ordering=N.capi.NMPC_ORDER_NESTED_DISSECTION, Hc=0):
+    p = N.Problem(N.distillation_structure(Ntr, H, 0.1, alpha, ordering=ordering, control_horizon=Hc))
     p.analyze()
     lib = p.export_symbolic()
-    m = DistillationOCP(Ntr, H, 0.1, alpha)
+    m = DistillationOCP(Ntr, H, 0.1, alpha, Hc=Hc)
+    assert p.m_c == m.m_c
     r, c = S.kkt_lower_pattern(m)
     nd = ordering == N.capi.NMPC_ORDER_NESTED_DISSECTION
     a = S.analyze(m.n, r, c, stages=(m.H, m.ns) if nd else None)
@@ -50,6 +51,17 @@ def _symbolic_parity(Ntr, H, alpha=2.5, ordering=N.capi.NMPC_ORDER_NESTED_DISSEC
 @pytest.mark.parametrize("Ntr,H", [(2, 1), (3, 4), (10, 20), (7, 13), (40, 100)])
 def test_symbolic_bit_exact_vs_oracle(Ntr, H):
     _symbolic_parity(Ntr, H)
+
+
+@pytest.mark.parametrize("Ntr,H,Hc", [(3, 4, 1), (10, 20, 5), (40, 100, 30)])
+def test_control_horizon_patterns_and_symbolic_vs_oracle(Ntr, H, Hc):
+    """Hold rows u_k - u_{k-1} (k >= Hc) join the equality rows; their products
+    lie inside the move penalty's pattern, so the analysis matches the oracle's
+    and equals the unheld problem's."""
+    lib = _symbolic_parity(Ntr, H, Hc=Hc)
+    free = _symbolic_parity(Ntr, H)
+    for key in ("perm", "parent", "colcount", "snode_ptr", "snode_rows"):
+        assert np.array_equal(lib[key], free[key]), key
 
 
 @pytest.mark.parametrize("Ntr,H", [(2, 1), (3, 4), (10, 20), (40, 100)])

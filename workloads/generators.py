@@ -51,6 +51,7 @@ class DistillationWorkload:
     x_hi: float = 1.0
     u_lo: float = 0.5
     u_hi: float = 5.0
+    Hc: int = 0             # control horizon in stages (0: the whole horizon)
 
     @property
     def nx(self) -> int:
@@ -115,12 +116,13 @@ def distillation_workload(name: str = "small", seed: int = 0, **over) -> Distill
     noise = rng.normal(0.0, 0.01, (max(nres, 1), nx))
     xD = over.pop("xD_sp", 0.95)
     xB = over.pop("xB_sp", 0.05)
+    Hc = over.pop("Hc", 0)
     if over:
         raise TypeError(f"unknown overrides {sorted(over)}")
     return DistillationWorkload(
         name=name, seed=seed, N=N, H=H, dt=dt, alpha=alpha, F=1.0,
         xD_sp=xD, xB_sp=xB, rho=1e-2, u_prev0=np.array([2.0, 2.5]),
-        x0=x0, resolve_noise=noise, zF_amp=amp, n_resolves=nres)
+        x0=x0, resolve_noise=noise, zF_amp=amp, n_resolves=nres, Hc=Hc)
 
 
 def batch_distillation_workloads(count: int = 64, base_seed: int = 1000):
