@@ -49,7 +49,15 @@ enum {
     NMPC_ERR_UNSUPPORTED = -7
 };
 
-enum { NMPC_FAMILY_DISTILLATION = 1, NMPC_FAMILY_HEATED_PLATE = 2 };
+/* Problem families.  DISTILLATION and HEATED_PLATE are the two workload
+ * families (Sections 4.1 and 4.2 in structure); REFLUX_COLUMN is the paper's
+ * own distillation case study of Section 4.1 as its OCP is written there:
+ * N trays (tray 1 the condenser, tray N the reboiler), feed tray N_f, fixed
+ * distillate flow D, reflux ratio u as the control, and the algebraic vapour
+ * fractions y and flows L = u D, V = L + D, S = L + F kept as variables with
+ * their own equality rows; objective dt sum_k (x_1 - xbar)^2 + w_u (u - ubar)^2
+ * with (xbar, ubar) the setpoint parameter. */
+enum { NMPC_FAMILY_DISTILLATION = 1, NMPC_FAMILY_HEATED_PLATE = 2, NMPC_FAMILY_REFLUX_COLUMN = 3 };
 
 /* Fill-reducing ordering of the analysis (eq. 19): nested dissection of the
  * family's stage structure (default: one-stage separators for the
@@ -99,6 +107,13 @@ typedef struct nmpc_structure {
      * rows, R then V per stage; 0 (or >= horizon): every stage has its own
      * control.  The plate family must leave it 0. */
     int32_t control_horizon;
+    /* reflux column (REFLUX_COLUMN; also uses n_trays, horizon, dt, alpha,
+     * feed_flow, x_lo/x_hi for x and y, u_lo/u_hi for the reflux ratio):
+     * feed tray (1-based), distillate flow D, feed composition x_f, molar
+     * holdups of condenser, trays and reboiler, weight of (u - ubar)^2, upper
+     * bound of the flows L, V, S (lower bound 0) */
+    int32_t feed_tray;
+    double distillate, feed_comp, hold_cond, hold_tray, hold_reb, u_weight, flow_hi;
 } nmpc_structure;
 
 /* Interior-point constants (the paper leaves them open; see the design notes).

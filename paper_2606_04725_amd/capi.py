@@ -15,7 +15,7 @@ NMPC_OK = 0
 NMPC_MAX_ITER, NMPC_LINESEARCH_FAIL, NMPC_REG_FAIL, NMPC_NONFINITE = 1, 2, 3, 4
 NMPC_ERR_INVALID_ARG, NMPC_ERR_BAD_ORDER, NMPC_ERR_STRUCT_MISMATCH = -1, -2, -3
 NMPC_ERR_NO_DEVICE, NMPC_ERR_HIP, NMPC_ERR_OOM, NMPC_ERR_UNSUPPORTED = -4, -5, -6, -7
-NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE = 1, 2
+NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE, NMPC_FAMILY_REFLUX_COLUMN = 1, 2, 3
 NMPC_ORDER_NESTED_DISSECTION, NMPC_ORDER_MIN_DEGREE = 0, 1
 NMPC_KKT_LIFTED, NMPC_KKT_HYKKT = 0, 1
 
@@ -26,7 +26,10 @@ class nmpc_structure(C.Structure):
                 ("move_penalty", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("u_lo", C.c_double), ("u_hi", C.c_double),
                 ("grid", C.c_int32), ("t_hi", C.c_double), ("c_lo", C.c_double), ("c_hi", C.c_double),
-                ("cond_slope", C.c_double), ("ordering", C.c_int32), ("control_horizon", C.c_int32)]
+                ("cond_slope", C.c_double), ("ordering", C.c_int32), ("control_horizon", C.c_int32),
+                ("feed_tray", C.c_int32), ("distillate", C.c_double), ("feed_comp", C.c_double),
+                ("hold_cond", C.c_double), ("hold_tray", C.c_double), ("hold_reb", C.c_double),
+                ("u_weight", C.c_double), ("flow_hi", C.c_double)]
 
 
 class nmpc_options(C.Structure):

@@ -218,7 +218,8 @@ nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
         std::string err;
         if (!nmpc::build_structure(*s, h->impl.st, err)) {
             delete h;
-            const bool known = s->family == NMPC_FAMILY_DISTILLATION || s->family == NMPC_FAMILY_HEATED_PLATE;
+            const bool known = s->family == NMPC_FAMILY_DISTILLATION || s->family == NMPC_FAMILY_HEATED_PLATE ||
+                               s->family == NMPC_FAMILY_REFLUX_COLUMN;
             return fail(known ? NMPC_ERR_INVALID_ARG : NMPC_ERR_UNSUPPORTED, err);
         }
         const auto& st = h->impl.st;
@@ -229,6 +230,9 @@ nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
         if (s->family == NMPC_FAMILY_DISTILLATION) {
             h->impl.setpoint = {0.95, 0.05};
             h->impl.u_prev = {2.0, 2.5};
+        } else if (s->family == NMPC_FAMILY_REFLUX_COLUMN) {   // the setpoint of Table 1, reflux ratio 2
+            h->impl.setpoint = {0.8958, 2.51459};
+            h->impl.u_prev = {2.0};
         } else {                               // plate: zero field, zero target, mid-range heaters
             h->impl.x0.assign(st.nx, 0.0);
             h->impl.setpoint.assign(st.nx, 0.0);

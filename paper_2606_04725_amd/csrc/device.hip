@@ -108,7 +108,7 @@ struct Batch {
     Group* groups = nullptr;
     int4* tasks = nullptr;
     std::vector<BLaunch> fac, fwd, bwd, fwd_rest;
-    bool has_distill = false, has_plate = false;
+    bool has_distill = false, has_plate = false, has_reflux = false;
     int* running = nullptr;        // device: instances running, instances waiting for corrections,
                                    // instances whose HyKKT conjugate gradients run
     int* hrunning = nullptr;       // pinned copy
@@ -249,6 +249,7 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
         hI[i].ctl = B->ctl + i;
         if (hI[i].family == NMPC_FAMILY_DISTILLATION) B->has_distill = true;
         if (hI[i].family == NMPC_FAMILY_HEATED_PLATE) B->has_plate = true;
+        if (hI[i].family == NMPC_FAMILY_REFLUX_COLUMN) B->has_reflux = true;
     }
     BTRY(upload(B->allocs, B->dI, hI));
     // index spaces
@@ -352,6 +353,7 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
 void eval(Batch& B, bool full, int src, int pred) {
     if (B.has_distill) launch_eval_distill(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
     if (B.has_plate) launch_eval_plate(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
+    if (B.has_reflux) launch_eval_reflux(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
 }
 
 void run_launch(Batch& B, const BLaunch& L, int pred, double eta_force, int which) {
@@ -599,7 +601,16 @@ nmpc_status device_init(Problem& p, std::string& err) {
     I.dc.alpha = s.alpha;
     I.dc.F = s.feed_flow;
     I.dc.rho = s.move_penalty;
-    if (st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
+    I.ns = st.n / st.H;
+    I.rps = st.nx;
+    if (st.desc.family == NMPC_FAMILY_REFLUX_COLUMN) {
+        I.rd = RefluxDims{s.n_trays, s.feed_tray, 2 * s.n_trays + 4, 2 * s.n_trays + 3, s.horizon};
+        I.rc = RefluxConst{s.dt, s.alpha, s.feed_flow, s.distillate, s.feed_comp, s.hold_cond, s.hold_tray,
+                           s.hold_reb, s.u_weight};
+        I.rps = I.rd.rps;
+        I.nsp = 2;
+        I.ntr = 0;
+    } else if (st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
         I.pd.G = s.grid;
         I.pd.nx = s.grid * s.grid;
         I.pd.ns = I.pd.nx + 16;
@@ -1635,7 +1646,7 @@ NoAllocLayout noalloc_layout(const Problem& p) {
     const Structure& st = p.st;
     const size_t n = (size_t)st.n, m = (size_t)(st.m_c + st.m_d);
     const size_t nsp = st.desc.family == NMPC_FAMILY_HEATED_PLATE ? (size_t)st.nx : 2;
-    const size_t ntr = st.desc.family == NMPC_FAMILY_HEATED_PLATE ? 0 : (size_t)st.H;
+    const size_t ntr = st.desc.family == NMPC_FAMILY_DISTILLATION ? (size_t)st.H : 0;
     const size_t nout = (size_t)st.nx + nsp + ntr + (size_t)st.nu;
     const size_t nuv = std::max<size_t>((size_t)p.sym.stored_uv, 1);
     NoAllocLayout L{};

@@ -6,6 +6,7 @@
 
 #include "distill_layout.h"
 #include "plate_layout.h"
+#include "reflux_layout.h"
 #include "internal.h"
 
 namespace nmpc {
@@ -174,6 +175,97 @@ static bool build_plate(const nmpc_structure& s, Structure& st, std::string& err
     return true;
 }
 
+static bool build_reflux(const nmpc_structure& s, Structure& st, std::string& err) {
+    if (s.n_trays < 4 || s.feed_tray < 2 || s.feed_tray > s.n_trays - 2 || s.horizon < 1 || !(s.dt > 0) ||
+        !(s.alpha > 1.0) || !(s.feed_flow > 0) || !(s.distillate > 0) || !(s.distillate < s.feed_flow) ||
+        !(s.hold_cond > 0) || !(s.hold_tray > 0) || !(s.hold_reb > 0) || !(s.u_weight >= 0) ||
+        !(s.x_lo < s.x_hi) || !(s.u_lo < s.u_hi) || !(s.flow_hi > 0) || s.control_horizon != 0) {
+        err = "reflux column: need n_trays >= 4, 2 <= feed_tray <= n_trays - 2, horizon >= 1, dt > 0, alpha > 1, "
+              "0 < distillate < feed_flow, positive holdups, u_weight >= 0, valid bounds, control_horizon 0";
+        return false;
+    }
+    RefluxDims D{s.n_trays, s.feed_tray, 2 * s.n_trays + 4, 2 * s.n_trays + 3, s.horizon};
+    const int N = D.N;
+    st.nx = N;
+    st.nu = 1;
+    st.H = D.H;
+    st.n = D.H * D.ns;
+    st.m_c = D.H * D.rps;
+    st.m_d = 0;
+    st.jptr.assign(st.m_c + 1, 0);
+    st.jcol.clear();
+    const int iu = N, iL = 2 * N + 1, iV = 2 * N + 2, iS = 2 * N + 3;
+    auto x = [&](int i) { return i - 1; };
+    auto y = [&](int i) { return N + i; };
+    for (int k = 0; k < D.H; ++k) {
+        const int b = k * D.ns;
+        for (int i = 1; i <= N; ++i) {
+            const int row = k * D.rps + i - 1;
+            if (k > 0) st.jcol.push_back((k - 1) * D.ns + x(i));
+            std::vector<int> cols;
+            if (i == 1) cols = {x(1), y(2), iV};
+            else if (i < D.Nf) cols = {x(i - 1), x(i), y(i), y(i + 1), iL, iV};
+            else if (i == D.Nf) cols = {x(i - 1), x(i), y(i), y(i + 1), iL, iV, iS};
+            else if (i < N) cols = {x(i - 1), x(i), y(i), y(i + 1), iV, iS};
+            else cols = {x(N - 1), x(N), y(N), iV, iS};
+            for (int c : cols) st.jcol.push_back(b + c);
+            st.jptr[row + 1] = (int)st.jcol.size();
+            if (st.jptr[row + 1] - st.jptr[row] != rx_tray_nnz(D, k, i)) {
+                err = "internal: reflux row layout mismatch";
+                return false;
+            }
+        }
+        for (int i = 1; i <= N; ++i) {
+            const int row = k * D.rps + N + i - 1;
+            st.jcol.push_back(b + x(i));
+            st.jcol.push_back(b + y(i));
+            st.jptr[row + 1] = (int)st.jcol.size();
+        }
+        const int flow[3][2] = {{iu, iL}, {iL, iV}, {iL, iS}};
+        for (int r = 0; r < 3; ++r) {
+            st.jcol.push_back(b + flow[r][0]);
+            st.jcol.push_back(b + flow[r][1]);
+            st.jptr[k * D.rps + 2 * N + r + 1] = (int)st.jcol.size();
+        }
+    }
+    st.jrow.resize(st.jcol.size());
+    for (int r = 0; r < st.m_c; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) st.jrow[p] = r;
+    const int ws = rx_wstage(D);
+    st.wrow.assign((size_t)ws * D.H, 0);
+    st.wcol.assign((size_t)ws * D.H, 0);
+    for (int k = 0; k < D.H; ++k) {
+        const int o = k * ws, b = k * D.ns;
+        auto put = [&](int slot, int r, int c) {
+            st.wrow[o + slot] = b + r;
+            st.wcol[o + slot] = b + c;
+        };
+        for (int i = 1; i <= N; ++i) put(i - 1, x(i), x(i));
+        put(N, iu, iu);
+        for (int j = 1; j < D.Nf; ++j) put(N + j, iL, x(j));
+        for (int j = D.Nf; j < N; ++j) put(N + j, iS, x(j));
+        put(2 * N, iV, x(1));
+        for (int j = 2; j <= N; ++j) put(2 * N + j - 1, iV, y(j));
+    }
+    st.lb.assign(st.n, 0.0);
+    st.ub.assign(st.n, 0.0);
+    for (int k = 0; k < D.H; ++k)
+        for (int j = 0; j < D.ns; ++j) {
+            const int v = k * D.ns + j;
+            if (j == iu) {
+                st.lb[v] = s.u_lo;
+                st.ub[v] = s.u_hi;
+            } else if (j >= iL) {
+                st.lb[v] = 0.0;
+                st.ub[v] = s.flow_hi;
+            } else {
+                st.lb[v] = s.x_lo;
+                st.ub[v] = s.x_hi;
+            }
+        }
+    return true;
+}
+
 bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) {
     out = Structure();
     out.desc = s;
@@ -186,6 +278,8 @@ bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) 
         ok = build_distillation(s, out, err);
     } else if (s.family == NMPC_FAMILY_HEATED_PLATE) {
         ok = build_plate(s, out, err);
+    } else if (s.family == NMPC_FAMILY_REFLUX_COLUMN) {
+        ok = build_reflux(s, out, err);
     } else {
         err = "unsupported problem family";
         return false;

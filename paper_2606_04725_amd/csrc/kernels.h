@@ -14,6 +14,7 @@
 #include "../../include/nmpc.h"
 #include "distill_layout.h"
 #include "plate_layout.h"
+#include "reflux_layout.h"
 
 namespace nmpc {
 
@@ -118,6 +119,9 @@ struct InstPtrs {
     DistillConst dc;
     PlateDims pd;
     PlateConst pc;
+    RefluxDims rd;
+    RefluxConst rc;
+    int ns, rps;        // variables and (dynamics block) equality rows per stage
     int nsp, ntr;       // setpoint and disturbance-trajectory lengths of the family
     // structure
     const int32_t *jptr, *jcol, *jt_ptr, *jt_slot, *jt_row;
@@ -216,6 +220,7 @@ enum EvalSrc : int { kSrcIter = 0, kSrcTrial = 1, kSrcUser = 2 };
 // terms; otherwise c, d and objective terms.  Space kSpN, one lane per variable.
 void launch_eval_distill(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st);
 void launch_eval_plate(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st);
+void launch_eval_reflux(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st);
 
 // ---- interior-point vector kernels and decisions (kernels_ipm.hip) ----------------
 struct IpmSpaces {

@@ -902,14 +902,31 @@ __global__ void __launch_bounds__(kBlock) k_adj_seed(const InstPtrs* __restrict_
     I.adj_rhs[j] = v;
 }
 
-// cold start, first guess: every stage holds the measured state and the last control
+// cold start, first guess: every stage holds the measured state and the last
+// control (the reflux column also its equilibrium vapour and the flows)
 __global__ void __launch_bounds__(kBlock) k_cold_guess(const InstPtrs* __restrict__ Ia, Space sp) {
     int lb;
     const InstPtrs& I = Ia[block_inst(sp, lb)];
     const int j = lb * kBlock + threadIdx.x;
     if (j >= I.n) return;
-    const int ns = I.nx + I.nu, r = j % ns;
-    I.y[j] = r < I.nx ? I.x0[r] : I.uprev[r - I.nx];
+    const int r = j % I.ns;
+    double v;
+    if (r < I.nx) {
+        v = I.x0[r];
+    } else if (r < I.nx + I.nu) {
+        v = I.uprev[r - I.nx];
+    } else {   // reflux column: y_i = phi(x0_i), then L = u D, V = L + D, S = L + F
+        const RefluxConst& C = I.rc;
+        const int N = I.rd.N;
+        if (r <= 2 * N) {
+            const double x = I.x0[r - N - 1];
+            v = C.alpha * x / (1.0 + (C.alpha - 1.0) * x);
+        } else {
+            const double L = I.uprev[0] * C.D;
+            v = r == 2 * N + 1 ? L : (r == 2 * N + 2 ? L + C.D : L + C.F);
+        }
+    }
+    I.y[j] = v;
 }
 
 __device__ inline double row_dot(const InstPtrs& I, int r, const double* __restrict__ v) {
@@ -1032,14 +1049,51 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_plate(const InstPtrs* __r
     out[D.nx + p] = 2.0 * sw - 2.0 * seed_obj * sd;
 }
 
+// Parameter contractions for the reflux column (one block): the objective is
+// dt sum_k (x_{k,1} - xbar)^2 + w_u (u_k - ubar)^2, so
+//   x0:     lam on the stage-1 tray rows
+//   xbar:   2 dt sum_k w(x_{k,1}) - 2 dt seed_obj sum_k (x_{k,1} - xbar)
+//   ubar:   2 dt w_u sum_k w(u_k) - 2 dt w_u seed_obj sum_k (u_k - ubar)
+//   u_prev: 0 (it enters no function of the problem)
+// out = [x0 (N) | setpoint (2) | u_prev (1)]
+__global__ void __launch_bounds__(kBlock) k_adj_gather_reflux(const InstPtrs* __restrict__ Ia) {
+    __shared__ double sh[kMaxQ * kWaves];
+    __shared__ double tot[4];
+    const InstPtrs& I = Ia[0];
+    const RefluxDims D = I.rd;
+    const RefluxConst C = I.rc;
+    const double seed_obj = I.adj_seed[I.nu];
+    const double xbar = I.setp[0], ubar = I.setp[1];
+    double* out = I.adj_out;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < D.N; t += kBlock) out[t] = I.adj_lam[t];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = tid; k < D.H; k += kBlock) {
+        const int64_t o = (int64_t)k * D.ns;
+        a[0] += I.adj_w[o];
+        a[1] += I.y[o] - xbar;
+        a[2] += I.adj_w[o + D.N];
+        a[3] += I.y[o + D.N] - ubar;
+    }
+    constexpr Ops ops{4, {kSum, kSum, kSum, kSum}};
+    const double r = block_reduce(a, ops, sh);
+    if (tid < 4) tot[tid] = r;
+    __syncthreads();
+    if (tid == 0) {
+        out[D.N] = 2.0 * C.dt * tot[0] - 2.0 * C.dt * seed_obj * tot[1];
+        out[D.N + 1] = 2.0 * C.dt * C.wu * tot[2] - 2.0 * C.dt * C.wu * seed_obj * tot[3];
+        out[D.N + 2] = 0.0;
+    }
+}
+
 // ---- shifted warm start -----------------------------------------------------------------
 // Stage k takes stage k + 1's values, the last stage keeps its own: variables by
-// stages of nx + nu; lifted rows [plus | minus | inequality] with the dynamics
-// rows by stages of nx, the hold rows of the control horizon by held stages of
-// two, the inequality rows by stages of two.
+// stages of ns; lifted rows [plus | minus | inequality] with the stage-major
+// equality rows by stages of rps, the hold rows of the control horizon by held
+// stages of two, the inequality rows by stages of two.
 __device__ inline int shift_src_var(const InstPtrs& I, int j) {
-    const int ns = I.nx + I.nu, k = j / ns;
-    return k < I.H - 1 ? j + ns : j;
+    const int k = j / I.ns;
+    return k < I.H - 1 ? j + I.ns : j;
 }
 
 __device__ inline int shift_src_row(const InstPtrs& I, int l) {
@@ -1048,8 +1102,8 @@ __device__ inline int shift_src_row(const InstPtrs& I, int l) {
         return k < I.H - 1 ? l + 2 : l;
     }
     const int r = l >= I.mc ? l - I.mc : l;
-    const int dyn = I.H * I.nx;
-    if (r < dyn) return r / I.nx < I.H - 1 ? l + I.nx : l;
+    const int dyn = I.H * I.rps;
+    if (r < dyn) return r / I.rps < I.H - 1 ? l + I.rps : l;
     const int hc = I.family == NMPC_FAMILY_DISTILLATION ? I.dd.hc : I.H;
     return hc + (r - dyn) / 2 < I.H - 1 ? l + 2 : l;
 }
@@ -1406,7 +1460,9 @@ void launch_hk_from_lifted(const InstPtrs* I, const IpmSpaces& S, hipStream_t st
 }
 
 void launch_adj_gather(const InstPtrs* I, int family, int nx, hipStream_t st) {
-    if (family == NMPC_FAMILY_HEATED_PLATE)
+    if (family == NMPC_FAMILY_REFLUX_COLUMN)
+        hipLaunchKernelGGL(k_adj_gather_reflux, dim3(1), dim3(kBlock), 0, st, I);
+    else if (family == NMPC_FAMILY_HEATED_PLATE)
         hipLaunchKernelGGL(k_adj_gather_plate, dim3((nx + kBlock - 1) / kBlock), dim3(kBlock), 0, st, I);
     else
         hipLaunchKernelGGL(k_adj_gather_distill, dim3(1), dim3(kBlock), 0, st, I);

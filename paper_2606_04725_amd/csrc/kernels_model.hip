@@ -234,7 +234,152 @@ k_eval_plate(const InstPtrs* __restrict__ Ia, Space sp, int src, int pred) {
     }
 }
 
+// Reflux column of the case study: one lane per variable of a stage.  A tray
+// lane (x_i) evaluates tray i's implicit-Euler row and equilibrium row, their
+// Jacobian rows, and the Hessian slots (x_i, x_i), (L, x_i) or (S, x_i) and, for
+// tray 1, (V, x_1); a y_i lane the slot (V, y_i); the u, L and V lanes one flow
+// row each (L - u D, V - L - D, S - L - F).  Tray rows are c = x_i - x_{i,prev}
+// - dt f_i with f the balances of the case study (condenser, rectifying trays,
+// feed tray, stripping trays, reboiler); a second derivative of row i's c is
+// -dt lam_i times that of f_i, w(i) = -dt lam_i / A_i below.
+template <bool Full>
+__global__ void __launch_bounds__(kBlock)
+k_eval_reflux(const InstPtrs* __restrict__ Ia, Space sp, int src, int pred) {
+    int lb;
+    const int inst = block_inst(sp, lb);
+    const InstPtrs& I = Ia[inst];
+    if (I.family != NMPC_FAMILY_REFLUX_COLUMN || !ctl_active(I.ctl, pred)) return;
+    const RefluxDims D = I.rd;
+    const RefluxConst C = I.rc;
+    const int t = lb * kBlock + threadIdx.x;
+    if (t >= D.H * D.ns) return;
+    const double* __restrict__ y = src == kSrcIter ? I.y : I.yt;
+    const double* __restrict__ om = src == kSrcUser ? I.dom : I.om;
+    const int N = D.N, Nf = D.Nf, mc = I.mc;
+    const int k = t / D.ns, j = t - k * D.ns;
+    const double* Y = y + (int64_t)k * D.ns;
+    const double u = Y[N], L = Y[2 * N + 1], V = Y[2 * N + 2], S = Y[2 * N + 3];
+    auto X = [&](int i) { return Y[i - 1]; };          // tray i, 1-based
+    auto Yv = [&](int i) { return Y[N + i]; };
+    const int row0 = k * D.rps;
+    // equality multiplier of tray row i of this stage
+    auto lam = [&](int i) { return om[row0 + i - 1] - om[mc + row0 + i - 1]; };
+    auto hold = [&](int i) { return i == 1 ? C.Ac : (i == N ? C.Ar : C.At); };
+    auto w = [&](int i) { return -C.dt * lam(i) / hold(i); };
+    double* wv = I.wv + (int64_t)k * rx_wstage(D);
+    double ft = 0.0, g = 0.0;
+    if (j < N) {
+        const int i = j + 1;
+        const double xi = X(i);
+        const double xprev = k > 0 ? y[(int64_t)(k - 1) * D.ns + j] : I.x0[j];
+        // balance f_i and its partials in the row's column order (after x_prev)
+        double f, pv[7];
+        int np = 0;
+        if (i == 1) {
+            f = V * (Yv(2) - xi) / C.Ac;
+            pv[np++] = -V / C.Ac;                         // x_1
+            pv[np++] = V / C.Ac;                          // y_2
+            pv[np++] = (Yv(2) - xi) / C.Ac;               // V
+        } else if (i < N) {
+            const double xm = X(i - 1), yi = Yv(i), yq = Yv(i + 1);
+            const double lin = i <= Nf ? L : S;           // liquid from above
+            const double lout = i < Nf ? L : S;           // liquid leaving
+            f = (lin * xm - lout * xi - V * (yi - yq) + (i == Nf ? C.F * C.xf : 0.0)) / C.At;
+            pv[np++] = lin / C.At;                        // x_{i-1}
+            pv[np++] = -lout / C.At;                      // x_i
+            pv[np++] = -V / C.At;                         // y_i
+            pv[np++] = V / C.At;                          // y_{i+1}
+            if (i < Nf) {
+                pv[np++] = (xm - xi) / C.At;              // L
+                pv[np++] = -(yi - yq) / C.At;             // V
+            } else if (i == Nf) {
+                pv[np++] = xm / C.At;                     // L
+                pv[np++] = -(yi - yq) / C.At;             // V
+                pv[np++] = -xi / C.At;                    // S
+            } else {
+                pv[np++] = -(yi - yq) / C.At;             // V
+                pv[np++] = (xm - xi) / C.At;              // S
+            }
+        } else {
+            const double xm = X(N - 1), yN = Yv(N);
+            f = (S * xm - (C.F - C.D) * xi - V * yN) / C.Ar;
+            pv[np++] = S / C.Ar;                          // x_{N-1}
+            pv[np++] = -(C.F - C.D) / C.Ar;               // x_N
+            pv[np++] = -V / C.Ar;                         // y_N
+            pv[np++] = -yN / C.Ar;                        // V
+            pv[np++] = xm / C.Ar;                         // S
+        }
+        const int row = row0 + j;
+        I.c[row] = xi - xprev - C.dt * f;
+        const double a = C.alpha, gg = 1.0 + (a - 1.0) * xi;
+        const int rv = row0 + N + j;
+        I.c[rv] = Yv(i) - a * xi / gg;
+        if (i == 1) {
+            ft = C.dt * (xi - I.setp[0]) * (xi - I.setp[0]);
+            g = 2.0 * C.dt * (xi - I.setp[0]);
+        }
+        if (Full) {
+            double* jr = I.jv + I.jptr[row];
+            int q = 0;
+            if (k > 0) jr[q++] = -1.0;
+            const int own = i == 1 ? 0 : 1;              // position of x_i among the partials
+            for (int e = 0; e < np; ++e) jr[q++] = -C.dt * pv[e] + (e == own ? 1.0 : 0.0);
+            double* je = I.jv + I.jptr[rv];
+            je[0] = -a / (gg * gg);
+            je[1] = 1.0;
+            // Hessian: equilibrium curvature (and the objective on tray 1)
+            const double lv = om[rv] - om[mc + rv];
+            wv[j] = lv * 2.0 * a * (a - 1.0) / (gg * gg * gg) + (i == 1 ? 2.0 * C.dt : 0.0);
+            if (i < Nf) {            // (L, x_i): +w(i+1) from tray i+1, -w(i) from tray i (2 <= i)
+                wv[N + i] = w(i + 1) - (i >= 2 ? w(i) : 0.0);
+            } else if (i < N) {      // (S, x_i): -w(i) from tray i, +w(i+1) from tray i+1
+                wv[N + i] = -w(i) + w(i + 1);
+            }
+            if (i == 1) wv[2 * N] = -w(1);   // (V, x_1)
+        }
+    } else if (j == N) {
+        I.c[row0 + 2 * N] = L - u * C.D;
+        ft = C.dt * C.wu * (u - I.setp[1]) * (u - I.setp[1]);
+        g = 2.0 * C.dt * C.wu * (u - I.setp[1]);
+        if (Full) {
+            double* jr = I.jv + I.jptr[row0 + 2 * N];
+            jr[0] = -C.D;
+            jr[1] = 1.0;
+            wv[N] = 2.0 * C.dt * C.wu;
+        }
+    } else if (j <= 2 * N) {
+        const int i = j - N;
+        if (Full && i >= 2) {        // (V, y_i): +w(i-1) from tray i-1, -w(i) from tray i
+            wv[2 * N + i - 1] = w(i - 1) - w(i);
+        }
+    } else if (j == 2 * N + 1) {
+        I.c[row0 + 2 * N + 1] = V - L - C.D;
+        if (Full) {
+            double* jr = I.jv + I.jptr[row0 + 2 * N + 1];
+            jr[0] = -1.0;
+            jr[1] = 1.0;
+        }
+    } else if (j == 2 * N + 2) {
+        I.c[row0 + 2 * N + 2] = S - L - C.F;
+        if (Full) {
+            double* jr = I.jv + I.jptr[row0 + 2 * N + 2];
+            jr[0] = -1.0;
+            jr[1] = 1.0;
+        }
+    }
+    I.fterm[t] = ft;
+    if (Full) I.grad[t] = g;
+}
+
 }  // namespace
+
+void launch_eval_reflux(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st) {
+    if (sp.blocks <= 0) return;
+    if (full)
+        hipLaunchKernelGGL(k_eval_reflux<true>, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp, src, pred);
+    else
+        hipLaunchKernelGGL(k_eval_reflux<false>, dim3(sp.blocks), dim3(kBlock), 0, st, I, sp, src, pred);
+}
 
 void launch_eval_plate(bool full, int src, int pred, const InstPtrs* I, const Space& sp, hipStream_t st) {
     if (sp.blocks <= 0) return;

@@ -5,7 +5,8 @@
 //     degree: exact, on the elimination graph of the condensed matrix pattern
 //     (true degrees, no mass elimination, no element absorption; ties go to the
 //     smallest original index).  Nested dissection, the default: for the
-//     distillation family by stages (a range of fewer than three stages keeps
+//     distillation families (the workload column and the reflux column of the
+//     case study) by stages (a range of fewer than three stages keeps
 //     its order, otherwise its middle stage t0 + (t1 - t0 - 1) / 2 separates
 //     it: left range, right range, separator stage); for the plate family on
 //     the (stage x grid) lattice of its condensed matrix: a box of lattice
@@ -363,7 +364,8 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
     // ---- 1. fill-reducing ordering ----------------------------------------------
     std::vector<int32_t> perm_md;
-    if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_DISTILLATION) {
+    if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION &&
+        (st.desc.family == NMPC_FAMILY_DISTILLATION || st.desc.family == NMPC_FAMILY_REFLUX_COLUMN)) {
         perm_md = stage_nd(st.H, n / st.H);
     } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
         LatticeNd nd(n, st.H, st.desc.grid, n / st.H, ent);

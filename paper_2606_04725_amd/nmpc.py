@@ -64,6 +64,18 @@ def distillation_structure(N, H, dt, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0,
     return s
 
 
+def reflux_structure(H, dt=2.0, N=32, Nf=17, D=0.2, F=0.4, alpha=1.6, xf=0.5, Ac=0.5, At=0.25, Ar=1.0, w_u=0.1,
+                     u_lo=1.0, u_hi=5.0, flow_hi=10.0, ordering=capi.NMPC_ORDER_NESTED_DISSECTION):
+    """The case-study column of Section 4.1 (defaults: Table 1)."""
+    s = nmpc_structure()
+    s.ordering = ordering
+    s.family = capi.NMPC_FAMILY_REFLUX_COLUMN
+    s.horizon, s.dt, s.n_trays, s.feed_tray, s.alpha, s.feed_flow = H, dt, N, Nf, alpha, F
+    s.distillate, s.feed_comp, s.hold_cond, s.hold_tray, s.hold_reb = D, xf, Ac, At, Ar
+    s.u_weight, s.x_lo, s.x_hi, s.u_lo, s.u_hi, s.flow_hi = w_u, 0.0, 1.0, u_lo, u_hi, flow_hi
+    return s
+
+
 def plate_structure(G, H, dt, cond_slope=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0,
                     ordering=capi.NMPC_ORDER_NESTED_DISSECTION):
     s = nmpc_structure()
@@ -191,10 +203,7 @@ class Problem:
         """Vector-Jacobian product of seed_u1 . u1* + seed_obj f* with respect to
         the parameters; returns (status, dict of gradients).  Distillation:
         setpoint (xD*, xB*), traj zF[H]; plate: setpoint = target field, no traj."""
-        plate = self.family == capi.NMPC_FAMILY_HEATED_PLATE
-        n_setpoint = self.nx if plate else 2
-        n_traj = 0 if plate else self.horizon
-        gx, gs, gt, gu = np.empty(self.nx), np.empty(n_setpoint), np.empty(n_traj), np.empty(self.nu)
+        gx, gs, gt, gu = np.empty(self.nx), np.empty(self.n_setpoint), np.empty(self.n_traj), np.empty(self.nu)
         rc = _check(capi.lib().nmpc_adjoint(self._h, _dp(_f64(seed_u1, self.nu)), float(seed_obj), _dp(gx),
                                             _dp(gs), _dp(gt), _dp(gu)))
         return rc, dict(x0=gx, setpoint=gs, traj=gt, u_prev=gu)
@@ -208,7 +217,7 @@ class Problem:
 
     @property
     def n_traj(self):
-        return 0 if self.family == capi.NMPC_FAMILY_HEATED_PLATE else self.horizon
+        return self.horizon if self.family == capi.NMPC_FAMILY_DISTILLATION else 0
 
     def set_parameters_dev(self, x0, setpoint=0, traj=0, u_prev=0, stream=0):
         _check(capi.lib().nmpc_set_parameters_dev(self._h, x0 or None, setpoint or None, traj or None,

@@ -10,5 +10,7 @@ from .generators import (  # noqa: F401
     batch_distillation_workloads,
     PlateWorkload,
     plate_workload,
+    RefluxWorkload,
+    reflux_workload,
     WORKLOADS,
 )

@@ -197,3 +197,37 @@ WORKLOADS = {
     "plate_large": lambda seed=0, **kw: plate_workload("large", seed, **kw),
     "plate_adjoint": lambda seed=0, **kw: plate_workload("adjoint", seed, **kw),
 }
+
+
+@dataclass
+class RefluxWorkload:
+    """The distillation case study of Section 4.1 (Table 1): 32 trays, feed on
+    tray 17, reflux-ratio control, horizon 180 s of 2 s stages, closed loop
+    from t = 0 to 300 s (150 NMPC steps), plant = the model."""
+    N: int = 32
+    Nf: int = 17
+    D: float = 0.2
+    F: float = 0.4
+    alpha: float = 1.6
+    xbar: float = 0.8958
+    ubar: float = 2.51459
+    xf: float = 0.5
+    Ac: float = 0.5
+    At: float = 0.25
+    Ar: float = 1.0
+    w_u: float = 0.1
+    dt: float = 2.0
+    H: int = 90
+    n_steps: int = 150
+    x0: np.ndarray = None   # first measured tray compositions (condenser first)
+    u_prev0: float = 2.0    # reflux ratio before the first solve
+
+
+def reflux_workload(**over) -> RefluxWorkload:
+    """The case study's parameters.  The paper gives no initial state; the
+    loop starts from a linear composition profile, 0.85 at the condenser to
+    0.12 at the reboiler, away from the steady state the controller targets."""
+    w = RefluxWorkload(**over)
+    if w.x0 is None:
+        w.x0 = np.linspace(0.85, 0.12, w.N)
+    return w
