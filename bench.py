@@ -254,6 +254,79 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return {"bytes": 2 * n * 8, "ms": ms, "gbps": 2 * n * 8 / (ms * 1e-3) / 1e9}
 
 
+PAPER_CASE_STUDY_TOTAL_S = 3.00   # Section 4.3: distillation, WS+PU, RTX 6000 Ada (context only)
+
+
+def run_case_study(N, eager=False):
+    """The paper's distillation case study (Section 4.1, Table 1): 32 trays,
+    reflux-ratio control, horizon 90 stages of 2 s, closed loop of 150 NMPC
+    steps from t = 0 to 300 s, plant = the model, symbolic analysis once and
+    warm starts (the paper's WS+PU configuration).  Timed end to end: the
+    analysis, the cold first solve and every step (parameter upload, solve,
+    first-stage download)."""
+    from workloads import reflux_workload
+    w = reflux_workload()
+    opts = N.default_options(graph=0 if eager else 1)
+    t0 = time.perf_counter()
+    p = N.Problem(N.reflux_structure(w.H, dt=w.dt))
+    p.analyze()
+    t_an = time.perf_counter() - t0
+    x0, up = w.x0.copy(), np.array([w.u_prev0])
+    lat, iters, bad = [], 0, 0
+    for k in range(w.n_steps):
+        t = time.perf_counter()
+        p.set_parameters(x0, setpoint=[w.xbar, w.ubar], u_prev=up)
+        r = p.solve(warm=k > 0, options=opts)
+        u1, x1 = p.first_stage()
+        lat.append((time.perf_counter() - t) * 1e3)
+        iters += r.iters
+        bad += r.status != 0
+        x0, up = x1, u1
+    total = time.perf_counter() - t0
+    _progress(f"case study: {w.n_steps} NMPC steps in {total:.2f} s")
+    return {"workload": f"distillation case study of Section 4.1 (Table 1): {w.N} trays, feed tray {w.Nf}, "
+                        f"reflux-ratio control, horizon {w.H} x {w.dt} s, {w.n_steps} NMPC steps, plant = model",
+            "n": p.n, "total_s": total, "analyze_ms": t_an * 1e3, "first_solve_ms": lat[0],
+            "p50_step_ms": _percentile(lat[1:], 50), "p99_step_ms": _percentile(lat[1:], 99),
+            "iters_total": iters, "nonzero_status": bad, "final_x1": float(x0[0]), "final_u": float(up[0]),
+            "paper_total_s": PAPER_CASE_STUDY_TOTAL_S,
+            "paper_hardware": "NVIDIA RTX 6000 Ada, MadNLP + cuDSS, WS+PU (context only)"}
+
+
+def run_mismatch(N, steps=30, seed=0, factor=1.08, eager=False):
+    """Closed loop of the small column against a plant whose relative
+    volatility is the model's times ``factor`` (plant-model mismatch), beside
+    the same loop with a matched plant: warm re-solves per step, measured
+    (not predicted) next state, tracking offsets at the end."""
+    from paper_2606_04725_amd.plant import DistillationPlant
+    from workloads import distillation_workload
+    w = distillation_workload("small", seed)
+    opts = N.default_options(graph=0 if eager else 1)
+    out = {"workload": f"distillation 10 trays, horizon 20, {steps} closed-loop steps, plant alpha = model alpha "
+                       f"x {factor} vs matched"}
+    for name, alpha in (("matched", w.alpha), ("mismatched", factor * w.alpha)):
+        plant = DistillationPlant(w.N, alpha, w.dt, F=w.F)
+        p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+        p.analyze()
+        x, up = w.x0.copy(), w.u_prev0.copy()
+        lat, iters, bad = [], 0, 0
+        for k in range(steps):
+            t = time.perf_counter()
+            p.set_parameters(x, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(k), u_prev=up)
+            r = p.solve(warm=k > 0, options=opts)
+            u1, _ = p.first_stage()
+            lat.append((time.perf_counter() - t) * 1e3)
+            iters += r.iters
+            bad += r.status != 0
+            x = plant.step(x, u1, zF=float(w.zF(k)[0]))
+            up = u1
+        out[name] = {"p50_resolve_ms": _percentile(lat[1:], 50), "iters_per_resolve": iters / steps,
+                     "nonzero_status": bad, "final_top_offset": float(x[0] - w.xD_sp),
+                     "final_bottom_offset": float(x[-1] - w.xB_sp)}
+    _progress("plant-model mismatch loop")
+    return out
+
+
 def run_batched(N, count=64, base_seed=1000, rounds=10, eager=False):
     """Batched form: 64 ragged distillation instances (trays U{20..60}, horizons
     U{40..120}, alpha U(2,3), own setpoints and noise), one cold solve, then
@@ -485,6 +558,8 @@ def main(argv=None):
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the analyze-once/every-solve and warm/cold ablation")
     ap.add_argument("--ablation-only", action="store_true", help="only run the ablation")
+    ap.add_argument("--case-study-only", action="store_true",
+                    help="only run the paper's distillation case study (150-step closed loop)")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
     ap.add_argument("--plate-case", choices=("plain", "adjoint", "both"), default="both",
                     help="with --plate-only: the 32x32x50 plate, the differentiated plate, or both")
@@ -513,6 +588,9 @@ def main(argv=None):
     if not torch.cuda.is_available() or not N.device_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if a.case_study_only:
+        print(json.dumps({"case_study": run_case_study(N, eager=a.eager)}), flush=True)
+        return 0
     if a.ablation_only:
         print(json.dumps({"ablation": ablations(N)}), flush=True)
         return 0
@@ -622,6 +700,8 @@ def main(argv=None):
     if not a.no_plate:
         out["plate"] = run_plate(N, eager=a.eager)
         out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
+    out["case_study"] = run_case_study(N, eager=a.eager)
+    out["mismatch"] = run_mismatch(N, eager=a.eager)
     if not a.no_ablation:
         out["ablation"] = ablations(N)
     if not a.no_cpu_baseline:

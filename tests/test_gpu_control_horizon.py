@@ -165,3 +165,35 @@ def test_shifted_episode_matches_oracle():
             assert d <= 1e-6, (i, key, d)
         u_prev = m.u1(st.y)
         x0 = w.next_measurement(m.x1(st.y), i)
+
+
+def test_closed_loop_with_plant_model_mismatch():
+    """Algorithm 1 against a plant whose relative volatility is 8 % above the
+    model's: every solve of the loop converges and is certified for the
+    parameters it was given (the measured state, not the prediction), and the
+    measured trajectory leaves the matched one."""
+    from paper_2606_04725_amd.plant import DistillationPlant
+    note("closed loop, plant alpha x 1.08")
+    w = distillation_workload("small", 0)
+    m = DistillationOCP.from_workload(w)
+    traj = {}
+    for name, alpha in (("matched", w.alpha), ("mismatched", 1.08 * w.alpha)):
+        plant = DistillationPlant(w.N, alpha, w.dt, F=w.F)
+        p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+        p.analyze()
+        x, up = w.x0.copy(), w.u_prev0.copy()
+        xs = []
+        for k in range(12):
+            p.set_parameters(x, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(k), u_prev=up)
+            r = p.solve(warm=k > 0)
+            assert r.status == 0, (name, k, r.status)
+            if k % 4 == 0:
+                m.set_parameters(x0=x, zF=w.zF(k), u_prev=up)
+                sol = p.solution()
+                assert kkt_error(m, sol["y"], sol["lam"], sol["omega_d"], sol["zL"], sol["zU"])["max"] <= 1e-8
+            u1, _ = p.first_stage()
+            x = plant.step(x, u1, zF=float(w.zF(k)[0]))
+            up = u1
+            xs.append(x.copy())
+        traj[name] = np.array(xs)
+    assert np.max(np.abs(traj["matched"] - traj["mismatched"])) > 1e-3
