@@ -28,10 +28,13 @@ def shift_state(m, st):
     moves one stage earlier (the solution predicted for stage k + 1 becomes the
     guess for stage k, since the horizon has advanced by one stage); the last
     stage keeps its values.  Lifted rows [plus | minus | inequality]: the
-    dynamics rows move by nx, the control-horizon hold rows (two per held
-    stage) by two within the held stages, the inequality rows by two."""
+    stage-major equality rows move by their number per stage (rps: the state
+    rows and, where the model has them, its algebraic rows; nx otherwise), the
+    control-horizon hold rows (two per held stage) by two within the held
+    stages, the inequality rows by two."""
     H, nx = m.H, m.nx
-    dyn = H * nx
+    rps = getattr(m, "rps", nx)
+    dyn = H * rps
     held = (m.m_c - dyn) // 2          # held stages (two hold rows each)
 
     def rows(v):
@@ -39,7 +42,7 @@ def shift_state(m, st):
         mc = m.m_c
         parts = []
         for blk in (v[:mc], v[mc:2 * mc]):
-            parts.append(_shift_stages(blk[:dyn], H, nx))
+            parts.append(_shift_stages(blk[:dyn], H, rps))
             if held:
                 parts.append(_shift_stages(blk[dyn:], held, 2))
         if m.m_d:

@@ -93,3 +93,25 @@ def test_shift_state_by_index(Hc):
             a = off + H * nx + 2 * (k - hc)
             b = off + H * nx + 2 * (src - hc)
             assert np.array_equal(sh.beta[a:a + 2], st.beta[b:b + 2])
+
+
+def test_shift_state_by_index_with_algebraic_rows():
+    """The case-study column (Section 4.1) has 2 N + 3 equality rows per stage
+    (tray balances, equilibrium rows, flow rows): all of a stage's rows move
+    together, checked against explicit index arithmetic on random data."""
+    from oracle.ipm import IPMState
+    from oracle.nmpc import shift_state
+    from oracle.reflux import RefluxColumnOCP
+    m = RefluxColumnOCP(5, N=6, Nf=3)
+    rng = np.random.default_rng(6)
+    ml = 2 * m.m_c + m.m_d
+    st = IPMState(*(rng.normal(size=k) for k in (m.n, ml, ml, ml, m.n, m.n)))
+    sh = shift_state(m, st)
+    H, rps, ns, mc = m.H, m.rps, m.ns, m.m_c
+    assert rps == 2 * 6 + 3 and mc == H * rps
+    for k in range(H):
+        src = k + 1 if k < H - 1 else k
+        assert np.array_equal(sh.y[k * ns:(k + 1) * ns], st.y[src * ns:(src + 1) * ns])
+        for v, w in ((sh.s, st.s), (sh.omega, st.omega), (sh.beta, st.beta)):
+            for off in (0, mc):
+                assert np.array_equal(v[off + k * rps:off + (k + 1) * rps], w[off + src * rps:off + (src + 1) * rps])
