@@ -57,7 +57,53 @@ enum {
  * fractions y and flows L = u D, V = L + D, S = L + F kept as variables with
  * their own equality rows; objective dt sum_k (x_1 - xbar)^2 + w_u (u - ubar)^2
  * with (xbar, ubar) the setpoint parameter. */
-enum { NMPC_FAMILY_DISTILLATION = 1, NMPC_FAMILY_HEATED_PLATE = 2, NMPC_FAMILY_REFLUX_COLUMN = 3 };
+enum {
+    NMPC_FAMILY_DISTILLATION = 1,
+    NMPC_FAMILY_HEATED_PLATE = 2,
+    NMPC_FAMILY_REFLUX_COLUMN = 3,
+    NMPC_FAMILY_STAGE_MODEL = 4   /* a model of the stage-pattern front end, see nmpc_stage_model */
+};
+
+/* A problem given by the pattern of one stage (eq. 3: one algebraic pattern
+ * evaluated at every discretization point, its derivatives derived once and
+ * compiled into kernels).  Every stage k = 1..H holds ns = nx + nu + na
+ * variables in the order [states | controls | algebraic] and rps = nx +
+ * n_alg_rows equality rows: first one row per state, which may also involve
+ * the previous stage's states (the measured state x0 at stage 1), linearly
+ * with the constant coefficients prev_coef, then the algebraic rows, which
+ * involve the stage's own variables only.  The objective is a sum of one term
+ * per stage in the stage's variables, the setpoint and the stage's
+ * trajectory value.  The stage Hessian of the Lagrangian is given by its lower
+ * pattern (w_rows >= w_cols).  No inequality rows (bounds go in lb / ub).
+ *
+ * The three kernels (value/derivative evaluation, cold-start guess, parameter
+ * contractions of the sensitivities) come in a gfx950 code object written for
+ * this library's kernel descriptor by the stage-pattern front end; the
+ * library loads it on the problem's device and launches them by name
+ * (nmpc_stage_eval, nmpc_stage_guess, nmpc_stage_adj); the kernels act only
+ * on instances whose descriptor carries their tag.  Every pointer is host
+ * memory the library copies at nmpc_create_problem.  Parameters: x0 (nx),
+ * setpoint (n_setpoint), traj (H values, read when uses_traj), u_prev (nu,
+ * read only by the cold-start guess). */
+typedef struct nmpc_stage_model {
+    int32_t nx, nu, na;         /* states (>= 1), controls (1..16), algebraic variables per stage */
+    int32_t n_alg_rows;         /* equality rows per stage after the nx state rows */
+    int32_t n_setpoint;         /* setpoint entries */
+    int32_t uses_traj;          /* 1: the objective or rows read one trajectory value per stage */
+    const int32_t* row_ptr;     /* rps + 1: own-stage columns of each stage row ... */
+    const int32_t* row_cols;    /* ... strictly ascending, in [0, ns); a state row holds its own state */
+    const int32_t* prev_ptr;    /* rps + 1: previous-stage state columns of each row (state rows only) ... */
+    const int32_t* prev_cols;   /* ... strictly ascending, in [0, nx) */
+    const double* prev_coef;    /* their constant coefficients, finite and nonzero */
+    int32_t nw;                 /* lower Hessian entries per stage */
+    const int32_t* w_rows;      /* nw: (w_rows[e], w_cols[e]), w_rows[e] >= w_cols[e], in [0, ns), distinct */
+    const int32_t* w_cols;
+    const double* lb;           /* ns: variable bounds of every stage; -inf / +inf for none, lb < ub */
+    const double* ub;
+    const void* code_object;    /* the kernels' code object ... */
+    uint64_t code_object_size;  /* ... and its size in bytes */
+    uint64_t tag;               /* the tag the kernels were generated with (nonzero) */
+} nmpc_stage_model;
 
 /* Fill-reducing ordering of the analysis (eq. 19): nested dissection of the
  * family's stage structure (default: one-stage separators for the
@@ -114,6 +160,9 @@ typedef struct nmpc_structure {
      * bound of the flows L, V, S (lower bound 0) */
     int32_t feed_tray;
     double distillate, feed_comp, hold_cond, hold_tray, hold_reb, u_weight, flow_hi;
+    /* STAGE_MODEL: the stage pattern (also uses horizon, dt, ordering; the
+     * control horizon must be 0) */
+    const nmpc_stage_model* stage_model;
 } nmpc_structure;
 
 /* Interior-point constants (the paper leaves them open; see the design notes).

@@ -36,14 +36,20 @@ class ToyOCP:
         self.h_rows = np.repeat(np.arange(self.n), 1)
         self.h_cols = np.arange(self.n)
 
-    def set_parameters(self, y0=None, tk=None):
+    def set_parameters(self, y0=None, tk=None, traj=None):
+        """traj: the tracked values of stages 1..H given directly (replacing
+        sin(t + tk)); None keeps the current choice."""
         if y0 is not None:
             self.y0 = float(y0)
         if tk is not None:
             self.tk = float(tk)
+        if traj is not None:
+            self.traj = np.array(traj, dtype=np.float64).reshape(self.H)
+
+    traj = None
 
     def sp(self):
-        return np.sin(self.t + self.tk)
+        return np.sin(self.t + self.tk) if self.traj is None else self.traj
 
     def f(self, y):
         Y = y[0::2]
@@ -85,6 +91,22 @@ class ToyOCP:
 
     def initial_guess(self):
         return np.tile([self.y0, 2.0], self.H)
+
+    def parameter_derivatives(self, y):
+        """Groups: y0 (1) enters the first state row with coefficient -1; traj
+        (H) the tracked value of each stage, in the objective only."""
+        Y = y[0::2]
+        H, n, dt = self.H, self.n, self.dt
+        dc = np.zeros((self.m_c, 1))
+        dc[0, 0] = -1.0
+        dg = np.zeros((n, H))
+        dg[2 * np.arange(H), np.arange(H)] = -2.0 * dt
+        dfv = -2.0 * dt * (Y - self.sp())
+        return {"y0": (dc, np.zeros((0, 1)), np.zeros((n, 1)), np.zeros(1)),
+                "traj": (np.zeros((self.m_c, H)), np.zeros((0, H)), dg, dfv)}
+
+    def u1_index(self):
+        return [1]
 
     def u1(self, y):
         return np.array([y[1]])

@@ -15,9 +15,20 @@ NMPC_OK = 0
 NMPC_MAX_ITER, NMPC_LINESEARCH_FAIL, NMPC_REG_FAIL, NMPC_NONFINITE = 1, 2, 3, 4
 NMPC_ERR_INVALID_ARG, NMPC_ERR_BAD_ORDER, NMPC_ERR_STRUCT_MISMATCH = -1, -2, -3
 NMPC_ERR_NO_DEVICE, NMPC_ERR_HIP, NMPC_ERR_OOM, NMPC_ERR_UNSUPPORTED = -4, -5, -6, -7
-NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE, NMPC_FAMILY_REFLUX_COLUMN = 1, 2, 3
+NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE, NMPC_FAMILY_REFLUX_COLUMN, NMPC_FAMILY_STAGE_MODEL = 1, 2, 3, 4
 NMPC_ORDER_NESTED_DISSECTION, NMPC_ORDER_MIN_DEGREE = 0, 1
 NMPC_KKT_LIFTED, NMPC_KKT_HYKKT = 0, 1
+
+
+class nmpc_stage_model(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nu", C.c_int32), ("na", C.c_int32), ("n_alg_rows", C.c_int32),
+                ("n_setpoint", C.c_int32), ("uses_traj", C.c_int32),
+                ("row_ptr", C.POINTER(C.c_int32)), ("row_cols", C.POINTER(C.c_int32)),
+                ("prev_ptr", C.POINTER(C.c_int32)), ("prev_cols", C.POINTER(C.c_int32)),
+                ("prev_coef", C.POINTER(C.c_double)), ("nw", C.c_int32),
+                ("w_rows", C.POINTER(C.c_int32)), ("w_cols", C.POINTER(C.c_int32)),
+                ("lb", C.POINTER(C.c_double)), ("ub", C.POINTER(C.c_double)),
+                ("code_object", C.c_void_p), ("code_object_size", C.c_uint64), ("tag", C.c_uint64)]
 
 
 class nmpc_structure(C.Structure):
@@ -29,7 +40,8 @@ class nmpc_structure(C.Structure):
                 ("cond_slope", C.c_double), ("ordering", C.c_int32), ("control_horizon", C.c_int32),
                 ("feed_tray", C.c_int32), ("distillate", C.c_double), ("feed_comp", C.c_double),
                 ("hold_cond", C.c_double), ("hold_tray", C.c_double), ("hold_reb", C.c_double),
-                ("u_weight", C.c_double), ("flow_hi", C.c_double)]
+                ("u_weight", C.c_double), ("flow_hi", C.c_double),
+                ("stage_model", C.POINTER(nmpc_stage_model))]
 
 
 class nmpc_options(C.Structure):

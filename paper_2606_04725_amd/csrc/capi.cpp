@@ -219,7 +219,7 @@ nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
         if (!nmpc::build_structure(*s, h->impl.st, err)) {
             delete h;
             const bool known = s->family == NMPC_FAMILY_DISTILLATION || s->family == NMPC_FAMILY_HEATED_PLATE ||
-                               s->family == NMPC_FAMILY_REFLUX_COLUMN;
+                               s->family == NMPC_FAMILY_REFLUX_COLUMN || s->family == NMPC_FAMILY_STAGE_MODEL;
             return fail(known ? NMPC_ERR_INVALID_ARG : NMPC_ERR_UNSUPPORTED, err);
         }
         const auto& st = h->impl.st;
@@ -233,6 +233,10 @@ nmpc_status nmpc_create_problem(const nmpc_structure* s, nmpc_problem** out) {
         } else if (s->family == NMPC_FAMILY_REFLUX_COLUMN) {   // the setpoint of Table 1, reflux ratio 2
             h->impl.setpoint = {0.8958, 2.51459};
             h->impl.u_prev = {2.0};
+        } else if (s->family == NMPC_FAMILY_STAGE_MODEL) {   // zero parameters
+            h->impl.x0.assign(st.nx, 0.0);
+            h->impl.setpoint.assign(st.gm.nsp, 0.0);
+            h->impl.traj.assign(st.H, 0.0);
         } else {                               // plate: zero field, zero target, mid-range heaters
             h->impl.x0.assign(st.nx, 0.0);
             h->impl.setpoint.assign(st.nx, 0.0);

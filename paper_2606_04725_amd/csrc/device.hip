@@ -85,6 +85,10 @@ struct Device {
     double* seed_lam = nullptr;    // nu x m multipliers; row k's first nx entries are d u1_k / d x0
     // this GPU's fixed buffer of the allocation-free Jacobian (resolved at set-up)
     unsigned char* scratch = nullptr;
+    // stage-model family: the generated kernels, loaded on this device
+    hipModule_t mod = nullptr;
+    hipFunction_t f_eval = nullptr, f_guess = nullptr, f_adj = nullptr;
+    double* gm_jac = nullptr;      // nu x nx: d u1 / d x0 mapped through the state rows' coefficients
 };
 
 // Emitted kernel launch of a batch schedule: a group launch (groups[off ..
@@ -109,6 +113,10 @@ struct Batch {
     int4* tasks = nullptr;
     std::vector<BLaunch> fac, fwd, bwd, fwd_rest;
     bool has_distill = false, has_plate = false, has_reflux = false;
+    // generated kernels of the stage models among the members (one entry per
+    // distinct code object; each launch covers the batch, its kernels skip
+    // instances with another tag)
+    std::vector<std::pair<hipFunction_t, hipFunction_t>> gen;   // (eval, guess)
     int* running = nullptr;        // device: instances running, instances waiting for corrections,
                                    // instances whose HyKKT conjugate gradients run
     int* hrunning = nullptr;       // pinned copy
@@ -250,6 +258,11 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
         if (hI[i].family == NMPC_FAMILY_DISTILLATION) B->has_distill = true;
         if (hI[i].family == NMPC_FAMILY_HEATED_PLATE) B->has_plate = true;
         if (hI[i].family == NMPC_FAMILY_REFLUX_COLUMN) B->has_reflux = true;
+        if (hI[i].family == NMPC_FAMILY_STAGE_MODEL) {
+            const std::pair<hipFunction_t, hipFunction_t> f{members[i]->f_eval, members[i]->f_guess};
+            if (f.first && f.second && std::find(B->gen.begin(), B->gen.end(), f) == B->gen.end())
+                B->gen.push_back(f);
+        }
     }
     BTRY(upload(B->allocs, B->dI, hI));
     // index spaces
@@ -354,6 +367,27 @@ void eval(Batch& B, bool full, int src, int pred) {
     if (B.has_distill) launch_eval_distill(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
     if (B.has_plate) launch_eval_plate(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
     if (B.has_reflux) launch_eval_reflux(full, src, pred, B.dI, B.spaces.sp[kSpN], B.stream);
+    // stage models: one lane per (stage, max(ns, rps)) -> the max(n, ml) space
+    // (ml = 2 H rps); a failed launch is left in hipGetLastError
+    for (const auto& g : B.gen) {
+        Space sp = B.spaces.sp[kSpMax];
+        const InstPtrs* dI = B.dI;
+        int fl = full ? 1 : 0;
+        void* args[] = {&dI, &sp, &src, &pred, &fl};
+        if (sp.blocks > 0)
+            (void)hipModuleLaunchKernel(g.first, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, args, nullptr);
+    }
+}
+
+void cold_guess(Batch& B) {
+    launch_cold_guess(B.dI, B.spaces.sp[kSpN], B.stream);
+    for (const auto& g : B.gen) {
+        Space sp = B.spaces.sp[kSpN];
+        const InstPtrs* dI = B.dI;
+        void* args[] = {&dI, &sp};
+        if (sp.blocks > 0)
+            (void)hipModuleLaunchKernel(g.second, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, args, nullptr);
+    }
 }
 
 void run_launch(Batch& B, const BLaunch& L, int pred, double eta_force, int which) {
@@ -546,6 +580,7 @@ void device_free(Problem& p) {
     batch_release(D.seeds);
     for (Device* c : D.seed_devs) delete c;
     for (void* a : D.allocs) (void)hipFree(a);
+    if (D.mod) (void)hipModuleUnload(D.mod);
     if (D.ev_in) (void)hipEventDestroy(D.ev_in);
     if (D.ev_out) (void)hipEventDestroy(D.ev_out);
     if (D.stream) (void)hipStreamDestroy(D.stream);
@@ -610,6 +645,33 @@ nmpc_status device_init(Problem& p, std::string& err) {
         I.rps = I.rd.rps;
         I.nsp = 2;
         I.ntr = 0;
+    } else if (st.desc.family == NMPC_FAMILY_STAGE_MODEL) {
+        const auto& M = st.gm;
+        I.ns = M.ns;
+        I.rps = M.rps;
+        I.nsp = M.nsp;
+        I.ntr = M.traj ? st.H : 0;
+        I.gm = StageConst{s.dt, (unsigned long long)M.tag, nullptr};
+        DTRY(hipModuleLoadData(&D.mod, M.code.data()));
+        DTRY(hipModuleGetFunction(&D.f_eval, D.mod, "nmpc_stage_eval"));
+        DTRY(hipModuleGetFunction(&D.f_guess, D.mod, "nmpc_stage_guess"));
+        DTRY(hipModuleGetFunction(&D.f_adj, D.mod, "nmpc_stage_adj"));
+        hipDeviceptr_t abi_ptr = nullptr;
+        size_t abi_bytes = 0;
+        DTRY(hipModuleGetGlobal(&abi_ptr, &abi_bytes, D.mod, "nmpc_stage_abi"));
+        unsigned int abi = 0;
+        if (abi_bytes == sizeof(abi)) DTRY(hipMemcpyDtoH(&abi, abi_ptr, sizeof(abi)));
+        if (abi != kStageAbi) {
+            err = "stage model: the code object was generated for another library build (descriptor layout)";
+            return bail(NMPC_ERR_INVALID_ARG);
+        }
+        if (!M.pc_minus_identity) {
+            double* pc = nullptr;
+            DTRY(dalloc(D.allocs, pc, M.pc.size()));
+            DTRY(hipMemcpy(pc, M.pc.data(), M.pc.size() * sizeof(double), hipMemcpyHostToDevice));
+            I.gm.pc = pc;
+            DTRY(dalloc(D.allocs, D.gm_jac, (size_t)st.nu * st.nx));
+        }
     } else if (st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
         I.pd.G = s.grid;
         I.pd.nx = s.grid * s.grid;
@@ -1125,7 +1187,7 @@ nmpc_status batch_solve(Batch& B, int warm, const nmpc_options& o, nmpc_result* 
         if (!B.members[0]->owner->iter_hyk) launch_hk_from_lifted(B.dI, B.spaces, st);
     }
     if (!warm) {
-        launch_cold_guess(B.dI, B.spaces.sp[kSpN], st);   // every stage: the measured state, the last control
+        cold_guess(B);   // every stage: the measured state, the last control (stage models: their guess)
         launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, false, st);
         eval(B, false, kSrcIter, kPredAll);
         launch_cold_start(B.dI, B.spaces, o.bound_push, o.slack_push, o.mu0_cold, true, st);
@@ -1431,7 +1493,15 @@ nmpc_status adjoint_run(Problem& p, std::string& err) {
         solve_launches(B, kPredAll, 3);
         launch_adj_refine(2, B.dI, B.spaces, D.adj_eta, B.stream);
     }
-    launch_adj_gather(B.dI, D.hI.family, D.hI.nx, B.stream);
+    if (D.hI.family == NMPC_FAMILY_STAGE_MODEL) {
+        const InstPtrs* dI = B.dI;
+        void* args[] = {&dI};
+        const int nout = D.hI.nx + D.hI.nsp + D.hI.ntr + D.hI.nu;
+        HIP_TRY(hipModuleLaunchKernel(D.f_adj, (nout + kBlock - 1) / kBlock, 1, 1, kBlock, 1, 1, 0, B.stream, args,
+                                      nullptr));
+    } else {
+        launch_adj_gather(B.dI, D.hI.family, D.hI.nx, B.stream);
+    }
     HIP_TRY(hipGetLastError());
     return NMPC_OK;
 }
@@ -1627,8 +1697,14 @@ nmpc_status device_jacobian_u1_x0(Problem& p, double* jac, std::string& err) {
         launch_adj_refine(2, S.dI, S.spaces, D.adj_eta, S.stream);
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpy2DAsync(jac, st.nx * sizeof(double), D.seed_lam, (size_t)D.hI.m * sizeof(double),
-                             st.nx * sizeof(double), K, hipMemcpyDeviceToHost, D.stream));
+    if (D.hI.gm.pc) {   // stage model whose state rows hold the previous states through a matrix
+        launch_x0_map(D.seed_lam, D.hI.m, D.hI.gm.pc, D.gm_jac, st.nx, K, D.stream);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(jac, D.gm_jac, (size_t)K * st.nx * sizeof(double), hipMemcpyDeviceToHost, D.stream));
+    } else {
+        HIP_TRY(hipMemcpy2DAsync(jac, st.nx * sizeof(double), D.seed_lam, (size_t)D.hI.m * sizeof(double),
+                                 st.nx * sizeof(double), K, hipMemcpyDeviceToHost, D.stream));
+    }
     HIP_TRY(hipStreamSynchronize(D.stream));
     return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;
 }
@@ -1645,8 +1721,13 @@ struct NoAllocLayout {
 NoAllocLayout noalloc_layout(const Problem& p) {
     const Structure& st = p.st;
     const size_t n = (size_t)st.n, m = (size_t)(st.m_c + st.m_d);
-    const size_t nsp = st.desc.family == NMPC_FAMILY_HEATED_PLATE ? (size_t)st.nx : 2;
-    const size_t ntr = st.desc.family == NMPC_FAMILY_DISTILLATION ? (size_t)st.H : 0;
+    const size_t nsp = st.desc.family == NMPC_FAMILY_HEATED_PLATE ? (size_t)st.nx
+                       : st.desc.family == NMPC_FAMILY_STAGE_MODEL ? (size_t)st.gm.nsp
+                                                                   : 2;
+    const size_t ntr = st.desc.family == NMPC_FAMILY_DISTILLATION || (st.desc.family == NMPC_FAMILY_STAGE_MODEL &&
+                                                                      st.gm.traj)
+                           ? (size_t)st.H
+                           : 0;
     const size_t nout = (size_t)st.nx + nsp + ntr + (size_t)st.nu;
     const size_t nuv = std::max<size_t>((size_t)p.sym.stored_uv, 1);
     NoAllocLayout L{};
@@ -1743,8 +1824,13 @@ nmpc_status device_jacobian_u1_x0_noalloc(Problem& p, double* jac, void* caller_
         }
         B.dI = own;
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(jac + (size_t)k * st.nx, J.adj_lam, st.nx * sizeof(double), hipMemcpyDeviceToDevice,
-                               B.stream));
+        if (J.gm.pc) {
+            launch_x0_map(J.adj_lam, 0, J.gm.pc, jac + (size_t)k * st.nx, st.nx, 1, B.stream);
+            HIP_TRY(hipGetLastError());
+        } else {
+            HIP_TRY(hipMemcpyAsync(jac + (size_t)k * st.nx, J.adj_lam, st.nx * sizeof(double),
+                                   hipMemcpyDeviceToDevice, B.stream));
+        }
     }
     HIP_TRY(join_out(D, caller));
     return D.adj_eta > 0.0 ? NMPC_REG_FAIL : NMPC_OK;

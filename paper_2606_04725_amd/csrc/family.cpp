@@ -266,6 +266,116 @@ static bool build_reflux(const nmpc_structure& s, Structure& st, std::string& er
     return true;
 }
 
+// Stage-pattern model (eq. 3): the per-stage patterns of the descriptor
+// repeated over the horizon.  A state row of stage k > 1 starts with its
+// previous-stage columns (lower indices), then its own columns.
+static bool build_stage_model(const nmpc_structure& s, Structure& st, std::string& err) {
+    const nmpc_stage_model* g = s.stage_model;
+    auto bad = [&](const char* what) {
+        err = std::string("stage model: ") + what;
+        return false;
+    };
+    if (!g) return bad("NULL descriptor");
+    if (s.horizon < 1 || !(s.dt > 0) || !std::isfinite(s.dt) || s.control_horizon != 0)
+        return bad("need horizon >= 1, finite dt > 0, control_horizon 0");
+    if (g->nx < 1 || g->nu < 1 || g->nu > 16 || g->na < 0 || g->n_alg_rows < 0 || g->n_setpoint < 0 ||
+        (g->uses_traj != 0 && g->uses_traj != 1) || g->nw < 0)
+        return bad("need nx >= 1, 1 <= nu <= 16, na, n_alg_rows, n_setpoint, nw >= 0, uses_traj 0 or 1");
+    if (!g->row_ptr || !g->prev_ptr || !g->lb || !g->ub || !g->code_object || g->code_object_size == 0 ||
+        g->tag == 0 || (g->nw > 0 && (!g->w_rows || !g->w_cols)))
+        return bad("missing pattern, bounds, code object or tag");
+    const int64_t ns64 = (int64_t)g->nx + g->nu + g->na, rps64 = (int64_t)g->nx + g->n_alg_rows;
+    if (ns64 * s.horizon > (int64_t)1 << 30 || rps64 * s.horizon > (int64_t)1 << 29 || g->nw > (1 << 24))
+        return bad("problem too large");
+    const int ns = (int)ns64, rps = (int)rps64, nx = g->nx, H = s.horizon;
+    if (g->row_ptr[0] != 0 || g->prev_ptr[0] != 0) return bad("row_ptr / prev_ptr must start at 0");
+    for (int r = 0; r < rps; ++r) {
+        if (g->row_ptr[r + 1] < g->row_ptr[r] || g->row_ptr[r + 1] - g->row_ptr[r] > ns ||
+            g->prev_ptr[r + 1] < g->prev_ptr[r] || g->prev_ptr[r + 1] - g->prev_ptr[r] > nx)
+            return bad("row_ptr / prev_ptr not monotone or a row too long");
+        if (r >= nx && g->prev_ptr[r + 1] != g->prev_ptr[r]) return bad("an algebraic row uses previous states");
+        if (g->row_ptr[r + 1] > g->row_ptr[r] && !g->row_cols) return bad("missing row_cols");
+        if (g->prev_ptr[r + 1] > g->prev_ptr[r] && (!g->prev_cols || !g->prev_coef)) return bad("missing prev_cols");
+        bool own = false;
+        for (int q = g->row_ptr[r]; q < g->row_ptr[r + 1]; ++q) {
+            const int c = g->row_cols[q];
+            if (c < 0 || c >= ns || (q > g->row_ptr[r] && c <= g->row_cols[q - 1]))
+                return bad("row_cols out of range or not strictly ascending");
+            own = own || c == r;
+        }
+        if (r < nx && !own) return bad("a state row does not hold its own state");
+        for (int q = g->prev_ptr[r]; q < g->prev_ptr[r + 1]; ++q) {
+            const int c = g->prev_cols[q];
+            if (c < 0 || c >= nx || (q > g->prev_ptr[r] && c <= g->prev_cols[q - 1]))
+                return bad("prev_cols out of range or not strictly ascending");
+            if (!std::isfinite(g->prev_coef[q]) || g->prev_coef[q] == 0.0) return bad("prev_coef not finite nonzero");
+        }
+    }
+    {
+        std::vector<int64_t> keys;
+        for (int e = 0; e < g->nw; ++e) {
+            const int a = g->w_rows[e], b = g->w_cols[e];
+            if (b < 0 || a < b || a >= ns) return bad("Hessian entry out of range or not lower");
+            keys.push_back((int64_t)a * ns + b);
+        }
+        std::sort(keys.begin(), keys.end());
+        if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return bad("repeated Hessian entry");
+    }
+    for (int j = 0; j < ns; ++j)
+        if (std::isnan(g->lb[j]) || std::isnan(g->ub[j]) || !(g->lb[j] < g->ub[j]) || g->lb[j] == INFINITY ||
+            g->ub[j] == -INFINITY)
+            return bad("bounds must satisfy lb < ub");
+    auto& M = st.gm;
+    M.ns = ns;
+    M.rps = rps;
+    M.nsp = g->n_setpoint;
+    M.nw = g->nw;
+    M.traj = g->uses_traj != 0;
+    M.tag = g->tag;
+    const unsigned char* code = static_cast<const unsigned char*>(g->code_object);
+    M.code.assign(code, code + g->code_object_size);
+    M.pc.assign((size_t)nx * nx, 0.0);
+    for (int r = 0; r < nx; ++r)
+        for (int q = g->prev_ptr[r]; q < g->prev_ptr[r + 1]; ++q) M.pc[(size_t)r * nx + g->prev_cols[q]] = g->prev_coef[q];
+    M.pc_minus_identity = true;
+    for (int r = 0; r < nx; ++r)
+        for (int c = 0; c < nx; ++c)
+            if (M.pc[(size_t)r * nx + c] != (r == c ? -1.0 : 0.0)) M.pc_minus_identity = false;
+    st.nx = nx;
+    st.nu = g->nu;
+    st.H = H;
+    st.n = H * ns;
+    st.m_c = H * rps;
+    st.m_d = 0;
+    st.jptr.assign(st.m_c + 1, 0);
+    st.jcol.clear();
+    for (int k = 0; k < H; ++k)
+        for (int r = 0; r < rps; ++r) {
+            if (k > 0)
+                for (int q = g->prev_ptr[r]; q < g->prev_ptr[r + 1]; ++q) st.jcol.push_back((k - 1) * ns + g->prev_cols[q]);
+            for (int q = g->row_ptr[r]; q < g->row_ptr[r + 1]; ++q) st.jcol.push_back(k * ns + g->row_cols[q]);
+            st.jptr[k * rps + r + 1] = (int)st.jcol.size();
+        }
+    st.jrow.resize(st.jcol.size());
+    for (int r = 0; r < st.m_c; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) st.jrow[p] = r;
+    st.wrow.assign((size_t)g->nw * H, 0);
+    st.wcol.assign((size_t)g->nw * H, 0);
+    for (int k = 0; k < H; ++k)
+        for (int e = 0; e < g->nw; ++e) {
+            st.wrow[(size_t)k * g->nw + e] = k * ns + g->w_rows[e];
+            st.wcol[(size_t)k * g->nw + e] = k * ns + g->w_cols[e];
+        }
+    st.lb.resize(st.n);
+    st.ub.resize(st.n);
+    for (int k = 0; k < H; ++k)
+        for (int j = 0; j < ns; ++j) {
+            st.lb[(size_t)k * ns + j] = g->lb[j];
+            st.ub[(size_t)k * ns + j] = g->ub[j];
+        }
+    return true;
+}
+
 bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) {
     out = Structure();
     out.desc = s;
@@ -280,10 +390,13 @@ bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) 
         ok = build_plate(s, out, err);
     } else if (s.family == NMPC_FAMILY_REFLUX_COLUMN) {
         ok = build_reflux(s, out, err);
+    } else if (s.family == NMPC_FAMILY_STAGE_MODEL) {
+        ok = build_stage_model(s, out, err);
     } else {
         err = "unsupported problem family";
         return false;
     }
+    out.desc.stage_model = nullptr;   // the caller's descriptor is not kept
     if (ok) finish_k_count(out);
     return ok;
 }

@@ -21,6 +21,16 @@ struct Structure {
     std::vector<int32_t> wrow, wcol;
     std::vector<double> lb, ub;
     int64_t nnz_k = 0;
+    // stage-model family: copies of the descriptor's data (desc.stage_model
+    // is cleared: the caller's descriptor is not kept)
+    struct StageModel {
+        int ns = 0, rps = 0, nsp = 0, nw = 0;
+        bool traj = false;
+        uint64_t tag = 0;
+        std::vector<unsigned char> code;
+        std::vector<double> pc;   // nx x nx coefficients of the previous states in the state rows, row-major
+        bool pc_minus_identity = false;
+    } gm;
 };
 
 // Result of SymCholesky (eqs. 18-19) plus every map the numeric phase needs.

@@ -30,6 +30,16 @@ struct DistillConst {
     double dt, alpha, F, rho;
 };
 
+// Stage-model family: constants its generated kernels read.  tag names the
+// kernels meant for the instance; pc is null when the state rows hold the
+// previous states with coefficient -1 each (implicit Euler), else the nx x nx
+// coefficient matrix (row-major) of the previous states in the state rows.
+struct StageConst {
+    double dt;
+    unsigned long long tag;
+    const double* pc;
+};
+
 // Per-supernode read-only symbolic data of one instance.
 // What the extend-add of the child at one position of child_list reads:
 // its update block (u_off), its rows' positions in the parent (rel_off), its
@@ -121,6 +131,7 @@ struct InstPtrs {
     PlateConst pc;
     RefluxDims rd;
     RefluxConst rc;
+    StageConst gm;
     int ns, rps;        // variables and (dynamics block) equality rows per stage
     int nsp, ntr;       // setpoint and disturbance-trajectory lengths of the family
     // structure
@@ -154,6 +165,12 @@ struct InstPtrs {
     double *hk_x, *hk_r, *hk_p, *hk_sp, *hk_t, *hk_w;
     Ctl* ctl;
 };
+
+// Layout check between the library and the code objects of generated stage
+// models (both read InstPtrs): the library refuses a code object whose
+// nmpc_stage_abi differs.
+constexpr unsigned int kStageAbiVersion = 1;
+constexpr unsigned int kStageAbi = kStageAbiVersion * 100000u + (unsigned int)sizeof(InstPtrs);
 
 // Right-hand side and solution of the solves: 0 rhs -> dy (Newton step),
 // 1 yt -> dzl (single-solve entry point), 2 adj_rhs -> adj_w (sensitivities),
@@ -267,6 +284,7 @@ void launch_cold_guess(const InstPtrs* I, const Space& spN, hipStream_t st);
 void launch_export_duals(const InstPtrs* I, double* lam, double* om_d, int rows, hipStream_t st);
 // out = [x0 (nx) | setpoint (nsp) | trajectory (ntr) | u_prev (nu)] for instance 0
 void launch_adj_gather(const InstPtrs* I, int family, int nx, hipStream_t st);
+void launch_x0_map(const double* lam, int64_t stride, const double* pc, double* out, int nx, int K, hipStream_t st);
 // Refinement of w = K^{-1} b against the uncondensed system [K0 J^T; J -Q^{-1}]
 // (K0 = W + Sigma + eta I): start sets lam = Q J w; residual forms
 // adj_rhs = b - K0 w - J^T lam + J^T qr with qr = lam - Q J w; update adds the

@@ -908,7 +908,7 @@ __global__ void __launch_bounds__(kBlock) k_cold_guess(const InstPtrs* __restric
     int lb;
     const InstPtrs& I = Ia[block_inst(sp, lb)];
     const int j = lb * kBlock + threadIdx.x;
-    if (j >= I.n) return;
+    if (j >= I.n || I.family == NMPC_FAMILY_STAGE_MODEL) return;   // stage models: their own guess kernel
     const int r = j % I.ns;
     double v;
     if (r < I.nx) {
@@ -1457,6 +1457,27 @@ void launch_shift(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
 
 void launch_hk_from_lifted(const InstPtrs* I, const IpmSpaces& S, hipStream_t st) {
     hipLaunchKernelGGL(k_hk_from_lifted, dim3(S.sp[kSpM].blocks), dim3(kBlock), 0, st, I, S.sp[kSpM]);
+}
+
+// d u1 / d x0 of a stage model whose state rows hold the previous states
+// through the matrix C (pc): row k is -C^T lam_k over the first stage's state
+// rows (lam_k: the sensitivity multipliers of seed k, stride apart).
+__global__ void __launch_bounds__(kBlock) k_x0_map(const double* __restrict__ lam, int64_t stride,
+                                                   const double* __restrict__ pc, double* __restrict__ out, int nx,
+                                                   int K) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nx * K) return;
+    const int k = t / nx, j = t - k * nx;
+    const double* l = lam + (int64_t)k * stride;
+    double acc = 0.0;
+    for (int i = 0; i < nx; ++i) acc -= pc[(int64_t)i * nx + j] * l[i];
+    out[t] = acc;
+}
+
+void launch_x0_map(const double* lam, int64_t stride, const double* pc, double* out, int nx, int K, hipStream_t st) {
+    if (nx * K > 0)
+        hipLaunchKernelGGL(k_x0_map, dim3((nx * K + kBlock - 1) / kBlock), dim3(kBlock), 0, st, lam, stride, pc, out,
+                           nx, K);
 }
 
 void launch_adj_gather(const InstPtrs* I, int family, int nx, hipStream_t st) {

@@ -365,7 +365,8 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     // ---- 1. fill-reducing ordering ----------------------------------------------
     std::vector<int32_t> perm_md;
     if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION &&
-        (st.desc.family == NMPC_FAMILY_DISTILLATION || st.desc.family == NMPC_FAMILY_REFLUX_COLUMN)) {
+        (st.desc.family == NMPC_FAMILY_DISTILLATION || st.desc.family == NMPC_FAMILY_REFLUX_COLUMN ||
+         st.desc.family == NMPC_FAMILY_STAGE_MODEL)) {
         perm_md = stage_nd(st.H, n / st.H);
     } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
         LatticeNd nd(n, st.H, st.desc.grid, n / st.H, ent);

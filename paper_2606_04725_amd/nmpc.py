@@ -86,6 +86,39 @@ def plate_structure(G, H, dt, cond_slope=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0,
     return s
 
 
+def stage_model_structure(gen, H, dt, ordering=capi.NMPC_ORDER_NESTED_DISSECTION):
+    """Structure of a model compiled by the stage-pattern front end
+    (simd.compile): its per-stage patterns, bounds and code object.  The
+    arrays stay referenced by the returned structure until the problem is
+    created (the library copies them then)."""
+    if not gen.code:
+        raise ValueError("the model has no code object (run simd.compile)")
+    i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+    keep = dict(row_ptr=i32(gen.row_ptr), row_cols=i32(gen.row_cols), prev_ptr=i32(gen.prev_ptr),
+                prev_cols=i32(gen.prev_cols), prev_coef=_f64(gen.prev_coef), w_rows=i32(gen.w_rows),
+                w_cols=i32(gen.w_cols), lb=_f64(gen.lb), ub=_f64(gen.ub),
+                code=C.create_string_buffer(gen.code, len(gen.code)))
+    d = capi.nmpc_stage_model()
+    d.nx, d.nu, d.na, d.n_alg_rows = gen.nx, gen.nu, gen.na, gen.n_alg_rows
+    d.n_setpoint, d.uses_traj = gen.n_setpoint, int(gen.uses_traj)
+    for k in ("row_ptr", "row_cols", "prev_ptr", "prev_cols", "w_rows", "w_cols"):
+        setattr(d, k, _ip(keep[k]))
+    for k in ("prev_coef", "lb", "ub"):
+        setattr(d, k, _dp(keep[k]))
+    d.nw = len(gen.w_rows)
+    d.code_object = C.cast(keep["code"], C.c_void_p)
+    d.code_object_size = len(gen.code)
+    d.tag = gen.tag
+    s = nmpc_structure()
+    s.ordering = ordering
+    s.family = capi.NMPC_FAMILY_STAGE_MODEL
+    s.horizon, s.dt = H, dt
+    s.stage_model = C.pointer(d)
+    s._keep = (keep, d)
+    s._sizes = (gen.n_setpoint, H if gen.uses_traj else 0)
+    return s
+
+
 class Problem:
     """One transcribed OCP structure: create -> analyze -> set_parameters -> solve."""
 
@@ -100,6 +133,7 @@ class Problem:
         self.n, self.m_c, self.m_d, self.nx, self.nu = n.value, mc.value, md.value, nx.value, nu.value
         self.horizon = structure.horizon
         self.family = structure.family
+        self._stage_sizes = getattr(structure, "_sizes", None)
         self.nnz_k = nk.value
         self.ml = 2 * self.m_c + self.m_d
         self.analyzed = False
@@ -152,8 +186,8 @@ class Problem:
     # ---- parameters and solves -------------------------------------------
     def set_parameters(self, x0, setpoint=None, traj=None, u_prev=None):
         x0 = _f64(x0, self.nx)
-        sp = None if setpoint is None else _f64(setpoint)
-        tr = None if traj is None else _f64(traj)
+        sp = None if setpoint is None else _f64(setpoint, self.n_setpoint)
+        tr = None if traj is None else _f64(traj, self.horizon)
         up = None if u_prev is None else _f64(u_prev, self.nu)
         _check(capi.lib().nmpc_set_parameters(self._h, _dp(x0), _dp(sp), _dp(tr), _dp(up)))
 
@@ -213,10 +247,14 @@ class Problem:
     # caller's hipStream_t (0 = null stream); ordered on that stream, no host sync.
     @property
     def n_setpoint(self):
+        if self.family == capi.NMPC_FAMILY_STAGE_MODEL:
+            return self._stage_sizes[0]
         return self.nx if self.family == capi.NMPC_FAMILY_HEATED_PLATE else 2
 
     @property
     def n_traj(self):
+        if self.family == capi.NMPC_FAMILY_STAGE_MODEL:
+            return self._stage_sizes[1]
         return self.horizon if self.family == capi.NMPC_FAMILY_DISTILLATION else 0
 
     def set_parameters_dev(self, x0, setpoint=0, traj=0, u_prev=0, stream=0):

@@ -1,0 +1,100 @@
+"""Models written with the stage-pattern front end (paper_2606_04725_amd.simd).
+
+Each function returns a StageModel; `simd.compile` turns it into the kernels
+the library loads (family NMPC_FAMILY_STAGE_MODEL).
+
+  toy_model        the one-state example of the re-solve listing (Section 3.3):
+                   dy/dt = 4 sin(u) - y^3, y >= 0, 1 <= u <= 3, objective
+                   dt sum_k (y_k - s_k)^2 with s_k the stage's trajectory value
+  lq_model         linear dynamics x_k = A x_{k-1} + B u_k (previous states
+                   through a constant matrix), objective
+                   sum_k (x_k - xs)^T Q (x_k - xs) + u_k^T R u_k, xs the setpoint
+  reflux_model     the distillation case study of Section 4.1 with the
+                   algebraic vapour fractions and flows kept as variables
+                   (the same problem as the library's REFLUX_COLUMN family)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .simd import StageModel, sin
+
+
+def toy_model() -> StageModel:
+    m = StageModel("toy_sin_cube")
+    y = m.state("y", lb=0.0)
+    u = m.control("u", lb=1.0, ub=3.0)
+    m.dynamics(y, 4.0 * sin(u) - y ** 3)
+    m.minimize(m.dt * (y - m.traj()) ** 2)
+    m.guess(u, 2.0)
+    return m
+
+
+def lq_model(A, B, Q, R, name="lq", x_bounds=None, u_bounds=None) -> StageModel:
+    A, B, Q, R = (np.asarray(v, dtype=np.float64) for v in (A, B, Q, R))
+    nx, nu = B.shape
+    m = StageModel(name, n_setpoint=nx)
+    xl, xh = x_bounds if x_bounds is not None else (-np.inf, np.inf)
+    ul, uh = u_bounds if u_bounds is not None else (-np.inf, np.inf)
+    X = [m.state(f"x{i}", xl, xh) for i in range(nx)]
+    U = [m.control(f"u{j}", ul, uh) for j in range(nu)]
+    for i in range(nx):
+        r = X[i]
+        for j in range(nx):
+            if A[i, j] != 0.0:
+                r = r - float(A[i, j]) * m.prev(X[j])
+        for j in range(nu):
+            if B[i, j] != 0.0:
+                r = r - float(B[i, j]) * U[j]
+        m.state_equation(X[i], r)
+    E = [X[i] - m.setpoint(i) for i in range(nx)]
+    f = 0.0
+    for i in range(nx):
+        for j in range(nx):
+            if Q[i, j] != 0.0:
+                f = f + float(Q[i, j]) * E[i] * E[j]
+    for i in range(nu):
+        for j in range(nu):
+            if R[i, j] != 0.0:
+                f = f + float(R[i, j]) * U[i] * U[j]
+    m.minimize(f)
+    for j in range(nu):
+        m.guess(U[j], 0.0)
+    return m
+
+
+def reflux_model(N=32, Nf=17, D=0.2, F=0.4, alpha=1.6, xf=0.5, Ac=0.5, At=0.25, Ar=1.0, w_u=0.1,
+                 x_lo=0.0, x_hi=1.0, u_lo=1.0, u_hi=5.0, flow_hi=10.0) -> StageModel:
+    """Setpoint (xbar, ubar): tracking of the condenser composition and the
+    reflux ratio; stage layout [x_1..x_N, u, y_1..y_N, L, V, S]."""
+    m = StageModel(f"reflux_N{N}_Nf{Nf}", n_setpoint=2)
+    x = [None] + [m.state(f"x{i}", x_lo, x_hi) for i in range(1, N + 1)]
+    u = m.control("u", u_lo, u_hi)
+    y = [None] + [m.algebraic_var(f"y{i}", x_lo, x_hi) for i in range(1, N + 1)]
+    L = m.algebraic_var("L", 0.0, flow_hi)
+    V = m.algebraic_var("V", 0.0, flow_hi)
+    S = m.algebraic_var("S", 0.0, flow_hi)
+    m.dynamics(x[1], V * (y[2] - x[1]) / Ac)
+    for i in range(2, N):
+        lin = L if i <= Nf else S
+        lout = L if i < Nf else S
+        f = lin * x[i - 1] - lout * x[i] - V * (y[i] - y[i + 1])
+        if i == Nf:
+            f = f + F * xf
+        m.dynamics(x[i], f / At)
+    m.dynamics(x[N], (S * x[N - 1] - (F - D) * x[N] - V * y[N]) / Ar)
+    for i in range(1, N + 1):
+        m.equality(y[i] - alpha * x[i] / (1.0 + (alpha - 1.0) * x[i]))
+    m.equality(L - u * D)
+    m.equality(V - L - D)
+    m.equality(S - L - F)
+    m.minimize(m.dt * ((x[1] - m.setpoint(0)) ** 2 + w_u * (u - m.setpoint(1)) ** 2))
+    # cold start: measured trays, last reflux ratio, its equilibrium vapour and flows
+    up = m.u_prev(0)
+    for i in range(1, N + 1):
+        xi = m.x0(i - 1)
+        m.guess(y[i], alpha * xi / (1.0 + (alpha - 1.0) * xi))
+    m.guess(L, up * D)
+    m.guess(V, up * D + D)
+    m.guess(S, up * D + F)
+    return m

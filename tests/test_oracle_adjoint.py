@@ -156,3 +156,35 @@ def test_plate_setpoint_gradient_envelope_theorem():
     T = st.y.reshape(m.H, m.ns)[:, :m.nx]
     partial = -2.0 * np.sum(T - m.target[None, :], axis=0)
     assert np.allclose(sens["setpoint"]["df"], partial, rtol=0, atol=1e-5)
+
+
+def test_toy_sensitivities_match_central_differences():
+    """The toy problem of the re-solve listing with an explicit trajectory: d u1
+    and d f* with respect to y0 and to the tracked value of two stages, against
+    central differences of fixed-mu re-solves (this pins the toy's
+    parameter_derivatives, which only the sensitivity solve uses)."""
+    from oracle.toy import ToyOCP
+    m = ToyOCP()
+    m.set_parameters(y0=0.7, traj=np.sin(m.t + 0.4))
+    ipm, res = _solve_cold(m)
+    mu = res.mu
+    st = ipm.solve(res.state, mu, fixed_mu=True, tol=1e-13).state
+    sens = sensitivities(ipm, st)
+    base = dict(y0=np.array([m.y0]), traj=m.traj.copy())
+    h = 1e-6
+    for group, idx in (("y0", 0), ("traj", 0), ("traj", 5)):
+        def setter(v, g=group):
+            m.set_parameters(**{g: (v[0] if g == "y0" else v)})
+        vals = []
+        for sgn in (+1, -1):
+            v = base[group].copy()
+            v[idx] += sgn * h
+            s2 = _fixed_mu_resolve(ipm, m, st, mu, setter, v)
+            vals.append((m.u1(s2.y), m.f(s2.y)))
+        setter(base[group])
+        du_fd = (vals[0][0] - vals[1][0]) / (2 * h)
+        df_fd = (vals[0][1] - vals[1][1]) / (2 * h)
+        du = sens[group]["du1"][:, idx]
+        df = sens[group]["df"][idx]
+        assert np.max(np.abs(du - du_fd)) <= 1e-5 * max(1e-3, np.max(np.abs(du_fd))) + 1e-7, (group, idx, du, du_fd)
+        assert abs(df - df_fd) <= 1e-5 * max(1e-3, abs(df_fd)) + 1e-7, (group, idx, df, df_fd)

@@ -12,5 +12,6 @@ from .generators import (  # noqa: F401
     plate_workload,
     RefluxWorkload,
     reflux_workload,
+    random_lq,
     WORKLOADS,
 )

@@ -231,3 +231,20 @@ def reflux_workload(**over) -> RefluxWorkload:
     if w.x0 is None:
         w.x0 = np.linspace(0.85, 0.12, w.N)
     return w
+
+
+def random_lq(nx, nu, H, seed, spectral_radius=0.95, indefinite=False):
+    """Seeded stable (A, B) and SPD weights (Q may be made indefinite)."""
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(nx, nx))
+    A *= spectral_radius / max(abs(np.linalg.eigvals(A)))
+    B = rng.normal(size=(nx, nu))
+    M = rng.normal(size=(nx, nx))
+    Q = M @ M.T / nx + 0.1 * np.eye(nx)
+    if indefinite:
+        Q[0, 0] -= 2.0 * (np.max(np.linalg.eigvalsh(Q)) + 1.0)
+    Mr = rng.normal(size=(nu, nu))
+    Rw = Mr @ Mr.T / nu + 0.5 * np.eye(nu)
+    x0 = rng.normal(size=nx)
+    xs = rng.normal(size=nx) * 0.5
+    return A, B, Q, Rw, x0, xs
