@@ -71,10 +71,14 @@ enum {
  * n_alg_rows equality rows: first one row per state, which may also involve
  * the previous stage's states (the measured state x0 at stage 1), linearly
  * with the constant coefficients prev_coef, then the algebraic rows, which
- * involve the stage's own variables only.  The objective is a sum of one term
- * per stage in the stage's variables, the setpoint and the stage's
- * trajectory value.  The stage Hessian of the Lagrangian is given by its lower
- * pattern (w_rows >= w_cols).  No inequality rows (bounds go in lb / ub).
+ * involve the stage's own variables only.  Each stage also has n_ineq_rows
+ * inequality rows d(stage) <= 0 in its own variables (stage-major after all
+ * equality rows).  The objective is a sum of one term per stage in the
+ * stage's variables, the previous stage's controls (u_prev at stage 1), the
+ * setpoint and the stage's trajectory value.  The Hessian of the Lagrangian
+ * is given per stage by its lower pattern within the stage (w_rows >= w_cols)
+ * and, for stages 2..H, by the entries between the stage's variables and the
+ * previous stage's controls (wx_rows, wx_cols).  Bounds go in lb / ub.
  *
  * The three kernels (value/derivative evaluation, cold-start guess, parameter
  * contractions of the sensitivities) come in a gfx950 code object written for
@@ -95,9 +99,15 @@ typedef struct nmpc_stage_model {
     const int32_t* prev_ptr;    /* rps + 1: previous-stage state columns of each row (state rows only) ... */
     const int32_t* prev_cols;   /* ... strictly ascending, in [0, nx) */
     const double* prev_coef;    /* their constant coefficients, finite and nonzero */
+    int32_t n_ineq_rows;        /* inequality rows per stage */
+    const int32_t* ineq_ptr;    /* n_ineq_rows + 1: own-stage columns of each inequality row ... */
+    const int32_t* ineq_cols;   /* ... strictly ascending, in [0, ns) */
     int32_t nw;                 /* lower Hessian entries per stage */
     const int32_t* w_rows;      /* nw: (w_rows[e], w_cols[e]), w_rows[e] >= w_cols[e], in [0, ns), distinct */
     const int32_t* w_cols;
+    int32_t nw_cross;           /* Hessian entries per stage with the previous stage's controls (stages 2..H) */
+    const int32_t* wx_rows;     /* nw_cross: the stage's variable, in [0, ns) ... */
+    const int32_t* wx_cols;     /* ... and the previous stage's control, in [0, nu); pairs distinct */
     const double* lb;           /* ns: variable bounds of every stage; -inf / +inf for none, lb < ub */
     const double* ub;
     const void* code_object;    /* the kernels' code object ... */

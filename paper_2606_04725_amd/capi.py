@@ -25,8 +25,10 @@ class nmpc_stage_model(C.Structure):
                 ("n_setpoint", C.c_int32), ("uses_traj", C.c_int32),
                 ("row_ptr", C.POINTER(C.c_int32)), ("row_cols", C.POINTER(C.c_int32)),
                 ("prev_ptr", C.POINTER(C.c_int32)), ("prev_cols", C.POINTER(C.c_int32)),
-                ("prev_coef", C.POINTER(C.c_double)), ("nw", C.c_int32),
-                ("w_rows", C.POINTER(C.c_int32)), ("w_cols", C.POINTER(C.c_int32)),
+                ("prev_coef", C.POINTER(C.c_double)), ("n_ineq_rows", C.c_int32),
+                ("ineq_ptr", C.POINTER(C.c_int32)), ("ineq_cols", C.POINTER(C.c_int32)), ("nw", C.c_int32),
+                ("w_rows", C.POINTER(C.c_int32)), ("w_cols", C.POINTER(C.c_int32)), ("nw_cross", C.c_int32),
+                ("wx_rows", C.POINTER(C.c_int32)), ("wx_cols", C.POINTER(C.c_int32)),
                 ("lb", C.POINTER(C.c_double)), ("ub", C.POINTER(C.c_double)),
                 ("code_object", C.c_void_p), ("code_object_size", C.c_uint64), ("tag", C.c_uint64)]
 

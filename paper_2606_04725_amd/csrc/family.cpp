@@ -279,15 +279,18 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
     if (s.horizon < 1 || !(s.dt > 0) || !std::isfinite(s.dt) || s.control_horizon != 0)
         return bad("need horizon >= 1, finite dt > 0, control_horizon 0");
     if (g->nx < 1 || g->nu < 1 || g->nu > 16 || g->na < 0 || g->n_alg_rows < 0 || g->n_setpoint < 0 ||
-        (g->uses_traj != 0 && g->uses_traj != 1) || g->nw < 0)
-        return bad("need nx >= 1, 1 <= nu <= 16, na, n_alg_rows, n_setpoint, nw >= 0, uses_traj 0 or 1");
+        (g->uses_traj != 0 && g->uses_traj != 1) || g->nw < 0 || g->n_ineq_rows < 0 || g->nw_cross < 0)
+        return bad("need nx >= 1, 1 <= nu <= 16, na, n_alg_rows, n_ineq_rows, n_setpoint, nw, nw_cross >= 0, "
+                   "uses_traj 0 or 1");
     if (!g->row_ptr || !g->prev_ptr || !g->lb || !g->ub || !g->code_object || g->code_object_size == 0 ||
-        g->tag == 0 || (g->nw > 0 && (!g->w_rows || !g->w_cols)))
+        g->tag == 0 || (g->nw > 0 && (!g->w_rows || !g->w_cols)) || (g->n_ineq_rows > 0 && !g->ineq_ptr) ||
+        (g->nw_cross > 0 && (!g->wx_rows || !g->wx_cols)))
         return bad("missing pattern, bounds, code object or tag");
     const int64_t ns64 = (int64_t)g->nx + g->nu + g->na, rps64 = (int64_t)g->nx + g->n_alg_rows;
-    if (ns64 * s.horizon > (int64_t)1 << 30 || rps64 * s.horizon > (int64_t)1 << 29 || g->nw > (1 << 24))
+    if (ns64 * s.horizon > (int64_t)1 << 30 || (rps64 + g->n_ineq_rows) * s.horizon > (int64_t)1 << 29 ||
+        g->nw > (1 << 24) || g->nw_cross > (1 << 24))
         return bad("problem too large");
-    const int ns = (int)ns64, rps = (int)rps64, nx = g->nx, H = s.horizon;
+    const int ns = (int)ns64, rps = (int)rps64, nx = g->nx, H = s.horizon, nd = g->n_ineq_rows;
     if (g->row_ptr[0] != 0 || g->prev_ptr[0] != 0) return bad("row_ptr / prev_ptr must start at 0");
     for (int r = 0; r < rps; ++r) {
         if (g->row_ptr[r + 1] < g->row_ptr[r] || g->row_ptr[r + 1] - g->row_ptr[r] > ns ||
@@ -311,6 +314,19 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
             if (!std::isfinite(g->prev_coef[q]) || g->prev_coef[q] == 0.0) return bad("prev_coef not finite nonzero");
         }
     }
+    if (nd > 0) {
+        if (g->ineq_ptr[0] != 0) return bad("ineq_ptr must start at 0");
+        for (int r = 0; r < nd; ++r) {
+            if (g->ineq_ptr[r + 1] < g->ineq_ptr[r] || g->ineq_ptr[r + 1] - g->ineq_ptr[r] > ns)
+                return bad("ineq_ptr not monotone or a row too long");
+            if (g->ineq_ptr[r + 1] > g->ineq_ptr[r] && !g->ineq_cols) return bad("missing ineq_cols");
+            for (int q = g->ineq_ptr[r]; q < g->ineq_ptr[r + 1]; ++q) {
+                const int c = g->ineq_cols[q];
+                if (c < 0 || c >= ns || (q > g->ineq_ptr[r] && c <= g->ineq_cols[q - 1]))
+                    return bad("ineq_cols out of range or not strictly ascending");
+            }
+        }
+    }
     {
         std::vector<int64_t> keys;
         for (int e = 0; e < g->nw; ++e) {
@@ -320,6 +336,14 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
         }
         std::sort(keys.begin(), keys.end());
         if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return bad("repeated Hessian entry");
+        keys.clear();
+        for (int e = 0; e < g->nw_cross; ++e) {
+            const int a = g->wx_rows[e], b = g->wx_cols[e];
+            if (a < 0 || a >= ns || b < 0 || b >= g->nu) return bad("cross-stage Hessian entry out of range");
+            keys.push_back((int64_t)a * g->nu + b);
+        }
+        std::sort(keys.begin(), keys.end());
+        if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return bad("repeated cross-stage entry");
     }
     for (int j = 0; j < ns; ++j)
         if (std::isnan(g->lb[j]) || std::isnan(g->ub[j]) || !(g->lb[j] < g->ub[j]) || g->lb[j] == INFINITY ||
@@ -330,6 +354,8 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
     M.rps = rps;
     M.nsp = g->n_setpoint;
     M.nw = g->nw;
+    M.nwx = g->nw_cross;
+    M.nd = nd;
     M.traj = g->uses_traj != 0;
     M.tag = g->tag;
     const unsigned char* code = static_cast<const unsigned char*>(g->code_object);
@@ -346,8 +372,9 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
     st.H = H;
     st.n = H * ns;
     st.m_c = H * rps;
-    st.m_d = 0;
-    st.jptr.assign(st.m_c + 1, 0);
+    st.m_d = H * nd;
+    const int m = st.m_c + st.m_d;
+    st.jptr.assign(m + 1, 0);
     st.jcol.clear();
     for (int k = 0; k < H; ++k)
         for (int r = 0; r < rps; ++r) {
@@ -356,16 +383,30 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
             for (int q = g->row_ptr[r]; q < g->row_ptr[r + 1]; ++q) st.jcol.push_back(k * ns + g->row_cols[q]);
             st.jptr[k * rps + r + 1] = (int)st.jcol.size();
         }
-    st.jrow.resize(st.jcol.size());
-    for (int r = 0; r < st.m_c; ++r)
-        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) st.jrow[p] = r;
-    st.wrow.assign((size_t)g->nw * H, 0);
-    st.wcol.assign((size_t)g->nw * H, 0);
     for (int k = 0; k < H; ++k)
-        for (int e = 0; e < g->nw; ++e) {
-            st.wrow[(size_t)k * g->nw + e] = k * ns + g->w_rows[e];
-            st.wcol[(size_t)k * g->nw + e] = k * ns + g->w_cols[e];
+        for (int r = 0; r < nd; ++r) {
+            for (int q = g->ineq_ptr[r]; q < g->ineq_ptr[r + 1]; ++q) st.jcol.push_back(k * ns + g->ineq_cols[q]);
+            st.jptr[st.m_c + k * nd + r + 1] = (int)st.jcol.size();
         }
+    st.jrow.resize(st.jcol.size());
+    for (int r = 0; r < m; ++r)
+        for (int p = st.jptr[r]; p < st.jptr[r + 1]; ++p) st.jrow[p] = r;
+    // Hessian slots: stage 1 its own entries; stage k > 1 its own, then those
+    // with the previous stage's controls
+    const size_t nwo = (size_t)g->nw, nwx = (size_t)g->nw_cross;
+    st.wrow.clear();
+    st.wcol.clear();
+    for (int k = 0; k < H; ++k) {
+        for (size_t e = 0; e < nwo; ++e) {
+            st.wrow.push_back(k * ns + g->w_rows[e]);
+            st.wcol.push_back(k * ns + g->w_cols[e]);
+        }
+        if (k > 0)
+            for (size_t e = 0; e < nwx; ++e) {
+                st.wrow.push_back(k * ns + g->wx_rows[e]);
+                st.wcol.push_back((k - 1) * ns + nx + g->wx_cols[e]);
+            }
+    }
     st.lb.resize(st.n);
     st.ub.resize(st.n);
     for (int k = 0; k < H; ++k)

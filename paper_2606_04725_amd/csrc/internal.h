@@ -24,7 +24,7 @@ struct Structure {
     // stage-model family: copies of the descriptor's data (desc.stage_model
     // is cleared: the caller's descriptor is not kept)
     struct StageModel {
-        int ns = 0, rps = 0, nsp = 0, nw = 0;
+        int ns = 0, rps = 0, nsp = 0, nw = 0, nwx = 0, nd = 0;
         bool traj = false;
         uint64_t tag = 0;
         std::vector<unsigned char> code;

@@ -1090,16 +1090,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather_reflux(const InstPtrs* __
 // Stage k takes stage k + 1's values, the last stage keeps its own: variables by
 // stages of ns; lifted rows [plus | minus | inequality] with the stage-major
 // equality rows by stages of rps, the hold rows of the control horizon by held
-// stages of two, the inequality rows by stages of two.
+// stages of two, the inequality rows by stages of md / H.
 __device__ inline int shift_src_var(const InstPtrs& I, int j) {
     const int k = j / I.ns;
     return k < I.H - 1 ? j + I.ns : j;
 }
 
 __device__ inline int shift_src_row(const InstPtrs& I, int l) {
-    if (l >= 2 * I.mc) {
-        const int k = (l - 2 * I.mc) / 2;
-        return k < I.H - 1 ? l + 2 : l;
+    if (l >= 2 * I.mc) {   // I.md > 0 here: the inequality rows, md / H per stage
+        const int nd = I.md / I.H;
+        const int k = (l - 2 * I.mc) / nd;
+        return k < I.H - 1 ? l + nd : l;
     }
     const int r = l >= I.mc ? l - I.mc : l;
     const int dyn = I.H * I.rps;

@@ -95,17 +95,21 @@ def stage_model_structure(gen, H, dt, ordering=capi.NMPC_ORDER_NESTED_DISSECTION
         raise ValueError("the model has no code object (run simd.compile)")
     i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
     keep = dict(row_ptr=i32(gen.row_ptr), row_cols=i32(gen.row_cols), prev_ptr=i32(gen.prev_ptr),
-                prev_cols=i32(gen.prev_cols), prev_coef=_f64(gen.prev_coef), w_rows=i32(gen.w_rows),
-                w_cols=i32(gen.w_cols), lb=_f64(gen.lb), ub=_f64(gen.ub),
+                prev_cols=i32(gen.prev_cols), prev_coef=_f64(gen.prev_coef), ineq_ptr=i32(gen.ineq_ptr),
+                ineq_cols=i32(gen.ineq_cols), w_rows=i32(gen.w_rows), w_cols=i32(gen.w_cols),
+                wx_rows=i32(gen.wx_rows), wx_cols=i32(gen.wx_cols), lb=_f64(gen.lb), ub=_f64(gen.ub),
                 code=C.create_string_buffer(gen.code, len(gen.code)))
     d = capi.nmpc_stage_model()
     d.nx, d.nu, d.na, d.n_alg_rows = gen.nx, gen.nu, gen.na, gen.n_alg_rows
     d.n_setpoint, d.uses_traj = gen.n_setpoint, int(gen.uses_traj)
-    for k in ("row_ptr", "row_cols", "prev_ptr", "prev_cols", "w_rows", "w_cols"):
+    for k in ("row_ptr", "row_cols", "prev_ptr", "prev_cols", "ineq_ptr", "ineq_cols", "w_rows", "w_cols",
+              "wx_rows", "wx_cols"):
         setattr(d, k, _ip(keep[k]))
     for k in ("prev_coef", "lb", "ub"):
         setattr(d, k, _dp(keep[k]))
+    d.n_ineq_rows = len(gen.ineq_ptr) - 1
     d.nw = len(gen.w_rows)
+    d.nw_cross = len(gen.wx_rows)
     d.code_object = C.cast(keep["code"], C.c_void_p)
     d.code_object_size = len(gen.code)
     d.tag = gen.tag

@@ -244,7 +244,8 @@ def kinds(e):
 @dataclass
 class StageModel:
     """One stage of a transcribed OCP (see the module docstring).  Rows of a
-    stage: the state equations in state order, then the equality rows."""
+    stage: the state equations in state order, then the equality rows; the
+    inequality rows d(stage) <= 0 come after all equality rows."""
     name: str
     n_setpoint: int = 0
     uses_traj: bool = False
@@ -253,6 +254,7 @@ class StageModel:
     algebraic: list = field(default_factory=list)
     state_rows: dict = field(default_factory=dict)  # state index -> residual
     alg_rows: list = field(default_factory=list)
+    ineq_rows: list = field(default_factory=list)
     objective: Ex = ZERO
     guesses: dict = field(default_factory=dict)     # flat variable index -> expression
 
@@ -274,6 +276,13 @@ class StageModel:
         """The previous stage's value of state x (x0 at the first stage)."""
         assert x.op == "s" and x.args[0] == "x"
         return sym("px", x.args[1])
+
+    @staticmethod
+    def prev_control(u):
+        """The previous stage's value of control u (the last applied control,
+        u_prev, at the first stage); objective only."""
+        assert u.op == "s" and u.args[0] == "u"
+        return sym("pu", u.args[1])
 
     @staticmethod
     def x0(i):
@@ -310,6 +319,10 @@ class StageModel:
     def equality(self, e):
         self.alg_rows.append(lift(e))
 
+    def inequality(self, e):
+        """A row e(stage) <= 0."""
+        self.ineq_rows.append(lift(e))
+
     def minimize(self, e):
         self.objective = lift(e)
 
@@ -332,6 +345,10 @@ class StageModel:
     @property
     def rps(self):
         return self.nx + len(self.alg_rows)
+
+    @property
+    def nd(self):
+        return len(self.ineq_rows)
 
     def flat(self, v):
         kind, j = v.args
@@ -359,25 +376,35 @@ class StageModel:
 # ---- derivation -----------------------------------------------------------------------------
 @dataclass
 class Derived:
-    """Everything the kernels compute, as expressions, plus the patterns."""
+    """Everything the kernels compute, as expressions, plus the patterns.
+    Symbols besides the stage's own: 'l' / 'ld' (multipliers of the stage's
+    equality / inequality rows), 'pu' (previous stage's controls)."""
     model: StageModel
-    rows: list            # residual of each stage row
-    jcols: list           # own-stage columns of each row (ascending)
+    rows: list            # residual of each equality row
+    jcols: list           # own-stage columns of each equality row (ascending)
     jexpr: list           # d row / d v for those columns
     pcols: list           # previous-stage state columns of each state row (ascending)
     pcoef: list           # their constant coefficients
+    drows: list           # inequality rows
+    dcols: list
+    dexpr: list
     grad: list            # d phi / d v_j
-    wslots: list          # (a, b), a >= b, per-stage lower Hessian pattern
-    wexpr: list
+    gnext: list           # d phi / d pu_j: the next stage's term in control j's gradient
+    wslots: list          # (a, b), a >= b: per-stage lower Hessian pattern
+    wexpr: list           # its value from this stage's functions
+    wnext: list           # its value from the next stage's objective (pu, pu), else ZERO
+    xslots: list          # (a, b): the stage's variable a with the previous stage's control b
+    xexpr: list
     adj_sp: list          # per setpoint entry: contribution of one stage
     adj_tr: Ex            # contribution of one stage to its trajectory value
+    adj_up: list          # per control: the first stage's contribution to d/du_prev
     guess: list           # per flat variable
 
 
 _ALLOWED = {
     "row": {"x", "u", "a", "px", "sp", "tr", "dt"},
     "alg": {"x", "u", "a", "sp", "tr", "dt"},
-    "obj": {"x", "u", "a", "sp", "tr", "dt"},
+    "obj": {"x", "u", "a", "pu", "sp", "tr", "dt"},
     "guess": {"x0", "up", "sp", "tr", "dt"},
 }
 
@@ -388,19 +415,32 @@ def derive(m: StageModel) -> Derived:
         bad = kinds(e) - _ALLOWED["row" if r < m.nx else "alg"]
         if bad:
             raise ValueError(f"{m.name}: row {r} uses {sorted(bad)}")
+    for r, e in enumerate(m.ineq_rows):
+        bad = kinds(e) - _ALLOWED["alg"]
+        if bad:
+            raise ValueError(f"{m.name}: inequality row {r} uses {sorted(bad)}")
     bad = kinds(m.objective) - _ALLOWED["obj"]
     if bad:
         raise ValueError(f"{m.name}: objective uses {sorted(bad)}")
     V = [m.var(j) for j in range(m.ns)]
-    jcols, jexpr, pcols, pcoef = [], [], [], []
-    dmemo = {}
-    for r, e in enumerate(rows):
+    PU = [sym("pu", j) for j in range(m.nu)]
+    memo = {}
+
+    def d1(e, s):
+        return diff(e, s, memo.setdefault(s, {}))
+
+    def jac(e):
         cols, ex = [], []
         for j, v in enumerate(V):
-            d = diff(e, v, dmemo.setdefault(v, {}))
+            d = d1(e, v)
             if not is_const(d, 0.0):
                 cols.append(j)
                 ex.append(d)
+        return cols, ex
+
+    jcols, jexpr, pcols, pcoef = [], [], [], []
+    for r, e in enumerate(rows):
+        cols, ex = jac(e)
         if r < m.nx and r not in cols:
             raise ValueError(f"{m.name}: state row {r} does not depend on its own state")
         jcols.append(cols)
@@ -417,9 +457,18 @@ def derive(m: StageModel) -> Derived:
                 pk.append(d.args[0])
         pcols.append(pc)
         pcoef.append(pk)
-    grad = [diff(m.objective, v, dmemo.setdefault(("obj", j), {})) for j, v in enumerate(V)]
-    # Hessian of the Lagrangian f + sum_r l_r c_r, lower triangle of one stage
-    wslots, wexpr = [], []
+    dcols, dexpr = [], []
+    for e in m.ineq_rows:
+        cols, ex = jac(e)
+        dcols.append(cols)
+        dexpr.append(ex)
+    grad = [d1(m.objective, v) for v in V]
+    gpu = [d1(m.objective, s) for s in PU]
+    gnext = [ZERO] * m.ns
+    for j in range(m.nu):
+        gnext[m.nx + j] = gpu[j]
+    # Hessian of the Lagrangian f + sum_r l_r c_r + sum_r ld_r d_r
+    wslots, wexpr, wnext = [], [], []
     for a in range(m.ns):
         for b in range(a + 1):
             acc = diff(grad[a], V[b])
@@ -428,12 +477,29 @@ def derive(m: StageModel) -> Derived:
                     d2 = diff(jexpr[r][jcols[r].index(a)], V[b])
                     if not is_const(d2, 0.0):
                         acc = add(acc, mul(sym("l", r), d2))
-            if not is_const(acc, 0.0):
+            for r in range(m.nd):
+                if a in dcols[r] and b in dcols[r]:
+                    d2 = diff(dexpr[r][dcols[r].index(a)], V[b])
+                    if not is_const(d2, 0.0):
+                        acc = add(acc, mul(sym("ld", r), d2))
+            nxt = ZERO
+            if m.nx <= b <= a < m.nx + m.nu:
+                nxt = diff(gpu[a - m.nx], PU[b - m.nx])
+            if not (is_const(acc, 0.0) and is_const(nxt, 0.0)):
                 wslots.append((a, b))
                 wexpr.append(acc)
+                wnext.append(nxt)
+    xslots, xexpr = [], []
+    for a in range(m.ns):
+        for b in range(m.nu):
+            d2 = diff(grad[a], PU[b])
+            if not is_const(d2, 0.0):
+                xslots.append((a, b))
+                xexpr.append(d2)
 
     # parameter contraction of one stage for a parameter symbol s:
-    #   - sum_v w_v d2L/dv ds - sum_r al_r dc_r/ds + so df/ds
+    #   - sum_v w_v d2L/dv ds - sum_b wp_b d2f/dpu_b ds - sum_r al_r dc_r/ds + so df/ds
+    # (wp: the previous stage's control entries of w; not at the first stage)
     def contraction(s):
         dfs = diff(m.objective, s)
         acc = mul(sym("so"), dfs)
@@ -443,14 +509,32 @@ def derive(m: StageModel) -> Derived:
             if not is_const(dcs, 0.0):
                 acc = add(acc, neg(mul(sym("al", r), dcs)))
                 dLs = add(dLs, mul(sym("l", r), dcs))
+        for r, e in enumerate(m.ineq_rows):
+            dds = diff(e, s)
+            if not is_const(dds, 0.0):
+                acc = add(acc, neg(mul(sym("ald", r), dds)))
+                dLs = add(dLs, mul(sym("ld", r), dds))
         for j, v in enumerate(V):
             d2 = diff(dLs, v)
             if not is_const(d2, 0.0):
                 acc = add(acc, neg(mul(sym("w", j), d2)))
+        for b, pu in enumerate(PU):
+            d2 = diff(dfs, pu)
+            if not is_const(d2, 0.0):
+                acc = add(acc, neg(mul(sym("wp", b), d2)))
         return acc
 
     adj_sp = [contraction(sym("sp", j)) for j in range(m.n_setpoint)]
     adj_tr = contraction(sym("tr"))
+    # u_prev enters the first stage's objective only (as pu)
+    adj_up = []
+    for b in range(m.nu):
+        acc = mul(sym("so"), gpu[b])
+        for j, v in enumerate(V):
+            d2 = diff(gpu[b], v)
+            if not is_const(d2, 0.0):
+                acc = add(acc, neg(mul(sym("w", j), d2)))
+        adj_up.append(acc)
     guess = []
     for j in range(m.ns):
         g = m.guesses.get(j)
@@ -460,20 +544,25 @@ def derive(m: StageModel) -> Derived:
         if bad:
             raise ValueError(f"{m.name}: guess of variable {j} uses {sorted(bad)}")
         guess.append(g)
-    return Derived(m, rows, jcols, jexpr, pcols, pcoef, grad, wslots, wexpr, adj_sp, adj_tr, guess)
+    return Derived(m, rows, jcols, jexpr, pcols, pcoef, list(m.ineq_rows), dcols, dexpr, grad, gnext, wslots,
+                   wexpr, wnext, xslots, xexpr, adj_sp, adj_tr, adj_up, guess)
 
 
 # ---- C emission ----------------------------------------------------------------------------------
 class _Emitter:
-    """SSA emission with common-subexpression reuse across nested scopes."""
+    """SSA emission with common-subexpression reuse across nested scopes.
+    `names` maps symbol kinds to C text (format field {j}); the stage's own
+    variables read from the array named `vname`."""
 
-    def __init__(self, m: StageModel, names):
+    def __init__(self, m: StageModel, names, vname="V", indent=2):
         self.m = m
-        self.names = names          # symbol kind -> C text format
+        self.names = names
+        self.vname = vname
         self.scopes = [{}]
         self.lines = []
         self.n = 0
-        self.indent = 2
+        self.indent = indent
+        self.prefix = "t"
 
     def push(self):
         self.scopes.append({})
@@ -486,12 +575,9 @@ class _Emitter:
 
     def leaf(self, e):
         kind, j = e.args
-        if kind == "x":
-            return f"V[{j}]"
-        if kind == "u":
-            return f"V[{self.m.nx + j}]"
-        if kind == "a":
-            return f"V[{self.m.nx + self.m.nu + j}]"
+        if kind in ("x", "u", "a"):
+            off = {"x": 0, "u": self.m.nx, "a": self.m.nx + self.m.nu}[kind]
+            return f"{self.vname}[{off + j}]"
         fmt = self.names.get(kind)
         if fmt is None:
             raise ValueError(f"symbol {kind} not available here")
@@ -530,7 +616,7 @@ class _Emitter:
                 text = f"pow({s}, {p!r})"
         else:
             text = f"{op}({self.val(e.args[0])})"
-        name = f"t{self.n}"
+        name = f"{self.prefix}{self.n}"
         self.n += 1
         self.line(f"const double {name} = {text};")
         self.scopes[-1][e] = name
@@ -541,20 +627,29 @@ def _tag(src_hash: str) -> int:
     return int(src_hash[:15], 16)
 
 
+_EVAL_NAMES = {"px": "P[{j}]", "pu": "PU[{j}]", "sp": "SP[{j}]", "tr": "TR", "dt": "DT",
+               "l": "(om[row0 + {j}] - om[mc + row0 + {j}])", "ld": "om[2 * mc + drow0 + {j}]"}
+# the next stage's objective seen from this stage: its previous controls are ours
+_NEXT_NAMES = {"pu": "V[NX + {j}]", "sp": "SP[{j}]", "tr": "TR1", "dt": "DT"}
+
+
 def _source(d: Derived, tag: int) -> str:
     m = d.model
-    ns, nx, nu, rps = m.ns, m.nx, m.nu, m.rps
-    lanes = max(ns, rps, 1)
-    nw = len(d.wslots)
+    ns, nx, nu, rps, nd = m.ns, m.nx, m.nu, m.rps, m.nd
+    lanes = max(ns, rps, nd, 1)
+    nwo, nwx = len(d.wslots), len(d.xslots)
+    has_next = any(not is_const(e, 0.0) for e in d.gnext) or any(not is_const(e, 0.0) for e in d.wnext)
     out = []
     w = out.append
     w(f"// Kernels of the stage model '{m.name}', written by the stage-pattern front end.")
     w("#include \"kernels.h\"")
     w("using namespace nmpc;")
     w("namespace {")
-    w(f"constexpr int NS = {ns}, NX = {nx}, NU = {nu}, RPS = {rps}, NW = {max(nw, 1)}, LANES = {lanes}, "
-      f"NSP = {m.n_setpoint};")
+    w(f"constexpr int NS = {ns}, NX = {nx}, NU = {nu}, RPS = {rps}, ND = {nd}, NWO = {nwo}, NWX = {nwx}, "
+      f"LANES = {lanes}, NSP = {m.n_setpoint};")
     w(f"constexpr unsigned long long TAG = {tag}ULL;")
+    w("// Hessian slots of stage k: its own NWO, then (k > 0) NWX with the previous stage's controls")
+    w("__device__ inline int64_t woff(int k) { return k == 0 ? 0 : NWO + (int64_t)(k - 1) * (NWO + NWX); }")
     w("}  // namespace")
     w("")
     w("// descriptor layout these kernels were built against (checked at load)")
@@ -571,57 +666,93 @@ def _source(d: Derived, tag: int) -> str:
     w("    const double* __restrict__ y = src == kSrcIter ? I.y : I.yt;")
     w("    const double* __restrict__ om = src == kSrcUser ? I.dom : I.om;")
     w("    const double* V = y + (int64_t)k * NS;")
+    w("    const double* P = k > 0 ? y + (int64_t)(k - 1) * NS : I.x0;")
+    w("    const double* PU = k > 0 ? y + (int64_t)(k - 1) * NS + NX : I.uprev;")
+    w("    const bool next = k + 1 < I.H;")
+    w("    const double* V1 = next ? y + (int64_t)(k + 1) * NS : V;")
     w("    const double* SP = I.setp;")
     w("    const double TR = I.ntr > 0 ? I.zF[k] : 0.0;")
+    w("    const double TR1 = I.ntr > 0 && next ? I.zF[k + 1] : 0.0;")
     w("    const double DT = I.gm.dt;")
-    w("    const int row0 = k * RPS, mc = I.mc;")
-    w("    double* wv = I.wv + (int64_t)k * NW;")
-    w("    (void)V; (void)SP; (void)TR; (void)DT; (void)om; (void)mc; (void)wv;")
-    if nx > 0:
-        w("    const double* P = k > 0 ? y + (int64_t)(k - 1) * NS : I.x0;")
-        w("    (void)P;")
+    w("    const int row0 = k * RPS, drow0 = k * ND, mc = I.mc;")
+    w("    double* wv = I.wv + woff(k);")
+    w("    (void)V; (void)P; (void)PU; (void)V1; (void)SP; (void)TR; (void)TR1; (void)DT; (void)om; (void)mc;")
+    w("    (void)wv; (void)row0; (void)drow0;")
     w("    switch (j) {")
-    names = {"px": "P[{j}]", "sp": "SP[{j}]", "tr": "TR", "dt": "DT",
-             "l": "(om[row0 + {j}] - om[mc + row0 + {j}])"}
+    nslots = nwo + nwx
     slot_lane = {}
-    for s in range(nw):
-        slot_lane.setdefault(s % lanes, []).append(s)
+    for s_ in range(nslots):
+        slot_lane.setdefault(s_ % lanes, []).append(s_)
     for j in range(lanes):
-        em = _Emitter(m, names)
+        em = _Emitter(m, _EVAL_NAMES)
         em.line(f"case {j}: {{")
         em.indent += 1
         if j < rps:
-            v = em.val(d.rows[j])
-            em.line(f"I.c[row0 + {j}] = {v};")
+            em.line(f"I.c[row0 + {j}] = {em.val(d.rows[j])};")
+        if j < nd:
+            em.line(f"I.d[drow0 + {j}] = {em.val(d.drows[j])};")
         if j < ns:
             em.line(f"I.fterm[(int64_t)k * NS + {j}] = {em.val(m.objective) if j == 0 else '0.0'};")
-        full_j = (j < rps) or (j < ns) or slot_lane.get(j)
-        if full_j:
-            em.line("if (full) {")
-            em.indent += 1
-            em.push()
-            if j < rps:
-                em.line(f"double* jr = I.jv + I.jptr[row0 + {j}];")
-                q0 = 0
-                if d.pcols[j]:
-                    em.line("int q = 0;")
-                    em.line("if (k > 0) {")
-                    for c in d.pcoef[j]:
-                        em.line(f"    jr[q++] = {c!r};")
-                    em.line("}")
-                    for e in d.jexpr[j]:
-                        em.line(f"jr[q++] = {em.val(e)};")
-                else:
-                    for e in d.jexpr[j]:
-                        em.line(f"jr[{q0}] = {em.val(e)};")
-                        q0 += 1
-            if j < ns:
-                em.line(f"I.grad[(int64_t)k * NS + {j}] = {em.val(d.grad[j])};")
-            for s in slot_lane.get(j, []):
-                em.line(f"wv[{s}] = {em.val(d.wexpr[s])};")
-            em.pop()
-            em.indent -= 1
+        em.line("if (full) {")
+        em.indent += 1
+        em.push()
+        if j < rps:
+            em.line(f"double* jr = I.jv + I.jptr[row0 + {j}];")
+            if d.pcols[j]:
+                em.line("int q = 0;")
+                em.line("if (k > 0) {")
+                for c in d.pcoef[j]:
+                    em.line(f"    jr[q++] = {c!r};")
+                em.line("}")
+                for e in d.jexpr[j]:
+                    em.line(f"jr[q++] = {em.val(e)};")
+            else:
+                for q, e in enumerate(d.jexpr[j]):
+                    em.line(f"jr[{q}] = {em.val(e)};")
+        if j < nd:
+            em.line(f"double* jd = I.jv + I.jptr[mc + drow0 + {j}];")
+            for q, e in enumerate(d.dexpr[j]):
+                em.line(f"jd[{q}] = {em.val(e)};")
+        if j < ns:
+            em.line(f"double g = {em.val(d.grad[j])};")
+        mine = slot_lane.get(j, [])
+        for s_ in mine:
+            if s_ < nwo:
+                em.line(f"double w{s_} = {em.val(d.wexpr[s_])};")
+        if has_next and ((j < ns and not is_const(d.gnext[j], 0.0)) or
+                         any(s_ < nwo and not is_const(d.wnext[s_], 0.0) for s_ in mine)):
+            # the next stage's objective term in this stage's controls
+            nx_em = _Emitter(m, _NEXT_NAMES, vname="V1", indent=em.indent + 1)
+            nx_em.prefix = "n"
+            em.line("if (next) {")
+            body = []
+            if j < ns and not is_const(d.gnext[j], 0.0):
+                body.append(f"g += {nx_em.val(d.gnext[j])};")
+            for s_ in mine:
+                if s_ < nwo and not is_const(d.wnext[s_], 0.0):
+                    body.append(f"w{s_} += {nx_em.val(d.wnext[s_])};")
+            em.lines.extend(nx_em.lines)
+            for b in body:
+                em.line("    " + b)
             em.line("}")
+        if j < ns:
+            em.line(f"I.grad[(int64_t)k * NS + {j}] = g;")
+        for s_ in mine:
+            if s_ < nwo:
+                em.line(f"wv[{s_}] = w{s_};")
+        cross = [s_ for s_ in mine if s_ >= nwo]
+        if cross:
+            em.line("if (k > 0) {")
+            em.push()
+            em.indent += 1
+            for s_ in cross:
+                em.line(f"wv[{s_}] = {em.val(d.xexpr[s_ - nwo])};")
+            em.indent -= 1
+            em.pop()
+            em.line("}")
+        em.pop()
+        em.indent -= 1
+        em.line("}")
         em.line("break;")
         em.indent -= 1
         em.line("}")
@@ -690,23 +821,30 @@ def _source(d: Derived, tag: int) -> str:
     w("        out[q] = acc;")
     w("        return;")
     w("    }")
+    adj_names = {"sp": "SP[{j}]", "tr": "TR", "dt": "DT", "so": "so", "pu": "PU[{j}]",
+                 "l": "(om[row0 + {j}] - om[mc + row0 + {j}])", "ld": "om[2 * mc + drow0 + {j}]",
+                 "al": "I.adj_lam[row0 + {j}]", "ald": "I.adj_lam[mc + drow0 + {j}]",
+                 "w": "I.adj_w[(int64_t)k * NS + {j}]", "wp": "WP({j})"}
 
     def stage_body(expr, indent):
-        em = _Emitter(m, {"sp": "SP[{j}]", "tr": "TR", "dt": "DT", "so": "so",
-                          "l": "(om[row0 + {j}] - om[mc + row0 + {j}])", "al": "I.adj_lam[row0 + {j}]",
-                          "w": "I.adj_w[(int64_t)k * NS + {j}]"})
-        em.indent = indent
+        em = _Emitter(m, adj_names, indent=indent)
         v = em.val(expr)
         return em.lines, v
 
+    stage_setup = [
+        "const double* V = I.y + (int64_t)k * NS;",
+        "const double* PU = k > 0 ? I.y + (int64_t)(k - 1) * NS + NX : I.uprev;",
+        "const double TR = ntr > 0 ? I.zF[k] : 0.0;",
+        "const int row0 = k * RPS, drow0 = k * ND;",
+        "auto WP = [&](int b) { return k > 0 ? I.adj_w[(int64_t)(k - 1) * NS + NX + b] : 0.0; };",
+        "(void)V; (void)PU; (void)TR; (void)row0; (void)drow0; (void)WP;",
+    ]
     w("    if (q < NX + NSP) {")
     w("        const int jsp = q - NX;")
     w("        double acc = 0.0;")
     w("        for (int k = 0; k < I.H; ++k) {")
-    w("            const double* V = I.y + (int64_t)k * NS;")
-    w("            const double TR = ntr > 0 ? I.zF[k] : 0.0;")
-    w("            const int row0 = k * RPS;")
-    w("            (void)V; (void)TR; (void)row0;")
+    for line in stage_setup:
+        w("            " + line)
     w("            switch (jsp) {")
     for jsp, expr in enumerate(d.adj_sp):
         lines, v = stage_body(expr, 5)
@@ -723,16 +861,30 @@ def _source(d: Derived, tag: int) -> str:
     w("    }")
     w("    if (q < NX + NSP + ntr) {")
     w("        const int k = q - NX - NSP;")
-    w("        const double* V = I.y + (int64_t)k * NS;")
-    w("        const double TR = I.zF[k];")
-    w("        const int row0 = k * RPS;")
-    w("        (void)V; (void)TR; (void)row0;")
+    for line in stage_setup:
+        w("        " + line)
     lines, v = stage_body(d.adj_tr, 2)
     out.extend(lines)
     w(f"        out[q] = {v};")
     w("        return;")
     w("    }")
-    w("    if (q < NX + NSP + ntr + NU) out[q] = 0.0;")
+    w("    if (q < NX + NSP + ntr + NU) {")
+    w("        const int k = 0, jup = q - NX - NSP - ntr;")
+    for line in stage_setup:
+        w("        " + line)
+    w("        double acc = 0.0;")
+    w("        switch (jup) {")
+    for b, expr in enumerate(d.adj_up):
+        lines, v = stage_body(expr, 3)
+        w(f"            case {b}: {{")
+        out.extend(lines)
+        w(f"                acc = {v};")
+        w("                break;")
+        w("            }")
+    w("            default: break;")
+    w("        }")
+    w("        out[q] = acc;")
+    w("    }")
     w("}")
     w("")
     return "\n".join(out) + "\n"
@@ -755,8 +907,12 @@ class GeneratedModel:
     prev_ptr: np.ndarray
     prev_cols: np.ndarray
     prev_coef: np.ndarray
+    ineq_ptr: np.ndarray
+    ineq_cols: np.ndarray
     w_rows: np.ndarray
     w_cols: np.ndarray
+    wx_rows: np.ndarray
+    wx_cols: np.ndarray
     lb: np.ndarray
     ub: np.ndarray
     source: str
@@ -804,8 +960,12 @@ def generate(m: StageModel) -> GeneratedModel:
         row_ptr=row_ptr, row_cols=np.array([c for cs in d.jcols for c in cs], dtype=np.int32),
         prev_ptr=prev_ptr, prev_cols=np.array([c for cs in d.pcols for c in cs], dtype=np.int32),
         prev_coef=np.array([c for cs in d.pcoef for c in cs], dtype=np.float64),
+        ineq_ptr=np.concatenate([[0], np.cumsum([len(c) for c in d.dcols])]).astype(np.int32),
+        ineq_cols=np.array([c for cs in d.dcols for c in cs], dtype=np.int32),
         w_rows=np.array([a for a, _ in d.wslots], dtype=np.int32),
         w_cols=np.array([b for _, b in d.wslots], dtype=np.int32),
+        wx_rows=np.array([a for a, _ in d.xslots], dtype=np.int32),
+        wx_cols=np.array([b for _, b in d.xslots], dtype=np.int32),
         lb=lb, ub=ub, source=_source(d, tag), tag=tag, derived=d)
 
 

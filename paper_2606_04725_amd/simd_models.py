@@ -12,6 +12,12 @@ the library loads (family NMPC_FAMILY_STAGE_MODEL).
   reflux_model     the distillation case study of Section 4.1 with the
                    algebraic vapour fractions and flows kept as variables
                    (the same problem as the library's REFLUX_COLUMN family)
+  distillation_model
+                   the workload column (the library's DISTILLATION family):
+                   reflux R and boilup V as controls, the equilibrium
+                   substituted, feed composition as the stage trajectory,
+                   inequality rows for nonnegative distillate and bottoms and
+                   a move penalty on the previous stage's controls
 """
 from __future__ import annotations
 
@@ -97,4 +103,35 @@ def reflux_model(N=32, Nf=17, D=0.2, F=0.4, alpha=1.6, xf=0.5, Ac=0.5, At=0.25, 
     m.guess(L, up * D)
     m.guess(V, up * D + D)
     m.guess(S, up * D + F)
+    return m
+
+
+def distillation_model(N, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0) -> StageModel:
+    """States x_0 (condenser) .. x_{N+1} (reboiler), controls (R, V), feed on
+    tray N // 2 with composition the stage's trajectory value; objective
+    (x_0 - xD*)^2 + (x_{N+1} - xB*)^2 + rho |u - u_prev|^2 per stage with
+    (xD*, xB*) the setpoint; R - V <= 0 and V - R - F <= 0."""
+    m = StageModel(f"distillation_N{N}", n_setpoint=2)
+    x = [m.state(f"x{i}", x_lo, x_hi) for i in range(N + 2)]
+    R = m.control("R", u_lo, u_hi)
+    V = m.control("V", u_lo, u_hi)
+    fd = N // 2
+    zF = m.traj()
+
+    def vle(xi):
+        return alpha * xi / (1.0 + (alpha - 1.0) * xi)
+
+    m.dynamics(x[0], V * (vle(x[1]) - x[0]))
+    for i in range(1, N + 1):
+        lin = R if i <= fd else R + F
+        lout = R if i < fd else R + F
+        f = lin * x[i - 1] - lout * x[i] + V * (vle(x[i + 1]) - vle(x[i]))
+        if i == fd:
+            f = f + F * zF
+        m.dynamics(x[i], f)
+    m.dynamics(x[N + 1], (R + F) * x[N] - V * vle(x[N + 1]) - (R + F - V) * x[N + 1])
+    m.inequality(R - V)
+    m.inequality(V - R - F)
+    m.minimize((x[0] - m.setpoint(0)) ** 2 + (x[N + 1] - m.setpoint(1)) ** 2
+               + rho * ((R - m.prev_control(R)) ** 2 + (V - m.prev_control(V)) ** 2))
     return m

@@ -36,18 +36,21 @@ def ev(e, env, memo=None):
     return v
 
 
-def stage_env(d, y, k, x0, dt, setpoint=(), traj=None, lam=None, extra=None):
+def stage_env(d, y, k, x0, dt, setpoint=(), traj=None, lam=None, lam_d=None, u_prev=None, extra=None):
     """Symbol values of stage k (0-based)."""
     m = d.model
     ns = m.ns
     V = y[k * ns:(k + 1) * ns]
     P = y[(k - 1) * ns:(k - 1) * ns + m.nx] if k > 0 else x0
+    PU = y[(k - 1) * ns + m.nx:(k - 1) * ns + m.nx + m.nu] if k > 0 else u_prev
     env = {("dt", 0): dt, ("tr", 0): 0.0 if traj is None else traj[k]}
     for j in range(m.nx):
         env[("x", j)] = V[j]
         env[("px", j)] = P[j]
     for j in range(m.nu):
         env[("u", j)] = V[m.nx + j]
+        if PU is not None:
+            env[("pu", j)] = PU[j]
     for j in range(len(m.algebraic)):
         env[("a", j)] = V[m.nx + m.nu + j]
     for j, v in enumerate(setpoint):
@@ -55,27 +58,38 @@ def stage_env(d, y, k, x0, dt, setpoint=(), traj=None, lam=None, extra=None):
     if lam is not None:
         for r in range(m.rps):
             env[("l", r)] = lam[k * m.rps + r]
+    if lam_d is not None:
+        for r in range(m.nd):
+            env[("ld", r)] = lam_d[k * m.nd + r]
     if extra:
         env.update(extra)
     return env
 
 
-def expand(d, y, H, x0, dt, setpoint=(), traj=None, lam=None):
-    """f, grad, c, Jacobian values in the library's row order (previous-stage
-    columns first for stages after the first), Hessian values per stage slot,
-    with the (row, col) of each entry."""
+def expand(d, y, H, x0, dt, setpoint=(), traj=None, lam=None, lam_d=None, u_prev=None):
+    """f, grad, c, d, Jacobian values in the library's row order (equality
+    rows with previous-stage columns first for stages after the first, then
+    the inequality rows), Hessian values per stage slot (own entries, then
+    those with the previous stage's controls), with (row, col) of each."""
     m = d.model
-    ns, rps = m.ns, m.rps
+    ns, rps, nd, nx = m.ns, m.rps, m.nd, m.nx
+    mc = H * rps
+    envs = [stage_env(d, y, k, x0, dt, setpoint, traj, lam, lam_d, u_prev) for k in range(H)]
+    memos = [{} for _ in range(H)]
     f = 0.0
     grad = np.zeros(H * ns)
     c = np.zeros(H * rps)
+    dv = np.zeros(H * nd)
     jv, jr, jc, wv, wr, wc = [], [], [], [], [], []
     for k in range(H):
-        env = stage_env(d, y, k, x0, dt, setpoint, traj, lam)
-        memo = {}
+        env, memo = envs[k], memos[k]
+        nxt = k + 1 < H
         f += ev(m.objective, env, memo)
         for j in range(ns):
-            grad[k * ns + j] = ev(d.grad[j], env, memo)
+            g = ev(d.grad[j], env, memo)
+            if nxt:
+                g += ev(d.gnext[j], envs[k + 1], memos[k + 1])
+            grad[k * ns + j] = g
         for r in range(rps):
             c[k * rps + r] = ev(d.rows[r], env, memo)
             if k > 0:
@@ -87,31 +101,60 @@ def expand(d, y, H, x0, dt, setpoint=(), traj=None, lam=None):
                 jv.append(ev(e, env, memo))
                 jr.append(k * rps + r)
                 jc.append(k * ns + col)
-        if lam is not None:
-            for (a, b), e in zip(d.wslots, d.wexpr):
-                wv.append(ev(e, env, memo))
+    for k in range(H):
+        env, memo = envs[k], memos[k]
+        for r in range(nd):
+            dv[k * nd + r] = ev(d.drows[r], env, memo)
+            for col, e in zip(d.dcols[r], d.dexpr[r]):
+                jv.append(ev(e, env, memo))
+                jr.append(mc + k * nd + r)
+                jc.append(k * ns + col)
+    if lam is not None:
+        for k in range(H):
+            env, memo = envs[k], memos[k]
+            for (a, b), e, en in zip(d.wslots, d.wexpr, d.wnext):
+                v = ev(e, env, memo)
+                if k + 1 < H:
+                    v += ev(en, envs[k + 1], memos[k + 1])
+                wv.append(v)
                 wr.append(k * ns + a)
                 wc.append(k * ns + b)
-    return dict(f=f, grad=grad, c=c, jv=np.array(jv), jr=np.array(jr), jc=np.array(jc), wv=np.array(wv),
-                wr=np.array(wr), wc=np.array(wc))
+            if k > 0:
+                for (a, b), e in zip(d.xslots, d.xexpr):
+                    wv.append(ev(e, env, memo))
+                    wr.append(k * ns + a)
+                    wc.append((k - 1) * ns + nx + b)
+    return dict(f=f, grad=grad, c=c, d=dv, jv=np.array(jv), jr=np.array(jr, dtype=int),
+                jc=np.array(jc, dtype=int), wv=np.array(wv), wr=np.array(wr, dtype=int),
+                wc=np.array(wc, dtype=int))
 
 
-def contraction(d, y, H, x0, dt, setpoint, traj, lam, al, w, so):
+def contraction(d, y, H, x0, dt, setpoint, traj, lam, al, w, so, lam_d=None, u_prev=None):
     """The parameter contractions the adjoint kernel computes: per setpoint
-    entry (summed over stages) and per stage for the trajectory."""
+    entry (summed over stages), per stage for the trajectory, and for the
+    last applied control (first stage)."""
     m = d.model
-    ns, rps = m.ns, m.rps
+    ns, rps, nd, nx = m.ns, m.rps, m.nd, m.nx
+    mc = H * rps
     gsp = np.zeros(m.n_setpoint)
     gtr = np.zeros(H)
+    gup = np.zeros(m.nu)
     for k in range(H):
         extra = {("so", 0): so}
         for r in range(rps):
             extra[("al", r)] = al[k * rps + r]
+        for r in range(nd):
+            extra[("ald", r)] = al[mc + k * nd + r]
         for j in range(ns):
             extra[("w", j)] = w[k * ns + j]
-        env = stage_env(d, y, k, x0, dt, setpoint, traj, lam, extra)
+        for b in range(m.nu):
+            extra[("wp", b)] = w[(k - 1) * ns + nx + b] if k > 0 else 0.0
+        env = stage_env(d, y, k, x0, dt, setpoint, traj, lam, lam_d, u_prev, extra)
         memo = {}
         for j in range(m.n_setpoint):
             gsp[j] += ev(d.adj_sp[j], env, memo)
         gtr[k] = ev(d.adj_tr, env, memo)
-    return gsp, gtr
+        if k == 0:
+            for b in range(m.nu):
+                gup[b] = ev(d.adj_up[b], env, memo)
+    return gsp, gtr, gup

@@ -64,43 +64,66 @@ def _reflux(H):
     return w, m, p
 
 
+def _column(kind, seed=0, H=None):
+    """The workload column written with the front end, and the oracle's."""
+    from oracle.distillation import DistillationOCP
+    from workloads import distillation_workload
+    w = distillation_workload(kind, seed) if H is None else distillation_workload(kind, seed, H=H)
+    m = DistillationOCP.from_workload(w)
+    m.set_parameters(x0=w.x0, zF=w.zF(0), u_prev=w.u_prev0)
+    g = simd.compile(SM.distillation_model(w.N, w.alpha, F=w.F, rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi, u_lo=w.u_lo,
+                                           u_hi=w.u_hi))
+    p = N.Problem(N.stage_model_structure(g, w.H, w.dt))
+    p.analyze()
+    p.set_parameters(w.x0, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
+    return w, m, p
+
+
 def _case(name):
     if name == "toy":
         return _toy()
     if name == "lq":
         return _lq()[:2]
+    if name == "column":
+        return _column("small")[1:]
     return _reflux(10)[1:]
 
 
-@pytest.mark.parametrize("name", ["toy", "lq", "reflux"])
+@pytest.mark.parametrize("name", ["toy", "lq", "reflux", "column"])
 def test_generated_eval_matches_oracle(name):
+    import scipy.sparse as sps
     note(f"stage model eval {name}")
     m, p = _case(name)
     rng = np.random.default_rng(5)
     y = m.initial_guess() + 0.05 * rng.normal(size=m.n)
-    lam = rng.normal(size=m.m_c)
-    out = p.eval(y, lam, np.zeros(0))
+    lam, lam_d = rng.normal(size=m.m_c), rng.normal(size=m.m_d)
+    out = p.eval(y, lam, lam_d)
     pat = p.patterns()
     assert abs(out["f"] - m.f(y)) <= 1e-13 * max(1.0, abs(m.f(y)))
     assert rel_dev(out["grad"], m.grad(y)) <= 1e-13
     assert rel_dev(out["c"], m.cons_c(y)) <= 1e-13
-    J = m.jac_c(y).tocsr()
+    if m.m_d:
+        assert rel_dev(out["d"], m.cons_d(y)) <= 1e-13
+    J = sps.vstack([m.jac_c(y), m.jac_d(y)]).tocsr() if m.m_d else m.jac_c(y).tocsr()
     assert rel_dev(out["j_vals"], np.asarray(J[pat["j_rows"], pat["j_cols"]]).ravel()) <= 1e-13
-    W = m.hess(y, lam, np.zeros(0)).tocsr()
+    W = m.hess(y, lam, lam_d).tocsr()
     assert rel_dev(out["w_vals"], np.asarray(W[pat["w_rows"], pat["w_cols"]]).ravel()) <= 1e-13
 
 
 def _compare(ipm, sol, st, tol=1e-6):
-    lam, _ = ipm.multipliers(st)
-    for key, got, want in (("y", sol["y"], st.y), ("lam", sol["lam"], lam), ("zL", sol["zL"], st.zL),
-                           ("zU", sol["zU"], st.zU)):
+    lam, nu = ipm.multipliers(st)
+    for key, got, want in (("y", sol["y"], st.y), ("lam", sol["lam"], lam), ("nu", sol["omega_d"], nu),
+                           ("zL", sol["zL"], st.zL), ("zU", sol["zU"], st.zU)):
+        if len(want) == 0:
+            continue
         d = rel_dev(got, want)
         note(f"tightened {key}: {d:.2e}")
         assert d <= tol, (key, d)
 
 
 @pytest.mark.parametrize("name,route", [("toy", "lifted"), ("lq", "lifted"), ("reflux", "lifted"),
-                                        ("toy", "hykkt"), ("lq", "hykkt")])
+                                        ("column", "lifted"), ("toy", "hykkt"), ("lq", "hykkt"),
+                                        ("column", "hykkt")])
 def test_generated_solve_matches_oracle(name, route):
     note(f"stage model solve {name} {route}")
     m, p = _case(name)
@@ -149,6 +172,49 @@ def test_generated_case_study_equals_the_hand_written_family():
         assert d <= 1e-9, (key, d)
     sol = out[0][1]
     assert kkt_error(m, sol["y"], sol["lam"], sol["omega_d"], sol["zL"], sol["zU"])["max"] <= 1e-8
+
+
+def test_generated_workload_column_equals_the_hand_written_family():
+    """The headline workload (40 trays, horizon 100) written with the front
+    end and the library's DISTILLATION family, over a cold solve and five warm
+    re-solves of the workload's closed loop at the default options (both fed
+    the hand-written side's first stage): equal iteration counts, returned
+    points within 1e-7 of each other (both stop inside the default tolerance's
+    ball; their model values differ only by rounding order)."""
+    note("generated vs hand-written workload column, 40 trays, H=100")
+    w, m, pg = _column("medium")
+    ph = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+    ph.analyze()
+    sp = [w.xD_sp, w.xB_sp]
+    x0, up = w.x0, w.u_prev0
+    for k in range(6):
+        res = []
+        for p in (pg, ph):
+            p.set_parameters(x0, setpoint=sp, traj=w.zF(k), u_prev=up)
+            r = p.solve(warm=k > 0)
+            assert r.status == 0
+            res.append((r.iters, p.solution()))
+        note(f"solve {k}: iterations generated {res[0][0]} hand-written {res[1][0]}")
+        assert res[0][0] == res[1][0]
+        for key in ("y", "lam", "omega_d", "zL", "zU"):
+            d = rel_dev(res[0][1][key], res[1][1][key])
+            assert d <= 1e-7, (k, key, d)
+        up, x1 = res[1][1]["u1"], res[1][1]["x1"]
+        x0 = w.next_measurement(x1, k)
+
+
+def test_column_model_sensitivities_match_oracle():
+    note("stage model sensitivities: workload column (x0, setpoint, traj, u_prev)")
+    w, m, p = _column("small", seed=2)
+    ipm, st = _solved(m, p)
+    sens = sensitivities(ipm, st)
+    su, so = np.array([0.4, -1.1]), 0.3
+    rc, g = p.adjoint(su, so)
+    assert rc == 0
+    for key, rk in (("x0", "x0"), ("setpoint", "setpoint"), ("traj", "zF"), ("u_prev", "u_prev")):
+        d = rel_dev(g[key], su @ sens[rk]["du1"] + so * sens[rk]["df"])
+        note(f"{key}: {d:.2e}")
+        assert d <= 1e-6, (key, d)
 
 
 def _solved(m, p):

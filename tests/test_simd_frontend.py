@@ -5,11 +5,12 @@ gradient, Hessian of the Lagrangian, cold-start guess, parameter
 contractions) are evaluated on the host and compared with the oracle's own
 model functions, which are pinned by complex step elsewhere: the toy problem of
 the re-solve listing (Section 3.3), a linear-quadratic problem (dynamics
-through a constant matrix) and the distillation case study of Section 4.1
-with its algebraic variables.  Then: the patterns cover every nonzero, the
-C ABI takes the descriptor, rejects malformed ones, and the case-study model
-gets the same KKT pattern as the library's hand-written REFLUX_COLUMN
-family."""
+through a constant matrix), the distillation case study of Section 4.1 with
+its algebraic variables and the workload column (inequality rows, move
+penalty on the previous stage's controls).  Then: the patterns cover every
+nonzero, the C ABI takes the descriptor and rejects malformed ones, and the
+two columns get the same KKT pattern and symbolic analysis as the library's
+hand-written REFLUX_COLUMN and DISTILLATION families."""
 import ctypes as C
 
 import numpy as np
@@ -43,6 +44,17 @@ def _lq():
                 up=np.zeros(2), sp_group="xs", tr_group=None)
 
 
+def _distillation():
+    from oracle.distillation import DistillationOCP
+    m = DistillationOCP(6, 5, 0.1, 2.3, F=1.0, rho=0.05)
+    rng = np.random.default_rng(1)
+    m.set_parameters(x0=rng.uniform(0.1, 0.9, m.nx), zF=rng.uniform(0.4, 0.6, m.H), u_prev=[1.5, 2.2],
+                     setpoint=[0.93, 0.07])
+    gm = SM.distillation_model(6, 2.3, F=1.0, rho=0.05)
+    return dict(name="distillation", gm=gm, om=m, H=5, dt=0.1, x0=m.x0, sp=np.array([0.93, 0.07]), traj=m.zF,
+                up=m.u_prev, sp_group="setpoint", tr_group="zF", up_group="u_prev")
+
+
 def _reflux():
     m = RefluxColumnOCP(5, N=8, Nf=4, w_u=0.3)
     m.set_parameters(setpoint=[0.9, 2.4], u_prev=[2.2])
@@ -51,7 +63,7 @@ def _reflux():
                 up=np.array([2.2]), sp_group="setpoint", tr_group=None)
 
 
-CASES = {"toy": _toy, "lq": _lq, "reflux": _reflux}
+CASES = {"toy": _toy, "lq": _lq, "reflux": _reflux, "distillation": _distillation}
 
 
 def _point(c, rng):
@@ -71,25 +83,29 @@ def test_generated_expressions_equal_the_oracle_model(case):
     om = c["om"]
     rng = np.random.default_rng(4)
     y = _point(c, rng)
-    lam = rng.normal(size=om.m_c)
-    e = expand(d, y, c["H"], c["x0"], c["dt"], c["sp"], c["traj"], lam)
+    lam, lam_d = rng.normal(size=om.m_c), rng.normal(size=om.m_d)
+    e = expand(d, y, c["H"], c["x0"], c["dt"], c["sp"], c["traj"], lam, lam_d, c["up"])
     scale = lambda v: max(1.0, float(np.max(np.abs(v))))
     assert abs(e["f"] - om.f(y)) <= TOL * scale(om.f(y))
     assert np.max(np.abs(e["grad"] - om.grad(y))) <= TOL * scale(om.grad(y))
     assert np.max(np.abs(e["c"] - om.cons_c(y))) <= TOL * scale(om.cons_c(y))
-    J = om.jac_c(y).toarray()
+    if om.m_d:
+        assert np.max(np.abs(e["d"] - om.cons_d(y))) <= TOL * scale(om.cons_d(y))
+        J = np.vstack([om.jac_c(y).toarray(), om.jac_d(y).toarray()])
+    else:
+        J = om.jac_c(y).toarray()
     assert np.max(np.abs(e["jv"] - J[e["jr"], e["jc"]])) <= TOL * scale(J)
     mask = np.zeros_like(J, dtype=bool)
     mask[e["jr"], e["jc"]] = True
     assert np.all(J[~mask] == 0.0), "the oracle's Jacobian has an entry outside the generated pattern"
-    W = om.hess(y, lam, np.zeros(0)).toarray()
+    W = om.hess(y, lam, lam_d).toarray()
     assert np.max(np.abs(e["wv"] - W[e["wr"], e["wc"]])) <= TOL * scale(W)
     wmask = np.zeros_like(W, dtype=bool)
     wmask[e["wr"], e["wc"]] = True
     low = np.tril(np.ones_like(W, dtype=bool))
     assert np.all(W[low & ~wmask] == 0.0), "the oracle's Hessian has an entry outside the generated pattern"
     # rows are ordered previous-stage columns first, then own columns: ascending
-    for r in range(om.m_c):
+    for r in range(om.m_c + om.m_d):
         cols = e["jc"][e["jr"] == r]
         assert np.all(np.diff(cols) > 0)
 
@@ -122,12 +138,17 @@ def test_parameter_contractions_equal_differences_of_the_oracle(case):
     om = c["om"]
     rng = np.random.default_rng(9)
     y = _point(c, rng)
-    lam, al, w, so = rng.normal(size=om.m_c), rng.normal(size=om.m_c), rng.normal(size=om.n), 0.7
-    gsp, gtr = contraction(d, y, c["H"], c["x0"], c["dt"], c["sp"], c["traj"], lam, al, w, so)
+    lam, lam_d = rng.normal(size=om.m_c), rng.normal(size=om.m_d)
+    al, w, so = rng.normal(size=om.m_c + om.m_d), rng.normal(size=om.n), 0.7
+    gsp, gtr, gup = contraction(d, y, c["H"], c["x0"], c["dt"], c["sp"], c["traj"], lam, al, w, so, lam_d,
+                                c["up"])
 
     def phi():
         gl = om.grad(y) + om.jac_c(y).T @ lam
-        return -w @ gl - al @ om.cons_c(y) + so * om.f(y)
+        val = -w @ gl - al[:om.m_c] @ om.cons_c(y) + so * om.f(y)
+        if om.m_d:
+            val += -w @ (om.jac_d(y).T @ lam_d) - al[om.m_c:] @ om.cons_d(y)
+        return val
 
     def fd(setter, base, idx, h=1e-4):
         vals = []
@@ -147,9 +168,17 @@ def test_parameter_contractions_equal_differences_of_the_oracle(case):
     else:
         assert gsp.size == 0
     if c["tr_group"]:
+        g = c["tr_group"]
         for k in (0, 3, c["H"] - 1):
-            want = fd(lambda v: om.set_parameters(traj=v), c["traj"], k)
+            want = fd(lambda v: om.set_parameters(**{g: v}), c["traj"], k)
             assert abs(gtr[k] - want) <= 1e-8 * max(1.0, abs(want)), (k, gtr[k], want)
+    if c.get("up_group"):
+        g = c["up_group"]
+        for b in range(len(c["up"])):
+            want = fd(lambda v: om.set_parameters(**{g: v}), c["up"], b)
+            assert abs(gup[b] - want) <= 1e-8 * max(1.0, abs(want)), (b, gup[b], want)
+    else:
+        assert np.all(gup == 0.0)
 
 
 def test_model_validation():
@@ -189,6 +218,22 @@ def test_model_validation():
         simd.derive(m)
 
 
+def test_inequality_and_previous_control_validation():
+    m = simd.StageModel("ineq_prev")
+    x = m.state("x")
+    u = m.control("u")
+    m.dynamics(x, u)
+    m.inequality(u - m.prev(x))
+    with pytest.raises(ValueError):
+        simd.derive(m)
+    m = simd.StageModel("rows_prev_control")
+    x = m.state("x")
+    u = m.control("u")
+    m.dynamics(x, u - m.prev_control(u))
+    with pytest.raises(ValueError):
+        simd.derive(m)
+
+
 @pytest.fixture(scope="module")
 def compiled():
     return {k: simd.compile(CASES[k]()["gm"]) for k in CASES}
@@ -218,6 +263,23 @@ def test_case_study_model_gets_the_hand_written_pattern(compiled):
         assert sa == sb, rk
     assert pg.symbolic_sizes() == ph.symbolic_sizes()
     assert pg.n_setpoint == 2 and pg.n_traj == 0
+
+
+def test_workload_column_model_gets_the_hand_written_pattern(compiled):
+    """The front end's workload column (inequality rows, move penalty on the
+    previous stage's controls) and the DISTILLATION family: same sizes,
+    Jacobian and Hessian patterns (as sets) and symbolic analysis."""
+    H = 7
+    pg = N.Problem(N.stage_model_structure(compiled["distillation"], H, 0.1))
+    ph = N.Problem(N.distillation_structure(6, H, 0.1, 2.3, F=1.0, rho=0.05))
+    assert (pg.n, pg.m_c, pg.m_d, pg.nx, pg.nu, pg.nnz_k) == (ph.n, ph.m_c, ph.m_d, ph.nx, ph.nu, ph.nnz_k)
+    pg.analyze()
+    ph.analyze()
+    a, b = pg.patterns(), ph.patterns()
+    for rk, ck in (("j_rows", "j_cols"), ("w_rows", "w_cols")):
+        assert set(zip(a[rk].tolist(), a[ck].tolist())) == set(zip(b[rk].tolist(), b[ck].tolist())), rk
+    assert pg.symbolic_sizes() == ph.symbolic_sizes()
+    assert pg.n_setpoint == 2 and pg.n_traj == H
 
 
 def _create_rc(s):
