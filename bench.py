@@ -293,6 +293,81 @@ def run_case_study(N, eager=False):
             "paper_hardware": "NVIDIA RTX 6000 Ada, MadNLP + cuDSS, WS+PU (context only)"}
 
 
+def _loop_rate(N, p, w, steps, warmup, eager):
+    """The headline re-solve loop on one problem: cold solve, warm-up, then
+    `steps` timed warm re-solves (parameter upload, solve, first-stage
+    download), each step measured from its own first stage."""
+    import torch
+    sp = [w.xD_sp, w.xB_sp]
+    opts = N.default_options(timing=1, graph=0 if eager else 1)
+    p.set_parameters(w.x0, setpoint=sp, traj=w.zF(0), u_prev=w.u_prev0)
+    r0 = p.solve(warm=False)
+    u1, x1 = p.first_stage()
+    lat, iters, ms_eval, bad = [], 0, 0.0, int(r0.status != 0)
+    torch.cuda.synchronize()
+    t_begin = None
+    for k in range(warmup + steps):
+        if k == warmup:
+            torch.cuda.synchronize()
+            t_begin = time.perf_counter()
+        t = time.perf_counter()
+        p.set_parameters(w.next_measurement(x1, k), setpoint=sp, traj=w.zF(k + 1), u_prev=u1)
+        r = p.solve(warm=True, options=opts)
+        u1, x1 = p.first_stage()
+        if k >= warmup:
+            lat.append((time.perf_counter() - t) * 1e3)
+            iters += r.iters
+            ms_eval += r.ms_eval
+            bad += r.status != 0
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_begin
+    return {"iters_per_s": iters / elapsed, "p50_resolve_ms": _percentile(lat, 50),
+            "p99_resolve_ms": _percentile(lat, 99), "iters": iters, "eval_ms_per_resolve": ms_eval / steps,
+            "cold_iters": r0.iters, "nonzero_status": bad}
+
+
+def run_front_end(N, steps=30, warmup=2, eager=False):
+    """The headline workload written with the stage-pattern front end (its
+    kernels generated from the stage expressions) beside the hand-written
+    DISTILLATION family: the same closed re-solve loop on each, and the
+    paper's case study (150 NMPC steps) through the generated case-study
+    model beside the hand-written one."""
+    from paper_2606_04725_amd import simd, simd_models as SM
+    from workloads import distillation_workload, reflux_workload
+    w = distillation_workload("medium", 0, n_resolves=warmup + steps + 1)
+    g = simd.compile(SM.distillation_model(w.N, w.alpha, F=w.F, rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi,
+                                           u_lo=w.u_lo, u_hi=w.u_hi))
+    out = {"workload": f"distillation {w.N} trays, horizon {w.H}, dt {w.dt}, seed 0, {steps} warm re-solves "
+                       f"(same loop as the headline line, without autotuning)"}
+    for name, st in (("generated", N.stage_model_structure(g, w.H, w.dt)),
+                     ("hand_written", N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))):
+        p = N.Problem(st)
+        p.analyze()
+        out[name] = _loop_rate(N, p, w, steps, warmup, eager)
+        p.close()
+    _progress(f"front end: generated {out['generated']['iters_per_s']:.0f} iters/s, "
+              f"hand-written {out['hand_written']['iters_per_s']:.0f} iters/s")
+    rw = reflux_workload()
+    gr = simd.compile(SM.reflux_model(N=rw.N, Nf=rw.Nf, D=rw.D, F=rw.F, alpha=rw.alpha, xf=rw.xf, Ac=rw.Ac,
+                                      At=rw.At, Ar=rw.Ar, w_u=rw.w_u))
+    opts = N.default_options(graph=0 if eager else 1)
+    t0 = time.perf_counter()
+    p = N.Problem(N.stage_model_structure(gr, rw.H, rw.dt))
+    p.analyze()
+    x0, up = rw.x0.copy(), np.array([rw.u_prev0])
+    iters, bad = 0, 0
+    for k in range(rw.n_steps):
+        p.set_parameters(x0, setpoint=[rw.xbar, rw.ubar], u_prev=up)
+        r = p.solve(warm=k > 0, options=opts)
+        up, x0 = p.first_stage()
+        iters += r.iters
+        bad += r.status != 0
+    out["case_study_generated"] = {"total_s": time.perf_counter() - t0, "iters_total": iters, "nonzero_status": bad,
+                                   "final_x1": float(x0[0]), "final_u": float(up[0])}
+    p.close()
+    return out
+
+
 def run_mismatch(N, steps=30, seed=0, factor=1.08, eager=False):
     """Closed loop of the small column against a plant whose relative
     volatility is the model's times ``factor`` (plant-model mismatch), beside
@@ -561,6 +636,8 @@ def main(argv=None):
     ap.add_argument("--case-study-only", action="store_true",
                     help="only run the paper's distillation case study (150-step closed loop)")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
+    ap.add_argument("--front-end-only", action="store_true",
+                    help="only run the stage-pattern front end's legs (generated vs hand-written kernels)")
     ap.add_argument("--plate-case", choices=("plain", "adjoint", "both"), default="both",
                     help="with --plate-only: the 32x32x50 plate, the differentiated plate, or both")
     ap.add_argument("--adjoint-grid", type=int, default=64, help="grid of the differentiated form (64 in the full run)")
@@ -593,6 +670,9 @@ def main(argv=None):
         return 0
     if a.ablation_only:
         print(json.dumps({"ablation": ablations(N)}), flush=True)
+        return 0
+    if a.front_end_only:
+        print(json.dumps({"front_end": run_front_end(N, eager=a.eager)}), flush=True)
         return 0
     if a.batch_only:
         print(json.dumps({"batched": run_batched(N, eager=a.eager)}), flush=True)
@@ -702,6 +782,7 @@ def main(argv=None):
         out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
     out["case_study"] = run_case_study(N, eager=a.eager)
     out["mismatch"] = run_mismatch(N, eager=a.eager)
+    out["front_end"] = run_front_end(N, eager=a.eager)
     if not a.no_ablation:
         out["ablation"] = ablations(N)
     if not a.no_cpu_baseline:

@@ -662,7 +662,8 @@ def _source(d: Derived, tag: int) -> str:
     w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG || !ctl_active(I.ctl, pred)) return;")
     w("    const int t = lb * kBlock + threadIdx.x;")
     w("    if (t >= I.H * LANES) return;")
-    w("    const int k = t / LANES, j = t - k * LANES;")
+    w("    // lane-major over stages: the lanes of a wavefront take the same case")
+    w("    const int j = t / I.H, k = t - j * I.H;")
     w("    const double* __restrict__ y = src == kSrcIter ? I.y : I.yt;")
     w("    const double* __restrict__ om = src == kSrcUser ? I.dom : I.om;")
     w("    const double* V = y + (int64_t)k * NS;")
@@ -769,7 +770,7 @@ def _source(d: Derived, tag: int) -> str:
     w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG) return;")
     w("    const int t = lb * kBlock + threadIdx.x;")
     w("    if (t >= I.n) return;")
-    w("    const int k = t / NS, j = t - k * NS;")
+    w("    const int j = t / I.H, k = t - j * I.H;")
     w("    const double* SP = I.setp;")
     w("    const double TR = I.ntr > 0 ? I.zF[k] : 0.0;")
     w("    const double DT = I.gm.dt;")
@@ -788,7 +789,7 @@ def _source(d: Derived, tag: int) -> str:
         out.extend(em.lines)
     w("        default: break;")
     w("    }")
-    w("    I.y[t] = v;")
+    w("    I.y[(int64_t)k * NS + j] = v;")
     w("}")
     w("")
     # parameter contractions (instance 0)
