@@ -368,6 +368,57 @@ def run_front_end(N, steps=30, warmup=2, eager=False):
     return out
 
 
+PAPER_PLATE_CASE_TOTAL_S = 3.28   # Table 3: InfiniteExaModels + MadNLP + cuDSS, WS + PU, PDE plate
+
+
+def run_plate_case_study(N, eager=False):
+    """The heated-plate case study of Section 4.2 (Table 2) written with the
+    stage-pattern front end: 21 x 21 grid, horizon 12 stages of 0.08 s, 38
+    NMPC steps from t = 0 to 3 s with the setpoint schedule 58 / 55 / 63, plant
+    = model, symbolic analysis once and warm starts.  Timed end to end like
+    the distillation case study."""
+    from paper_2606_04725_amd import simd, simd_models as SM
+    from workloads import plate_case_workload
+    w = plate_case_workload()
+    g = simd.compile(SM.plate_case_model(n=w.n, alpha=w.alpha, Tb=w.Tb, loss=w.loss, rho=w.rho, Q_lo=w.Q_lo,
+                                         q_scale=w.q_scale, dt=w.dt))
+    opts = N.default_options(graph=0 if eager else 1)
+    t0 = time.perf_counter()
+    p = N.Problem(N.stage_model_structure(g, w.H, w.dt))
+    p.analyze()
+    t_an = time.perf_counter() - t0
+    nx = p.nx
+    x0, up = np.full(nx, w.T0), np.array([w.Q_prev0 / w.q_scale])
+    lat, iters, bad, qs, means = [], 0, 0, [], []
+    region = None
+    for k in range(w.n_steps):
+        t = time.perf_counter()
+        p.set_parameters(x0, traj=w.traj(k), u_prev=up)
+        r = p.solve(warm=k > 0, options=opts)
+        u1, x1 = p.first_stage()
+        lat.append((time.perf_counter() - t) * 1e3)
+        iters += r.iters
+        bad += r.status != 0
+        x0, up = x1, u1
+        qs.append(float(u1[0]) * w.q_scale)
+        if region is None:
+            gpts = w.n - 2
+            xs = -1.0 + (2.0 / (w.n - 1)) * np.arange(1, w.n - 1)
+            inside = np.abs(xs) <= 0.5 + 1e-12
+            region = np.outer(inside, inside).reshape(-1)
+        means.append(float(np.mean(x1[region])))
+    total = time.perf_counter() - t0
+    _progress(f"plate case study: {w.n_steps} NMPC steps in {total:.2f} s")
+    return {"workload": f"heated-plate case study of Section 4.2 (Table 2): {w.n} x {w.n} grid, horizon {w.H} x "
+                        f"{w.dt} s, {w.n_steps} NMPC steps, setpoint 58 / 55 / 63, plant = model, loss term read "
+                        f"as {w.loss}", "n": p.n, "total_s": total, "analyze_ms": t_an * 1e3,
+            "first_solve_ms": lat[0], "p50_step_ms": _percentile(lat[1:], 50),
+            "p99_step_ms": _percentile(lat[1:], 99), "iters_total": iters, "nonzero_status": bad,
+            "Q_first_last": [qs[0], qs[-1]], "region_mean_at_steps_6_18_37": [means[6], means[18], means[-1]],
+            "paper_total_s": PAPER_PLATE_CASE_TOTAL_S,
+            "paper_hardware": "NVIDIA RTX 6000 Ada, MadNLP + cuDSS, WS+PU (context only)"}
+
+
 def run_mismatch(N, steps=30, seed=0, factor=1.08, eager=False):
     """Closed loop of the small column against a plant whose relative
     volatility is the model's times ``factor`` (plant-model mismatch), beside
@@ -634,7 +685,7 @@ def main(argv=None):
                     help="skip the analyze-once/every-solve and warm/cold ablation")
     ap.add_argument("--ablation-only", action="store_true", help="only run the ablation")
     ap.add_argument("--case-study-only", action="store_true",
-                    help="only run the paper's distillation case study (150-step closed loop)")
+                    help="only run the paper's two case studies (distillation 150 steps, heated plate 38 steps)")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
     ap.add_argument("--front-end-only", action="store_true",
                     help="only run the stage-pattern front end's legs (generated vs hand-written kernels)")
@@ -666,7 +717,8 @@ def main(argv=None):
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     if a.case_study_only:
-        print(json.dumps({"case_study": run_case_study(N, eager=a.eager)}), flush=True)
+        print(json.dumps({"case_study": run_case_study(N, eager=a.eager),
+                          "plate_case_study": run_plate_case_study(N, eager=a.eager)}), flush=True)
         return 0
     if a.ablation_only:
         print(json.dumps({"ablation": ablations(N)}), flush=True)
@@ -781,6 +833,7 @@ def main(argv=None):
         out["plate"] = run_plate(N, eager=a.eager)
         out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
     out["case_study"] = run_case_study(N, eager=a.eager)
+    out["plate_case_study"] = run_plate_case_study(N, eager=a.eager)
     out["mismatch"] = run_mismatch(N, eager=a.eager)
     out["front_end"] = run_front_end(N, eager=a.eager)
     if not a.no_ablation:

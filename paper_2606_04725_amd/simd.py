@@ -429,10 +429,13 @@ def derive(m: StageModel) -> Derived:
     def d1(e, s):
         return diff(e, s, memo.setdefault(s, {}))
 
+    def own_vars(e):
+        return sorted(m.flat(s) for s in symbols(e) if s.args[0] in ("x", "u", "a"))
+
     def jac(e):
         cols, ex = [], []
-        for j, v in enumerate(V):
-            d = d1(e, v)
+        for j in own_vars(e):
+            d = d1(e, V[j])
             if not is_const(d, 0.0):
                 cols.append(j)
                 ex.append(d)
@@ -462,26 +465,29 @@ def derive(m: StageModel) -> Derived:
         cols, ex = jac(e)
         dcols.append(cols)
         dexpr.append(ex)
-    grad = [d1(m.objective, v) for v in V]
+    in_obj = set(own_vars(m.objective))
+    grad = [d1(m.objective, v) if j in in_obj else ZERO for j, v in enumerate(V)]
     gpu = [d1(m.objective, s) for s in PU]
     gnext = [ZERO] * m.ns
     for j in range(m.nu):
         gnext[m.nx + j] = gpu[j]
     # Hessian of the Lagrangian f + sum_r l_r c_r + sum_r ld_r d_r
+    # rows holding both columns of each lower pair, in row order
+    pair_rows = {}
+    for kind, cols_of, ex_of in (("l", jcols, jexpr), ("ld", dcols, dexpr)):
+        for r, cols in enumerate(cols_of):
+            for ia, a in enumerate(cols):
+                for b in cols[:ia + 1]:
+                    pair_rows.setdefault((a, b), []).append((kind, r, ex_of[r][ia]))
+    obj_vars = in_obj
     wslots, wexpr, wnext = [], [], []
     for a in range(m.ns):
         for b in range(a + 1):
-            acc = diff(grad[a], V[b])
-            for r in range(len(rows)):
-                if a in jcols[r] and b in jcols[r]:
-                    d2 = diff(jexpr[r][jcols[r].index(a)], V[b])
-                    if not is_const(d2, 0.0):
-                        acc = add(acc, mul(sym("l", r), d2))
-            for r in range(m.nd):
-                if a in dcols[r] and b in dcols[r]:
-                    d2 = diff(dexpr[r][dcols[r].index(a)], V[b])
-                    if not is_const(d2, 0.0):
-                        acc = add(acc, mul(sym("ld", r), d2))
+            acc = diff(grad[a], V[b]) if (a in obj_vars and b in obj_vars) else ZERO
+            for kind, r, ea in pair_rows.get((a, b), ()):
+                d2 = diff(ea, V[b])
+                if not is_const(d2, 0.0):
+                    acc = add(acc, mul(sym(kind, r), d2))
             nxt = ZERO
             if m.nx <= b <= a < m.nx + m.nu:
                 nxt = diff(gpu[a - m.nx], PU[b - m.nx])

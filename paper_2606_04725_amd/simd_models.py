@@ -18,6 +18,13 @@ the library loads (family NMPC_FAMILY_STAGE_MODEL).
                    substituted, feed composition as the stage trajectory,
                    inequality rows for nonnegative distillate and bottoms and
                    a move penalty on the previous stage's controls
+  plate_case_model the heated-plate case study of Section 4.2: (n - 2)^2
+                   interior temperatures of a grid on [-1, 1]^2 under a
+                   5-point Laplacian, heated through the left and bottom edges
+                   by the input Q (edge values 4.1 Q^(1/3) and Q^(1/2)),
+                   tracking of a region's temperature (trapezoid weights) as
+                   the stage trajectory; input in units of q_scale, rows
+                   divided by their diagonal coefficient
 """
 from __future__ import annotations
 
@@ -134,4 +141,47 @@ def distillation_model(N, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, 
     m.inequality(V - R - F)
     m.minimize((x[0] - m.setpoint(0)) ** 2 + (x[N + 1] - m.setpoint(1)) ** 2
                + rho * ((R - m.prev_control(R)) ** 2 + (V - m.prev_control(V)) ** 2))
+    return m
+
+
+def plate_case_model(n=21, alpha=230.0, Tb=50.0, loss=50.0, rho=1e-8, Q_lo=50.0, q_scale=1e4,
+                     dt=0.08) -> StageModel:
+    """Stage layout [T at the interior points (x1 fastest), q = Q / q_scale];
+    rows rs (T - T_prev - dt alpha (lap_h T - loss)) with rs = 1 / (1 + 4 dt
+    alpha / h^2); objective dt (sum_p w_p (T_p - T_sp)^2 + rho Q^2) with the
+    tracked temperature T_sp the stage's trajectory value and w_p the
+    trapezoid weights of [-0.5, 0.5]^2.  The stage length is a number of the
+    model here (the row scale depends on it): create the structure with the
+    same dt."""
+    g = n - 2
+    h = 2.0 / (n - 1)
+    rs = 1.0 / (1.0 + 4.0 * dt * alpha / (h * h))
+    m = StageModel(f"plate_case_n{n}")
+    T = [m.state(f"T{p}") for p in range(g * g)]
+    q = m.control("q", lb=Q_lo / q_scale)
+    Q = q_scale * q
+    left, bottom = 4.1 * Q ** (1.0 / 3.0), Q ** 0.5
+    for j in range(g):
+        for i in range(g):
+            p = j * g + i
+            west = T[p - 1] if i > 0 else left
+            east = T[p + 1] if i < g - 1 else Tb
+            south = T[p - g] if j > 0 else bottom
+            north = T[p + g] if j < g - 1 else Tb
+            lap = (west + east + south + north - 4.0 * T[p]) * (1.0 / (h * h))
+            m.state_equation(T[p], rs * (T[p] - m.prev(T[p])) - (rs * dt * alpha) * (lap - loss))
+    coord = [-1.0 + h * (i + 1) for i in range(g)]
+
+    def weight(x):
+        if abs(x) > 0.5 + 1e-12:
+            return 0.0
+        return 0.5 if abs(abs(x) - 0.5) < 1e-12 else 1.0
+
+    track = 0.0
+    for j in range(g):
+        for i in range(g):
+            wgt = weight(coord[i]) * weight(coord[j])
+            if wgt:
+                track = track + (h * h * wgt) * (T[j * g + i] - m.traj()) ** 2
+    m.minimize(dt * (track + rho * Q * Q))
     return m

@@ -13,5 +13,7 @@ from .generators import (  # noqa: F401
     RefluxWorkload,
     reflux_workload,
     random_lq,
+    PlateCaseWorkload,
+    plate_case_workload,
     WORKLOADS,
 )

@@ -248,3 +248,45 @@ def random_lq(nx, nu, H, seed, spectral_radius=0.95, indefinite=False):
     x0 = rng.normal(size=nx)
     xs = rng.normal(size=nx) * 0.5
     return A, B, Q, Rw, x0, xs
+
+
+@dataclass
+class PlateCaseWorkload:
+    """The heated-plate case study of Section 4.2 (Table 2): a 21 x 21 grid on
+    [-1, 1]^2 (spacing 0.1 = L), alpha 230, T_b 50, rho 1e-8, q_loss 10, Q >= 50;
+    NMPC steps of dt = 0.08 s from t = 0 to 3 s (38 steps), horizon 12 stages
+    (0.96 s: the printed 1.0 s is not a multiple of dt), setpoint 58 / 55 / 63
+    switching at 0.5 s and 1.5 s, plate initially at T_b (the paper gives no
+    T_0), plant = model.  The loss term is read as 5 q_loss (printed 5 q_loss^2;
+    see the design notes); the input enters the problem in units of q_scale."""
+    n: int = 21
+    alpha: float = 230.0
+    Tb: float = 50.0
+    q_loss: float = 10.0
+    loss: float = 50.0
+    rho: float = 1e-8
+    Q_lo: float = 50.0
+    q_scale: float = 1e4
+    dt: float = 0.08
+    H: int = 12
+    n_steps: int = 38
+    T0: float = 50.0
+    Q_prev0: float = 50.0
+
+    @staticmethod
+    def setpoint(t):
+        t = np.asarray(t, dtype=np.float64)
+        return np.where(t < 0.5, 58.0, np.where(t < 1.5, 55.0, 63.0))
+
+    def traj(self, k):
+        """Tracked temperature of the H stages of the solve at step k (t = k dt)."""
+        return self.setpoint(self.dt * (k + np.arange(1, self.H + 1)))
+
+    @property
+    def nx(self):
+        return (self.n - 2) ** 2
+
+
+def plate_case_workload(**over) -> PlateCaseWorkload:
+    return PlateCaseWorkload(**over)
+
