@@ -368,6 +368,75 @@ def run_front_end(N, steps=30, warmup=2, eager=False):
     return out
 
 
+def run_device_loop(N, steps=50, warmup=2, passes=(1, 2, 3)):
+    """Algorithm 1's loop with plant = model and the workload's measurement
+    noise, driven from the host (set_parameters, solve, first_stage per step)
+    and on the device (nmpc_closed_loop_dev: the parameter update and the
+    first passes of each re-solve in one captured graph), on the headline
+    column (40 trays, horizon 100) and the case study of Section 4.1."""
+    import torch
+    from workloads import distillation_workload, reflux_workload
+    w = distillation_workload("medium", 0, n_resolves=warmup + steps + 1)
+    sp = [w.xD_sp, w.xB_sp]
+    dev = torch.device("cuda")
+    traj = torch.tensor(np.array([w.zF(k + 1) for k in range(warmup + steps)]), dtype=torch.float64, device=dev)
+    noise = torch.tensor(w.resolve_noise[:warmup + steps], dtype=torch.float64, device=dev)
+
+    def fresh():
+        p = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
+        p.analyze()
+        p.autotune(reps=3)
+        p.set_parameters(w.x0, setpoint=sp, traj=w.zF(0), u_prev=w.u_prev0)
+        assert p.solve(warm=False).status == 0
+        return p
+
+    out = {"workload": f"distillation {w.N} trays, horizon {w.H}, seed 0: {steps} warm re-solves after {warmup}, "
+                       f"measurement = predicted x1 + the workload's noise"}
+    p = fresh()
+    u1, x1 = p.first_stage()
+    iters = 0
+    for k in range(warmup + steps):
+        if k == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        p.set_parameters(w.next_measurement(x1, k), setpoint=sp, traj=w.zF(k + 1), u_prev=u1)
+        r = p.solve(warm=True)
+        u1, x1 = p.first_stage()
+        if k >= warmup:
+            iters += r.iters
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["host_loop"] = {"iters_per_s": iters / el, "ms_per_resolve": el * 1e3 / steps, "iters": iters}
+    p.close()
+    for ppg in passes:
+        p = fresh()
+        rc, _, _ = p.closed_loop_dev(warmup, traj.data_ptr(), noise.data_ptr(), passes_per_step=ppg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, done, it = p.closed_loop_dev(steps, traj[warmup:].data_ptr(), noise[warmup:].data_ptr(),
+                                         passes_per_step=ppg)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"device_loop_{ppg}_passes"] = {"iters_per_s": it / el, "ms_per_resolve": el * 1e3 / steps,
+                                            "iters": it, "status": rc, "steps": done}
+        p.close()
+    # the case study, device loop (analysis and the cold first solve included)
+    rw = reflux_workload()
+    t0 = time.perf_counter()
+    p = N.Problem(N.reflux_structure(rw.H, dt=rw.dt))
+    p.analyze()
+    p.set_parameters(rw.x0, setpoint=[rw.xbar, rw.ubar], u_prev=[rw.u_prev0])
+    r0 = p.solve(warm=False)
+    rc, done, it = p.closed_loop_dev(rw.n_steps - 1, passes_per_step=2)
+    torch.cuda.synchronize()
+    out["case_study_device_loop"] = {"total_s": time.perf_counter() - t0, "iters_total": r0.iters + it,
+                                     "status": rc, "steps": done + 1}
+    p.close()
+    _progress(f"device loop: host {out['host_loop']['iters_per_s']:.0f} iters/s, device (2 passes) "
+              f"{out['device_loop_2_passes']['iters_per_s']:.0f} iters/s")
+    return out
+
+
 PAPER_PLATE_CASE_TOTAL_S = 3.28   # Table 3: InfiniteExaModels + MadNLP + cuDSS, WS + PU, PDE plate
 
 
@@ -687,6 +756,8 @@ def main(argv=None):
     ap.add_argument("--case-study-only", action="store_true",
                     help="only run the paper's two case studies (distillation 150 steps, heated plate 38 steps)")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
+    ap.add_argument("--device-loop-only", action="store_true",
+                    help="only run the closed loop driven from the host vs on the device")
     ap.add_argument("--front-end-only", action="store_true",
                     help="only run the stage-pattern front end's legs (generated vs hand-written kernels)")
     ap.add_argument("--plate-case", choices=("plain", "adjoint", "both"), default="both",
@@ -722,6 +793,9 @@ def main(argv=None):
         return 0
     if a.ablation_only:
         print(json.dumps({"ablation": ablations(N)}), flush=True)
+        return 0
+    if a.device_loop_only:
+        print(json.dumps({"device_loop": run_device_loop(N)}), flush=True)
         return 0
     if a.front_end_only:
         print(json.dumps({"front_end": run_front_end(N, eager=a.eager)}), flush=True)
@@ -836,6 +910,7 @@ def main(argv=None):
     out["plate_case_study"] = run_plate_case_study(N, eager=a.eager)
     out["mismatch"] = run_mismatch(N, eager=a.eager)
     out["front_end"] = run_front_end(N, eager=a.eager)
+    out["device_loop"] = run_device_loop(N)
     if not a.no_ablation:
         out["ablation"] = ablations(N)
     if not a.no_cpu_baseline:

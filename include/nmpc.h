@@ -437,6 +437,32 @@ nmpc_status nmpc_get_solution_dev(const nmpc_problem* p, double* y, double* lam,
 nmpc_status nmpc_adjoint_dev(nmpc_problem* p, const double* seed_u1, const double* seed_obj, double* grad_x0,
                              double* grad_setpoint, double* grad_traj, double* grad_uprev, void* stream);
 
+/* Closed loop on the device (Algorithm 1 with plant = model: the applied
+ * control and the next measurement never leave the GPU).  Starting from the
+ * held solution, for k = 0 .. steps-1: the solution's first stage is the
+ * applied control u1 and the predicted state x1 (written to row k of u_out,
+ * steps x nu, and of x_out, steps x nx, when not NULL); the next parameters
+ * are formed on the device: x0 = x1 + noise row k (noise: steps x nx, NULL =
+ * none), clipped to the first stage's state bounds; u_prev = u1; traj = row k
+ * of traj (steps x H, NULL = kept); the setpoint is kept; then the problem is
+ * re-solved warm (as nmpc_solve with warm = 1).  The parameter update, the
+ * reset of the interior-point control block and passes_per_step passes of the
+ * method are one captured graph, replayed once per step; the host then reads
+ * two integers and replays single passes until the solve stops, so a step
+ * costs one host round trip when it converges within passes_per_step passes.
+ * Every pointer is a device address on the handle's GPU owned by the caller;
+ * stream as for the _dev entry points.  Requires a held Lifted-KKT solution
+ * for the current parameters (BAD_ORDER otherwise) and options with
+ * kkt = NMPC_KKT_LIFTED and timing = 0 (INVALID_ARG otherwise);
+ * 1 <= passes_per_step <= 16.  Returns NMPC_OK when every step's solve
+ * succeeded, else the first failing solve's status (a positive outcome as
+ * nmpc_solve's), with *steps_done the number of steps taken (the failing one
+ * included) and *iters_total their interior-point iterations; the problem then
+ * holds that step's iterate and parameters (host copies updated). */
+nmpc_status nmpc_closed_loop_dev(nmpc_problem* p, int32_t steps, const double* traj, const double* noise,
+                                 double* u_out, double* x_out, int32_t passes_per_step, const nmpc_options* opts,
+                                 int32_t* steps_done, int32_t* iters_total, void* stream);
+
 /* Autotuner of the supernode front kernels (the batched form's tile shapes):
  * for every factor launch of the problem's schedule, time each variant of the
  * one-workgroup front kernel (threads per workgroup 128 / 256 / 512, panel

@@ -103,6 +103,9 @@ SIGNATURES = {
     "nmpc_adjoint_dev": (C.c_int32, [_P] + [C.c_void_p] * 7),
     "nmpc_jacobian_u1_x0": (C.c_int32, [_P, _D]),
     "nmpc_jacobian_u1_x0_noalloc": (C.c_int32, [_P, C.c_void_p, C.c_void_p]),
+    "nmpc_closed_loop_dev": (C.c_int32, [_P, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                         C.POINTER(nmpc_options), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.c_void_p]),
     "nmpc_solution_id": (C.c_int32, [_P, _L, _I]),
     "nmpc_autotune": (C.c_int32, [_P, C.c_int32, _I]),
     "nmpc_batch_create": (C.c_int32, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),

@@ -385,6 +385,38 @@ nmpc_status nmpc_solve(nmpc_problem* p, int32_t warm, const nmpc_options* opts, 
     });
 }
 
+nmpc_status nmpc_closed_loop_dev(nmpc_problem* p, int32_t steps, const double* traj, const double* noise,
+                                 double* u_out, double* x_out, int32_t passes_per_step, const nmpc_options* opts,
+                                 int32_t* steps_done, int32_t* iters_total, void* stream) {
+    if (!p || !steps_done || !iters_total) return fail(NMPC_ERR_INVALID_ARG, "closed_loop: NULL argument");
+    *steps_done = 0;
+    *iters_total = 0;
+    if (steps < 0 || passes_per_step < 1 || passes_per_step > 16)
+        return fail(NMPC_ERR_INVALID_ARG, "closed_loop: need steps >= 0 and 1 <= passes_per_step <= 16");
+    if (!p->impl.analyzed || !p->impl.dev) return fail(NMPC_ERR_BAD_ORDER, "closed_loop: call nmpc_analyze first");
+    if (!p->impl.have_iterate || !p->impl.params_current || p->impl.iter_hyk)
+        return fail(NMPC_ERR_BAD_ORDER, "closed_loop: needs a Lifted-KKT solution for the current parameters");
+    nmpc_options o;
+    if (!resolve_options(opts, o)) return fail(NMPC_ERR_INVALID_ARG, "closed_loop: invalid options");
+    if (o.kkt != NMPC_KKT_LIFTED || o.timing != 0)
+        return fail(NMPC_ERR_INVALID_ARG, "closed_loop: needs kkt = NMPC_KKT_LIFTED and timing = 0");
+    if (steps == 0) return NMPC_OK;
+    return guarded([&]() -> nmpc_status {
+        std::string err;
+        int done = 0, iters = 0;
+        nmpc_status rc = nmpc::device_closed_loop(p->impl, steps, traj, noise, u_out, x_out, passes_per_step, o,
+                                                  stream, &done, &iters, err);
+        *steps_done = done;
+        *iters_total = iters;
+        if (rc < 0) return fail(rc, err);
+        p->impl.have_iterate = true;
+        p->impl.params_current = true;
+        p->impl.iter_hyk = false;
+        p->impl.solution_id += done;
+        return rc;
+    });
+}
+
 nmpc_status nmpc_get_solution(const nmpc_problem* p, double* y, double* lam, double* omega_d, double* zL,
                               double* zU, double* u1, double* x1) {
     if (!p) return fail(NMPC_ERR_INVALID_ARG, "get_solution: NULL handle");

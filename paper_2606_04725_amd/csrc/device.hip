@@ -128,6 +128,18 @@ struct Batch {
     hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
     DevOpts graph_opts[4] = {};                       // options the graphs were captured with
     bool graph_failed[2] = {false, false};
+    // closed loop on the device: the parameter update, the control-block reset
+    // and a fixed number of passes, captured together (and what they were
+    // captured with)
+    hipGraph_t loop_graph = nullptr;
+    hipGraphExec_t loop_exec = nullptr;
+    struct LoopKey {
+        DevOpts o;
+        const void *traj, *noise, *u_out, *x_out;
+        int passes;
+    } loop_key{};
+    int* loop_ctr = nullptr;       // device: index of the next step
+    Ctl* loop_ctl = nullptr;       // pinned: the control block every step starts from
     std::vector<void*> allocs;
 };
 
@@ -216,9 +228,12 @@ void batch_release(Batch* B) {
         if (B->exec[k]) (void)hipGraphExecDestroy(B->exec[k]);
         if (B->graph[k]) (void)hipGraphDestroy(B->graph[k]);
     }
+    if (B->loop_exec) (void)hipGraphExecDestroy(B->loop_exec);
+    if (B->loop_graph) (void)hipGraphDestroy(B->loop_graph);
     for (void* a : B->allocs) (void)hipFree(a);
     if (B->hrunning) (void)hipHostFree(B->hrunning);
     if (B->hctl) (void)hipHostFree(B->hctl);
+    if (B->loop_ctl) (void)hipHostFree(B->loop_ctl);
     for (auto e : B->ev)
         if (e) (void)hipEventDestroy(e);
     if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
@@ -1284,6 +1299,142 @@ nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_resul
     return batch_solve(*p.dev->self, warm, o, &r, err);
 }
 
+// ---- closed loop on the device (Algorithm 1) ----------------------------------------------
+namespace {
+
+hipError_t join_in(Device& D, hipStream_t caller);
+hipError_t join_out(Device& D, hipStream_t caller);
+
+// Step k of the loop (k read from ctr): the held solution's first stage is the
+// applied control and the predicted state (rows k of u_out / x_out); the next
+// solve's parameters are x0 = x1 + noise row k clipped to the first stage's
+// state bounds, u_prev = u1 and traj = traj row k (each optional).  One block.
+__global__ void __launch_bounds__(kBlock)
+k_loop_update(const InstPtrs* __restrict__ Ia, int* ctr, const double* __restrict__ traj,
+              const double* __restrict__ noise, double* __restrict__ u_out, double* __restrict__ x_out) {
+    const InstPtrs& I = Ia[0];
+    __shared__ int k;
+    if (threadIdx.x == 0) k = *ctr;
+    __syncthreads();
+    const int nx = I.nx, nu = I.nu;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        const double x1 = I.y[i];
+        if (x_out) x_out[(int64_t)k * nx + i] = x1;
+        const double v = x1 + (noise ? noise[(int64_t)k * nx + i] : 0.0);
+        const_cast<double*>(I.x0)[i] = fmin(fmax(v, I.lb[i]), I.ub[i]);
+    }
+    for (int j = threadIdx.x; j < nu; j += blockDim.x) {
+        const double u1 = I.y[nx + j];
+        if (u_out) u_out[(int64_t)k * nu + j] = u1;
+        const_cast<double*>(I.uprev)[j] = u1;
+    }
+    if (traj)
+        for (int t = threadIdx.x; t < I.H; t += blockDim.x) const_cast<double*>(I.zF)[t] = traj[(int64_t)k * I.H + t];
+    __syncthreads();
+    if (threadIdx.x == 0) *ctr = k + 1;
+}
+
+}  // namespace
+
+nmpc_status device_closed_loop(Problem& p, int steps, const double* traj, const double* noise, double* u_out,
+                               double* x_out, int passes, const nmpc_options& o, void* caller_stream,
+                               int* steps_done, int* iters_total, std::string& err) {
+    Device& D = *p.dev;
+    Batch& B = *D.self;
+    const hipStream_t caller = static_cast<hipStream_t>(caller_stream);
+    const hipStream_t st = B.stream;
+    DevOpts dop = dev_opts(o);
+    *steps_done = 0;
+    *iters_total = 0;
+    if (!B.loop_ctr) HIP_TRY(dalloc(B.allocs, B.loop_ctr, 1));
+    if (!B.loop_ctl) HIP_TRY(hipHostMalloc((void**)&B.loop_ctl, sizeof(Ctl), hipHostMallocDefault));
+    // the control block of a warm solve, the same for every step (pinned; the
+    // captured copy reads it at each replay)
+    {
+        Ctl c{};
+        c.mu = o.mu0_warm;
+        c.tau = std::max(o.tau_min, 1.0 - c.mu);
+        c.E0 = INFINITY;
+        c.filter_mu = std::nan("");
+        c.nu = 1.0;
+        c.gamma = o.gamma;
+        c.status = kStatusRunning;
+        c.phase = kPhA;
+        *B.loop_ctl = c;
+    }
+    Batch::LoopKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.o = dop;
+    key.traj = traj;
+    key.noise = noise;
+    key.u_out = u_out;
+    key.x_out = x_out;
+    key.passes = passes;
+    if (!B.loop_exec || std::memcmp(&B.loop_key, &key, sizeof(key)) != 0) {
+        if (B.loop_exec) (void)hipGraphExecDestroy(B.loop_exec);
+        if (B.loop_graph) (void)hipGraphDestroy(B.loop_graph);
+        B.loop_exec = nullptr;
+        B.loop_graph = nullptr;
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipLaunchKernelGGL(k_loop_update, dim3(1), dim3(kBlock), 0, st, B.dI, B.loop_ctr, traj, noise, u_out, x_out);
+        (void)hipMemcpyAsync(B.ctl, B.loop_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st);
+        for (int k = 0; k < passes; ++k) enqueue_pass(B, dop, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (e == hipSuccess) e = hipGraphInstantiate(&B.loop_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            B.loop_exec = nullptr;
+            err = std::string("closed loop: graph capture failed: ") + hipGetErrorString(e);
+            return NMPC_ERR_HIP;
+        }
+        B.loop_graph = g;
+        B.loop_key = key;
+    }
+    const bool socs = o.soc_max > 0;
+    if (ensure_graph(B, dop, false, 0) != hipSuccess || (socs && ensure_graph(B, dop, false, 1) != hipSuccess)) {
+        err = "closed loop: pass graph capture failed";
+        return NMPC_ERR_HIP;
+    }
+    D.adj_ready = false;
+    D.gamma_last = o.gamma;
+    HIP_TRY(join_in(D, caller));
+    HIP_TRY(hipMemsetAsync(B.loop_ctr, 0, sizeof(int), st));   // not captured
+    const long max_passes = (long)(o.max_iter + 1) * (2L * o.ls_max + o.soc_max + 64) + 8;
+    int status = NMPC_OK;
+    for (int k = 0; k < steps; ++k) {
+        HIP_TRY(hipGraphLaunch(B.loop_exec, st));
+        long npass = passes;
+        while (true) {
+            HIP_TRY(hipMemcpyAsync(B.hrunning, B.running, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (B.hrunning[0] == 0) break;
+            if (npass >= max_passes) {
+                err = "closed loop: pass limit reached";
+                return NMPC_ERR_HIP;
+            }
+            if (B.hrunning[1] > 0) HIP_TRY(hipGraphLaunch(B.exec[2], st));
+            HIP_TRY(hipGraphLaunch(B.exec[0], st));
+            ++npass;
+        }
+        HIP_TRY(hipMemcpyAsync(B.hctl, B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        *iters_total += B.hctl[0].it;
+        status = B.hctl[0].status;
+        *steps_done = k + 1;
+        if (status != NMPC_OK) break;
+    }
+    // the host copies of the parameters follow the device's
+    const InstPtrs& I = D.hI;
+    HIP_TRY(hipMemcpyAsync(p.x0.data(), I.x0, p.x0.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(p.u_prev.data(), I.uprev, p.u_prev.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (traj) HIP_TRY(hipMemcpyAsync(p.traj.data(), I.zF, p.traj.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(join_out(D, caller));
+    return status;
+}
+
 nmpc_status batch_create(const std::vector<Problem*>& ps, Batch*& out, std::string& err) {
     std::vector<Device*> members;
     for (Problem* p : ps) members.push_back(p->dev);
@@ -1878,6 +2029,10 @@ void apply_variants(Device& D, const std::vector<int>& v) {
         B.exec[k] = nullptr;
         B.graph[k] = nullptr;
     }
+    if (B.loop_exec) (void)hipGraphExecDestroy(B.loop_exec);
+    if (B.loop_graph) (void)hipGraphDestroy(B.loop_graph);
+    B.loop_exec = nullptr;
+    B.loop_graph = nullptr;
 }
 
 }  // namespace

@@ -108,6 +108,11 @@ nmpc_status device_get_solution_dev(const Problem& p, double* y, double* lam, do
 nmpc_status device_adjoint_dev(Problem& p, const double* seed_u1, const double* seed_obj, double* gx0, double* gsp,
                                double* gtraj, double* gup, void* caller, std::string& err);
 nmpc_status device_solve(Problem& p, int warm, const nmpc_options& o, nmpc_result& r, std::string& err);
+// Closed loop on the device: per step the parameter update from the held
+// solution and `passes` passes in one captured graph, then passes until done.
+nmpc_status device_closed_loop(Problem& p, int steps, const double* traj, const double* noise, double* u_out,
+                               double* x_out, int passes, const nmpc_options& o, void* caller_stream,
+                               int* steps_done, int* iters_total, std::string& err);
 nmpc_status device_get_iterate(const Problem& p, double* y, double* s, double* om, double* be,
                                double* zl, double* zu, std::string& err);
 nmpc_status device_get_first_stage(const Problem& p, double* u1, double* x1, std::string& err);

@@ -274,6 +274,17 @@ class Problem:
                                                   grad_setpoint or None, grad_traj or None, grad_u_prev or None,
                                                   stream or None))
 
+    def closed_loop_dev(self, steps, traj=0, noise=0, u_out=0, x_out=0, passes_per_step=2,
+                        options: nmpc_options | None = None, stream=0):
+        """Device-resident closed loop (plant = model) from the held solution;
+        device addresses (0 = NULL).  Returns (status, steps_done, iters)."""
+        done, iters = C.c_int32(), C.c_int32()
+        rc = _check(capi.lib().nmpc_closed_loop_dev(self._h, int(steps), traj or None, noise or None, u_out or None,
+                                                    x_out or None, int(passes_per_step),
+                                                    None if options is None else C.byref(options), C.byref(done),
+                                                    C.byref(iters), stream or None))
+        return rc, done.value, iters.value
+
     def solution_id(self):
         """(id, current): id counts the iterates the handle has taken; current is
         False once parameters were set after the last one."""

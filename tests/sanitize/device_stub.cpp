@@ -27,6 +27,8 @@ nmpc_status device_get_solution_dev(const Problem&, double*, double*, double*, d
 nmpc_status device_adjoint_dev(Problem&, const double*, const double*, double*, double*, double*, double*, void*,
                                std::string& err) { return none(err); }
 nmpc_status device_solve(Problem&, int, const nmpc_options&, nmpc_result&, std::string& err) { return none(err); }
+nmpc_status device_closed_loop(Problem&, int, const double*, const double*, double*, double*, int,
+                               const nmpc_options&, void*, int*, int*, std::string& err) { return none(err); }
 nmpc_status device_get_iterate(const Problem&, double*, double*, double*, double*, double*, double*,
                                std::string& err) { return none(err); }
 nmpc_status device_get_first_stage(const Problem&, double*, double*, std::string& err) { return none(err); }
