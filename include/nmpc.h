@@ -113,6 +113,10 @@ typedef struct nmpc_stage_model {
     const void* code_object;    /* the kernels' code object ... */
     uint64_t code_object_size;  /* ... and its size in bytes */
     uint64_t tag;               /* the tag the kernels were generated with (nonzero) */
+    int64_t scratch_per_stage;  /* doubles of per-stage scratch the kernels accumulate into (>= 0); when
+                                   > 0 the code object also exports nmpc_stage_reduce, which the library
+                                   launches after every evaluation to sum the scratch into the Hessian,
+                                   gradient and objective terms; the library owns the array */
 } nmpc_stage_model;
 
 /* Fill-reducing ordering of the analysis (eq. 19): nested dissection of the

@@ -30,7 +30,8 @@ class nmpc_stage_model(C.Structure):
                 ("w_rows", C.POINTER(C.c_int32)), ("w_cols", C.POINTER(C.c_int32)), ("nw_cross", C.c_int32),
                 ("wx_rows", C.POINTER(C.c_int32)), ("wx_cols", C.POINTER(C.c_int32)),
                 ("lb", C.POINTER(C.c_double)), ("ub", C.POINTER(C.c_double)),
-                ("code_object", C.c_void_p), ("code_object_size", C.c_uint64), ("tag", C.c_uint64)]
+                ("code_object", C.c_void_p), ("code_object_size", C.c_uint64), ("tag", C.c_uint64),
+                ("scratch_per_stage", C.c_int64)]
 
 
 class nmpc_structure(C.Structure):

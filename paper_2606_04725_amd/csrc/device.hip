@@ -88,7 +88,14 @@ struct Device {
     // stage-model family: the generated kernels, loaded on this device
     hipModule_t mod = nullptr;
     hipFunction_t f_eval = nullptr, f_guess = nullptr, f_adj = nullptr;
+    hipFunction_t f_reduce = nullptr;   // pattern models: sums the per-stage scratch after an evaluation
     double* gm_jac = nullptr;      // nu x nx: d u1 / d x0 mapped through the state rows' coefficients
+};
+
+// Kernels of one generated stage model as a batch launches them.
+struct GenFns {
+    hipFunction_t eval, guess, reduce;
+    bool operator==(const GenFns& o) const { return eval == o.eval && guess == o.guess && reduce == o.reduce; }
 };
 
 // Emitted kernel launch of a batch schedule: a group launch (groups[off ..
@@ -116,7 +123,7 @@ struct Batch {
     // generated kernels of the stage models among the members (one entry per
     // distinct code object; each launch covers the batch, its kernels skip
     // instances with another tag)
-    std::vector<std::pair<hipFunction_t, hipFunction_t>> gen;   // (eval, guess)
+    std::vector<GenFns> gen;
     int* running = nullptr;        // device: instances running, instances waiting for corrections,
                                    // instances whose HyKKT conjugate gradients run
     int* hrunning = nullptr;       // pinned copy
@@ -274,8 +281,8 @@ nmpc_status batch_build(const std::vector<Device*>& members, hipStream_t stream,
         if (hI[i].family == NMPC_FAMILY_HEATED_PLATE) B->has_plate = true;
         if (hI[i].family == NMPC_FAMILY_REFLUX_COLUMN) B->has_reflux = true;
         if (hI[i].family == NMPC_FAMILY_STAGE_MODEL) {
-            const std::pair<hipFunction_t, hipFunction_t> f{members[i]->f_eval, members[i]->f_guess};
-            if (f.first && f.second && std::find(B->gen.begin(), B->gen.end(), f) == B->gen.end())
+            const GenFns f{members[i]->f_eval, members[i]->f_guess, members[i]->f_reduce};
+            if (f.eval && f.guess && std::find(B->gen.begin(), B->gen.end(), f) == B->gen.end())
                 B->gen.push_back(f);
         }
     }
@@ -390,7 +397,11 @@ void eval(Batch& B, bool full, int src, int pred) {
         int fl = full ? 1 : 0;
         void* args[] = {&dI, &sp, &src, &pred, &fl};
         if (sp.blocks > 0)
-            (void)hipModuleLaunchKernel(g.first, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, args, nullptr);
+            (void)hipModuleLaunchKernel(g.eval, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, args, nullptr);
+        // pattern models: sum the instances' contributions (same space, grid-stride inside)
+        void* rargs[] = {&dI, &sp, &pred, &fl};
+        if (sp.blocks > 0 && g.reduce)
+            (void)hipModuleLaunchKernel(g.reduce, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, rargs, nullptr);
     }
 }
 
@@ -401,7 +412,7 @@ void cold_guess(Batch& B) {
         const InstPtrs* dI = B.dI;
         void* args[] = {&dI, &sp};
         if (sp.blocks > 0)
-            (void)hipModuleLaunchKernel(g.second, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, args, nullptr);
+            (void)hipModuleLaunchKernel(g.guess, sp.blocks, 1, 1, kBlock, 1, 1, 0, B.stream, args, nullptr);
     }
 }
 
@@ -666,11 +677,19 @@ nmpc_status device_init(Problem& p, std::string& err) {
         I.rps = M.rps;
         I.nsp = M.nsp;
         I.ntr = M.traj ? st.H : 0;
-        I.gm = StageConst{s.dt, (unsigned long long)M.tag, nullptr};
+        I.gm = StageConst{s.dt, (unsigned long long)M.tag, nullptr, nullptr};
         DTRY(hipModuleLoadData(&D.mod, M.code.data()));
         DTRY(hipModuleGetFunction(&D.f_eval, D.mod, "nmpc_stage_eval"));
         DTRY(hipModuleGetFunction(&D.f_guess, D.mod, "nmpc_stage_guess"));
         DTRY(hipModuleGetFunction(&D.f_adj, D.mod, "nmpc_stage_adj"));
+        if (M.scratch > 0) {
+            if (hipModuleGetFunction(&D.f_reduce, D.mod, "nmpc_stage_reduce") != hipSuccess) {
+                (void)hipGetLastError();
+                err = "stage model: a model with per-stage scratch needs nmpc_stage_reduce in its code object";
+                return bail(NMPC_ERR_INVALID_ARG);
+            }
+            DTRY(dalloc(D.allocs, I.gm.scratch, (size_t)st.H * (size_t)M.scratch));
+        }
         hipDeviceptr_t abi_ptr = nullptr;
         size_t abi_bytes = 0;
         DTRY(hipModuleGetGlobal(&abi_ptr, &abi_bytes, D.mod, "nmpc_stage_abi"));

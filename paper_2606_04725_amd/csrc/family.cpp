@@ -279,16 +279,17 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
     if (s.horizon < 1 || !(s.dt > 0) || !std::isfinite(s.dt) || s.control_horizon != 0)
         return bad("need horizon >= 1, finite dt > 0, control_horizon 0");
     if (g->nx < 1 || g->nu < 1 || g->nu > 16 || g->na < 0 || g->n_alg_rows < 0 || g->n_setpoint < 0 ||
-        (g->uses_traj != 0 && g->uses_traj != 1) || g->nw < 0 || g->n_ineq_rows < 0 || g->nw_cross < 0)
-        return bad("need nx >= 1, 1 <= nu <= 16, na, n_alg_rows, n_ineq_rows, n_setpoint, nw, nw_cross >= 0, "
-                   "uses_traj 0 or 1");
+        (g->uses_traj != 0 && g->uses_traj != 1) || g->nw < 0 || g->n_ineq_rows < 0 || g->nw_cross < 0 ||
+        g->scratch_per_stage < 0)
+        return bad("need nx >= 1, 1 <= nu <= 16, na, n_alg_rows, n_ineq_rows, n_setpoint, nw, nw_cross, "
+                   "scratch_per_stage >= 0, uses_traj 0 or 1");
     if (!g->row_ptr || !g->prev_ptr || !g->lb || !g->ub || !g->code_object || g->code_object_size == 0 ||
         g->tag == 0 || (g->nw > 0 && (!g->w_rows || !g->w_cols)) || (g->n_ineq_rows > 0 && !g->ineq_ptr) ||
         (g->nw_cross > 0 && (!g->wx_rows || !g->wx_cols)))
         return bad("missing pattern, bounds, code object or tag");
     const int64_t ns64 = (int64_t)g->nx + g->nu + g->na, rps64 = (int64_t)g->nx + g->n_alg_rows;
     if (ns64 * s.horizon > (int64_t)1 << 30 || (rps64 + g->n_ineq_rows) * s.horizon > (int64_t)1 << 29 ||
-        g->nw > (1 << 24) || g->nw_cross > (1 << 24))
+        g->nw > (1 << 24) || g->nw_cross > (1 << 24) || g->scratch_per_stage * s.horizon > ((int64_t)1 << 31))
         return bad("problem too large");
     const int ns = (int)ns64, rps = (int)rps64, nx = g->nx, H = s.horizon, nd = g->n_ineq_rows;
     if (g->row_ptr[0] != 0 || g->prev_ptr[0] != 0) return bad("row_ptr / prev_ptr must start at 0");
@@ -360,13 +361,22 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
     M.tag = g->tag;
     const unsigned char* code = static_cast<const unsigned char*>(g->code_object);
     M.code.assign(code, code + g->code_object_size);
-    M.pc.assign((size_t)nx * nx, 0.0);
-    for (int r = 0; r < nx; ++r)
-        for (int q = g->prev_ptr[r]; q < g->prev_ptr[r + 1]; ++q) M.pc[(size_t)r * nx + g->prev_cols[q]] = g->prev_coef[q];
+    M.scratch = g->scratch_per_stage;
+    // the dense coefficient matrix only when it is not minus the identity
     M.pc_minus_identity = true;
     for (int r = 0; r < nx; ++r)
-        for (int c = 0; c < nx; ++c)
-            if (M.pc[(size_t)r * nx + c] != (r == c ? -1.0 : 0.0)) M.pc_minus_identity = false;
+        if (g->prev_ptr[r + 1] - g->prev_ptr[r] != 1 || g->prev_cols[g->prev_ptr[r]] != r ||
+            g->prev_coef[g->prev_ptr[r]] != -1.0)
+            M.pc_minus_identity = false;
+    M.pc.clear();
+    if (!M.pc_minus_identity) {
+        if ((int64_t)nx * nx > ((int64_t)1 << 26))
+            return bad("state rows whose previous-state coefficients are not minus the identity need nx <= 8192");
+        M.pc.assign((size_t)nx * nx, 0.0);
+        for (int r = 0; r < nx; ++r)
+            for (int q = g->prev_ptr[r]; q < g->prev_ptr[r + 1]; ++q)
+                M.pc[(size_t)r * nx + g->prev_cols[q]] = g->prev_coef[q];
+    }
     st.nx = nx;
     st.nu = g->nu;
     st.H = H;

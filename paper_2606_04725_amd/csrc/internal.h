@@ -29,7 +29,9 @@ struct Structure {
         uint64_t tag = 0;
         std::vector<unsigned char> code;
         std::vector<double> pc;   // nx x nx coefficients of the previous states in the state rows, row-major
+                                  // (left empty when they are minus the identity)
         bool pc_minus_identity = false;
+        int64_t scratch = 0;      // per-stage scratch doubles of the kernels (then they have a reduce kernel)
     } gm;
 };
 

@@ -38,6 +38,7 @@ struct StageConst {
     double dt;
     unsigned long long tag;
     const double* pc;
+    double* scratch;   // H x (the model's per-stage scratch) doubles, or null
 };
 
 // Per-supernode read-only symbolic data of one instance.
@@ -169,7 +170,7 @@ struct InstPtrs {
 // Layout check between the library and the code objects of generated stage
 // models (both read InstPtrs): the library refuses a code object whose
 // nmpc_stage_abi differs.
-constexpr unsigned int kStageAbiVersion = 1;
+constexpr unsigned int kStageAbiVersion = 2;
 constexpr unsigned int kStageAbi = kStageAbiVersion * 100000u + (unsigned int)sizeof(InstPtrs);
 
 // Right-hand side and solution of the solves: 0 rhs -> dy (Newton step),

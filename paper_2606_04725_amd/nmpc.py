@@ -113,6 +113,7 @@ def stage_model_structure(gen, H, dt, ordering=capi.NMPC_ORDER_NESTED_DISSECTION
     d.code_object = C.cast(keep["code"], C.c_void_p)
     d.code_object_size = len(gen.code)
     d.tag = gen.tag
+    d.scratch_per_stage = int(gen.scratch_per_stage)
     s = nmpc_structure()
     s.ordering = ordering
     s.family = capi.NMPC_FAMILY_STAGE_MODEL

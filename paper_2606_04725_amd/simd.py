@@ -927,6 +927,7 @@ class GeneratedModel:
     derived: Derived = None
     code: bytes = b""
     path: str = ""
+    scratch_per_stage: int = 0   # pattern models: doubles of per-stage scratch the kernels sum
 
     @property
     def ns(self):
@@ -983,7 +984,12 @@ HIP_FLAGS = ["--genco", "--offload-arch=gfx950", "-O3", "-std=c++17",
 def compile(m: StageModel | GeneratedModel, cache_dir: str = GEN_DIR, force: bool = False) -> GeneratedModel:
     """Generate (if needed) and compile the model's kernels to a gfx950 code
     object, cached under cache_dir by the model's tag."""
-    g = m if isinstance(m, GeneratedModel) else generate(m)
+    if isinstance(m, GeneratedModel):
+        g = m
+    elif isinstance(m, StageModel):
+        g = generate(m)
+    else:                  # index-data pattern models generate themselves
+        g = m.generate()
     os.makedirs(cache_dir, exist_ok=True)
     stem = os.path.join(cache_dir, f"{g.name}_{g.tag:015x}")
     src, obj = stem + ".hip", stem + ".hsaco"

@@ -25,12 +25,20 @@ the library loads (family NMPC_FAMILY_STAGE_MODEL).
                    tracking of a region's temperature (trapezoid weights) as
                    the stage trajectory; input in units of q_scale, rows
                    divided by their diagonal coefficient
+  plate_pattern_model
+                   the workload plate (the library's HEATED_PLATE family)
+                   written with index-data patterns: one 5-point stencil
+                   row pattern over the G^2 nodes (a neighbour beyond an
+                   edge is that edge's heater segment, a control) and one
+                   tracking pattern over the nodes with the target field as
+                   setpoint
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .simd import StageModel, sin
+from .simd_patterns import PatternModel
 
 
 def toy_model() -> StageModel:
@@ -184,4 +192,41 @@ def plate_case_model(n=21, alpha=230.0, Tb=50.0, loss=50.0, rho=1e-8, Q_lo=50.0,
             if wgt:
                 track = track + (h * h * wgt) * (T[j * g + i] - m.traj()) ** 2
     m.minimize(dt * (track + rho * Q * Q))
+    return m
+
+
+def plate_pattern_model(G, sigma=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0) -> PatternModel:
+    """The plate of eq. (3)'s repeated pattern: G x G interior nodes at
+    spacing h = 1 / (G + 1), node p = b G + a; conductivity 1 + sigma T with
+    the face average, so the flux from a neighbour v into T is
+    [(v - T) + (sigma / 2)(v^2 - T^2)] / h^2; backward Euler in time.  The
+    four neighbours in the order below, left, right, above; one beyond an
+    edge is the heater segment of that edge covering the node (edges bottom,
+    right, top, left, 4 segments of G / 4 nodes each, segment 4 edge +
+    coordinate // (G / 4)).  Objective: sum over nodes of (T_p - T*_p)^2, T*
+    the setpoint field.  Bounds T <= t_hi, c_lo <= u <= c_hi."""
+    if G % 4 or G < 4:
+        raise ValueError("the grid size must be a positive multiple of 4")
+    m = PatternModel(f"plate_pattern_G{G}", n_setpoint=G * G)
+    T = m.states(G * G, ub=t_hi)
+    U = m.controls(16, lb=c_lo, ub=c_hi)
+    q = G // 4
+    kap, inv_h2 = 0.5 * sigma, float((G + 1) * (G + 1))
+
+    def neighbours(a, b):
+        return [T[(b - 1) * G + a] if b > 0 else U[0 * 4 + a // q],
+                T[b * G + a - 1] if a > 0 else U[3 * 4 + b // q],
+                T[b * G + a + 1] if a < G - 1 else U[1 * 4 + b // q],
+                T[(b + 1) * G + a] if b < G - 1 else U[2 * 4 + a // q]]
+
+    def stencil(v, p, d):
+        t = v[0]
+        flux = sum(((n - t) + kap * (n * n - t * t) for n in v[1:]), 0.0)
+        return t - p[0] - m.dt * inv_h2 * flux
+
+    rows = [dict(target=T[b * G + a], vars=[T[b * G + a]] + neighbours(a, b), prevs=[T[b * G + a]])
+            for b in range(G) for a in range(G)]
+    m.row_pattern(stencil, rows, nv=5, nprev=1)
+    m.objective_pattern(lambda v, d, s: (v[0] - s[0]) ** 2,
+                        [dict(vars=[T[p]], sps=[p]) for p in range(G * G)], nv=1, nsp=1)
     return m

@@ -1,0 +1,545 @@
+"""Index-data patterns for the stage-pattern front end (eq. 3: one algebraic
+pattern evaluated at many discretization points, differing only in the data
+it reads).
+
+A PatternModel writes a stage's rows and objective as a few templates, each
+instantiated over a table: an instance names the stage variables bound to the
+template's variable slots, the previous-stage states bound to its previous
+slots, numeric data, setpoint entries and (for rows) the state whose equation
+it is.  The templates are differentiated once; the generated kernels give
+every instance of a pattern the same code (no divergence within a pattern),
+reading their bindings from tables compiled into the code object.  Rows own
+their Jacobian entries; the Hessian, gradient and objective contributions of
+the instances go to a per-stage scratch array and a second generated kernel
+sums them per Hessian slot, gradient entry and stage in a fixed order.
+
+Scope: state rows and objective terms (no algebraic or inequality rows);
+previous states only in state rows, linearly with constant coefficients;
+objective templates may read setpoint entries, the stage's trajectory value
+and dt; the cold-start guess is the measured state and the last control.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .simd import (GeneratedModel, ZERO, _Emitter, _header_text, _tag, add, diff, is_const, lift, mul, neg,
+                   sym, symbols)
+
+
+def _kinds(e):
+    return {s.args[0] for s in symbols(e)}
+
+
+@dataclass
+class Pattern:
+    kind: str            # "row" or "obj"
+    expr: object
+    nv: int
+    nprev: int
+    ndata: int
+    nsp: int
+    instances: list      # dicts: vars, prevs, data, sps, target
+
+
+@dataclass
+class PatternModel:
+    """Stage layout [states | controls]; every state's row comes from exactly
+    one instance of a row pattern."""
+    name: str
+    n_setpoint: int = 0
+    uses_traj: bool = False
+    lb: list = field(default_factory=list)
+    ub: list = field(default_factory=list)
+    nx: int = 0
+    nu: int = 0
+    patterns: list = field(default_factory=list)
+
+    def states(self, count, lb=-math.inf, ub=math.inf):
+        if self.nu:
+            raise ValueError("declare the states before the controls")
+        first = self.nx
+        self.nx += count
+        self.lb += [float(lb)] * count
+        self.ub += [float(ub)] * count
+        return list(range(first, first + count))
+
+    def controls(self, count, lb=-math.inf, ub=math.inf):
+        first = self.nx + self.nu
+        self.nu += count
+        self.lb += [float(lb)] * count
+        self.ub += [float(ub)] * count
+        return list(range(first, first + count))
+
+    @property
+    def ns(self):
+        return self.nx + self.nu
+
+    @property
+    def dt(self):
+        return sym("dt")
+
+    def traj(self):
+        self.uses_traj = True
+        return sym("tr")
+
+    def row_pattern(self, template, instances, nv, nprev=0, ndata=0):
+        """template(v, p, d) -> residual; v: nv variable slots, p: nprev
+        previous-state slots, d: ndata numeric data.  instances: dicts with
+        target (state index), vars (nv stage-variable indices, distinct), prevs
+        (nprev state indices), data (ndata floats)."""
+        v = [sym("sv", j) for j in range(nv)]
+        p = [sym("sprev", j) for j in range(nprev)]
+        d = [sym("sd", j) for j in range(ndata)]
+        self.patterns.append(Pattern("row", lift(template(v, p, d)), nv, nprev, ndata, 0, list(instances)))
+
+    def generate(self):
+        return generate(self)
+
+    def objective_pattern(self, template, instances, nv, ndata=0, nsp=0):
+        """template(v, d, s) -> stage term; s: nsp setpoint slots.
+        instances: dicts with vars, data, sps (setpoint indices)."""
+        v = [sym("sv", j) for j in range(nv)]
+        d = [sym("sd", j) for j in range(ndata)]
+        s = [sym("ssp", j) for j in range(nsp)]
+        self.patterns.append(Pattern("obj", lift(template(v, d, s)), nv, 0, ndata, nsp, list(instances)))
+
+
+# ---- derivation --------------------------------------------------------------------
+@dataclass
+class PatternDerived:
+    pat: Pattern
+    dv: list             # d expr / d sv_j
+    pcoef: list          # constant d expr / d sprev_j (rows)
+    pairs: list          # (j, l) slot pairs with a nonzero second derivative
+    d2: list             # their expressions (times the row multiplier for rows)
+
+
+def _derive_pattern(pat: Pattern):
+    allowed = {"sv", "sprev", "sd", "dt"} if pat.kind == "row" else {"sv", "sd", "ssp", "tr", "dt"}
+    bad = _kinds(pat.expr) - allowed
+    if bad:
+        raise ValueError(f"a {pat.kind} pattern uses {sorted(bad)}")
+    memo = {}
+    V = [sym("sv", j) for j in range(pat.nv)]
+    dv = [diff(pat.expr, v, memo.setdefault(v, {})) for v in V]
+    pcoef = []
+    for j in range(pat.nprev):
+        c = diff(pat.expr, sym("sprev", j))
+        if not is_const(c) or is_const(c, 0.0):
+            raise ValueError("previous-state slots must enter linearly with nonzero constant coefficients")
+        pcoef.append(c.args[0])
+    pairs, d2 = [], []
+    for j in range(pat.nv):
+        for l in range(j + 1):
+            e = diff(dv[j], V[l])
+            if not is_const(e, 0.0):
+                pairs.append((j, l))
+                d2.append(e)
+    return PatternDerived(pat, dv, pcoef, pairs, d2)
+
+
+def _structure(m: PatternModel, ders):
+    """Per-stage patterns, per-instance Jacobian positions, the Hessian slots
+    and the scratch layout with the reduction lists."""
+    ns, nx = m.ns, m.nx
+    row_of = {}
+    rows = [None] * nx
+    for pi, dd in enumerate(ders):
+        if dd.pat.kind != "row":
+            continue
+        for ii, inst in enumerate(dd.pat.instances):
+            t = int(inst["target"])
+            if not 0 <= t < nx or rows[t] is not None:
+                raise ValueError(f"state {t}: no or several row instances")
+            vs = [int(v) for v in inst["vars"]]
+            if len(vs) != dd.pat.nv or len(set(vs)) != len(vs) or not all(0 <= v < ns for v in vs):
+                raise ValueError(f"row of state {t}: variable slots must be distinct stage variables")
+            if t not in vs:
+                raise ValueError(f"row of state {t} does not hold its own state")
+            ps = [int(q) for q in inst.get("prevs", [])]
+            if len(ps) != dd.pat.nprev or len(set(ps)) != len(ps) or not all(0 <= q < nx for q in ps):
+                raise ValueError(f"row of state {t}: previous slots must be distinct states")
+            if len(inst.get("data", [])) != dd.pat.ndata:
+                raise ValueError(f"row of state {t}: wrong number of data values")
+            rows[t] = (pi, ii)
+            row_of[(pi, ii)] = t
+    if any(r is None for r in rows):
+        raise ValueError(f"states without a row: {[t for t, r in enumerate(rows) if r is None][:8]} ...")
+    # per-row columns (own sorted; previous sorted) and slot positions
+    row_ptr, row_cols, prev_ptr, prev_cols, prev_coef = [0], [], [0], [], []
+    jpos, ppos = {}, {}
+    for t in range(nx):
+        pi, ii = rows[t]
+        dd = ders[pi]
+        inst = dd.pat.instances[ii]
+        own = sorted(int(v) for v in inst["vars"])
+        row_cols += own
+        row_ptr.append(len(row_cols))
+        pv = [int(q) for q in inst.get("prevs", [])]
+        order = sorted(range(len(pv)), key=lambda j: pv[j])
+        prev_cols += [pv[j] for j in order]
+        prev_coef += [dd.pcoef[j] for j in order]
+        prev_ptr.append(len(prev_cols))
+        jpos[(pi, ii)] = [own.index(int(v)) for v in inst["vars"]]
+        ppos[(pi, ii)] = [order.index(j) for j in range(len(pv))]
+    # Hessian slots: lower pairs of stage variables over all instances
+    wkeys = {}
+    for pi, dd in enumerate(ders):
+        for inst in dd.pat.instances:
+            vs = [int(v) for v in inst["vars"]]
+            for (j, l) in dd.pairs:
+                a, b = max(vs[j], vs[l]), min(vs[j], vs[l])
+                wkeys.setdefault((a, b), None)
+    wlist = sorted(wkeys)
+    widx = {k: i for i, k in enumerate(wlist)}
+    # scratch of a stage: per pattern, entry c of instance i at base + c n + i
+    # (n instances; consecutive lanes write consecutive doubles).  Entries: the
+    # Hessian contributions, then (objective) the gradient contributions and
+    # the value.  The objective values are spread over the stage's NS
+    # objective-term slots (value of the f-th instance overall -> slot f % NS).
+    coo_base, ncoo = [], 0
+    w_lists = [[] for _ in wlist]
+    g_lists = [[] for _ in range(ns)]
+    f_lists = [[] for _ in range(ns)]
+    nf = 0
+    for pi, dd in enumerate(ders):
+        n = len(dd.pat.instances)
+        per = len(dd.pairs) + (dd.pat.nv + 1 if dd.pat.kind == "obj" else 0)
+        coo_base.append(ncoo)
+        for ii, inst in enumerate(dd.pat.instances):
+            vs = [int(v) for v in inst["vars"]]
+            for c, (j, l) in enumerate(dd.pairs):
+                w_lists[widx[(max(vs[j], vs[l]), min(vs[j], vs[l]))]].append(ncoo + c * n + ii)
+            if dd.pat.kind == "obj":
+                for j in range(dd.pat.nv):
+                    g_lists[vs[j]].append(ncoo + (len(dd.pairs) + j) * n + ii)
+                f_lists[nf % ns].append(ncoo + (len(dd.pairs) + dd.pat.nv) * n + ii)
+                nf += 1
+        ncoo += per * n
+    return dict(rows=rows, row_ptr=row_ptr, row_cols=row_cols, prev_ptr=prev_ptr, prev_cols=prev_cols,
+                prev_coef=prev_coef, jpos=jpos, ppos=ppos, wlist=wlist, coo_base=coo_base, ncoo=ncoo,
+                w_lists=w_lists, g_lists=g_lists, f_lists=f_lists)
+
+
+# ---- C emission ---------------------------------------------------------------------------
+def _ints(name, vals):
+    vals = [int(v) for v in vals] or [0]
+    body = ",".join(str(int(v)) for v in vals)
+    return f"__device__ const int {name}[{len(vals)}] = {{{body}}};"
+
+
+def _dbls(name, vals):
+    vals = list(vals) or [0.0]
+    body = ",".join(repr(float(v)) for v in vals)
+    return f"__device__ const double {name}[{len(vals)}] = {{{body}}};"
+
+
+def _csr(name, lists):
+    ptr = [0]
+    idx = []
+    for l in lists:
+        idx += l
+        ptr.append(len(idx))
+    return _ints(name + "_PTR", ptr) + "\n" + _ints(name + "_IDX", idx)
+
+
+def _source(m: PatternModel, ders, st, tag: int) -> str:
+    nx, nu, ns = m.nx, m.nu, m.ns
+    nw = len(st["wlist"])
+    nlanes = sum(len(d.pat.instances) for d in ders)
+    out = []
+    w = out.append
+    w(f"// Kernels of the pattern model '{m.name}', written by the stage-pattern front end.")
+    w("#include \"kernels.h\"")
+    w("using namespace nmpc;")
+    w("namespace {")
+    w(f"constexpr int NS = {ns}, NX = {nx}, NU = {nu}, RPS = {nx}, NW = {nw}, NCOO = {max(st['ncoo'], 1)}, "
+      f"NLANES = {nlanes}, NSP = {m.n_setpoint};")
+    w("// (a model with no Hessian, gradient or objective contributions still has one scratch double")
+    w("// per stage, so the summing kernel runs and writes the zeros)")
+    w(f"constexpr unsigned long long TAG = {tag}ULL;")
+    w("// binding tables of the instances (instance-major), compiled into the code object")
+    for pi, dd in enumerate(ders):
+        insts = dd.pat.instances
+        w(_ints(f"P{pi}_V", [v for inst in insts for v in inst["vars"]]))
+        if dd.pat.nprev:
+            w(_ints(f"P{pi}_PV", [q for inst in insts for q in inst["prevs"]]))
+            w(_ints(f"P{pi}_PP", [p for ii in range(len(insts)) for p in st["ppos"][(pi, ii)]]))
+        if dd.pat.ndata:
+            w(_dbls(f"P{pi}_D", [x for inst in insts for x in inst["data"]]))
+        if dd.pat.nsp:
+            w(_ints(f"P{pi}_SP", [q for inst in insts for q in inst["sps"]]))
+            for slot in range(dd.pat.nsp):
+                inv = [[] for _ in range(m.n_setpoint)]
+                for ii, inst in enumerate(insts):
+                    inv[int(inst["sps"][slot])].append(ii)
+                w(_csr(f"P{pi}_S{slot}", inv))
+        if dd.pat.kind == "row":
+            w(_ints(f"P{pi}_T", [inst["target"] for inst in insts]))
+            w(_ints(f"P{pi}_JP", [p for ii in range(len(insts)) for p in st["jpos"][(pi, ii)]]))
+    w("// summation lists of a stage's scratch: Hessian slots, gradient entries, objective-term slots")
+    w(_csr("RW", st["w_lists"]))
+    w(_csr("RG", st["g_lists"]))
+    w(_csr("RF", st["f_lists"]))
+    # x0 contraction: the state rows holding each previous state, with coefficients
+    xl = [[] for _ in range(nx)]
+    for t in range(nx):
+        for q in range(st["prev_ptr"][t], st["prev_ptr"][t + 1]):
+            xl[st["prev_cols"][q]].append((t, st["prev_coef"][q]))
+    w(_ints("XR_PTR", np.concatenate([[0], np.cumsum([len(l) for l in xl])])))
+    w(_ints("XR_ROW", [r for l in xl for r, _ in l]))
+    w(_dbls("XR_COEF", [c for l in xl for _, c in l]))
+    w("}  // namespace")
+    w("")
+    w("// descriptor layout these kernels were built against (checked at load)")
+    w("extern \"C\" __device__ unsigned int nmpc_stage_abi = kStageAbi;")
+    w("")
+    # evaluation: one lane per (stage, instance), instances fastest, grid-stride
+    w("// One lane per (stage, instance), instances fastest: the lanes of a wavefront")
+    w("// run one pattern on neighbouring instances of one stage.")
+    w("extern \"C\" __global__ void __launch_bounds__(kBlock)")
+    w("nmpc_stage_eval(const InstPtrs* __restrict__ Ia, Space sp, int src, int pred, int full) {")
+    w("    int lb;")
+    w("    const int inst = block_inst(sp, lb);")
+    w("    const InstPtrs& I = Ia[inst];")
+    w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG || !ctl_active(I.ctl, pred)) return;")
+    w("    const int lanes = (sp.bfirst[inst + 1] - sp.bfirst[inst]) * kBlock;")
+    w("    const double* __restrict__ y = src == kSrcIter ? I.y : I.yt;")
+    w("    const double* __restrict__ om = src == kSrcUser ? I.dom : I.om;")
+    w("    const double* SP = I.setp;")
+    w("    const double DT = I.gm.dt;")
+    w("    const int mc = I.mc;")
+    w("    (void)SP; (void)DT; (void)om; (void)mc;")
+    w("    for (int t = lb * kBlock + threadIdx.x; t < I.H * NLANES; t += lanes) {")
+    w("        const int k = t / NLANES, j = t - k * NLANES;")
+    w("        const double* V = y + (int64_t)k * NS;")
+    w("        const double TR = I.ntr > 0 ? I.zF[k] : 0.0;")
+    w("        double* Sk = I.gm.scratch + (int64_t)k * NCOO;")
+    w("        (void)V; (void)TR; (void)Sk;")
+    start = 0
+    for pi, dd in enumerate(ders):
+        pat = dd.pat
+        n = len(pat.instances)
+        base = st["coo_base"][pi]
+        w(f"        {'if' if pi == 0 else 'else if'} (j < {start + n}) {{")
+        w(f"            const int i = j - {start};")
+        names = {"sv": f"V[P{pi}_V[i * {pat.nv} + {{j}}]]", "dt": "DT", "tr": "TR"}
+        if pat.ndata:
+            names["sd"] = f"P{pi}_D[i * {pat.ndata} + {{j}}]"
+        if pat.nsp:
+            names["ssp"] = f"SP[P{pi}_SP[i * {pat.nsp} + {{j}}]]"
+        if pat.nprev:
+            names["sprev"] = (f"(k > 0 ? y[(int64_t)(k - 1) * NS + P{pi}_PV[i * {pat.nprev} + {{j}}]] "
+                              f": I.x0[P{pi}_PV[i * {pat.nprev} + {{j}}]])")
+        em = _Emitter(None, names, indent=3)
+        if pat.kind == "row":
+            em.line(f"const int r = k * RPS + P{pi}_T[i];")
+            em.line(f"I.c[r] = {em.val(pat.expr)};")
+            em.line("if (full) {")
+            em.indent += 1
+            em.push()
+            if pat.nprev:
+                em.line(f"double* jr = I.jv + I.jptr[r] + (k > 0 ? {pat.nprev} : 0);")
+                em.line("if (k > 0) {")
+                for q, c in enumerate(dd.pcoef):
+                    em.line(f"    I.jv[I.jptr[r] + P{pi}_PP[i * {pat.nprev} + {q}]] = {c!r};")
+                em.line("}")
+            else:
+                em.line("double* jr = I.jv + I.jptr[r];")
+            for s_, e in enumerate(dd.dv):
+                em.line(f"jr[P{pi}_JP[i * {pat.nv} + {s_}]] = {em.val(e)};")
+            if dd.pairs:
+                em.line("const double lam = om[r] - om[mc + r];")
+                for c, e in enumerate(dd.d2):
+                    em.line(f"Sk[{base + c * n} + i] = lam * {em.val(e)};")
+            em.pop()
+            em.indent -= 1
+            em.line("}")
+        else:
+            np_ = len(dd.pairs)
+            em.line(f"Sk[{base + (np_ + pat.nv) * n} + i] = {em.val(pat.expr)};")
+            em.line("if (full) {")
+            em.indent += 1
+            em.push()
+            for c, e in enumerate(dd.d2):
+                em.line(f"Sk[{base + c * n} + i] = {em.val(e)};")
+            for s_, e in enumerate(dd.dv):
+                em.line(f"Sk[{base + (np_ + s_) * n} + i] = {em.val(e)};")
+            em.pop()
+            em.indent -= 1
+            em.line("}")
+        out.extend(em.lines)
+        w("        }")
+        start += n
+    w("    }")
+    w("}")
+    w("")
+    # reduction: Hessian slots, gradient entries and objective-term slots, in list order
+    w("// Sums of the scratch, one lane per (stage, Hessian slot or variable), in the")
+    w("// fixed order of the lists: Hessian values, gradient and objective terms.")
+    w("extern \"C\" __global__ void __launch_bounds__(kBlock)")
+    w("nmpc_stage_reduce(const InstPtrs* __restrict__ Ia, Space sp, int pred, int full) {")
+    w("    int lb;")
+    w("    const int inst = block_inst(sp, lb);")
+    w("    const InstPtrs& I = Ia[inst];")
+    w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG || !ctl_active(I.ctl, pred)) return;")
+    w("    const int lanes = (sp.bfirst[inst + 1] - sp.bfirst[inst]) * kBlock;")
+    w("    for (int t = lb * kBlock + threadIdx.x; t < I.H * (NW + NS); t += lanes) {")
+    w("        const int k = t / (NW + NS), e = t - k * (NW + NS);")
+    w("        const double* Sk = I.gm.scratch + (int64_t)k * NCOO;")
+    w("        if (e < NW) {")
+    w("            if (!full) continue;")
+    w("            double acc = 0.0;")
+    w("            for (int q = RW_PTR[e]; q < RW_PTR[e + 1]; ++q) acc += Sk[RW_IDX[q]];")
+    w("            I.wv[(int64_t)k * NW + e] = acc;")
+    w("        } else {")
+    w("            const int v = e - NW;")
+    w("            if (full) {")
+    w("                double acc = 0.0;")
+    w("                for (int q = RG_PTR[v]; q < RG_PTR[v + 1]; ++q) acc += Sk[RG_IDX[q]];")
+    w("                I.grad[(int64_t)k * NS + v] = acc;")
+    w("            }")
+    w("            double f = 0.0;")
+    w("            for (int q = RF_PTR[v]; q < RF_PTR[v + 1]; ++q) f += Sk[RF_IDX[q]];")
+    w("            I.fterm[(int64_t)k * NS + v] = f;")
+    w("        }")
+    w("    }")
+    w("}")
+    w("")
+    # cold-start guess: the measured state and the last control
+    w("extern \"C\" __global__ void __launch_bounds__(kBlock)")
+    w("nmpc_stage_guess(const InstPtrs* __restrict__ Ia, Space sp) {")
+    w("    int lb;")
+    w("    const InstPtrs& I = Ia[block_inst(sp, lb)];")
+    w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG) return;")
+    w("    const int t = lb * kBlock + threadIdx.x;")
+    w("    if (t >= I.n) return;")
+    w("    const int j = t % NS;")
+    w("    I.y[t] = j < NX ? I.x0[j] : I.uprev[j - NX];")
+    w("}")
+    w("")
+    # parameter contractions (instance 0)
+    objs = [(pi, dd) for pi, dd in enumerate(ders) if dd.pat.kind == "obj"]
+
+    def contraction(dd, s):
+        """so d(term)/ds - sum over slots of w_slot d2(term)/(dv_slot ds)."""
+        dfs = diff(dd.pat.expr, s)
+        acc = mul(sym("so"), dfs)
+        for j in range(dd.pat.nv):
+            d2 = diff(dfs, sym("sv", j))
+            if not is_const(d2, 0.0):
+                acc = add(acc, neg(mul(sym("w", j), d2)))
+        return acc
+
+    def obj_names(pi, dd):
+        names = {"sv": f"V[P{pi}_V[i * {dd.pat.nv} + {{j}}]]", "dt": "DT", "tr": "TR", "so": "so",
+                 "w": f"I.adj_w[(int64_t)k * NS + P{pi}_V[i * {dd.pat.nv} + {{j}}]]"}
+        if dd.pat.ndata:
+            names["sd"] = f"P{pi}_D[i * {dd.pat.ndata} + {{j}}]"
+        if dd.pat.nsp:
+            names["ssp"] = f"SP[P{pi}_SP[i * {dd.pat.nsp} + {{j}}]]"
+        return names
+
+    w("// Parameter contractions of the sensitivity solve (instance 0):")
+    w("// out = [x0 (nx) | setpoint (nsp) | trajectory (H or 0) | last control (nu)].")
+    w("extern \"C\" __global__ void __launch_bounds__(kBlock) nmpc_stage_adj(const InstPtrs* __restrict__ Ia) {")
+    w("    const InstPtrs& I = Ia[0];")
+    w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG) return;")
+    w("    const int q = blockIdx.x * kBlock + threadIdx.x;")
+    w("    const int ntr = I.ntr;")
+    w("    const double so = I.adj_seed[I.nu];")
+    w("    const double* SP = I.setp;")
+    w("    const double DT = I.gm.dt;")
+    w("    double* out = I.adj_out;")
+    w("    (void)so; (void)SP; (void)DT;")
+    w("    if (q < NX) {")
+    w("        // x0 enters the first stage's state rows: - sum_rows coefficient * multiplier")
+    w("        double acc = 0.0;")
+    w("        for (int e = XR_PTR[q]; e < XR_PTR[q + 1]; ++e) acc -= XR_COEF[e] * I.adj_lam[XR_ROW[e]];")
+    w("        out[q] = acc;")
+    w("        return;")
+    w("    }")
+    w("    if (q < NX + NSP) {")
+    w("        const int jsp = q - NX;")
+    w("        double acc = 0.0;")
+    w("        for (int k = 0; k < I.H; ++k) {")
+    w("            const double* V = I.y + (int64_t)k * NS;")
+    w("            const double TR = ntr > 0 ? I.zF[k] : 0.0;")
+    w("            (void)V; (void)TR;")
+    for pi, dd in objs:
+        for slot in range(dd.pat.nsp):
+            e = contraction(dd, sym("ssp", slot))
+            if is_const(e, 0.0):
+                continue
+            w(f"            for (int e = P{pi}_S{slot}_PTR[jsp]; e < P{pi}_S{slot}_PTR[jsp + 1]; ++e) {{")
+            w(f"                const int i = P{pi}_S{slot}_IDX[e];")
+            em = _Emitter(None, obj_names(pi, dd), indent=4)
+            v = em.val(e)
+            out.extend(em.lines)
+            w(f"                acc += {v};")
+            w("            }")
+    w("        }")
+    w("        out[q] = acc;")
+    w("        return;")
+    w("    }")
+    w("    if (q < NX + NSP + ntr) {")
+    w("        const int k = q - NX - NSP;")
+    w("        const double* V = I.y + (int64_t)k * NS;")
+    w("        const double TR = I.zF[k];")
+    w("        (void)V; (void)TR;")
+    w("        double acc = 0.0;")
+    for pi, dd in objs:
+        e = contraction(dd, sym("tr"))
+        if is_const(e, 0.0):
+            continue
+        w(f"        for (int i = 0; i < {len(dd.pat.instances)}; ++i) {{")
+        em = _Emitter(None, obj_names(pi, dd), indent=3)
+        v = em.val(e)
+        out.extend(em.lines)
+        w(f"            acc += {v};")
+        w("        }")
+    w("        out[q] = acc;")
+    w("        return;")
+    w("    }")
+    w("    // no pattern reads the last control")
+    w("    if (q < NX + NSP + ntr + NU) out[q] = 0.0;")
+    w("}")
+    return "\n".join(out) + "\n"
+
+
+def generate(m: PatternModel) -> GeneratedModel:
+    if not m.patterns:
+        raise ValueError(f"{m.name}: no patterns")
+    ders = [_derive_pattern(p) for p in m.patterns]
+    for dd in ders:
+        for inst in dd.pat.instances:
+            if dd.pat.kind == "obj":
+                vs = [int(v) for v in inst["vars"]]
+                if len(vs) != dd.pat.nv or len(set(vs)) != len(vs) or not all(0 <= v < m.ns for v in vs):
+                    raise ValueError("objective instance: variable slots must be distinct stage variables")
+                if len(inst.get("sps", [])) != dd.pat.nsp or not all(0 <= s < m.n_setpoint for s in inst.get("sps", [])):
+                    raise ValueError("objective instance: wrong setpoint slots")
+                if len(inst.get("data", [])) != dd.pat.ndata:
+                    raise ValueError("objective instance: wrong number of data values")
+    if any("tr" in _kinds(d.pat.expr) for d in ders):
+        m.uses_traj = True
+    st = _structure(m, ders)
+    body = _source(m, ders, st, 0)
+    tag = _tag(hashlib.sha256(body.encode() + _header_text()).hexdigest())
+    g = GeneratedModel(
+        name=m.name, nx=m.nx, nu=m.nu, na=0, n_alg_rows=0, n_setpoint=m.n_setpoint, uses_traj=m.uses_traj,
+        row_ptr=np.array(st["row_ptr"], dtype=np.int32), row_cols=np.array(st["row_cols"], dtype=np.int32),
+        prev_ptr=np.array(st["prev_ptr"], dtype=np.int32), prev_cols=np.array(st["prev_cols"], dtype=np.int32),
+        prev_coef=np.array(st["prev_coef"], dtype=np.float64),
+        ineq_ptr=np.zeros(1, dtype=np.int32), ineq_cols=np.zeros(0, dtype=np.int32),
+        w_rows=np.array([a for a, _ in st["wlist"]], dtype=np.int32),
+        w_cols=np.array([b for _, b in st["wlist"]], dtype=np.int32),
+        wx_rows=np.zeros(0, dtype=np.int32), wx_cols=np.zeros(0, dtype=np.int32),
+        lb=np.array(m.lb), ub=np.array(m.ub), source=_source(m, ders, st, tag), tag=tag, derived=None)
+    g.scratch_per_stage = max(st["ncoo"], 1)
+    g.pattern_structure = (ders, st)
+    return g

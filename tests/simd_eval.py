@@ -158,3 +158,78 @@ def contraction(d, y, H, x0, dt, setpoint, traj, lam, al, w, so, lam_d=None, u_p
             for b in range(m.nu):
                 gup[b] = ev(d.adj_up[b], env, memo)
     return gsp, gtr, gup
+
+
+def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None):
+    """The same outputs for a pattern model (simd_patterns.generate),
+    emulating its kernels: every instance's values go to the per-stage
+    scratch at the generated positions, the Jacobian entries to the
+    generated slots, and the sums follow the generated lists."""
+    ders, st = g.pattern_structure
+    ns, nx = g.ns, g.nx
+    nw = len(g.w_rows)
+    ncoo = max(st["ncoo"], 1)
+    jptr = [0]
+    jr, jc = [], []
+    for k in range(H):
+        for r in range(nx):
+            if k > 0:
+                for q in range(st["prev_ptr"][r], st["prev_ptr"][r + 1]):
+                    jr.append(k * nx + r)
+                    jc.append((k - 1) * ns + st["prev_cols"][q])
+            for q in range(st["row_ptr"][r], st["row_ptr"][r + 1]):
+                jr.append(k * nx + r)
+                jc.append(k * ns + st["row_cols"][q])
+            jptr.append(len(jr))
+    jv = np.full(len(jr), np.nan)
+    c = np.zeros(H * nx)
+    wv = np.zeros(H * nw)
+    grad = np.zeros(H * ns)
+    fterm = np.zeros(H * ns)
+    for k in range(H):
+        S = np.full(ncoo, np.nan)
+        V = y[k * ns:(k + 1) * ns]
+        P = y[(k - 1) * ns:(k - 1) * ns + nx] if k > 0 else x0
+        for pi, dd in enumerate(ders):
+            pat = dd.pat
+            n = len(pat.instances)
+            base = st["coo_base"][pi]
+            for i, inst in enumerate(pat.instances):
+                env = {("dt", 0): dt, ("tr", 0): 0.0 if traj is None else traj[k]}
+                for j, v in enumerate(inst["vars"]):
+                    env[("sv", j)] = V[v]
+                for j, q in enumerate(inst.get("prevs", [])):
+                    env[("sprev", j)] = P[q]
+                for j, x in enumerate(inst.get("data", [])):
+                    env[("sd", j)] = x
+                for j, q in enumerate(inst.get("sps", [])):
+                    env[("ssp", j)] = setpoint[q]
+                memo = {}
+                if pat.kind == "row":
+                    r = k * nx + inst["target"]
+                    c[r] = ev(pat.expr, env, memo)
+                    off = len(inst["prevs"]) if k > 0 else 0
+                    for s_, e in enumerate(dd.dv):
+                        jv[jptr[r] + off + st["jpos"][(pi, i)][s_]] = ev(e, env, memo)
+                    if k > 0:
+                        for qi, coef in enumerate(dd.pcoef):
+                            jv[jptr[r] + st["ppos"][(pi, i)][qi]] = coef
+                    lr = 0.0 if lam is None else lam[r]
+                    for cc, e in enumerate(dd.d2):
+                        S[base + cc * n + i] = lr * ev(e, env, memo)
+                else:
+                    npair = len(dd.pairs)
+                    S[base + (npair + pat.nv) * n + i] = ev(pat.expr, env, memo)
+                    for cc, e in enumerate(dd.d2):
+                        S[base + cc * n + i] = ev(e, env, memo)
+                    for s_, e in enumerate(dd.dv):
+                        S[base + (npair + s_) * n + i] = ev(e, env, memo)
+        for e, lst in enumerate(st["w_lists"]):
+            wv[k * nw + e] = sum(S[q] for q in lst)
+        for v in range(ns):
+            grad[k * ns + v] = sum(S[q] for q in st["g_lists"][v])
+            fterm[k * ns + v] = sum(S[q] for q in st["f_lists"][v])
+    wr = np.array([k * ns + a for k in range(H) for a in g.w_rows], dtype=int)
+    wc = np.array([k * ns + b for k in range(H) for b in g.w_cols], dtype=int)
+    return dict(f=fterm.sum(), grad=grad, c=c, jv=jv, jr=np.array(jr, dtype=int), jc=np.array(jc, dtype=int),
+                wv=wv, wr=wr, wc=wc)

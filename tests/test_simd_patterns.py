@@ -1,0 +1,166 @@
+"""Index-data patterns of the stage-pattern front end (eq. 3: one pattern
+repeated over discretization points), on the CPU: the workload plate written
+as one stencil row pattern and one tracking pattern, its per-stage structure
+and its values, Jacobian, Lagrangian Hessian, gradient and objective
+(emulating the generated kernels' scratch positions and summation lists)
+against the oracle's own transcription of the plate (oracle/plate.py), and
+the generator's rules."""
+import numpy as np
+import pytest
+
+from oracle.plate import PlateOCP
+from paper_2606_04725_amd import simd_models as SM
+from paper_2606_04725_amd import simd_patterns as SPn
+from paper_2606_04725_amd.simd import sin
+from simd_eval import expand_patterns
+
+
+def _pair(G=8, H=3, dt=0.01, seed=0):
+    m = PlateOCP(G, H, dt)
+    rng = np.random.default_rng(seed)
+    m.set_parameters(x0=rng.uniform(0.0, 1.2, m.nx), target=rng.uniform(0.2, 1.0, m.nx))
+    g = SPn.generate(SM.plate_pattern_model(G))
+    return m, g, rng
+
+
+@pytest.mark.parametrize("G", [4, 8])
+def test_plate_pattern_structure_matches_the_oracle(G):
+    m, g, rng = _pair(G)
+    assert (g.nx, g.nu, g.n_setpoint) == (m.nx, m.nu, m.nx)
+    y = rng.uniform(0.0, 1.2, m.n)
+    out = expand_patterns(g, y, m.H, m.x0, m.dt, m.target, lam=rng.normal(size=m.m_c))
+    J = m.jac_c(y).tocsr()
+    got = set(zip(out["jr"].tolist(), out["jc"].tolist()))
+    assert len(got) == len(out["jr"])
+    assert got == set(zip(*J.nonzero()))
+    W = m.hess(y, rng.normal(size=m.m_c), np.zeros(0)).tocsr()
+    Wl = set((a, b) for a, b in zip(*W.nonzero()) if a >= b)
+    assert Wl <= set(zip(out["wr"].tolist(), out["wc"].tolist()))
+    lo, hi = np.tile(g.lb, m.H), np.tile(g.ub, m.H)
+    assert np.array_equal(lo, m.lb) and np.array_equal(hi, m.ub)
+
+
+@pytest.mark.parametrize("G,seed", [(4, 1), (8, 2)])
+def test_plate_pattern_values_match_the_oracle(G, seed):
+    m, g, rng = _pair(G, seed=seed)
+    y = rng.uniform(0.0, 1.2, m.n)
+    lam = rng.normal(size=m.m_c)
+    out = expand_patterns(g, y, m.H, m.x0, m.dt, m.target, lam=lam)
+    assert abs(out["f"] - m.f(y)) <= 1e-13 * abs(m.f(y))
+    assert np.max(np.abs(out["grad"] - m.grad(y))) <= 1e-13 * np.max(np.abs(m.grad(y)))
+    assert np.max(np.abs(out["c"] - m.cons_c(y))) <= 1e-12 * np.max(np.abs(m.cons_c(y)))
+    J = m.jac_c(y).tocsr()
+    want = np.asarray(J[out["jr"], out["jc"]]).ravel()
+    assert not np.isnan(out["jv"]).any()
+    assert np.max(np.abs(out["jv"] - want)) <= 1e-13 * np.max(np.abs(want))
+    W = m.hess(y, lam, np.zeros(0)).tocsr()
+    want = np.asarray(W[out["wr"], out["wc"]]).ravel()
+    assert np.max(np.abs(out["wv"] - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_scratch_lists_partition_the_scratch():
+    """Every scratch double a kernel writes is summed exactly once."""
+    g = SPn.generate(SM.plate_pattern_model(8))
+    _, st = g.pattern_structure
+    seen = [q for lists in ("w_lists", "g_lists", "f_lists") for l in st[lists] for q in l]
+    assert sorted(seen) == list(range(st["ncoo"]))
+    assert g.scratch_per_stage == st["ncoo"] == 8 * 8 * 5 + 8 * 8 * 3
+    assert "nmpc_stage_reduce" in g.source and "nmpc_stage_eval" in g.source
+
+
+def test_pattern_with_data_and_setpoints():
+    """Two row patterns with per-instance data and an objective with two
+    setpoint slots and the stage trajectory, against direct evaluation."""
+    m = SPn.PatternModel("mixed", n_setpoint=3)
+    X = m.states(4, lb=-5.0)
+    U = m.controls(2, lb=-1.0, ub=1.0)
+    tr = m.traj()
+    m.row_pattern(lambda v, p, d: v[0] - p[0] - m.dt * (d[0] * v[1] + d[1] * sin(v[0])),
+                  [dict(target=X[0], vars=[X[0], U[0]], prevs=[X[0]], data=[1.5, 0.3]),
+                   dict(target=X[1], vars=[X[1], U[1]], prevs=[X[1]], data=[-0.5, 0.7])], nv=2, nprev=1, ndata=2)
+    m.row_pattern(lambda v, p, d: 2.0 * v[0] - p[0] + 0.5 * p[1] - v[1] * v[1],
+                  [dict(target=X[2], vars=[X[2], X[0]], prevs=[X[2], X[3]]),
+                   dict(target=X[3], vars=[X[3], X[1]], prevs=[X[3], X[0]])], nv=2, nprev=2)
+    m.objective_pattern(lambda v, d, s: d[0] * (v[0] - s[0]) ** 2 + (v[1] - s[1] * tr) ** 2,
+                        [dict(vars=[X[0], U[0]], data=[2.0], sps=[0, 2]),
+                         dict(vars=[X[3], U[1]], data=[0.5], sps=[1, 2])], nv=2, ndata=1, nsp=2)
+    g = SPn.generate(m)
+    assert g.uses_traj
+    H, dt = 3, 0.1
+    rng = np.random.default_rng(5)
+    y, x0, sp, traj = rng.normal(size=H * 6), rng.normal(size=4), rng.normal(size=3), rng.normal(size=H)
+    lam = rng.normal(size=H * 4)
+    out = expand_patterns(g, y, H, x0, dt, sp, traj, lam)
+
+    def rows(y):
+        Y = y.reshape(H, 6)
+        P = np.vstack([x0, Y[:-1, :4]])
+        r = np.empty((H, 4), dtype=y.dtype)
+        r[:, 0] = Y[:, 0] - P[:, 0] - dt * (1.5 * Y[:, 4] + 0.3 * np.sin(Y[:, 0]))
+        r[:, 1] = Y[:, 1] - P[:, 1] - dt * (-0.5 * Y[:, 5] + 0.7 * np.sin(Y[:, 1]))
+        r[:, 2] = 2.0 * Y[:, 2] - P[:, 2] + 0.5 * P[:, 3] - Y[:, 0] ** 2
+        r[:, 3] = 2.0 * Y[:, 3] - P[:, 3] + 0.5 * P[:, 0] - Y[:, 1] ** 2
+        return r.reshape(-1)
+
+    def obj(y):
+        Y = y.reshape(H, 6)
+        return np.sum(2.0 * (Y[:, 0] - sp[0]) ** 2 + (Y[:, 4] - sp[2] * traj) ** 2
+                      + 0.5 * (Y[:, 3] - sp[1]) ** 2 + (Y[:, 5] - sp[2] * traj) ** 2)
+
+    assert np.max(np.abs(out["c"] - rows(y))) <= 1e-14
+    assert abs(out["f"] - obj(y)) <= 1e-12
+    hcs = 1e-30
+    E = np.eye(H * 6)
+    Jcs = np.array([rows(y + 1j * hcs * E[i]).imag / hcs for i in range(H * 6)]).T
+    assert np.max(np.abs(out["jv"] - Jcs[out["jr"], out["jc"]])) <= 1e-14
+    assert np.count_nonzero(Jcs) == len(out["jv"])
+    gcs = np.array([obj(y + 1j * hcs * E[i]).imag / hcs for i in range(H * 6)])
+    assert np.max(np.abs(out["grad"] - gcs)) <= 1e-13
+
+    def lag_grad(y):
+        return np.array([(obj(y + 1j * hcs * E[i]) + lam @ rows(y + 1j * hcs * E[i])).imag / hcs
+                         for i in range(H * 6)])
+
+    h = 1e-6
+    Wfd = np.array([(lag_grad(y + h * E[i]) - lag_grad(y - h * E[i])) / (2 * h) for i in range(H * 6)])
+    assert np.max(np.abs(out["wv"] - Wfd[out["wr"], out["wc"]])) <= 1e-7
+    on = set(zip(out["wr"].tolist(), out["wc"].tolist()))
+    assert all((a, b) in on for a, b in zip(*np.nonzero(np.abs(np.tril(Wfd)) > 1e-6)))
+
+
+def test_generator_rules():
+    def model():
+        m = SPn.PatternModel("bad")
+        X = m.states(2)
+        U = m.controls(1)
+        return m, X, U
+
+    m, X, U = model()
+    m.row_pattern(lambda v, p, d: v[0] - p[0] - v[1], [dict(target=X[0], vars=[X[0], U[0]], prevs=[X[0]])],
+                  nv=2, nprev=1)
+    with pytest.raises(ValueError, match="without a row"):
+        SPn.generate(m)
+    m, X, U = model()
+    inst = [dict(target=X[0], vars=[X[1], U[0]], prevs=[X[0]]), dict(target=X[1], vars=[X[1], U[0]], prevs=[X[1]])]
+    m.row_pattern(lambda v, p, d: v[0] - p[0] - v[1], inst, nv=2, nprev=1)
+    with pytest.raises(ValueError, match="own state"):
+        SPn.generate(m)
+    m, X, U = model()
+    inst = [dict(target=X[0], vars=[X[0], X[0]], prevs=[X[0]]), dict(target=X[1], vars=[X[1], U[0]], prevs=[X[1]])]
+    m.row_pattern(lambda v, p, d: v[0] - p[0] - v[1], inst, nv=2, nprev=1)
+    with pytest.raises(ValueError, match="distinct"):
+        SPn.generate(m)
+    m, X, U = model()
+    inst = [dict(target=X[j], vars=[X[j], U[0]], prevs=[X[j]]) for j in range(2)]
+    m.row_pattern(lambda v, p, d: v[0] - p[0] * p[0] - v[1], inst, nv=2, nprev=1)
+    with pytest.raises(ValueError, match="linearly"):
+        SPn.generate(m)
+    m, X, U = model()
+    m.row_pattern(lambda v, p, d: v[0] - p[0] - v[1], [dict(target=X[j], vars=[X[j], U[0]], prevs=[X[j]])
+                                                        for j in range(2)], nv=2, nprev=1)
+    m.objective_pattern(lambda v, d, s: (v[0] - s[0]) ** 2, [dict(vars=[X[0]], sps=[3])], nv=1, nsp=1)
+    with pytest.raises(ValueError, match="setpoint"):
+        SPn.generate(m)
+    m, X, U = model()
+    with pytest.raises(ValueError, match="before the controls"):
+        m.states(1)
