@@ -326,12 +326,20 @@ def _loop_rate(N, p, w, steps, warmup, eager):
             "cold_iters": r0.iters, "nonzero_status": bad}
 
 
-def run_front_end(N, steps=30, warmup=2, eager=False):
+def _plate_summary(r):
+    keys = ("p50_resolve_ms", "p99_resolve_ms", "iters_per_s", "iters_per_resolve", "nonzero_status",
+            "cold_iters", "cold_status", "factor_ms", "phase_ms_per_resolve")
+    return {k: r[k] for k in keys}
+
+
+def run_front_end(N, steps=30, warmup=2, eager=False, plate_hand=None):
     """The headline workload written with the stage-pattern front end (its
     kernels generated from the stage expressions) beside the hand-written
-    DISTILLATION family: the same closed re-solve loop on each, and the
-    paper's case study (150 NMPC steps) through the generated case-study
-    model beside the hand-written one."""
+    DISTILLATION family: the same closed re-solve loop on each; the workload
+    plate written with index-data patterns beside the hand-written
+    HEATED_PLATE family (plate_hand: that family's run_plate result when the
+    caller has one); and the paper's case study (150 NMPC steps) through the
+    generated case-study model beside the hand-written one."""
     from paper_2606_04725_amd import simd, simd_models as SM
     from workloads import distillation_workload, reflux_workload
     w = distillation_workload("medium", 0, n_resolves=warmup + steps + 1)
@@ -347,6 +355,12 @@ def run_front_end(N, steps=30, warmup=2, eager=False):
         p.close()
     _progress(f"front end: generated {out['generated']['iters_per_s']:.0f} iters/s, "
               f"hand-written {out['hand_written']['iters_per_s']:.0f} iters/s")
+    hand = plate_hand if plate_hand is not None else run_plate(N, eager=eager)
+    out["plate"] = {"workload": hand["workload"] + "; generated = one stencil pattern and one tracking pattern",
+                    "generated": _plate_summary(run_plate(N, eager=eager, model="pattern")),
+                    "hand_written": _plate_summary(hand)}
+    _progress(f"front end plate: generated p50 {out['plate']['generated']['p50_resolve_ms']:.2f} ms, "
+              f"hand-written p50 {out['plate']['hand_written']['p50_resolve_ms']:.2f} ms")
     rw = reflux_workload()
     gr = simd.compile(SM.reflux_model(N=rw.N, Nf=rw.Nf, D=rw.D, F=rw.F, alpha=rw.alpha, xf=rw.xf, Ac=rw.Ac,
                                       At=rw.At, Ar=rw.Ar, w_u=rw.w_u))
@@ -639,15 +653,22 @@ def run_small(N, seeds=20, resolves=5, eager=False):
             "p50_first_solve_ms": _percentile(first, 50), "nonzero_status": sum(1 for s_ in statuses if s_ != 0)}
 
 
-def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False):
+def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False, model="hand_written"):
     """Heated plate: G x G grid, horizon H, dt 0.01, 16 heaters in [0, 1],
     T <= 1.5, Gaussian-bump target from the seed, T0 = 0.  One analyze and cold
     solve, then warm re-solves where the plant is the model (the next
     measurement is the predicted first-stage field).  With adjoint, after each
-    re-solve d u1*/d x0 (nu x G^2) and d f*/d setpoint (G^2) are computed."""
+    re-solve d u1*/d x0 (nu x G^2) and d f*/d setpoint (G^2) are computed.
+    model: the hand-written HEATED_PLATE family, or "pattern" for the same
+    plate written with the front end's index-data patterns."""
     from workloads import plate_workload
     w = plate_workload("large", seed, G=G, H=H)
-    p = N.Problem(N.plate_structure(G, H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi))
+    if model == "pattern":
+        from paper_2606_04725_amd import simd, simd_models as SM
+        st = N.stage_model_structure(simd.compile(SM.plate_pattern_model(G)), H, w.dt)
+    else:
+        st = N.plate_structure(G, H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi)
+    p = N.Problem(st)
     t0 = time.perf_counter()
     p.analyze()
     t_an = time.perf_counter() - t0
@@ -756,6 +777,8 @@ def main(argv=None):
     ap.add_argument("--case-study-only", action="store_true",
                     help="only run the paper's two case studies (distillation 150 steps, heated plate 38 steps)")
     ap.add_argument("--plate-only", action="store_true", help="only run the heated-plate workloads")
+    ap.add_argument("--plate-model", choices=("hand_written", "pattern"), default="hand_written",
+                    help="with --plate-only: the hand-written plate family or the index-data pattern model")
     ap.add_argument("--device-loop-only", action="store_true",
                     help="only run the closed loop driven from the host vs on the device")
     ap.add_argument("--front-end-only", action="store_true",
@@ -806,9 +829,10 @@ def main(argv=None):
     if a.plate_only:
         out = {}
         if a.plate_case in ("plain", "both"):
-            out["plate"] = run_plate(N, eager=a.eager)
+            out["plate"] = run_plate(N, eager=a.eager, model=a.plate_model)
         if a.plate_case in ("adjoint", "both"):
-            out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager)
+            out["plate_adjoint"] = run_plate(N, G=a.adjoint_grid, H=100, resolves=10, adjoint=True, eager=a.eager,
+                                             model=a.plate_model)
         print(json.dumps(out), flush=True)
         return 0
     w = distillation_workload("medium", a.seed, n_resolves=a.warmup + a.steps + 1)
@@ -909,7 +933,7 @@ def main(argv=None):
     out["case_study"] = run_case_study(N, eager=a.eager)
     out["plate_case_study"] = run_plate_case_study(N, eager=a.eager)
     out["mismatch"] = run_mismatch(N, eager=a.eager)
-    out["front_end"] = run_front_end(N, eager=a.eager)
+    out["front_end"] = run_front_end(N, eager=a.eager, plate_hand=out.get("plate"))
     out["device_loop"] = run_device_loop(N)
     if not a.no_ablation:
         out["ablation"] = ablations(N)

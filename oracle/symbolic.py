@@ -42,6 +42,38 @@ left (right) part only, otherwise to the separator.  Order: left box, right
 box, the separator's points in increasing index, its controls in increasing
 index.
 
+Stage-and-graph nested dissection (models of the stage-pattern front end,
+whose within-stage structure the analysis is not told).  With ns variables per
+stage, nx of them states, the projected graph on [0, ns) joins a != b when the
+matrix couples some variable a of one stage with variable b of the same or
+another stage.  A box [t0, t1) x V (V a set of stage variables) has two
+possible cuts:
+  * in time, when t1 - t0 >= 3: stage pos = t0 + (t1 - t0 - 1) // 2 times V
+    separates [t0, pos) x V from [pos + 1, t1) x V (|V| separator points);
+  * in the graph, when (t1 - t0) |V| > ND_LEAF and V holds at least three
+    states: a level structure of the projected graph restricted to V's
+    states C (the levels of a breadth-first search: level 0 the root, level
+    i + 1 the unvisited neighbours of level i).  The root: start at the
+    smallest vertex of C; repeatedly take the vertex of the last level with
+    the fewest neighbours in C (ties: smallest index) and move the root there
+    while that lengthens the structure.  With L >= 3 levels and R states
+    reached, the separator level l is, among the levels in [1, L - 2] whose
+    predecessors hold between R / 4 and 3 R / 4 states, the smallest one
+    (ties: levels 0..l holding closest to half of R, then the smallest l);
+    with no such level, the smallest l in [1, L - 2] whose levels 0..l hold
+    at least half of R, else L - 2.  The states of the levels before l form
+    the left part, those after l and the unreached ones the right part.  A
+    vertex of V that is not a state joins the left (right) part when its
+    neighbours among C meet the left (right) part only, else the separator;
+    then every such vertex with a neighbour across (left to right or right
+    to left) moves to the separator, all at once.  ((t1 - t0) |separator|
+    separator points.)  States of non-adjacent levels are never neighbours,
+    so the two parts are uncoupled over the whole range.
+The cut with fewer separator points wins, ties to the time cut; a box with no
+cut lists its variables in increasing index.  Order: left box, right box, the
+separator's variables in increasing index.  With no graph cut anywhere this is
+the stage nested dissection.
+
 Conventions: ``perm[k]`` is the original index of the k-th pivot (new -> old),
 ``iperm[v]`` is the pivot position of original index v (old -> new).
 
@@ -117,6 +149,106 @@ def stage_nd_order(H, ns):
         order.extend(range(pos * ns, (pos + 1) * ns))
 
     rec(0, H)
+    return np.array(order, dtype=np.int64)
+
+
+def _levels(adjV, V, root):
+    """Breadth-first levels from root inside V (adjV: neighbours within V)."""
+    seen = {root}
+    levels = [[root]]
+    while True:
+        nxt = sorted({b for a in levels[-1] for b in adjV[a] if b not in seen})
+        if not nxt:
+            return levels
+        seen.update(nxt)
+        levels.append(nxt)
+
+
+def graph_stage_nd_order(n, adj, H, ns, nx, cuts=None):
+    """Stage-and-graph nested dissection (rule in the module docstring):
+    perm (new -> old).  cuts, if a list, receives every cut made:
+    ("time", t0, t1, V, pos) or ("graph", t0, t1, left, S, right)."""
+    proj = [set() for _ in range(ns)]
+    for i in range(n):
+        for j in adj[i]:
+            a, b = i % ns, j % ns
+            if a != b:
+                proj[a].add(b)
+    order = []
+
+    def graph_cut(V):
+        C = [v for v in V if v < nx]
+        if len(C) < 3:
+            return None
+        Cs = set(C)
+        adjC = {a: [b for b in proj[a] if b in Cs] for a in C}
+        lv = _levels(adjC, C, C[0])
+        while True:
+            cand = min(lv[-1], key=lambda v: (len(adjC[v]), v))
+            lc = _levels(adjC, C, cand)
+            if len(lc) > len(lv):
+                lv = lc
+            else:
+                break
+        L = len(lv)
+        if L < 3:
+            return None
+        R = sum(len(x) for x in lv)
+        before = [0] * L            # states in the levels before each level
+        for l in range(1, L):
+            before[l] = before[l - 1] + len(lv[l - 1])
+        window = [l for l in range(1, L - 1) if R <= 4 * before[l] <= 3 * R]
+        if window:
+            sep = min(window, key=lambda l: (len(lv[l]), abs(2 * (before[l] + len(lv[l])) - R), l))
+        else:
+            sep = next((l for l in range(1, L - 1) if 2 * (before[l] + len(lv[l])) >= R), L - 2)
+        left_states = {v for x in lv[:sep] for v in x}
+        S = set(lv[sep])
+        right_states = Cs - left_states - S
+        left, right = set(left_states), set(right_states)
+        for v in V:
+            if v >= nx:
+                inl = any(b in left_states for b in proj[v])
+                inr = any(b in right_states for b in proj[v])
+                (left if inl and not inr else right if inr and not inl else S).add(v)
+        clash = {v for v in left if v >= nx and proj[v] & right} | {v for v in right if v >= nx and proj[v] & left}
+        left -= clash
+        right -= clash
+        S |= clash
+        return sorted(left), sorted(S), sorted(right)
+
+    def emit(t0, t1, V):
+        order.extend(t * ns + v for t in range(t0, t1) for v in V)
+
+    def rec(t0, t1, V):
+        best = None
+        if t1 - t0 >= 3:
+            best = (len(V), "time", None)
+        if (t1 - t0) * len(V) > ND_LEAF:
+            g = graph_cut(V)
+            if g is not None and (best is None or (t1 - t0) * len(g[1]) < best[0]):
+                best = ((t1 - t0) * len(g[1]), "graph", g)
+        if best is None:
+            emit(t0, t1, V)
+            return
+        if best[1] == "time":
+            pos = t0 + (t1 - t0 - 1) // 2
+            if cuts is not None:
+                cuts.append(("time", t0, t1, list(V), pos))
+            rec(t0, pos, V)
+            rec(pos + 1, t1, V)
+            emit(pos, pos + 1, V)
+        else:
+            left, S, right = best[2]
+            if cuts is not None:
+                cuts.append(("graph", t0, t1, left, S, right))
+            rec(t0, t1, left)
+            rec(t0, t1, right)
+            emit(t0, t1, S)
+
+    rec(0, H, list(range(ns)))
+    if sorted(order) != list(range(n)):
+        raise AssertionError("nested dissection did not produce a permutation")
     return np.array(order, dtype=np.int64)
 
 
@@ -324,11 +456,13 @@ def etree_liu(n, rows, cols, iperm):
     return np.array(parent, dtype=np.int64)
 
 
-def final_permutation(n, rows, cols, lattice=None, stages=None):
+def final_permutation(n, rows, cols, lattice=None, stages=None, graph_stages=None):
     """The permutation of ``analyze`` (ordering, then the postorder of its
     elimination tree) without the column structures: perm (new -> old)."""
     if lattice is not None:
         perm_md = lattice_nd_order(n, adjacency_from_lower(n, rows, cols), *lattice)
+    elif graph_stages is not None:
+        perm_md = graph_stage_nd_order(n, adjacency_from_lower(n, rows, cols), *graph_stages)
     elif stages is not None:
         perm_md = stage_nd_order(*stages)
     else:
@@ -338,12 +472,13 @@ def final_permutation(n, rows, cols, lattice=None, stages=None):
     return perm_md[postorder(etree_liu(n, rows, cols, iperm_md))]
 
 
-def analyze(n, rows, cols, lattice=None, stages=None):
+def analyze(n, rows, cols, lattice=None, stages=None, graph_stages=None):
     """Full symbolic analysis of a lower pattern (original indexing).
 
     lattice = (H, G, ns) selects the lattice nested dissection of a plate
     transcription, stages = (H, ns) the stage nested dissection of a
-    stage-major transcription; otherwise exact minimum degree.  Returns a dict with perm,
+    stage-major transcription, graph_stages = (H, ns, nx) the stage-and-graph
+    nested dissection; otherwise exact minimum degree.  Returns a dict with perm,
     iperm, parent (column etree in final order), colcount (per column of the
     exact factor), nnz_L (exact), snode_ptr, snode_rows (row list per supernode,
     stored pattern), snode_parent.
@@ -351,6 +486,8 @@ def analyze(n, rows, cols, lattice=None, stages=None):
     adj = adjacency_from_lower(n, rows, cols)
     if lattice is not None:
         perm_md = lattice_nd_order(n, adj, *lattice)
+    elif graph_stages is not None:
+        perm_md = graph_stage_nd_order(n, adj, *graph_stages)
     elif stages is not None:
         perm_md = stage_nd_order(*stages)
     else:

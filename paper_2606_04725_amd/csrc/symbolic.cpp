@@ -17,7 +17,24 @@
 //     most kNdLeaf points, or with no cuttable dimension, are leaves.  A control
 //     follows the side holding every lattice point it is coupled to, else the
 //     slab.  Order: left box, right box, slab points, slab controls; inside a
-//     leaf, points then controls, each in increasing index.
+//     leaf, points then controls, each in increasing index.  For stage models
+//     (whose within-stage structure comes only from their patterns) on the
+//     (stage x projected graph) product: the projected graph joins stage
+//     variables a != b that the matrix couples in any pair of stages; a box
+//     [t0, t1) x V is cut in time (t1 - t0 >= 3: the middle stage t0 +
+//     (t1 - t0 - 1) / 2 times V) or, when it holds more than kNdLeaf points
+//     and V at least 3 states, in the graph by one level of a breadth-first
+//     level structure over V's states (root moved from the smallest state to
+//     the least-connected state of the last level while that lengthens the
+//     structure; with L >= 3 levels and R states reached: among levels l in
+//     [1, L - 2] with between R / 4 and 3 R / 4 states before them the
+//     smallest, ties closest to halving R, then the first; none: the first
+//     level whose prefix holds half of R, else L - 2).  Earlier levels go
+//     left, later levels and unreached states right; a non-state joins the
+//     side its state neighbours lie on when they lie on one side, else the
+//     separator, and non-states with a neighbour across the cut then move to
+//     the separator together.  Fewer separator points wins, ties to time; no
+//     cut: the box's variables in increasing index.
 //  2. Elimination tree parent(j) = min{i > j : L_ij != 0} and column
 //     structures struct(L_*j) = struct(K_P lower col j) united with the
 //     structures of j's children minus the children themselves.
@@ -206,6 +223,183 @@ std::vector<int32_t> stage_nd(int H, int ns) {
     return out;
 }
 
+// Stage-and-graph nested dissection of a stage-major transcription whose
+// stages carry no geometry (perm, new -> old); ent: lower pattern entries;
+// the first nx variables of a stage are its states.
+class GraphStageNd {
+  public:
+    GraphStageNd(int n, int H, int ns, int nx, const std::vector<std::pair<int32_t, int32_t>>& ent)
+        : H_(H), ns_(ns), nx_(nx), proj_(ns), in_(ns, 0), seen_(ns, 0), side_(ns, 0) {
+        for (auto [i, j] : ent) {
+            const int a = i % ns, b = j % ns;
+            if (i != j && a != b) {
+                proj_[a].push_back(b);
+                proj_[b].push_back(a);
+            }
+        }
+        for (auto& l : proj_) {
+            std::sort(l.begin(), l.end());
+            l.erase(std::unique(l.begin(), l.end()), l.end());
+        }
+        out_.reserve(n);
+    }
+    std::vector<int32_t> order() {
+        std::vector<int32_t> all(ns_);
+        for (int v = 0; v < ns_; ++v) all[v] = v;
+        rec(0, H_, all);
+        return out_;
+    }
+
+  private:
+    using Levels = std::vector<std::vector<int32_t>>;
+    // breadth-first levels from root inside the states marked with stamp_in_
+    Levels levels(int32_t root) {
+        const int s = ++stamp_seen_;
+        Levels lv{{root}};
+        seen_[root] = s;
+        for (;;) {
+            std::vector<int32_t> nxt;
+            for (int32_t a : lv.back())
+                for (int32_t b : proj_[a])
+                    if (in_[b] == stamp_in_ && seen_[b] != s) {
+                        seen_[b] = s;
+                        nxt.push_back(b);
+                    }
+            if (nxt.empty()) return lv;
+            std::sort(nxt.begin(), nxt.end());
+            lv.push_back(std::move(nxt));
+        }
+    }
+    int deg_in(int32_t v) const {
+        int d = 0;
+        for (int32_t b : proj_[v]) d += in_[b] == stamp_in_;
+        return d;
+    }
+    // level-structure cut of V over its states: false when V holds fewer than
+    // 3 states or their structure has fewer than 3 levels
+    bool graph_cut(const std::vector<int32_t>& V, std::vector<int32_t>& left, std::vector<int32_t>& sep,
+                   std::vector<int32_t>& right) {
+        stamp_in_ = ++stamp_in_ctr_;
+        int nc = 0;
+        int32_t first = -1;
+        for (int32_t v : V)
+            if (v < nx_) {
+                in_[v] = stamp_in_;
+                if (first < 0) first = v;
+                ++nc;
+            }
+        if (nc < 3) return false;
+        Levels lv = levels(first);
+        for (;;) {
+            int32_t cand = -1;
+            int cdeg = 0;
+            for (int32_t v : lv.back()) {
+                const int d = deg_in(v);
+                if (cand < 0 || d < cdeg || (d == cdeg && v < cand)) {
+                    cand = v;
+                    cdeg = d;
+                }
+            }
+            Levels lc = levels(cand);
+            if (lc.size() > lv.size()) lv = std::move(lc);
+            else break;
+        }
+        const int L = (int)lv.size();
+        if (L < 3) return false;
+        std::vector<int64_t> before(L, 0);   // states in the levels before each level
+        for (int l = 1; l < L; ++l) before[l] = before[l - 1] + (int64_t)lv[l - 1].size();
+        const int64_t R = before[L - 1] + (int64_t)lv[L - 1].size();
+        int cut = -1;
+        int64_t csize = 0, cdist = 0;
+        for (int l = 1; l <= L - 2; ++l) {
+            if (4 * before[l] < R || 4 * before[l] > 3 * R) continue;
+            const int64_t sz = (int64_t)lv[l].size();
+            const int64_t dist = std::llabs(2 * (before[l] + sz) - R);
+            if (cut < 0 || sz < csize || (sz == csize && dist < cdist)) {
+                cut = l;
+                csize = sz;
+                cdist = dist;
+            }
+        }
+        if (cut < 0) {
+            cut = L - 2;
+            for (int l = 1; l <= L - 2; ++l)
+                if (2 * (before[l] + (int64_t)lv[l].size()) >= R) {
+                    cut = l;
+                    break;
+                }
+        }
+        // sides: 1 left, 2 separator, 3 right (states first, then the others)
+        const int base = stamp_side_ += 4;
+        for (int l = 0; l < L; ++l)
+            for (int32_t v : lv[l]) side_[v] = base + (l < cut ? 1 : (l == cut ? 2 : 3));
+        for (int32_t v : V)
+            if (v < nx_ && (side_[v] <= base || side_[v] > base + 3)) side_[v] = base + 3;   // unreached
+        for (int32_t v : V) {
+            if (v < nx_) continue;
+            bool inl = false, inr = false;
+            for (int32_t b : proj_[v])
+                if (b < nx_ && in_[b] == stamp_in_) {
+                    inl = inl || side_[b] == base + 1;
+                    inr = inr || side_[b] == base + 3;
+                }
+            side_[v] = base + (inl && !inr ? 1 : (inr && !inl ? 3 : 2));
+        }
+        // non-states with a neighbour across the cut move to the separator, all at once
+        std::vector<int32_t> clash;
+        for (int32_t v : V) {
+            if (v < nx_ || side_[v] == base + 2) continue;
+            const int other = side_[v] == base + 1 ? base + 3 : base + 1;
+            for (int32_t b : proj_[v])   // (vertices outside V hold older stamps)
+                if (side_[b] == other) {
+                    clash.push_back(v);
+                    break;
+                }
+        }
+        for (int32_t v : clash) side_[v] = base + 2;
+        left.clear();
+        sep.clear();
+        right.clear();
+        for (int32_t v : V) (side_[v] == base + 1 ? left : (side_[v] == base + 2 ? sep : right)).push_back(v);
+        return true;
+    }
+    void emit(int t0, int t1, const std::vector<int32_t>& V) {
+        for (int t = t0; t < t1; ++t)
+            for (int32_t v : V) out_.push_back(t * ns_ + v);
+    }
+    void rec(int t0, int t1, const std::vector<int32_t>& V) {
+        const int64_t span = t1 - t0;
+        bool have = false, graph = false;
+        int64_t best = 0;
+        if (span >= 3) {
+            have = true;
+            best = (int64_t)V.size();
+        }
+        std::vector<int32_t> left, sep, right;
+        if (span * (int64_t)V.size() > kNdLeaf && graph_cut(V, left, sep, right) &&
+            (!have || span * (int64_t)sep.size() < best)) {
+            have = graph = true;
+        }
+        if (!have) {
+            emit(t0, t1, V);
+        } else if (!graph) {
+            const int pos = t0 + (t1 - t0 - 1) / 2;
+            rec(t0, pos, V);
+            rec(pos + 1, t1, V);
+            emit(pos, pos + 1, V);
+        } else {
+            rec(t0, t1, left);
+            rec(t0, t1, right);
+            emit(t0, t1, sep);
+        }
+    }
+    int H_, ns_, nx_;
+    std::vector<std::vector<int32_t>> proj_;
+    std::vector<int> in_, seen_, side_;
+    int stamp_in_ = 0, stamp_in_ctr_ = 0, stamp_seen_ = 0, stamp_side_ = 0;
+    std::vector<int32_t> out_;
+};
+
 // Lower pattern of P K P^T as sorted per-column row lists (diagonal included).
 Adj permute_lower(int n, const std::vector<std::pair<int32_t, int32_t>>& ent,
                   const std::vector<int32_t>& iperm) {
@@ -365,9 +559,12 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     // ---- 1. fill-reducing ordering ----------------------------------------------
     std::vector<int32_t> perm_md;
     if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION &&
-        (st.desc.family == NMPC_FAMILY_DISTILLATION || st.desc.family == NMPC_FAMILY_REFLUX_COLUMN ||
-         st.desc.family == NMPC_FAMILY_STAGE_MODEL)) {
+        (st.desc.family == NMPC_FAMILY_DISTILLATION || st.desc.family == NMPC_FAMILY_REFLUX_COLUMN)) {
         perm_md = stage_nd(st.H, n / st.H);
+    } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_STAGE_MODEL) {
+        GraphStageNd nd(n, st.H, n / st.H, st.nx, ent);
+        perm_md = nd.order();
+        if ((int)perm_md.size() != n) throw std::runtime_error("nested dissection: incomplete order");
     } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
         LatticeNd nd(n, st.H, st.desc.grid, n / st.H, ent);
         perm_md = nd.order();

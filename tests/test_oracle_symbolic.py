@@ -285,3 +285,111 @@ def test_stage_nested_dissection(N_, H):
     for i, j in zip(r, c):
         ti, tj = i // m.ns, j // m.ns
         assert not ((ti < mid < tj) or (tj < mid < ti))
+
+
+def _check_cuts(cuts, r, c, ns):
+    """No matrix entry joins the two sides of any cut over the cut's range."""
+    side = {}
+    for cut in cuts:
+        if cut[0] == "time":
+            _, t0, t1, V, pos = cut
+            Vs = set(V)
+            lo = {t * ns + v for t in range(t0, pos) for v in Vs}
+            hi = {t * ns + v for t in range(pos + 1, t1) for v in Vs}
+        else:
+            _, t0, t1, left, sep, right = cut
+            assert left and right and sep
+            assert not (set(left) & set(right)) and not (set(sep) & (set(left) | set(right)))
+            lo = {t * ns + v for t in range(t0, t1) for v in left}
+            hi = {t * ns + v for t in range(t0, t1) for v in right}
+        for i, j in zip(r, c):
+            assert not ((i in lo and j in hi) or (i in hi and j in lo)), cut[:3]
+        side[cut[:3]] = True
+    return side
+
+
+def test_graph_stage_nd_is_stage_nd_when_no_graph_cut_applies():
+    """Small columns: every box either holds at most ND_LEAF points or is cut
+    cheaper in time (a tray-chain level plus the two controls, which enter
+    every tray's row, times the range), so the rule reduces to the stage
+    nested dissection."""
+    from oracle.distillation import DistillationOCP
+    for N_, H in ((4, 7), (10, 20)):
+        m = DistillationOCP(N_, H, 0.1, 2.5)
+        r, c = S.kkt_lower_pattern(m)
+        adj = S.adjacency_from_lower(m.n, r, c)
+        cuts = []
+        order = S.graph_stage_nd_order(m.n, adj, m.H, m.ns, m.nx, cuts=cuts)
+        assert np.array_equal(order, S.stage_nd_order(m.H, m.ns))
+        assert all(cut[0] == "time" for cut in cuts)
+
+
+def test_graph_stage_nd_on_the_workload_column():
+    """40 trays, horizon 100: short stage ranges are cut along the tray chain
+    (a level of two trays plus both controls); every cut leaves its sides
+    uncoupled and the factor is smaller than the stage nested dissection's."""
+    from oracle.distillation import DistillationOCP
+    m = DistillationOCP(40, 100, 0.05, 2.5)
+    r, c = S.kkt_lower_pattern(m)
+    adj = S.adjacency_from_lower(m.n, r, c)
+    cuts = []
+    S.graph_stage_nd_order(m.n, adj, m.H, m.ns, m.nx, cuts=cuts)
+    _check_cuts(cuts, r, c, m.ns)
+    graph = [cut for cut in cuts if cut[0] == "graph"]
+    assert graph
+    for cut in graph:       # the controls, where the box has them, are in the separator
+        for u in (m.nx, m.nx + 1):
+            assert u not in cut[3] and u not in cut[5]
+    assert any(m.nx in cut[4] and m.nx + 1 in cut[4] for cut in graph)
+    a = S.analyze(m.n, r, c, graph_stages=(m.H, m.ns, m.nx))
+    b = S.analyze(m.n, r, c, stages=(m.H, m.ns))
+    assert a["nnz_L"] < 0.7 * b["nnz_L"], (a["nnz_L"], b["nnz_L"])
+
+
+@pytest.mark.parametrize("G,H", [(4, 3), (8, 6), (12, 1)])
+def test_graph_stage_nd_on_the_plate(G, H):
+    """On the plate's condensed matrix (whose stages are grids): a permutation;
+    every cut, in time or in the graph, leaves its two sides uncoupled; graph
+    cuts are made (the grid has long paths); the factor pattern equals dense
+    elimination in that order; and the fill is below the stage nested
+    dissection's (which keeps each stage whole) and within 10% of the lattice
+    nested dissection's, which is told the grid (the heater controls follow
+    the side of the nodes they heat, as there)."""
+    from oracle.plate import PlateOCP
+    m = PlateOCP(G, H, 0.01)
+    r, c = S.kkt_lower_pattern(m)
+    adj = S.adjacency_from_lower(m.n, r, c)
+    cuts = []
+    order = S.graph_stage_nd_order(m.n, adj, m.H, m.ns, m.nx, cuts=cuts)
+    assert sorted(order.tolist()) == list(range(m.n))
+    _check_cuts(cuts, r, c, m.ns)
+    assert any(cut[0] == "graph" for cut in cuts)
+    a = S.analyze(m.n, r, c, graph_stages=(m.H, m.ns, m.nx))
+    iperm = a["iperm"]
+    M, par_dense = _dense_symbolic(m.n, [iperm[i] for i in r], [iperm[j] for j in c])
+    assert np.array_equal(a["parent"], par_dense)
+    assert a["nnz_L"] == int(M.sum())
+    b = S.analyze(m.n, r, c, stages=(m.H, m.ns))
+    lat = S.analyze(m.n, r, c, lattice=(m.H, G, m.ns))
+    if G >= 8:
+        assert a["nnz_L"] < b["nnz_L"], (a["nnz_L"], b["nnz_L"])
+        assert a["nnz_L"] <= 1.1 * lat["nnz_L"], (a["nnz_L"], lat["nnz_L"])
+
+
+def test_graph_stage_nd_level_separator_on_a_path():
+    """A single stage whose variables form a path 0 - 1 - ... - 99: the root
+    search ends at an end of the path, the levels are single vertices, and
+    the first cut takes the vertex where half the path is reached (every
+    level in the balanced window has one vertex)."""
+    n = 100
+    adj = [set() for _ in range(n)]
+    for v in range(n - 1):
+        adj[v].add(v + 1)
+        adj[v + 1].add(v)
+    cuts = []
+    order = S.graph_stage_nd_order(n, adj, 1, n, n, cuts=cuts)
+    assert sorted(order.tolist()) == list(range(n))
+    first = cuts[0]
+    assert first[0] == "graph" and first[4] == [49]
+    assert first[3] == list(range(49)) and first[5] == list(range(50, 100))
+    assert order[-1] == 49

@@ -164,3 +164,44 @@ def test_generator_rules():
     m, X, U = model()
     with pytest.raises(ValueError, match="before the controls"):
         m.states(1)
+
+
+def _stage_symbolic_case(kind):
+    from oracle.distillation import DistillationOCP
+    from oracle.plate_case import PlateCaseOCP
+    from paper_2606_04725_amd import simd
+    if kind == "plate8":
+        return simd.compile(SM.plate_pattern_model(8)), PlateOCP(8, 6, 0.01)
+    if kind == "plate16":
+        return simd.compile(SM.plate_pattern_model(16)), PlateOCP(16, 10, 0.01)
+    if kind == "column":
+        return (simd.compile(SM.distillation_model(6, 2.3, F=1.0, rho=0.05)),
+                DistillationOCP(6, 30, 0.1, 2.3, F=1.0, rho=0.05))
+    return simd.compile(SM.plate_case_model(n=9)), PlateCaseOCP(H=5, n=9)
+
+
+@pytest.mark.parametrize("kind", ["plate8", "plate16", "column", "plate_case"])
+def test_stage_model_symbolic_bit_exact_vs_oracle(kind):
+    """The library's analysis of a front-end model (its default ordering, the
+    stage-and-graph nested dissection, told only the patterns and the number
+    of states) equals the oracle's on the oracle model's own condensed
+    pattern: permutation, elimination tree, column counts and supernodes."""
+    from oracle import symbolic as S
+    from paper_2606_04725_amd import nmpc as N
+    g, m = _stage_symbolic_case(kind)
+    p = N.Problem(N.stage_model_structure(g, m.H, m.dt))
+    p.analyze()
+    lib = p.export_symbolic()
+    r, c = S.kkt_lower_pattern(m)
+    pat = p.patterns()
+    assert set(zip(pat["k_rows"].tolist(), pat["k_cols"].tolist())) == set(zip(r, c))
+    a = S.analyze(m.n, r, c, graph_stages=(m.H, m.ns, m.nx))
+    assert np.array_equal(lib["perm"], a["perm"])
+    assert np.array_equal(lib["parent"], a["parent"])
+    assert np.array_equal(lib["colcount"], a["colcount"])
+    assert np.array_equal(lib["snode_ptr"], a["snode_ptr"])
+    rp = lib["snode_rows_ptr"]
+    for s_, rows in enumerate(a["snode_rows"]):
+        assert np.array_equal(lib["snode_rows"][rp[s_]:rp[s_ + 1]], rows)
+    assert lib["nnz_l"] == a["nnz_L"] and lib["flops"] == a["flops"]
+    p.close()
