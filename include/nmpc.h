@@ -119,11 +119,16 @@ typedef struct nmpc_stage_model {
                                    gradient and objective terms; the library owns the array */
 } nmpc_stage_model;
 
-/* Fill-reducing ordering of the analysis (eq. 19): nested dissection of the
- * family's stage structure (default: one-stage separators for the
- * distillation column, stage x grid slabs for the plate), or exact minimum
- * degree of the condensed matrix's elimination graph. */
-enum { NMPC_ORDER_NESTED_DISSECTION = 0, NMPC_ORDER_MIN_DEGREE = 1 };
+/* Fill-reducing ordering of the analysis (eq. 19).  NESTED_DISSECTION, the
+ * default: stage-and-graph nested dissection of every family (boxes of stages
+ * x stage variables cut by a middle stage or by one breadth-first level of the
+ * graph the condensed matrix induces on a stage's states; controls and other
+ * non-states follow their state neighbours' side, else the separator).
+ * MIN_DEGREE: exact minimum degree of the condensed matrix's elimination
+ * graph.  FAMILY_DISSECTION: the families' own dissections (one-stage
+ * separators for the columns and front-end models, stage x grid slabs for the
+ * plate). */
+enum { NMPC_ORDER_NESTED_DISSECTION = 0, NMPC_ORDER_MIN_DEGREE = 1, NMPC_ORDER_FAMILY_DISSECTION = 2 };
 
 /* How the Newton system of Section 3.2 is made solvable by Cholesky (the two
  * reformulations the section names).  LIFTED: Lifted-KKT, the equalities

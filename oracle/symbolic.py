@@ -5,12 +5,15 @@ Given the lower-triangular sparsity pattern of the condensed matrix K_c^l
 
   * the fill-reducing permutation P (eq. 19).  The paper names minimum degree
     and nested dissection without fixing one.  The readings taken here: nested
-    dissection of the stage structure by default -- stage nested dissection for
-    the distillation family (its stages couple only to their neighbours, so one
-    stage separates the horizon: a shallow elimination tree, whose critical
-    path is what a GPU factorization waits on), lattice nested dissection
-    (rule below) for the plate family, whose condensed matrix is a
-    three-dimensional (stage x grid) lattice -- and, as an option, exact
+    dissection of the stage structure by default -- the stage-and-graph
+    nested dissection (rule below) for every family: stages couple only to
+    their neighbours, so one stage separates the horizon (a shallow
+    elimination tree, whose critical path is what a GPU factorization waits
+    on), and within a range of stages a level of the graph the matrix
+    induces on a stage's states separates it as well; the families' own
+    dissections as an option -- stage nested dissection for the columns,
+    lattice nested dissection for the plate family, whose condensed matrix
+    is a three-dimensional (stage x grid) lattice -- and, as an option, exact
     minimum degree on the elimination graph (true degrees, no mass
     elimination, no absorption, no dense-row handling), ties broken by the
     smallest original index.  Every ordering is followed by a postorder of the
@@ -175,8 +178,15 @@ def graph_stage_nd_order(n, adj, H, ns, nx, cuts=None):
             if a != b:
                 proj[a].add(b)
     order = []
+    memo = {}    # a cut depends on V only, and time cuts repeat V over many ranges
 
     def graph_cut(V):
+        key = tuple(V)
+        if key not in memo:
+            memo[key] = level_cut(V)
+        return memo[key]
+
+    def level_cut(V):
         C = [v for v in V if v < nx]
         if len(C) < 3:
             return None

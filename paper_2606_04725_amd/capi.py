@@ -16,7 +16,7 @@ NMPC_MAX_ITER, NMPC_LINESEARCH_FAIL, NMPC_REG_FAIL, NMPC_NONFINITE = 1, 2, 3, 4
 NMPC_ERR_INVALID_ARG, NMPC_ERR_BAD_ORDER, NMPC_ERR_STRUCT_MISMATCH = -1, -2, -3
 NMPC_ERR_NO_DEVICE, NMPC_ERR_HIP, NMPC_ERR_OOM, NMPC_ERR_UNSUPPORTED = -4, -5, -6, -7
 NMPC_FAMILY_DISTILLATION, NMPC_FAMILY_HEATED_PLATE, NMPC_FAMILY_REFLUX_COLUMN, NMPC_FAMILY_STAGE_MODEL = 1, 2, 3, 4
-NMPC_ORDER_NESTED_DISSECTION, NMPC_ORDER_MIN_DEGREE = 0, 1
+NMPC_ORDER_NESTED_DISSECTION, NMPC_ORDER_MIN_DEGREE, NMPC_ORDER_FAMILY_DISSECTION = 0, 1, 2
 NMPC_KKT_LIFTED, NMPC_KKT_HYKKT = 0, 1
 
 

@@ -430,7 +430,8 @@ static bool build_stage_model(const nmpc_structure& s, Structure& st, std::strin
 bool build_structure(const nmpc_structure& s, Structure& out, std::string& err) {
     out = Structure();
     out.desc = s;
-    if (s.ordering != NMPC_ORDER_NESTED_DISSECTION && s.ordering != NMPC_ORDER_MIN_DEGREE) {
+    if (s.ordering != NMPC_ORDER_NESTED_DISSECTION && s.ordering != NMPC_ORDER_MIN_DEGREE &&
+        s.ordering != NMPC_ORDER_FAMILY_DISSECTION) {
         err = "unknown ordering";
         return false;
     }

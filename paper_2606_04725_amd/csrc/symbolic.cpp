@@ -4,9 +4,9 @@
 //  1. Fill-reducing ordering P (NMPC_ORDER_* of the structure).  Minimum
 //     degree: exact, on the elimination graph of the condensed matrix pattern
 //     (true degrees, no mass elimination, no element absorption; ties go to the
-//     smallest original index).  Nested dissection, the default: for the
+//     smallest original index).  Family dissection: for the
 //     distillation families (the workload column and the reflux column of the
-//     case study) by stages (a range of fewer than three stages keeps
+//     case study) and front-end models by stages (a range of fewer than three stages keeps
 //     its order, otherwise its middle stage t0 + (t1 - t0 - 1) / 2 separates
 //     it: left range, right range, separator stage); for the plate family on
 //     the (stage x grid) lattice of its condensed matrix: a box of lattice
@@ -17,9 +17,10 @@
 //     most kNdLeaf points, or with no cuttable dimension, are leaves.  A control
 //     follows the side holding every lattice point it is coupled to, else the
 //     slab.  Order: left box, right box, slab points, slab controls; inside a
-//     leaf, points then controls, each in increasing index.  For stage models
-//     (whose within-stage structure comes only from their patterns) on the
-//     (stage x projected graph) product: the projected graph joins stage
+//     leaf, points then controls, each in increasing index.  Nested
+//     dissection, the default for every family, on the (stage x projected
+//     graph) product of the condensed matrix, which needs no geometry (the
+//     first nx variables of a stage are its states): the projected graph joins stage
 //     variables a != b that the matrix couples in any pair of stages; a box
 //     [t0, t1) x V is cut in time (t1 - t0 >= 3: the middle stage t0 +
 //     (t1 - t0 - 1) / 2 times V) or, when it holds more than kNdLeaf points
@@ -558,14 +559,13 @@ void symbolic_analyze(const Structure& st, Symbolic& sym) {
     ent.erase(std::unique(ent.begin(), ent.end()), ent.end());
     // ---- 1. fill-reducing ordering ----------------------------------------------
     std::vector<int32_t> perm_md;
-    if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION &&
-        (st.desc.family == NMPC_FAMILY_DISTILLATION || st.desc.family == NMPC_FAMILY_REFLUX_COLUMN)) {
-        perm_md = stage_nd(st.H, n / st.H);
-    } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_STAGE_MODEL) {
+    if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION) {
         GraphStageNd nd(n, st.H, n / st.H, st.nx, ent);
         perm_md = nd.order();
         if ((int)perm_md.size() != n) throw std::runtime_error("nested dissection: incomplete order");
-    } else if (st.desc.ordering == NMPC_ORDER_NESTED_DISSECTION && st.desc.family == NMPC_FAMILY_HEATED_PLATE) {
+    } else if (st.desc.ordering == NMPC_ORDER_FAMILY_DISSECTION && st.desc.family != NMPC_FAMILY_HEATED_PLATE) {
+        perm_md = stage_nd(st.H, n / st.H);
+    } else if (st.desc.ordering == NMPC_ORDER_FAMILY_DISSECTION) {
         LatticeNd nd(n, st.H, st.desc.grid, n / st.H, ent);
         perm_md = nd.order();
         if ((int)perm_md.size() != n) throw std::runtime_error("nested dissection: incomplete order");

@@ -27,8 +27,12 @@ def _symbolic_parity(Ntr, H, alpha=2.5, ordering=N.capi.NMPC_ORDER_NESTED_DISSEC
     m = DistillationOCP(Ntr, H, 0.1, alpha, Hc=Hc)
     assert p.m_c == m.m_c
     r, c = S.kkt_lower_pattern(m)
-    nd = ordering == N.capi.NMPC_ORDER_NESTED_DISSECTION
-    a = S.analyze(m.n, r, c, stages=(m.H, m.ns) if nd else None)
+    if ordering == N.capi.NMPC_ORDER_NESTED_DISSECTION:
+        a = S.analyze(m.n, r, c, graph_stages=(m.H, m.ns, m.nx))
+    elif ordering == N.capi.NMPC_ORDER_FAMILY_DISSECTION:
+        a = S.analyze(m.n, r, c, stages=(m.H, m.ns))
+    else:
+        a = S.analyze(m.n, r, c)
     assert np.array_equal(lib["perm"], a["perm"])
     assert np.array_equal(lib["parent"], a["parent"])
     assert np.array_equal(lib["colcount"], a["colcount"])
@@ -69,6 +73,11 @@ def test_symbolic_bit_exact_vs_oracle_min_degree(Ntr, H):
     _symbolic_parity(Ntr, H, ordering=N.capi.NMPC_ORDER_MIN_DEGREE)
 
 
+@pytest.mark.parametrize("Ntr,H", [(2, 1), (3, 4), (10, 20), (40, 100)])
+def test_symbolic_bit_exact_vs_oracle_family_dissection(Ntr, H):
+    _symbolic_parity(Ntr, H, ordering=N.capi.NMPC_ORDER_FAMILY_DISSECTION)
+
+
 @pytest.mark.slow
 def test_symbolic_bit_exact_batch_instance_sizes():
     from workloads.generators import batch_distillation_workloads
@@ -77,15 +86,20 @@ def test_symbolic_bit_exact_batch_instance_sizes():
     _symbolic_parity(big.N, big.H, big.alpha)
 
 
+@pytest.mark.parametrize("family", [False, True], ids=["nested_dissection", "family_dissection"])
 @pytest.mark.parametrize("G,H", [(4, 3), (8, 4), (12, 7), (16, 10)])
-def test_plate_symbolic_bit_exact_vs_oracle(G, H):
+def test_plate_symbolic_bit_exact_vs_oracle(G, H, family):
     from oracle.plate import PlateOCP
-    p = N.Problem(N.plate_structure(G, H, 0.01))
+    o = N.capi.NMPC_ORDER_FAMILY_DISSECTION if family else N.capi.NMPC_ORDER_NESTED_DISSECTION
+    p = N.Problem(N.plate_structure(G, H, 0.01, ordering=o))
     p.analyze()
     lib = p.export_symbolic()
     m = PlateOCP(G, H, 0.01)
     r, c = S.kkt_lower_pattern(m)
-    a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
+    if family:
+        a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
+    else:
+        a = S.analyze(m.n, r, c, graph_stages=(H, m.ns, m.nx))
     for key in ("perm", "parent", "colcount", "snode_ptr"):
         assert np.array_equal(lib[key], a[key if key != "snode_ptr" else "snode_ptr"]), key
     rp = lib["snode_rows_ptr"]
@@ -98,14 +112,21 @@ def test_plate_symbolic_bit_exact_vs_oracle(G, H):
 
 
 def test_plate_symbolic_bit_exact_full_size():
-    """The 32 x 32 x 50 plate workload (n = 52,000): the whole analysis."""
+    """The 32 x 32 x 50 plate workload (n = 52,000): the whole analysis
+    under the family (lattice) dissection, and the permutation under the
+    default one (the oracle's column structures in that order take three
+    minutes of host time; its permutation a few seconds)."""
     from oracle.plate import PlateOCP
     G, H = 32, 50
-    p = N.Problem(N.plate_structure(G, H, 0.01))
-    p.analyze()
-    lib = p.export_symbolic()
     m = PlateOCP(G, H, 0.01)
     r, c = S.kkt_lower_pattern(m)
+    p = N.Problem(N.plate_structure(G, H, 0.01))
+    p.analyze()
+    assert np.array_equal(p.export_symbolic()["perm"],
+                          S.final_permutation(m.n, r, c, graph_stages=(H, m.ns, m.nx)))
+    p = N.Problem(N.plate_structure(G, H, 0.01, ordering=N.capi.NMPC_ORDER_FAMILY_DISSECTION))
+    p.analyze()
+    lib = p.export_symbolic()
     a = S.analyze(m.n, r, c, lattice=(H, G, m.ns))
     for key in ("perm", "parent", "colcount", "snode_ptr"):
         assert np.array_equal(lib[key], a[key]), key
@@ -131,7 +152,7 @@ def test_plate_permutation_bit_exact_differentiated_size():
     assert np.array_equal(q.export_symbolic()["perm"], perm)
     m = PlateOCP(G, H, 0.01)
     r, c = S.kkt_lower_pattern(m)
-    assert np.array_equal(perm, S.final_permutation(m.n, r, c, lattice=(H, G, m.ns)))
+    assert np.array_equal(perm, S.final_permutation(m.n, r, c, graph_stages=(H, m.ns, m.nx)))
 
 
 def test_create_rejects_bad_structures():

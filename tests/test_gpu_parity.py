@@ -123,7 +123,7 @@ def test_factor_and_solve_match_dense_cholesky(Ntr, H):
     assert np.linalg.norm(Ld - Lref) / np.linalg.norm(Lref) <= 1e-12
     # entries the exact factor does not have are stored as exact zeros
     r, c = S.kkt_lower_pattern(m)
-    a = S.analyze(m.n, r, c, stages=(m.H, m.ns))
+    a = S.analyze(m.n, r, c, graph_stages=(m.H, m.ns, m.nx))
     mask = np.zeros((m.n, m.n), dtype=bool)
     for j, sset in enumerate(a["struct"]):
         mask[list(sset), j] = True

@@ -32,10 +32,10 @@ def _opts(**kw):
     return IPMOptions(tol=PARITY_TOL, **kw)
 
 
-def _pair(G, H, seed=0):
+def _pair(G, H, seed=0, ordering=N.capi.NMPC_ORDER_NESTED_DISSECTION):
     w = plate_workload("large", seed, G=G, H=H)
     m = PlateOCP.from_workload(w)
-    p = N.Problem(N.plate_structure(G, H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi))
+    p = N.Problem(N.plate_structure(G, H, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi, ordering=ordering))
     p.analyze()
     p.set_parameters(w.T0, setpoint=w.target, u_prev=m.u_prev)
     return w, m, p
@@ -67,11 +67,14 @@ def _kkt_at_cold_start(m, mu=0.1, seed=0):
     return ipm, st, step
 
 
+@pytest.mark.parametrize("ordering", [N.capi.NMPC_ORDER_NESTED_DISSECTION, N.capi.NMPC_ORDER_FAMILY_DISSECTION])
 @pytest.mark.parametrize("G,H", [(8, 4), (16, 10)])
-def test_plate_factor_and_solve_match_dense_cholesky(G, H):
-    """16 x 16 x 10 has fronts of every class (up to 416 rows, 256 columns)."""
-    _note(f"plate factor G={G} H={H}")
-    w, m, p = _pair(G, H)
+def test_plate_factor_and_solve_match_dense_cholesky(G, H, ordering):
+    """16 x 16 x 10 has fronts of every class (up to 416 rows and 256
+    columns under the family dissection, 410 rows and 250 columns under the
+    default)."""
+    _note(f"plate factor G={G} H={H} ordering={ordering}")
+    w, m, p = _pair(G, H, ordering=ordering)
     ipm, st, step = _kkt_at_cold_start(m)
     K = (step["K"] + step["eta"] * sp.identity(m.n)).tocsr()
     pat = p.patterns()

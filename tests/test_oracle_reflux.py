@@ -79,7 +79,7 @@ def test_library_patterns_and_symbolic_match_oracle(H):
     assert (p.n, p.m_c, p.m_d, p.nx, p.nu) == (m.n, m.m_c, 0, m.N, 1)
     p.analyze()
     r, c = S.kkt_lower_pattern(m)
-    a = S.analyze(m.n, r, c, stages=(m.H, m.ns))
+    a = S.analyze(m.n, r, c, graph_stages=(m.H, m.ns, m.N))
     lib = p.export_symbolic()
     for key, ref in (("perm", a["perm"]), ("parent", a["parent"]), ("colcount", a["colcount"]),
                      ("snode_ptr", a["snode_ptr"])):
