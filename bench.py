@@ -786,6 +786,8 @@ def main(argv=None):
     ap.add_argument("--plate-case", choices=("plain", "adjoint", "both"), default="both",
                     help="with --plate-only: the 32x32x50 plate, the differentiated plate, or both")
     ap.add_argument("--adjoint-grid", type=int, default=64, help="grid of the differentiated form (64 in the full run)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline re-solve loop (its JSON line without the other legs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 10 times (counter calibration)")
     a = ap.parse_args(argv)
@@ -921,6 +923,9 @@ def main(argv=None):
                      "kernel": "numeric supernodal factorization (all levels of one factorization)",
                      "bytes_per_unit": bytes_per_factor},
     }
+    if a.headline_only:
+        print(json.dumps(out), flush=True)
+        return 0
     out["trisolve"] = trisolve_rate(p, sym["nnz_l"])
     out["measured_copy"] = copy_bandwidth()
     if not a.no_small:
