@@ -138,3 +138,40 @@ def test_pattern_plate_workload_size_matches_hand_written_family():
         d = rel_dev(res[0][1][key], res[1][1][key])
         note(f"tightened {key}: {d:.2e}")
         assert d <= 1e-6, (key, d)
+
+
+def test_pattern_batch_equals_one_by_one():
+    """One batch holding two instances of the pattern plate (different
+    targets and fields: each has its own scratch) and the hand-written plate:
+    every instance's iterations and solution are those of its own solve, bit
+    for bit, over a cold solve and a warm re-solve."""
+    note("batch: pattern plate x 2 + hand-written plate, G=8 H=5")
+
+    def make():
+        out = []
+        for seed in (0, 1):
+            w = plate_workload("large", seed, G=8, H=5)
+            out.append((w, _pattern_problem(w, PlateOCP.from_workload(w))))
+        w = plate_workload("large", 2, G=8, H=5)
+        p = N.Problem(N.plate_structure(8, 5, w.dt, t_hi=w.T_hi, c_lo=w.u_lo, c_hi=w.u_hi))
+        p.analyze()
+        p.set_parameters(w.T0, setpoint=w.target, u_prev=PlateOCP.from_workload(w).u_prev)
+        out.append((w, p))
+        return out
+
+    batched, single = make(), make()
+    b = N.Batch([p for _, p in batched])
+    for k in range(2):
+        rc, res = b.solve(warm=k > 0)
+        assert rc == 0, [r.status for r in res]
+        for i, ((w, pb), (_, ps)) in enumerate(zip(batched, single)):
+            r1 = ps.solve(warm=k > 0)
+            assert r1.status == 0 and res[i].iters == r1.iters, (k, i, res[i].iters, r1.iters)
+            sb, ss = pb.solution(), ps.solution()
+            for key in ("y", "lam", "zL", "zU"):
+                assert np.array_equal(sb[key], ss[key]), (k, i, key)
+        for (w, pb), (_, ps) in zip(batched, single):
+            u1, x1 = ps.first_stage()
+            for p in (pb, ps):
+                p.set_parameters(x1, setpoint=w.target, u_prev=u1)
+    b.close()
