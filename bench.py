@@ -454,17 +454,20 @@ def run_device_loop(N, steps=50, warmup=2, passes=(1, 2, 3)):
 PAPER_PLATE_CASE_TOTAL_S = 3.28   # Table 3: InfiniteExaModels + MadNLP + cuDSS, WS + PU, PDE plate
 
 
-def run_plate_case_study(N, eager=False):
+def run_plate_case_study(N, eager=False, model="stage"):
     """The heated-plate case study of Section 4.2 (Table 2) written with the
     stage-pattern front end: 21 x 21 grid, horizon 12 stages of 0.08 s, 38
     NMPC steps from t = 0 to 3 s with the setpoint schedule 58 / 55 / 63, plant
     = model, symbolic analysis once and warm starts.  Timed end to end like
-    the distillation case study."""
+    the distillation case study.  model: "stage" (one generated case per grid
+    point) or "pattern" (index-data patterns); the pattern form's run is
+    reported under "pattern_model"."""
     from paper_2606_04725_amd import simd, simd_models as SM
     from workloads import plate_case_workload
     w = plate_case_workload()
-    g = simd.compile(SM.plate_case_model(n=w.n, alpha=w.alpha, Tb=w.Tb, loss=w.loss, rho=w.rho, Q_lo=w.Q_lo,
-                                         q_scale=w.q_scale, dt=w.dt))
+    make = SM.plate_case_model if model == "stage" else SM.plate_case_pattern_model
+    g = simd.compile(make(n=w.n, alpha=w.alpha, Tb=w.Tb, loss=w.loss, rho=w.rho, Q_lo=w.Q_lo, q_scale=w.q_scale,
+                          dt=w.dt))
     opts = N.default_options(graph=0 if eager else 1)
     t0 = time.perf_counter()
     p = N.Problem(N.stage_model_structure(g, w.H, w.dt))
@@ -491,8 +494,11 @@ def run_plate_case_study(N, eager=False):
             region = np.outer(inside, inside).reshape(-1)
         means.append(float(np.mean(x1[region])))
     total = time.perf_counter() - t0
-    _progress(f"plate case study: {w.n_steps} NMPC steps in {total:.2f} s")
-    return {"workload": f"heated-plate case study of Section 4.2 (Table 2): {w.n} x {w.n} grid, horizon {w.H} x "
+    _progress(f"plate case study ({model} model): {w.n_steps} NMPC steps in {total:.2f} s")
+    if model != "stage":
+        return {"total_s": total, "p50_step_ms": _percentile(lat[1:], 50), "iters_total": iters,
+                "nonzero_status": bad, "Q_first_last": [qs[0], qs[-1]]}
+    out = {"workload": f"heated-plate case study of Section 4.2 (Table 2): {w.n} x {w.n} grid, horizon {w.H} x "
                         f"{w.dt} s, {w.n_steps} NMPC steps, setpoint 58 / 55 / 63, plant = model, loss term read "
                         f"as {w.loss}", "n": p.n, "total_s": total, "analyze_ms": t_an * 1e3,
             "first_solve_ms": lat[0], "p50_step_ms": _percentile(lat[1:], 50),
@@ -500,6 +506,8 @@ def run_plate_case_study(N, eager=False):
             "Q_first_last": [qs[0], qs[-1]], "region_mean_at_steps_6_18_37": [means[6], means[18], means[-1]],
             "paper_total_s": PAPER_PLATE_CASE_TOTAL_S,
             "paper_hardware": "NVIDIA RTX 6000 Ada, MadNLP + cuDSS, WS+PU (context only)"}
+    out["pattern_model"] = run_plate_case_study(N, eager=eager, model="pattern")
+    return out
 
 
 def run_mismatch(N, steps=30, seed=0, factor=1.08, eager=False):

@@ -230,3 +230,75 @@ def plate_pattern_model(G, sigma=0.1, t_hi=1.5, c_lo=0.0, c_hi=1.0) -> PatternMo
     m.objective_pattern(lambda v, d, s: (v[0] - s[0]) ** 2,
                         [dict(vars=[T[p]], sps=[p]) for p in range(G * G)], nv=1, nsp=1)
     return m
+
+
+def plate_case_pattern_model(n=21, alpha=230.0, Tb=50.0, loss=50.0, rho=1e-8, Q_lo=50.0, q_scale=1e4,
+                             dt=0.08) -> PatternModel:
+    """The heated-plate case study (the same problem as plate_case_model)
+    written with index-data patterns: one row pattern per kind of grid point
+    (interior; an edge point next to a heated edge, the heater's edge function
+    chosen by instance data; next to an unheated edge; the four corner kinds)
+    and two objective patterns (the tracking term of a weighted point, the
+    input cost).  Stage layout [T at the interior points (x1 fastest), q]."""
+    g = n - 2
+    h = 2.0 / (n - 1)
+    inv_h2 = 1.0 / (h * h)
+    rs = 1.0 / (1.0 + 4.0 * dt * alpha * inv_h2)
+    m = PatternModel(f"plate_case_pattern_n{n}")
+    T = m.states(g * g)
+    (q,) = m.controls(1, lb=Q_lo / q_scale)
+
+    def left(v):
+        return 4.1 * (q_scale * v) ** (1.0 / 3.0)
+
+    def bottom(v):
+        return (q_scale * v) ** 0.5
+
+    def row(t, prev, nbr_sum):
+        lap = (nbr_sum - 4.0 * t) * inv_h2
+        return rs * (t - prev) - (rs * dt * alpha) * (lap - loss)
+
+    kinds = {}   # kind -> list of instances
+    for j in range(g):
+        for i in range(g):
+            p = j * g + i
+            nb, heat, cold = [], [], 0
+            if i > 0:
+                nb.append(T[p - 1])
+            else:
+                heat.append(0)            # west: the left heater
+            if i < g - 1:
+                nb.append(T[p + 1])
+            else:
+                cold += 1                 # east: Tb
+            if j > 0:
+                nb.append(T[p - g])
+            else:
+                heat.append(1)            # south: the bottom heater
+            if j < g - 1:
+                nb.append(T[p + g])
+            else:
+                cold += 1                 # north: Tb
+            inst = dict(target=T[p], vars=[T[p]] + nb + ([q] if heat else []), prevs=[T[p]],
+                        data=[1.0 if 0 in heat else 0.0, 1.0 if 1 in heat else 0.0])
+            kinds.setdefault((len(nb), len(heat), cold), []).append(inst)
+    for (nn, nh, nc), insts in sorted(kinds.items()):
+        def tmpl(v, p, d, nn=nn, nh=nh, nc=nc):
+            s = sum(v[1:1 + nn], 0.0) + nc * Tb
+            if nh:
+                s = s + d[0] * left(v[1 + nn]) + d[1] * bottom(v[1 + nn])
+            return row(v[0], p[0], s)
+        m.row_pattern(tmpl, insts, nv=1 + nn + (1 if nh else 0), nprev=1, ndata=2)
+    coord = [-1.0 + h * (i + 1) for i in range(g)]
+
+    def weight(x):
+        if abs(x) > 0.5 + 1e-12:
+            return 0.0
+        return 0.5 if abs(abs(x) - 0.5) < 1e-12 else 1.0
+
+    track = [dict(vars=[T[j * g + i]], data=[h * h * weight(coord[i]) * weight(coord[j])])
+             for j in range(g) for i in range(g) if weight(coord[i]) * weight(coord[j])]
+    tr = m.traj()
+    m.objective_pattern(lambda v, d, s: dt * d[0] * (v[0] - tr) ** 2, track, nv=1, ndata=1)
+    m.objective_pattern(lambda v, d, s: (dt * rho * q_scale * q_scale) * v[0] * v[0], [dict(vars=[q])], nv=1)
+    return m

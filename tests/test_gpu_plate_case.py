@@ -5,7 +5,9 @@ the 21 x 21 grid, the first NMPC solve (certified, then compared entry by
 entry after each side tightens its point on the final barrier problem), the
 sensitivities (the measured field enters the first stage's rows with the row
 scale as coefficient, so they go through the state rows' matrix), and the
-closed loop's first steps with each side fed the same measurement."""
+closed loop's first steps with each side fed the same measurement.  The
+model values, the first solve and the sensitivities are also checked for the
+same plate written as index-data patterns (simd_models.plate_case_pattern_model)."""
 import numpy as np
 import pytest
 
@@ -22,23 +24,25 @@ from workloads import plate_case_workload
 pytestmark = pytest.mark.gpu
 
 
-def _pair(k=0):
+def _pair(k=0, model="stage"):
     w = plate_case_workload()
     m = PlateCaseOCP(H=w.H, dt=w.dt, n=w.n, alpha=w.alpha, Tb=w.Tb, loss=w.loss, rho=w.rho, Q_lo=w.Q_lo,
                      q_scale=w.q_scale)
     x0, up = np.full(m.nx, w.T0), np.array([w.Q_prev0 / w.q_scale])
     m.set_parameters(x0=x0, traj=w.traj(k), u_prev=up)
-    g = simd.compile(SM.plate_case_model(n=w.n, alpha=w.alpha, Tb=w.Tb, loss=w.loss, rho=w.rho, Q_lo=w.Q_lo,
-                                         q_scale=w.q_scale, dt=w.dt))
+    make = SM.plate_case_model if model == "stage" else SM.plate_case_pattern_model
+    g = simd.compile(make(n=w.n, alpha=w.alpha, Tb=w.Tb, loss=w.loss, rho=w.rho, Q_lo=w.Q_lo,
+                          q_scale=w.q_scale, dt=w.dt))
     p = N.Problem(N.stage_model_structure(g, w.H, w.dt))
     p.analyze()
     p.set_parameters(x0, traj=w.traj(k), u_prev=up)
     return w, m, p
 
 
-def test_plate_case_eval_matches_oracle():
-    note("plate case study eval, 21 x 21, H 12")
-    w, m, p = _pair()
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_plate_case_eval_matches_oracle(model):
+    note(f"plate case study eval, 21 x 21, H 12, {model} model")
+    w, m, p = _pair(model=model)
     rng = np.random.default_rng(4)
     y = m.initial_guess() + rng.normal(size=m.n)
     y[m.nx::m.ns] = rng.uniform(0.3, 1.5, m.H)
@@ -62,9 +66,10 @@ def _compare(ipm, sol, st, tol=1e-6):
         assert d <= tol, (key, d)
 
 
-def test_plate_case_first_solve_matches_oracle():
-    note("plate case study first solve")
-    w, m, p = _pair()
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_plate_case_first_solve_matches_oracle(model):
+    note(f"plate case study first solve, {model} model")
+    w, m, p = _pair(model=model)
     ipm = LiftedIPM(m, IPMOptions(tol=PARITY_TOL))
     ref = ipm.solve(ipm.cold_start(m.initial_guess(), ipm.o.mu0_cold), ipm.o.mu0_cold)
     assert ref.status == 0
@@ -81,13 +86,14 @@ def test_plate_case_first_solve_matches_oracle():
     _compare(ipm, p.solution(), ref_t.state)
 
 
-def test_plate_case_sensitivities_match_oracle():
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_plate_case_sensitivities_match_oracle(model):
     """At a constant setpoint over the horizon.  (A setpoint step inside the
     horizon drives the lifted weights of the rows around it to 1e16-1e17 at
     mu_min: the condensed matrix at the solution is then numerically
     indefinite and the sensitivity solve reports NMPC_REG_FAIL.)"""
-    note("plate case study sensitivities (x0 through the row scale, trajectory)")
-    w, m, p = _pair()
+    note(f"plate case study sensitivities (x0 through the row scale, trajectory), {model} model")
+    w, m, p = _pair(model=model)
     m.set_parameters(traj=np.full(w.H, 58.0))
     p.set_parameters(m.x0, traj=np.full(w.H, 58.0), u_prev=m.u_prev)
     ipm = LiftedIPM(m)

@@ -205,3 +205,32 @@ def test_stage_model_symbolic_bit_exact_vs_oracle(kind):
         assert np.array_equal(lib["snode_rows"][rp[s_]:rp[s_ + 1]], rows)
     assert lib["nnz_l"] == a["nnz_L"] and lib["flops"] == a["flops"]
     p.close()
+
+
+@pytest.mark.parametrize("n,seed", [(9, 3), (21, 4)])
+def test_case_study_plate_as_patterns_matches_the_oracle(n, seed):
+    """The heated-plate case study (Section 4.2) written as six row patterns
+    and two objective patterns: values and derivatives against the oracle's
+    transcription (oracle/plate_case.py)."""
+    from oracle.plate_case import PlateCaseOCP
+    m = PlateCaseOCP(H=3, n=n)
+    rng = np.random.default_rng(seed)
+    m.set_parameters(x0=rng.uniform(40.0, 70.0, m.nx), traj=rng.uniform(54.0, 64.0, m.H))
+    g = SPn.generate(SM.plate_case_pattern_model(n=n))
+    assert (g.nx, g.nu) == (m.nx, 1)
+    y = rng.uniform(40.0, 70.0, m.n)
+    y[m.nx::m.ns] = rng.uniform(0.2, 2.0, m.H)
+    lam = rng.normal(size=m.m_c)
+    out = expand_patterns(g, y, m.H, m.x0, m.dt, (), m.traj, lam=lam)
+    assert abs(out["f"] - m.f(y)) <= 1e-13 * abs(m.f(y))
+    assert np.max(np.abs(out["grad"] - m.grad(y))) <= 1e-13 * np.max(np.abs(m.grad(y)))
+    assert np.max(np.abs(out["c"] - m.cons_c(y))) <= 1e-12 * max(1.0, np.max(np.abs(m.cons_c(y))))
+    J = m.jac_c(y).tocsr()
+    want = np.asarray(J[out["jr"], out["jc"]]).ravel()
+    assert set(zip(out["jr"].tolist(), out["jc"].tolist())) == set(zip(*J.nonzero()))
+    assert np.max(np.abs(out["jv"] - want)) <= 1e-13 * np.max(np.abs(want))
+    W = m.hess(y, lam, np.zeros(0)).tocsr()
+    want = np.asarray(W[out["wr"], out["wc"]]).ravel()
+    assert np.max(np.abs(out["wv"] - want)) <= 1e-12 * np.max(np.abs(want))
+    lo = np.tile(g.lb, m.H)
+    assert np.array_equal(np.isfinite(lo), np.isfinite(m.lb)) and np.allclose(lo[np.isfinite(lo)], m.lb[np.isfinite(m.lb)])
