@@ -339,7 +339,7 @@ def run_front_end(N, steps=30, warmup=2, eager=False, plate_hand=None):
     plate written with index-data patterns beside the hand-written
     HEATED_PLATE family (plate_hand: that family's run_plate result when the
     caller has one); and the paper's case study (150 NMPC steps) through the
-    generated case-study model beside the hand-written one."""
+    generated case-study model and its index-data pattern form."""
     from paper_2606_04725_amd import simd, simd_models as SM
     from workloads import distillation_workload, reflux_workload
     w = distillation_workload("medium", 0, n_resolves=warmup + steps + 1)
@@ -362,23 +362,24 @@ def run_front_end(N, steps=30, warmup=2, eager=False, plate_hand=None):
     _progress(f"front end plate: generated p50 {out['plate']['generated']['p50_resolve_ms']:.2f} ms, "
               f"hand-written p50 {out['plate']['hand_written']['p50_resolve_ms']:.2f} ms")
     rw = reflux_workload()
-    gr = simd.compile(SM.reflux_model(N=rw.N, Nf=rw.Nf, D=rw.D, F=rw.F, alpha=rw.alpha, xf=rw.xf, Ac=rw.Ac,
-                                      At=rw.At, Ar=rw.Ar, w_u=rw.w_u))
     opts = N.default_options(graph=0 if eager else 1)
-    t0 = time.perf_counter()
-    p = N.Problem(N.stage_model_structure(gr, rw.H, rw.dt))
-    p.analyze()
-    x0, up = rw.x0.copy(), np.array([rw.u_prev0])
-    iters, bad = 0, 0
-    for k in range(rw.n_steps):
-        p.set_parameters(x0, setpoint=[rw.xbar, rw.ubar], u_prev=up)
-        r = p.solve(warm=k > 0, options=opts)
-        up, x0 = p.first_stage()
-        iters += r.iters
-        bad += r.status != 0
-    out["case_study_generated"] = {"total_s": time.perf_counter() - t0, "iters_total": iters, "nonzero_status": bad,
-                                   "final_x1": float(x0[0]), "final_u": float(up[0])}
-    p.close()
+    for key, make in (("case_study_generated", SM.reflux_model), ("case_study_pattern", SM.reflux_pattern_model)):
+        gr = simd.compile(make(N=rw.N, Nf=rw.Nf, D=rw.D, F=rw.F, alpha=rw.alpha, xf=rw.xf, Ac=rw.Ac, At=rw.At,
+                               Ar=rw.Ar, w_u=rw.w_u))
+        t0 = time.perf_counter()
+        p = N.Problem(N.stage_model_structure(gr, rw.H, rw.dt))
+        p.analyze()
+        x0, up = rw.x0.copy(), np.array([rw.u_prev0])
+        iters, bad = 0, 0
+        for k in range(rw.n_steps):
+            p.set_parameters(x0, setpoint=[rw.xbar, rw.ubar], u_prev=up)
+            r = p.solve(warm=k > 0, options=opts)
+            up, x0 = p.first_stage()
+            iters += r.iters
+            bad += r.status != 0
+        out[key] = {"total_s": time.perf_counter() - t0, "iters_total": iters, "nonzero_status": bad,
+                    "final_x1": float(x0[0]), "final_u": float(up[0])}
+        p.close()
     return out
 
 

@@ -302,3 +302,73 @@ def plate_case_pattern_model(n=21, alpha=230.0, Tb=50.0, loss=50.0, rho=1e-8, Q_
     m.objective_pattern(lambda v, d, s: dt * d[0] * (v[0] - tr) ** 2, track, nv=1, ndata=1)
     m.objective_pattern(lambda v, d, s: (dt * rho * q_scale * q_scale) * v[0] * v[0], [dict(vars=[q])], nv=1)
     return m
+
+
+def reflux_pattern_model(N=32, Nf=17, D=0.2, F=0.4, alpha=1.6, xf=0.5, Ac=0.5, At=0.25, Ar=1.0, w_u=0.1,
+                         x_lo=0.0, x_hi=1.0, u_lo=1.0, u_hi=5.0, flow_hi=10.0) -> PatternModel:
+    """The distillation case study (the same problem as reflux_model) written
+    with index-data patterns: a tray pattern (the liquid flow slot bound to L
+    above the feed and S below it), the feed tray, condenser and reboiler;
+    the equilibrium as one algebraic pattern over the trays and the three
+    flow balances; tracking of the condenser and the reflux ratio; guesses of
+    the vapour fractions and flows from the measured trays and the last
+    reflux ratio.  Stage layout [x_1..x_N, u, y_1..y_N, L, V, S]."""
+    m = PatternModel(f"reflux_pattern_N{N}_Nf{Nf}", n_setpoint=2)
+    x = [None] + m.states(N, x_lo, x_hi)
+    (u,) = m.controls(1, u_lo, u_hi)
+    y = [None] + m.algebraic(N, x_lo, x_hi)
+    L, V, S = m.algebraic(3, 0.0, flow_hi)
+    dt = m.dt
+
+    def euler(v, p, f):
+        return v[0] - p[0] - dt * f
+
+    # condenser: V (y_2 - x_1) / Ac
+    m.row_pattern(lambda v, p, d: euler(v, p, v[1] * (v[2] - v[0]) / Ac),
+                  [dict(target=x[1], vars=[x[1], V, y[2]], prevs=[x[1]])], nv=3, nprev=1)
+    # trays other than the feed: Fl (x_{i-1} - x_i) - V (y_i - y_{i+1}), Fl = L above the feed, S below
+    trays = [dict(target=x[i], vars=[x[i], L if i < Nf else S, x[i - 1], V, y[i], y[i + 1]], prevs=[x[i]])
+             for i in range(2, N) if i != Nf]
+    m.row_pattern(lambda v, p, d: euler(v, p, (v[1] * (v[2] - v[0]) - v[3] * (v[4] - v[5])) / At),
+                  trays, nv=6, nprev=1)
+    # feed tray: L x_{i-1} - S x_i - V (y_i - y_{i+1}) + F xf
+    m.row_pattern(lambda v, p, d: euler(v, p, (v[1] * v[3] - v[2] * v[0] - v[4] * (v[5] - v[6]) + F * xf) / At),
+                  [dict(target=x[Nf], vars=[x[Nf], L, S, x[Nf - 1], V, y[Nf], y[Nf + 1]], prevs=[x[Nf]])],
+                  nv=7, nprev=1)
+    # reboiler: S x_{N-1} - (F - D) x_N - V y_N
+    m.row_pattern(lambda v, p, d: euler(v, p, (v[1] * v[2] - (F - D) * v[0] - v[3] * v[4]) / Ar),
+                  [dict(target=x[N], vars=[x[N], S, x[N - 1], V, y[N]], prevs=[x[N]])], nv=5, nprev=1)
+    m.algebraic_row_pattern(lambda v, d: v[0] - alpha * v[1] / (1.0 + (alpha - 1.0) * v[1]),
+                            [dict(vars=[y[i], x[i]]) for i in range(1, N + 1)], nv=2)
+    m.algebraic_row_pattern(lambda v, d: v[0] - v[1] * D, [dict(vars=[L, u])], nv=2)
+    m.algebraic_row_pattern(lambda v, d: v[0] - v[1] - D, [dict(vars=[V, L])], nv=2)
+    m.algebraic_row_pattern(lambda v, d: v[0] - v[1] - F, [dict(vars=[S, L])], nv=2)
+    m.objective_pattern(lambda v, d, s: dt * ((v[0] - s[0]) ** 2 + w_u * (v[1] - s[1]) ** 2),
+                        [dict(vars=[x[1], u], sps=[0, 1])], nv=2, nsp=2)
+    m.guess_pattern(lambda xs, us, d: alpha * xs[0] / (1.0 + (alpha - 1.0) * xs[0]),
+                    [dict(target=y[i], x0s=[x[i]]) for i in range(1, N + 1)], nx0=1)
+    m.guess_pattern(lambda xs, us, d: us[0] * D + d[0],
+                    [dict(target=L, ups=[0], data=[0.0]), dict(target=V, ups=[0], data=[D]),
+                     dict(target=S, ups=[0], data=[F])], nup=1, ndata=1)
+    return m
+
+
+def row_kinds_model() -> PatternModel:
+    """A small pattern model with every row kind: two state rows, an
+    algebraic row, two inequality rows, an objective and a guess pattern
+    (stage layout [x0, x1, u0, u1, a]); the tests compare its generated kernels
+    with the host evaluation of the same expressions."""
+    m = PatternModel("row_kinds")
+    X = m.states(2)
+    U = m.controls(2, lb=-1.0, ub=1.0)
+    (A,) = m.algebraic(1)
+    m.row_pattern(lambda v, p, d: v[0] - p[0] - m.dt * v[1] * v[1],
+                  [dict(target=X[j], vars=[X[j], U[j]], prevs=[X[j]]) for j in range(2)], nv=2, nprev=1)
+    m.algebraic_row_pattern(lambda v, d: v[0] - v[1] * v[2], [dict(vars=[A, X[0], X[1]])], nv=3)
+    m.inequality_pattern(lambda v, d: d[0] * v[0] * v[0] + v[1] - d[1],
+                         [dict(vars=[U[0], X[1]], data=[2.0, 1.0]), dict(vars=[U[1], A], data=[0.5, 3.0])],
+                         nv=2, ndata=2)
+    m.objective_pattern(lambda v, d, s: (v[0] - 1.0) ** 2 + v[1] ** 2, [dict(vars=[X[0], A])], nv=2)
+    m.guess_pattern(lambda x, u, d: x[0] * x[1] + d[0], [dict(target=A, x0s=[0, 1], data=[0.25])], nx0=2,
+                    ndata=1)
+    return m

@@ -13,10 +13,13 @@ their Jacobian entries; the Hessian, gradient and objective contributions of
 the instances go to a per-stage scratch array and a second generated kernel
 sums them per Hessian slot, gradient entry and stage in a fixed order.
 
-Scope: state rows and objective terms (no algebraic or inequality rows);
-previous states only in state rows, linearly with constant coefficients;
-objective templates may read setpoint entries, the stage's trajectory value
-and dt; the cold-start guess is the measured state and the last control.
+Pattern kinds follow eq. (3): state rows (the differential patterns, one per
+state), algebraic equality rows, inequality rows d <= 0, and objective terms.
+Previous states enter state rows only, linearly with constant coefficients;
+rows read variables, data and dt; objective templates may also read setpoint
+entries and the stage's trajectory value.  The cold-start guess is the
+measured state and the last control, and for algebraic variables a guess
+pattern over measured states, last controls and data (0 where none is given).
 """
 from __future__ import annotations
 
@@ -36,7 +39,7 @@ def _kinds(e):
 
 @dataclass
 class Pattern:
-    kind: str            # "row" or "obj"
+    kind: str            # "row" (state rows), "alg" (algebraic rows), "ineq" or "obj"
     expr: object
     nv: int
     nprev: int
@@ -46,9 +49,18 @@ class Pattern:
 
 
 @dataclass
+class GuessPattern:
+    expr: object
+    nx0: int
+    nup: int
+    ndata: int
+    instances: list      # dicts: target (algebraic variable), x0s, ups, data
+
+
+@dataclass
 class PatternModel:
-    """Stage layout [states | controls]; every state's row comes from exactly
-    one instance of a row pattern."""
+    """Stage layout [states | controls | algebraic variables]; every state's
+    row comes from exactly one instance of a state-row pattern."""
     name: str
     n_setpoint: int = 0
     uses_traj: bool = False
@@ -56,11 +68,13 @@ class PatternModel:
     ub: list = field(default_factory=list)
     nx: int = 0
     nu: int = 0
+    na: int = 0
     patterns: list = field(default_factory=list)
+    guesses: list = field(default_factory=list)
 
     def states(self, count, lb=-math.inf, ub=math.inf):
-        if self.nu:
-            raise ValueError("declare the states before the controls")
+        if self.nu or self.na:
+            raise ValueError("declare the states before the controls and algebraic variables")
         first = self.nx
         self.nx += count
         self.lb += [float(lb)] * count
@@ -68,15 +82,24 @@ class PatternModel:
         return list(range(first, first + count))
 
     def controls(self, count, lb=-math.inf, ub=math.inf):
+        if self.na:
+            raise ValueError("declare the controls before the algebraic variables")
         first = self.nx + self.nu
         self.nu += count
         self.lb += [float(lb)] * count
         self.ub += [float(ub)] * count
         return list(range(first, first + count))
 
+    def algebraic(self, count, lb=-math.inf, ub=math.inf):
+        first = self.ns
+        self.na += count
+        self.lb += [float(lb)] * count
+        self.ub += [float(ub)] * count
+        return list(range(first, first + count))
+
     @property
     def ns(self):
-        return self.nx + self.nu
+        return self.nx + self.nu + self.na
 
     @property
     def dt(self):
@@ -95,6 +118,30 @@ class PatternModel:
         p = [sym("sprev", j) for j in range(nprev)]
         d = [sym("sd", j) for j in range(ndata)]
         self.patterns.append(Pattern("row", lift(template(v, p, d)), nv, nprev, ndata, 0, list(instances)))
+
+    def algebraic_row_pattern(self, template, instances, nv, ndata=0):
+        """template(v, d) -> residual of an equality row within the stage (no
+        previous states); one row per instance, numbered in declaration order.
+        instances: dicts with vars and data."""
+        v = [sym("sv", j) for j in range(nv)]
+        d = [sym("sd", j) for j in range(ndata)]
+        self.patterns.append(Pattern("alg", lift(template(v, d)), nv, 0, ndata, 0, list(instances)))
+
+    def inequality_pattern(self, template, instances, nv, ndata=0):
+        """template(v, d) -> d_row, the row d_row <= 0; one per instance."""
+        v = [sym("sv", j) for j in range(nv)]
+        d = [sym("sd", j) for j in range(ndata)]
+        self.patterns.append(Pattern("ineq", lift(template(v, d)), nv, 0, ndata, 0, list(instances)))
+
+    def guess_pattern(self, template, instances, nx0=0, nup=0, ndata=0):
+        """template(x, u, d) -> cold-start value of an algebraic variable from
+        measured-state slots x, last-control slots u and data d.  instances:
+        dicts with target (algebraic variable), x0s (state indices), ups
+        (control numbers, 0-based), data."""
+        x = [sym("sx0", j) for j in range(nx0)]
+        u = [sym("sup", j) for j in range(nup)]
+        d = [sym("sd", j) for j in range(ndata)]
+        self.guesses.append(GuessPattern(lift(template(x, u, d)), nx0, nup, ndata, list(instances)))
 
     def generate(self):
         return generate(self)
@@ -118,8 +165,12 @@ class PatternDerived:
     d2: list             # their expressions (times the row multiplier for rows)
 
 
+_ALLOWED = {"row": {"sv", "sprev", "sd", "dt"}, "alg": {"sv", "sd", "dt"}, "ineq": {"sv", "sd", "dt"},
+            "obj": {"sv", "sd", "ssp", "tr", "dt"}}
+
+
 def _derive_pattern(pat: Pattern):
-    allowed = {"sv", "sprev", "sd", "dt"} if pat.kind == "row" else {"sv", "sd", "ssp", "tr", "dt"}
+    allowed = _ALLOWED[pat.kind]
     bad = _kinds(pat.expr) - allowed
     if bad:
         raise ValueError(f"a {pat.kind} pattern uses {sorted(bad)}")
@@ -169,10 +220,28 @@ def _structure(m: PatternModel, ders):
             row_of[(pi, ii)] = t
     if any(r is None for r in rows):
         raise ValueError(f"states without a row: {[t for t, r in enumerate(rows) if r is None][:8]} ...")
+    # algebraic and inequality rows, numbered in declaration order
+    arow, drow = {}, {}
+    for pi, dd in enumerate(ders):
+        if dd.pat.kind not in ("alg", "ineq"):
+            continue
+        for ii, inst in enumerate(dd.pat.instances):
+            vs = [int(v) for v in inst["vars"]]
+            if len(vs) != dd.pat.nv or len(set(vs)) != len(vs) or not all(0 <= v < ns for v in vs):
+                raise ValueError(f"{dd.pat.kind} row: variable slots must be distinct stage variables")
+            if len(inst.get("data", [])) != dd.pat.ndata:
+                raise ValueError(f"{dd.pat.kind} row: wrong number of data values")
+            if dd.pat.kind == "alg":
+                arow[(pi, ii)] = nx + len(arow)
+            else:
+                drow[(pi, ii)] = len(drow)
+    rows = rows + [None] * len(arow)
+    for key, r in arow.items():
+        rows[r] = key
     # per-row columns (own sorted; previous sorted) and slot positions
     row_ptr, row_cols, prev_ptr, prev_cols, prev_coef = [0], [], [0], [], []
     jpos, ppos = {}, {}
-    for t in range(nx):
+    for t in range(len(rows)):
         pi, ii = rows[t]
         dd = ders[pi]
         inst = dd.pat.instances[ii]
@@ -186,6 +255,12 @@ def _structure(m: PatternModel, ders):
         prev_ptr.append(len(prev_cols))
         jpos[(pi, ii)] = [own.index(int(v)) for v in inst["vars"]]
         ppos[(pi, ii)] = [order.index(j) for j in range(len(pv))]
+    ineq_ptr, ineq_cols = [0], []
+    for (pi, ii), d in sorted(drow.items(), key=lambda kv: kv[1]):
+        own = sorted(int(v) for v in ders[pi].pat.instances[ii]["vars"])
+        ineq_cols += own
+        ineq_ptr.append(len(ineq_cols))
+        jpos[(pi, ii)] = [own.index(int(v)) for v in ders[pi].pat.instances[ii]["vars"]]
     # Hessian slots: lower pairs of stage variables over all instances
     wkeys = {}
     for pi, dd in enumerate(ders):
@@ -222,7 +297,8 @@ def _structure(m: PatternModel, ders):
         ncoo += per * n
     return dict(rows=rows, row_ptr=row_ptr, row_cols=row_cols, prev_ptr=prev_ptr, prev_cols=prev_cols,
                 prev_coef=prev_coef, jpos=jpos, ppos=ppos, wlist=wlist, coo_base=coo_base, ncoo=ncoo,
-                w_lists=w_lists, g_lists=g_lists, f_lists=f_lists)
+                w_lists=w_lists, g_lists=g_lists, f_lists=f_lists, arow=arow, drow=drow, n_alg=len(arow),
+                nd=len(drow), ineq_ptr=ineq_ptr, ineq_cols=ineq_cols)
 
 
 # ---- C emission ---------------------------------------------------------------------------
@@ -257,8 +333,8 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     w("#include \"kernels.h\"")
     w("using namespace nmpc;")
     w("namespace {")
-    w(f"constexpr int NS = {ns}, NX = {nx}, NU = {nu}, RPS = {nx}, NW = {nw}, NCOO = {max(st['ncoo'], 1)}, "
-      f"NLANES = {nlanes}, NSP = {m.n_setpoint};")
+    w(f"constexpr int NS = {ns}, NX = {nx}, NU = {nu}, RPS = {nx + st['n_alg']}, ND = {st['nd']}, NW = {nw}, "
+      f"NCOO = {max(st['ncoo'], 1)}, NLANES = {nlanes}, NSP = {m.n_setpoint};")
     w("// (a model with no Hessian, gradient or objective contributions still has one scratch double")
     w("// per stage, so the summing kernel runs and writes the zeros)")
     w(f"constexpr unsigned long long TAG = {tag}ULL;")
@@ -278,9 +354,26 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
                 for ii, inst in enumerate(insts):
                     inv[int(inst["sps"][slot])].append(ii)
                 w(_csr(f"P{pi}_S{slot}", inv))
-        if dd.pat.kind == "row":
-            w(_ints(f"P{pi}_T", [inst["target"] for inst in insts]))
+        if dd.pat.kind != "obj":   # the row of each instance (stage-local) and its Jacobian slots
+            rowno = {"row": lambda ii: insts[ii]["target"], "alg": lambda ii: st["arow"][(pi, ii)],
+                     "ineq": lambda ii: st["drow"][(pi, ii)]}[dd.pat.kind]
+            w(_ints(f"P{pi}_T", [rowno(ii) for ii in range(len(insts))]))
             w(_ints(f"P{pi}_JP", [p for ii in range(len(insts)) for p in st["jpos"][(pi, ii)]]))
+    for gi, gp in enumerate(m.guesses):
+        insts = gp.instances
+        if gp.nx0:
+            w(_ints(f"G{gi}_X", [q for inst in insts for q in inst["x0s"]]))
+        if gp.nup:
+            w(_ints(f"G{gi}_U", [q for inst in insts for q in inst["ups"]]))
+        if gp.ndata:
+            w(_dbls(f"G{gi}_D", [x for inst in insts for x in inst["data"]]))
+    # guess of each algebraic variable: (guess pattern, instance), or -1
+    gsel = [(-1, 0)] * m.na
+    for gi, gp in enumerate(m.guesses):
+        for ii, inst in enumerate(gp.instances):
+            gsel[int(inst["target"]) - nx - nu] = (gi, ii)
+    w(_ints("GA_P", [a for a, _ in gsel]))
+    w(_ints("GA_I", [b for _, b in gsel]))
     w("// summation lists of a stage's scratch: Hessian slots, gradient entries, objective-term slots")
     w(_csr("RW", st["w_lists"]))
     w(_csr("RG", st["g_lists"]))
@@ -336,7 +429,23 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
             names["sprev"] = (f"(k > 0 ? y[(int64_t)(k - 1) * NS + P{pi}_PV[i * {pat.nprev} + {{j}}]] "
                               f": I.x0[P{pi}_PV[i * {pat.nprev} + {{j}}]])")
         em = _Emitter(None, names, indent=3)
-        if pat.kind == "row":
+        if pat.kind == "ineq":
+            em.line(f"const int r = k * ND + P{pi}_T[i];")
+            em.line(f"I.d[r] = {em.val(pat.expr)};")
+            em.line("if (full) {")
+            em.indent += 1
+            em.push()
+            em.line("double* jr = I.jv + I.jptr[mc + r];")
+            for s_, e in enumerate(dd.dv):
+                em.line(f"jr[P{pi}_JP[i * {pat.nv} + {s_}]] = {em.val(e)};")
+            if dd.pairs:
+                em.line("const double lam = om[2 * mc + r];")
+                for c, e in enumerate(dd.d2):
+                    em.line(f"Sk[{base + c * n} + i] = lam * {em.val(e)};")
+            em.pop()
+            em.indent -= 1
+            em.line("}")
+        elif pat.kind in ("row", "alg"):
             em.line(f"const int r = k * RPS + P{pi}_T[i];")
             em.line(f"I.c[r] = {em.val(pat.expr)};")
             em.line("if (full) {")
@@ -419,7 +528,35 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     w("    const int t = lb * kBlock + threadIdx.x;")
     w("    if (t >= I.n) return;")
     w("    const int j = t % NS;")
-    w("    I.y[t] = j < NX ? I.x0[j] : I.uprev[j - NX];")
+    w("    double v = 0.0;")
+    w("    if (j < NX) {")
+    w("        v = I.x0[j];")
+    w("    } else if (j < NX + NU) {")
+    w("        v = I.uprev[j - NX];")
+    if m.guesses:
+        w("    } else {")
+        w("        const int i = GA_I[j - NX - NU];")
+        w("        switch (GA_P[j - NX - NU]) {")
+        for gi, gp in enumerate(m.guesses):
+            names = {"dt": "I.gm.dt"}
+            if gp.nx0:
+                names["sx0"] = f"I.x0[G{gi}_X[i * {gp.nx0} + {{j}}]]"
+            if gp.nup:
+                names["sup"] = f"I.uprev[G{gi}_U[i * {gp.nup} + {{j}}]]"
+            if gp.ndata:
+                names["sd"] = f"G{gi}_D[i * {gp.ndata} + {{j}}]"
+            em = _Emitter(None, names, indent=4)
+            val = em.val(gp.expr)
+            w(f"            case {gi}: {{")
+            out.extend(em.lines)
+            w(f"                v = {val};")
+            w("                break;")
+            w("            }")
+        w("            default: break;")
+        w("        }")
+    w("    }")
+    w("    (void)v;")
+    w("    I.y[t] = v;")
     w("}")
     w("")
     # parameter contractions (instance 0)
@@ -527,19 +664,36 @@ def generate(m: PatternModel) -> GeneratedModel:
                     raise ValueError("objective instance: wrong number of data values")
     if any("tr" in _kinds(d.pat.expr) for d in ders):
         m.uses_traj = True
+    seen = set()
+    for gp in m.guesses:
+        bad = _kinds(gp.expr) - {"sx0", "sup", "sd", "dt"}
+        if bad:
+            raise ValueError(f"a guess pattern uses {sorted(bad)}")
+        for inst in gp.instances:
+            t = int(inst["target"])
+            if not m.nx + m.nu <= t < m.ns or t in seen:
+                raise ValueError(f"guess of variable {t}: not an algebraic variable, or guessed twice")
+            seen.add(t)
+            if (len(inst.get("x0s", [])) != gp.nx0 or len(inst.get("ups", [])) != gp.nup
+                    or len(inst.get("data", [])) != gp.ndata
+                    or not all(0 <= q < m.nx for q in inst.get("x0s", []))
+                    or not all(0 <= q < m.nu for q in inst.get("ups", []))):
+                raise ValueError(f"guess of variable {t}: wrong slots")
     st = _structure(m, ders)
     body = _source(m, ders, st, 0)
     tag = _tag(hashlib.sha256(body.encode() + _header_text()).hexdigest())
     g = GeneratedModel(
-        name=m.name, nx=m.nx, nu=m.nu, na=0, n_alg_rows=0, n_setpoint=m.n_setpoint, uses_traj=m.uses_traj,
+        name=m.name, nx=m.nx, nu=m.nu, na=m.na, n_alg_rows=st["n_alg"], n_setpoint=m.n_setpoint,
+        uses_traj=m.uses_traj,
         row_ptr=np.array(st["row_ptr"], dtype=np.int32), row_cols=np.array(st["row_cols"], dtype=np.int32),
         prev_ptr=np.array(st["prev_ptr"], dtype=np.int32), prev_cols=np.array(st["prev_cols"], dtype=np.int32),
         prev_coef=np.array(st["prev_coef"], dtype=np.float64),
-        ineq_ptr=np.zeros(1, dtype=np.int32), ineq_cols=np.zeros(0, dtype=np.int32),
+        ineq_ptr=np.array(st["ineq_ptr"], dtype=np.int32), ineq_cols=np.array(st["ineq_cols"], dtype=np.int32),
         w_rows=np.array([a for a, _ in st["wlist"]], dtype=np.int32),
         w_cols=np.array([b for _, b in st["wlist"]], dtype=np.int32),
         wx_rows=np.zeros(0, dtype=np.int32), wx_cols=np.zeros(0, dtype=np.int32),
         lb=np.array(m.lb), ub=np.array(m.ub), source=_source(m, ders, st, tag), tag=tag, derived=None)
     g.scratch_per_stage = max(st["ncoo"], 1)
     g.pattern_structure = (ders, st)
+    g.pattern_model = m
     return g

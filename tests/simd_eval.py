@@ -160,29 +160,40 @@ def contraction(d, y, H, x0, dt, setpoint, traj, lam, al, w, so, lam_d=None, u_p
     return gsp, gtr, gup
 
 
-def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None):
+def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None, lam_d=None, u_prev=None):
     """The same outputs for a pattern model (simd_patterns.generate),
     emulating its kernels: every instance's values go to the per-stage
     scratch at the generated positions, the Jacobian entries to the
-    generated slots, and the sums follow the generated lists."""
+    generated slots, and the sums follow the generated lists.  lam: the
+    equality rows' multipliers (state and algebraic rows, stage-major),
+    lam_d: the inequality rows'.  Also returns the cold-start guess."""
     ders, st = g.pattern_structure
     ns, nx = g.ns, g.nx
+    rps, nd = nx + st["n_alg"], st["nd"]
+    mc = H * rps
     nw = len(g.w_rows)
     ncoo = max(st["ncoo"], 1)
     jptr = [0]
     jr, jc = [], []
     for k in range(H):
-        for r in range(nx):
+        for r in range(rps):
             if k > 0:
                 for q in range(st["prev_ptr"][r], st["prev_ptr"][r + 1]):
-                    jr.append(k * nx + r)
+                    jr.append(k * rps + r)
                     jc.append((k - 1) * ns + st["prev_cols"][q])
             for q in range(st["row_ptr"][r], st["row_ptr"][r + 1]):
-                jr.append(k * nx + r)
+                jr.append(k * rps + r)
                 jc.append(k * ns + st["row_cols"][q])
             jptr.append(len(jr))
+    for k in range(H):
+        for r in range(nd):
+            for q in range(st["ineq_ptr"][r], st["ineq_ptr"][r + 1]):
+                jr.append(mc + k * nd + r)
+                jc.append(k * ns + st["ineq_cols"][q])
+            jptr.append(len(jr))
     jv = np.full(len(jr), np.nan)
-    c = np.zeros(H * nx)
+    c = np.zeros(H * rps)
+    dvals = np.zeros(H * nd)
     wv = np.zeros(H * nw)
     grad = np.zeros(H * ns)
     fterm = np.zeros(H * ns)
@@ -205,16 +216,22 @@ def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None):
                 for j, q in enumerate(inst.get("sps", [])):
                     env[("ssp", j)] = setpoint[q]
                 memo = {}
-                if pat.kind == "row":
-                    r = k * nx + inst["target"]
-                    c[r] = ev(pat.expr, env, memo)
-                    off = len(inst["prevs"]) if k > 0 else 0
+                if pat.kind in ("row", "alg", "ineq"):
+                    if pat.kind == "ineq":
+                        r = k * nd + st["drow"][(pi, i)]
+                        dvals[r] = ev(pat.expr, env, memo)
+                        row0, off = jptr[mc + r], 0
+                        lr = 0.0 if lam_d is None else lam_d[r]
+                    else:
+                        r = k * rps + (inst["target"] if pat.kind == "row" else st["arow"][(pi, i)])
+                        c[r] = ev(pat.expr, env, memo)
+                        row0, off = jptr[r], (len(inst.get("prevs", [])) if k > 0 else 0)
+                        lr = 0.0 if lam is None else lam[r]
+                        if k > 0:
+                            for qi, coef in enumerate(dd.pcoef):
+                                jv[row0 + st["ppos"][(pi, i)][qi]] = coef
                     for s_, e in enumerate(dd.dv):
-                        jv[jptr[r] + off + st["jpos"][(pi, i)][s_]] = ev(e, env, memo)
-                    if k > 0:
-                        for qi, coef in enumerate(dd.pcoef):
-                            jv[jptr[r] + st["ppos"][(pi, i)][qi]] = coef
-                    lr = 0.0 if lam is None else lam[r]
+                        jv[row0 + off + st["jpos"][(pi, i)][s_]] = ev(e, env, memo)
                     for cc, e in enumerate(dd.d2):
                         S[base + cc * n + i] = lr * ev(e, env, memo)
                 else:
@@ -231,5 +248,23 @@ def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None):
             fterm[k * ns + v] = sum(S[q] for q in st["f_lists"][v])
     wr = np.array([k * ns + a for k in range(H) for a in g.w_rows], dtype=int)
     wc = np.array([k * ns + b for k in range(H) for b in g.w_cols], dtype=int)
-    return dict(f=fterm.sum(), grad=grad, c=c, jv=jv, jr=np.array(jr, dtype=int), jc=np.array(jc, dtype=int),
-                wv=wv, wr=wr, wc=wc)
+    guess = None
+    if u_prev is not None:
+        gs = np.zeros(ns)
+        gs[:nx] = x0
+        gs[nx:nx + g.nu] = u_prev
+        m = g.pattern_model
+        for gp in m.guesses:
+            for inst in gp.instances:
+                env = {("dt", 0): dt}
+                for j, q in enumerate(inst.get("x0s", [])):
+                    env[("sx0", j)] = x0[q]
+                for j, q in enumerate(inst.get("ups", [])):
+                    env[("sup", j)] = u_prev[q]
+                for j, x in enumerate(inst.get("data", [])):
+                    env[("sd", j)] = x
+                gs[inst["target"]] = ev(gp.expr, env)
+        guess = np.tile(gs, H)
+    return dict(f=fterm.sum(), grad=grad, c=c, d=dvals, jv=jv, jr=np.array(jr, dtype=int),
+                jc=np.array(jc, dtype=int), wv=wv, wr=wr, wc=wc, guess=guess)
+

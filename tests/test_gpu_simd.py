@@ -52,12 +52,13 @@ def _lq():
     return m, p, (A, B, Q, R, x0, xs)
 
 
-def _reflux(H):
+def _reflux(H, model="stage"):
     w = reflux_workload(H=H)
     m = RefluxColumnOCP(H=H)
     m.set_parameters(x0=w.x0, setpoint=[w.xbar, w.ubar], u_prev=[w.u_prev0])
-    g = simd.compile(SM.reflux_model(N=w.N, Nf=w.Nf, D=w.D, F=w.F, alpha=w.alpha, xf=w.xf, Ac=w.Ac, At=w.At,
-                                     Ar=w.Ar, w_u=w.w_u))
+    make = SM.reflux_model if model == "stage" else SM.reflux_pattern_model
+    g = simd.compile(make(N=w.N, Nf=w.Nf, D=w.D, F=w.F, alpha=w.alpha, xf=w.xf, Ac=w.Ac, At=w.At, Ar=w.Ar,
+                          w_u=w.w_u))
     p = N.Problem(N.stage_model_structure(g, H, w.dt))
     p.analyze()
     p.set_parameters(w.x0, setpoint=[w.xbar, w.ubar], u_prev=[w.u_prev0])
@@ -148,12 +149,15 @@ def test_generated_solve_matches_oracle(name, route):
     _compare(ipm, p.solution(), ref_t.state)
 
 
-def test_generated_case_study_equals_the_hand_written_family():
-    """The case-study column written with the front end and the library's
-    REFLUX_COLUMN family solve the same problem at the full horizon (90
-    stages): same iteration count, points equal to 1e-9 after tightening."""
-    note("generated vs hand-written case-study column, H=90")
-    w, m, pg = _reflux(90)
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_generated_case_study_equals_the_hand_written_family(model):
+    """The case-study column written with the front end (as a stage model,
+    or as index-data patterns with algebraic rows and guess patterns) and the
+    library's REFLUX_COLUMN family solve the same problem at the full horizon
+    (90 stages): same iteration count, points equal to 1e-9 after
+    tightening."""
+    note(f"generated ({model}) vs hand-written case-study column, H=90")
+    w, m, pg = _reflux(90, model)
     ph = N.Problem(N.reflux_structure(90))
     ph.analyze()
     ph.set_parameters(w.x0, setpoint=[w.xbar, w.ubar], u_prev=[w.u_prev0])
@@ -276,9 +280,10 @@ def test_lq_sensitivities_through_the_state_matrix():
     assert np.array_equal(jd.cpu().numpy(), J)
 
 
-def test_reflux_model_sensitivities_match_oracle():
-    note("stage model sensitivities: case-study column (x0, setpoint)")
-    w, m, p = _reflux(10)
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_reflux_model_sensitivities_match_oracle(model):
+    note(f"{model} model sensitivities: case-study column (x0, setpoint)")
+    w, m, p = _reflux(10, model)
     ipm, st = _solved(m, p)
     sens = sensitivities(ipm, st)
     su, so = np.array([0.8]), 0.3

@@ -234,3 +234,74 @@ def test_case_study_plate_as_patterns_matches_the_oracle(n, seed):
     assert np.max(np.abs(out["wv"] - want)) <= 1e-12 * np.max(np.abs(want))
     lo = np.tile(g.lb, m.H)
     assert np.array_equal(np.isfinite(lo), np.isfinite(m.lb)) and np.allclose(lo[np.isfinite(lo)], m.lb[np.isfinite(m.lb)])
+
+
+def test_case_study_column_as_patterns_matches_the_oracle():
+    """The distillation case study (Section 4.1) written with tray, feed,
+    condenser and reboiler row patterns, algebraic equilibrium and flow
+    patterns and guess patterns: values, derivatives and the cold-start guess
+    against the oracle's transcription (oracle/reflux.py)."""
+    from oracle.reflux import RefluxColumnOCP
+    from workloads import reflux_workload
+    w = reflux_workload(H=4)
+    m = RefluxColumnOCP(H=4)
+    rng = np.random.default_rng(7)
+    x0 = rng.uniform(0.1, 0.9, m.N)
+    m.set_parameters(x0=x0, setpoint=[w.xbar, w.ubar], u_prev=[2.3])
+    g = SPn.generate(SM.reflux_pattern_model(N=w.N, Nf=w.Nf, D=w.D, F=w.F, alpha=w.alpha, xf=w.xf, Ac=w.Ac,
+                                              At=w.At, Ar=w.Ar, w_u=w.w_u))
+    assert (g.nx, g.nu, g.na, g.n_alg_rows) == (m.N, 1, m.N + 3, m.N + 3)
+    y = m.initial_guess() + rng.normal(scale=0.05, size=m.n)
+    lam = rng.normal(size=m.m_c)
+    out = expand_patterns(g, y, m.H, x0, m.dt, [w.xbar, w.ubar], lam=lam, u_prev=[2.3])
+    assert np.max(np.abs(out["guess"] - m.initial_guess())) <= 1e-15
+    assert abs(out["f"] - m.f(y)) <= 1e-14 * max(1.0, abs(m.f(y)))
+    assert np.max(np.abs(out["grad"] - m.grad(y))) <= 1e-14
+    assert np.max(np.abs(out["c"] - m.cons_c(y))) <= 1e-13
+    J = m.jac_c(y).tocsr()
+    assert set(zip(out["jr"].tolist(), out["jc"].tolist())) == set(zip(*J.nonzero()))
+    want = np.asarray(J[out["jr"], out["jc"]]).ravel()
+    assert np.max(np.abs(out["jv"] - want)) <= 1e-13 * max(1.0, np.max(np.abs(want)))
+    W = m.hess(y, lam, np.zeros(0)).tocsr()
+    want = np.asarray(W[out["wr"], out["wc"]]).ravel()
+    assert np.max(np.abs(out["wv"] - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def test_inequality_patterns_against_direct_evaluation():
+    """Inequality rows from a pattern (one per instance), with an algebraic
+    variable and a guess pattern: values, Jacobian rows after the equality
+    rows, Hessian weighted by the inequality multipliers."""
+    m = SM.row_kinds_model()
+    g = SPn.generate(m)
+    assert (g.na, g.n_alg_rows, len(g.ineq_ptr) - 1) == (1, 1, 2)
+    H, dt = 3, 0.2
+    rng = np.random.default_rng(9)
+    y, x0 = rng.normal(size=H * 5), rng.normal(size=2)
+    lam, lam_d = rng.normal(size=H * 3), rng.uniform(0.1, 1.0, size=H * 2)
+    out = expand_patterns(g, y, H, x0, dt, lam=lam, lam_d=lam_d, u_prev=[0.3, -0.2])
+    Y = y.reshape(H, 5)
+    dd = np.stack([2.0 * Y[:, 2] ** 2 + Y[:, 1] - 1.0, 0.5 * Y[:, 3] ** 2 + Y[:, 4] - 3.0], axis=1).reshape(-1)
+    assert np.max(np.abs(out["d"] - dd)) <= 1e-14
+    mc = H * 3
+    assert set(out["jr"][out["jr"] >= mc].tolist()) == set(range(mc, mc + H * 2))
+    assert np.allclose(out["guess"][4::5], x0[0] * x0[1] + 0.25)
+    # Hessian of lam^T c + lam_d^T d + f against central differences of its gradient
+    hcs = 1e-30
+    E = np.eye(H * 5)
+
+    def lagr(yy):
+        Yy = yy.reshape(H, 5)
+        P = np.vstack([x0, Yy[:-1, :2]])
+        c = np.stack([Yy[:, 0] - P[:, 0] - dt * Yy[:, 2] ** 2, Yy[:, 1] - P[:, 1] - dt * Yy[:, 3] ** 2,
+                      Yy[:, 4] - Yy[:, 0] * Yy[:, 1]], axis=1).reshape(-1)
+        d = np.stack([2.0 * Yy[:, 2] ** 2 + Yy[:, 1] - 1.0, 0.5 * Yy[:, 3] ** 2 + Yy[:, 4] - 3.0],
+                     axis=1).reshape(-1)
+        f = np.sum((Yy[:, 0] - 1.0) ** 2 + Yy[:, 4] ** 2)
+        return f + lam @ c + lam_d @ d
+
+    def grad(yy):
+        return np.array([lagr(yy + 1j * hcs * E[i]).imag / hcs for i in range(H * 5)])
+
+    h = 1e-6
+    Wfd = np.array([(grad(y + h * E[i]) - grad(y - h * E[i])) / (2 * h) for i in range(H * 5)])
+    assert np.max(np.abs(out["wv"] - Wfd[out["wr"], out["wc"]])) <= 1e-7
