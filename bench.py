@@ -334,8 +334,9 @@ def _plate_summary(r):
 
 def run_front_end(N, steps=30, warmup=2, eager=False, plate_hand=None):
     """The headline workload written with the stage-pattern front end (its
-    kernels generated from the stage expressions) beside the hand-written
-    DISTILLATION family: the same closed re-solve loop on each; the workload
+    kernels generated from the stage expressions, as a stage model and as
+    index-data patterns) beside the hand-written DISTILLATION family: the
+    same closed re-solve loop on each; the workload
     plate written with index-data patterns beside the hand-written
     HEATED_PLATE family (plate_hand: that family's run_plate result when the
     caller has one); and the paper's case study (150 NMPC steps) through the
@@ -343,18 +344,20 @@ def run_front_end(N, steps=30, warmup=2, eager=False, plate_hand=None):
     from paper_2606_04725_amd import simd, simd_models as SM
     from workloads import distillation_workload, reflux_workload
     w = distillation_workload("medium", 0, n_resolves=warmup + steps + 1)
-    g = simd.compile(SM.distillation_model(w.N, w.alpha, F=w.F, rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi,
-                                           u_lo=w.u_lo, u_hi=w.u_hi))
+    args = dict(F=w.F, rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi, u_lo=w.u_lo, u_hi=w.u_hi)
+    g = simd.compile(SM.distillation_model(w.N, w.alpha, **args))
+    gp = simd.compile(SM.distillation_pattern_model(w.N, w.alpha, **args))
     out = {"workload": f"distillation {w.N} trays, horizon {w.H}, dt {w.dt}, seed 0, {steps} warm re-solves "
                        f"(same loop as the headline line, without autotuning)"}
     for name, st in (("generated", N.stage_model_structure(g, w.H, w.dt)),
+                     ("pattern", N.stage_model_structure(gp, w.H, w.dt)),
                      ("hand_written", N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))):
         p = N.Problem(st)
         p.analyze()
         out[name] = _loop_rate(N, p, w, steps, warmup, eager)
         p.close()
-    _progress(f"front end: generated {out['generated']['iters_per_s']:.0f} iters/s, "
-              f"hand-written {out['hand_written']['iters_per_s']:.0f} iters/s")
+    _progress(f"front end: generated {out['generated']['iters_per_s']:.0f} iters/s, pattern "
+              f"{out['pattern']['iters_per_s']:.0f}, hand-written {out['hand_written']['iters_per_s']:.0f} iters/s")
     hand = plate_hand if plate_hand is not None else run_plate(N, eager=eager)
     out["plate"] = {"workload": hand["workload"] + "; generated = one stencil pattern and one tracking pattern",
                     "generated": _plate_summary(run_plate(N, eager=eager, model="pattern")),

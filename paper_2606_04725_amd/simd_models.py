@@ -372,3 +372,43 @@ def row_kinds_model() -> PatternModel:
     m.guess_pattern(lambda x, u, d: x[0] * x[1] + d[0], [dict(target=A, x0s=[0, 1], data=[0.25])], nx0=2,
                     ndata=1)
     return m
+
+
+def distillation_pattern_model(N, alpha, F=1.0, rho=1e-2, x_lo=0.0, x_hi=1.0, u_lo=0.5, u_hi=5.0) -> PatternModel:
+    """The workload column (the same problem as distillation_model and the
+    library's DISTILLATION family) written with index-data patterns: one tray
+    pattern over the trays other than the feed tray (liquid flow R above the
+    feed, R + F below it, chosen by instance data), the feed tray (which reads
+    the stage's feed composition), condenser and reboiler; both flow
+    inequalities as one pattern; the objective with the move penalty in the
+    previous stage's controls.  Stage layout [x_0 .. x_{N+1}, R, V]."""
+    m = PatternModel(f"distillation_pattern_N{N}", n_setpoint=2)
+    x = m.states(N + 2, x_lo, x_hi)
+    R, V = m.controls(2, u_lo, u_hi)
+    fd = N // 2
+    dt, zF = m.dt, m.traj()
+
+    def vle(xi):
+        return alpha * xi / (1.0 + (alpha - 1.0) * xi)
+
+    def euler(v, p, f):
+        return v[0] - p[0] - dt * f
+
+    m.row_pattern(lambda v, p, d: euler(v, p, v[1] * (vle(v[2]) - v[0])),
+                  [dict(target=x[0], vars=[x[0], V, x[1]], prevs=[x[0]])], nv=3, nprev=1)
+    # trays i != fd: (R + d0) (x_{i-1} - x_i) + V (vle(x_{i+1}) - vle(x_i)), d0 = 0 above the feed, F below
+    trays = [dict(target=x[i], vars=[x[i], R, V, x[i - 1], x[i + 1]], prevs=[x[i]], data=[0.0 if i < fd else F])
+             for i in range(1, N + 1) if i != fd]
+    m.row_pattern(lambda v, p, d: euler(v, p, (v[1] + d[0]) * (v[3] - v[0]) + v[2] * (vle(v[4]) - vle(v[0]))),
+                  trays, nv=5, nprev=1, ndata=1)
+    m.row_pattern(lambda v, p, d: euler(v, p, v[1] * v[3] - (v[1] + F) * v[0] + v[2] * (vle(v[4]) - vle(v[0]))
+                                        + F * zF),
+                  [dict(target=x[fd], vars=[x[fd], R, V, x[fd - 1], x[fd + 1]], prevs=[x[fd]])], nv=5, nprev=1)
+    m.row_pattern(lambda v, p, d: euler(v, p, (v[1] + F) * v[3] - v[2] * vle(v[0]) - (v[1] + F - v[2]) * v[0]),
+                  [dict(target=x[N + 1], vars=[x[N + 1], R, V, x[N]], prevs=[x[N + 1]])], nv=4, nprev=1)
+    m.inequality_pattern(lambda v, d: v[0] - v[1] - d[0], [dict(vars=[R, V], data=[0.0]),
+                                                           dict(vars=[V, R], data=[F])], nv=2, ndata=1)
+    m.objective_pattern(lambda v, d, s, pu: (v[0] - s[0]) ** 2 + (v[1] - s[1]) ** 2
+                        + rho * ((v[2] - pu[0]) ** 2 + (v[3] - pu[1]) ** 2),
+                        [dict(vars=[x[0], x[N + 1], R, V], sps=[0, 1], pus=[0, 1])], nv=4, nsp=2, npu=2)
+    return m

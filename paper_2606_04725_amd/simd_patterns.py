@@ -45,7 +45,8 @@ class Pattern:
     nprev: int
     ndata: int
     nsp: int
-    instances: list      # dicts: vars, prevs, data, sps, target
+    instances: list      # dicts: vars, prevs, data, sps, target, pus
+    npu: int = 0         # objective: slots of the previous stage's controls
 
 
 @dataclass
@@ -146,13 +147,17 @@ class PatternModel:
     def generate(self):
         return generate(self)
 
-    def objective_pattern(self, template, instances, nv, ndata=0, nsp=0):
-        """template(v, d, s) -> stage term; s: nsp setpoint slots.
-        instances: dicts with vars, data, sps (setpoint indices)."""
+    def objective_pattern(self, template, instances, nv, ndata=0, nsp=0, npu=0):
+        """template(v, d, s) -> stage term, or template(v, d, s, pu) with npu
+        > 0; s: nsp setpoint slots; pu: slots of the previous stage's controls
+        (the last applied control at the first stage), as move penalties use.
+        instances: dicts with vars, data, sps (setpoint indices), pus (control
+        numbers, 0-based)."""
         v = [sym("sv", j) for j in range(nv)]
         d = [sym("sd", j) for j in range(ndata)]
         s = [sym("ssp", j) for j in range(nsp)]
-        self.patterns.append(Pattern("obj", lift(template(v, d, s)), nv, 0, ndata, nsp, list(instances)))
+        args = (v, d, s) if npu == 0 else (v, d, s, [sym("spu", j) for j in range(npu)])
+        self.patterns.append(Pattern("obj", lift(template(*args)), nv, 0, ndata, nsp, list(instances), npu))
 
 
 # ---- derivation --------------------------------------------------------------------
@@ -163,10 +168,15 @@ class PatternDerived:
     pcoef: list          # constant d expr / d sprev_j (rows)
     pairs: list          # (j, l) slot pairs with a nonzero second derivative
     d2: list             # their expressions (times the row multiplier for rows)
+    dpu: list = None     # objective: d expr / d spu_b
+    xpairs: list = None  # (variable slot j, previous-control slot b) with a nonzero second derivative
+    xd2: list = None
+    ppairs: list = None  # (b, b2), b >= b2: previous-control pairs (the previous stage's Hessian)
+    pd2: list = None
 
 
-_ALLOWED = {"row": {"sv", "sprev", "sd", "dt"}, "alg": {"sv", "sd", "dt"}, "ineq": {"sv", "sd", "dt"},
-            "obj": {"sv", "sd", "ssp", "tr", "dt"}}
+_ALLOWED = {"row": {"sv", "sprev", "sd", "dt", "tr"}, "alg": {"sv", "sd", "dt", "tr"}, "ineq": {"sv", "sd", "dt", "tr"},
+            "obj": {"sv", "sd", "ssp", "tr", "dt", "spu"}}
 
 
 def _derive_pattern(pat: Pattern):
@@ -190,7 +200,22 @@ def _derive_pattern(pat: Pattern):
             if not is_const(e, 0.0):
                 pairs.append((j, l))
                 d2.append(e)
-    return PatternDerived(pat, dv, pcoef, pairs, d2)
+    PU = [sym("spu", b) for b in range(pat.npu)]
+    dpu = [diff(pat.expr, u, memo.setdefault(u, {})) for u in PU]
+    xpairs, xd2, ppairs, pd2 = [], [], [], []
+    for j in range(pat.nv):
+        for b in range(pat.npu):
+            e = diff(dv[j], PU[b])
+            if not is_const(e, 0.0):
+                xpairs.append((j, b))
+                xd2.append(e)
+    for b in range(pat.npu):
+        for b2 in range(b + 1):
+            e = diff(dpu[b], PU[b2])
+            if not is_const(e, 0.0):
+                ppairs.append((b, b2))
+                pd2.append(e)
+    return PatternDerived(pat, dv, pcoef, pairs, d2, dpu, xpairs, xd2, ppairs, pd2)
 
 
 def _structure(m: PatternModel, ders):
@@ -261,43 +286,78 @@ def _structure(m: PatternModel, ders):
         ineq_cols += own
         ineq_ptr.append(len(ineq_cols))
         jpos[(pi, ii)] = [own.index(int(v)) for v in ders[pi].pat.instances[ii]["vars"]]
-    # Hessian slots: lower pairs of stage variables over all instances
-    wkeys = {}
+    # Hessian slots: lower pairs of stage variables over all instances (the
+    # previous-control pairs of objective terms land in the previous stage's
+    # own slots), and pairs (stage variable, previous stage's control)
+    wkeys, xkeys = {}, {}
     for pi, dd in enumerate(ders):
         for inst in dd.pat.instances:
             vs = [int(v) for v in inst["vars"]]
+            pus = [int(b) for b in inst.get("pus", [])]
             for (j, l) in dd.pairs:
                 a, b = max(vs[j], vs[l]), min(vs[j], vs[l])
                 wkeys.setdefault((a, b), None)
+            for (b, b2) in (dd.ppairs or []):
+                a, c = nx + max(pus[b], pus[b2]), nx + min(pus[b], pus[b2])
+                wkeys.setdefault((a, c), None)
+            for (j, b) in (dd.xpairs or []):
+                xkeys.setdefault((vs[j], pus[b]), None)
     wlist = sorted(wkeys)
     widx = {k: i for i, k in enumerate(wlist)}
+    xlist = sorted(xkeys)
+    xidx = {k: i for i, k in enumerate(xlist)}
     # scratch of a stage: per pattern, entry c of instance i at base + c n + i
     # (n instances; consecutive lanes write consecutive doubles).  Entries: the
     # Hessian contributions, then (objective) the gradient contributions and
     # the value.  The objective values are spread over the stage's NS
     # objective-term slots (value of the f-th instance overall -> slot f % NS).
+    # Objective instances with previous-control slots add, after their own
+    # entries, the cross pairs, the previous-control pairs and the gradient
+    # in the previous controls; the last two are summed by the previous
+    # stage's lanes (lists wn_lists, gn_lists over the next stage's scratch).
     coo_base, ncoo = [], 0
     w_lists = [[] for _ in wlist]
+    wn_lists = [[] for _ in wlist]
+    x_lists = [[] for _ in xlist]
     g_lists = [[] for _ in range(ns)]
+    gn_lists = [[] for _ in range(ns)]
     f_lists = [[] for _ in range(ns)]
     nf = 0
+    offs = []
     for pi, dd in enumerate(ders):
         n = len(dd.pat.instances)
-        per = len(dd.pairs) + (dd.pat.nv + 1 if dd.pat.kind == "obj" else 0)
+        npr, nxp, npp = len(dd.pairs), len(dd.xpairs or []), len(dd.ppairs or [])
+        if dd.pat.kind == "obj":
+            o_x = npr + dd.pat.nv + 1          # cross pairs
+            o_p = o_x + nxp                    # previous-control pairs
+            o_g = o_p + npp                    # gradient in the previous controls
+            per = o_g + dd.pat.npu
+        else:
+            o_x = o_p = o_g = per = npr
+        offs.append((o_x, o_p, o_g))
         coo_base.append(ncoo)
         for ii, inst in enumerate(dd.pat.instances):
             vs = [int(v) for v in inst["vars"]]
+            pus = [int(b) for b in inst.get("pus", [])]
             for c, (j, l) in enumerate(dd.pairs):
                 w_lists[widx[(max(vs[j], vs[l]), min(vs[j], vs[l]))]].append(ncoo + c * n + ii)
             if dd.pat.kind == "obj":
                 for j in range(dd.pat.nv):
-                    g_lists[vs[j]].append(ncoo + (len(dd.pairs) + j) * n + ii)
-                f_lists[nf % ns].append(ncoo + (len(dd.pairs) + dd.pat.nv) * n + ii)
+                    g_lists[vs[j]].append(ncoo + (npr + j) * n + ii)
+                f_lists[nf % ns].append(ncoo + (npr + dd.pat.nv) * n + ii)
                 nf += 1
+                for c, (j, b) in enumerate(dd.xpairs or []):
+                    x_lists[xidx[(vs[j], pus[b])]].append(ncoo + (o_x + c) * n + ii)
+                for c, (b, b2) in enumerate(dd.ppairs or []):
+                    key = (nx + max(pus[b], pus[b2]), nx + min(pus[b], pus[b2]))
+                    wn_lists[widx[key]].append(ncoo + (o_p + c) * n + ii)
+                for b in range(dd.pat.npu):
+                    gn_lists[nx + pus[b]].append(ncoo + (o_g + b) * n + ii)
         ncoo += per * n
     return dict(rows=rows, row_ptr=row_ptr, row_cols=row_cols, prev_ptr=prev_ptr, prev_cols=prev_cols,
                 prev_coef=prev_coef, jpos=jpos, ppos=ppos, wlist=wlist, coo_base=coo_base, ncoo=ncoo,
                 w_lists=w_lists, g_lists=g_lists, f_lists=f_lists, arow=arow, drow=drow, n_alg=len(arow),
+                xlist=xlist, x_lists=x_lists, wn_lists=wn_lists, gn_lists=gn_lists, offs=offs,
                 nd=len(drow), ineq_ptr=ineq_ptr, ineq_cols=ineq_cols)
 
 
@@ -325,7 +385,7 @@ def _csr(name, lists):
 
 def _source(m: PatternModel, ders, st, tag: int) -> str:
     nx, nu, ns = m.nx, m.nu, m.ns
-    nw = len(st["wlist"])
+    nw, nwx = len(st["wlist"]), len(st["xlist"])
     nlanes = sum(len(d.pat.instances) for d in ders)
     out = []
     w = out.append
@@ -334,10 +394,12 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     w("using namespace nmpc;")
     w("namespace {")
     w(f"constexpr int NS = {ns}, NX = {nx}, NU = {nu}, RPS = {nx + st['n_alg']}, ND = {st['nd']}, NW = {nw}, "
-      f"NCOO = {max(st['ncoo'], 1)}, NLANES = {nlanes}, NSP = {m.n_setpoint};")
+      f"NWX = {nwx}, NCOO = {max(st['ncoo'], 1)}, NLANES = {nlanes}, NSP = {m.n_setpoint};")
     w("// (a model with no Hessian, gradient or objective contributions still has one scratch double")
     w("// per stage, so the summing kernel runs and writes the zeros)")
     w(f"constexpr unsigned long long TAG = {tag}ULL;")
+    w("// Hessian slots of stage k: its own NW, then (k > 0) NWX with the previous stage's controls")
+    w("__device__ inline int64_t woff(int k) { return k == 0 ? 0 : NW + (int64_t)(k - 1) * (NW + NWX); }")
     w("// binding tables of the instances (instance-major), compiled into the code object")
     for pi, dd in enumerate(ders):
         insts = dd.pat.instances
@@ -347,6 +409,8 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
             w(_ints(f"P{pi}_PP", [p for ii in range(len(insts)) for p in st["ppos"][(pi, ii)]]))
         if dd.pat.ndata:
             w(_dbls(f"P{pi}_D", [x for inst in insts for x in inst["data"]]))
+        if dd.pat.npu:
+            w(_ints(f"P{pi}_PU", [b for inst in insts for b in inst["pus"]]))
         if dd.pat.nsp:
             w(_ints(f"P{pi}_SP", [q for inst in insts for q in inst["sps"]]))
             for slot in range(dd.pat.nsp):
@@ -374,10 +438,14 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
             gsel[int(inst["target"]) - nx - nu] = (gi, ii)
     w(_ints("GA_P", [a for a, _ in gsel]))
     w(_ints("GA_I", [b for _, b in gsel]))
-    w("// summation lists of a stage's scratch: Hessian slots, gradient entries, objective-term slots")
+    w("// summation lists of a stage's scratch: Hessian slots, gradient entries, objective-term slots;")
+    w("// cross slots; and the next stage's entries that belong to this stage's controls")
     w(_csr("RW", st["w_lists"]))
     w(_csr("RG", st["g_lists"]))
     w(_csr("RF", st["f_lists"]))
+    w(_csr("RX", st["x_lists"]))
+    w(_csr("RWN", st["wn_lists"]))
+    w(_csr("RGN", st["gn_lists"]))
     # x0 contraction: the state rows holding each previous state, with coefficients
     xl = [[] for _ in range(nx)]
     for t in range(nx):
@@ -428,6 +496,9 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
         if pat.nprev:
             names["sprev"] = (f"(k > 0 ? y[(int64_t)(k - 1) * NS + P{pi}_PV[i * {pat.nprev} + {{j}}]] "
                               f": I.x0[P{pi}_PV[i * {pat.nprev} + {{j}}]])")
+        if pat.npu:
+            names["spu"] = (f"(k > 0 ? y[(int64_t)(k - 1) * NS + NX + P{pi}_PU[i * {pat.npu} + {{j}}]] "
+                            f": I.uprev[P{pi}_PU[i * {pat.npu} + {{j}}]])")
         em = _Emitter(None, names, indent=3)
         if pat.kind == "ineq":
             em.line(f"const int r = k * ND + P{pi}_T[i];")
@@ -470,6 +541,7 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
             em.line("}")
         else:
             np_ = len(dd.pairs)
+            o_x, o_p, o_g = st["offs"][pi]
             em.line(f"Sk[{base + (np_ + pat.nv) * n} + i] = {em.val(pat.expr)};")
             em.line("if (full) {")
             em.indent += 1
@@ -478,6 +550,12 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
                 em.line(f"Sk[{base + c * n} + i] = {em.val(e)};")
             for s_, e in enumerate(dd.dv):
                 em.line(f"Sk[{base + (np_ + s_) * n} + i] = {em.val(e)};")
+            for c, e in enumerate(dd.xd2 or []):
+                em.line(f"Sk[{base + (o_x + c) * n} + i] = {em.val(e)};")
+            for c, e in enumerate(dd.pd2 or []):
+                em.line(f"Sk[{base + (o_p + c) * n} + i] = {em.val(e)};")
+            for b_, e in enumerate(dd.dpu or []):
+                em.line(f"Sk[{base + (o_g + b_) * n} + i] = {em.val(e)};")
             em.pop()
             em.indent -= 1
             em.line("}")
@@ -497,19 +575,30 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     w("    const InstPtrs& I = Ia[inst];")
     w("    if (I.family != NMPC_FAMILY_STAGE_MODEL || I.gm.tag != TAG || !ctl_active(I.ctl, pred)) return;")
     w("    const int lanes = (sp.bfirst[inst + 1] - sp.bfirst[inst]) * kBlock;")
-    w("    for (int t = lb * kBlock + threadIdx.x; t < I.H * (NW + NS); t += lanes) {")
-    w("        const int k = t / (NW + NS), e = t - k * (NW + NS);")
+    w("    for (int t = lb * kBlock + threadIdx.x; t < I.H * (NW + NWX + NS); t += lanes) {")
+    w("        const int k = t / (NW + NWX + NS), e = t - k * (NW + NWX + NS);")
     w("        const double* Sk = I.gm.scratch + (int64_t)k * NCOO;")
+    w("        const double* Sn = Sk + NCOO;   // the next stage's scratch (k + 1 < H)")
+    w("        const bool next = k + 1 < I.H;")
     w("        if (e < NW) {")
     w("            if (!full) continue;")
     w("            double acc = 0.0;")
     w("            for (int q = RW_PTR[e]; q < RW_PTR[e + 1]; ++q) acc += Sk[RW_IDX[q]];")
-    w("            I.wv[(int64_t)k * NW + e] = acc;")
+    w("            if (next)")
+    w("                for (int q = RWN_PTR[e]; q < RWN_PTR[e + 1]; ++q) acc += Sn[RWN_IDX[q]];")
+    w("            I.wv[woff(k) + e] = acc;")
+    w("        } else if (e < NW + NWX) {")
+    w("            if (!full || k == 0) continue;")
+    w("            double acc = 0.0;")
+    w("            for (int q = RX_PTR[e - NW]; q < RX_PTR[e - NW + 1]; ++q) acc += Sk[RX_IDX[q]];")
+    w("            I.wv[woff(k) + e] = acc;")
     w("        } else {")
-    w("            const int v = e - NW;")
+    w("            const int v = e - NW - NWX;")
     w("            if (full) {")
     w("                double acc = 0.0;")
     w("                for (int q = RG_PTR[v]; q < RG_PTR[v + 1]; ++q) acc += Sk[RG_IDX[q]];")
+    w("                if (next)")
+    w("                    for (int q = RGN_PTR[v]; q < RGN_PTR[v + 1]; ++q) acc += Sn[RGN_IDX[q]];")
     w("                I.grad[(int64_t)k * NS + v] = acc;")
     w("            }")
     w("            double f = 0.0;")
@@ -562,14 +651,19 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     # parameter contractions (instance 0)
     objs = [(pi, dd) for pi, dd in enumerate(ders) if dd.pat.kind == "obj"]
 
-    def contraction(dd, s):
-        """so d(term)/ds - sum over slots of w_slot d2(term)/(dv_slot ds)."""
+    def contraction(dd, s, with_prev=True):
+        """so d(term)/ds - sum over the variables the term reads (its slots,
+        and with_prev the previous stage's controls) of w_var d2(term)/(dvar ds)."""
         dfs = diff(dd.pat.expr, s)
         acc = mul(sym("so"), dfs)
         for j in range(dd.pat.nv):
             d2 = diff(dfs, sym("sv", j))
             if not is_const(d2, 0.0):
                 acc = add(acc, neg(mul(sym("w", j), d2)))
+        for b in range(dd.pat.npu if with_prev else 0):
+            d2 = diff(dfs, sym("spu", b))
+            if not is_const(d2, 0.0):
+                acc = add(acc, neg(mul(sym("wp", b), d2)))
         return acc
 
     def obj_names(pi, dd):
@@ -579,6 +673,10 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
             names["sd"] = f"P{pi}_D[i * {dd.pat.ndata} + {{j}}]"
         if dd.pat.nsp:
             names["ssp"] = f"SP[P{pi}_SP[i * {dd.pat.nsp} + {{j}}]]"
+        if dd.pat.npu:
+            pu = f"P{pi}_PU[i * {dd.pat.npu} + {{j}}]"
+            names["spu"] = f"(k > 0 ? I.y[(int64_t)(k - 1) * NS + NX + {pu}] : I.uprev[{pu}])"
+            names["wp"] = f"(k > 0 ? I.adj_w[(int64_t)(k - 1) * NS + NX + {pu}] : 0.0)"
         return names
 
     w("// Parameter contractions of the sensitivity solve (instance 0):")
@@ -627,8 +725,42 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     w("        const int k = q - NX - NSP;")
     w("        const double* V = I.y + (int64_t)k * NS;")
     w("        const double TR = I.zF[k];")
-    w("        (void)V; (void)TR;")
+    w("        const int mc = I.mc;")
+    w("        const double* om = I.om;")
+    w("        (void)V; (void)TR; (void)mc; (void)om;")
     w("        double acc = 0.0;")
+    # rows reading the trajectory: - al_r dc_r/dtr - sum_j w_j lam_r d2c_r/(dv_j dtr)
+    for pi, dd in enumerate(ders):
+        pat = dd.pat
+        if pat.kind == "obj" or "tr" not in _kinds(pat.expr):
+            continue
+        dcs = diff(pat.expr, sym("tr"))
+        if is_const(dcs, 0.0):
+            continue
+        acc_e = neg(mul(sym("al"), dcs))
+        for j in range(pat.nv):
+            d2 = diff(dcs, sym("sv", j))
+            if not is_const(d2, 0.0):
+                acc_e = add(acc_e, neg(mul(mul(sym("w", j), sym("lam")), d2)))
+        names = {"sv": f"V[P{pi}_V[i * {pat.nv} + {{j}}]]", "dt": "DT", "tr": "TR",
+                 "w": f"I.adj_w[(int64_t)k * NS + P{pi}_V[i * {pat.nv} + {{j}}]]"}
+        if pat.ndata:
+            names["sd"] = f"P{pi}_D[i * {pat.ndata} + {{j}}]"
+        if pat.kind == "ineq":
+            names["lam"] = "om[2 * mc + r]"
+            names["al"] = "I.adj_lam[mc + r]"
+            rexpr = f"k * ND + P{pi}_T[i]"
+        else:
+            names["lam"] = "(om[r] - om[mc + r])"
+            names["al"] = "I.adj_lam[r]"
+            rexpr = f"k * RPS + P{pi}_T[i]"
+        w(f"        for (int i = 0; i < {len(pat.instances)}; ++i) {{")
+        w(f"            const int r = {rexpr};")
+        em = _Emitter(None, names, indent=3)
+        v = em.val(acc_e)
+        out.extend(em.lines)
+        w(f"            acc += {v};")
+        w("        }")
     for pi, dd in objs:
         e = contraction(dd, sym("tr"))
         if is_const(e, 0.0):
@@ -642,8 +774,27 @@ def _source(m: PatternModel, ders, st, tag: int) -> str:
     w("        out[q] = acc;")
     w("        return;")
     w("    }")
-    w("    // no pattern reads the last control")
-    w("    if (q < NX + NSP + ntr + NU) out[q] = 0.0;")
+    w("    if (q < NX + NSP + ntr + NU) {")
+    w("        // the last control enters the first stage's terms in previous-control slots")
+    w("        const int bq = q - NX - NSP - ntr, k = 0;")
+    w("        const double* V = I.y;")
+    w("        const double TR = ntr > 0 ? I.zF[0] : 0.0;")
+    w("        (void)V; (void)TR; (void)bq; (void)k;")
+    w("        double acc = 0.0;")
+    for pi, dd in objs:
+        for slot in range(dd.pat.npu):
+            e = contraction(dd, sym("spu", slot), with_prev=False)
+            if is_const(e, 0.0):
+                continue
+            w(f"        for (int i = 0; i < {len(dd.pat.instances)}; ++i) {{")
+            w(f"            if (P{pi}_PU[i * {dd.pat.npu} + {slot}] != bq) continue;")
+            em = _Emitter(None, obj_names(pi, dd), indent=3)
+            v = em.val(e)
+            out.extend(em.lines)
+            w(f"            acc += {v};")
+            w("        }")
+    w("        out[q] = acc;")
+    w("    }")
     w("}")
     return "\n".join(out) + "\n"
 
@@ -662,6 +813,9 @@ def generate(m: PatternModel) -> GeneratedModel:
                     raise ValueError("objective instance: wrong setpoint slots")
                 if len(inst.get("data", [])) != dd.pat.ndata:
                     raise ValueError("objective instance: wrong number of data values")
+                pus = [int(b) for b in inst.get("pus", [])]
+                if len(pus) != dd.pat.npu or len(set(pus)) != len(pus) or not all(0 <= b < m.nu for b in pus):
+                    raise ValueError("objective instance: previous-control slots must be distinct controls")
     if any("tr" in _kinds(d.pat.expr) for d in ders):
         m.uses_traj = True
     seen = set()
@@ -691,7 +845,8 @@ def generate(m: PatternModel) -> GeneratedModel:
         ineq_ptr=np.array(st["ineq_ptr"], dtype=np.int32), ineq_cols=np.array(st["ineq_cols"], dtype=np.int32),
         w_rows=np.array([a for a, _ in st["wlist"]], dtype=np.int32),
         w_cols=np.array([b for _, b in st["wlist"]], dtype=np.int32),
-        wx_rows=np.zeros(0, dtype=np.int32), wx_cols=np.zeros(0, dtype=np.int32),
+        wx_rows=np.array([a for a, _ in st["xlist"]], dtype=np.int32),
+        wx_cols=np.array([b for _, b in st["xlist"]], dtype=np.int32),
         lb=np.array(m.lb), ub=np.array(m.ub), source=_source(m, ders, st, tag), tag=tag, derived=None)
     g.scratch_per_stage = max(st["ncoo"], 1)
     g.pattern_structure = (ders, st)

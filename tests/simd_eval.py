@@ -171,7 +171,6 @@ def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None, lam_d=Non
     ns, nx = g.ns, g.nx
     rps, nd = nx + st["n_alg"], st["nd"]
     mc = H * rps
-    nw = len(g.w_rows)
     ncoo = max(st["ncoo"], 1)
     jptr = [0]
     jr, jc = [], []
@@ -194,13 +193,16 @@ def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None, lam_d=Non
     jv = np.full(len(jr), np.nan)
     c = np.zeros(H * rps)
     dvals = np.zeros(H * nd)
-    wv = np.zeros(H * nw)
     grad = np.zeros(H * ns)
     fterm = np.zeros(H * ns)
+    nwx = len(st["xlist"])
+    Ss = []
     for k in range(H):
         S = np.full(ncoo, np.nan)
+        Ss.append(S)
         V = y[k * ns:(k + 1) * ns]
         P = y[(k - 1) * ns:(k - 1) * ns + nx] if k > 0 else x0
+        PU = y[(k - 1) * ns + nx:(k - 1) * ns + nx + g.nu] if k > 0 else u_prev
         for pi, dd in enumerate(ders):
             pat = dd.pat
             n = len(pat.instances)
@@ -215,6 +217,8 @@ def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None, lam_d=Non
                     env[("sd", j)] = x
                 for j, q in enumerate(inst.get("sps", [])):
                     env[("ssp", j)] = setpoint[q]
+                for j, b in enumerate(inst.get("pus", [])):
+                    env[("spu", j)] = PU[b]
                 memo = {}
                 if pat.kind in ("row", "alg", "ineq"):
                     if pat.kind == "ineq":
@@ -236,18 +240,41 @@ def expand_patterns(g, y, H, x0, dt, setpoint=(), traj=None, lam=None, lam_d=Non
                         S[base + cc * n + i] = lr * ev(e, env, memo)
                 else:
                     npair = len(dd.pairs)
+                    o_x, o_p, o_g = st["offs"][pi]
                     S[base + (npair + pat.nv) * n + i] = ev(pat.expr, env, memo)
                     for cc, e in enumerate(dd.d2):
                         S[base + cc * n + i] = ev(e, env, memo)
                     for s_, e in enumerate(dd.dv):
                         S[base + (npair + s_) * n + i] = ev(e, env, memo)
+                    for cc, e in enumerate(dd.xd2 or []):
+                        S[base + (o_x + cc) * n + i] = ev(e, env, memo)
+                    for cc, e in enumerate(dd.pd2 or []):
+                        S[base + (o_p + cc) * n + i] = ev(e, env, memo)
+                    for b, e in enumerate(dd.dpu or []):
+                        S[base + (o_g + b) * n + i] = ev(e, env, memo)
+    wv, wr, wc = [], [], []
+    for k in range(H):
+        S = Ss[k]
+        Sn = Ss[k + 1] if k + 1 < H else None
         for e, lst in enumerate(st["w_lists"]):
-            wv[k * nw + e] = sum(S[q] for q in lst)
+            acc = sum(S[q] for q in lst)
+            if Sn is not None:
+                acc += sum(Sn[q] for q in st["wn_lists"][e])
+            wv.append(acc)
+            wr.append(k * ns + g.w_rows[e])
+            wc.append(k * ns + g.w_cols[e])
+        if k > 0:
+            for e, lst in enumerate(st["x_lists"]):
+                wv.append(sum(S[q] for q in lst))
+                wr.append(k * ns + g.wx_rows[e])
+                wc.append((k - 1) * ns + nx + g.wx_cols[e])
         for v in range(ns):
-            grad[k * ns + v] = sum(S[q] for q in st["g_lists"][v])
+            acc = sum(S[q] for q in st["g_lists"][v])
+            if Sn is not None:
+                acc += sum(Sn[q] for q in st["gn_lists"][v])
+            grad[k * ns + v] = acc
             fterm[k * ns + v] = sum(S[q] for q in st["f_lists"][v])
-    wr = np.array([k * ns + a for k in range(H) for a in g.w_rows], dtype=int)
-    wc = np.array([k * ns + b for k in range(H) for b in g.w_cols], dtype=int)
+    wv, wr, wc = np.array(wv), np.array(wr, dtype=int), np.array(wc, dtype=int)
     guess = None
     if u_prev is not None:
         gs = np.zeros(ns)

@@ -65,15 +65,16 @@ def _reflux(H, model="stage"):
     return w, m, p
 
 
-def _column(kind, seed=0, H=None):
-    """The workload column written with the front end, and the oracle's."""
+def _column(kind, seed=0, H=None, model="stage"):
+    """The workload column written with the front end (as a stage model or
+    as index-data patterns), and the oracle's."""
     from oracle.distillation import DistillationOCP
     from workloads import distillation_workload
     w = distillation_workload(kind, seed) if H is None else distillation_workload(kind, seed, H=H)
     m = DistillationOCP.from_workload(w)
     m.set_parameters(x0=w.x0, zF=w.zF(0), u_prev=w.u_prev0)
-    g = simd.compile(SM.distillation_model(w.N, w.alpha, F=w.F, rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi, u_lo=w.u_lo,
-                                           u_hi=w.u_hi))
+    make = SM.distillation_model if model == "stage" else SM.distillation_pattern_model
+    g = simd.compile(make(w.N, w.alpha, F=w.F, rho=w.rho, x_lo=w.x_lo, x_hi=w.x_hi, u_lo=w.u_lo, u_hi=w.u_hi))
     p = N.Problem(N.stage_model_structure(g, w.H, w.dt))
     p.analyze()
     p.set_parameters(w.x0, setpoint=[w.xD_sp, w.xB_sp], traj=w.zF(0), u_prev=w.u_prev0)
@@ -87,10 +88,14 @@ def _case(name):
         return _lq()[:2]
     if name == "column":
         return _column("small")[1:]
+    if name == "column_pattern":
+        return _column("small", model="pattern")[1:]
+    if name == "reflux_pattern":
+        return _reflux(10, "pattern")[1:]
     return _reflux(10)[1:]
 
 
-@pytest.mark.parametrize("name", ["toy", "lq", "reflux", "column"])
+@pytest.mark.parametrize("name", ["toy", "lq", "reflux", "column", "column_pattern", "reflux_pattern"])
 def test_generated_eval_matches_oracle(name):
     import scipy.sparse as sps
     note(f"stage model eval {name}")
@@ -178,15 +183,17 @@ def test_generated_case_study_equals_the_hand_written_family(model):
     assert kkt_error(m, sol["y"], sol["lam"], sol["omega_d"], sol["zL"], sol["zU"])["max"] <= 1e-8
 
 
-def test_generated_workload_column_equals_the_hand_written_family():
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_generated_workload_column_equals_the_hand_written_family(model):
     """The headline workload (40 trays, horizon 100) written with the front
-    end and the library's DISTILLATION family, over a cold solve and five warm
-    re-solves of the workload's closed loop at the default options (both fed
-    the hand-written side's first stage): equal iteration counts, returned
-    points within 1e-7 of each other (both stop inside the default tolerance's
-    ball; their model values differ only by rounding order)."""
-    note("generated vs hand-written workload column, 40 trays, H=100")
-    w, m, pg = _column("medium")
+    end (as a stage model, or as index-data patterns) and the library's
+    DISTILLATION family, over a cold solve and five warm re-solves of the
+    workload's closed loop at the default options (both fed the hand-written
+    side's first stage): equal iteration counts, returned points within 1e-7
+    of each other (both stop inside the default tolerance's ball; their model
+    values differ only by rounding order)."""
+    note(f"generated ({model}) vs hand-written workload column, 40 trays, H=100")
+    w, m, pg = _column("medium", model=model)
     ph = N.Problem(N.distillation_structure(w.N, w.H, w.dt, w.alpha, F=w.F, rho=w.rho))
     ph.analyze()
     sp = [w.xD_sp, w.xB_sp]
@@ -207,9 +214,10 @@ def test_generated_workload_column_equals_the_hand_written_family():
         x0 = w.next_measurement(x1, k)
 
 
-def test_column_model_sensitivities_match_oracle():
-    note("stage model sensitivities: workload column (x0, setpoint, traj, u_prev)")
-    w, m, p = _column("small", seed=2)
+@pytest.mark.parametrize("model", ["stage", "pattern"])
+def test_column_model_sensitivities_match_oracle(model):
+    note(f"{model} model sensitivities: workload column (x0, setpoint, traj, u_prev)")
+    w, m, p = _column("small", seed=2, model=model)
     ipm, st = _solved(m, p)
     sens = sensitivities(ipm, st)
     su, so = np.array([0.4, -1.1]), 0.3

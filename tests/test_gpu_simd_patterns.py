@@ -207,3 +207,40 @@ def test_every_row_kind_generated_eval_matches_the_derivation():
     wref = dict(zip(zip(ref["wr"].tolist(), ref["wc"].tolist()), ref["wv"]))
     assert close(out["w_vals"], [wref[(r, c)] for r, c in zip(pat["w_rows"].tolist(), pat["w_cols"].tolist())],
                  1e-13)
+
+
+def test_pattern_plate_closed_loop_on_the_device_equals_the_host_loop():
+    """Algorithm 1 on the device (nmpc_closed_loop_dev: the parameter update
+    and the first passes of each re-solve in one captured graph, the
+    evaluation and the summing kernel inside it) with the pattern plate:
+    the applied controls, predicted fields, iteration counts and final
+    iterate equal the host-driven loop bit for bit."""
+    import torch
+    note("closed loop on the device, pattern plate G=8 H=5, 6 steps")
+    steps = 6
+
+    def make():
+        w = plate_workload("large", 0, G=8, H=5)
+        p = _pattern_problem(w, PlateOCP.from_workload(w))
+        assert p.solve(warm=False).status == 0
+        return w, p
+
+    (w, ph), (_, pd) = make(), make()
+    us, xs, iters = [], [], 0
+    for k in range(steps):
+        u1, x1 = ph.first_stage()
+        us.append(u1)
+        xs.append(x1)
+        ph.set_parameters(x1, setpoint=w.target, u_prev=u1)
+        r = ph.solve(warm=True)
+        assert r.status == 0
+        iters += r.iters
+    u_out = torch.zeros((steps, pd.nu), dtype=torch.float64, device="cuda")
+    x_out = torch.zeros((steps, pd.nx), dtype=torch.float64, device="cuda")
+    rc, done, it = pd.closed_loop_dev(steps, u_out=u_out.data_ptr(), x_out=x_out.data_ptr(), passes_per_step=2)
+    torch.cuda.synchronize()
+    assert rc == 0 and done == steps and it == iters
+    assert np.array_equal(u_out.cpu().numpy(), np.array(us))
+    assert np.array_equal(x_out.cpu().numpy(), np.array(xs))
+    for key in ("y", "lam", "zL", "zU"):
+        assert np.array_equal(ph.solution()[key], pd.solution()[key]), key

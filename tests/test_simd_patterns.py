@@ -305,3 +305,40 @@ def test_inequality_patterns_against_direct_evaluation():
     h = 1e-6
     Wfd = np.array([(grad(y + h * E[i]) - grad(y - h * E[i])) / (2 * h) for i in range(H * 5)])
     assert np.max(np.abs(out["wv"] - Wfd[out["wr"], out["wc"]])) <= 1e-7
+
+
+@pytest.mark.parametrize("N_,H", [(6, 4), (10, 3)])
+def test_workload_column_as_patterns_matches_the_oracle(N_, H):
+    """The workload column written as patterns (the feed tray reads the
+    stage's feed composition; the move penalty reads the previous stage's
+    controls, whose gradient and Hessian terms are summed into the previous
+    stage and whose cross terms fill the cross-stage slots): values and
+    derivatives against the oracle's column (oracle/distillation.py), and
+    exactly its KKT pattern."""
+    from oracle.distillation import DistillationOCP
+    from oracle import symbolic as S
+    m = DistillationOCP(N_, H, 0.1, 2.3, F=1.0, rho=0.05)
+    rng = np.random.default_rng(N_)
+    zF = rng.uniform(0.4, 0.6, H)
+    up = rng.uniform(1.0, 3.0, 2)
+    m.set_parameters(x0=rng.uniform(0.05, 0.95, m.nx), zF=zF, u_prev=up)
+    g = SPn.generate(SM.distillation_pattern_model(N_, 2.3, F=1.0, rho=0.05))
+    y = m.initial_guess() + rng.normal(scale=0.05, size=m.n)
+    lam, lam_d = rng.normal(size=m.m_c), rng.uniform(0.1, 1.0, m.m_d)
+    sp = [m.xD_sp, m.xB_sp]
+    out = expand_patterns(g, y, H, m.x0, m.dt, sp, zF, lam=lam, lam_d=lam_d, u_prev=up)
+    assert abs(out["f"] - m.f(y)) <= 1e-14 * max(1.0, abs(m.f(y)))
+    assert np.max(np.abs(out["grad"] - m.grad(y))) <= 1e-13
+    assert np.max(np.abs(out["c"] - m.cons_c(y))) <= 1e-13
+    assert np.max(np.abs(out["d"] - m.cons_d(y))) <= 1e-14
+    Jc, Jd = m.jac_c(y).tocsr(), m.jac_d(y).tocsr()
+    import scipy.sparse as sps
+    J = sps.vstack([Jc, Jd]).tocsr()
+    assert set(zip(out["jr"].tolist(), out["jc"].tolist())) == set(zip(*J.nonzero()))
+    want = np.asarray(J[out["jr"], out["jc"]]).ravel()
+    assert np.max(np.abs(out["jv"] - want)) <= 1e-13 * max(1.0, np.max(np.abs(want)))
+    W = m.hess(y, lam, lam_d).tocsr()
+    want = np.asarray(W[out["wr"], out["wc"]]).ravel()
+    assert np.max(np.abs(out["wv"] - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+    Wl = set((a, b) for a, b in zip(*W.nonzero()) if a >= b)
+    assert Wl <= set(zip(out["wr"].tolist(), out["wc"].tolist()))
