@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .simd import (GeneratedModel, ZERO, _Emitter, _header_text, _tag, add, diff, is_const, lift, mul, neg,
+from .simd import (GeneratedModel, _Emitter, _header_text, _tag, add, diff, is_const, lift, mul, neg,
                    sym, symbols)
 
 
@@ -222,7 +222,6 @@ def _structure(m: PatternModel, ders):
     """Per-stage patterns, per-instance Jacobian positions, the Hessian slots
     and the scratch layout with the reduction lists."""
     ns, nx = m.ns, m.nx
-    row_of = {}
     rows = [None] * nx
     for pi, dd in enumerate(ders):
         if dd.pat.kind != "row":
@@ -242,7 +241,6 @@ def _structure(m: PatternModel, ders):
             if len(inst.get("data", [])) != dd.pat.ndata:
                 raise ValueError(f"row of state {t}: wrong number of data values")
             rows[t] = (pi, ii)
-            row_of[(pi, ii)] = t
     if any(r is None for r in rows):
         raise ValueError(f"states without a row: {[t for t, r in enumerate(rows) if r is None][:8]} ...")
     # algebraic and inequality rows, numbered in declaration order
