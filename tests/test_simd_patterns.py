@@ -342,3 +342,14 @@ def test_workload_column_as_patterns_matches_the_oracle(N_, H):
     assert np.max(np.abs(out["wv"] - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
     Wl = set((a, b) for a, b in zip(*W.nonzero()) if a >= b)
     assert Wl <= set(zip(out["wr"].tolist(), out["wc"].tolist()))
+
+
+def test_generation_is_deterministic_and_tagged_by_content():
+    """The same pattern model generates the same source and tag (the code
+    object cache relies on it); a change of one instance's data changes both."""
+    a = SPn.generate(SM.plate_case_pattern_model(n=9))
+    b = SPn.generate(SM.plate_case_pattern_model(n=9))
+    assert a.source == b.source and a.tag == b.tag
+    c = SPn.generate(SM.plate_case_pattern_model(n=9, Tb=51.0))
+    assert c.tag != a.tag and c.source != a.source
+    assert f"TAG = {a.tag}ULL" in a.source
