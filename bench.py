@@ -9,7 +9,7 @@ upload, every interior-point iteration on the GPU (eval, assembly, supernodal
 Cholesky, solves, line search), and the download of u_1 and x_1 for the plant.
 The first solve (analyze + cold start) is reported on its own.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -814,7 +814,7 @@ def main(argv=None):
         print(json.dumps({"copy_bytes": n * 8, "copies": 10}), flush=True)
         return 0
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not supported", file=sys.stderr)
+        print("bench.py: measures one GPU; runs on several GPUs are not supported", file=sys.stderr)
         return 2
 
     import torch
