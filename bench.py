@@ -27,21 +27,23 @@ FP64_PEAK_TFLOPS = 78.6
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "factor_distill_medium_hbm_traffic.txt")
+PLATE_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                  "factor_plate_32x32x50_hbm_traffic.txt")
 
 
-def measured_traffic():
-    """HBM bytes per factorization from the committed counter summary, or None
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per factorization from a committed counter summary, or None
     when a source of the factorization kernels changed since the counters were
     taken (the summary lists the files and their SHA-256)."""
     import hashlib
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if line.startswith("#") or ":" not in line:
                 continue
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-        root = os.path.join(os.path.dirname(TRAFFIC_FILE), "..")
+        root = os.path.join(os.path.dirname(path), "..")
         files, shas = kv["source_file"].split(), kv["source_sha256"].split()
         if len(files) != len(shas):
             return None
@@ -748,7 +750,9 @@ def run_plate(N, G=32, H=50, seed=0, resolves=20, adjoint=False, eager=False, mo
            "factor_ms": ms_fact / facts if facts else None,
            "phase_ms_per_resolve": {k_: v / max(1, resolves) for k_, v in phase.items()},
            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                        "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
+                        "traffic": (measured_traffic(PLATE_TRAFFIC_FILE)
+                                    if (G, H, model, seed) == (32, 50, "hand_written", 0) and not adjoint else None),
                         "kernel": "numeric supernodal factorization (all launches of one factorization)",
                         "flops_per_unit": flops}}
     if adjoint:
