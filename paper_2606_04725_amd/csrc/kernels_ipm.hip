@@ -47,11 +47,28 @@ __device__ inline double wave_reduce(double v, int op) {
 
 // Reduce every quantity over the block (waves, then the per-wave results in
 // wave order); thread q returns quantity q's block result in out (q < ops.q).
-__device__ double block_reduce(const double* v, const Ops& ops, double* sh) {
+// The butterfly steps of all quantities go level by level, so each level's
+// lane exchanges are in flight together (per quantity the same steps as
+// wave_reduce).
+__device__ __attribute__((always_inline)) inline double block_reduce(const double* v, const Ops& ops, double* sh) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = 0; q < ops.q; ++q) {
-        const double r = wave_reduce(v[q], ops.op[q]);
-        if (lane == 0) sh[q * kWaves + wv] = r;
+    double r[kMaxQ];
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) r[q] = q < ops.q ? v[q] : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double x[kMaxQ];
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q)
+            if (q < ops.q) x[q] = __shfl_xor(r[q], off, 64);
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q)
+            if (q < ops.q) r[q] = combine(ops.op[q], r[q], x[q]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q)
+            if (q < ops.q) sh[q * kWaves + wv] = r[q];
     }
     __syncthreads();
     double acc = 0.0;
@@ -64,19 +81,25 @@ __device__ double block_reduce(const double* v, const Ops& ops, double* sh) {
 }
 
 // Block partials of one instance: part[q * nb + lb].
-__device__ void store_partials(const double* v, const Ops& ops, double* part, int nb, int lb, double* sh) {
+__device__ __attribute__((always_inline)) inline void store_partials(const double* v, const Ops& ops, double* part, int nb, int lb, double* sh) {
     const double r = block_reduce(v, ops, sh);
     if ((int)threadIdx.x < ops.q) part[(int64_t)threadIdx.x * nb + lb] = r;
 }
 
 // Decision block of one instance: reduce its nb partials in block order; the
 // totals land in tot[0 .. ops.q) (shared memory) for thread 0.
-__device__ void finalize_partials(const double* part, int nb, const Ops& ops, double* sh, double* tot) {
+__device__ __attribute__((always_inline)) inline void finalize_partials(const double* part, int nb, const Ops& ops, double* sh, double* tot) {
     double v[kMaxQ];
-    for (int q = 0; q < ops.q; ++q) {
-        double acc = ident(ops.op[q]);
-        for (int b = threadIdx.x; b < nb; b += kBlock) acc = combine(ops.op[q], acc, part[(int64_t)q * nb + b]);
-        v[q] = acc;
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) v[q] = q < ops.q ? ident(ops.op[q]) : 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {   // per quantity in block order; the loads go together
+        double x[kMaxQ];
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q)
+            if (q < ops.q) x[q] = part[(int64_t)q * nb + b];
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q)
+            if (q < ops.q) v[q] = combine(ops.op[q], v[q], x[q]);
     }
     const double r = block_reduce(v, ops, sh);
     if ((int)threadIdx.x < ops.q) tot[threadIdx.x] = r;
@@ -132,13 +155,17 @@ __global__ void __launch_bounds__(kBlock) k_phaseA(const InstPtrs* __restrict__ 
         const double acc = gather_sum(
             I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
             [&](int2 rs) {
+                // both multipliers are loaded whatever the row's kind, so the
+                // batch's loads are issued together (no branch between them)
                 const int r = rs.x;
-                const double lam = r < I.mc ? I.om[r] - I.om[I.mc + r] : I.om[I.mc + r];
+                const double a = I.om[r < I.mc ? r : I.mc + r], b = I.om[I.mc + r];
+                const double lam = r < I.mc ? a - b : b;
                 return I.jv[rs.y] * lam;
             });
         I.gtw[j] = acc;
         const bool hl = hasL(I, j), hu = hasU(I, j);
-        const double zl = hl ? I.zl[j] : 0.0, zu = hu ? I.zu[j] : 0.0;
+        const double zlj = I.zl[j], zuj = I.zu[j];
+        const double zl = hl ? zlj : 0.0, zu = hu ? zuj : 0.0;
         const double dual = I.grad[j] + acc - zl + zu;
         q[0] = I.fterm[j];
         q[1] = fabs(dual);
@@ -373,23 +400,39 @@ __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ 
         const int r = t;
         double jdy = 0.0;
         for (int p = I.jptr[r]; p < I.jptr[r + 1]; ++p) jdy += I.jv[p] * I.dy[I.jcol[p]];
-        const int nl = r < I.mc ? 2 : 1;
-        for (int h = 0; h < nl; ++h) {
-            const int l = r < I.mc ? (h == 0 ? r : I.mc + r) : I.mc + r;
-            const double sgn = (r < I.mc && h == 1) ? -1.0 : 1.0;
-            const double sl = I.s[l], Ql = I.Q[l];
-            const double dsl = -I.r4[l] - sgn * jdy;
-            const double doml = -I.r2[l] - Ql * dsl;
-            const double dbel = mu / sl - I.be[l] - Ql * dsl;
-            I.ds[l] = dsl;
-            I.dom[l] = doml;
-            I.dbe[l] = dbel;
-            q[0] = fmin(q[0], ftb(sl, dsl, tau));
-            q[2] = fmax(q[2], fabs(I.om[l] + doml));
-            q[1] = fmin(q[1], ftb(I.be[l], dbel, tau));
-            q[4] += dsl / sl;
-            q[7] += fabs(I.r4[l]);
-            q[8] += log(sl);
+        // the lifted rows of r: r and mc + r for an equality row, mc + r
+        // otherwise; every operand of both is loaded before the first store
+        const bool eq = r < I.mc;
+        const int nl = eq ? 2 : 1;
+        int l[2];
+        l[0] = eq ? r : I.mc + r;
+        l[1] = I.mc + r;
+        double sl[2], Ql[2], r4[2], r2[2], be[2], om[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            sl[h] = I.s[l[h]];
+            Ql[h] = I.Q[l[h]];
+            r4[h] = I.r4[l[h]];
+            r2[h] = I.r2[l[h]];
+            be[h] = I.be[l[h]];
+            om[h] = I.om[l[h]];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nl) break;
+            const double sgn = (eq && h == 1) ? -1.0 : 1.0;
+            const double dsl = -r4[h] - sgn * jdy;
+            const double doml = -r2[h] - Ql[h] * dsl;
+            const double dbel = mu / sl[h] - be[h] - Ql[h] * dsl;
+            I.ds[l[h]] = dsl;
+            I.dom[l[h]] = doml;
+            I.dbe[l[h]] = dbel;
+            q[0] = fmin(q[0], ftb(sl[h], dsl, tau));
+            q[2] = fmax(q[2], fabs(om[h] + doml));
+            q[1] = fmin(q[1], ftb(be[h], dbel, tau));
+            q[4] += dsl / sl[h];
+            q[7] += fabs(r4[h]);
+            q[8] += log(sl[h]);
         }
     } else if (t < I.m + I.n) {
         const int j = t - I.m;
@@ -397,7 +440,8 @@ __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ 
         const double gl = hl ? I.y[j] - I.lb[j] : 1.0;
         const double gu = hu ? I.ub[j] - I.y[j] : 1.0;
         const double dyj = I.dy[j];
-        const double zl = hl ? I.zl[j] : 0.0, zu = hu ? I.zu[j] : 0.0;
+        const double zlj = I.zl[j], zuj = I.zu[j];
+        const double zl = hl ? zlj : 0.0, zu = hu ? zuj : 0.0;
         const double dzlj = hl ? mu / gl - zl - (zl / gl) * dyj : 0.0;
         const double dzuj = hu ? mu / gu - zu + (zu / gu) * dyj : 0.0;
         I.dzl[j] = dzlj;
