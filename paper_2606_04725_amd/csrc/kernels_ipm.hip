@@ -152,6 +152,9 @@ __global__ void __launch_bounds__(kBlock) k_phaseA(const InstPtrs* __restrict__ 
     const int t = lb * kBlock + threadIdx.x;
     if (t < I.n) {
         const int j = t;
+        // the variable's own values are loaded with the gather's first indices
+        const double lbj = I.lb[j], ubj = I.ub[j], yj = I.y[j], zlj = I.zl[j], zuj = I.zu[j];
+        const double gradj = I.grad[j], ftj = I.fterm[j];
         const double acc = gather_sum(
             I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
             [&](int2 rs) {
@@ -163,23 +166,22 @@ __global__ void __launch_bounds__(kBlock) k_phaseA(const InstPtrs* __restrict__ 
                 return I.jv[rs.y] * lam;
             });
         I.gtw[j] = acc;
-        const bool hl = hasL(I, j), hu = hasU(I, j);
-        const double zlj = I.zl[j], zuj = I.zu[j];
+        const bool hl = lbj > -INFINITY, hu = ubj < INFINITY;
         const double zl = hl ? zlj : 0.0, zu = hu ? zuj : 0.0;
-        const double dual = I.grad[j] + acc - zl + zu;
-        q[0] = I.fterm[j];
+        const double dual = gradj + acc - zl + zu;
+        q[0] = ftj;
         q[1] = fabs(dual);
         if (hl) {
-            const double p = (I.y[j] - I.lb[j]) * zl;
+            const double p = (yj - lbj) * zl;
             q[6] = p;
             q[7] = p;
         }
         if (hu) {
-            const double p = (I.ub[j] - I.y[j]) * zu;
+            const double p = (ubj - yj) * zu;
             q[8] = p;
             q[9] = p;
         }
-        if (!isfinite(I.fterm[j]) || !isfinite(I.grad[j])) q[10] = 1.0;
+        if (!isfinite(ftj) || !isfinite(gradj)) q[10] = 1.0;
     } else if (t < I.n + I.ml) {
         const int r = t - I.n;
         if (I.ctl->hyk && r < 2 * I.mc) {
@@ -302,14 +304,17 @@ __global__ void __launch_bounds__(kBlock) k_var_prep(const InstPtrs* __restrict_
     const double mu = I.ctl->mu;
     const int j = lb * kBlock + threadIdx.x;
     if (j >= I.n) return;
-    const bool hl = hasL(I, j), hu = hasU(I, j);
-    const double gl = hl ? I.y[j] - I.lb[j] : 1.0;
-    const double gu = hu ? I.ub[j] - I.y[j] : 1.0;
-    I.sig[j] = (hl ? I.zl[j] / gl : 0.0) + (hu ? I.zu[j] / gu : 0.0);
-    const double r1 = I.grad[j] + I.gtw[j] - (hl ? mu / gl : 0.0) + (hu ? mu / gu : 0.0);
+    // every load (the variable's values and the gather) before the first store
+    const double lbj = I.lb[j], ubj = I.ub[j], yj = I.y[j], zlj = I.zl[j], zuj = I.zu[j];
+    const double gradj = I.grad[j], gtwj = I.gtw[j];
     const double acc = gather_sum(
         I.jt_ptr[j], I.jt_ptr[j + 1], 0.0, [&](int e) { return int2{I.jt_row[e], I.jt_slot[e]}; },
         [&](int2 rs) { return I.jv[rs.y] * I.vcomb[rs.x]; });
+    const bool hl = lbj > -INFINITY, hu = ubj < INFINITY;
+    const double gl = hl ? yj - lbj : 1.0;
+    const double gu = hu ? ubj - yj : 1.0;
+    I.sig[j] = (hl ? zlj / gl : 0.0) + (hu ? zuj / gu : 0.0);
+    const double r1 = gradj + gtwj - (hl ? mu / gl : 0.0) + (hu ? mu / gu : 0.0);
     I.r1v[j] = r1;
     I.rhs[j] = -r1 - acc;
 }
@@ -398,10 +403,9 @@ __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ 
         q[7] = fabs(I.r4[r]);
     } else if (t < I.m) {
         const int r = t;
-        double jdy = 0.0;
-        for (int p = I.jptr[r]; p < I.jptr[r + 1]; ++p) jdy += I.jv[p] * I.dy[I.jcol[p]];
         // the lifted rows of r: r and mc + r for an equality row, mc + r
-        // otherwise; every operand of both is loaded before the first store
+        // otherwise; every operand of both is loaded before the row's product
+        // and the first store
         const bool eq = r < I.mc;
         const int nl = eq ? 2 : 1;
         int l[2];
@@ -417,6 +421,8 @@ __global__ void __launch_bounds__(kBlock) k_phaseE(const InstPtrs* __restrict__ 
             be[h] = I.be[l[h]];
             om[h] = I.om[l[h]];
         }
+        double jdy = 0.0;
+        for (int p = I.jptr[r]; p < I.jptr[r + 1]; ++p) jdy += I.jv[p] * I.dy[I.jcol[p]];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h >= nl) break;
@@ -824,33 +830,49 @@ __global__ void __launch_bounds__(kBlock) k_update(const InstPtrs* __restrict__ 
     const double* __restrict__ dzl = soc ? I.dzl_s : I.dzl;
     const double* __restrict__ dzu = soc ? I.dzu_s : I.dzu;
     const int t = lb * kBlock + threadIdx.x;
-    if (t < I.n) {
+    // every load of the thread's variable and lifted row is issued before the
+    // first store
+    const bool var = t < I.n, hyk = I.ctl->hyk != 0;
+    const bool row = t < I.ml && !(hyk && t < 2 * I.mc), lam = hyk && t < I.mc;
+    double yj = 0.0, dyj = 0.0, lbj = 0.0, ubj = 0.0, zlj = 0.0, zuj = 0.0, dzlj = 0.0, dzuj = 0.0;
+    if (var) {
+        yj = I.y[t]; dyj = dy[t]; lbj = I.lb[t]; ubj = I.ub[t];
+        zlj = I.zl[t]; zuj = I.zu[t]; dzlj = dzl[t]; dzuj = dzu[t];
+    }
+    double sr = 0.0, dsr = 0.0, omr = 0.0, domr = 0.0, ber = 0.0, dber = 0.0;
+    if (row) {
+        sr = I.s[t]; dsr = ds[t]; ber = I.be[t]; dber = dbe[t];
+    }
+    if (row || lam) {
+        omr = I.om[t]; domr = dom[t];
+    }
+    if (var) {
         const int j = t;
-        const double yn = I.y[j] + alpha * dy[j];
+        const double yn = yj + alpha * dyj;
         I.y[j] = yn;
-        if (hasL(I, j)) {
-            const double gl = yn - I.lb[j];
-            const double z = I.zl[j] + alpha * dzl[j];
+        if (lbj > -INFINITY) {
+            const double gl = yn - lbj;
+            const double z = zlj + alpha * dzlj;
             I.zl[j] = fmin(fmax(z, mu / (ks * gl)), ks * mu / gl);
         } else {
             I.zl[j] = 0.0;
         }
-        if (hasU(I, j)) {
-            const double gu = I.ub[j] - yn;
-            const double z = I.zu[j] + alpha * dzu[j];
+        if (ubj < INFINITY) {
+            const double gu = ubj - yn;
+            const double z = zuj + alpha * dzuj;
             I.zu[j] = fmin(fmax(z, mu / (ks * gu)), ks * mu / gu);
         } else {
             I.zu[j] = 0.0;
         }
     }
-    if (t < 2 * I.mc && I.ctl->hyk) {
-        if (t < I.mc) I.om[t] = I.om[t] + alpha * dom[t];   // HyKKT: lambda; no slack or slack dual
-    } else if (t < I.ml) {
+    if (lam) {
+        I.om[t] = omr + alpha * domr;   // HyKKT: lambda; no slack or slack dual
+    } else if (row) {
         const int r = t;
-        const double sn = I.s[r] + alpha * ds[r];
+        const double sn = sr + alpha * dsr;
         I.s[r] = sn;
-        I.om[r] = I.om[r] + alpha * dom[r];
-        const double b = I.be[r] + alpha * dbe[r];
+        I.om[r] = omr + alpha * domr;
+        const double b = ber + alpha * dber;
         I.be[r] = fmin(fmax(b, mu / (ks * sn)), ks * mu / sn);
     }
 }

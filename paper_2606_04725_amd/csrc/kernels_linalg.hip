@@ -382,6 +382,20 @@ __device__ __attribute__((always_inline)) inline double lane_value(double v, int
 // Shared memory: diagonal block (w (w | 1)) + rdiag (w) + xb (m - w) + v (w) + xs (w).
 constexpr int kBwdCols = 4;    // columns per 16-lane group in the rows-below product
 constexpr int kBwdDepth = 8;   // rows per lane whose loads are in flight together
+constexpr int kBwdSub = 16;    // lanes per column in the rows-below product
+
+// Butterfly sums of kBwdCols values over each kBwdSub-lane group, one level for
+// all columns at a time so that a level's lane exchanges are in flight together.
+__device__ __attribute__((always_inline)) inline void group_sums(double (&acc)[kBwdCols]) {
+#pragma unroll
+    for (int off = kBwdSub / 2; off > 0; off >>= 1) {
+        double x[kBwdCols];
+#pragma unroll
+        for (int u = 0; u < kBwdCols; ++u) x[u] = __shfl_xor(acc[u], off, kBwdSub);
+#pragma unroll
+        for (int u = 0; u < kBwdCols; ++u) acc[u] += x[u];
+    }
+}
 __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
                         const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
     const int f = S.sn_ptr[s];
@@ -405,7 +419,7 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
     // rows-below product: 16 lanes per column, kBwdCols columns per lane group;
     // when it takes one pass (w <= kBwdCols * groups, nb <= kSub * kBwdDepth)
     // the panel's values are loaded here, with everything else
-    constexpr int kSub = 16;
+    constexpr int kSub = kBwdSub;
     const int sub = tid % kSub, grp = tid / kSub, ngrp = nthr / kSub;
     const bool one_pass = nb > 0 && w <= kBwdCols * ngrp && nb <= kSub * kBwdDepth;
     double lp[kBwdDepth][kBwdCols];
@@ -463,9 +477,9 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
 #pragma unroll
                 for (int u = 0; u < kBwdCols; ++u) acc[u] = fma(lp[t][u], xv, acc[u]);
             }
+            group_sums(acc);
 #pragma unroll
             for (int u = 0; u < kBwdCols; ++u) {
-                for (int off = kSub / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, kSub);
                 const int jc = grp + u * ngrp;
                 if (sub == 0 && jc < w) v[jc] -= acc[u];
             }
@@ -497,9 +511,9 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
 #pragma unroll
                 for (int u = 0; u < kBwdCols; ++u) acc[u] = fma(lv[t][u], xv[t], acc[u]);
         }
+        group_sums(acc);
 #pragma unroll
         for (int u = 0; u < kBwdCols; ++u) {
-            for (int off = kSub / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, kSub);
             const int jc = jc0 + u * ngrp;
             if (sub == 0 && jc < w) v[jc] -= acc[u];
         }
