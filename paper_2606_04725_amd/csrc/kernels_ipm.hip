@@ -130,10 +130,13 @@ __device__ __attribute__((always_inline)) inline double gather_sum(int e0, int e
 __device__ inline bool hasL(const InstPtrs& I, int j) { return I.lb[j] > -INFINITY; }
 __device__ inline bool hasU(const InstPtrs& I, int j) { return I.ub[j] < INFINITY; }
 
+// Lifted row r: c_r - gamma, -c_{r - mc} - gamma, or d_{r - 2 mc}; one load
+// from a per-lane source (no branch, so it issues with the caller's others).
 __device__ inline double lifted_g(const InstPtrs& I, double gamma, int r) {
-    if (r < I.mc) return I.c[r] - gamma;
-    if (r < 2 * I.mc) return -I.c[r - I.mc] - gamma;
-    return I.d[r - 2 * I.mc];
+    const bool up = r < I.mc, lo = !up && r < 2 * I.mc;
+    const double* src = up || lo ? I.c : I.d;
+    const double v = src[up ? r : (lo ? r - I.mc : r - 2 * I.mc)];
+    return up ? v - gamma : (lo ? -v - gamma : v);
 }
 
 __device__ inline int nblocks_of(const Space& sp, int inst) { return sp.bfirst[inst + 1] - sp.bfirst[inst]; }
