@@ -123,17 +123,21 @@ __device__ __attribute__((always_inline)) inline void panel_solve(double* F, Idx
     }
 }
 
-// The factored pivot block into the front (thread i stores row i).
+// The factored pivot block into the front by thread 0 (every value is in its
+// registers): per column one base address, then the column's entries at
+// constant offsets from it, all under one branch.
 template <int P, class Idx>
 __device__ __attribute__((always_inline)) inline void store_pivot_block(double* F, Idx ix, int kb, int kw,
                                                                        const double (&d)[P][P]) {
-    const int tid = threadIdx.x;
+    if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (tid == i && i < kw) {
+    for (int j = 0; j < P; ++j) {
+        if (j >= kw) break;
+        double* col = F + ix(kb, kb + j);   // entry (kb + i, kb + j) is col[i]
 #pragma unroll
-            for (int j = 0; j <= i; ++j) F[ix(kb + i, kb + j)] = d[i][j];
-        }
+        for (int i = j; i < P; ++i)
+            if (i < kw) col[i] = d[i][j];
+    }
 }
 
 // Step 3 on one 16 x 16 tile (ti, tj) of the lower trapezoid right of and
@@ -228,7 +232,10 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
         const int kw = min(P, w - kb), t0 = kb + kw;
         const int nt = (m - t0 + 15) / 16, nc = (w - t0 + 15) / 16;
         __syncthreads();
-        store_pivot_block<P>(F, ix, kb, kw, d);
+        if (kw == P)   // a full panel: the width is a constant and the stores need no bounds
+            store_pivot_block<P>(F, ix, kb, P, d);
+        else
+            store_pivot_block<P>(F, ix, kb, kw, d);
         if (t0 < w)
             for (int ti = wv; ti < nt; ti += nw) trapezoid_tile<P>(F, ix, m, w, kb, kw, ti, 0);
         __syncthreads();
