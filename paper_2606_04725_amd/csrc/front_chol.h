@@ -43,17 +43,18 @@ __device__ inline void tile_of(int tt, int nc, int& ti, int& tj) {
 
 // Steps 1 and 2 of pivot columns [kb, kb + kw), kw <= P (a full panel is
 // called with kw = P as a constant, so its bounds checks fold away): d gets
-// the factored P x P pivot block, in the registers of every thread that takes
-// part (waves that own a row below the block, and wave 0, which stores the
-// block); the others would repeat the block's factorization for nothing on a
-// SIMD that a working wave shares.
+// the factored P x P pivot block and, with fv, xk the panel's part of the
+// forward solve, in the registers of every thread that takes part (waves that
+// own a row below the block, and wave 0, which stores both); the others would
+// repeat the block's factorization for nothing on a SIMD that a working wave
+// shares.
 template <int P, class Idx>
 __device__ __attribute__((always_inline)) inline void panel_solve(double* F, Idx ix, int m, int kb, int kw, int* fail,
-                                                                 double* fv, double* xo, double (&d)[P][P]) {
+                                                                 double* fv, double (&d)[P][P], double (&xk)[P]) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wv = tid / kCholWave;
     if (!(wv == 0 || kb + kw + wv * kCholWave < m)) return;
-    double rinv[P], rd[P], xk[P];
+    double rinv[P], rd[P];
 #pragma unroll
     for (int i = 0; i < P; ++i)
 #pragma unroll
@@ -90,12 +91,6 @@ __device__ __attribute__((always_inline)) inline void panel_solve(double* F, Idx
             for (int j = 0; j < k; ++j) acc = fma(-d[k][j], xk[j], acc);
             xk[k] = k < kw ? acc * rd[k] : 0.0;
         }
-        if (tid < kw) {   // thread k stores x_k (picked from the registers by selects)
-            double x = xk[0];
-#pragma unroll
-            for (int k = 1; k < P; ++k) x = tid == k ? xk[k] : x;
-            xo[kb + tid] = x;
-        }
     }
     // step 2 follows at once: it reads only rows below the block, and the
     // factored block is stored after the next barrier, when every wave has
@@ -125,11 +120,19 @@ __device__ __attribute__((always_inline)) inline void panel_solve(double* F, Idx
 
 // The factored pivot block into the front by thread 0 (every value is in its
 // registers): per column one base address, then the column's entries at
-// constant offsets from it, all under one branch.
+// constant offsets from it, all under one branch.  With fv, the panel's part
+// of the forward solve replaces its right-hand side there (every wave that
+// read that right-hand side has passed the barrier before this call).
 template <int P, class Idx>
 __device__ __attribute__((always_inline)) inline void store_pivot_block(double* F, Idx ix, int kb, int kw,
-                                                                       const double (&d)[P][P]) {
+                                                                       const double (&d)[P][P], double* fv,
+                                                                       const double (&xk)[P]) {
     if (threadIdx.x != 0) return;
+    if (fv) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (k < kw) fv[kb + k] = xk[k];
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         if (j >= kw) break;
@@ -148,14 +151,24 @@ __device__ __attribute__((always_inline)) inline void trapezoid_tile(double* F, 
                                                                     int ti, int tj) {
     const int lane = threadIdx.x & (kCholWave - 1), li = lane & 15, lk = lane >> 4;
     const int t0 = kb + kw, i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
+    // every operand is loaded from an entry inside the front (rows and pivot
+    // columns clamped) and zeroed afterwards where it lies outside, so the
+    // loads need no branch
+    const bool va = i0 + li < m, vb = j0 + li < w;
+    const int ra = va ? i0 + li : m - 1, rb = vb ? j0 + li : w - 1;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    double av[P / 4], bv[P / 4];
 #pragma unroll
     for (int s4 = 0; s4 < P / 4; ++s4) {
         const int kk = 4 * s4 + lk;
-        const double* col = F + ix.base(kb + kk);
-        const double a = (kk < kw && i0 + li < m) ? col[i0 + li] : 0.0;
-        const double b = (kk < kw && j0 + li < w) ? col[j0 + li] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        const double* col = F + ix.base(kb + (kk < kw ? kk : kw - 1));
+        av[s4] = col[ra];
+        bv[s4] = col[rb];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < P / 4; ++s4) {
+        const bool in = 4 * s4 + lk < kw;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in && va ? av[s4] : 0.0, in && vb ? bv[s4] : 0.0, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -178,14 +191,37 @@ __device__ __attribute__((always_inline)) inline void update_block(double* F, Id
         int ti, tj;
         tile_of(tt, nt, ti, tj);
         const int i0 = w + 16 * ti, j0 = w + 16 * tj;
+        // rows clamped into the front and zeroed after the load (no branch
+        // around the loads); the steps whose four columns all lie below w
+        // run without a column check, the last step clamps its columns too
+        const bool va = i0 + li < m, vb = j0 + li < m;
+        const int ra = va ? i0 + li : m - 1, rb = vb ? j0 + li : m - 1;
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k4 = 0; k4 < w; k4 += 4) {
+        const int wfull = w & ~3;
+        int k4 = 0;
+        for (; k4 + 16 <= wfull; k4 += 16) {   // four steps: eight loads in flight, then the products
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double* col = F + ix.base(k4 + 4 * u + lk);
+                a[u] = col[ra];
+                b[u] = col[rb];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va ? a[u] : 0.0, vb ? b[u] : 0.0, acc, 0, 0, 0);
+        }
+        for (; k4 < wfull; k4 += 4) {
+            const double* col = F + ix.base(k4 + lk);
+            const double a = col[ra], b = col[rb];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va ? a : 0.0, vb ? b : 0.0, acc, 0, 0, 0);
+        }
+        if (k4 < w) {
             const int kk = k4 + lk;
-            const double* col = F + ix.base(kk);
-            const double a = (kk < w && i0 + li < m) ? col[i0 + li] : 0.0;
-            const double b = (kk < w && j0 + li < m) ? col[j0 + li] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            const double* col = F + ix.base(kk < w ? kk : w - 1);
+            const double a = col[ra], b = col[rb];
+            const bool in = kk < w;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in && va ? a : 0.0, in && vb ? b : 0.0, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -215,27 +251,30 @@ __device__ __attribute__((always_inline)) inline void update_block(double* F, Id
 // numerically positive definite); the arithmetic continues with pivot 1.
 // With fv, a forward substitution rides along: fv (shared memory, m values)
 // holds the right-hand side over the front's rows; each panel's x = D^{-1}
-// fv[panel] is formed from the registers holding D and written to xo, and
-// every row below takes fv[r] -= L[r, panel] x in step 2.  On return fv[w, m)
-// is the update vector of the rows below.
+// fv[panel] is formed from the registers holding D, every row below takes
+// fv[r] -= L[r, panel] x in step 2, and x replaces fv[panel] with the pivot
+// block's store.  On return (after a barrier) fv[0, w) holds the solution of
+// the front's columns and fv[w, m) the update vector of the rows below; the
+// caller writes them out (global stores here would hold up the next shared-
+// memory loads that reuse their registers).
 template <int P, class Idx>
 __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F, Idx ix, int m, int w, int* fail, double* fv = nullptr,
-                                        double* xo = nullptr, bool with_update = true) {
+                                        bool with_update = true) {
     static_assert(P % 4 == 0 && P <= 16, "the next pivot columns lie in the first tile column");
     const int wv = threadIdx.x / kCholWave, nw = blockDim.x / kCholWave;
-    double d[P][P];
+    double d[P][P], xk[P];
     if (w >= P)
-        panel_solve<P>(F, ix, m, 0, P, fail, fv, xo, d);
+        panel_solve<P>(F, ix, m, 0, P, fail, fv, d, xk);
     else if (w > 0)
-        panel_solve<P>(F, ix, m, 0, w, fail, fv, xo, d);
+        panel_solve<P>(F, ix, m, 0, w, fail, fv, d, xk);
     for (int kb = 0; kb < w; kb += P) {   // steps 1 and 2 of panel kb are done
         const int kw = min(P, w - kb), t0 = kb + kw;
         const int nt = (m - t0 + 15) / 16, nc = (w - t0 + 15) / 16;
         __syncthreads();
         if (kw == P)   // a full panel: the width is a constant and the stores need no bounds
-            store_pivot_block<P>(F, ix, kb, P, d);
+            store_pivot_block<P>(F, ix, kb, P, d, fv, xk);
         else
-            store_pivot_block<P>(F, ix, kb, kw, d);
+            store_pivot_block<P>(F, ix, kb, kw, d, fv, xk);
         if (t0 < w)
             for (int ti = wv; ti < nt; ti += nw) trapezoid_tile<P>(F, ix, m, w, kb, kw, ti, 0);
         __syncthreads();
@@ -252,9 +291,9 @@ __device__ __attribute__((always_inline)) inline void partial_cholesky(double* F
                     trapezoid_tile<P>(F, ix, m, w, kb, kw, ti + 1, tj + 1);
                 }
             if (kw2 == P)
-                panel_solve<P>(F, ix, m, t0, P, fail, fv, xo, d);
+                panel_solve<P>(F, ix, m, t0, P, fail, fv, d, xk);
             else
-                panel_solve<P>(F, ix, m, t0, kw2, fail, fv, xo, d);
+                panel_solve<P>(F, ix, m, t0, kw2, fail, fv, d, xk);
         }
     }
     if (with_update && m > w) update_block(F, ix, m, w);

@@ -183,11 +183,12 @@ k_big_potrf(const InstPtrs* __restrict__ Ia, const int4* __restrict__ tasks, int
     const bool fw = fwd_fused(I, tk.y, pred);
     if (fw && (int)threadIdx.x < pw) fv[threadIdx.x] = *fwd_entry(I, F, tk.y, kb + threadIdx.x);
     __syncthreads();
-    partial_cholesky<8>(D, SquareIdx{ldd}, pw, pw, &I.ctl->fail, fw ? fv : nullptr, fw ? I.xp + F.f + kb : nullptr);
+    partial_cholesky<8>(D, SquareIdx{ldd}, pw, pw, &I.ctl->fail, fw ? fv : nullptr);
     for (int e = threadIdx.x; e < kBigPanel * kBigPanel; e += blockDim.x) {
         const int i = e % kBigPanel, j = e / kBigPanel;
         if (i < pw && j <= i) global(F.L)[(kb + i) + (int64_t)(kb + j) * F.m] = D[i + j * ldd];
     }
+    if (fw && (int)threadIdx.x < pw) I.xp[F.f + kb + threadIdx.x] = fv[threadIdx.x];
 }
 
 // task (inst, s, kb, row block): solve x D^T = a for the rows

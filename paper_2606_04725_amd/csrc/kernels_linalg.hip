@@ -233,18 +233,20 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
         ci = cn;
         ra = rb;
     }
-    partial_cholesky<P>(F, ix, m, w, fail, fw ? v : nullptr, fw ? I.xp + f : nullptr, false);
-    // the panel is final: it is stored while the update block (rows and
-    // columns w and on, which the store does not read) takes its update
+    partial_cholesky<P>(F, ix, m, w, fail, fw ? v : nullptr, false);
+    // the update block (rows and columns w and on) takes its update before the
+    // panel goes out: global stores in flight would hold the update's first
+    // shared-memory loads until they complete (their data registers are reused)
+    if (nb > 0) update_block(F, ix, m, w);
     double* Ls = L + S.l_off[s];
     for (int jc = wv; jc < w; jc += nw)
         for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = i >= jc ? F[ix(i, jc)] : 0.0;
-    if (fw && nb > 0) {   // the update vector is final too
+    if (fw) {   // the forward solve's part of the columns and the update vector
+        for (int k = tid; k < w; k += nthr) I.xp[f + k] = v[k];
         double* us = I.uvec + S.uv_off[s];
         for (int i = w + tid; i < m; i += nthr) us[i - w] = v[i];
     }
     if (nb > 0) {
-        update_block(F, ix, m, w);
         double* Us = U + S.u_off[s];
         for (int jj = wv; jj < nb; jj += nw)
             for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[ix(w + ii, w + jj)];
