@@ -121,6 +121,19 @@ __host__ __device__ inline bool ctl_active(const Ctl* c, int pred) {
     return ph == pred;
 }
 
+// Loads through a pointer in the global address space are global (not flat)
+// instructions: they count only against the vector-memory counter, so waits
+// for shared memory do not also wait for them.
+typedef __attribute__((address_space(1))) double gdouble;
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* global(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Everything a kernel needs to know about one instance.
 struct InstPtrs {
     int family;

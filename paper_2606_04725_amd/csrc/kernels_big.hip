@@ -42,19 +42,6 @@ constexpr int kStage = kWave * kWave / kBlock;   // entries of a 64 x 64 block s
 constexpr int kUpdateDepth = 8;  // 4-column steps of an update tile whose loads are in flight together
 constexpr int kExtendDepth = 4;  // child rows per thread whose loads are in flight together
 
-// Loads through a pointer in the global address space are global (not flat)
-// instructions: they count only against the vector-memory counter, so waits
-// for shared memory do not also wait for them.
-typedef __attribute__((address_space(1))) double gdouble;
-template <class T>
-__device__ inline const __attribute__((address_space(1))) T* global(const T* p) {
-    return (const __attribute__((address_space(1))) T*)p;
-}
-template <class T>
-__device__ inline __attribute__((address_space(1))) T* global(T* p) {
-    return (__attribute__((address_space(1))) T*)p;
-}
-
 struct Front {
     double* L;     // panel, leading dimension m
     double* U;     // update block, leading dimension m - w

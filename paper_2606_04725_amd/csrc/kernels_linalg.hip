@@ -84,8 +84,8 @@ __device__ __attribute__((always_inline)) inline void child_round(const double* 
         r.ur[u] = -1;
         r.uv[u] = 0.0;
         if (uvec && i < nc) {
-            r.uv[u] = uvec[i];
-            r.ur[u] = rel[i];
+            r.uv[u] = global(uvec)[i];
+            r.ur[u] = global(rel)[i];
         }
     }
 #pragma unroll
@@ -97,11 +97,24 @@ __device__ __attribute__((always_inline)) inline void child_round(const double* 
         if (e < ne) {
             int i, j;
             unpack_lower(e, nc, i, j);
-            r.v[u] = Uc[i + (int64_t)j * nc];
-            r.ri[u] = rel[i];
-            r.rj[u] = rel[j];
+            r.v[u] = global(Uc)[i + (int64_t)j * nc];
+            r.ri[u] = global(rel)[i];
+            r.rj[u] = global(rel)[j];
         }
     }
+}
+
+// A child record read through a global-address-space pointer (field by field:
+// a structure copy does not cross address spaces).
+__device__ __attribute__((always_inline)) inline ChildRec child_rec_at(const ChildRec* recs, int k) {
+    const auto* g = global(recs) + k;
+    ChildRec r;
+    r.u_off = g->u_off;
+    r.rel_off = g->rel_off;
+    r.uv_off = g->uv_off;
+    r.nc = g->nc;
+    r.child = g->child;
+    return r;
 }
 
 // The group's first supernode, or -1 when the instance is not in the launch's
@@ -110,8 +123,8 @@ __device__ __attribute__((always_inline)) inline void child_round(const double* 
 __device__ __attribute__((always_inline)) inline int first_node(const InstPtrs& I, const Group& g, int pred) {
     const int32_t* sched = I.S.sched_nodes;
     const Ctl* c = I.ctl;   // every instance has its control block
-    const int s0 = sched[g.begin];
-    const int ph = c->phase;
+    const int s0 = global(sched)[g.begin];
+    const int ph = global(c)->phase;
     const bool active = pred == kPredAll || (pred == kPredFactor ? (ph == kPhB || ph == kPhF) : ph == pred);
     return active ? s0 : -1;
 }
@@ -124,62 +137,79 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
                            double* __restrict__ U, int* __restrict__ fail, double* F, double* v, const InstPtrs& I,
                            bool fwd) {
     using Idx = typename std::conditional<Lds, PackedIdx, SquareIdx>::type;
-    const int f = S.sn_ptr[s];
-    const int w = S.sn_ptr[s + 1] - f;
-    const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
+    const int f = global(S.sn_ptr)[s];
+    const int w = global(S.sn_ptr)[s + 1] - f;
+    const int m = (int)(global(S.rows_ptr)[s + 1] - global(S.rows_ptr)[s]);
     Idx ix;
     if constexpr (Lds) ix.m = m; else ix.ld = m | 1;
     const int nb = m - w;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
-    const bool fw = fwd && S.fused[s];
-    // first round of the first child's update block and the first original
-    // entries in flight while the front is cleared
-    const int c0 = S.child_ptr[s], c1 = S.child_ptr[s + 1];
-    ChildRound ra;
-    int ci = c0, nc = 0, ne = 0, e0 = 0;
-    const double* Uc = nullptr;
-    const int32_t* rel = nullptr;
-    const double* uvc = nullptr;
-    auto open_child = [&](int k) {   // one record read per child
-        const ChildRec cr = S.child_rec[k];
-        nc = cr.nc;
-        ne = (nc * (nc + 1)) / 2;
-        Uc = U + cr.u_off;
-        rel = S.rel + cr.rel_off;
-        uvc = fw ? I.uvec + cr.uv_off : nullptr;
-        e0 = 0;
-    };
-    const double* cur_uv = nullptr;      // the child whose round is in ra
-    int cur_nc = 0;
-    const int32_t* cur_rel = nullptr;
-    bool cur_first = false;
-    if (ci < c1) {
-        open_child(ci);
-        child_round(Uc, rel, nc, ne, e0, ra, uvc);
-        cur_uv = uvc;
-        cur_nc = nc;
-        cur_rel = rel;
-        cur_first = true;
-    }
+    const bool fw = fwd && global(S.fused)[s];
     // original entries of the condensed matrix in this supernode's columns, the
-    // first kBatch per thread loaded with the child's round; a diagonal entry's
+    // first kBatch per thread loaded before the children's rounds (so that
+    // waiting for them does not wait for the rounds); a diagonal entry's
     // position is stored complemented and takes + eta
-    const int kt0 = S.k_ptr[s], kt1 = S.k_ptr[s + 1];
+    const int kt0 = global(S.k_ptr)[s], kt1 = global(S.k_ptr)[s + 1];
+    const int c0 = global(S.child_ptr)[s], c1 = global(S.child_ptr)[s + 1];   // read with the entry range
     int kp[kBatch];
     double kx[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
         const int t = kt0 + tid + u * nthr;
-        kp[u] = t < kt1 ? S.k_fpos[t] : 0;
-        kx[u] = t < kt1 ? kv[t] : 0.0;
+        kp[u] = t < kt1 ? global(S.k_fpos)[t] : 0;
+        kx[u] = t < kt1 ? global(kv)[t] : 0.0;
     }
+    // The children's update blocks go in rounds (kBatch entries per thread),
+    // child after child; the loads of two rounds are in flight ahead of the one
+    // being added, the first two issued before the front is cleared.  The
+    // records of the current and the next child are read ahead of their rounds.
+    const int step = nthr * kBatch;
+    struct RoundInfo {   // what the adds of an issued round need
+        int child, nc;
+        bool first;
+        const int32_t* rel;
+        const double* uv;
+    };
+    int pci = c0, pe0 = 0;   // the next round to issue
+    ChildRec prec{}, pnext{};
+    if (pci < c1) prec = child_rec_at(S.child_rec, pci);
+    if (pci + 1 < c1) pnext = child_rec_at(S.child_rec, pci + 1);
+    // the fused forward solve's right-hand side of the supernode's columns:
+    // the permutation is read with the records, thread i's entry of the
+    // right-hand side before the rounds (loads complete in the order issued,
+    // so each wait is for one level of dependent loads)
+    const int pk0 = fw && tid < w ? global(I.perm)[f + tid] : 0;
+    double rv = 0.0;
+    if (fw && tid < w) rv = global(I.rhs)[pk0];
+    auto issue = [&](ChildRound& r, RoundInfo& info) -> bool {
+        if (pci >= c1) return false;
+        const int nc = prec.nc, ne = (nc * (nc + 1)) / 2;
+        const int32_t* rel = S.rel + prec.rel_off;
+        const double* uvc = fw ? I.uvec + prec.uv_off : nullptr;
+        const bool first = pe0 == 0;
+        child_round(U + prec.u_off, rel, nc, ne, pe0, r, first ? uvc : nullptr);
+        info = RoundInfo{pci, nc, first, rel, uvc};
+        if (pe0 + step < ne) {
+            pe0 += step;
+        } else {
+            ++pci;
+            pe0 = 0;
+            prec = pnext;
+            if (pci + 1 < c1) pnext = child_rec_at(S.child_rec, pci + 1);
+        }
+        return true;
+    };
+    ChildRound ra, rb;
+    RoundInfo ia{}, ib{};
+    bool ha = issue(ra, ia);
+    bool hb = issue(rb, ib);
     const int fsize = Lds ? (m * (m + 1)) / 2 : m * (m | 1);
     for (int e = tid; e < fsize; e += nthr) F[e] = 0.0;
     // fused forward solve of the Newton step: v over the front's rows starts
     // from the permuted right-hand side of the supernode's columns
     if (fw)
-        for (int i = tid; i < m; i += nthr) v[i] = i < w ? I.rhs[I.perm[f + i]] : 0.0;
+        for (int i = tid; i < m; i += nthr) v[i] = i < w ? (i == tid ? rv : I.rhs[I.perm[f + i]]) : 0.0;
     __syncthreads();
     auto place = [&](int pos, double v) {
         if (pos < 0) {
@@ -191,63 +221,46 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
         if (kt0 + tid + u * nthr < kt1) place(kp[u], kx[u]);
-    for (int t = kt0 + tid + kBatch * nthr; t < kt1; t += nthr) place(S.k_fpos[t], kv[t]);
+    for (int t = kt0 + tid + kBatch * nthr; t < kt1; t += nthr) place(global(S.k_fpos)[t], global(kv)[t]);
     __syncthreads();
-    // extend-add of the children's update blocks in fixed order, one round of
-    // kBatch entries per thread at a time; the next round's loads are issued
-    // before the current round is added, and children are separated by barriers
-    // (two children can add into the same entry)
-    while (ci < c1) {
-        ChildRound rb;
-        int cn = ci;
-        bool next = true;
-        if (e0 + nthr * kBatch < ne) {
-            e0 += nthr * kBatch;
-        } else if (ci + 1 < c1) {
-            cn = ci + 1;
-        } else {
-            next = false;
-        }
-        const bool new_child = cn != ci;
-        if (next) {
-            if (new_child) open_child(cn);
-            child_round(Uc, rel, nc, ne, e0, rb, new_child ? uvc : nullptr);
-        }
+    // extend-add in fixed order; children are separated by barriers (two
+    // children can add into the same entry, one child's entries are distinct)
+    while (ha) {
+        ChildRound rc;
+        RoundInfo ic{};
+        const bool hc = issue(rc, ic);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
             if (ra.ri[u] >= 0) F[ix(ra.ri[u], ra.rj[u])] += ra.v[u];
-        if (fw && cur_first) {   // the child's update vector, with its first round
+        if (fw && ia.first) {   // the child's update vector, with its first round
 #pragma unroll
             for (int u = 0; u < kUvec; ++u)
                 if (ra.ur[u] >= 0) v[ra.ur[u]] += ra.uv[u];
-            for (int i = tid + kUvec * nthr; i < cur_nc; i += nthr) v[cur_rel[i]] += cur_uv[i];
+            for (int i = tid + kUvec * nthr; i < ia.nc; i += nthr) v[ia.rel[i]] += ia.uv[i];
         }
-        if (new_child || !next) __syncthreads();
-        if (!next) break;
-        cur_first = new_child;
-        if (new_child) {
-            cur_uv = uvc;
-            cur_nc = nc;
-            cur_rel = rel;
-        }
-        ci = cn;
+        if (!hb || ib.child != ia.child) __syncthreads();
         ra = rb;
+        ia = ib;
+        ha = hb;
+        rb = rc;
+        ib = ic;
+        hb = hc;
     }
     partial_cholesky<P>(F, ix, m, w, fail, fw ? v : nullptr, false);
     // the update block (rows and columns w and on) takes its update before the
     // panel goes out: global stores in flight would hold the update's first
     // shared-memory loads until they complete (their data registers are reused)
     if (nb > 0) update_block(F, ix, m, w);
-    double* Ls = L + S.l_off[s];
+    auto* Ls = global(L + global(S.l_off)[s]);
     for (int jc = wv; jc < w; jc += nw)
         for (int i = lane; i < m; i += kWave) Ls[i + jc * m] = i >= jc ? F[ix(i, jc)] : 0.0;
     if (fw) {   // the forward solve's part of the columns and the update vector
-        for (int k = tid; k < w; k += nthr) I.xp[f + k] = v[k];
-        double* us = I.uvec + S.uv_off[s];
+        for (int k = tid; k < w; k += nthr) global(I.xp)[f + k] = v[k];
+        auto* us = global(I.uvec + global(S.uv_off)[s]);
         for (int i = w + tid; i < m; i += nthr) us[i - w] = v[i];
     }
     if (nb > 0) {
-        double* Us = U + S.u_off[s];
+        auto* Us = global(U + global(S.u_off)[s]);
         for (int jj = wv; jj < nb; jj += nw)
             for (int ii = jj + lane; ii < nb; ii += kWave) Us[ii + jj * nb] = F[ix(w + ii, w + jj)];
     }
@@ -400,9 +413,9 @@ __device__ __attribute__((always_inline)) inline void group_sums(double (&acc)[k
 }
 __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, const double* __restrict__ L, double* __restrict__ xp,
                         const int32_t* __restrict__ perm, double* __restrict__ out, double* lds) {
-    const int f = S.sn_ptr[s];
-    const int w = S.sn_ptr[s + 1] - f;
-    const int m = (int)(S.rows_ptr[s + 1] - S.rows_ptr[s]);
+    const int f = global(S.sn_ptr)[s];
+    const int w = global(S.sn_ptr)[s + 1] - f;
+    const int m = (int)(global(S.rows_ptr)[s + 1] - global(S.rows_ptr)[s]);
     const int nb = m - w;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave;
@@ -412,12 +425,12 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
     double* xb = rdiag + w;
     double* v = xb + nb;
     double* xs = v + w;
-    const double* Ls = L + S.l_off[s];
-    const int32_t* rows = S.rows + S.rows_ptr[s];
-    const int ri = tid < nb ? rows[w + tid] : 0;
-    const double dg = tid < w ? Ls[tid + (int64_t)tid * m] : 1.0;
-    const double xv = tid < w ? xp[f + tid] : 0.0;
-    const int pk = tid < w ? perm[f + tid] : 0;
+    const double* Ls = L + global(S.l_off)[s];
+    const int32_t* rows = S.rows + global(S.rows_ptr)[s];
+    const int ri = tid < nb ? global(rows)[w + tid] : 0;
+    const double dg = tid < w ? global(Ls)[tid + (int64_t)tid * m] : 1.0;
+    const double xv = tid < w ? global(xp)[f + tid] : 0.0;
+    const int pk = tid < w ? global(perm)[f + tid] : 0;
     // rows-below product: 16 lanes per column, kBwdCols columns per lane group;
     // when it takes one pass (w <= kBwdCols * groups, nb <= kSub * kBwdDepth)
     // the panel's values are loaded here, with everything else
@@ -431,7 +444,7 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
             const int jc = grp + u * ngrp;
             const double* col = Ls + (int64_t)(jc < w ? jc : 0) * m + w;
 #pragma unroll
-            for (int t = 0; t < kBwdDepth; ++t) lp[t][u] = col[min(sub + kSub * t, nb - 1)];
+            for (int t = 0; t < kBwdDepth; ++t) lp[t][u] = global(col)[min(sub + kSub * t, nb - 1)];
         }
     }
     const int ww = w * w;
@@ -446,7 +459,7 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
         for (int u = 0; u < kBatch; ++u) {
             const int e = e0 + tid + u * nthr, c = (int)(((float)e + 0.5f) * rw), r = e - c * w;
             cc[u] = c;
-            t[u] = (e < ww && r >= c) ? Ls[r + (int64_t)c * m] : 0.0;
+            t[u] = (e < ww && r >= c) ? global(Ls)[r + (int64_t)c * m] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -454,17 +467,17 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
             if (e < ww && r >= c) PT[c + r * ld] = t[u];
         }
     }
-    if (tid < nb) xb[tid] = xp[ri];
+    if (tid < nb) xb[tid] = global(xp)[ri];
     if (tid < w) {
         rdiag[tid] = 1.0 / dg;
         v[tid] = xv;
     }
     // the panel fits in shared memory, so w < nthr; a narrow supernode can have
     // more rows below than threads
-    for (int i = tid + nthr; i < nb; i += nthr) xb[i] = xp[rows[w + i]];
+    for (int i = tid + nthr; i < nb; i += nthr) xb[i] = global(xp)[global(rows)[w + i]];
     for (int k = tid + nthr; k < w; k += nthr) {
-        rdiag[k] = 1.0 / Ls[k + (int64_t)k * m];
-        v[k] = xp[f + k];
+        rdiag[k] = 1.0 / global(Ls)[k + (int64_t)k * m];
+        v[k] = global(xp)[f + k];
     }
     __syncthreads();
     if (one_pass) {
@@ -506,7 +519,7 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
                 const int i = i0 + kSub * t, ic = min(i, nb - 1);
                 xv[t] = i < nb ? xb[ic] : 0.0;
 #pragma unroll
-                for (int u = 0; u < kBwdCols; ++u) lv[t][u] = col[u][ic];
+                for (int u = 0; u < kBwdCols; ++u) lv[t][u] = global(col[u])[ic];
             }
 #pragma unroll
             for (int t = 0; t < kBwdDepth; ++t)
@@ -547,12 +560,12 @@ __device__ __attribute__((always_inline)) void bwd_one(int s, const SnView& S, c
         }
     }
     if (tid < w) {
-        xp[f + tid] = xs[tid];
-        out[pk] = xs[tid];
+        global(xp)[f + tid] = xs[tid];
+        global(out)[pk] = xs[tid];
     }
     for (int k = tid + nthr; k < w; k += nthr) {
-        xp[f + k] = xs[k];
-        out[perm[f + k]] = xs[k];
+        global(xp)[f + k] = xs[k];
+        global(out)[global(perm)[f + k]] = xs[k];
     }
     __syncthreads();
 }
