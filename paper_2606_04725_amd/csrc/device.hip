@@ -1082,6 +1082,11 @@ nmpc_status device_init(Problem& p, std::string& err) {
                               (int32_t)(sy.sn_rows_ptr[c + 1] - sy.sn_rows_ptr[c]) - wc, c};
         }
         DTRY(upload_c(A, I.S.child_rec, rec));
+        std::vector<ChildRec> first((size_t)2 * std::max(sy.nsn, 1), ChildRec{0, 0, 0, 0, 0});
+        for (int sn = 0; sn < sy.nsn; ++sn)
+            for (int k = 0; k < 2 && sy.child_ptr[sn] + k < sy.child_ptr[sn + 1]; ++k)
+                first[(size_t)2 * sn + k] = rec[(size_t)sy.child_ptr[sn] + k];
+        DTRY(upload_c(A, I.S.first_recs, first));
     }
     DTRY(upload_c(A, I.S.l_off, sy.l_off));
     DTRY(upload_c(A, I.S.u_off, u_off));

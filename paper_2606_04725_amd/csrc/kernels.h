@@ -57,6 +57,7 @@ struct SnView {
     const int32_t* child_ptr;
     const int32_t* child_list;
     const ChildRec* child_rec;    // per child_list position
+    const ChildRec* first_recs;   // per supernode: the records of its first two children (zero past the last)
     const int64_t* l_off;
     const int64_t* u_off;
     const int64_t* uv_off;

@@ -137,6 +137,9 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
                            double* __restrict__ U, int* __restrict__ fail, double* F, double* v, const InstPtrs& I,
                            bool fwd) {
     using Idx = typename std::conditional<Lds, PackedIdx, SquareIdx>::type;
+    // the first two children's records hang off the supernode itself, so they
+    // are read with its sizes (one level of dependent loads less for the rounds)
+    const ChildRec rec0 = child_rec_at(S.first_recs, 2 * s), rec1 = child_rec_at(S.first_recs, 2 * s + 1);
     const int f = global(S.sn_ptr)[s];
     const int w = global(S.sn_ptr)[s + 1] - f;
     const int m = (int)(global(S.rows_ptr)[s + 1] - global(S.rows_ptr)[s]);
@@ -172,16 +175,12 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
         const double* uv;
     };
     int pci = c0, pe0 = 0;   // the next round to issue
-    ChildRec prec{}, pnext{};
-    if (pci < c1) prec = child_rec_at(S.child_rec, pci);
-    if (pci + 1 < c1) pnext = child_rec_at(S.child_rec, pci + 1);
+    ChildRec prec = rec0, pnext = rec1;
     // the fused forward solve's right-hand side of the supernode's columns:
-    // the permutation is read with the records, thread i's entry of the
-    // right-hand side before the rounds (loads complete in the order issued,
-    // so each wait is for one level of dependent loads)
+    // the permutation is read before the rounds, thread i's entry of the
+    // right-hand side after them (loads complete in the order issued; the
+    // right-hand side is waited for where the rounds are about to be added)
     const int pk0 = fw && tid < w ? global(I.perm)[f + tid] : 0;
-    double rv = 0.0;
-    if (fw && tid < w) rv = global(I.rhs)[pk0];
     auto issue = [&](ChildRound& r, RoundInfo& info) -> bool {
         if (pci >= c1) return false;
         const int nc = prec.nc, ne = (nc * (nc + 1)) / 2;
@@ -204,12 +203,10 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
     RoundInfo ia{}, ib{};
     bool ha = issue(ra, ia);
     bool hb = issue(rb, ib);
+    double rv = 0.0;
+    if (fw && tid < w) rv = global(I.rhs)[pk0];
     const int fsize = Lds ? (m * (m + 1)) / 2 : m * (m | 1);
     for (int e = tid; e < fsize; e += nthr) F[e] = 0.0;
-    // fused forward solve of the Newton step: v over the front's rows starts
-    // from the permuted right-hand side of the supernode's columns
-    if (fw)
-        for (int i = tid; i < m; i += nthr) v[i] = i < w ? (i == tid ? rv : I.rhs[I.perm[f + i]]) : 0.0;
     __syncthreads();
     auto place = [&](int pos, double v) {
         if (pos < 0) {
@@ -222,6 +219,12 @@ __device__ __attribute__((always_inline)) void factor_one(int s, const SnView& S
     for (int u = 0; u < kBatch; ++u)
         if (kt0 + tid + u * nthr < kt1) place(kp[u], kx[u]);
     for (int t = kt0 + tid + kBatch * nthr; t < kt1; t += nthr) place(global(S.k_fpos)[t], global(kv)[t]);
+    // fused forward solve of the Newton step: v over the front's rows starts
+    // from the permuted right-hand side of the supernode's columns (before the
+    // barrier that precedes the children's update vectors)
+    if (fw)
+        for (int i = tid; i < m; i += nthr)
+            v[i] = i < w ? (i == tid ? rv : global(I.rhs)[global(I.perm)[f + i]]) : 0.0;
     __syncthreads();
     // extend-add in fixed order; children are separated by barriers (two
     // children can add into the same entry, one child's entries are distinct)
